@@ -1,0 +1,90 @@
+"""Planted mistakes in the oracle must be caught by its pins.
+
+Each mutant is a copy of the oracle's C source with one plausible mistake (a
+wrong comparison, a dropped term, a swapped index or direction, a wrong tie
+rule).  It is compiled on the CPU, loaded in place of the real oracle, and the
+pin tests of test_oracle_pins are run against it: at least one must fail.
+"""
+import os
+import subprocess
+
+import pytest
+
+import test_oracle_pins as pins
+from oracle import oracle as O
+
+MUTANTS = [
+    ("census <= instead of <", "(uint64_t)(v < centre ? 1 : 0)", "(uint64_t)(v <= centre ? 1 : 0)"),
+    ("census > instead of <", "(uint64_t)(v < centre ? 1 : 0)", "(uint64_t)(v > centre ? 1 : 0)"),
+    ("census column-major order",
+     "for (int dy = -ry; dy <= ry; ++dy) {\n                for (int dx = -rx; dx <= rx; ++dx) {",
+     "for (int dx = -rx; dx <= rx; ++dx) {\n                for (int dy = -ry; dy <= ry; ++dy) {"),
+    ("cost: valid range off by one", "if (x - d >= 0)\n", "if (x - d > 0)\n"),
+    ("cost: zero instead of N_b left of image", "c = nbits;", "c = 0;"),
+    ("P2 used for one-step change", "lp[d - 1] + p1 < best) best = lp[d - 1] + p1",
+     "lp[d - 1] + p2 < best) best = lp[d - 1] + p2"),
+    ("predecessor minimum not subtracted", "l[d] = (int32_t)c[d] + best - m;", "l[d] = (int32_t)c[d] + best;"),
+    ("P1 instead of P2 for large jumps", "if (m + p2 < best) best = m + p2;", "if (m + p1 < best) best = m + p1;"),
+    ("d+1 neighbour dropped", "if (d + 1 < d_max && lp[d + 1] + p1 < best)", "if (0 && lp[d + 1] + p1 < best)"),
+    ("predecessor on the wrong side", "int px_ = (x) - dx, py_ = (y) - dy;", "int px_ = (x) + dx, py_ = (y) - dy;"),
+    ("path start not equal to cost", "for (int d = 0; d < d_max; ++d) l[d] = c[d];",
+     "for (int d = 0; d < d_max; ++d) l[d] = 0;"),
+    ("diagonal direction table swapped", "{+1, -1, 0, 0, +1, -1, -1, +1}", "{+1, -1, 0, 0, +1, -1, +1, -1}"),
+    ("WTA picks the last tie", "if (s[d] < s[best]) best = d;", "if (s[d] <= s[best]) best = d;"),
+    ("right disparity picks the last tie", "if (v < bestv) { bestv = v; best = d; }",
+     "if (v <= bestv) { bestv = v; best = d; }"),
+    ("LR strict difference", "if (diff <= max_diff) v = (uint16_t)dl;", "if (diff < max_diff) v = (uint16_t)dl;"),
+    ("LR accepts left-of-image", "if (xr >= 0) {", "if (xr >= 0 || 1) { if (xr < 0) xr = 0;"),
+    ("median picks the wrong rank", "out[(int64_t)y * w + x] = win[n / 2];",
+     "out[(int64_t)y * w + x] = win[n / 2 + (n > 1)];"),
+    ("V-map skips d = 0", "v[(int64_t)y * d_max + d] += 1;", "v[(int64_t)y * d_max + d] += (d > 0);"),
+]
+
+PIN_CALLS = [
+    (pins.test_census_worked_example, {}),
+    (pins.test_census_constant_image_is_zero, {}),
+    (pins.test_census_one_dark_pixel_sets_one_bit_per_neighbour, {"cw": 5, "ch": 5}),
+    (pins.test_census_uses_strict_less_than_and_clamped_borders, {}),
+    (pins.test_cost_is_popcount_of_xor_and_nbits_left_of_image, {}),
+    (pins.test_cost_constant_images, {}),
+    (pins.test_cost_zero_at_true_shift, {}),
+    (pins.test_aggregation_worked_example, {}),
+    (pins.test_aggregation_matches_enumeration_on_tiny_scanlines, {}),
+    (pins.test_aggregation_zero_penalties_is_sum_of_costs, {}),
+    (pins.test_aggregation_infinite_penalties_is_prefix_sum, {}),
+    (pins.test_aggregation_direction_conventions_by_symmetry, {}),
+    (pins.test_wta_is_first_argmin, {}),
+    (pins.test_right_disparity_and_lr_worked_example, {}),
+    (pins.test_right_disparity_is_argmin_of_resampled_volume, {}),
+    (pins.test_lr_check_hand_built_cases, {}),
+    (pins.test_median_matches_scipy, {"k": 3}),
+    (pins.test_uv_maps_are_histograms, {}),
+]
+
+
+@pytest.fixture(scope="module")
+def restore_oracle():
+    yield
+    O.load()
+
+
+@pytest.mark.parametrize("name,old,new", MUTANTS, ids=[m[0] for m in MUTANTS])
+def test_pins_catch_planted_mistake(tmp_path, restore_oracle, name, old, new):
+    src = open(O.SRC).read()
+    assert src.count(old) >= 1, "mutation site not found: " + name
+    mutated = src.replace(old, new)
+    c_path = tmp_path / "mutant.c"
+    so_path = tmp_path / "libmutant.so"
+    c_path.write_text(mutated)
+    subprocess.check_call(["gcc", "-O1", "-std=c11", "-shared", "-fPIC", "-o", str(so_path), str(c_path)])
+    O.load(str(so_path))
+    caught = []
+    try:
+        for fn, kw in PIN_CALLS:
+            try:
+                fn(**kw)
+            except (AssertionError, O.OracleError):
+                caught.append(fn.__name__)
+    finally:
+        O.load()
+    assert caught, "no pin caught the planted mistake: " + name
