@@ -1,0 +1,187 @@
+/*
+ * sgm.h -- C ABI of the MI355X (gfx950) semi-global-matching library.
+ *
+ * The library computes the stereo disparity path of Ruf et al., "Real-time
+ * on-board obstacle avoidance for UAVs based on embedded stereo vision"
+ * (arXiv 1807.06271): rectified 8-bit left/right images in, a disparity map
+ * and its U-/V-map histograms out (section 3.1 and 3.2).  Every stage is a
+ * hand-written HIP kernel; all arithmetic is integer.
+ *
+ * Conventions shared by every entry point
+ *  - Pointers named as device buffers must point to device memory of the
+ *    context's device (e.g. a torch CUDA tensor's data_ptr()).  The caller
+ *    owns every input and output buffer; the library never frees them, and they
+ *    must stay valid until the work enqueued on `stream` has finished (or, for
+ *    sgm_submit, until sgm_poll reports the ticket done).
+ *  - `stream` is a hipStream_t passed as void*; NULL means the default stream.
+ *    Stage calls only enqueue work and return at once.
+ *  - Every call returns an sgm_status.  Argument errors are reported before
+ *    anything is enqueued.  An asynchronous device fault is reported as
+ *    SGM_EHIP by the next call that notices it.  sgm_last_error() gives a
+ *    thread-local text for the last failure of the calling thread.
+ *  - A context may be used from several threads (calls are serialised by an
+ *    internal lock), but the stage calls of one context share its scratch
+ *    memory: work of two stage calls on different streams of the same context
+ *    must not overlap in time (use one context per stream for that).
+ *    sgm_submit batches use their own scratch and may overlap freely.
+ *
+ * Layouts (row-major, no padding unless a pitch is given)
+ *  - image   uint8  [H][pitch]      pitch >= W bytes
+ *  - census  uint64 [H][W]          N_b = census_w*census_h - 1 low bits used
+ *  - cost    uint16 [H][W][D]       disparity fastest
+ *  - aggr    uint16 [H][W][D]       S = sum of the selected path costs
+ *  - disp    uint16 [H][W]          values < D, or `invalid`
+ *  - umap    uint16 [D][W]          U[d][x] = #{y : disp(x,y) = d}
+ *  - vmap    uint16 [H][D]          V[y][d] = #{x : disp(x,y) = d}
+ */
+#ifndef SGM_H
+#define SGM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  SGM_OK = 0,
+  SGM_EINVAL = -1,    /* invalid argument (nothing was enqueued)            */
+  SGM_ENOMEM = -2,    /* scratch would exceed the context's memory budget   */
+  SGM_EHIP = -3,      /* HIP runtime error, including earlier async faults  */
+  SGM_EBUSY = -4,     /* batch not admissible now; poll, then submit again  */
+  SGM_ENOTFOUND = -5  /* unknown ticket                                     */
+} sgm_status;
+
+/* Aggregation path directions r = (dx, dy) (section 3.1.3).  Each path starts
+ * at the image border and visits p - r before p. */
+enum {
+  SGM_PATH_L2R = 1u << 0,   /* (+1,  0) left to right                     */
+  SGM_PATH_R2L = 1u << 1,   /* (-1,  0) right to left                     */
+  SGM_PATH_T2B = 1u << 2,   /* ( 0, +1) top to bottom                     */
+  SGM_PATH_B2T = 1u << 3,   /* ( 0, -1) bottom to top                     */
+  SGM_PATH_TL2BR = 1u << 4, /* (+1, +1) diagonal to the bottom right      */
+  SGM_PATH_BR2TL = 1u << 5, /* (-1, -1) diagonal to the top left          */
+  SGM_PATH_TR2BL = 1u << 6, /* (-1, +1) diagonal to the bottom left       */
+  SGM_PATH_BL2TR = 1u << 7  /* (+1, -1) diagonal to the top right         */
+};
+/* The paper's four streaming paths (figure 2: 0, 45, 90 and 135 degrees). */
+#define SGM_PATHS_PAPER4 (SGM_PATH_L2R | SGM_PATH_TL2BR | SGM_PATH_T2B | SGM_PATH_TR2BL)
+/* Horizontal and vertical paths in both senses. */
+#define SGM_PATHS_HV4 (SGM_PATH_L2R | SGM_PATH_R2L | SGM_PATH_T2B | SGM_PATH_B2T)
+#define SGM_PATHS_ALL8 0xFFu
+
+/* Parameters of one frame.  Validated by every call:
+ *   1 <= width, height <= 16384;  1 <= max_disp (D) <= 256;
+ *   census_w, census_h odd and >= 1 with 1 <= census_w*census_h - 1 <= 64;
+ *   path_mask a nonzero subset of SGM_PATH_*;  p1 <= p2;
+ *   popcount(path_mask) * (N_b + p2) <= 65535 (no 16-bit overflow of S);
+ *   lr_check 0 or 1, lr_max_diff >= 0;  median 0 (off), 3 or 5;
+ *   invalid >= D (255 is the usual value for D <= 255, 65535 above). */
+typedef struct {
+  int32_t width, height;
+  int32_t max_disp;
+  int32_t census_w, census_h;
+  uint32_t path_mask;
+  uint16_t p1, p2;
+  int32_t lr_check;
+  int32_t lr_max_diff;
+  int32_t median;
+  uint16_t invalid;
+  uint16_t reserved; /* must be 0 */
+} sgm_params;
+
+typedef struct sgm_ctx sgm_ctx;
+
+/* Check a parameter set without touching the GPU: SGM_OK, or SGM_EINVAL
+ * with the reason in sgm_last_error().  Every other call runs the same
+ * checks. */
+int sgm_validate(const sgm_params *p);
+
+/* Create a context on HIP device `device`.  hbm_budget_bytes caps the device
+ * scratch the context may hold (stage-call scratch plus in-flight batches);
+ * 0 selects half of the device's free memory.  Returns SGM_EINVAL for a bad
+ * device or null `ctx`. */
+int sgm_create(sgm_ctx **ctx, int device, size_t hbm_budget_bytes);
+
+/* Wait for all work the context enqueued, free its scratch, destroy it.
+ * Outstanding tickets become unknown.  A null ctx is a no-op. */
+int sgm_destroy(sgm_ctx *ctx);
+
+/* Text of the calling thread's last failure ("" if none).  Owned by the
+ * library, valid until the thread's next call. */
+const char *sgm_last_error(void);
+
+/* Census transform (section 3.1.2): for each pixel p, an N_b-bit code of the
+ * comparisons [I(q) < I(p)] over the census_w x census_h window, neighbours in
+ * raster order with the first one in bit N_b-1, coordinates clamped to the
+ * image.  img: device uint8 [H][pitch]; census: device uint64 [H][W]. */
+int sgm_census(sgm_ctx *ctx, const sgm_params *p, const uint8_t *img, int64_t pitch,
+               uint64_t *census, void *stream);
+
+/* Matching cost volume, equation (1) with the Census/Hamming similarity:
+ * cost(x,y,d) = popcount(cl(x,y) XOR cr(x-d,y)) for x >= d, else N_b.
+ * cl, cr: device uint64 [H][W]; cost: device uint16 [H][W][D]. */
+int sgm_cost(sgm_ctx *ctx, const sgm_params *p, const uint64_t *cl, const uint64_t *cr,
+             uint16_t *cost, void *stream);
+
+/* Semi-global aggregation (section 3.1.3, equation (2) as Hirschmueller's
+ * path recurrence): for each path r in path_mask,
+ *   L_r(p,d) = C(p,d) + min(L_r(p-r,d), L_r(p-r,d+-1) + P1, m + P2) - m,
+ *   m = min_k L_r(p-r,k);  L_r(p,d) = C(p,d) at the first pixel of a path;
+ * and aggr = S = sum_r L_r.  cost values must be <= N_b (as sgm_cost makes
+ * them); larger values give unspecified (but memory-safe) results.
+ * cost, aggr: device uint16 [H][W][D]; may not alias. */
+int sgm_aggregate(sgm_ctx *ctx, const sgm_params *p, const uint16_t *cost, uint16_t *aggr,
+                  void *stream);
+
+/* Disparity selection (sections 3.1.3 to 3.1.5) from S:
+ *   D_L(p) = smallest argmin_d S(p,d);
+ *   if lr_check: D_R(x,y) = smallest argmin_{d < min(D, W-x)} S(x+d,y,d) and
+ *     the pixel keeps D_L iff x - D_L >= 0 and |D_L - D_R(x-D_L,y)| <= lr_max_diff,
+ *     else it becomes `invalid`;
+ *   if median: k x k median (clamped borders) of that map.
+ * aggr: device uint16 [H][W][D]; disp: device uint16 [H][W]. */
+int sgm_disparity(sgm_ctx *ctx, const sgm_params *p, const uint16_t *aggr, uint16_t *disp,
+                  void *stream);
+
+/* U-/V-maps (section 3.2): per-column and per-row disparity histograms of
+ * disp; values >= D (the invalid marker) are not counted.  disp: device
+ * uint16 [H][W]; umap: device uint16 [D][W]; vmap: device uint16 [H][D]. */
+int uv_maps(sgm_ctx *ctx, const sgm_params *p, const uint16_t *disp, uint16_t *umap,
+            uint16_t *vmap, void *stream);
+
+/* One frame of the whole path for sgm_submit.  left/right: device uint8
+ * [H][pitch]; disp, umap, vmap: device outputs as above (umap/vmap may be
+ * NULL to skip the histograms). */
+typedef struct {
+  const uint8_t *left, *right;
+  int64_t pitch;
+  sgm_params p;
+  uint16_t *disp, *umap, *vmap;
+} sgm_frame;
+
+/* Enqueue the whole path (census .. U/V maps) for n >= 1 frames, which may
+ * differ in size and parameters, as one batch on the context's own streams.
+ * Results equal those of the stage calls on each frame alone.  The batch's
+ * scratch is taken from the context's budget: if it does not fit next to the
+ * batches still in flight, returns SGM_EBUSY (retry after sgm_poll); if it
+ * can never fit, SGM_ENOMEM.  On success *ticket identifies the batch. */
+int sgm_submit(sgm_ctx *ctx, const sgm_frame *frames, int n, uint64_t *ticket);
+
+/* Non-blocking completion check: *done = 1 once every frame of the ticket's
+ * batch is finished (its scratch is then returned to the budget and the
+ * ticket forgotten), else 0.  SGM_ENOTFOUND for an unknown ticket. */
+int sgm_poll(sgm_ctx *ctx, uint64_t ticket, int *done);
+
+/* Block until the ticket's batch has finished, then behave as sgm_poll. */
+int sgm_wait(sgm_ctx *ctx, uint64_t ticket);
+
+/* Bytes of budget currently held by in-flight batches, and the budget. */
+int sgm_memory(sgm_ctx *ctx, size_t *in_flight_bytes, size_t *budget_bytes);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SGM_H */

@@ -1,0 +1,613 @@
+// C-ABI of the SGM library (declared in include/sgm.h): argument validation,
+// context and scratch management, stage calls, and the batched
+// sgm_submit / sgm_poll path.
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/sgm.h"
+#include "sgm_kernels.h"
+
+using namespace sgmk;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+#define HIP_TRY(expr)                                                                    \
+  do {                                                                                   \
+    hipError_t e_ = (expr);                                                              \
+    if (e_ != hipSuccess) return fail(SGM_EHIP, "%s: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+int popcount8(uint32_t m) { return __builtin_popcount(m & 0xFFu); }
+
+int validate(const sgm_params *p) {
+  if (!p) return fail(SGM_EINVAL, "params is null");
+  if (p->width < 1 || p->height < 1 || p->width > 16384 || p->height > 16384)
+    return fail(SGM_EINVAL, "width/height must be in [1, 16384] (got %d x %d)", p->width, p->height);
+  if (p->max_disp < 1 || p->max_disp > 256)
+    return fail(SGM_EINVAL, "max_disp must be in [1, 256] (got %d)", p->max_disp);
+  if (p->census_w < 1 || p->census_h < 1 || !(p->census_w & 1) || !(p->census_h & 1))
+    return fail(SGM_EINVAL, "census window must have odd sides >= 1 (got %d x %d)", p->census_w,
+                p->census_h);
+  const int nb = p->census_w * p->census_h - 1;
+  if (nb < 1 || nb > 64)
+    return fail(SGM_EINVAL, "census_w*census_h-1 must be in [1, 64] (got %d)", nb);
+  if (p->path_mask == 0 || (p->path_mask & ~0xFFu))
+    return fail(SGM_EINVAL, "path_mask must be a nonzero subset of the 8 directions (got 0x%x)",
+                p->path_mask);
+  if (p->p1 > p->p2) return fail(SGM_EINVAL, "p1 must be <= p2 (got %u > %u)", p->p1, p->p2);
+  if ((long)popcount8(p->path_mask) * (nb + p->p2) > 65535)
+    return fail(SGM_EINVAL, "paths*(N_b+p2) = %ld exceeds 65535: S could overflow 16 bits",
+                (long)popcount8(p->path_mask) * (nb + p->p2));
+  if (p->lr_check != 0 && p->lr_check != 1) return fail(SGM_EINVAL, "lr_check must be 0 or 1");
+  if (p->lr_max_diff < 0) return fail(SGM_EINVAL, "lr_max_diff must be >= 0");
+  if (p->median != 0 && p->median != 3 && p->median != 5)
+    return fail(SGM_EINVAL, "median must be 0, 3 or 5 (got %d)", p->median);
+  if (p->invalid < p->max_disp)
+    return fail(SGM_EINVAL, "invalid (%u) must be >= max_disp (%d)", p->invalid, p->max_disp);
+  if (p->reserved != 0) return fail(SGM_EINVAL, "reserved must be 0");
+  return SGM_OK;
+}
+
+int nbits_of(const sgm_params &p) { return p.census_w * p.census_h - 1; }
+int dpl_of(const sgm_params &p) { return (p.max_disp + 63) / 64; }
+// Path costs fit in 8 bits when C + P2 <= 255 (C <= N_b, L_r <= C + P2).
+int lr_bytes_of(const sgm_params &p) { return nbits_of(p) + p.p2 <= 255 ? 1 : 2; }
+
+int fill_dirs(uint32_t mask, int *dirs) {
+  int n = 0;
+  for (int d = 0; d < 8; ++d)
+    if (mask & (1u << d)) dirs[n++] = d;
+  return n;
+}
+
+size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+// Device scratch held by a context: one growable buffer for stage calls and
+// a cache of idle batch blocks.
+struct Block {
+  void *ptr = nullptr;
+  size_t bytes = 0;
+};
+
+struct Batch {
+  hipEvent_t done = nullptr;
+  Block mem;
+  int stream = 0;
+};
+
+}  // namespace
+
+struct sgm_ctx {
+  int device = 0;
+  size_t budget = 0;
+  std::mutex mu;
+  Block stage;                  // stage-call scratch
+  std::vector<Block> idle;      // finished batch blocks kept for reuse
+  std::map<uint64_t, Batch> inflight;
+  uint64_t next_ticket = 1;
+  static constexpr int kStreams = 4;
+  hipStream_t streams[kStreams] = {};
+  int next_stream = 0;
+
+  size_t held() const {
+    size_t s = stage.bytes;
+    for (auto &b : idle) s += b.bytes;
+    for (auto &kv : inflight) s += kv.second.mem.bytes;
+    return s;
+  }
+  size_t inflight_bytes() const {
+    size_t s = 0;
+    for (auto &kv : inflight) s += kv.second.mem.bytes;
+    return s;
+  }
+};
+
+namespace {
+
+struct DeviceGuard {
+  int prev = -1;
+  bool ok = true;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    if (prev != dev) ok = hipSetDevice(dev) == hipSuccess;
+  }
+  ~DeviceGuard() {
+    int cur = -1;
+    if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+  }
+};
+
+// Free idle batch blocks until `need` more bytes fit in the budget.
+int make_room(sgm_ctx *c, size_t need) {
+  while (c->held() + need > c->budget && !c->idle.empty()) {
+    HIP_TRY(hipFree(c->idle.back().ptr));
+    c->idle.pop_back();
+  }
+  return SGM_OK;
+}
+
+// Ensure the stage scratch holds `bytes`; work already enqueued on `s` may
+// still use the old buffer, so the stream is drained before freeing it.
+int stage_scratch(sgm_ctx *c, size_t bytes, hipStream_t s, void **out) {
+  bytes = align256(bytes);
+  if (c->stage.bytes < bytes) {
+    const size_t old = c->stage.bytes;
+    int rc = make_room(c, bytes - old);
+    if (rc) return rc;
+    if (c->held() - old + bytes > c->budget)
+      return fail(SGM_ENOMEM, "stage scratch of %zu bytes exceeds the budget (%zu held of %zu)",
+                  bytes, c->held(), c->budget);
+    if (c->stage.ptr) {
+      HIP_TRY(hipStreamSynchronize(s));
+      HIP_TRY(hipFree(c->stage.ptr));
+      c->stage = Block{};
+    }
+    HIP_TRY(hipMalloc(&c->stage.ptr, bytes));
+    c->stage.bytes = bytes;
+  }
+  *out = c->stage.ptr;
+  return SGM_OK;
+}
+
+int check_launch() {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(SGM_EHIP, "kernel launch: %s", hipGetErrorString(e));
+  return SGM_OK;
+}
+
+// Check that a pointer is device memory of this device (or managed memory).
+int check_dev_ptr(const void *ptr, int dev, const char *name) {
+  if (!ptr) return fail(SGM_EINVAL, "%s is null", name);
+  hipPointerAttribute_t a;
+  if (hipPointerGetAttributes(&a, ptr) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(SGM_EINVAL, "%s is not a HIP allocation", name);
+  }
+  if (a.type != hipMemoryTypeDevice && a.type != hipMemoryTypeManaged)
+    return fail(SGM_EINVAL, "%s is not device memory", name);
+  if (a.type == hipMemoryTypeDevice && a.device != dev)
+    return fail(SGM_EINVAL, "%s lives on device %d, context is on device %d", name, a.device, dev);
+  return SGM_OK;
+}
+
+#define CHECK(expr)       \
+  do {                    \
+    int rc_ = (expr);     \
+    if (rc_) return rc_;  \
+  } while (0)
+
+// ------------------------------------------------------ whole-frame plan
+
+struct FramePlan {
+  size_t off_cl, off_cr, off_lr, off_dlr, bytes;
+};
+
+FramePlan plan_frame(const sgm_params &p, size_t base) {
+  const size_t px = (size_t)p.width * p.height;
+  FramePlan f;
+  f.off_cl = base;
+  f.off_cr = f.off_cl + align256(px * 8);
+  f.off_lr = f.off_cr + align256(px * 8);
+  f.off_dlr = f.off_lr + align256(px * p.max_disp * (size_t)popcount8(p.path_mask) * lr_bytes_of(p));
+  f.bytes = f.off_dlr + align256(px * 2) - base;
+  return f;
+}
+
+// Enqueue census -> aggregation (costs recomputed from the Census codes) ->
+// disparity selection -> median -> U/V maps for `n` frames on `s`, with the
+// frames' scratch at `mem` laid out by plan_frame.
+int enqueue_frames(const sgm_frame *fr, int n, const std::vector<FramePlan> &plans, char *mem,
+                   hipStream_t s) {
+  std::vector<CensusJob> cj;
+  for (int i = 0; i < n; ++i) {
+    const sgm_params &p = fr[i].p;
+    for (int side = 0; side < 2; ++side) {
+      CensusJob j{};
+      j.img = side ? fr[i].right : fr[i].left;
+      j.pitch = fr[i].pitch;
+      j.out = reinterpret_cast<uint64_t *>(mem + (side ? plans[i].off_cr : plans[i].off_cl));
+      j.W = p.width;
+      j.H = p.height;
+      j.cw = p.census_w;
+      j.ch = p.census_h;
+      cj.push_back(j);
+    }
+  }
+  launch_census(cj, s);
+  CHECK(check_launch());
+  // aggregation, one launch per (disparities per lane, path-cost width)
+  for (int dpl = 1; dpl <= 4; ++dpl)
+    for (int lb = 1; lb <= 2; ++lb) {
+      std::vector<AggJob> aj;
+      for (int i = 0; i < n; ++i) {
+        const sgm_params &p = fr[i].p;
+        if (dpl_of(p) != dpl || lr_bytes_of(p) != lb) continue;
+        AggJob j{};
+        j.cl = reinterpret_cast<const uint64_t *>(mem + plans[i].off_cl);
+        j.cr = reinterpret_cast<const uint64_t *>(mem + plans[i].off_cr);
+        j.lr = mem + plans[i].off_lr;
+        j.W = p.width;
+        j.H = p.height;
+        j.D = p.max_disp;
+        j.nbits = nbits_of(p);
+        j.p1 = p.p1;
+        j.p2 = p.p2;
+        j.ndirs = fill_dirs(p.path_mask, j.dirs);
+        aj.push_back(j);
+      }
+      if (!aj.empty()) {
+        launch_aggregate(aj, kFromCensus, dpl, lb, s);
+        CHECK(check_launch());
+      }
+    }
+  for (int lb = 1; lb <= 2; ++lb) {
+    std::vector<DispJob> dj;
+    for (int i = 0; i < n; ++i) {
+      const sgm_params &p = fr[i].p;
+      if (lr_bytes_of(p) != lb) continue;
+      DispJob j{};
+      j.lr = mem + plans[i].off_lr;
+      j.P = popcount8(p.path_mask);
+      j.out = p.median ? reinterpret_cast<uint16_t *>(mem + plans[i].off_dlr) : fr[i].disp;
+      j.W = p.width;
+      j.H = p.height;
+      j.D = p.max_disp;
+      j.lr_check = p.lr_check;
+      j.max_diff = p.lr_max_diff;
+      j.invalid = p.invalid;
+      dj.push_back(j);
+    }
+    if (!dj.empty()) {
+      launch_disparity(dj, lb, s);
+      CHECK(check_launch());
+    }
+  }
+  std::vector<MedianJob> mj;
+  for (int i = 0; i < n; ++i) {
+    const sgm_params &p = fr[i].p;
+    if (!p.median) continue;
+    MedianJob j{};
+    j.in = reinterpret_cast<const uint16_t *>(mem + plans[i].off_dlr);
+    j.out = fr[i].disp;
+    j.W = p.width;
+    j.H = p.height;
+    j.k = p.median;
+    mj.push_back(j);
+  }
+  if (!mj.empty()) {
+    launch_median(mj, s);
+    CHECK(check_launch());
+  }
+  std::vector<UVJob> uj;
+  for (int i = 0; i < n; ++i) {
+    if (!fr[i].umap || !fr[i].vmap) continue;
+    UVJob j{};
+    j.disp = fr[i].disp;
+    j.U = fr[i].umap;
+    j.V = fr[i].vmap;
+    j.W = fr[i].p.width;
+    j.H = fr[i].p.height;
+    j.D = fr[i].p.max_disp;
+    uj.push_back(j);
+  }
+  if (!uj.empty()) {
+    launch_uv(uj, s);
+    CHECK(check_launch());
+  }
+  return SGM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *sgm_last_error(void) { return g_err.c_str(); }
+
+int sgm_validate(const sgm_params *p) { return validate(p); }
+
+int sgm_create(sgm_ctx **ctx, int device, size_t hbm_budget_bytes) {
+  if (!ctx) return fail(SGM_EINVAL, "ctx is null");
+  *ctx = nullptr;
+  int ndev = 0;
+  HIP_TRY(hipGetDeviceCount(&ndev));
+  if (device < 0 || device >= ndev)
+    return fail(SGM_EINVAL, "device %d out of range (%d devices)", device, ndev);
+  DeviceGuard g(device);
+  if (!g.ok) return fail(SGM_EHIP, "hipSetDevice(%d) failed", device);
+  size_t freeb = 0, total = 0;
+  HIP_TRY(hipMemGetInfo(&freeb, &total));
+  auto *c = new sgm_ctx();
+  c->device = device;
+  c->budget = hbm_budget_bytes ? hbm_budget_bytes : freeb / 2;
+  for (int i = 0; i < sgm_ctx::kStreams; ++i) {
+    if (hipStreamCreateWithFlags(&c->streams[i], hipStreamNonBlocking) != hipSuccess) {
+      for (int k = 0; k < i; ++k) (void)hipStreamDestroy(c->streams[k]);
+      delete c;
+      return fail(SGM_EHIP, "hipStreamCreate failed");
+    }
+  }
+  *ctx = c;
+  return SGM_OK;
+}
+
+int sgm_destroy(sgm_ctx *c) {
+  if (!c) return SGM_OK;
+  int rc = SGM_OK;
+  {
+    std::lock_guard<std::mutex> lk(c->mu);
+    DeviceGuard g(c->device);
+    if (hipDeviceSynchronize() != hipSuccess) rc = fail(SGM_EHIP, "device fault before destroy");
+    for (auto &kv : c->inflight) {
+      (void)hipEventDestroy(kv.second.done);
+      (void)hipFree(kv.second.mem.ptr);
+    }
+    for (auto &b : c->idle) (void)hipFree(b.ptr);
+    if (c->stage.ptr) (void)hipFree(c->stage.ptr);
+    for (auto &s : c->streams) (void)hipStreamDestroy(s);
+  }
+  delete c;
+  return rc;
+}
+
+int sgm_census(sgm_ctx *c, const sgm_params *p, const uint8_t *img, int64_t pitch, uint64_t *census,
+               void *stream) {
+  if (!c) return fail(SGM_EINVAL, "ctx is null");
+  CHECK(validate(p));
+  if (pitch < p->width) return fail(SGM_EINVAL, "pitch %lld < width %d", (long long)pitch, p->width);
+  std::lock_guard<std::mutex> lk(c->mu);
+  DeviceGuard g(c->device);
+  CHECK(check_dev_ptr(img, c->device, "img"));
+  CHECK(check_dev_ptr(census, c->device, "census"));
+  CensusJob j{};
+  j.img = img;
+  j.pitch = pitch;
+  j.out = census;
+  j.W = p->width;
+  j.H = p->height;
+  j.cw = p->census_w;
+  j.ch = p->census_h;
+  launch_census({j}, (hipStream_t)stream);
+  return check_launch();
+}
+
+int sgm_cost(sgm_ctx *c, const sgm_params *p, const uint64_t *cl, const uint64_t *cr, uint16_t *cost,
+             void *stream) {
+  if (!c) return fail(SGM_EINVAL, "ctx is null");
+  CHECK(validate(p));
+  std::lock_guard<std::mutex> lk(c->mu);
+  DeviceGuard g(c->device);
+  CHECK(check_dev_ptr(cl, c->device, "cl"));
+  CHECK(check_dev_ptr(cr, c->device, "cr"));
+  CHECK(check_dev_ptr(cost, c->device, "cost"));
+  CostJob j{};
+  j.cl = cl;
+  j.cr = cr;
+  j.cost = cost;
+  j.W = p->width;
+  j.H = p->height;
+  j.D = p->max_disp;
+  j.nbits = nbits_of(*p);
+  launch_cost({j}, (hipStream_t)stream);
+  return check_launch();
+}
+
+int sgm_aggregate(sgm_ctx *c, const sgm_params *p, const uint16_t *cost, uint16_t *aggr,
+                  void *stream) {
+  if (!c) return fail(SGM_EINVAL, "ctx is null");
+  CHECK(validate(p));
+  if ((const void *)cost == (const void *)aggr) return fail(SGM_EINVAL, "cost and aggr alias");
+  std::lock_guard<std::mutex> lk(c->mu);
+  DeviceGuard g(c->device);
+  CHECK(check_dev_ptr(cost, c->device, "cost"));
+  CHECK(check_dev_ptr(aggr, c->device, "aggr"));
+  hipStream_t s = (hipStream_t)stream;
+  const int lb = lr_bytes_of(*p);
+  const int P = popcount8(p->path_mask);
+  const int64_t cells = (int64_t)p->width * p->height * p->max_disp;
+  void *lr = nullptr;
+  CHECK(stage_scratch(c, (size_t)cells * P * lb, s, &lr));
+  AggJob j{};
+  j.cost = cost;
+  j.lr = lr;
+  j.W = p->width;
+  j.H = p->height;
+  j.D = p->max_disp;
+  j.nbits = nbits_of(*p);
+  j.p1 = p->p1;
+  j.p2 = p->p2;
+  j.ndirs = fill_dirs(p->path_mask, j.dirs);
+  launch_aggregate({j}, kFromCost, dpl_of(*p), lb, s);
+  CHECK(check_launch());
+  SumJob sj{};
+  sj.lr = lr;
+  sj.S = aggr;
+  sj.cells = cells;
+  sj.P = P;
+  launch_sum({sj}, lb, s);
+  return check_launch();
+}
+
+int sgm_disparity(sgm_ctx *c, const sgm_params *p, const uint16_t *aggr, uint16_t *disp,
+                  void *stream) {
+  if (!c) return fail(SGM_EINVAL, "ctx is null");
+  CHECK(validate(p));
+  std::lock_guard<std::mutex> lk(c->mu);
+  DeviceGuard g(c->device);
+  CHECK(check_dev_ptr(aggr, c->device, "aggr"));
+  CHECK(check_dev_ptr(disp, c->device, "disp"));
+  hipStream_t s = (hipStream_t)stream;
+  uint16_t *tmp = nullptr;
+  if (p->median) {
+    void *v = nullptr;
+    CHECK(stage_scratch(c, (size_t)p->width * p->height * 2, s, &v));
+    tmp = reinterpret_cast<uint16_t *>(v);
+  }
+  DispJob j{};
+  j.S = aggr;
+  j.P = popcount8(p->path_mask);
+  j.out = p->median ? tmp : disp;
+  j.W = p->width;
+  j.H = p->height;
+  j.D = p->max_disp;
+  j.lr_check = p->lr_check;
+  j.max_diff = p->lr_max_diff;
+  j.invalid = p->invalid;
+  launch_disparity({j}, 0, s);
+  CHECK(check_launch());
+  if (p->median) {
+    MedianJob m{};
+    m.in = tmp;
+    m.out = disp;
+    m.W = p->width;
+    m.H = p->height;
+    m.k = p->median;
+    launch_median({m}, s);
+    CHECK(check_launch());
+  }
+  return SGM_OK;
+}
+
+int uv_maps(sgm_ctx *c, const sgm_params *p, const uint16_t *disp, uint16_t *umap, uint16_t *vmap,
+            void *stream) {
+  if (!c) return fail(SGM_EINVAL, "ctx is null");
+  CHECK(validate(p));
+  std::lock_guard<std::mutex> lk(c->mu);
+  DeviceGuard g(c->device);
+  CHECK(check_dev_ptr(disp, c->device, "disp"));
+  CHECK(check_dev_ptr(umap, c->device, "umap"));
+  CHECK(check_dev_ptr(vmap, c->device, "vmap"));
+  UVJob j{};
+  j.disp = disp;
+  j.U = umap;
+  j.V = vmap;
+  j.W = p->width;
+  j.H = p->height;
+  j.D = p->max_disp;
+  launch_uv({j}, (hipStream_t)stream);
+  return check_launch();
+}
+
+int sgm_submit(sgm_ctx *c, const sgm_frame *frames, int n, uint64_t *ticket) {
+  if (!c) return fail(SGM_EINVAL, "ctx is null");
+  if (!frames || n < 1 || !ticket) return fail(SGM_EINVAL, "need frames, n >= 1 and a ticket pointer");
+  std::vector<FramePlan> plans(n);
+  size_t total = 0;
+  for (int i = 0; i < n; ++i) {
+    int rc = validate(&frames[i].p);
+    if (rc) return fail(rc, "frame %d: %s", i, g_err.c_str());
+    if (frames[i].pitch < frames[i].p.width) return fail(SGM_EINVAL, "frame %d: pitch < width", i);
+    if ((frames[i].umap == nullptr) != (frames[i].vmap == nullptr))
+      return fail(SGM_EINVAL, "frame %d: give both umap and vmap, or neither", i);
+    plans[i] = plan_frame(frames[i].p, total);
+    total += plans[i].bytes;
+  }
+  std::lock_guard<std::mutex> lk(c->mu);
+  DeviceGuard g(c->device);
+  for (int i = 0; i < n; ++i) {
+    CHECK(check_dev_ptr(frames[i].left, c->device, "left"));
+    CHECK(check_dev_ptr(frames[i].right, c->device, "right"));
+    CHECK(check_dev_ptr(frames[i].disp, c->device, "disp"));
+    if (frames[i].umap) {
+      CHECK(check_dev_ptr(frames[i].umap, c->device, "umap"));
+      CHECK(check_dev_ptr(frames[i].vmap, c->device, "vmap"));
+    }
+  }
+  total = align256(total);
+  if (total + c->stage.bytes > c->budget)
+    return fail(SGM_ENOMEM, "batch needs %zu bytes of scratch, budget is %zu", total, c->budget);
+  // reuse an idle block that is big enough (and not more than twice the need)
+  Block blk;
+  for (size_t i = 0; i < c->idle.size(); ++i) {
+    if (c->idle[i].bytes >= total && c->idle[i].bytes <= 2 * total) {
+      blk = c->idle[i];
+      c->idle.erase(c->idle.begin() + i);
+      break;
+    }
+  }
+  if (!blk.ptr) {
+    CHECK(make_room(c, total));
+    if (c->held() + total > c->budget)
+      return fail(SGM_EBUSY, "batch needs %zu bytes, %zu of %zu held by batches in flight", total,
+                  c->inflight_bytes(), c->budget);
+    HIP_TRY(hipMalloc(&blk.ptr, total));
+    blk.bytes = total;
+  }
+  Batch b;
+  b.mem = blk;
+  b.stream = c->next_stream;
+  c->next_stream = (c->next_stream + 1) % sgm_ctx::kStreams;
+  hipStream_t s = c->streams[b.stream];
+  int rc = enqueue_frames(frames, n, plans, reinterpret_cast<char *>(blk.ptr), s);
+  if (rc == SGM_OK && hipEventCreateWithFlags(&b.done, hipEventDisableTiming) != hipSuccess)
+    rc = fail(SGM_EHIP, "hipEventCreate failed");
+  if (rc == SGM_OK && hipEventRecord(b.done, s) != hipSuccess) rc = fail(SGM_EHIP, "hipEventRecord failed");
+  if (rc != SGM_OK) {
+    (void)hipStreamSynchronize(s);
+    if (b.done) (void)hipEventDestroy(b.done);
+    c->idle.push_back(blk);
+    return rc;
+  }
+  *ticket = c->next_ticket++;
+  c->inflight[*ticket] = b;
+  return SGM_OK;
+}
+
+static int poll_locked(sgm_ctx *c, uint64_t ticket, int *done, bool block) {
+  auto it = c->inflight.find(ticket);
+  if (it == c->inflight.end()) return fail(SGM_ENOTFOUND, "unknown ticket %llu", (unsigned long long)ticket);
+  hipError_t e = block ? hipEventSynchronize(it->second.done) : hipEventQuery(it->second.done);
+  if (e == hipErrorNotReady) {
+    *done = 0;
+    return SGM_OK;
+  }
+  if (e != hipSuccess) return fail(SGM_EHIP, "batch %llu: %s", (unsigned long long)ticket, hipGetErrorString(e));
+  (void)hipEventDestroy(it->second.done);
+  c->idle.push_back(it->second.mem);
+  c->inflight.erase(it);
+  *done = 1;
+  return SGM_OK;
+}
+
+int sgm_poll(sgm_ctx *c, uint64_t ticket, int *done) {
+  if (!c || !done) return fail(SGM_EINVAL, "ctx and done must be non-null");
+  std::lock_guard<std::mutex> lk(c->mu);
+  DeviceGuard g(c->device);
+  return poll_locked(c, ticket, done, false);
+}
+
+int sgm_wait(sgm_ctx *c, uint64_t ticket) {
+  if (!c) return fail(SGM_EINVAL, "ctx is null");
+  std::lock_guard<std::mutex> lk(c->mu);
+  DeviceGuard g(c->device);
+  int done = 0;
+  return poll_locked(c, ticket, &done, true);
+}
+
+int sgm_memory(sgm_ctx *c, size_t *in_flight_bytes, size_t *budget_bytes) {
+  if (!c) return fail(SGM_EINVAL, "ctx is null");
+  std::lock_guard<std::mutex> lk(c->mu);
+  if (in_flight_bytes) *in_flight_bytes = c->inflight_bytes();
+  if (budget_bytes) *budget_bytes = c->budget;
+  return SGM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,98 @@
+// Device helpers shared by the kernels: job lookup, DPP cross-lane moves and
+// reductions for 64-wide CDNA wavefronts, and batching of job tables into
+// launches.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <algorithm>
+#include <vector>
+
+#include "sgm_kernels.h"
+
+namespace sgmk {
+
+// DPP control words (GCN/CDNA "dpp_ctrl" encodings).
+enum : int {
+  kDppRowShr1 = 0x111,
+  kDppRowShr2 = 0x112,
+  kDppRowShr4 = 0x114,
+  kDppRowShr8 = 0x118,
+  kDppWaveShl1 = 0x130,  // lane i reads lane i+1 (lane 63 has no source)
+  kDppWaveShr1 = 0x138,  // lane i reads lane i-1 (lane 0 has no source)
+  kDppRowBcast15 = 0x142,
+  kDppRowBcast31 = 0x143,
+};
+
+// Value of lane i-1 (lane 0 gets `edge`).
+__device__ __forceinline__ uint32_t from_lower_lane(uint32_t v, uint32_t edge) {
+  return (uint32_t)__builtin_amdgcn_update_dpp((int)edge, (int)v, kDppWaveShr1, 0xF, 0xF, false);
+}
+// Value of lane i+1 (lane 63 gets `edge`).
+__device__ __forceinline__ uint32_t from_upper_lane(uint32_t v, uint32_t edge) {
+  return (uint32_t)__builtin_amdgcn_update_dpp((int)edge, (int)v, kDppWaveShl1, 0xF, 0xF, false);
+}
+
+// Unsigned minimum over all 64 lanes, returned as a wave-uniform value.
+// Rows of 16 lanes are reduced with row_shr (lanes whose source falls outside
+// the row keep the identity), then rows are combined with row_bcast:15/31;
+// lane 63 ends up with the full minimum.
+__device__ __forceinline__ uint32_t wave_min_u32(uint32_t v) {
+  const int id = -1;  // 0xFFFFFFFF: identity of unsigned min
+  v = min(v, (uint32_t)__builtin_amdgcn_update_dpp(id, (int)v, kDppRowShr1, 0xF, 0xF, false));
+  v = min(v, (uint32_t)__builtin_amdgcn_update_dpp(id, (int)v, kDppRowShr2, 0xF, 0xF, false));
+  v = min(v, (uint32_t)__builtin_amdgcn_update_dpp(id, (int)v, kDppRowShr4, 0xF, 0xF, false));
+  v = min(v, (uint32_t)__builtin_amdgcn_update_dpp(id, (int)v, kDppRowShr8, 0xF, 0xF, false));
+  v = min(v, (uint32_t)__builtin_amdgcn_update_dpp(id, (int)v, kDppRowBcast15, 0xA, 0xF, false));
+  v = min(v, (uint32_t)__builtin_amdgcn_update_dpp(id, (int)v, kDppRowBcast31, 0xC, 0xF, false));
+  return (uint32_t)__builtin_amdgcn_readlane((int)v, 63);
+}
+
+// Unsigned minimum over each aligned group of 16 lanes; every lane of the
+// group receives the group's minimum.
+__device__ __forceinline__ uint32_t row16_min_u32(uint32_t v) {
+  v = min(v, (uint32_t)__shfl_xor((int)v, 8, 16));
+  v = min(v, (uint32_t)__shfl_xor((int)v, 4, 16));
+  v = min(v, (uint32_t)__shfl_xor((int)v, 2, 16));
+  v = min(v, (uint32_t)__shfl_xor((int)v, 1, 16));
+  return v;
+}
+
+__device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// Index of the job owning global block (or wave) index `b`: the last job with
+// start <= b.  Jobs are sorted by start.
+template <class Job>
+__device__ __forceinline__ int find_job(const Job *jobs, int n, int b) {
+  int j = 0;
+  for (int k = 1; k < n; ++k)
+    if (b >= jobs[k].blk0) j = k;
+  return j;
+}
+
+template <class Job>
+struct JobTable {
+  Job j[kMaxJobs];
+  int n;
+};
+
+// Split `jobs` into tables of at most kMaxJobs entries, assign blk0 as the
+// running block count (blocks_of(job) blocks each) and call
+// launch(table, total_blocks) for each table.
+template <class Job, class BlocksOf, class Launch>
+void for_each_table(std::vector<Job> &jobs, BlocksOf blocks_of, Launch launch) {
+  for (size_t i = 0; i < jobs.size(); i += kMaxJobs) {
+    JobTable<Job> t;
+    t.n = (int)std::min<size_t>(kMaxJobs, jobs.size() - i);
+    long total = 0;
+    for (int k = 0; k < t.n; ++k) {
+      t.j[k] = jobs[i + k];
+      t.j[k].blk0 = (int)total;
+      total += blocks_of(t.j[k]);
+    }
+    if (total > 0) launch(t, (int)total);
+  }
+}
+
+}  // namespace sgmk

@@ -1,0 +1,175 @@
+// Disparity selection from the aggregated volume (sections 3.1.3 to 3.1.5).
+//
+// disp_kernel: one block per image row.  Groups of 16 lanes take one pixel at
+// a time, each lane K contiguous disparities.  A cell's 32-bit key
+// (S << 8) | d orders by cost and then by disparity, so an unsigned minimum
+// is the smallest-d argmin.  The left map D_L is the minimum key over d
+// (reduced across the 16 lanes); the right map D_R(x_r) = argmin_d
+// S(x_r + d, d) collects the same keys by LDS atomicMin into slot x - d.
+// After a barrier the row's left-right check is done from LDS.
+//
+// median_kernel: k x k median with clamped borders by an odd-even
+// transposition network on k*k registers.
+#include "device_util.h"
+
+namespace sgmk {
+
+template <int IN>
+__device__ __forceinline__ uint32_t load_cost_sum(const DispJob &J, int64_t cell, int64_t cells) {
+  if (IN == 0) return J.S[cell];
+  uint32_t s = 0;
+  if (IN == 1) {
+    const uint8_t *lr = reinterpret_cast<const uint8_t *>(J.lr);
+    for (int p = 0; p < J.P; ++p) s += lr[(int64_t)p * cells + cell];
+  } else {
+    const uint16_t *lr = reinterpret_cast<const uint16_t *>(J.lr);
+    for (int p = 0; p < J.P; ++p) s += lr[(int64_t)p * cells + cell];
+  }
+  return s;
+}
+
+template <int K, int IN>
+__global__ __launch_bounds__(256) void disp_kernel(JobTable<DispJob> t) {
+  extern __shared__ uint32_t smem[];
+  const int ji = find_job(t.j, t.n, (int)blockIdx.x);
+  const DispJob &J = t.j[ji];
+  const int y = (int)blockIdx.x - J.blk0;
+  const int W = J.W, D = J.D;
+  uint32_t *keyR = smem;                                      // [W]
+  uint16_t *dl = reinterpret_cast<uint16_t *>(smem + W);      // [W]
+  for (int i = threadIdx.x; i < W; i += blockDim.x) keyR[i] = 0xFFFFFFFFu;
+  __syncthreads();
+  const int64_t cells = (int64_t)J.H * W * D;
+  const int g = threadIdx.x >> 4, j = threadIdx.x & 15;
+  const int dbase = j * K;
+  for (int x = g; x < W; x += 16) {
+    const int64_t cell0 = ((int64_t)y * W + x) * D;
+    uint32_t best = 0xFFFFFFFFu;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const int d = dbase + k;
+      if (d < D) {
+        const uint32_t key = (load_cost_sum<IN>(J, cell0 + d, cells) << 8) | (uint32_t)d;
+        best = min(best, key);
+        if (J.lr_check && x >= d) atomicMin(&keyR[x - d], key);
+      }
+    }
+    best = row16_min_u32(best);
+    if (j == 0) dl[x] = (uint16_t)(best & 0xFF);
+  }
+  __syncthreads();
+  uint16_t *out = J.out + (int64_t)y * W;
+  for (int x = threadIdx.x; x < W; x += blockDim.x) {
+    const int d = dl[x];
+    int v = d;
+    if (J.lr_check) {
+      v = J.invalid;
+      const int xr = x - d;
+      if (xr >= 0) {
+        const int dr = (int)(keyR[xr] & 0xFF);
+        if (abs(d - dr) <= J.max_diff) v = d;
+      }
+    }
+    out[x] = (uint16_t)v;
+  }
+}
+
+template <int K>
+static void launch_disp_k(int in_kind, const JobTable<DispJob> &t, int blocks, size_t lds,
+                          hipStream_t s) {
+  switch (in_kind) {
+    case 0: hipLaunchKernelGGL((disp_kernel<K, 0>), dim3(blocks), dim3(256), lds, s, t); break;
+    case 1: hipLaunchKernelGGL((disp_kernel<K, 1>), dim3(blocks), dim3(256), lds, s, t); break;
+    default: hipLaunchKernelGGL((disp_kernel<K, 2>), dim3(blocks), dim3(256), lds, s, t); break;
+  }
+}
+
+void launch_disparity(std::vector<DispJob> jobs, int in_kind, hipStream_t s) {
+  // one launch per lanes-per-pixel width K (d per lane), so each frame gets
+  // the narrowest K with 16*K >= D
+  for (int K : {1, 2, 4, 8, 16}) {
+    std::vector<DispJob> sub;
+    int maxw = 0;
+    for (auto &j : jobs) {
+      int need = 1;
+      while (16 * need < j.D) need *= 2;
+      if (need == K) {
+        sub.push_back(j);
+        maxw = std::max(maxw, j.W);
+      }
+    }
+    if (sub.empty()) continue;
+    const size_t lds = (size_t)maxw * 6;
+    for_each_table(
+        sub, [](const DispJob &j) { return (long)j.H; },
+        [&](const JobTable<DispJob> &t, int blocks) {
+          switch (K) {
+            case 1: launch_disp_k<1>(in_kind, t, blocks, lds, s); break;
+            case 2: launch_disp_k<2>(in_kind, t, blocks, lds, s); break;
+            case 4: launch_disp_k<4>(in_kind, t, blocks, lds, s); break;
+            case 8: launch_disp_k<8>(in_kind, t, blocks, lds, s); break;
+            default: launch_disp_k<16>(in_kind, t, blocks, lds, s); break;
+          }
+        });
+  }
+}
+
+// ------------------------------------------------------------- median
+
+constexpr int kMedTile = 16;
+
+template <int N>
+__device__ __forceinline__ void oddeven_sort(uint32_t (&v)[N]) {
+#pragma unroll
+  for (int pass = 0; pass < N; ++pass) {
+#pragma unroll
+    for (int i = pass & 1; i + 1 < N; i += 2) {
+      const uint32_t a = v[i], b = v[i + 1];
+      v[i] = min(a, b);
+      v[i + 1] = max(a, b);
+    }
+  }
+}
+
+template <int KS>
+__global__ __launch_bounds__(256) void median_kernel(JobTable<MedianJob> t) {
+  const int ji = find_job(t.j, t.n, (int)blockIdx.x);
+  const MedianJob &J = t.j[ji];
+  const int tb = (int)blockIdx.x - J.blk0;
+  const int x = (tb % J.tiles_x) * kMedTile + (int)(threadIdx.x & (kMedTile - 1));
+  const int y = (tb / J.tiles_x) * kMedTile + (int)(threadIdx.x >> 4);
+  if (x >= J.W || y >= J.H) return;
+  constexpr int R = KS / 2;
+  uint32_t v[KS * KS];
+#pragma unroll
+  for (int dy = -R; dy <= R; ++dy) {
+    const int yy = min(max(y + dy, 0), J.H - 1);
+#pragma unroll
+    for (int dx = -R; dx <= R; ++dx) {
+      const int xx = min(max(x + dx, 0), J.W - 1);
+      v[(dy + R) * KS + dx + R] = J.in[(int64_t)yy * J.W + xx];
+    }
+  }
+  oddeven_sort<KS * KS>(v);
+  J.out[(int64_t)y * J.W + x] = (uint16_t)v[(KS * KS) / 2];
+}
+
+void launch_median(std::vector<MedianJob> jobs, hipStream_t s) {
+  for (int K : {3, 5}) {
+    std::vector<MedianJob> sub;
+    for (auto &j : jobs)
+      if (j.k == K) {
+        j.tiles_x = (j.W + kMedTile - 1) / kMedTile;
+        sub.push_back(j);
+      }
+    if (sub.empty()) continue;
+    for_each_table(
+        sub, [](const MedianJob &j) { return (long)j.tiles_x * ((j.H + kMedTile - 1) / kMedTile); },
+        [&](const JobTable<MedianJob> &t, int blocks) {
+          if (K == 3) hipLaunchKernelGGL(median_kernel<3>, dim3(blocks), dim3(256), 0, s, t);
+          else hipLaunchKernelGGL(median_kernel<5>, dim3(blocks), dim3(256), 0, s, t);
+        });
+  }
+}
+
+}  // namespace sgmk

@@ -1,0 +1,103 @@
+// Internal interface between the C-ABI layer (api.hip) and the HIP kernels.
+//
+// Every kernel takes a small table of "jobs" by value (one job = one frame's
+// share of that stage) so that one launch can cover a whole batch of frames
+// of different sizes; a single-frame call is a table of one.  A job records
+// the first block index it owns (blk0); a block finds its job by scanning the
+// table (at most kMaxJobs entries, all in the kernel-argument segment).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <vector>
+
+namespace sgmk {
+
+constexpr int kMaxJobs = 24;  // jobs per launch (kernel arguments stay < 4 KB)
+
+// ---------------------------------------------------------------- census
+struct CensusJob {
+  const uint8_t *img;
+  int64_t pitch;
+  uint64_t *out;  // [H][W]
+  int W, H, cw, ch;
+  int blk0, tiles_x;
+};
+void launch_census(std::vector<CensusJob> jobs, hipStream_t s);
+
+// ------------------------------------------------------------------ cost
+struct CostJob {
+  const uint64_t *cl, *cr;
+  uint16_t *cost;  // [H][W][D]
+  int W, H, D, nbits;
+  int blk0, chunks_x;
+};
+void launch_cost(std::vector<CostJob> jobs, hipStream_t s);
+
+// ----------------------------------------------------------- aggregation
+// Source of the matching costs inside the aggregation kernel.
+enum AggSource { kFromCost = 0, kFromCensus = 1 };
+
+struct AggJob {
+  const uint16_t *cost;          // kFromCost: [H][W][D]
+  const uint64_t *cl, *cr;       // kFromCensus: [H][W] each
+  void *lr;                      // path costs [P][H][W][D], uint8 or uint16
+  int W, H, D, nbits, p1, p2;
+  int ndirs;                     // P = number of active directions
+  int dirs[8];                   // direction index of each slot
+  int line0[9];                  // first scanline (wave) of each slot; line0[P] = total
+  int blk0;                      // first global wave (one wave per scanline)
+};
+// dpl: disparities per lane (D <= 64 * dpl); lr_bytes: 1 or 2.
+void launch_aggregate(std::vector<AggJob> jobs, AggSource src, int dpl, int lr_bytes,
+                      hipStream_t s);
+// Number of scanlines of direction `dir` on a W x H image.
+int agg_lines(int dir, int W, int H);
+
+// Sum of the P path-cost volumes into S (uint16 [cells]).
+struct SumJob {
+  const void *lr;
+  uint16_t *S;
+  int64_t cells;
+  int P;
+  int blk0;
+};
+void launch_sum(std::vector<SumJob> jobs, int lr_bytes, hipStream_t s);
+
+// ------------------------------------------------ disparity selection
+// WTA, right-view disparity and left-right check for one image row per
+// block.  Input is either S (uint16) or the P path-cost volumes (summed on
+// the fly).
+struct DispJob {
+  const uint16_t *S;  // [H][W][D] or null
+  const void *lr;     // [P][H][W][D] or null
+  int P;
+  uint16_t *out;      // [H][W]: LR-checked map (or D_L when lr_check = 0)
+  int W, H, D;
+  int lr_check, max_diff;
+  int invalid;
+  int blk0;
+};
+// in_kind: 0 = S, 1 = uint8 path costs, 2 = uint16 path costs
+void launch_disparity(std::vector<DispJob> jobs, int in_kind, hipStream_t s);
+
+struct MedianJob {
+  const uint16_t *in;
+  uint16_t *out;
+  int W, H, k;
+  int blk0, tiles_x;
+};
+void launch_median(std::vector<MedianJob> jobs, hipStream_t s);
+
+// --------------------------------------------------------------- U/V maps
+struct UVJob {
+  const uint16_t *disp;
+  uint16_t *U, *V;  // [D][W], [H][D]
+  int W, H, D;
+  int blk0;         // first block; blocks [blk0, blk0+H) build V rows,
+  int ublocks;      // then `ublocks` blocks of 64 columns build U
+};
+void launch_uv(std::vector<UVJob> jobs, hipStream_t s);
+
+}  // namespace sgmk

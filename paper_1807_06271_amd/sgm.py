@@ -1,0 +1,326 @@
+"""Python binding of libsgm.so (include/sgm.h): argument marshalling only.
+
+Every entry point keeps the C name and takes torch CUDA tensors (device
+memory) plus an optional torch stream; all computation runs in the library's
+HIP kernels.  There is no fallback: if libsgm.so is missing or the GPU is not
+usable, the calls raise.
+
+    from paper_1807_06271_amd import sgm
+    ctx = sgm.Context()
+    p = sgm.Params(width=1242, height=375, max_disp=128)
+    sgm.sgm_census(ctx, p, left, census_l)
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+import os
+
+import torch  # loaded first so that libsgm.so shares torch's HIP runtime
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libsgm.so")
+
+SGM_OK, SGM_EINVAL, SGM_ENOMEM, SGM_EHIP, SGM_EBUSY, SGM_ENOTFOUND = 0, -1, -2, -3, -4, -5
+STATUS_NAMES = {0: "SGM_OK", -1: "SGM_EINVAL", -2: "SGM_ENOMEM", -3: "SGM_EHIP", -4: "SGM_EBUSY",
+                -5: "SGM_ENOTFOUND"}
+
+PATH_L2R, PATH_R2L, PATH_T2B, PATH_B2T = 1, 2, 4, 8
+PATH_TL2BR, PATH_BR2TL, PATH_TR2BL, PATH_BL2TR = 16, 32, 64, 128
+PATHS_PAPER4 = PATH_L2R | PATH_TL2BR | PATH_T2B | PATH_TR2BL
+PATHS_HV4 = PATH_L2R | PATH_R2L | PATH_T2B | PATH_B2T
+PATHS_ALL8 = 0xFF
+
+EXPORTS = ["sgm_validate", "sgm_create", "sgm_destroy", "sgm_last_error", "sgm_census", "sgm_cost", "sgm_aggregate",
+           "sgm_disparity", "uv_maps", "sgm_submit", "sgm_poll", "sgm_wait", "sgm_memory"]
+
+
+class SgmError(RuntimeError):
+    def __init__(self, status: int, what: str, message: str):
+        super().__init__("%s: %s (%s)" % (what, message, STATUS_NAMES.get(status, status)))
+        self.status = status
+
+
+class sgm_params(ctypes.Structure):
+    _fields_ = [("width", ctypes.c_int32), ("height", ctypes.c_int32), ("max_disp", ctypes.c_int32),
+                ("census_w", ctypes.c_int32), ("census_h", ctypes.c_int32),
+                ("path_mask", ctypes.c_uint32), ("p1", ctypes.c_uint16), ("p2", ctypes.c_uint16),
+                ("lr_check", ctypes.c_int32), ("lr_max_diff", ctypes.c_int32),
+                ("median", ctypes.c_int32), ("invalid", ctypes.c_uint16),
+                ("reserved", ctypes.c_uint16)]
+
+
+class sgm_frame(ctypes.Structure):
+    _fields_ = [("left", ctypes.c_void_p), ("right", ctypes.c_void_p), ("pitch", ctypes.c_int64),
+                ("p", sgm_params), ("disp", ctypes.c_void_p), ("umap", ctypes.c_void_p),
+                ("vmap", ctypes.c_void_p)]
+
+
+@dataclasses.dataclass
+class Params:
+    """Frame parameters (mirrors sgm_params)."""
+    width: int
+    height: int
+    max_disp: int
+    census_w: int = 9
+    census_h: int = 7
+    path_mask: int = PATHS_ALL8
+    p1: int = 10
+    p2: int = 120
+    lr_check: int = 1
+    lr_max_diff: int = 1
+    median: int = 3
+    invalid: int | None = None
+
+    @property
+    def nbits(self) -> int:
+        return self.census_w * self.census_h - 1
+
+    @property
+    def paths(self) -> int:
+        return bin(self.path_mask).count("1")
+
+    def inv(self) -> int:
+        return (255 if self.max_disp <= 255 else 65535) if self.invalid is None else self.invalid
+
+    def c(self) -> sgm_params:
+        return sgm_params(self.width, self.height, self.max_disp, self.census_w, self.census_h,
+                          self.path_mask, self.p1, self.p2, self.lr_check, self.lr_max_diff,
+                          self.median, self.inv(), 0)
+
+    def disp_evals(self) -> int:
+        """W*H*D*paths: the unit of the throughput metric."""
+        return self.width * self.height * self.max_disp * self.paths
+
+
+_lib = None
+
+
+def lib():
+    """Load libsgm.so once (raises if it was not built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libsgm.so is not built; run `python -m paper_1807_06271_amd.build` "
+                               "(there is no CPU fallback)")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i32, P = ctypes.c_void_p, ctypes.c_int, ctypes.POINTER
+        L.sgm_validate.argtypes = [P(sgm_params)]
+        L.sgm_create.argtypes = [P(vp), i32, ctypes.c_size_t]
+        L.sgm_destroy.argtypes = [vp]
+        L.sgm_last_error.argtypes = []
+        L.sgm_last_error.restype = ctypes.c_char_p
+        L.sgm_census.argtypes = [vp, P(sgm_params), vp, ctypes.c_int64, vp, vp]
+        L.sgm_cost.argtypes = [vp, P(sgm_params), vp, vp, vp, vp]
+        L.sgm_aggregate.argtypes = [vp, P(sgm_params), vp, vp, vp]
+        L.sgm_disparity.argtypes = [vp, P(sgm_params), vp, vp, vp]
+        L.uv_maps.argtypes = [vp, P(sgm_params), vp, vp, vp, vp]
+        L.sgm_submit.argtypes = [vp, P(sgm_frame), i32, P(ctypes.c_uint64)]
+        L.sgm_poll.argtypes = [vp, ctypes.c_uint64, P(i32)]
+        L.sgm_wait.argtypes = [vp, ctypes.c_uint64]
+        L.sgm_memory.argtypes = [vp, P(ctypes.c_size_t), P(ctypes.c_size_t)]
+        for name in EXPORTS:
+            if name != "sgm_last_error":
+                getattr(L, name).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _check(rc: int, what: str) -> int:
+    if rc != SGM_OK:
+        raise SgmError(rc, what, lib().sgm_last_error().decode(errors="replace"))
+    return rc
+
+
+def _stream(stream) -> int | None:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
+
+
+def _ptr(t) -> int | None:
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError("expected a CUDA (HIP) torch tensor")
+    if not t.is_contiguous():
+        raise ValueError("tensor must be contiguous")
+    return t.data_ptr()
+
+
+def _need(t, shape, dtype, name):
+    if tuple(t.shape) != tuple(shape) or t.dtype != dtype:
+        raise ValueError("%s must be %s %s, got %s %s" % (name, dtype, tuple(shape), t.dtype, tuple(t.shape)))
+
+
+def sgm_validate(p: Params) -> None:
+    """Raise SgmError(SGM_EINVAL) if the parameters are not accepted (no GPU used)."""
+    _check(lib().sgm_validate(ctypes.byref(p.c())), "sgm_validate")
+
+
+class Context:
+    """An sgm_ctx on one device; frees it on close() / exit / GC."""
+
+    def __init__(self, device: int = 0, hbm_budget_bytes: int = 0):
+        self._h = ctypes.c_void_p()
+        _check(lib().sgm_create(ctypes.byref(self._h), device, hbm_budget_bytes), "sgm_create")
+        self.device = device
+
+    @property
+    def handle(self):
+        if not self._h:
+            raise RuntimeError("context is closed")
+        return self._h
+
+    def close(self):
+        if self._h:
+            h, self._h = self._h, ctypes.c_void_p()
+            _check(lib().sgm_destroy(h), "sgm_destroy")
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def sgm_census(ctx: Context, p: Params, img, census, stream=None):
+    _need(census, (p.height, p.width), torch.uint64, "census")
+    if img.dtype != torch.uint8 or img.dim() != 2 or img.shape[0] != p.height or img.shape[1] < p.width:
+        raise ValueError("img must be uint8 [H][pitch >= W]")
+    pitch = img.stride(0)
+    if img.stride(1) != 1:
+        raise ValueError("img rows must be contiguous")
+    _check(lib().sgm_census(ctx.handle, ctypes.byref(p.c()), img.data_ptr(), pitch, _ptr(census),
+                            _stream(stream)), "sgm_census")
+
+
+def sgm_cost(ctx: Context, p: Params, cl, cr, cost, stream=None):
+    for t, n in ((cl, "cl"), (cr, "cr")):
+        _need(t, (p.height, p.width), torch.uint64, n)
+    _need(cost, (p.height, p.width, p.max_disp), torch.uint16, "cost")
+    _check(lib().sgm_cost(ctx.handle, ctypes.byref(p.c()), _ptr(cl), _ptr(cr), _ptr(cost),
+                          _stream(stream)), "sgm_cost")
+
+
+def sgm_aggregate(ctx: Context, p: Params, cost, aggr, stream=None):
+    for t, n in ((cost, "cost"), (aggr, "aggr")):
+        _need(t, (p.height, p.width, p.max_disp), torch.uint16, n)
+    _check(lib().sgm_aggregate(ctx.handle, ctypes.byref(p.c()), _ptr(cost), _ptr(aggr), _stream(stream)),
+           "sgm_aggregate")
+
+
+def sgm_disparity(ctx: Context, p: Params, aggr, disp, stream=None):
+    _need(aggr, (p.height, p.width, p.max_disp), torch.uint16, "aggr")
+    _need(disp, (p.height, p.width), torch.uint16, "disp")
+    _check(lib().sgm_disparity(ctx.handle, ctypes.byref(p.c()), _ptr(aggr), _ptr(disp), _stream(stream)),
+           "sgm_disparity")
+
+
+def uv_maps(ctx: Context, p: Params, disp, umap, vmap, stream=None):
+    _need(disp, (p.height, p.width), torch.uint16, "disp")
+    _need(umap, (p.max_disp, p.width), torch.uint16, "umap")
+    _need(vmap, (p.height, p.max_disp), torch.uint16, "vmap")
+    _check(lib().uv_maps(ctx.handle, ctypes.byref(p.c()), _ptr(disp), _ptr(umap), _ptr(vmap),
+                         _stream(stream)), "uv_maps")
+
+
+@dataclasses.dataclass
+class Frame:
+    """One frame for sgm_submit: inputs and (preallocated) outputs."""
+    p: Params
+    left: torch.Tensor
+    right: torch.Tensor
+    disp: torch.Tensor
+    umap: torch.Tensor | None = None
+    vmap: torch.Tensor | None = None
+
+    @staticmethod
+    def alloc(p: Params, left, right, uv: bool = True) -> "Frame":
+        dev = left.device
+        disp = torch.empty((p.height, p.width), dtype=torch.uint16, device=dev)
+        u = torch.empty((p.max_disp, p.width), dtype=torch.uint16, device=dev) if uv else None
+        v = torch.empty((p.height, p.max_disp), dtype=torch.uint16, device=dev) if uv else None
+        return Frame(p, left, right, disp, u, v)
+
+    def c(self) -> sgm_frame:
+        for t, n in ((self.left, "left"), (self.right, "right")):
+            if t.dtype != torch.uint8 or t.dim() != 2 or t.shape[0] != self.p.height \
+                    or t.shape[1] < self.p.width or t.stride(1) != 1:
+                raise ValueError("%s must be uint8 [H][pitch >= W] with contiguous rows" % n)
+        if self.left.stride(0) != self.right.stride(0):
+            raise ValueError("left and right must share one pitch")
+        _need(self.disp, (self.p.height, self.p.width), torch.uint16, "disp")
+        if (self.umap is None) != (self.vmap is None):
+            raise ValueError("give both umap and vmap or neither")
+        if self.umap is not None:
+            _need(self.umap, (self.p.max_disp, self.p.width), torch.uint16, "umap")
+            _need(self.vmap, (self.p.height, self.p.max_disp), torch.uint16, "vmap")
+        return sgm_frame(self.left.data_ptr(), self.right.data_ptr(), self.left.stride(0), self.p.c(),
+                         _ptr(self.disp), _ptr(self.umap), _ptr(self.vmap))
+
+
+def sgm_submit(ctx: Context, frames) -> int:
+    """Enqueue a batch; returns its ticket.  Raises SgmError with status
+    SGM_EBUSY when the batch does not fit next to the batches in flight."""
+    arr = (sgm_frame * len(frames))(*[f.c() for f in frames])
+    t = ctypes.c_uint64()
+    _check(lib().sgm_submit(ctx.handle, arr, len(frames), ctypes.byref(t)), "sgm_submit")
+    return t.value
+
+
+def try_submit(ctx: Context, frames) -> int | None:
+    """Like sgm_submit, but returns None instead of raising on SGM_EBUSY."""
+    arr = (sgm_frame * len(frames))(*[f.c() for f in frames])
+    t = ctypes.c_uint64()
+    rc = lib().sgm_submit(ctx.handle, arr, len(frames), ctypes.byref(t))
+    if rc == SGM_EBUSY:
+        return None
+    _check(rc, "sgm_submit")
+    return t.value
+
+
+def sgm_poll(ctx: Context, ticket: int) -> bool:
+    done = ctypes.c_int()
+    _check(lib().sgm_poll(ctx.handle, ticket, ctypes.byref(done)), "sgm_poll")
+    return bool(done.value)
+
+
+def sgm_wait(ctx: Context, ticket: int) -> None:
+    _check(lib().sgm_wait(ctx.handle, ticket), "sgm_wait")
+
+
+def sgm_memory(ctx: Context):
+    a, b = ctypes.c_size_t(), ctypes.c_size_t()
+    _check(lib().sgm_memory(ctx.handle, ctypes.byref(a), ctypes.byref(b)), "sgm_memory")
+    return a.value, b.value
+
+
+def run_stages(ctx: Context, p: Params, left, right, stream=None, keep=False):
+    """The per-frame path through the five stage calls.  Returns the final
+    disparity map, U-map and V-map (and, with keep=True, every intermediate)."""
+    dev = left.device
+    H, W, D = p.height, p.width, p.max_disp
+    cl = torch.empty((H, W), dtype=torch.uint64, device=dev)
+    cr = torch.empty((H, W), dtype=torch.uint64, device=dev)
+    cost = torch.empty((H, W, D), dtype=torch.uint16, device=dev)
+    aggr = torch.empty((H, W, D), dtype=torch.uint16, device=dev)
+    disp = torch.empty((H, W), dtype=torch.uint16, device=dev)
+    u = torch.empty((D, W), dtype=torch.uint16, device=dev)
+    v = torch.empty((H, D), dtype=torch.uint16, device=dev)
+    sgm_census(ctx, p, left, cl, stream)
+    sgm_census(ctx, p, right, cr, stream)
+    sgm_cost(ctx, p, cl, cr, cost, stream)
+    sgm_aggregate(ctx, p, cost, aggr, stream)
+    sgm_disparity(ctx, p, aggr, disp, stream)
+    uv_maps(ctx, p, disp, u, v, stream)
+    out = {"disp": disp, "umap": u, "vmap": v}
+    if keep:
+        out.update(census_l=cl, census_r=cr, cost=cost, aggr=aggr)
+    return out
