@@ -1,0 +1,287 @@
+"""Benchmark of the SGM hot path on one MI355X.
+
+    python bench.py [--steps K] [--warmup W] [--extras none|batch|all] [--serve-seconds S]
+
+A step is one pass of the whole path (Census of both views, Hamming costs,
+8-path aggregation, WTA + right-view disparity + left-right check, 3x3
+median, U-/V-maps) over one synthetic 1242x375 pair with D = 128 (the
+KITTI-shaped workload), inputs already in device memory.  Steps go through
+sgm_submit on the library's streams with up to 4 frames in flight; the timed
+region is bracketed by torch.cuda.synchronize().
+
+Prints ONE JSON line: the throughput in Mdisp-evals/s (W*H*D*paths per
+second), the aggregation kernel's roofline position (its average launch time
+from HIP events the library records around it on its own stream), the CPU
+oracle timed on a bounded sample of the same workload, and secondary
+measurements (per-frame stage calls, a batch of 32 mixed pairs, a batch of 8
+1920x1080 D=256 pairs, and the multi-camera request loop).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
+ALG_BYTES_PER_EVAL = 4         # read + write of a uint16 running sum per path and cell
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def kitti_params(sgm, W=1242, H=375, D=128):
+    return sgm.Params(width=W, height=H, max_disp=D, census_w=9, census_h=7, path_mask=0xFF,
+                      p1=10, p2=120, lr_check=1, median=3)
+
+
+def time_submit_stream(torch, sgm, ctx, frames_fn, steps, warmup, depth=4):
+    """Run `steps` submits of one batch each, keeping up to `depth` in flight.
+    Returns (seconds, list of per-step Frame lists)."""
+    outs = [frames_fn(i) for i in range(depth)]
+
+    def run(n):
+        inflight = []
+        for s in range(n):
+            if len(inflight) >= depth:
+                sgm.sgm_wait(ctx, inflight.pop(0))
+            inflight.append(sgm.sgm_submit(ctx, outs[s % depth]))
+        for t in inflight:
+            sgm.sgm_wait(ctx, t)
+
+    run(warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    run(steps)
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0, outs
+
+
+def cpu_baseline(left, right, p, seconds_target=12.0):
+    from oracle import oracle as O
+    threads = O.threads()
+    runs, t_total = 0, 0.0
+    while t_total < seconds_target or runs == 0:
+        t0 = time.perf_counter()
+        O.sgm(left, right, p.max_disp, p.census_w, p.census_h, p.path_mask, p.p1, p.p2, True,
+              p.lr_max_diff, p.median, p.inv())
+        t_total += time.perf_counter() - t0
+        runs += 1
+        if runs >= 5:
+            break
+    return {"value": round(runs * p.disp_evals() / t_total / 1e6, 2), "unit": "Mdisp-evals/s",
+            "cores": threads, "kind": "oracle",
+            "sample": "%d full %dx%d D=%d 8-path pairs through the C oracle (-O2, OpenMP over "
+                      "scanlines), %.1f s" % (runs, p.width, p.height, p.max_disp, t_total)}
+
+
+def bench_batch32(torch, sgm, ctx, synthetic):
+    specs = synthetic.mixed_batch_specs(32, seed=2000)
+    frames = []
+    for (W, H, D, seed) in specs:
+        L, R, _ = synthetic.make_pair("kitti", seed, W, H, D)
+        p = kitti_params(sgm, W, H, D)
+        frames.append(sgm.Frame.alloc(p, torch.from_numpy(L).cuda(), torch.from_numpy(R).cuda()))
+    evals = sum(f.p.disp_evals() for f in frames)
+    res = {}
+    # one submit of all 32
+    for _ in range(2):
+        sgm.sgm_wait(ctx, sgm.sgm_submit(ctx, frames))
+    torch.cuda.synchronize()
+    reps = 5
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        sgm.sgm_wait(ctx, sgm.sgm_submit(ctx, frames))
+    torch.cuda.synchronize()
+    tb = (time.perf_counter() - t0) / reps
+    batched = [f.disp.clone() for f in frames]
+    # 32 sequential per-frame submits, each waited for
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        for f in frames:
+            sgm.sgm_wait(ctx, sgm.sgm_submit(ctx, [f]))
+    torch.cuda.synchronize()
+    ts = (time.perf_counter() - t0) / reps
+    same = all(torch.equal(a, f.disp) for a, f in zip(batched, frames))
+    # 32 sequential per-frame stage-call pipelines
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for f in frames:
+        sgm.run_stages(ctx, f.p, f.left, f.right)
+    torch.cuda.synchronize()
+    tst = time.perf_counter() - t0
+    res.update(frames=32, disp_evals=evals, batched_ms=tb * 1e3,
+               batched_mdisp_evals_per_s=evals / tb / 1e6,
+               sequential_submit_ms=ts * 1e3, sequential_submit_mdisp_evals_per_s=evals / ts / 1e6,
+               sequential_stage_calls_ms=tst * 1e3,
+               sequential_stage_calls_mdisp_evals_per_s=evals / tst / 1e6,
+               batched_equals_sequential=bool(same))
+    return res
+
+
+def bench_large(torch, sgm, ctx, synthetic, nframes=8):
+    frames = []
+    for i in range(nframes):
+        L, R, _ = synthetic.make_pair("large", 4000 + i)
+        p = kitti_params(sgm, 1920, 1080, 256)
+        p.invalid = 65535
+        frames.append(sgm.Frame.alloc(p, torch.from_numpy(L).cuda(), torch.from_numpy(R).cuda()))
+    evals = sum(f.p.disp_evals() for f in frames)
+    sgm.sgm_wait(ctx, sgm.sgm_submit(ctx, frames))
+    sgm.sgm_profile_read(ctx, reset=True)
+    torch.cuda.synchronize()
+    reps = 2
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        sgm.sgm_wait(ctx, sgm.sgm_submit(ctx, frames))
+    torch.cuda.synchronize()
+    t = (time.perf_counter() - t0) / reps
+    prof = sgm.sgm_profile_read(ctx, reset=True)
+    agg_ms, agg_n = prof["aggregate"]
+    agg_avg = agg_ms / max(agg_n, 1)
+    achieved = ALG_BYTES_PER_EVAL * evals / (agg_avg * 1e-3) / 1e9
+    return {"frames": nframes, "width": 1920, "height": 1080, "max_disp": 256, "paths": 8,
+            "batch_ms": t * 1e3, "mdisp_evals_per_s": evals / t / 1e6, "fps": nframes / t,
+            "aggregate_launch_ms": agg_avg,
+            "aggregate_alg_GBs": achieved, "aggregate_hbm_frac": achieved / HBM_PEAK_GBS,
+            "stage_ms_per_batch": {k: v[0] / reps for k, v in prof.items()}}
+
+
+def bench_serve(torch, sgm, synthetic, seconds):
+    from paper_1807_06271_amd import serve
+    cams = []
+    for cam in range(4):
+        sc = synthetic.camera_scene(cam)
+        pairs = [synthetic.render_pair(sc, k)[:2] for k in range(3)]
+        p = kitti_params(sgm, sc.width, sc.height, 128)
+        cams.append(serve.Camera(p, pairs))
+    trace = synthetic.poisson_trace(4, 30.0, seconds, seed=3000)
+    out = {"cameras": 4, "fps_per_camera": 30, "seconds": seconds, "frames": len(trace)}
+    with sgm.Context(0) as ctx:
+        # warm the batch-block cache and the kernels
+        serve.serve(ctx, cams, [(0.0, c, 0) for c in range(4)], continuous=True)
+        for mode, cont in (("continuous_batching", True), ("per_frame", False)):
+            stats, _ = serve.serve(ctx, cams, trace, continuous=cont)
+            out[mode] = stats
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--extras", choices=["none", "batch", "all"], default="all")
+    ap.add_argument("--serve-seconds", type=float, default=10.0)
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(frames would shard across GPUs with no exchange; see the design notes)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from gen import synthetic
+    from paper_1807_06271_amd import sgm
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    sgm.lib()  # raises if libsgm.so is missing: no fallback
+
+    left, right, _ = synthetic.make_pair("kitti", 1001)
+    p = kitti_params(sgm)
+    L = torch.from_numpy(left).cuda()
+    R = torch.from_numpy(right).cuda()
+    ctx = sgm.Context(0)
+    sgm.sgm_profile(ctx, True)
+
+    log("main: 1242x375 D=128 8 paths, steps", args.steps)
+    dt, outs = time_submit_stream(torch, sgm, ctx, lambda i: [sgm.Frame.alloc(p, L, R)],
+                                  args.steps, args.warmup)
+    prof = sgm.sgm_profile_read(ctx, reset=True)
+    evals = p.disp_evals()
+    value = evals * args.steps / dt / 1e6
+    # per-stage averages over warmup + timed steps (every batch is profiled)
+    n_batches = args.steps + args.warmup
+    stage_avg_ms = {k: v[0] / max(v[1], 1) for k, v in prof.items()}
+    agg_ms = stage_avg_ms["aggregate"]
+    achieved = ALG_BYTES_PER_EVAL * evals / (agg_ms * 1e-3) / 1e9
+
+    # frame latency of the fused path, one frame at a time
+    lat = []
+    for _ in range(20):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sgm.sgm_wait(ctx, sgm.sgm_submit(ctx, outs[0]))
+        lat.append(time.perf_counter() - t0)
+    lat_ms = np.array(lat) * 1e3
+
+    # per-frame stage-call path (materialised cost and S volumes)
+    for _ in range(2):
+        sgm.run_stages(ctx, p, L, R)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    nst = 10
+    for _ in range(nst):
+        sgm.run_stages(ctx, p, L, R)
+    torch.cuda.synchronize()
+    stage_path = evals * nst / (time.perf_counter() - t0) / 1e6
+
+    extras = {}
+    if args.extras in ("batch", "all"):
+        log("batch of 32 mixed pairs")
+        extras["batch32_mixed"] = bench_batch32(torch, sgm, ctx, synthetic)
+        log("batch of 8 1920x1080 D=256")
+        extras["batch8_1920x1080_d256"] = bench_large(torch, sgm, ctx, synthetic)
+    if args.extras == "all":
+        log("request loop, 4 cameras,", args.serve_seconds, "s per mode")
+        extras["served_4cams"] = bench_serve(torch, sgm, synthetic, args.serve_seconds)
+    ctx.close()
+
+    log("cpu baseline")
+    cpu = cpu_baseline(left, right, p, args.cpu_seconds)
+
+    line = {
+        "metric": "SGM Mdisp-evals/s (W*H*D*paths), whole path census..U/V maps",
+        "value": round(value, 2),
+        "unit": "Mdisp-evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(dt / args.steps * 1e3, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u16",
+        "data": "synthetic",
+        "config": {"workload": "1242x375 uint8 pair, D=128, Census 9x7, 8 paths, P1=10, P2=120, "
+                               "LR |dL-dR|<=1, 3x3 median, U/V maps (KITTI-shaped slanted planes)",
+                   "frames_per_step": 1, "in_flight": 4, "path": "sgm_submit (fused)"},
+        "fps": round(args.steps / dt, 1),
+        "frame_latency_ms": {"p50": float(np.percentile(lat_ms, 50)), "p99": float(np.percentile(lat_ms, 99))},
+        "stage_avg_ms": {k: round(v, 5) for k, v in stage_avg_ms.items()},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "kernel": "agg_kernel (8 directions, costs from Census codes)",
+                     "alg_bytes_per_launch": ALG_BYTES_PER_EVAL * evals,
+                     "avg_launch_ms": round(agg_ms, 5), "launches": prof["aggregate"][1],
+                     "batches_profiled": n_batches},
+        "per_frame_stage_calls_mdisp_evals_per_s": round(stage_path, 2),
+        "cpu_baseline": cpu,
+        "extras": extras,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -177,6 +177,24 @@ int sgm_poll(sgm_ctx *ctx, uint64_t ticket, int *done);
 /* Block until the ticket's batch has finished, then behave as sgm_poll. */
 int sgm_wait(sgm_ctx *ctx, uint64_t ticket);
 
+/* Stage timing of batches (sgm_submit).  While enabled, every stage of a
+ * batch is bracketed by HIP events on the batch's stream; when the batch is
+ * found done (sgm_poll / sgm_wait) the elapsed times are added per stage.
+ * A stage is one kernel launch per group of frames with the same kernel
+ * variant (a batch of uniform frames: one launch per stage). */
+enum {
+  SGM_STAGE_CENSUS = 0,
+  SGM_STAGE_AGGREGATE = 1,
+  SGM_STAGE_DISPARITY = 2,
+  SGM_STAGE_MEDIAN = 3,
+  SGM_STAGE_UV = 4,
+  SGM_NSTAGES = 5
+};
+int sgm_profile(sgm_ctx *ctx, int enable);
+/* ms[SGM_NSTAGES]: summed milliseconds; count[SGM_NSTAGES]: launches summed
+ * (either may be NULL).  reset != 0 clears the sums after reading. */
+int sgm_profile_read(sgm_ctx *ctx, double *ms, uint64_t *count, int reset);
+
 /* Bytes of budget currently held by in-flight batches, and the budget. */
 int sgm_memory(sgm_ctx *ctx, size_t *in_flight_bytes, size_t *budget_bytes);
 

@@ -88,10 +88,17 @@ struct Block {
   size_t bytes = 0;
 };
 
+struct StageEvents {
+  int stage;
+  int launches;
+  hipEvent_t begin, end;
+};
+
 struct Batch {
   hipEvent_t done = nullptr;
   Block mem;
   int stream = 0;
+  std::vector<StageEvents> prof;  // empty unless profiling
 };
 
 }  // namespace
@@ -107,6 +114,9 @@ struct sgm_ctx {
   static constexpr int kStreams = 4;
   hipStream_t streams[kStreams] = {};
   int next_stream = 0;
+  bool profiling = false;
+  double stage_ms[SGM_NSTAGES] = {};
+  uint64_t stage_count[SGM_NSTAGES] = {};
 
   size_t held() const {
     size_t s = stage.bytes;
@@ -215,8 +225,31 @@ FramePlan plan_frame(const sgm_params &p, size_t base) {
 // Enqueue census -> aggregation (costs recomputed from the Census codes) ->
 // disparity selection -> median -> U/V maps for `n` frames on `s`, with the
 // frames' scratch at `mem` laid out by plan_frame.
+// Brackets the launches of one stage with timing events when profiling.
+struct StageMark {
+  std::vector<StageEvents> *out;
+  hipStream_t s;
+  StageEvents cur{};
+  int begin(int stage) {
+    if (!out) return SGM_OK;
+    cur = StageEvents{stage, 0, nullptr, nullptr};
+    HIP_TRY(hipEventCreate(&cur.begin));
+    HIP_TRY(hipEventCreate(&cur.end));
+    HIP_TRY(hipEventRecord(cur.begin, s));
+    return SGM_OK;
+  }
+  int end(int launches) {
+    if (!out) return SGM_OK;
+    cur.launches = launches;
+    HIP_TRY(hipEventRecord(cur.end, s));
+    out->push_back(cur);
+    return SGM_OK;
+  }
+};
+
 int enqueue_frames(const sgm_frame *fr, int n, const std::vector<FramePlan> &plans, char *mem,
-                   hipStream_t s) {
+                   hipStream_t s, std::vector<StageEvents> *prof) {
+  StageMark mark{prof, s};
   std::vector<CensusJob> cj;
   for (int i = 0; i < n; ++i) {
     const sgm_params &p = fr[i].p;
@@ -232,9 +265,13 @@ int enqueue_frames(const sgm_frame *fr, int n, const std::vector<FramePlan> &pla
       cj.push_back(j);
     }
   }
+  CHECK(mark.begin(SGM_STAGE_CENSUS));
   launch_census(cj, s);
   CHECK(check_launch());
+  CHECK(mark.end(1));
   // aggregation, one launch per (disparities per lane, path-cost width)
+  CHECK(mark.begin(SGM_STAGE_AGGREGATE));
+  int groups = 0;
   for (int dpl = 1; dpl <= 4; ++dpl)
     for (int lb = 1; lb <= 2; ++lb) {
       std::vector<AggJob> aj;
@@ -257,8 +294,12 @@ int enqueue_frames(const sgm_frame *fr, int n, const std::vector<FramePlan> &pla
       if (!aj.empty()) {
         launch_aggregate(aj, kFromCensus, dpl, lb, s);
         CHECK(check_launch());
+        ++groups;
       }
     }
+  CHECK(mark.end(groups));
+  CHECK(mark.begin(SGM_STAGE_DISPARITY));
+  groups = 0;
   for (int lb = 1; lb <= 2; ++lb) {
     std::vector<DispJob> dj;
     for (int i = 0; i < n; ++i) {
@@ -279,8 +320,10 @@ int enqueue_frames(const sgm_frame *fr, int n, const std::vector<FramePlan> &pla
     if (!dj.empty()) {
       launch_disparity(dj, lb, s);
       CHECK(check_launch());
+      ++groups;
     }
   }
+  CHECK(mark.end(groups));
   std::vector<MedianJob> mj;
   for (int i = 0; i < n; ++i) {
     const sgm_params &p = fr[i].p;
@@ -294,8 +337,10 @@ int enqueue_frames(const sgm_frame *fr, int n, const std::vector<FramePlan> &pla
     mj.push_back(j);
   }
   if (!mj.empty()) {
+    CHECK(mark.begin(SGM_STAGE_MEDIAN));
     launch_median(mj, s);
     CHECK(check_launch());
+    CHECK(mark.end(1));
   }
   std::vector<UVJob> uj;
   for (int i = 0; i < n; ++i) {
@@ -310,10 +355,22 @@ int enqueue_frames(const sgm_frame *fr, int n, const std::vector<FramePlan> &pla
     uj.push_back(j);
   }
   if (!uj.empty()) {
+    CHECK(mark.begin(SGM_STAGE_UV));
     launch_uv(uj, s);
     CHECK(check_launch());
+    CHECK(mark.end(1));
   }
   return SGM_OK;
+}
+
+void destroy_events(Batch &b) {
+  for (auto &e : b.prof) {
+    if (e.begin) (void)hipEventDestroy(e.begin);
+    if (e.end) (void)hipEventDestroy(e.end);
+  }
+  b.prof.clear();
+  if (b.done) (void)hipEventDestroy(b.done);
+  b.done = nullptr;
 }
 
 }  // namespace
@@ -357,7 +414,7 @@ int sgm_destroy(sgm_ctx *c) {
     DeviceGuard g(c->device);
     if (hipDeviceSynchronize() != hipSuccess) rc = fail(SGM_EHIP, "device fault before destroy");
     for (auto &kv : c->inflight) {
-      (void)hipEventDestroy(kv.second.done);
+      destroy_events(kv.second);
       (void)hipFree(kv.second.mem.ptr);
     }
     for (auto &b : c->idle) (void)hipFree(b.ptr);
@@ -556,13 +613,14 @@ int sgm_submit(sgm_ctx *c, const sgm_frame *frames, int n, uint64_t *ticket) {
   b.stream = c->next_stream;
   c->next_stream = (c->next_stream + 1) % sgm_ctx::kStreams;
   hipStream_t s = c->streams[b.stream];
-  int rc = enqueue_frames(frames, n, plans, reinterpret_cast<char *>(blk.ptr), s);
+  int rc = enqueue_frames(frames, n, plans, reinterpret_cast<char *>(blk.ptr), s,
+                          c->profiling ? &b.prof : nullptr);
   if (rc == SGM_OK && hipEventCreateWithFlags(&b.done, hipEventDisableTiming) != hipSuccess)
     rc = fail(SGM_EHIP, "hipEventCreate failed");
   if (rc == SGM_OK && hipEventRecord(b.done, s) != hipSuccess) rc = fail(SGM_EHIP, "hipEventRecord failed");
   if (rc != SGM_OK) {
     (void)hipStreamSynchronize(s);
-    if (b.done) (void)hipEventDestroy(b.done);
+    destroy_events(b);
     c->idle.push_back(blk);
     return rc;
   }
@@ -580,7 +638,14 @@ static int poll_locked(sgm_ctx *c, uint64_t ticket, int *done, bool block) {
     return SGM_OK;
   }
   if (e != hipSuccess) return fail(SGM_EHIP, "batch %llu: %s", (unsigned long long)ticket, hipGetErrorString(e));
-  (void)hipEventDestroy(it->second.done);
+  for (auto &e : it->second.prof) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, e.begin, e.end) == hipSuccess) {
+      c->stage_ms[e.stage] += ms;
+      c->stage_count[e.stage] += (uint64_t)e.launches;
+    }
+  }
+  destroy_events(it->second);
   c->idle.push_back(it->second.mem);
   c->inflight.erase(it);
   *done = 1;
@@ -600,6 +665,27 @@ int sgm_wait(sgm_ctx *c, uint64_t ticket) {
   DeviceGuard g(c->device);
   int done = 0;
   return poll_locked(c, ticket, &done, true);
+}
+
+int sgm_profile(sgm_ctx *c, int enable) {
+  if (!c) return fail(SGM_EINVAL, "ctx is null");
+  std::lock_guard<std::mutex> lk(c->mu);
+  c->profiling = enable != 0;
+  return SGM_OK;
+}
+
+int sgm_profile_read(sgm_ctx *c, double *ms, uint64_t *count, int reset) {
+  if (!c) return fail(SGM_EINVAL, "ctx is null");
+  std::lock_guard<std::mutex> lk(c->mu);
+  for (int i = 0; i < SGM_NSTAGES; ++i) {
+    if (ms) ms[i] = c->stage_ms[i];
+    if (count) count[i] = c->stage_count[i];
+    if (reset) {
+      c->stage_ms[i] = 0;
+      c->stage_count[i] = 0;
+    }
+  }
+  return SGM_OK;
 }
 
 int sgm_memory(sgm_ctx *c, size_t *in_flight_bytes, size_t *budget_bytes) {

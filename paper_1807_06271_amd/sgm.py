@@ -31,8 +31,11 @@ PATHS_PAPER4 = PATH_L2R | PATH_TL2BR | PATH_T2B | PATH_TR2BL
 PATHS_HV4 = PATH_L2R | PATH_R2L | PATH_T2B | PATH_B2T
 PATHS_ALL8 = 0xFF
 
-EXPORTS = ["sgm_validate", "sgm_create", "sgm_destroy", "sgm_last_error", "sgm_census", "sgm_cost", "sgm_aggregate",
-           "sgm_disparity", "uv_maps", "sgm_submit", "sgm_poll", "sgm_wait", "sgm_memory"]
+EXPORTS = ["sgm_validate", "sgm_create", "sgm_destroy", "sgm_last_error", "sgm_census", "sgm_cost",
+           "sgm_aggregate",
+           "sgm_disparity", "uv_maps", "sgm_submit", "sgm_poll", "sgm_wait", "sgm_memory", "sgm_profile",
+           "sgm_profile_read"]
+STAGES = ["census", "aggregate", "disparity", "median", "uv"]
 
 
 class SgmError(RuntimeError):
@@ -119,6 +122,8 @@ def lib():
         L.sgm_poll.argtypes = [vp, ctypes.c_uint64, P(i32)]
         L.sgm_wait.argtypes = [vp, ctypes.c_uint64]
         L.sgm_memory.argtypes = [vp, P(ctypes.c_size_t), P(ctypes.c_size_t)]
+        L.sgm_profile.argtypes = [vp, i32]
+        L.sgm_profile_read.argtypes = [vp, P(ctypes.c_double), P(ctypes.c_uint64), i32]
         for name in EXPORTS:
             if name != "sgm_last_error":
                 getattr(L, name).restype = ctypes.c_int
@@ -300,6 +305,18 @@ def sgm_memory(ctx: Context):
     a, b = ctypes.c_size_t(), ctypes.c_size_t()
     _check(lib().sgm_memory(ctx.handle, ctypes.byref(a), ctypes.byref(b)), "sgm_memory")
     return a.value, b.value
+
+
+def sgm_profile(ctx: Context, enable: bool) -> None:
+    _check(lib().sgm_profile(ctx.handle, int(bool(enable))), "sgm_profile")
+
+
+def sgm_profile_read(ctx: Context, reset: bool = False) -> dict:
+    """{stage: (summed ms, launches)} for batches found done since the last reset."""
+    ms = (ctypes.c_double * len(STAGES))()
+    n = (ctypes.c_uint64 * len(STAGES))()
+    _check(lib().sgm_profile_read(ctx.handle, ms, n, int(bool(reset))), "sgm_profile_read")
+    return {name: (ms[i], n[i]) for i, name in enumerate(STAGES)}
 
 
 def run_stages(ctx: Context, p: Params, left, right, stream=None, keep=False):
