@@ -6,8 +6,8 @@ A step is one pass of the whole path (Census of both views, Hamming costs,
 8-path aggregation, WTA + right-view disparity + left-right check, 3x3
 median, U-/V-maps) over one synthetic 1242x375 pair with D = 128 (the
 KITTI-shaped workload), inputs already in device memory.  Steps go through
-sgm_submit on the library's streams with up to 4 frames in flight; the timed
-region is bracketed by torch.cuda.synchronize().
+sgm_submit on one library stream (frames run back to back, up to 8 queued);
+the timed region is bracketed by torch.cuda.synchronize().
 
 Prints ONE JSON line: the throughput in Mdisp-evals/s (W*H*D*paths per
 second), the aggregation kernel's roofline position (its average launch time
@@ -42,8 +42,9 @@ def kitti_params(sgm, W=1242, H=375, D=128):
                       p1=10, p2=120, lr_check=1, median=3)
 
 
-def time_submit_stream(torch, sgm, ctx, frames_fn, steps, warmup, depth=4):
-    """Run `steps` submits of one batch each, keeping up to `depth` in flight.
+def time_submit_stream(torch, sgm, ctx, frames_fn, steps, warmup, depth=8):
+    """Run `steps` submits of one batch each, keeping up to `depth` in flight
+    (how they overlap on the GPU depends on the context's stream count).
     Returns (seconds, list of per-step Frame lists)."""
     outs = [frames_fn(i) for i in range(depth)]
 
@@ -174,6 +175,23 @@ def bench_serve(torch, sgm, synthetic, seconds):
     return out
 
 
+def measured_traffic(kernel_prefix):
+    """HBM bytes per launch of the aggregation kernel from the committed
+    FETCH_SIZE / WRITE_SIZE counter runs (scaled by a copy of known size), or
+    None when the kernel sources changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", "traffic_agg_1242x375_d128.json")
+    if not os.path.exists(path):
+        return None
+    from paper_1807_06271_amd.profiling import source_hash
+    rec = json.load(open(path))
+    if rec.get("source_hash") != source_hash():
+        return None
+    for name, k in rec["kernels"].items():
+        if kernel_prefix in name:
+            return int(k["fetch_bytes"] + k["write_bytes"])
+    return None
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -182,6 +200,9 @@ def main():
     ap.add_argument("--extras", choices=["none", "batch", "all"], default="all")
     ap.add_argument("--serve-seconds", type=float, default=10.0)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run one plain device copy of a known size (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -202,13 +223,29 @@ def main():
     p = kitti_params(sgm)
     L = torch.from_numpy(left).cuda()
     R = torch.from_numpy(right).cuda()
+    if args.calibrate_copy:
+        from paper_1807_06271_amd.profiling import CALIBRATION_BYTES
+        src = torch.ones(CALIBRATION_BYTES, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     ctx = sgm.Context(0)
     sgm.sgm_profile(ctx, True)
 
     log("main: 1242x375 D=128 8 paths, steps", args.steps)
+    # one stream: the frames run back to back, so each kernel's event-timed
+    # duration is its own (no other frame shares the GPU meanwhile)
+    sgm.sgm_set_streams(ctx, 1)
     dt, outs = time_submit_stream(torch, sgm, ctx, lambda i: [sgm.Frame.alloc(p, L, R)],
                                   args.steps, args.warmup)
     prof = sgm.sgm_profile_read(ctx, reset=True)
+    # the same frames with 4 streams: consecutive frames overlap on the GPU
+    sgm.sgm_profile(ctx, False)
+    sgm.sgm_set_streams(ctx, 4)
+    dt4, _ = time_submit_stream(torch, sgm, ctx, lambda i: [sgm.Frame.alloc(p, L, R)],
+                                args.steps, args.warmup)
+    sgm.sgm_profile(ctx, True)
     evals = p.disp_evals()
     value = evals * args.steps / dt / 1e6
     # per-stage averages over warmup + timed steps (every batch is profiled)
@@ -248,8 +285,11 @@ def main():
         extras["served_4cams"] = bench_serve(torch, sgm, synthetic, args.serve_seconds)
     ctx.close()
 
-    log("cpu baseline")
-    cpu = cpu_baseline(left, right, p, args.cpu_seconds)
+    cpu = None
+    if not args.no_cpu:
+        log("cpu baseline")
+        cpu = cpu_baseline(left, right, p, args.cpu_seconds)
+    traffic = measured_traffic("agg_kernel<8, 0, unsigned char")
 
     line = {
         "metric": "SGM Mdisp-evals/s (W*H*D*paths), whole path census..U/V maps",
@@ -266,17 +306,18 @@ def main():
         "data": "synthetic",
         "config": {"workload": "1242x375 uint8 pair, D=128, Census 9x7, 8 paths, P1=10, P2=120, "
                                "LR |dL-dR|<=1, 3x3 median, U/V maps (KITTI-shaped slanted planes)",
-                   "frames_per_step": 1, "in_flight": 4, "path": "sgm_submit (fused)"},
+                   "frames_per_step": 1, "streams": 1, "path": "sgm_submit (fused kernels)"},
         "fps": round(args.steps / dt, 1),
         "frame_latency_ms": {"p50": float(np.percentile(lat_ms, 50)), "p99": float(np.percentile(lat_ms, 99))},
         "stage_avg_ms": {k: round(v, 5) for k, v in stage_avg_ms.items()},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                     "kernel": "agg_kernel (8 directions, costs from Census codes)",
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                     "kernel": "agg_kernel (8 directions, uint8 costs, uint8 path costs)",
                      "alg_bytes_per_launch": ALG_BYTES_PER_EVAL * evals,
                      "avg_launch_ms": round(agg_ms, 5), "launches": prof["aggregate"][1],
                      "batches_profiled": n_batches},
         "per_frame_stage_calls_mdisp_evals_per_s": round(stage_path, 2),
+        "four_streams_mdisp_evals_per_s": round(evals * args.steps / dt4 / 1e6, 2),
         "cpu_baseline": cpu,
         "extras": extras,
     }

@@ -77,7 +77,9 @@ enum {
  *   path_mask a nonzero subset of SGM_PATH_*;  p1 <= p2;
  *   popcount(path_mask) * (N_b + p2) <= 65535 (no 16-bit overflow of S);
  *   lr_check 0 or 1, lr_max_diff >= 0;  median 0 (off), 3 or 5;
- *   invalid >= D (255 is the usual value for D <= 255, 65535 above). */
+ *   invalid >= D (255 is the usual value for D <= 255, 65535 above);
+ *   width * height * Dp * 2 < 4 GiB, with Dp = D rounded up to 64, 128, 192
+ *   or 256 (the padded disparity stride of the internal volumes). */
 typedef struct {
   int32_t width, height;
   int32_t max_disp;
@@ -168,6 +170,11 @@ typedef struct {
  * batches still in flight, returns SGM_EBUSY (retry after sgm_poll); if it
  * can never fit, SGM_ENOMEM.  On success *ticket identifies the batch. */
 int sgm_submit(sgm_ctx *ctx, const sgm_frame *frames, int n, uint64_t *ticket);
+
+/* Number of internal streams that consecutive batches rotate over (1 to 8;
+ * 4 after sgm_create).  With 1, batches run one after another on the GPU;
+ * with more, a batch can start while earlier ones still run. */
+int sgm_set_streams(sgm_ctx *ctx, int n);
 
 /* Non-blocking completion check: *done = 1 once every frame of the ticket's
  * batch is finished (its scratch is then returned to the budget and the

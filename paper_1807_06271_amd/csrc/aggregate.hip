@@ -5,15 +5,19 @@
 //   L_r(p,d) = C(p,d) + min(L_r(p-r,d), L_r(p-r,d-1)+P1, L_r(p-r,d+1)+P1, m+P2) - m,
 //   m = min_k L_r(p-r,k),   L_r(p,d) = C(p,d) at the first pixel of a path.
 //
-// Work decomposition: one 64-lane wavefront per scanline of one direction;
-// the disparity axis is spread over the lanes, DPL contiguous disparities per
-// lane (d = lane*DPL + k).  The d-1 / d+1 neighbours that live in the
-// adjacent lane come over DPP (wave_shr / wave_shl by one lane); the per-step
-// minimum over d is a DPP row reduction followed by row broadcasts and one
-// readlane, so the whole recurrence stays in registers and the only memory
-// traffic is reading C (or the two Census rows) and writing L_r.  All
-// directions of all frames of a batch are waves of the same launch, so the
-// many short diagonal scanlines fill the chip next to the long ones.
+// Work decomposition (CDNA wave64): a scanline of one direction belongs to
+// one 16-lane DPP row, so a wavefront runs four scanlines side by side.  Lane
+// j of a row owns the K contiguous disparities d = j*K .. j*K+K-1 (16*K >= D).
+// The d-1 / d+1 neighbours held by the adjacent lane arrive by DPP row_shr /
+// row_shl (the row ends feed "infinity"), and the per-pixel minimum over d is
+// a 4-step DPP row_ror butterfly that leaves the minimum in every lane of the
+// row: no LDS, no readlane, no barrier.  Costs stream through a register ring
+// PF pixels ahead of the recurrence so that HBM latency overlaps the
+// dependent chain.  All directions of all frames of a launch are waves of one
+// grid, so the short diagonal scanlines run next to the long rows.
+//
+// Internal volumes (costs and path costs) are stored [H][W][Dp] with the
+// disparity stride padded to Dp = 16*K; cells with d >= D are never read.
 #include "device_util.h"
 
 namespace sgmk {
@@ -21,11 +25,13 @@ namespace sgmk {
 __device__ __constant__ int kDirDx[8] = {+1, -1, 0, 0, +1, -1, -1, +1};
 __device__ __constant__ int kDirDy[8] = {0, 0, +1, -1, +1, -1, +1, -1};
 
-int agg_lines(int dir, int W, int H) {
+__host__ __device__ int agg_lines(int dir, int W, int H) {
   if (dir < 2) return H;
   if (dir < 4) return W;
   return W + H - 1;
 }
+
+int agg_k(int D) { return D <= 64 ? 4 : D <= 128 ? 8 : D <= 192 ? 12 : 16; }
 
 // First pixel and length of scanline `line` of direction `dir`.
 __device__ __forceinline__ void line_start(int dir, int line, int W, int H, int &sx, int &sy,
@@ -54,32 +60,65 @@ __device__ __forceinline__ void line_start(int dir, int line, int W, int H, int 
   }
 }
 
-constexpr uint32_t kInf = 0x3FFFFFFFu;  // above any path cost, safe to add P1/P2 to
+// Path costs are carried as packed pairs of 16-bit values (disparities 2i and
+// 2i+1 of the lane in one 32-bit register) so that every min / add of the
+// recurrence is one v_pk_* instruction for two disparities.  Values never
+// exceed N_b + P2 <= 65535 (parameter check); 0xFFFF stands for "no such
+// disparity" and the additions that can meet it saturate.
+typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
 
-template <int DPL, int SRC>
-__device__ __forceinline__ void load_costs(const AggJob &J, int x, int y, int dbase,
-                                           uint32_t (&c)[DPL]) {
-  const int64_t pix = (int64_t)y * J.W + x;
-  if (SRC == kFromCost) {
-    const uint16_t *row = J.cost + pix * J.D;
+__device__ __forceinline__ u16x2 as_pair(uint32_t v) { return __builtin_bit_cast(u16x2, v); }
+__device__ __forceinline__ uint32_t as_u32(u16x2 v) { return __builtin_bit_cast(uint32_t, v); }
+__device__ __forceinline__ u16x2 pmin(u16x2 a, u16x2 b) { return __builtin_elementwise_min(a, b); }
+__device__ __forceinline__ u16x2 padd_sat(u16x2 a, u16x2 b) { return __builtin_elementwise_add_sat(a, b); }
+
+constexpr uint32_t kInfPair = 0xFFFFFFFFu;
+
+// Cost words of one pixel for one lane: SRC kCost8 = K bytes (K/4 dwords) of
+// the padded uint8 volume; SRC kCost16 = K values of the caller's unpadded
+// uint16 volume, two per word.
+enum { kCost8 = 0, kCost16 = 1 };
+
+template <int K, int SRC>
+struct CostWords {
+  static constexpr int N = SRC == kCost8 ? K / 4 : K / 2;
+  uint32_t w[N];
+};
+
+template <int K, int SRC>
+__device__ __forceinline__ void load_cost(CostWords<K, SRC> &cw, const char *p, int dvalid) {
+  if (SRC == kCost8) {
+    const U32N<K / 4> v = *reinterpret_cast<const U32N<K / 4> *>(p);
 #pragma unroll
-    for (int k = 0; k < DPL; ++k) c[k] = (dbase + k < J.D) ? row[dbase + k] : 0u;
+    for (int i = 0; i < K / 4; ++i) cw.w[i] = v.v[i];
   } else {
-    const uint64_t cl = J.cl[pix];
-    const uint64_t *cr = J.cr + pix;  // cr[-d] is the right code at x - d
+    const uint16_t *q = reinterpret_cast<const uint16_t *>(p);
 #pragma unroll
-    for (int k = 0; k < DPL; ++k) {
-      const int d = dbase + k;
-      const uint64_t r = cr[-min(d, x)];  // clamped index: never reads left of the row
-      c[k] = (d < J.D && x >= d) ? (uint32_t)__popcll(cl ^ r) : (uint32_t)J.nbits;
+    for (int i = 0; i < K / 2; ++i) {
+      const uint32_t lo = 2 * i < dvalid ? q[2 * i] : 0u;
+      const uint32_t hi = 2 * i + 1 < dvalid ? q[2 * i + 1] : 0u;
+      cw.w[i] = lo | hi << 16;
     }
   }
 }
 
-template <int DPL, int SRC, typename LT>
+// Costs of disparities (2i, 2i+1) as a packed pair.
+template <int K, int SRC>
+__device__ __forceinline__ u16x2 cost_pair(const CostWords<K, SRC> &cw, int i) {
+  if (SRC == kCost8) {
+    // bytes 2i and 2i+1 of the lane's K bytes, zero-extended into 16-bit halves
+    const uint32_t sel = (i & 1) ? 0x0c030c02u : 0x0c010c00u;
+    return as_pair(__builtin_amdgcn_perm(0u, cw.w[i >> 1], sel));
+  }
+  return as_pair(cw.w[i]);
+}
+
+template <int K, int SRC, typename LT, int PF, bool PAD>
 __global__ __launch_bounds__(256) void agg_kernel(JobTable<AggJob> t) {
-  const int gw = uniform((int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6));
+  constexpr int NP = K / 2;  // packed pairs per lane
+  const int gw = uniform((int)(blockIdx.x * 4 + (threadIdx.x >> 6)));  // global wave
   const int lane = (int)(threadIdx.x & 63);
+  const int row = lane >> 4, j = lane & 15;
   const int ji = find_job(t.j, t.n, gw);
   const AggJob &J = t.j[ji];
   const int w = gw - J.blk0;
@@ -88,115 +127,172 @@ __global__ __launch_bounds__(256) void agg_kernel(JobTable<AggJob> t) {
   for (int k = 1; k < J.ndirs; ++k)
     if (w >= J.line0[k]) slot = k;
   const int dir = J.dirs[slot];
-  int sx, sy, len;
-  line_start(dir, w - J.line0[slot], J.W, J.H, sx, sy, len);
-  const int dx = kDirDx[dir], dy = kDirDy[dir];
-  const int D = J.D;
-  const uint32_t p1 = (uint32_t)J.p1, p2 = (uint32_t)J.p2;
-  LT *out = reinterpret_cast<LT *>(J.lr) + (int64_t)slot * J.H * J.W * D;
-  const int dbase = lane * DPL;
+  const int W = J.W, H = J.H, D = J.D, Dp = J.Dp;
+  const int line = (w - J.line0[slot]) * 4 + row;
+  int sx = 0, sy = 0, len = 0;
+  if (line < agg_lines(dir, W, H)) line_start(dir, line, W, H, sx, sy, len);
+  // the wave runs until its longest row is done
+  const int maxlen = max(max(__builtin_amdgcn_readlane(len, 0), __builtin_amdgcn_readlane(len, 16)),
+                         max(__builtin_amdgcn_readlane(len, 32), __builtin_amdgcn_readlane(len, 48)));
+  const int64_t step = (int64_t)kDirDy[dir] * W + kDirDx[dir];  // pixel index step (uniform)
+  const int64_t pix0 = (int64_t)sy * W + sx;
+  const int dbase = j * K;
+  // disparities of this lane below D (all K unless the row is padded, PAD)
+  const int dvalid = PAD ? min(K, max(0, D - dbase)) : K;
+  // halves for d >= D are forced to 0xFFFF after every pixel
+  uint32_t padmask[NP];
+#pragma unroll
+  for (int i = 0; i < NP; ++i)
+    padmask[i] = (2 * i < dvalid ? 0u : 0xFFFFu) | (2 * i + 1 < dvalid ? 0u : 0xFFFF0000u);
+  const u16x2 P1 = {(unsigned short)J.p1, (unsigned short)J.p1};
+  const u16x2 P2 = {(unsigned short)J.p2, (unsigned short)J.p2};
 
-  uint32_t Lp[DPL];
-  uint32_t mp = 0;
-  uint32_t c[DPL];
-  int x = sx, y = sy;
-  load_costs<DPL, SRC>(J, x, y, dbase, c);
-  for (int i = 0; i < len; ++i) {
-    // issue the next pixel's loads before this pixel's arithmetic
-    uint32_t cn[DPL];
-    const int xn = x + dx, yn = y + dy;
-    if (i + 1 < len) load_costs<DPL, SRC>(J, xn, yn, dbase, cn);
-    uint32_t Lc[DPL];
-    if (i == 0) {
+  // Addresses are a wave-uniform base that advances by a uniform step per
+  // pixel plus a per-lane 32-bit offset that stays fixed along the scanline.
+  constexpr int CB = SRC == kCost8 ? 1 : 2;  // bytes per cost element
+  const int cpp = SRC == kCost8 ? Dp : D;    // cost elements per pixel
+  const char *cbase = SRC == kCost8 ? reinterpret_cast<const char *>(J.cost8)
+                                    : reinterpret_cast<const char *>(J.cost16);
+  const uint32_t coff = (uint32_t)((pix0 * cpp + dbase) * CB);
+  const int64_t cstep = step * cpp * CB;
+  char *obase = reinterpret_cast<char *>(J.lr) + (int64_t)slot * H * W * Dp * (int64_t)sizeof(LT);
+  const uint32_t ooff = (uint32_t)((pix0 * Dp + dbase) * (int64_t)sizeof(LT));
+  const int64_t ostep = step * Dp * (int64_t)sizeof(LT);
+
+  CostWords<K, SRC> ring[PF];
 #pragma unroll
-      for (int k = 0; k < DPL; ++k) Lc[k] = (dbase + k < D) ? c[k] : kInf;
-    } else {
-      const uint32_t lo = from_lower_lane(Lp[DPL - 1], kInf);  // L(d-1) for k = 0
-      const uint32_t hi = from_upper_lane(Lp[0], kInf);        // L(d+1) for k = DPL-1
-      const uint32_t mP2 = mp + p2;
+  for (int s = 0; s < PF; ++s)
+    if (s < len) load_cost<K, SRC>(ring[s], cbase + s * cstep + coff, dvalid);
+
+  // A path's first pixel behaves as if its predecessor had all-zero path
+  // costs: then every candidate is >= 0 = m, so L = C.
+  u16x2 Lp[NP];
 #pragma unroll
-      for (int k = 0; k < DPL; ++k) {
-        const uint32_t l = (k == 0) ? lo : Lp[k - 1];
-        const uint32_t r = (k == DPL - 1) ? hi : Lp[k + 1];
-        const uint32_t best = min(min(Lp[k], min(l, r) + p1), mP2);
-        Lc[k] = (dbase + k < D) ? c[k] + best - mp : kInf;
+  for (int i = 0; i < NP; ++i) Lp[i] = as_pair(padmask[i]);
+  uint32_t mp = 0;  // the predecessor's minimum (row-uniform)
+
+  auto pixel = [&](int i, CostWords<K, SRC> &rs) {
+    const CostWords<K, SRC> cw = rs;
+    if (i + PF < len) load_cost<K, SRC>(rs, cbase + (int64_t)(i + PF) * cstep + coff, dvalid);
+    // neighbour pairs: Nb[q] = (L[2q-1], L[2q]) for q = 0..NP, so that pair q
+    // has its d-1 values in Nb[q] and its d+1 values in Nb[q+1]
+    const uint32_t prev = (uint32_t)__builtin_amdgcn_update_dpp(
+        (int)kInfPair, (int)as_u32(Lp[NP - 1]), kDppRowShr1, 0xF, 0xF, false);
+    const uint32_t next = (uint32_t)__builtin_amdgcn_update_dpp(
+        (int)kInfPair, (int)as_u32(Lp[0]), kDppRowShl1, 0xF, 0xF, false);
+    u16x2 Nb[NP + 1];
+    Nb[0] = as_pair(__builtin_amdgcn_alignbit(as_u32(Lp[0]), prev, 16));
+#pragma unroll
+    for (int q = 1; q < NP; ++q) Nb[q] = as_pair(__builtin_amdgcn_alignbit(as_u32(Lp[q]), as_u32(Lp[q - 1]), 16));
+    Nb[NP] = as_pair(__builtin_amdgcn_alignbit(next, as_u32(Lp[NP - 1]), 16));
+    const u16x2 M = {(unsigned short)mp, (unsigned short)mp};
+    const u16x2 MP2 = padd_sat(M, P2);
+    u16x2 Lc[NP];
+#pragma unroll
+    for (int q = 0; q < NP; ++q) {
+      u16x2 best = padd_sat(pmin(Nb[q], Nb[q + 1]), P1);
+      best = pmin(pmin(best, Lp[q]), MP2);
+      u16x2 v = best - M + cost_pair<K, SRC>(cw, q);
+      if (PAD) v = as_pair(as_u32(v) | padmask[q]);
+      Lc[q] = v;
+    }
+    if (i < len) {
+      char *o = obase + (int64_t)i * ostep + ooff;
+      if (sizeof(LT) == 1) {
+        U32N<K / 4> pk;
+#pragma unroll
+        for (int q = 0; q < K / 4; ++q)  // low bytes of the four 16-bit values
+          pk.v[q] = __builtin_amdgcn_perm(as_u32(Lc[2 * q + 1]), as_u32(Lc[2 * q]), 0x06040200u);
+        *reinterpret_cast<U32N<K / 4> *>(o) = pk;
+      } else {
+        U32N<NP> pk;
+#pragma unroll
+        for (int q = 0; q < NP; ++q) pk.v[q] = as_u32(Lc[q]);
+        *reinterpret_cast<U32N<NP> *>(o) = pk;
       }
     }
-    LT *o = out + ((int64_t)y * J.W + x) * D + dbase;
-    uint32_t lm = Lc[0];
+    u16x2 lm = Lc[0];
 #pragma unroll
-    for (int k = 0; k < DPL; ++k) {
-      if (dbase + k < D) o[k] = (LT)Lc[k];
-      lm = min(lm, Lc[k]);
-      Lp[k] = Lc[k];
-    }
-    mp = wave_min_u32(lm);
-    x = xn;
-    y = yn;
+    for (int q = 1; q < NP; ++q) lm = pmin(lm, Lc[q]);
+    mp = row16_allmin_u32(min((uint32_t)lm.x, (uint32_t)lm.y));
 #pragma unroll
-    for (int k = 0; k < DPL; ++k) c[k] = cn[k];
+    for (int q = 0; q < NP; ++q) Lp[q] = Lc[q];
+  };
+
+  int i0 = 0;
+  for (; i0 + PF <= maxlen; i0 += PF) {  // whole blocks of PF pixels
+#pragma unroll
+    for (int s = 0; s < PF; ++s) pixel(i0 + s, ring[s]);
   }
+#pragma unroll
+  for (int s = 0; s < PF; ++s)  // remaining < PF pixels
+    if (i0 + s < maxlen) pixel(i0 + s, ring[s]);
 }
 
-template <int DPL, int SRC, typename LT>
+template <int K, int SRC, typename LT>
 static void launch_one(const JobTable<AggJob> &t, int waves, hipStream_t s) {
+  constexpr int PF = SRC == kCost8 ? 8 : 4;
   const int blocks = (waves + 3) / 4;
-  hipLaunchKernelGGL((agg_kernel<DPL, SRC, LT>), dim3(blocks), dim3(256), 0, s, t);
+  bool pad = false;  // some frame's D is not a multiple of 16*K: mask the tail lanes
+  for (int i = 0; i < t.n; ++i) pad |= t.j[i].D != 16 * K;
+  if (pad) hipLaunchKernelGGL((agg_kernel<K, SRC, LT, PF, true>), dim3(blocks), dim3(256), 0, s, t);
+  else hipLaunchKernelGGL((agg_kernel<K, SRC, LT, PF, false>), dim3(blocks), dim3(256), 0, s, t);
 }
 
 template <int SRC, typename LT>
-static void launch_dpl(int dpl, const JobTable<AggJob> &t, int waves, hipStream_t s) {
-  switch (dpl) {
-    case 1: launch_one<1, SRC, LT>(t, waves, s); break;
-    case 2: launch_one<2, SRC, LT>(t, waves, s); break;
-    case 3: launch_one<3, SRC, LT>(t, waves, s); break;
-    default: launch_one<4, SRC, LT>(t, waves, s); break;
+static void launch_k(int K, const JobTable<AggJob> &t, int waves, hipStream_t s) {
+  switch (K) {
+    case 4: launch_one<4, SRC, LT>(t, waves, s); break;
+    case 8: launch_one<8, SRC, LT>(t, waves, s); break;
+    case 12: launch_one<12, SRC, LT>(t, waves, s); break;
+    default: launch_one<16, SRC, LT>(t, waves, s); break;
   }
 }
 
-void launch_aggregate(std::vector<AggJob> jobs, AggSource src, int dpl, int lr_bytes,
+void launch_aggregate(std::vector<AggJob> jobs, bool from_cost16, int K, int lr_bytes,
                       hipStream_t s) {
   for (auto &j : jobs) {
     int total = 0;
     for (int k = 0; k < j.ndirs; ++k) {
       j.line0[k] = total;
-      total += agg_lines(j.dirs[k], j.W, j.H);
+      total += (agg_lines(j.dirs[k], j.W, j.H) + 3) / 4;  // four scanlines per wave
     }
     j.line0[j.ndirs] = total;
   }
   for_each_table(
       jobs, [](const AggJob &j) { return (long)j.line0[j.ndirs]; },
       [&](const JobTable<AggJob> &t, int waves) {
-        if (src == kFromCost) {
-          if (lr_bytes == 1) launch_dpl<kFromCost, uint8_t>(dpl, t, waves, s);
-          else launch_dpl<kFromCost, uint16_t>(dpl, t, waves, s);
+        if (!from_cost16) {
+          if (lr_bytes == 1) launch_k<kCost8, uint8_t>(K, t, waves, s);
+          else launch_k<kCost8, uint16_t>(K, t, waves, s);
         } else {
-          if (lr_bytes == 1) launch_dpl<kFromCensus, uint8_t>(dpl, t, waves, s);
-          else launch_dpl<kFromCensus, uint16_t>(dpl, t, waves, s);
+          if (lr_bytes == 1) launch_k<kCost16, uint8_t>(K, t, waves, s);
+          else launch_k<kCost16, uint16_t>(K, t, waves, s);
         }
       });
 }
 
-// S = sum over the P slots of the path-cost volumes; 4 cells per thread.
+// S = sum over the P slots of the (padded) path-cost volumes, written
+// unpadded: one thread per output cell.
 template <typename LT>
 __global__ __launch_bounds__(256) void sum_kernel(JobTable<SumJob> t) {
   const int ji = find_job(t.j, t.n, (int)blockIdx.x);
   const SumJob &J = t.j[ji];
-  const int64_t base = ((int64_t)((int)blockIdx.x - J.blk0) * 256 + threadIdx.x) * 4;
+  const int64_t i = (int64_t)((int)blockIdx.x - J.blk0) * 256 + threadIdx.x;
+  if (i >= J.cells) return;
+  const int64_t pix = i / J.D;
+  const int d = (int)(i - pix * J.D);
+  const int64_t src = pix * J.Dp + d;
+  const int64_t slot_stride = J.cells / J.D * J.Dp;
   const LT *lr = reinterpret_cast<const LT *>(J.lr);
-#pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const int64_t i = base + q;
-    if (i >= J.cells) break;
-    uint32_t s = 0;
-    for (int p = 0; p < J.P; ++p) s += lr[(int64_t)p * J.cells + i];
-    J.S[i] = (uint16_t)s;
-  }
+  uint32_t s = 0;
+  for (int p = 0; p < J.P; ++p) s += lr[(int64_t)p * slot_stride + src];
+  J.S[i] = (uint16_t)s;
 }
 
 void launch_sum(std::vector<SumJob> jobs, int lr_bytes, hipStream_t s) {
   for_each_table(
-      jobs, [](const SumJob &j) { return (long)((j.cells + 1023) / 1024); },
+      jobs, [](const SumJob &j) { return (long)((j.cells + 255) / 256); },
       [&](const JobTable<SumJob> &t, int blocks) {
         if (lr_bytes == 1) hipLaunchKernelGGL(sum_kernel<uint8_t>, dim3(blocks), dim3(256), 0, s, t);
         else hipLaunchKernelGGL(sum_kernel<uint16_t>, dim3(blocks), dim3(256), 0, s, t);

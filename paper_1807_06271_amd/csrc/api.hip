@@ -64,11 +64,20 @@ int validate(const sgm_params *p) {
   if (p->invalid < p->max_disp)
     return fail(SGM_EINVAL, "invalid (%u) must be >= max_disp (%d)", p->invalid, p->max_disp);
   if (p->reserved != 0) return fail(SGM_EINVAL, "reserved must be 0");
+  // the kernels address one path-cost volume (padded disparity stride, up to
+  // 2 bytes per cell) with 32-bit offsets
+  const int64_t dp = 16 * (int64_t)agg_k(p->max_disp);
+  if ((int64_t)p->width * p->height * dp * 2 >= (int64_t)1 << 32)
+    return fail(SGM_EINVAL, "image too large: width*height*%lld*2 bytes must stay below 4 GiB",
+                (long long)dp);
   return SGM_OK;
 }
 
 int nbits_of(const sgm_params &p) { return p.census_w * p.census_h - 1; }
-int dpl_of(const sgm_params &p) { return (p.max_disp + 63) / 64; }
+// Disparities per lane of the aggregation / selection kernels, and the
+// padded disparity stride of the internal volumes.
+int k_of(const sgm_params &p) { return agg_k(p.max_disp); }
+int dp_of(const sgm_params &p) { return 16 * k_of(p); }
 // Path costs fit in 8 bits when C + P2 <= 255 (C <= N_b, L_r <= C + P2).
 int lr_bytes_of(const sgm_params &p) { return nbits_of(p) + p.p2 <= 255 ? 1 : 2; }
 
@@ -111,8 +120,9 @@ struct sgm_ctx {
   std::vector<Block> idle;      // finished batch blocks kept for reuse
   std::map<uint64_t, Batch> inflight;
   uint64_t next_ticket = 1;
-  static constexpr int kStreams = 4;
+  static constexpr int kStreams = 8;
   hipStream_t streams[kStreams] = {};
+  int nstreams = 4;  // streams in use (round robin)
   int next_stream = 0;
   bool profiling = false;
   double stage_ms[SGM_NSTAGES] = {};
@@ -208,16 +218,21 @@ int check_dev_ptr(const void *ptr, int dev, const char *name) {
 // ------------------------------------------------------ whole-frame plan
 
 struct FramePlan {
-  size_t off_cl, off_cr, off_lr, off_dlr, bytes;
+  size_t off_cl, off_cr, off_cost, off_lr, off_dlr, bytes;
 };
 
+// Scratch of one frame of a batch: Census codes of both views, the padded
+// uint8 cost volume, the P padded path-cost volumes and the LR-checked map
+// before the median.
 FramePlan plan_frame(const sgm_params &p, size_t base) {
   const size_t px = (size_t)p.width * p.height;
+  const size_t dp = (size_t)dp_of(p);
   FramePlan f;
   f.off_cl = base;
   f.off_cr = f.off_cl + align256(px * 8);
-  f.off_lr = f.off_cr + align256(px * 8);
-  f.off_dlr = f.off_lr + align256(px * p.max_disp * (size_t)popcount8(p.path_mask) * lr_bytes_of(p));
+  f.off_cost = f.off_cr + align256(px * 8);
+  f.off_lr = f.off_cost + align256(px * dp);
+  f.off_dlr = f.off_lr + align256(px * dp * (size_t)popcount8(p.path_mask) * lr_bytes_of(p));
   f.bytes = f.off_dlr + align256(px * 2) - base;
   return f;
 }
@@ -268,31 +283,47 @@ int enqueue_frames(const sgm_frame *fr, int n, const std::vector<FramePlan> &pla
   CHECK(mark.begin(SGM_STAGE_CENSUS));
   launch_census(cj, s);
   CHECK(check_launch());
-  CHECK(mark.end(1));
+  // Hamming costs into the padded uint8 volume (costs <= N_b <= 64)
+  std::vector<CostJob> kj;
+  for (int i = 0; i < n; ++i) {
+    const sgm_params &p = fr[i].p;
+    CostJob j{};
+    j.cl = reinterpret_cast<const uint64_t *>(mem + plans[i].off_cl);
+    j.cr = reinterpret_cast<const uint64_t *>(mem + plans[i].off_cr);
+    j.out8 = reinterpret_cast<uint8_t *>(mem + plans[i].off_cost);
+    j.W = p.width;
+    j.H = p.height;
+    j.D = p.max_disp;
+    j.Dp = dp_of(p);
+    j.nbits = nbits_of(p);
+    kj.push_back(j);
+  }
+  launch_cost(kj, s);
+  CHECK(check_launch());
+  CHECK(mark.end(2));
   // aggregation, one launch per (disparities per lane, path-cost width)
   CHECK(mark.begin(SGM_STAGE_AGGREGATE));
   int groups = 0;
-  for (int dpl = 1; dpl <= 4; ++dpl)
+  for (int K : {4, 8, 12, 16})
     for (int lb = 1; lb <= 2; ++lb) {
       std::vector<AggJob> aj;
       for (int i = 0; i < n; ++i) {
         const sgm_params &p = fr[i].p;
-        if (dpl_of(p) != dpl || lr_bytes_of(p) != lb) continue;
+        if (k_of(p) != K || lr_bytes_of(p) != lb) continue;
         AggJob j{};
-        j.cl = reinterpret_cast<const uint64_t *>(mem + plans[i].off_cl);
-        j.cr = reinterpret_cast<const uint64_t *>(mem + plans[i].off_cr);
+        j.cost8 = reinterpret_cast<const uint8_t *>(mem + plans[i].off_cost);
         j.lr = mem + plans[i].off_lr;
         j.W = p.width;
         j.H = p.height;
         j.D = p.max_disp;
-        j.nbits = nbits_of(p);
+        j.Dp = dp_of(p);
         j.p1 = p.p1;
         j.p2 = p.p2;
         j.ndirs = fill_dirs(p.path_mask, j.dirs);
         aj.push_back(j);
       }
       if (!aj.empty()) {
-        launch_aggregate(aj, kFromCensus, dpl, lb, s);
+        launch_aggregate(aj, false, K, lb, s);
         CHECK(check_launch());
         ++groups;
       }
@@ -312,6 +343,7 @@ int enqueue_frames(const sgm_frame *fr, int n, const std::vector<FramePlan> &pla
       j.W = p.width;
       j.H = p.height;
       j.D = p.max_disp;
+      j.Dp = dp_of(p);
       j.lr_check = p.lr_check;
       j.max_diff = p.lr_max_diff;
       j.invalid = p.invalid;
@@ -458,10 +490,11 @@ int sgm_cost(sgm_ctx *c, const sgm_params *p, const uint64_t *cl, const uint64_t
   CostJob j{};
   j.cl = cl;
   j.cr = cr;
-  j.cost = cost;
+  j.out16 = cost;
   j.W = p->width;
   j.H = p->height;
   j.D = p->max_disp;
+  j.Dp = dp_of(*p);
   j.nbits = nbits_of(*p);
   launch_cost({j}, (hipStream_t)stream);
   return check_launch();
@@ -479,25 +512,28 @@ int sgm_aggregate(sgm_ctx *c, const sgm_params *p, const uint16_t *cost, uint16_
   hipStream_t s = (hipStream_t)stream;
   const int lb = lr_bytes_of(*p);
   const int P = popcount8(p->path_mask);
-  const int64_t cells = (int64_t)p->width * p->height * p->max_disp;
+  const int Dp = dp_of(*p);
+  const int64_t px = (int64_t)p->width * p->height;
   void *lr = nullptr;
-  CHECK(stage_scratch(c, (size_t)cells * P * lb, s, &lr));
+  CHECK(stage_scratch(c, (size_t)px * Dp * P * lb, s, &lr));
   AggJob j{};
-  j.cost = cost;
+  j.cost16 = cost;
   j.lr = lr;
   j.W = p->width;
   j.H = p->height;
   j.D = p->max_disp;
-  j.nbits = nbits_of(*p);
+  j.Dp = Dp;
   j.p1 = p->p1;
   j.p2 = p->p2;
   j.ndirs = fill_dirs(p->path_mask, j.dirs);
-  launch_aggregate({j}, kFromCost, dpl_of(*p), lb, s);
+  launch_aggregate({j}, true, k_of(*p), lb, s);
   CHECK(check_launch());
   SumJob sj{};
   sj.lr = lr;
   sj.S = aggr;
-  sj.cells = cells;
+  sj.cells = px * p->max_disp;
+  sj.D = p->max_disp;
+  sj.Dp = Dp;
   sj.P = P;
   launch_sum({sj}, lb, s);
   return check_launch();
@@ -525,6 +561,7 @@ int sgm_disparity(sgm_ctx *c, const sgm_params *p, const uint16_t *aggr, uint16_
   j.W = p->width;
   j.H = p->height;
   j.D = p->max_disp;
+  j.Dp = dp_of(*p);
   j.lr_check = p->lr_check;
   j.max_diff = p->lr_max_diff;
   j.invalid = p->invalid;
@@ -611,7 +648,7 @@ int sgm_submit(sgm_ctx *c, const sgm_frame *frames, int n, uint64_t *ticket) {
   Batch b;
   b.mem = blk;
   b.stream = c->next_stream;
-  c->next_stream = (c->next_stream + 1) % sgm_ctx::kStreams;
+  c->next_stream = (c->next_stream + 1) % c->nstreams;
   hipStream_t s = c->streams[b.stream];
   int rc = enqueue_frames(frames, n, plans, reinterpret_cast<char *>(blk.ptr), s,
                           c->profiling ? &b.prof : nullptr);
@@ -665,6 +702,15 @@ int sgm_wait(sgm_ctx *c, uint64_t ticket) {
   DeviceGuard g(c->device);
   int done = 0;
   return poll_locked(c, ticket, &done, true);
+}
+
+int sgm_set_streams(sgm_ctx *c, int n) {
+  if (!c) return fail(SGM_EINVAL, "ctx is null");
+  if (n < 1 || n > sgm_ctx::kStreams) return fail(SGM_EINVAL, "streams must be in [1, %d]", sgm_ctx::kStreams);
+  std::lock_guard<std::mutex> lk(c->mu);
+  c->nstreams = n;
+  c->next_stream = 0;
+  return SGM_OK;
 }
 
 int sgm_profile(sgm_ctx *c, int enable) {

@@ -15,10 +15,15 @@ namespace sgmk {
 
 // DPP control words (GCN/CDNA "dpp_ctrl" encodings).
 enum : int {
-  kDppRowShr1 = 0x111,
+  kDppRowShr1 = 0x111,   // lane i reads lane i-1 of its row (row start has no source)
   kDppRowShr2 = 0x112,
   kDppRowShr4 = 0x114,
   kDppRowShr8 = 0x118,
+  kDppRowShl1 = 0x101,   // lane i reads lane i+1 of its row (row end has no source)
+  kDppRowRor1 = 0x121,   // row_ror:n = 0x120 + n
+  kDppRowRor2 = 0x122,
+  kDppRowRor4 = 0x124,
+  kDppRowRor8 = 0x128,
   kDppWaveShl1 = 0x130,  // lane i reads lane i+1 (lane 63 has no source)
   kDppWaveShr1 = 0x138,  // lane i reads lane i-1 (lane 0 has no source)
   kDppRowBcast15 = 0x142,
@@ -49,8 +54,19 @@ __device__ __forceinline__ uint32_t wave_min_u32(uint32_t v) {
   return (uint32_t)__builtin_amdgcn_readlane((int)v, 63);
 }
 
-// Unsigned minimum over each aligned group of 16 lanes; every lane of the
-// group receives the group's minimum.
+// Unsigned minimum over each 16-lane DPP row, delivered to every lane of the
+// row: a butterfly of row rotations by 8, 4, 2 and 1 lanes.
+__device__ __forceinline__ uint32_t row16_allmin_u32(uint32_t v) {
+  // every source lane of a rotation is valid, so bound_ctrl is irrelevant;
+  // setting it lets the compiler fold each move into the v_min as a DPP operand
+  v = min(v, (uint32_t)__builtin_amdgcn_mov_dpp((int)v, kDppRowRor8, 0xF, 0xF, true));
+  v = min(v, (uint32_t)__builtin_amdgcn_mov_dpp((int)v, kDppRowRor4, 0xF, 0xF, true));
+  v = min(v, (uint32_t)__builtin_amdgcn_mov_dpp((int)v, kDppRowRor2, 0xF, 0xF, true));
+  v = min(v, (uint32_t)__builtin_amdgcn_mov_dpp((int)v, kDppRowRor1, 0xF, 0xF, true));
+  return v;
+}
+
+// Same result through __shfl_xor within aligned 16-lane groups.
 __device__ __forceinline__ uint32_t row16_min_u32(uint32_t v) {
   v = min(v, (uint32_t)__shfl_xor((int)v, 8, 16));
   v = min(v, (uint32_t)__shfl_xor((int)v, 4, 16));
@@ -58,6 +74,12 @@ __device__ __forceinline__ uint32_t row16_min_u32(uint32_t v) {
   v = min(v, (uint32_t)__shfl_xor((int)v, 1, 16));
   return v;
 }
+
+// N consecutive 32-bit words, loaded / stored as one vector access.
+template <int N>
+struct alignas(4) U32N {
+  uint32_t v[N];
+};
 
 __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
 

@@ -1,12 +1,16 @@
 // Disparity selection from the aggregated volume (sections 3.1.3 to 3.1.5).
 //
-// disp_kernel: one block per image row.  Groups of 16 lanes take one pixel at
-// a time, each lane K contiguous disparities.  A cell's 32-bit key
-// (S << 8) | d orders by cost and then by disparity, so an unsigned minimum
-// is the smallest-d argmin.  The left map D_L is the minimum key over d
-// (reduced across the 16 lanes); the right map D_R(x_r) = argmin_d
-// S(x_r + d, d) collects the same keys by LDS atomicMin into slot x - d.
-// After a barrier the row's left-right check is done from LDS.
+// disp_kernel: one 1024-thread block per image row.  Each 16-lane DPP row
+// takes one pixel at a time, lane j owning K contiguous disparities (the
+// same lane layout as the aggregation).  With path-cost volumes as input the
+// P uint8 (or uint16) volumes are read with one vector load per slot and
+// summed as packed 16-bit fields (two cells per 32-bit word, no carries:
+// S <= 65535 by the parameter check).  A cell's 32-bit key (S << 8) | d
+// orders by cost, then by disparity, so an unsigned minimum picks the
+// smallest-d argmin: D_L is the minimum key over d (DPP row butterfly), and
+// D_R(x_r) = argmin_d S(x_r + d, d) collects the same keys by LDS atomicMin
+// into slot x - d.  After a barrier the row's left-right check reads both
+// maps from LDS.
 //
 // median_kernel: k x k median with clamped borders by an odd-even
 // transposition network on k*k registers.
@@ -14,47 +18,87 @@
 
 namespace sgmk {
 
-template <int IN>
-__device__ __forceinline__ uint32_t load_cost_sum(const DispJob &J, int64_t cell, int64_t cells) {
-  if (IN == 0) return J.S[cell];
-  uint32_t s = 0;
-  if (IN == 1) {
-    const uint8_t *lr = reinterpret_cast<const uint8_t *>(J.lr);
-    for (int p = 0; p < J.P; ++p) s += lr[(int64_t)p * cells + cell];
+constexpr int kDispThreads = 1024;
+
+// Summed costs S of the lane's K disparities (d >= D lanes get garbage that
+// is never used).
+template <int K, int IN>
+__device__ __forceinline__ void load_sums(const DispJob &J, int64_t pix, int dbase, int dvalid,
+                                          uint32_t (&S)[K]) {
+  if (IN == 0) {
+    const uint16_t *q = J.S + pix * J.D + dbase;
+#pragma unroll
+    for (int k = 0; k < K; ++k) S[k] = k < dvalid ? q[k] : 0u;
+  } else if (IN == 1) {
+    const int64_t slot = (int64_t)J.H * J.W * J.Dp;
+    const uint8_t *b = reinterpret_cast<const uint8_t *>(J.lr) + pix * J.Dp + dbase;
+    uint32_t ev[K / 4], od[K / 4];
+#pragma unroll
+    for (int q = 0; q < K / 4; ++q) ev[q] = od[q] = 0;
+    for (int p = 0; p < J.P; ++p) {
+      const U32N<K / 4> v = *reinterpret_cast<const U32N<K / 4> *>(b + p * slot);
+#pragma unroll
+      for (int q = 0; q < K / 4; ++q) {
+        ev[q] += v.v[q] & 0x00FF00FFu;         // d = 4q, 4q+2 in the low/high half
+        od[q] += (v.v[q] >> 8) & 0x00FF00FFu;  // d = 4q+1, 4q+3
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < K / 4; ++q) {
+      S[4 * q] = ev[q] & 0xFFFF;
+      S[4 * q + 1] = od[q] & 0xFFFF;
+      S[4 * q + 2] = ev[q] >> 16;
+      S[4 * q + 3] = od[q] >> 16;
+    }
   } else {
-    const uint16_t *lr = reinterpret_cast<const uint16_t *>(J.lr);
-    for (int p = 0; p < J.P; ++p) s += lr[(int64_t)p * cells + cell];
+    const int64_t slot = (int64_t)J.H * J.W * J.Dp;
+    const uint16_t *b = reinterpret_cast<const uint16_t *>(J.lr) + pix * J.Dp + dbase;
+    uint32_t acc[K / 2];
+#pragma unroll
+    for (int q = 0; q < K / 2; ++q) acc[q] = 0;
+    for (int p = 0; p < J.P; ++p) {
+      const U32N<K / 2> v = *reinterpret_cast<const U32N<K / 2> *>(b + p * slot);
+#pragma unroll
+      for (int q = 0; q < K / 2; ++q) acc[q] += v.v[q];  // two 16-bit sums per word
+    }
+#pragma unroll
+    for (int q = 0; q < K / 2; ++q) {
+      S[2 * q] = acc[q] & 0xFFFF;
+      S[2 * q + 1] = acc[q] >> 16;
+    }
   }
-  return s;
 }
 
 template <int K, int IN>
-__global__ __launch_bounds__(256) void disp_kernel(JobTable<DispJob> t) {
+__global__ __launch_bounds__(kDispThreads) void disp_kernel(JobTable<DispJob> t) {
   extern __shared__ uint32_t smem[];
   const int ji = find_job(t.j, t.n, (int)blockIdx.x);
   const DispJob &J = t.j[ji];
   const int y = (int)blockIdx.x - J.blk0;
   const int W = J.W, D = J.D;
-  uint32_t *keyR = smem;                                      // [W]
-  uint16_t *dl = reinterpret_cast<uint16_t *>(smem + W);      // [W]
-  for (int i = threadIdx.x; i < W; i += blockDim.x) keyR[i] = 0xFFFFFFFFu;
+  uint32_t *keyR = smem;                                  // [W]
+  uint16_t *dl = reinterpret_cast<uint16_t *>(smem + W);  // [W]
+  if (J.lr_check)
+    for (int i = threadIdx.x; i < W; i += blockDim.x) keyR[i] = 0xFFFFFFFFu;
   __syncthreads();
-  const int64_t cells = (int64_t)J.H * W * D;
-  const int g = threadIdx.x >> 4, j = threadIdx.x & 15;
+  const int j = threadIdx.x & 15;
   const int dbase = j * K;
-  for (int x = g; x < W; x += 16) {
-    const int64_t cell0 = ((int64_t)y * W + x) * D;
+  const int dvalid = min(K, max(0, D - dbase));
+  for (int x = (int)(threadIdx.x >> 4); x < W; x += kDispThreads / 16) {
+    const int64_t pix = (int64_t)y * W + x;
+    uint32_t S[K];
+    load_sums<K, IN>(J, pix, dbase, dvalid, S);
     uint32_t best = 0xFFFFFFFFu;
 #pragma unroll
     for (int k = 0; k < K; ++k) {
-      const int d = dbase + k;
-      if (d < D) {
-        const uint32_t key = (load_cost_sum<IN>(J, cell0 + d, cells) << 8) | (uint32_t)d;
+      if (k < dvalid) {
+        const int d = dbase + k;
+        const uint32_t key = (S[k] << 8) | (uint32_t)d;
         best = min(best, key);
         if (J.lr_check && x >= d) atomicMin(&keyR[x - d], key);
       }
     }
-    best = row16_min_u32(best);
+    best = row16_allmin_u32(best);
     if (j == 0) dl[x] = (uint16_t)(best & 0xFF);
   }
   __syncthreads();
@@ -77,37 +121,33 @@ __global__ __launch_bounds__(256) void disp_kernel(JobTable<DispJob> t) {
 template <int K>
 static void launch_disp_k(int in_kind, const JobTable<DispJob> &t, int blocks, size_t lds,
                           hipStream_t s) {
+  const dim3 b(kDispThreads);
   switch (in_kind) {
-    case 0: hipLaunchKernelGGL((disp_kernel<K, 0>), dim3(blocks), dim3(256), lds, s, t); break;
-    case 1: hipLaunchKernelGGL((disp_kernel<K, 1>), dim3(blocks), dim3(256), lds, s, t); break;
-    default: hipLaunchKernelGGL((disp_kernel<K, 2>), dim3(blocks), dim3(256), lds, s, t); break;
+    case 0: hipLaunchKernelGGL((disp_kernel<K, 0>), dim3(blocks), b, lds, s, t); break;
+    case 1: hipLaunchKernelGGL((disp_kernel<K, 1>), dim3(blocks), b, lds, s, t); break;
+    default: hipLaunchKernelGGL((disp_kernel<K, 2>), dim3(blocks), b, lds, s, t); break;
   }
 }
 
 void launch_disparity(std::vector<DispJob> jobs, int in_kind, hipStream_t s) {
-  // one launch per lanes-per-pixel width K (d per lane), so each frame gets
-  // the narrowest K with 16*K >= D
-  for (int K : {1, 2, 4, 8, 16}) {
+  // one launch per disparities-per-lane width K
+  for (int K : {4, 8, 12, 16}) {
     std::vector<DispJob> sub;
     int maxw = 0;
-    for (auto &j : jobs) {
-      int need = 1;
-      while (16 * need < j.D) need *= 2;
-      if (need == K) {
+    for (auto &j : jobs)
+      if (agg_k(j.D) == K) {
         sub.push_back(j);
         maxw = std::max(maxw, j.W);
       }
-    }
     if (sub.empty()) continue;
     const size_t lds = (size_t)maxw * 6;
     for_each_table(
         sub, [](const DispJob &j) { return (long)j.H; },
         [&](const JobTable<DispJob> &t, int blocks) {
           switch (K) {
-            case 1: launch_disp_k<1>(in_kind, t, blocks, lds, s); break;
-            case 2: launch_disp_k<2>(in_kind, t, blocks, lds, s); break;
             case 4: launch_disp_k<4>(in_kind, t, blocks, lds, s); break;
             case 8: launch_disp_k<8>(in_kind, t, blocks, lds, s); break;
+            case 12: launch_disp_k<12>(in_kind, t, blocks, lds, s); break;
             default: launch_disp_k<16>(in_kind, t, blocks, lds, s); break;
           }
         });

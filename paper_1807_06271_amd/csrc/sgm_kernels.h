@@ -27,54 +27,58 @@ struct CensusJob {
 void launch_census(std::vector<CensusJob> jobs, hipStream_t s);
 
 // ------------------------------------------------------------------ cost
+// Hamming costs of equation (1).  out16 != null: the caller's uint16
+// [H][W][D] volume.  Otherwise out8: the internal uint8 [H][W][Dp] volume
+// (Dp = 16 * agg_k(D); cells with d >= D hold N_b).
 struct CostJob {
   const uint64_t *cl, *cr;
-  uint16_t *cost;  // [H][W][D]
-  int W, H, D, nbits;
+  uint16_t *out16;
+  uint8_t *out8;
+  int W, H, D, Dp, nbits;
   int blk0, chunks_x;
 };
 void launch_cost(std::vector<CostJob> jobs, hipStream_t s);
 
 // ----------------------------------------------------------- aggregation
-// Source of the matching costs inside the aggregation kernel.
-enum AggSource { kFromCost = 0, kFromCensus = 1 };
+// Disparities per lane for D (16 lanes per scanline): 4, 8, 12 or 16.
+int agg_k(int D);
+// Number of scanlines of direction `dir` on a W x H image.
+__host__ __device__ int agg_lines(int dir, int W, int H);
 
 struct AggJob {
-  const uint16_t *cost;          // kFromCost: [H][W][D]
-  const uint64_t *cl, *cr;       // kFromCensus: [H][W] each
-  void *lr;                      // path costs [P][H][W][D], uint8 or uint16
-  int W, H, D, nbits, p1, p2;
+  const uint8_t *cost8;          // internal padded uint8 costs [H][W][Dp], or
+  const uint16_t *cost16;        // the caller's uint16 costs [H][W][D]
+  void *lr;                      // path costs [P][H][W][Dp], uint8 or uint16
+  int W, H, D, Dp, p1, p2;
   int ndirs;                     // P = number of active directions
   int dirs[8];                   // direction index of each slot
-  int line0[9];                  // first scanline (wave) of each slot; line0[P] = total
-  int blk0;                      // first global wave (one wave per scanline)
+  int line0[9];                  // first wave of each slot; line0[P] = waves of the job
+  int blk0;                      // first global wave of this job
 };
-// dpl: disparities per lane (D <= 64 * dpl); lr_bytes: 1 or 2.
-void launch_aggregate(std::vector<AggJob> jobs, AggSource src, int dpl, int lr_bytes,
+// K = agg_k(D) of every job; lr_bytes: 1 or 2.
+void launch_aggregate(std::vector<AggJob> jobs, bool from_cost16, int K, int lr_bytes,
                       hipStream_t s);
-// Number of scanlines of direction `dir` on a W x H image.
-int agg_lines(int dir, int W, int H);
 
-// Sum of the P path-cost volumes into S (uint16 [cells]).
+// S (unpadded uint16 [H][W][D]) = sum over the P slots of the padded path costs.
 struct SumJob {
   const void *lr;
   uint16_t *S;
-  int64_t cells;
-  int P;
+  int64_t cells;  // H * W * D
+  int D, Dp, P;
   int blk0;
 };
 void launch_sum(std::vector<SumJob> jobs, int lr_bytes, hipStream_t s);
 
 // ------------------------------------------------ disparity selection
 // WTA, right-view disparity and left-right check for one image row per
-// block.  Input is either S (uint16) or the P path-cost volumes (summed on
-// the fly).
+// block.  Input is either S (caller's unpadded uint16) or the P padded path
+// cost volumes, summed on the fly.
 struct DispJob {
   const uint16_t *S;  // [H][W][D] or null
-  const void *lr;     // [P][H][W][D] or null
+  const void *lr;     // [P][H][W][Dp] or null
   int P;
   uint16_t *out;      // [H][W]: LR-checked map (or D_L when lr_check = 0)
-  int W, H, D;
+  int W, H, D, Dp;
   int lr_check, max_diff;
   int invalid;
   int blk0;

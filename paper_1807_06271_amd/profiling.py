@@ -1,0 +1,105 @@
+"""Summaries of rocprofv3 CSV output for the profiles/ directory.
+
+    python -m paper_1807_06271_amd.profiling stats  <kernel_stats.csv> <out.txt> "<command>"
+    python -m paper_1807_06271_amd.profiling traffic <fetch_counter_collection.csv> \
+        <write_counter_collection.csv> <out.json> "<fetch command>" "<write command>"
+
+`stats` keeps the per-kernel call count and average / min / max durations.
+`traffic` turns FETCH_SIZE and WRITE_SIZE (KiB per dispatch) into bytes per
+launch of each kernel, scaled by what the same counter reads for the plain
+copy kernel of known size that the profiled run also executes (bench.py
+--calibrate-copy copies CALIBRATION_BYTES between two device buffers); the
+JSON also records a hash of the kernel sources, so a reader can tell whether
+the counters still describe the current kernels.
+"""
+from __future__ import annotations
+
+import csv
+import hashlib
+import json
+import os
+import sys
+from collections import defaultdict
+
+CALIBRATION_BYTES = 1 << 30  # 1 GiB device-to-device copy
+PKG = os.path.dirname(os.path.abspath(__file__))
+
+
+def source_hash(files=("aggregate.hip", "device_util.h", "sgm_kernels.h")) -> str:
+    h = hashlib.sha256()
+    for f in files:
+        with open(os.path.join(PKG, "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def short_name(name: str) -> str:
+    name = name.replace("(sgmk::JobTable<sgmk::", "(").replace("void ", "")
+    return name[:110]
+
+
+def stats(csv_path: str, out_path: str, command: str) -> None:
+    rows = list(csv.DictReader(open(csv_path)))
+    lines = ["# rocprofv3 kernel statistics", "# command: " + command, "#",
+             "%-100s %6s %12s %12s %12s %7s" % ("kernel", "calls", "avg_us", "min_us", "max_us", "pct")]
+    for r in rows:
+        lines.append("%-100s %6s %12.1f %12.1f %12.1f %7.2f" % (
+            short_name(r["Name"]), r["Calls"], float(r["AverageNs"]) / 1e3, float(r["MinNs"]) / 1e3,
+            float(r["MaxNs"]) / 1e3, float(r["Percentage"])))
+    open(out_path, "w").write("\n".join(lines) + "\n")
+
+
+def _per_kernel(csv_path: str, counter: str):
+    """{kernel name: [per-dispatch counter values]} from counter_collection.csv."""
+    acc = defaultdict(list)
+    for r in csv.DictReader(open(csv_path)):
+        if r.get("Counter_Name") != counter:
+            continue
+        acc[r["Kernel_Name"]].append(float(r["Counter_Value"]))
+    return acc
+
+
+def traffic(fetch_csv: str, write_csv: str, out_path: str, fetch_cmd: str, write_cmd: str) -> dict:
+    f = _per_kernel(fetch_csv, "FETCH_SIZE")
+    w = _per_kernel(write_csv, "WRITE_SIZE")
+    copy = [k for k in f if "copy" in k.lower() or "elementwise" in k.lower()]
+    # the calibration copy is the dispatch whose fetch is largest among copies
+    best = None
+    for k in copy:
+        for v in f[k]:
+            if best is None or v > best[1]:
+                best = (k, v)
+    if best is None:
+        raise SystemExit("no copy kernel found for calibration")
+    cname, cfetch = best
+    cwrite = max(w.get(cname, [0.0]))
+    fetch_factor = CALIBRATION_BYTES / (cfetch * 1024.0)
+    write_factor = CALIBRATION_BYTES / (cwrite * 1024.0) if cwrite else None
+    kernels = {}
+    for k in f:
+        if k == cname:
+            continue
+        fv = sorted(f[k])[len(f[k]) // 2]
+        wv = sorted(w.get(k, [0.0]))[len(w.get(k, [0.0])) // 2]
+        kernels[short_name(k)] = {
+            "dispatches": len(f[k]),
+            "fetch_kib_median": fv, "write_kib_median": wv,
+            "fetch_bytes": fv * 1024.0 * fetch_factor,
+            "write_bytes": wv * 1024.0 * (write_factor or 1.0),
+        }
+    out = {"calibration": {"kernel": short_name(cname), "bytes": CALIBRATION_BYTES,
+                           "fetch_kib": cfetch, "write_kib": cwrite,
+                           "fetch_factor": fetch_factor, "write_factor": write_factor},
+           "source_hash": source_hash(), "fetch_command": fetch_cmd, "write_command": write_cmd,
+           "kernels": kernels}
+    json.dump(out, open(out_path, "w"), indent=1)
+    return out
+
+
+if __name__ == "__main__":
+    if sys.argv[1] == "stats":
+        stats(sys.argv[2], sys.argv[3], sys.argv[4])
+    elif sys.argv[1] == "traffic":
+        traffic(sys.argv[2], sys.argv[3], sys.argv[4], sys.argv[5], sys.argv[6])
+    else:
+        raise SystemExit(__doc__)

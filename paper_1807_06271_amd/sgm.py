@@ -34,7 +34,7 @@ PATHS_ALL8 = 0xFF
 EXPORTS = ["sgm_validate", "sgm_create", "sgm_destroy", "sgm_last_error", "sgm_census", "sgm_cost",
            "sgm_aggregate",
            "sgm_disparity", "uv_maps", "sgm_submit", "sgm_poll", "sgm_wait", "sgm_memory", "sgm_profile",
-           "sgm_profile_read"]
+           "sgm_profile_read", "sgm_set_streams"]
 STAGES = ["census", "aggregate", "disparity", "median", "uv"]
 
 
@@ -123,6 +123,7 @@ def lib():
         L.sgm_wait.argtypes = [vp, ctypes.c_uint64]
         L.sgm_memory.argtypes = [vp, P(ctypes.c_size_t), P(ctypes.c_size_t)]
         L.sgm_profile.argtypes = [vp, i32]
+        L.sgm_set_streams.argtypes = [vp, i32]
         L.sgm_profile_read.argtypes = [vp, P(ctypes.c_double), P(ctypes.c_uint64), i32]
         for name in EXPORTS:
             if name != "sgm_last_error":
@@ -305,6 +306,10 @@ def sgm_memory(ctx: Context):
     a, b = ctypes.c_size_t(), ctypes.c_size_t()
     _check(lib().sgm_memory(ctx.handle, ctypes.byref(a), ctypes.byref(b)), "sgm_memory")
     return a.value, b.value
+
+
+def sgm_set_streams(ctx: Context, n: int) -> None:
+    _check(lib().sgm_set_streams(ctx.handle, int(n)), "sgm_set_streams")
 
 
 def sgm_profile(ctx: Context, enable: bool) -> None:
