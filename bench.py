@@ -92,6 +92,13 @@ def bench_batch32(torch, sgm, ctx, synthetic):
         frames.append(sgm.Frame.alloc(p, torch.from_numpy(L).cuda(), torch.from_numpy(R).cuda()))
     evals = sum(f.p.disp_evals() for f in frames)
     res = {}
+    # autotune each distinct shape once on its first frame
+    tuned = {}
+    for f in frames:
+        key = (f.p.width, f.p.height, f.p.max_disp)
+        if key not in tuned:
+            tuned[key] = sgm.sgm_autotune(ctx, f, reps=3)[0]
+    res["schedules"] = {"%dx%d D%d" % k: v for k, v in tuned.items()}
     # one submit of all 32
     for _ in range(2):
         sgm.sgm_wait(ctx, sgm.sgm_submit(ctx, frames))
@@ -136,6 +143,7 @@ def bench_large(torch, sgm, ctx, synthetic, nframes=8):
         p.invalid = 65535
         frames.append(sgm.Frame.alloc(p, torch.from_numpy(L).cuda(), torch.from_numpy(R).cuda()))
     evals = sum(f.p.disp_evals() for f in frames)
+    h_lanes = sgm.sgm_autotune(ctx, frames[0], reps=2)[0]
     sgm.sgm_wait(ctx, sgm.sgm_submit(ctx, frames))
     sgm.sgm_profile_read(ctx, reset=True)
     torch.cuda.synchronize()
@@ -150,6 +158,7 @@ def bench_large(torch, sgm, ctx, synthetic, nframes=8):
     agg_avg = agg_ms / max(agg_n, 1)
     achieved = ALG_BYTES_PER_EVAL * evals / (agg_avg * 1e-3) / 1e9
     return {"frames": nframes, "width": 1920, "height": 1080, "max_disp": 256, "paths": 8,
+            "h_lanes": h_lanes,
             "batch_ms": t * 1e3, "mdisp_evals_per_s": evals / t / 1e6, "fps": nframes / t,
             "aggregate_launch_ms": agg_avg,
             "aggregate_alg_GBs": achieved, "aggregate_hbm_frac": achieved / HBM_PEAK_GBS,
@@ -233,6 +242,9 @@ def main():
     ctx = sgm.Context(0)
     sgm.sgm_profile(ctx, True)
 
+    # autotune the schedule of this shape once (the winner stays in the context)
+    h_lanes, tune_ms = sgm.sgm_autotune(ctx, sgm.Frame.alloc(p, L, R), reps=5)
+    log("autotuned h_lanes", h_lanes, tune_ms)
     log("main: 1242x375 D=128 8 paths, steps", args.steps)
     # one stream: the frames run back to back, so each kernel's event-timed
     # duration is its own (no other frame shares the GPU meanwhile)
@@ -306,7 +318,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": "1242x375 uint8 pair, D=128, Census 9x7, 8 paths, P1=10, P2=120, "
                                "LR |dL-dR|<=1, 3x3 median, U/V maps (KITTI-shaped slanted planes)",
-                   "frames_per_step": 1, "streams": 1, "path": "sgm_submit (fused kernels)"},
+                   "frames_per_step": 1, "streams": 1, "path": "sgm_submit (fused kernels)",
+                   "schedule": {"h_lanes": h_lanes, "autotune_ms": tune_ms}},
         "fps": round(args.steps / dt, 1),
         "frame_latency_ms": {"p50": float(np.percentile(lat_ms, 50)), "p99": float(np.percentile(lat_ms, 99))},
         "stage_avg_ms": {k: round(v, 5) for k, v in stage_avg_ms.items()},

@@ -184,6 +184,32 @@ int sgm_poll(sgm_ctx *ctx, uint64_t ticket, int *done);
 /* Block until the ticket's batch has finished, then behave as sgm_poll. */
 int sgm_wait(sgm_ctx *ctx, uint64_t ticket);
 
+/* Work schedule of the whole-path kernels for one frame shape.  Only the
+ * speed depends on it; every schedule gives bit-identical results. */
+typedef struct {
+  /* lanes per horizontal (left-right) scanline in the aggregation: 16, 32 or
+   * 64; 0 = the library's default for the shape.  Wider rows shorten the
+   * dependent chain along the long image rows; other paths use 16 lanes. */
+  int32_t h_lanes;
+  int32_t reserved[3]; /* must be 0 */
+} sgm_schedule;
+
+/* Set the schedule used by sgm_submit for frames of the shape of `shape`
+ * (width, height, max_disp, path_mask and the path-cost width it implies);
+ * with shape == NULL, set the default for shapes without an entry. */
+int sgm_set_schedule(sgm_ctx *ctx, const sgm_params *shape, const sgm_schedule *s);
+/* The schedule sgm_submit would use for `shape` (after defaults). */
+int sgm_get_schedule(sgm_ctx *ctx, const sgm_params *shape, sgm_schedule *s);
+/* Autotuner: run `sample` (one frame, inputs and outputs as for sgm_submit)
+ * under every candidate schedule, `reps` timed repetitions each after one
+ * warm-up, keep the fastest for the sample's shape (as sgm_set_schedule) and
+ * return it in *best (may be NULL).  Blocks until done.  `ms`, if non-NULL,
+ * receives per-candidate milliseconds for up to `n_ms` candidates in the
+ * order 16, 32, 64 lanes (-1 where a candidate does not apply).  Must not
+ * run concurrently with other submissions on the same context. */
+int sgm_autotune(sgm_ctx *ctx, const sgm_frame *sample, int reps, sgm_schedule *best, float *ms,
+                 int n_ms);
+
 /* Stage timing of batches (sgm_submit).  While enabled, every stage of a
  * batch is bracketed by HIP events on the batch's stream; when the batch is
  * found done (sgm_poll / sgm_wait) the elapsed times are added per stage.

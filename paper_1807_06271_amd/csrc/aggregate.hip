@@ -81,16 +81,26 @@ enum { kCost8 = 0, kCost16 = 1 };
 
 template <int K, int SRC>
 struct CostWords {
-  static constexpr int N = SRC == kCost8 ? K / 4 : K / 2;
+  static constexpr int N = SRC == kCost8 ? (K + 3) / 4 : K / 2;
   uint32_t w[N];
 };
 
 template <int K, int SRC>
 __device__ __forceinline__ void load_cost(CostWords<K, SRC> &cw, const char *p, int dvalid) {
   if (SRC == kCost8) {
-    const U32N<K / 4> v = *reinterpret_cast<const U32N<K / 4> *>(p);
+    if (K % 4 == 0) {  // dword-aligned (Dp and K are multiples of 4)
+      const U32N<K / 4> v = *reinterpret_cast<const U32N<K / 4> *>(p);
 #pragma unroll
-    for (int i = 0; i < K / 4; ++i) cw.w[i] = v.v[i];
+      for (int i = 0; i < K / 4; ++i) cw.w[i] = v.v[i];
+    } else {  // K = 2 or 6: 2-byte aligned, one 16-bit load per pair
+      const uint16_t *q = reinterpret_cast<const uint16_t *>(p);
+#pragma unroll
+      for (int i = 0; i < (K + 3) / 4; ++i) {
+        const uint32_t lo = q[2 * i];
+        const uint32_t hi = 2 * i + 1 < K / 2 ? (uint32_t)q[2 * i + 1] : 0u;
+        cw.w[i] = lo | hi << 16;
+      }
+    }
   } else {
     const uint16_t *q = reinterpret_cast<const uint16_t *>(p);
 #pragma unroll
@@ -113,27 +123,41 @@ __device__ __forceinline__ u16x2 cost_pair(const CostWords<K, SRC> &cw, int i) {
   return as_pair(cw.w[i]);
 }
 
-template <int K, int SRC, typename LT, int PF, bool PAD>
-__global__ __launch_bounds__(256) void agg_kernel(JobTable<AggJob> t) {
-  constexpr int NP = K / 2;  // packed pairs per lane
-  const int gw = uniform((int)(blockIdx.x * 4 + (threadIdx.x >> 6)));  // global wave
+// Minimum over each group of LPS lanes (16, 32 or 64), delivered to every lane
+// of the group: a DPP row butterfly, then permlane swaps across row pairs and
+// wave halves.
+template <int LPS>
+__device__ __forceinline__ uint32_t group_allmin_u32(uint32_t v) {
+  v = row16_allmin_u32(v);
+  if (LPS >= 32) {
+    // rows (0,1) and (2,3) exchange: each lane then sees both rows' minima
+    const auto r = __builtin_amdgcn_permlane16_swap(v, v, false, false);
+    v = min((uint32_t)r[0], (uint32_t)r[1]);
+  }
+  if (LPS == 64) {
+    const auto r = __builtin_amdgcn_permlane32_swap(v, v, false, false);
+    v = min((uint32_t)r[0], (uint32_t)r[1]);
+  }
+  return v;
+}
+
+// One wave's share of one direction: 64/LPS scanlines side by side, LPS lanes
+// per scanline, K disparities per lane (K * LPS = Dp).
+template <int K, int LPS, int SRC, typename LT, int PF, bool PAD>
+__device__ __forceinline__ void agg_wave(const AggJob &J, int slot, int wave_in_slot) {
+  constexpr int NP = K / 2;       // packed pairs per lane
+  constexpr int SPW = 64 / LPS;   // scanlines per wave
   const int lane = (int)(threadIdx.x & 63);
-  const int row = lane >> 4, j = lane & 15;
-  const int ji = find_job(t.j, t.n, gw);
-  const AggJob &J = t.j[ji];
-  const int w = gw - J.blk0;
-  if (w >= J.line0[J.ndirs]) return;  // whole wave: tail of the grid
-  int slot = 0;
-  for (int k = 1; k < J.ndirs; ++k)
-    if (w >= J.line0[k]) slot = k;
+  const int row = lane / LPS, j = lane % LPS;
   const int dir = J.dirs[slot];
   const int W = J.W, H = J.H, D = J.D, Dp = J.Dp;
-  const int line = (w - J.line0[slot]) * 4 + row;
+  const int line = wave_in_slot * SPW + row;
   int sx = 0, sy = 0, len = 0;
   if (line < agg_lines(dir, W, H)) line_start(dir, line, W, H, sx, sy, len);
-  // the wave runs until its longest row is done
-  const int maxlen = max(max(__builtin_amdgcn_readlane(len, 0), __builtin_amdgcn_readlane(len, 16)),
-                         max(__builtin_amdgcn_readlane(len, 32), __builtin_amdgcn_readlane(len, 48)));
+  // the wave runs until its longest scanline is done
+  int maxlen = __builtin_amdgcn_readlane(len, 0);
+#pragma unroll
+  for (int r = 1; r < SPW; ++r) maxlen = max(maxlen, __builtin_amdgcn_readlane(len, r * LPS));
   const int64_t step = (int64_t)kDirDy[dir] * W + kDirDx[dir];  // pixel index step (uniform)
   const int64_t pix0 = (int64_t)sy * W + sx;
   const int dbase = j * K;
@@ -146,6 +170,9 @@ __global__ __launch_bounds__(256) void agg_kernel(JobTable<AggJob> t) {
     padmask[i] = (2 * i < dvalid ? 0u : 0xFFFFu) | (2 * i + 1 < dvalid ? 0u : 0xFFFF0000u);
   const u16x2 P1 = {(unsigned short)J.p1, (unsigned short)J.p1};
   const u16x2 P2 = {(unsigned short)J.p2, (unsigned short)J.p2};
+  // lanes at the ends of a scanline's lane group take "no such disparity"
+  // from outside the group
+  const bool first_lane = j == 0, last_lane = j == LPS - 1;
 
   // Addresses are a wave-uniform base that advances by a uniform step per
   // pixel plus a per-lane 32-bit offset that stays fixed along the scanline.
@@ -169,17 +196,29 @@ __global__ __launch_bounds__(256) void agg_kernel(JobTable<AggJob> t) {
   u16x2 Lp[NP];
 #pragma unroll
   for (int i = 0; i < NP; ++i) Lp[i] = as_pair(padmask[i]);
-  uint32_t mp = 0;  // the predecessor's minimum (row-uniform)
+  uint32_t mp = 0;  // the predecessor's minimum (uniform over the lane group)
 
   auto pixel = [&](int i, CostWords<K, SRC> &rs) {
     const CostWords<K, SRC> cw = rs;
     if (i + PF < len) load_cost<K, SRC>(rs, cbase + (int64_t)(i + PF) * cstep + coff, dvalid);
     // neighbour pairs: Nb[q] = (L[2q-1], L[2q]) for q = 0..NP, so that pair q
     // has its d-1 values in Nb[q] and its d+1 values in Nb[q+1]
-    const uint32_t prev = (uint32_t)__builtin_amdgcn_update_dpp(
-        (int)kInfPair, (int)as_u32(Lp[NP - 1]), kDppRowShr1, 0xF, 0xF, false);
-    const uint32_t next = (uint32_t)__builtin_amdgcn_update_dpp(
-        (int)kInfPair, (int)as_u32(Lp[0]), kDppRowShl1, 0xF, 0xF, false);
+    uint32_t prev, next;
+    if (LPS == 16) {
+      prev = (uint32_t)__builtin_amdgcn_update_dpp((int)kInfPair, (int)as_u32(Lp[NP - 1]), kDppRowShr1,
+                                                   0xF, 0xF, false);
+      next = (uint32_t)__builtin_amdgcn_update_dpp((int)kInfPair, (int)as_u32(Lp[0]), kDppRowShl1,
+                                                   0xF, 0xF, false);
+    } else {
+      prev = (uint32_t)__builtin_amdgcn_update_dpp((int)kInfPair, (int)as_u32(Lp[NP - 1]), kDppWaveShr1,
+                                                   0xF, 0xF, false);
+      next = (uint32_t)__builtin_amdgcn_update_dpp((int)kInfPair, (int)as_u32(Lp[0]), kDppWaveShl1,
+                                                   0xF, 0xF, false);
+      if (LPS < 64) {
+        prev = first_lane ? kInfPair : prev;
+        next = last_lane ? kInfPair : next;
+      }
+    }
     u16x2 Nb[NP + 1];
     Nb[0] = as_pair(__builtin_amdgcn_alignbit(as_u32(Lp[0]), prev, 16));
 #pragma unroll
@@ -199,11 +238,18 @@ __global__ __launch_bounds__(256) void agg_kernel(JobTable<AggJob> t) {
     if (i < len) {
       char *o = obase + (int64_t)i * ostep + ooff;
       if (sizeof(LT) == 1) {
-        U32N<K / 4> pk;
+        if (K % 4 == 0) {
+          U32N<K / 4> pk;
 #pragma unroll
-        for (int q = 0; q < K / 4; ++q)  // low bytes of the four 16-bit values
-          pk.v[q] = __builtin_amdgcn_perm(as_u32(Lc[2 * q + 1]), as_u32(Lc[2 * q]), 0x06040200u);
-        *reinterpret_cast<U32N<K / 4> *>(o) = pk;
+          for (int q = 0; q < K / 4; ++q)  // low bytes of the four 16-bit values
+            pk.v[q] = __builtin_amdgcn_perm(as_u32(Lc[2 * q + 1]), as_u32(Lc[2 * q]), 0x06040200u);
+          *reinterpret_cast<U32N<K / 4> *>(o) = pk;
+        } else {  // K = 2 or 6: 2-byte aligned, one 16-bit store per pair
+#pragma unroll
+          for (int q = 0; q < NP; ++q)
+            reinterpret_cast<uint16_t *>(o)[q] =
+                (uint16_t)__builtin_amdgcn_perm(0u, as_u32(Lc[q]), 0x0c0c0200u);
+        }
       } else {
         U32N<NP> pk;
 #pragma unroll
@@ -214,7 +260,7 @@ __global__ __launch_bounds__(256) void agg_kernel(JobTable<AggJob> t) {
     u16x2 lm = Lc[0];
 #pragma unroll
     for (int q = 1; q < NP; ++q) lm = pmin(lm, Lc[q]);
-    mp = row16_allmin_u32(min((uint32_t)lm.x, (uint32_t)lm.y));
+    mp = group_allmin_u32<LPS>(min((uint32_t)lm.x, (uint32_t)lm.y));
 #pragma unroll
     for (int q = 0; q < NP; ++q) Lp[q] = Lc[q];
   };
@@ -229,33 +275,83 @@ __global__ __launch_bounds__(256) void agg_kernel(JobTable<AggJob> t) {
     if (i0 + s < maxlen) pixel(i0 + s, ring[s]);
 }
 
-template <int K, int SRC, typename LT>
+// Scanlines per wave of direction `dir` under a schedule whose horizontal
+// directions use `hlps` lanes per scanline (all others use 16).
+__host__ __device__ inline int lanes_per_scanline(int dir, int hlps) { return dir < 2 ? hlps : 16; }
+
+// Each wave finds its job and direction slot, then runs that direction's
+// scanlines with the lane layout of the schedule: KH disparities per lane
+// over HLPS lanes for horizontal paths, K over 16 lanes for the others.
+template <int K, int KH, int HLPS, int SRC, typename LT, int PF, bool PAD>
+__global__ __launch_bounds__(256) void agg_kernel(JobTable<AggJob> t) {
+  const int gw = uniform((int)(blockIdx.x * 4 + (threadIdx.x >> 6)));  // global wave
+  const int ji = find_job(t.j, t.n, gw);
+  const AggJob &J = t.j[ji];
+  const int w = gw - J.blk0;
+  if (w >= J.line0[J.ndirs]) return;  // whole wave: tail of the grid
+  int slot = 0;
+  for (int k = 1; k < J.ndirs; ++k)
+    if (w >= J.line0[k]) slot = k;
+  const int wave_in_slot = w - J.line0[slot];
+  if (HLPS != 16 && J.dirs[slot] < 2)
+    agg_wave<KH, HLPS, SRC, LT, PF, PAD>(J, slot, wave_in_slot);
+  else
+    agg_wave<K, 16, SRC, LT, PF, PAD>(J, slot, wave_in_slot);
+}
+
+template <int K, int KH, int HLPS, int SRC, typename LT>
 static void launch_one(const JobTable<AggJob> &t, int waves, hipStream_t s) {
   constexpr int PF = SRC == kCost8 ? 8 : 4;
   const int blocks = (waves + 3) / 4;
   bool pad = false;  // some frame's D is not a multiple of 16*K: mask the tail lanes
   for (int i = 0; i < t.n; ++i) pad |= t.j[i].D != 16 * K;
-  if (pad) hipLaunchKernelGGL((agg_kernel<K, SRC, LT, PF, true>), dim3(blocks), dim3(256), 0, s, t);
-  else hipLaunchKernelGGL((agg_kernel<K, SRC, LT, PF, false>), dim3(blocks), dim3(256), 0, s, t);
+  if (pad) hipLaunchKernelGGL((agg_kernel<K, KH, HLPS, SRC, LT, PF, true>), dim3(blocks), dim3(256), 0, s, t);
+  else hipLaunchKernelGGL((agg_kernel<K, KH, HLPS, SRC, LT, PF, false>), dim3(blocks), dim3(256), 0, s, t);
 }
 
-template <int SRC, typename LT>
-static void launch_k(int K, const JobTable<AggJob> &t, int waves, hipStream_t s) {
+template <typename LT>
+static void launch_one_cost16(int K, const JobTable<AggJob> &t, int waves, hipStream_t s) {
   switch (K) {
-    case 4: launch_one<4, SRC, LT>(t, waves, s); break;
-    case 8: launch_one<8, SRC, LT>(t, waves, s); break;
-    case 12: launch_one<12, SRC, LT>(t, waves, s); break;
-    default: launch_one<16, SRC, LT>(t, waves, s); break;
+    case 4: launch_one<4, 4, 16, kCost16, LT>(t, waves, s); break;
+    case 8: launch_one<8, 8, 16, kCost16, LT>(t, waves, s); break;
+    case 12: launch_one<12, 12, 16, kCost16, LT>(t, waves, s); break;
+    default: launch_one<16, 16, 16, kCost16, LT>(t, waves, s); break;
   }
 }
 
-void launch_aggregate(std::vector<AggJob> jobs, bool from_cost16, int K, int lr_bytes,
+// Lanes per horizontal scanline available for a disparity width K (16 lanes):
+// the horizontal layout needs an even number of disparities per lane.
+bool agg_hlps_ok(int K, int hlps) {
+  if (hlps == 16) return true;
+  const int kh = 16 * K / hlps;
+  return (hlps == 32 || hlps == 64) && kh >= 2 && kh % 2 == 0;
+}
+
+template <int SRC, typename LT>
+static void launch_k(int K, int hlps, const JobTable<AggJob> &t, int waves, hipStream_t s) {
+  switch (K * 100 + hlps) {
+    case 416: launch_one<4, 4, 16, SRC, LT>(t, waves, s); break;
+    case 432: launch_one<4, 2, 32, SRC, LT>(t, waves, s); break;
+    case 816: launch_one<8, 8, 16, SRC, LT>(t, waves, s); break;
+    case 832: launch_one<8, 4, 32, SRC, LT>(t, waves, s); break;
+    case 864: launch_one<8, 2, 64, SRC, LT>(t, waves, s); break;
+    case 1216: launch_one<12, 12, 16, SRC, LT>(t, waves, s); break;
+    case 1232: launch_one<12, 6, 32, SRC, LT>(t, waves, s); break;
+    case 1616: launch_one<16, 16, 16, SRC, LT>(t, waves, s); break;
+    case 1632: launch_one<16, 8, 32, SRC, LT>(t, waves, s); break;
+    default: launch_one<16, 4, 64, SRC, LT>(t, waves, s); break;
+  }
+}
+
+void launch_aggregate(std::vector<AggJob> jobs, bool from_cost16, int K, int hlps, int lr_bytes,
                       hipStream_t s) {
+  if (from_cost16 || !agg_hlps_ok(K, hlps)) hlps = 16;
   for (auto &j : jobs) {
     int total = 0;
     for (int k = 0; k < j.ndirs; ++k) {
       j.line0[k] = total;
-      total += (agg_lines(j.dirs[k], j.W, j.H) + 3) / 4;  // four scanlines per wave
+      const int spw = 64 / lanes_per_scanline(j.dirs[k], hlps);  // scanlines per wave
+      total += (agg_lines(j.dirs[k], j.W, j.H) + spw - 1) / spw;
     }
     j.line0[j.ndirs] = total;
   }
@@ -263,11 +359,11 @@ void launch_aggregate(std::vector<AggJob> jobs, bool from_cost16, int K, int lr_
       jobs, [](const AggJob &j) { return (long)j.line0[j.ndirs]; },
       [&](const JobTable<AggJob> &t, int waves) {
         if (!from_cost16) {
-          if (lr_bytes == 1) launch_k<kCost8, uint8_t>(K, t, waves, s);
-          else launch_k<kCost8, uint16_t>(K, t, waves, s);
+          if (lr_bytes == 1) launch_k<kCost8, uint8_t>(K, hlps, t, waves, s);
+          else launch_k<kCost8, uint16_t>(K, hlps, t, waves, s);
         } else {
-          if (lr_bytes == 1) launch_k<kCost16, uint8_t>(K, t, waves, s);
-          else launch_k<kCost16, uint16_t>(K, t, waves, s);
+          if (lr_bytes == 1) launch_one_cost16<uint8_t>(K, t, waves, s);
+          else launch_one_cost16<uint16_t>(K, t, waves, s);
         }
       });
 }

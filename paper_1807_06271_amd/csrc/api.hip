@@ -9,6 +9,7 @@
 #include <map>
 #include <mutex>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "../../include/sgm.h"
@@ -112,6 +113,15 @@ struct Batch {
 
 }  // namespace
 
+struct ShapeKey {
+  int W, H, D;
+  uint32_t mask;
+  int lb;
+  bool operator<(const ShapeKey &o) const {
+    return std::tie(W, H, D, mask, lb) < std::tie(o.W, o.H, o.D, o.mask, o.lb);
+  }
+};
+
 struct sgm_ctx {
   int device = 0;
   size_t budget = 0;
@@ -125,6 +135,8 @@ struct sgm_ctx {
   int nstreams = 4;  // streams in use (round robin)
   int next_stream = 0;
   bool profiling = false;
+  sgm_schedule dflt{};                     // h_lanes 0: library default
+  std::map<ShapeKey, sgm_schedule> tuned;  // per-shape schedules (sgm_set_schedule / autotune)
   double stage_ms[SGM_NSTAGES] = {};
   uint64_t stage_count[SGM_NSTAGES] = {};
 
@@ -240,6 +252,35 @@ FramePlan plan_frame(const sgm_params &p, size_t base) {
 // Enqueue census -> aggregation (costs recomputed from the Census codes) ->
 // disparity selection -> median -> U/V maps for `n` frames on `s`, with the
 // frames' scratch at `mem` laid out by plan_frame.
+ShapeKey shape_key(const sgm_params &p) {
+  return ShapeKey{p.width, p.height, p.max_disp, p.path_mask, lr_bytes_of(p)};
+}
+
+// Lanes per horizontal scanline for a frame: the tuned entry for its shape,
+// else the context default, else a width rule measured on MI355X (wide
+// lane groups pay off on long rows, where the horizontal paths' dependent
+// chain is the critical path): 64 from 1024 columns, 32 from 400, else 16,
+// stepping down to a layout that fits the disparity count.
+int resolve_hlps(const sgm_ctx *c, const sgm_params &p) {
+  int h = 0;
+  auto it = c->tuned.find(shape_key(p));
+  if (it != c->tuned.end()) h = it->second.h_lanes;
+  if (h == 0) h = c->dflt.h_lanes;
+  if (h == 0) h = p.width >= 1024 ? 64 : p.width >= 400 ? 32 : 16;
+  const int K = k_of(p);
+  for (int cand : {64, 32, 16})
+    if (cand <= h && agg_hlps_ok(K, cand)) return cand;
+  return 16;
+}
+
+int check_schedule(const sgm_schedule *s) {
+  if (!s) return fail(SGM_EINVAL, "schedule is null");
+  if (s->h_lanes != 0 && s->h_lanes != 16 && s->h_lanes != 32 && s->h_lanes != 64)
+    return fail(SGM_EINVAL, "h_lanes must be 0, 16, 32 or 64 (got %d)", s->h_lanes);
+  if (s->reserved[0] || s->reserved[1] || s->reserved[2]) return fail(SGM_EINVAL, "reserved must be 0");
+  return SGM_OK;
+}
+
 // Brackets the launches of one stage with timing events when profiling.
 struct StageMark {
   std::vector<StageEvents> *out;
@@ -262,8 +303,9 @@ struct StageMark {
   }
 };
 
-int enqueue_frames(const sgm_frame *fr, int n, const std::vector<FramePlan> &plans, char *mem,
-                   hipStream_t s, std::vector<StageEvents> *prof) {
+int enqueue_frames(const sgm_frame *fr, int n, const std::vector<FramePlan> &plans,
+                   const std::vector<int> &hlps, char *mem, hipStream_t s,
+                   std::vector<StageEvents> *prof) {
   StageMark mark{prof, s};
   std::vector<CensusJob> cj;
   for (int i = 0; i < n; ++i) {
@@ -305,11 +347,12 @@ int enqueue_frames(const sgm_frame *fr, int n, const std::vector<FramePlan> &pla
   CHECK(mark.begin(SGM_STAGE_AGGREGATE));
   int groups = 0;
   for (int K : {4, 8, 12, 16})
-    for (int lb = 1; lb <= 2; ++lb) {
+    for (int lb = 1; lb <= 2; ++lb)
+    for (int c_hlps : {16, 32, 64}) {
       std::vector<AggJob> aj;
       for (int i = 0; i < n; ++i) {
         const sgm_params &p = fr[i].p;
-        if (k_of(p) != K || lr_bytes_of(p) != lb) continue;
+        if (k_of(p) != K || lr_bytes_of(p) != lb || hlps[i] != c_hlps) continue;
         AggJob j{};
         j.cost8 = reinterpret_cast<const uint8_t *>(mem + plans[i].off_cost);
         j.lr = mem + plans[i].off_lr;
@@ -323,7 +366,7 @@ int enqueue_frames(const sgm_frame *fr, int n, const std::vector<FramePlan> &pla
         aj.push_back(j);
       }
       if (!aj.empty()) {
-        launch_aggregate(aj, false, K, lb, s);
+        launch_aggregate(aj, false, K, c_hlps, lb, s);
         CHECK(check_launch());
         ++groups;
       }
@@ -526,7 +569,7 @@ int sgm_aggregate(sgm_ctx *c, const sgm_params *p, const uint16_t *cost, uint16_
   j.p1 = p->p1;
   j.p2 = p->p2;
   j.ndirs = fill_dirs(p->path_mask, j.dirs);
-  launch_aggregate({j}, true, k_of(*p), lb, s);
+  launch_aggregate({j}, true, k_of(*p), 16, lb, s);
   CHECK(check_launch());
   SumJob sj{};
   sj.lr = lr;
@@ -650,7 +693,9 @@ int sgm_submit(sgm_ctx *c, const sgm_frame *frames, int n, uint64_t *ticket) {
   b.stream = c->next_stream;
   c->next_stream = (c->next_stream + 1) % c->nstreams;
   hipStream_t s = c->streams[b.stream];
-  int rc = enqueue_frames(frames, n, plans, reinterpret_cast<char *>(blk.ptr), s,
+  std::vector<int> hl(n);
+  for (int i = 0; i < n; ++i) hl[i] = resolve_hlps(c, frames[i].p);
+  int rc = enqueue_frames(frames, n, plans, hl, reinterpret_cast<char *>(blk.ptr), s,
                           c->profiling ? &b.prof : nullptr);
   if (rc == SGM_OK && hipEventCreateWithFlags(&b.done, hipEventDisableTiming) != hipSuccess)
     rc = fail(SGM_EHIP, "hipEventCreate failed");
@@ -702,6 +747,77 @@ int sgm_wait(sgm_ctx *c, uint64_t ticket) {
   DeviceGuard g(c->device);
   int done = 0;
   return poll_locked(c, ticket, &done, true);
+}
+
+int sgm_set_schedule(sgm_ctx *c, const sgm_params *shape, const sgm_schedule *sc) {
+  if (!c) return fail(SGM_EINVAL, "ctx is null");
+  CHECK(check_schedule(sc));
+  if (shape) CHECK(validate(shape));
+  std::lock_guard<std::mutex> lk(c->mu);
+  if (shape) c->tuned[shape_key(*shape)] = *sc;
+  else c->dflt = *sc;
+  return SGM_OK;
+}
+
+int sgm_get_schedule(sgm_ctx *c, const sgm_params *shape, sgm_schedule *sc) {
+  if (!c || !sc) return fail(SGM_EINVAL, "ctx and schedule must be non-null");
+  CHECK(validate(shape));
+  std::lock_guard<std::mutex> lk(c->mu);
+  *sc = sgm_schedule{};
+  sc->h_lanes = resolve_hlps(c, *shape);
+  return SGM_OK;
+}
+
+int sgm_autotune(sgm_ctx *c, const sgm_frame *sample, int reps, sgm_schedule *best, float *ms,
+                 int n_ms) {
+  if (!c || !sample) return fail(SGM_EINVAL, "ctx and sample must be non-null");
+  if (reps < 1) return fail(SGM_EINVAL, "reps must be >= 1");
+  CHECK(validate(&sample->p));
+  const int cands[3] = {16, 32, 64};
+  float times[3] = {-1.f, -1.f, -1.f};
+  int bi = -1;
+  for (int ci = 0; ci < 3; ++ci) {
+    if (!agg_hlps_ok(k_of(sample->p), cands[ci])) continue;
+    sgm_schedule sc{};
+    sc.h_lanes = cands[ci];
+    CHECK(sgm_set_schedule(c, &sample->p, &sc));
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    uint64_t t = 0;
+    CHECK(sgm_submit(c, sample, 1, &t));  // warm-up (also sizes the scratch)
+    CHECK(sgm_wait(c, t));
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    hipStream_t s0 = c->streams[0];
+    const int saved = c->nstreams;
+    c->nstreams = 1;
+    c->next_stream = 0;
+    int rc = hipEventRecord(e0, s0) == hipSuccess ? SGM_OK : fail(SGM_EHIP, "event record");
+    std::vector<uint64_t> tk;
+    for (int r = 0; r < reps && rc == SGM_OK; ++r) {
+      rc = sgm_submit(c, sample, 1, &t);
+      if (rc == SGM_OK) tk.push_back(t);
+    }
+    if (rc == SGM_OK && hipEventRecord(e1, s0) != hipSuccess) rc = fail(SGM_EHIP, "event record");
+    for (uint64_t k : tk) {
+      int r2 = sgm_wait(c, k);
+      if (rc == SGM_OK) rc = r2;
+    }
+    c->nstreams = saved;
+    float el = 0.f;
+    if (rc == SGM_OK && hipEventSynchronize(e1) != hipSuccess) rc = fail(SGM_EHIP, "event sync");
+    if (rc == SGM_OK && hipEventElapsedTime(&el, e0, e1) != hipSuccess) rc = fail(SGM_EHIP, "elapsed");
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc) return rc;
+    times[ci] = el / reps;
+    if (bi < 0 || times[ci] < times[bi]) bi = ci;
+  }
+  sgm_schedule win{};
+  win.h_lanes = bi >= 0 ? cands[bi] : 16;
+  CHECK(sgm_set_schedule(c, &sample->p, &win));
+  if (best) *best = win;
+  for (int i = 0; ms && i < n_ms && i < 3; ++i) ms[i] = times[i];
+  return SGM_OK;
 }
 
 int sgm_set_streams(sgm_ctx *c, int n) {

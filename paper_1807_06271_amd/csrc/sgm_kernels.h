@@ -55,9 +55,11 @@ struct AggJob {
   int line0[9];                  // first wave of each slot; line0[P] = waves of the job
   int blk0;                      // first global wave of this job
 };
-// K = agg_k(D) of every job; lr_bytes: 1 or 2.
-void launch_aggregate(std::vector<AggJob> jobs, bool from_cost16, int K, int lr_bytes,
+// K = agg_k(D) of every job; hlps: lanes per horizontal scanline (16, 32 or
+// 64; falls back to 16 where the layout does not fit K); lr_bytes: 1 or 2.
+void launch_aggregate(std::vector<AggJob> jobs, bool from_cost16, int K, int hlps, int lr_bytes,
                       hipStream_t s);
+bool agg_hlps_ok(int K, int hlps);
 
 // S (unpadded uint16 [H][W][D]) = sum over the P slots of the padded path costs.
 struct SumJob {

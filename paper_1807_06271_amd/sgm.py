@@ -34,7 +34,8 @@ PATHS_ALL8 = 0xFF
 EXPORTS = ["sgm_validate", "sgm_create", "sgm_destroy", "sgm_last_error", "sgm_census", "sgm_cost",
            "sgm_aggregate",
            "sgm_disparity", "uv_maps", "sgm_submit", "sgm_poll", "sgm_wait", "sgm_memory", "sgm_profile",
-           "sgm_profile_read", "sgm_set_streams"]
+           "sgm_profile_read", "sgm_set_streams", "sgm_set_schedule", "sgm_get_schedule",
+           "sgm_autotune"]
 STAGES = ["census", "aggregate", "disparity", "median", "uv"]
 
 
@@ -51,6 +52,10 @@ class sgm_params(ctypes.Structure):
                 ("lr_check", ctypes.c_int32), ("lr_max_diff", ctypes.c_int32),
                 ("median", ctypes.c_int32), ("invalid", ctypes.c_uint16),
                 ("reserved", ctypes.c_uint16)]
+
+
+class sgm_schedule(ctypes.Structure):
+    _fields_ = [("h_lanes", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
 
 
 class sgm_frame(ctypes.Structure):
@@ -124,6 +129,9 @@ def lib():
         L.sgm_memory.argtypes = [vp, P(ctypes.c_size_t), P(ctypes.c_size_t)]
         L.sgm_profile.argtypes = [vp, i32]
         L.sgm_set_streams.argtypes = [vp, i32]
+        L.sgm_set_schedule.argtypes = [vp, P(sgm_params), P(sgm_schedule)]
+        L.sgm_get_schedule.argtypes = [vp, P(sgm_params), P(sgm_schedule)]
+        L.sgm_autotune.argtypes = [vp, P(sgm_frame), i32, P(sgm_schedule), P(ctypes.c_float), i32]
         L.sgm_profile_read.argtypes = [vp, P(ctypes.c_double), P(ctypes.c_uint64), i32]
         for name in EXPORTS:
             if name != "sgm_last_error":
@@ -306,6 +314,29 @@ def sgm_memory(ctx: Context):
     a, b = ctypes.c_size_t(), ctypes.c_size_t()
     _check(lib().sgm_memory(ctx.handle, ctypes.byref(a), ctypes.byref(b)), "sgm_memory")
     return a.value, b.value
+
+
+def sgm_set_schedule(ctx: Context, p: Params | None, h_lanes: int) -> None:
+    """Schedule for frames of p's shape (p=None: the default)."""
+    sc = sgm_schedule(h_lanes)
+    _check(lib().sgm_set_schedule(ctx.handle, ctypes.byref(p.c()) if p is not None else None,
+                                  ctypes.byref(sc)), "sgm_set_schedule")
+
+
+def sgm_get_schedule(ctx: Context, p: Params) -> int:
+    sc = sgm_schedule()
+    _check(lib().sgm_get_schedule(ctx.handle, ctypes.byref(p.c()), ctypes.byref(sc)), "sgm_get_schedule")
+    return sc.h_lanes
+
+
+def sgm_autotune(ctx: Context, sample: "Frame", reps: int = 5):
+    """Time every candidate schedule on `sample`, keep the fastest for its
+    shape; returns (h_lanes, {h_lanes: ms per frame})."""
+    best = sgm_schedule()
+    ms = (ctypes.c_float * 3)()
+    f = sample.c()
+    _check(lib().sgm_autotune(ctx.handle, ctypes.byref(f), reps, ctypes.byref(best), ms, 3), "sgm_autotune")
+    return best.h_lanes, {h: ms[i] for i, h in enumerate((16, 32, 64)) if ms[i] >= 0}
 
 
 def sgm_set_streams(ctx: Context, n: int) -> None:

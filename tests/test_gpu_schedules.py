@@ -1,0 +1,72 @@
+"""Schedules and the autotuner (GPU required): every aggregation lane layout
+gives output bit-identical to the oracle, and the autotuner keeps a valid
+schedule for the shape."""
+import numpy as np
+import pytest
+
+from gen import synthetic
+from gpu_util import announce, assert_equal, gpu_or_skip, to_dev, to_np
+from oracle import oracle as O
+
+pytestmark = pytest.mark.gpu
+
+SHAPES = [  # W, H, D, census, mask, p1, p2
+    (203, 61, 128, (9, 7), 0xFF, 10, 120),
+    (150, 40, 64, (5, 5), 0x0F, 10, 120),
+    (97, 33, 256, (9, 7), 0x03, 10, 120),
+    (120, 30, 192, (9, 7), 0xFF, 10, 120),
+    (131, 47, 60, (5, 5), 0x55, 8, 32),     # padded disparity rows
+    (90, 25, 100, (9, 7), 0xFF, 20, 300),   # padded, 16-bit path costs
+]
+
+
+@pytest.fixture(scope="module")
+def env():
+    torch = gpu_or_skip()
+    from paper_1807_06271_amd import sgm
+    ctx = sgm.Context(0)
+    yield torch, sgm, ctx
+    torch.cuda.synchronize()
+    ctx.close()
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+@pytest.mark.parametrize("h_lanes", [16, 32, 64])
+def test_every_lane_layout_matches_oracle(env, shape, h_lanes):
+    torch, sgm, ctx = env
+    W, H, D, (cw, ch), mask, p1, p2 = shape
+    announce("schedule", h_lanes, shape)
+    left, right, _ = synthetic.make_pair("kitti", W + D + mask, W, H, D)
+    p = sgm.Params(width=W, height=H, max_disp=D, census_w=cw, census_h=ch, path_mask=mask, p1=p1, p2=p2)
+    sgm.sgm_set_schedule(ctx, p, h_lanes)
+    used = sgm.sgm_get_schedule(ctx, p)
+    assert used in (16, 32, 64) and (used == h_lanes or used < h_lanes)
+    f = sgm.Frame.alloc(p, to_dev(torch, left), to_dev(torch, right))
+    sgm.sgm_wait(ctx, sgm.sgm_submit(ctx, [f]))
+    want = O.sgm(left, right, D, cw, ch, mask, p1, p2, True, 1, 3, p.inv())
+    assert_equal(to_np(f.disp), want["disp"], "disp h_lanes=%d" % h_lanes)
+    assert_equal(to_np(f.umap), want["umap"], "umap")
+    assert_equal(to_np(f.vmap), want["vmap"], "vmap")
+
+
+def test_autotune_keeps_a_valid_schedule(env):
+    torch, sgm, ctx = env
+    announce("autotune")
+    W, H, D = 300, 90, 128
+    left, right, _ = synthetic.make_pair("kitti", 77, W, H, D)
+    p = sgm.Params(width=W, height=H, max_disp=D)
+    f = sgm.Frame.alloc(p, to_dev(torch, left), to_dev(torch, right))
+    best, ms = sgm.sgm_autotune(ctx, f, reps=2)
+    assert best in ms and set(ms) == {16, 32, 64}
+    assert all(v > 0 for v in ms.values())
+    assert best == min(ms, key=ms.get)
+    assert sgm.sgm_get_schedule(ctx, p) == best
+    sgm.sgm_wait(ctx, sgm.sgm_submit(ctx, [f]))
+    want = O.sgm(left, right, D, 9, 7, 0xFF, 10, 120, True, 1, 3)
+    assert_equal(to_np(f.disp), want["disp"], "disp after autotune")
+
+
+def test_schedule_rejects_bad_values(env):
+    torch, sgm, ctx = env
+    with pytest.raises(sgm.SgmError):
+        sgm.sgm_set_schedule(ctx, None, 48)
