@@ -83,6 +83,27 @@ def cpu_baseline(left, right, p, seconds_target=12.0):
                       "scanlines), %.1f s" % (runs, p.width, p.height, p.max_disp, t_total)}
 
 
+def bench_small(torch, sgm, ctx, synthetic, steps=200):
+    """320x240, D=64, Census 5x5, L->R/R->L/T->B/B->T, WTA only: one pair per
+    step on one stream, then with 4 streams."""
+    L, R, _ = synthetic.make_pair("small", 1000)
+    p = sgm.Params(width=320, height=240, max_disp=64, census_w=5, census_h=5, path_mask=0x0F,
+                   p1=10, p2=120, lr_check=0, median=0)
+    Lt, Rt = torch.from_numpy(L).cuda(), torch.from_numpy(R).cuda()
+    h = sgm.sgm_autotune(ctx, sgm.Frame.alloc(p, Lt, Rt), reps=5)[0]
+    prof_on = True
+    sgm.sgm_profile(ctx, False)
+    res = {"h_lanes": h}
+    for streams in (1, 4):
+        sgm.sgm_set_streams(ctx, streams)
+        dt, _ = time_submit_stream(torch, sgm, ctx, lambda i: [sgm.Frame.alloc(p, Lt, Rt)], steps, 10)
+        res["streams%d_mdisp_evals_per_s" % streams] = p.disp_evals() * steps / dt / 1e6
+        res["streams%d_fps" % streams] = steps / dt
+    sgm.sgm_set_streams(ctx, 1)
+    sgm.sgm_profile(ctx, prof_on)
+    return res
+
+
 def bench_batch32(torch, sgm, ctx, synthetic):
     specs = synthetic.mixed_batch_specs(32, seed=2000)
     frames = []
@@ -92,6 +113,7 @@ def bench_batch32(torch, sgm, ctx, synthetic):
         frames.append(sgm.Frame.alloc(p, torch.from_numpy(L).cuda(), torch.from_numpy(R).cuda()))
     evals = sum(f.p.disp_evals() for f in frames)
     res = {}
+    sgm.sgm_profile(ctx, False)
     # autotune each distinct shape once on its first frame
     tuned = {}
     for f in frames:
@@ -110,6 +132,17 @@ def bench_batch32(torch, sgm, ctx, synthetic):
     torch.cuda.synchronize()
     tb = (time.perf_counter() - t0) / reps
     batched = [f.disp.clone() for f in frames]
+    sgm.sgm_set_graphs(ctx, True)
+    for _ in range(2):
+        sgm.sgm_wait(ctx, sgm.sgm_submit(ctx, frames))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        sgm.sgm_wait(ctx, sgm.sgm_submit(ctx, frames))
+    torch.cuda.synchronize()
+    tg = (time.perf_counter() - t0) / reps
+    sgm.sgm_set_graphs(ctx, False)
+    same_graph = all(torch.equal(a, f.disp) for a, f in zip(batched, frames))
     # 32 sequential per-frame submits, each waited for
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -131,7 +164,9 @@ def bench_batch32(torch, sgm, ctx, synthetic):
                sequential_submit_ms=ts * 1e3, sequential_submit_mdisp_evals_per_s=evals / ts / 1e6,
                sequential_stage_calls_ms=tst * 1e3,
                sequential_stage_calls_mdisp_evals_per_s=evals / tst / 1e6,
-               batched_equals_sequential=bool(same))
+               batched_equals_sequential=bool(same), graph_batched_ms=tg * 1e3,
+               graph_batched_mdisp_evals_per_s=evals / tg / 1e6, graph_equals_direct=bool(same_graph))
+    sgm.sgm_profile(ctx, True)
     return res
 
 
@@ -165,22 +200,38 @@ def bench_large(torch, sgm, ctx, synthetic, nframes=8):
             "stage_ms_per_batch": {k: v[0] / reps for k, v in prof.items()}}
 
 
-def bench_serve(torch, sgm, synthetic, seconds):
+def bench_serve(torch, sgm, synthetic, seconds, stress_cameras=48, stress_seconds=4.0):
+    """The 4-camera request loop at 30 fps per camera (640x480 and 1242x375,
+    D=128, 8 paths), continuous batching vs one frame at a time on the
+    identical trace; then the same with `stress_cameras` cameras, a load at
+    which one-at-a-time processing queues up.  Also checks that every frame's
+    disparity map is identical in both modes (alone vs in the mix)."""
     from paper_1807_06271_amd import serve
-    cams = []
+    base = []
     for cam in range(4):
         sc = synthetic.camera_scene(cam)
         pairs = [synthetic.render_pair(sc, k)[:2] for k in range(3)]
         p = kitti_params(sgm, sc.width, sc.height, 128)
-        cams.append(serve.Camera(p, pairs))
-    trace = synthetic.poisson_trace(4, 30.0, seconds, seed=3000)
-    out = {"cameras": 4, "fps_per_camera": 30, "seconds": seconds, "frames": len(trace)}
+        base.append((p, pairs))
+    out = {}
     with sgm.Context(0) as ctx:
-        # warm the batch-block cache and the kernels
-        serve.serve(ctx, cams, [(0.0, c, 0) for c in range(4)], continuous=True)
-        for mode, cont in (("continuous_batching", True), ("per_frame", False)):
-            stats, _ = serve.serve(ctx, cams, trace, continuous=cont)
-            out[mode] = stats
+        # autotune both frame shapes once (kept by the context)
+        for p, pairs in base[1:3]:
+            f = sgm.Frame.alloc(p, torch.from_numpy(pairs[0][0]).cuda(), torch.from_numpy(pairs[0][1]).cuda())
+            sgm.sgm_autotune(ctx, f, reps=3)
+        for label, ncam, secs in (("4cams_30fps", 4, seconds), ("%dcams_30fps" % stress_cameras, stress_cameras, stress_seconds)):
+            cams = [serve.Camera(base[c % 4][0], base[c % 4][1]) for c in range(ncam)]
+            trace = synthetic.poisson_trace(ncam, 30.0, secs, seed=3000 + ncam)
+            serve.serve(ctx, cams, [(0.0, c, 0) for c in range(min(ncam, 8))], continuous=True)  # warm-up
+            res = {"cameras": ncam, "fps_per_camera": 30, "seconds": secs, "frames": len(trace)}
+            maps = {}
+            for mode, cont in (("continuous_batching", True), ("per_frame", False)):
+                stats, done = serve.serve(ctx, cams, trace, continuous=cont)
+                res[mode] = stats
+                maps[mode] = done
+            a, b = maps["continuous_batching"], maps["per_frame"]
+            res["mix_equals_alone"] = bool(a.keys() == b.keys() and all(torch.equal(a[k], b[k]) for k in a))
+            out[label] = res
     return out
 
 
@@ -240,27 +291,39 @@ def main():
         torch.cuda.synchronize()
         del src, dst
     ctx = sgm.Context(0)
-    sgm.sgm_profile(ctx, True)
 
     # autotune the schedule of this shape once (the winner stays in the context)
     h_lanes, tune_ms = sgm.sgm_autotune(ctx, sgm.Frame.alloc(p, L, R), reps=5)
     log("autotuned h_lanes", h_lanes, tune_ms)
     log("main: 1242x375 D=128 8 paths, steps", args.steps)
-    # one stream: the frames run back to back, so each kernel's event-timed
-    # duration is its own (no other frame shares the GPU meanwhile)
+    # one stream: the frames run back to back, nothing else shares the GPU
     sgm.sgm_set_streams(ctx, 1)
+    sgm.sgm_profile(ctx, False)
     dt, outs = time_submit_stream(torch, sgm, ctx, lambda i: [sgm.Frame.alloc(p, L, R)],
                                   args.steps, args.warmup)
+    # the same loop again with per-stage HIP events (they add a marker per
+    # stage boundary, so they stay out of the headline loop); the
+    # aggregation kernel's event-timed duration gives the roofline position
+    sgm.sgm_profile(ctx, True)
+    sgm.sgm_profile_read(ctx, reset=True)
+    dtp, _ = time_submit_stream(torch, sgm, ctx, lambda i: [sgm.Frame.alloc(p, L, R)],
+                                args.steps, args.warmup)
     prof = sgm.sgm_profile_read(ctx, reset=True)
-    # the same frames with 4 streams: consecutive frames overlap on the GPU
+    # the same frames on 4 streams: consecutive frames overlap on the GPU
     sgm.sgm_profile(ctx, False)
     sgm.sgm_set_streams(ctx, 4)
     dt4, _ = time_submit_stream(torch, sgm, ctx, lambda i: [sgm.Frame.alloc(p, L, R)],
                                 args.steps, args.warmup)
-    sgm.sgm_profile(ctx, True)
+    # and in graph mode (captured batches replayed from the graph cache)
+    sgm.sgm_set_streams(ctx, 1)
+    sgm.sgm_set_graphs(ctx, True)
+    dtg, _ = time_submit_stream(torch, sgm, ctx, lambda i: [sgm.Frame.alloc(p, L, R)],
+                                args.steps, args.warmup)
+    sgm.sgm_set_graphs(ctx, False)
+    sgm.sgm_profile(ctx, True)  # the extras read stage times too
     evals = p.disp_evals()
     value = evals * args.steps / dt / 1e6
-    # per-stage averages over warmup + timed steps (every batch is profiled)
+    # per-stage averages over the profiled loop (warm-up + timed steps)
     n_batches = args.steps + args.warmup
     stage_avg_ms = {k: v[0] / max(v[1], 1) for k, v in prof.items()}
     agg_ms = stage_avg_ms["aggregate"]
@@ -288,13 +351,15 @@ def main():
 
     extras = {}
     if args.extras in ("batch", "all"):
+        log("320x240 D=64 5x5 4 paths, WTA only")
+        extras["small_320x240_d64_4path_wta"] = bench_small(torch, sgm, ctx, synthetic)
         log("batch of 32 mixed pairs")
         extras["batch32_mixed"] = bench_batch32(torch, sgm, ctx, synthetic)
         log("batch of 8 1920x1080 D=256")
         extras["batch8_1920x1080_d256"] = bench_large(torch, sgm, ctx, synthetic)
     if args.extras == "all":
         log("request loop, 4 cameras,", args.serve_seconds, "s per mode")
-        extras["served_4cams"] = bench_serve(torch, sgm, synthetic, args.serve_seconds)
+        extras["served"] = bench_serve(torch, sgm, synthetic, args.serve_seconds)
     ctx.close()
 
     cpu = None
@@ -330,7 +395,9 @@ def main():
                      "avg_launch_ms": round(agg_ms, 5), "launches": prof["aggregate"][1],
                      "batches_profiled": n_batches},
         "per_frame_stage_calls_mdisp_evals_per_s": round(stage_path, 2),
+        "profiled_loop_mdisp_evals_per_s": round(evals * args.steps / dtp / 1e6, 2),
         "four_streams_mdisp_evals_per_s": round(evals * args.steps / dt4 / 1e6, 2),
+        "graph_mode_mdisp_evals_per_s": round(evals * args.steps / dtg / 1e6, 2),
         "cpu_baseline": cpu,
         "extras": extras,
     }

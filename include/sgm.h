@@ -149,13 +149,15 @@ int sgm_disparity(sgm_ctx *ctx, const sgm_params *p, const uint16_t *aggr, uint1
 
 /* U-/V-maps (section 3.2): per-column and per-row disparity histograms of
  * disp; values >= D (the invalid marker) are not counted.  disp: device
- * uint16 [H][W]; umap: device uint16 [D][W]; vmap: device uint16 [H][D]. */
+ * uint16 [H][W]; umap: device uint16 [D][W], 4-byte aligned (SGM_EINVAL
+ * otherwise); vmap: device uint16 [H][D]. */
 int uv_maps(sgm_ctx *ctx, const sgm_params *p, const uint16_t *disp, uint16_t *umap,
             uint16_t *vmap, void *stream);
 
 /* One frame of the whole path for sgm_submit.  left/right: device uint8
- * [H][pitch]; disp, umap, vmap: device outputs as above (umap/vmap may be
- * NULL to skip the histograms). */
+ * [H][pitch] sharing one pitch; disp, umap, vmap: device outputs as above
+ * (umap 4-byte aligned; umap and vmap may both be NULL to skip the
+ * histograms). */
 typedef struct {
   const uint8_t *left, *right;
   int64_t pitch;
@@ -175,6 +177,17 @@ int sgm_submit(sgm_ctx *ctx, const sgm_frame *frames, int n, uint64_t *ticket);
  * 4 after sgm_create).  With 1, batches run one after another on the GPU;
  * with more, a batch can start while earlier ones still run. */
 int sgm_set_streams(sgm_ctx *ctx, int n);
+
+/* Graph mode for sgm_submit (0 = off, the default after sgm_create; 1 = on).
+ * When on, a batch's launches are captured into a HIP graph; graphs are
+ * cached by batch composition (frame shapes, parameters and schedules), and
+ * a later batch of the same composition updates the cached executable graph
+ * with its buffers and replays it instead of instantiating a new one.
+ * Batches submitted while stage profiling is enabled are launched directly. */
+int sgm_set_graphs(sgm_ctx *ctx, int on);
+/* Batches replayed from the graph cache (hits) and newly instantiated graphs
+ * (misses) since sgm_create; either pointer may be NULL. */
+int sgm_graph_stats(sgm_ctx *ctx, uint64_t *hits, uint64_t *misses);
 
 /* Non-blocking completion check: *done = 1 once every frame of the ticket's
  * batch is finished (its scratch is then returned to the budget and the

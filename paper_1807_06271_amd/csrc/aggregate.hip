@@ -293,8 +293,10 @@ __global__ __launch_bounds__(256) void agg_kernel(JobTable<AggJob> t) {
   for (int k = 1; k < J.ndirs; ++k)
     if (w >= J.line0[k]) slot = k;
   const int wave_in_slot = w - J.line0[slot];
+  // Wider lane groups finish a pixel in fewer instructions, so they prefetch
+  // proportionally further ahead to cover the same memory latency.
   if (HLPS != 16 && J.dirs[slot] < 2)
-    agg_wave<KH, HLPS, SRC, LT, PF, PAD>(J, slot, wave_in_slot);
+    agg_wave<KH, HLPS, SRC, LT, PF * HLPS / 16, PAD>(J, slot, wave_in_slot);
   else
     agg_wave<K, 16, SRC, LT, PF, PAD>(J, slot, wave_in_slot);
 }
@@ -369,26 +371,58 @@ void launch_aggregate(std::vector<AggJob> jobs, bool from_cost16, int K, int hlp
 }
 
 // S = sum over the P slots of the (padded) path-cost volumes, written
-// unpadded: one thread per output cell.
+// unpadded: one thread per (pixel, 4 consecutive disparities); the P slot
+// loads are issued together, summed as packed 16-bit fields.
 template <typename LT>
 __global__ __launch_bounds__(256) void sum_kernel(JobTable<SumJob> t) {
   const int ji = find_job(t.j, t.n, (int)blockIdx.x);
   const SumJob &J = t.j[ji];
-  const int64_t i = (int64_t)((int)blockIdx.x - J.blk0) * 256 + threadIdx.x;
-  if (i >= J.cells) return;
-  const int64_t pix = i / J.D;
-  const int d = (int)(i - pix * J.D);
-  const int64_t src = pix * J.Dp + d;
-  const int64_t slot_stride = J.cells / J.D * J.Dp;
-  const LT *lr = reinterpret_cast<const LT *>(J.lr);
-  uint32_t s = 0;
-  for (int p = 0; p < J.P; ++p) s += lr[(int64_t)p * slot_stride + src];
-  J.S[i] = (uint16_t)s;
+  const int qpp = J.Dp / 4;  // 4-disparity groups per pixel (padded)
+  const int64_t g = (int64_t)((int)blockIdx.x - J.blk0) * 256 + threadIdx.x;
+  const int64_t npix = J.cells / J.D;
+  if (g >= npix * qpp) return;
+  const int64_t pix = g / qpp;
+  const int d0 = (int)(g - pix * qpp) * 4;
+  if (d0 >= J.D) return;
+  const int64_t slot = npix * J.Dp;
+  const LT *src = reinterpret_cast<const LT *>(J.lr) + pix * J.Dp + d0;
+  uint32_t lo = 0, hi = 0;  // (d0, d0+2) and (d0+1, d0+3) as 16-bit pairs
+  if (sizeof(LT) == 1) {
+    uint32_t v[8];
+#pragma unroll
+    for (int p = 0; p < 8; ++p)
+      if (p < J.P) v[p] = *reinterpret_cast<const uint32_t *>(src + p * slot);
+#pragma unroll
+    for (int p = 0; p < 8; ++p) {
+      if (p >= J.P) break;
+      lo += v[p] & 0x00FF00FFu;
+      hi += (v[p] >> 8) & 0x00FF00FFu;
+    }
+  } else {
+    uint2 v[8];
+#pragma unroll
+    for (int p = 0; p < 8; ++p)
+      if (p < J.P) v[p] = *reinterpret_cast<const uint2 *>(src + p * slot);
+    uint32_t a = 0, b = 0;  // (d0, d0+1), (d0+2, d0+3)
+#pragma unroll
+    for (int p = 0; p < 8; ++p) {
+      if (p >= J.P) break;
+      a += v[p].x;
+      b += v[p].y;
+    }
+    lo = (a & 0xFFFF) | (b << 16);
+    hi = (a >> 16) | (b & 0xFFFF0000u);
+  }
+  const uint32_t s4[4] = {lo & 0xFFFF, hi & 0xFFFF, lo >> 16, hi >> 16};
+  uint16_t *dst = J.S + pix * J.D + d0;
+#pragma unroll
+  for (int k = 0; k < 4; ++k)
+    if (d0 + k < J.D) dst[k] = (uint16_t)s4[k];
 }
 
 void launch_sum(std::vector<SumJob> jobs, int lr_bytes, hipStream_t s) {
   for_each_table(
-      jobs, [](const SumJob &j) { return (long)((j.cells + 255) / 256); },
+      jobs, [](const SumJob &j) { return (long)((j.cells / j.D * (j.Dp / 4) + 255) / 256); },
       [&](const JobTable<SumJob> &t, int blocks) {
         if (lr_bytes == 1) hipLaunchKernelGGL(sum_kernel<uint8_t>, dim3(blocks), dim3(256), 0, s, t);
         else hipLaunchKernelGGL(sum_kernel<uint16_t>, dim3(blocks), dim3(256), 0, s, t);

@@ -135,6 +135,9 @@ struct sgm_ctx {
   int nstreams = 4;  // streams in use (round robin)
   int next_stream = 0;
   bool profiling = false;
+  bool graphs = false;
+  std::map<std::string, hipGraphExec_t> graph_cache;  // by batch composition
+  uint64_t graph_hits = 0, graph_misses = 0;
   sgm_schedule dflt{};                     // h_lanes 0: library default
   std::map<ShapeKey, sgm_schedule> tuned;  // per-shape schedules (sgm_set_schedule / autotune)
   double stage_ms[SGM_NSTAGES] = {};
@@ -230,19 +233,16 @@ int check_dev_ptr(const void *ptr, int dev, const char *name) {
 // ------------------------------------------------------ whole-frame plan
 
 struct FramePlan {
-  size_t off_cl, off_cr, off_cost, off_lr, off_dlr, bytes;
+  size_t off_cost, off_lr, off_dlr, bytes;
 };
 
-// Scratch of one frame of a batch: Census codes of both views, the padded
-// uint8 cost volume, the P padded path-cost volumes and the LR-checked map
-// before the median.
+// Scratch of one frame of a batch: the padded uint8 cost volume, the P
+// padded path-cost volumes and the LR-checked map before the median.
 FramePlan plan_frame(const sgm_params &p, size_t base) {
   const size_t px = (size_t)p.width * p.height;
   const size_t dp = (size_t)dp_of(p);
   FramePlan f;
-  f.off_cl = base;
-  f.off_cr = f.off_cl + align256(px * 8);
-  f.off_cost = f.off_cr + align256(px * 8);
+  f.off_cost = base;
   f.off_lr = f.off_cost + align256(px * dp);
   f.off_dlr = f.off_lr + align256(px * dp * (size_t)popcount8(p.path_mask) * lr_bytes_of(p));
   f.bytes = f.off_dlr + align256(px * 2) - base;
@@ -271,6 +271,21 @@ int resolve_hlps(const sgm_ctx *c, const sgm_params &p) {
   for (int cand : {64, 32, 16})
     if (cand <= h && agg_hlps_ok(K, cand)) return cand;
   return 16;
+}
+
+// Everything that decides a batch's launch sequence (kernels, grids, LDS):
+// the frames' parameters and schedules, in order.
+std::string composition_key(const sgm_frame *fr, int n, const std::vector<int> &hlps) {
+  std::string k;
+  char buf[160];
+  for (int i = 0; i < n; ++i) {
+    const sgm_params &p = fr[i].p;
+    snprintf(buf, sizeof buf, "%d,%d,%d,%d,%d,%u,%u,%u,%d,%d,%d,%u,%d,%d;", p.width, p.height,
+             p.max_disp, p.census_w, p.census_h, p.path_mask, p.p1, p.p2, p.lr_check, p.lr_max_diff,
+             p.median, p.invalid, hlps[i], fr[i].umap ? 1 : 0);
+    k += buf;
+  }
+  return k;
 }
 
 int check_schedule(const sgm_schedule *s) {
@@ -307,42 +322,29 @@ int enqueue_frames(const sgm_frame *fr, int n, const std::vector<FramePlan> &pla
                    const std::vector<int> &hlps, char *mem, hipStream_t s,
                    std::vector<StageEvents> *prof) {
   StageMark mark{prof, s};
-  std::vector<CensusJob> cj;
+  // Census of both views + padded uint8 costs, one launch for all frames
+  std::vector<FusedCostJob> fj;
   for (int i = 0; i < n; ++i) {
     const sgm_params &p = fr[i].p;
-    for (int side = 0; side < 2; ++side) {
-      CensusJob j{};
-      j.img = side ? fr[i].right : fr[i].left;
-      j.pitch = fr[i].pitch;
-      j.out = reinterpret_cast<uint64_t *>(mem + (side ? plans[i].off_cr : plans[i].off_cl));
-      j.W = p.width;
-      j.H = p.height;
-      j.cw = p.census_w;
-      j.ch = p.census_h;
-      cj.push_back(j);
-    }
-  }
-  CHECK(mark.begin(SGM_STAGE_CENSUS));
-  launch_census(cj, s);
-  CHECK(check_launch());
-  // Hamming costs into the padded uint8 volume (costs <= N_b <= 64)
-  std::vector<CostJob> kj;
-  for (int i = 0; i < n; ++i) {
-    const sgm_params &p = fr[i].p;
-    CostJob j{};
-    j.cl = reinterpret_cast<const uint64_t *>(mem + plans[i].off_cl);
-    j.cr = reinterpret_cast<const uint64_t *>(mem + plans[i].off_cr);
+    FusedCostJob j{};
+    j.left = fr[i].left;
+    j.right = fr[i].right;
+    j.pitch = fr[i].pitch;
     j.out8 = reinterpret_cast<uint8_t *>(mem + plans[i].off_cost);
+    j.umap = fr[i].umap;
     j.W = p.width;
     j.H = p.height;
     j.D = p.max_disp;
     j.Dp = dp_of(p);
     j.nbits = nbits_of(p);
-    kj.push_back(j);
+    j.cw = p.census_w;
+    j.ch = p.census_h;
+    fj.push_back(j);
   }
-  launch_cost(kj, s);
+  CHECK(mark.begin(SGM_STAGE_CENSUS));
+  launch_census_cost(fj, s);
   CHECK(check_launch());
-  CHECK(mark.end(2));
+  CHECK(mark.end(1));
   // aggregation, one launch per (disparities per lane, path-cost width)
   CHECK(mark.begin(SGM_STAGE_AGGREGATE));
   int groups = 0;
@@ -448,6 +450,50 @@ void destroy_events(Batch &b) {
   b.done = nullptr;
 }
 
+// Capture the batch's launches on `s` into a graph, then replay it through
+// the cached executable graph of the same composition (updated with this
+// batch's buffers), instantiating one on a miss.
+int enqueue_graph(sgm_ctx *c, const sgm_frame *fr, int n, const std::vector<FramePlan> &plans,
+                  const std::vector<int> &hlps, char *mem, hipStream_t s) {
+  HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed));
+  int rc = enqueue_frames(fr, n, plans, hlps, mem, s, nullptr);
+  hipGraph_t g = nullptr;
+  hipError_t e = hipStreamEndCapture(s, &g);
+  if (rc != SGM_OK) {
+    if (g) (void)hipGraphDestroy(g);
+    return rc;
+  }
+  if (e != hipSuccess) return fail(SGM_EHIP, "graph capture: %s", hipGetErrorString(e));
+  const std::string key = composition_key(fr, n, hlps);
+  auto it = c->graph_cache.find(key);
+  hipGraphExec_t ex = nullptr;
+  if (it != c->graph_cache.end()) {
+    hipGraphExecUpdateResult res;
+    hipGraphNode_t bad = nullptr;
+    if (hipGraphExecUpdate(it->second, g, &bad, &res) == hipSuccess && res == hipGraphExecUpdateSuccess) {
+      ex = it->second;
+      ++c->graph_hits;
+    } else {
+      (void)hipGetLastError();
+      (void)hipGraphExecDestroy(it->second);
+      c->graph_cache.erase(it);
+    }
+  }
+  if (!ex) {
+    e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+      (void)hipGraphDestroy(g);
+      return fail(SGM_EHIP, "graph instantiate: %s", hipGetErrorString(e));
+    }
+    c->graph_cache[key] = ex;
+    ++c->graph_misses;
+  }
+  e = hipGraphLaunch(ex, s);
+  (void)hipGraphDestroy(g);
+  if (e != hipSuccess) return fail(SGM_EHIP, "graph launch: %s", hipGetErrorString(e));
+  return SGM_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -493,6 +539,7 @@ int sgm_destroy(sgm_ctx *c) {
       (void)hipFree(kv.second.mem.ptr);
     }
     for (auto &b : c->idle) (void)hipFree(b.ptr);
+    for (auto &kv : c->graph_cache) (void)hipGraphExecDestroy(kv.second);
     if (c->stage.ptr) (void)hipFree(c->stage.ptr);
     for (auto &s : c->streams) (void)hipStreamDestroy(s);
   }
@@ -632,6 +679,8 @@ int uv_maps(sgm_ctx *c, const sgm_params *p, const uint16_t *disp, uint16_t *uma
   CHECK(check_dev_ptr(disp, c->device, "disp"));
   CHECK(check_dev_ptr(umap, c->device, "umap"));
   CHECK(check_dev_ptr(vmap, c->device, "vmap"));
+  if (reinterpret_cast<uintptr_t>(umap) & 3) return fail(SGM_EINVAL, "umap must be 4-byte aligned");
+  launch_zero({ZeroJob{umap, (int64_t)p->max_disp * p->width, 0}}, (hipStream_t)stream);
   UVJob j{};
   j.disp = disp;
   j.U = umap;
@@ -666,19 +715,22 @@ int sgm_submit(sgm_ctx *c, const sgm_frame *frames, int n, uint64_t *ticket) {
     if (frames[i].umap) {
       CHECK(check_dev_ptr(frames[i].umap, c->device, "umap"));
       CHECK(check_dev_ptr(frames[i].vmap, c->device, "vmap"));
+      if (reinterpret_cast<uintptr_t>(frames[i].umap) & 3)
+        return fail(SGM_EINVAL, "frame %d: umap must be 4-byte aligned", i);
     }
   }
   total = align256(total);
   if (total + c->stage.bytes > c->budget)
     return fail(SGM_ENOMEM, "batch needs %zu bytes of scratch, budget is %zu", total, c->budget);
-  // reuse an idle block that is big enough (and not more than twice the need)
+  // reuse the smallest idle block that is big enough
   Block blk;
-  for (size_t i = 0; i < c->idle.size(); ++i) {
-    if (c->idle[i].bytes >= total && c->idle[i].bytes <= 2 * total) {
-      blk = c->idle[i];
-      c->idle.erase(c->idle.begin() + i);
-      break;
-    }
+  size_t bi = c->idle.size();
+  for (size_t i = 0; i < c->idle.size(); ++i)
+    if (c->idle[i].bytes >= total && (bi == c->idle.size() || c->idle[i].bytes < c->idle[bi].bytes))
+      bi = i;
+  if (bi < c->idle.size()) {  // already counted in held(): no admission change
+    blk = c->idle[bi];
+    c->idle.erase(c->idle.begin() + bi);
   }
   if (!blk.ptr) {
     CHECK(make_room(c, total));
@@ -695,8 +747,13 @@ int sgm_submit(sgm_ctx *c, const sgm_frame *frames, int n, uint64_t *ticket) {
   hipStream_t s = c->streams[b.stream];
   std::vector<int> hl(n);
   for (int i = 0; i < n; ++i) hl[i] = resolve_hlps(c, frames[i].p);
-  int rc = enqueue_frames(frames, n, plans, hl, reinterpret_cast<char *>(blk.ptr), s,
-                          c->profiling ? &b.prof : nullptr);
+  int rc = SGM_OK;
+  if (c->graphs && !c->profiling) {
+    rc = enqueue_graph(c, frames, n, plans, hl, reinterpret_cast<char *>(blk.ptr), s);
+  } else {
+    rc = enqueue_frames(frames, n, plans, hl, reinterpret_cast<char *>(blk.ptr), s,
+                        c->profiling ? &b.prof : nullptr);
+  }
   if (rc == SGM_OK && hipEventCreateWithFlags(&b.done, hipEventDisableTiming) != hipSuccess)
     rc = fail(SGM_EHIP, "hipEventCreate failed");
   if (rc == SGM_OK && hipEventRecord(b.done, s) != hipSuccess) rc = fail(SGM_EHIP, "hipEventRecord failed");
@@ -817,6 +874,21 @@ int sgm_autotune(sgm_ctx *c, const sgm_frame *sample, int reps, sgm_schedule *be
   CHECK(sgm_set_schedule(c, &sample->p, &win));
   if (best) *best = win;
   for (int i = 0; ms && i < n_ms && i < 3; ++i) ms[i] = times[i];
+  return SGM_OK;
+}
+
+int sgm_graph_stats(sgm_ctx *c, uint64_t *hits, uint64_t *misses) {
+  if (!c) return fail(SGM_EINVAL, "ctx is null");
+  std::lock_guard<std::mutex> lk(c->mu);
+  if (hits) *hits = c->graph_hits;
+  if (misses) *misses = c->graph_misses;
+  return SGM_OK;
+}
+
+int sgm_set_graphs(sgm_ctx *c, int on) {
+  if (!c) return fail(SGM_EINVAL, "ctx is null");
+  std::lock_guard<std::mutex> lk(c->mu);
+  c->graphs = on != 0;
   return SGM_OK;
 }
 

@@ -58,6 +58,134 @@ __global__ __launch_bounds__(256) void cost_kernel(JobTable<CostJob> t) {
   }
 }
 
+// ------------------------------------------------- fused Census + cost
+// One block per (row, 256-pixel segment).  The block stages the CH image rows
+// around y of both views in LDS (clamped halo; the right view also D - 1
+// pixels to the left, which the segment's costs reach), computes the Census
+// codes of its pixels (left) and of the pixels its disparities reach (right)
+// into LDS, then writes the segment's padded uint8 costs.  Saves the Census
+// round trip through HBM and two launches per batch; the right-view codes of
+// the D - 1 halo pixels are computed twice (by this and the previous
+// segment).  Blocks of segment 0 also clear the caller's U-map rows
+// d = y, y + H, ... (the U-map kernel accumulates into it at the end).
+
+constexpr int kSeg = 256;
+
+template <int CW, int CH>
+__device__ __forceinline__ uint64_t census_fixed(const uint8_t *rows, int stride, int x) {
+  constexpr int RX = CW / 2, RY = CH / 2;
+  const uint8_t c = rows[RY * stride + x + RX];
+  uint64_t code = 0;
+#pragma unroll
+  for (int dy = 0; dy < CH; ++dy)
+#pragma unroll
+    for (int dx = 0; dx < CW; ++dx) {
+      if (dy == RY && dx == RX) continue;
+      code = (code << 1) | (uint64_t)(rows[dy * stride + x + dx] < c);
+    }
+  return code;
+}
+
+__device__ __forceinline__ uint64_t census_any(const uint8_t *rows, int stride, int x, int cw, int ch) {
+  const int rx = cw / 2, ry = ch / 2;
+  const uint8_t c = rows[ry * stride + x + rx];
+  uint64_t code = 0;
+  for (int dy = 0; dy < ch; ++dy)
+    for (int dx = 0; dx < cw; ++dx) {
+      if (dy == ry && dx == rx) continue;
+      code = (code << 1) | (uint64_t)(rows[dy * stride + x + dx] < c);
+    }
+  return code;
+}
+
+__device__ __forceinline__ uint64_t census_at(const uint8_t *rows, int stride, int x, int cw, int ch) {
+  if (cw == 9 && ch == 7) return census_fixed<9, 7>(rows, stride, x);
+  if (cw == 5 && ch == 5) return census_fixed<5, 5>(rows, stride, x);
+  return census_any(rows, stride, x, cw, ch);
+}
+
+__global__ __launch_bounds__(256) void census_cost_kernel(JobTable<FusedCostJob> t) {
+  extern __shared__ uint64_t lds64[];
+  const int ji = find_job(t.j, t.n, (int)blockIdx.x);
+  const FusedCostJob &J = t.j[ji];
+  const int tb = (int)blockIdx.x - J.blk0;
+  const int segs = (J.W + kSeg - 1) / kSeg;
+  const int y = tb / segs;
+  const int x0 = (tb - y * segs) * kSeg;
+  const int W = J.W, H = J.H, D = J.D, Dp = J.Dp;
+  const int nx = min(kSeg, W - x0);
+  const int xr0 = max(0, x0 - D + 1);  // first right-view pixel the segment reaches
+  const int nr = x0 + nx - xr0;         // right-view codes needed
+  const int rx = J.cw / 2, ry = J.ch / 2;
+  const int sl = nx + 2 * rx, sr = nr + 2 * rx;  // staged row lengths
+  uint64_t *codeL = lds64;            // [nx]   codes of x0 ..
+  uint64_t *codeR = lds64 + kSeg;     // [nr]   codes of xr0 ..
+  uint8_t *rowsL = reinterpret_cast<uint8_t *>(lds64 + 2 * kSeg + 256);  // [ch][sl]
+  uint8_t *rowsR = rowsL + J.ch * (kSeg + 2 * rx);                       // [ch][sr]
+  for (int r = 0; r < J.ch; ++r) {
+    const int64_t gy = min(max(y - ry + r, 0), H - 1) * J.pitch;
+    for (int c = threadIdx.x; c < sr; c += blockDim.x) {
+      rowsR[r * sr + c] = J.right[gy + min(max(xr0 - rx + c, 0), W - 1)];
+      if (c < sl) rowsL[r * sl + c] = J.left[gy + min(max(x0 - rx + c, 0), W - 1)];
+    }
+  }
+  if (J.umap && x0 == 0)
+    for (int d = y; d < D; d += H)
+      for (int x = threadIdx.x; x < W; x += blockDim.x) J.umap[(int64_t)d * W + x] = 0;
+  __syncthreads();
+  for (int i = threadIdx.x; i < nr; i += blockDim.x) {
+    codeR[i] = census_at(rowsR, sr, i, J.cw, J.ch);
+    if (i < nx) codeL[i] = census_at(rowsL, sl, i, J.cw, J.ch);
+  }
+  __syncthreads();
+  // each thread keeps one 4-disparity group q of the padded row and walks
+  // the segment's pixels: no division in the loop
+  const int qpp = Dp >> 2;               // dwords per pixel (16..64)
+  const int groups = blockDim.x / qpp;   // pixels per sweep
+  const int q = threadIdx.x % qpp, g = threadIdx.x / qpp;
+  if (g >= groups) return;
+  const int d0 = q * 4;
+  uint32_t *out = reinterpret_cast<uint32_t *>(J.out8 + ((int64_t)y * W + x0) * Dp) + q;
+  // pixels x >= d0 + 3 with all four disparities below D need no checks
+  const bool full = d0 + 3 < D;
+  const int xs = max(0, d0 + 3 - x0);  // first segment pixel with x >= d0 + 3
+  for (int xi = g; xi < nx; xi += groups) {
+    const int x = x0 + xi;
+    const uint64_t cl = codeL[xi];
+    uint32_t word = 0;
+    if (full && xi >= xs) {
+      const uint64_t *cr = codeR + (x - d0 - xr0);  // cr[-b] is the code at x - d0 - b
+#pragma unroll
+      for (int b = 0; b < 4; ++b) word |= (uint32_t)__popcll(cl ^ cr[-b]) << (8 * b);
+    } else {
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        const int d = d0 + b;
+        const int v = (d < D && x >= d) ? __popcll(cl ^ codeR[max(x - d - xr0, 0)]) : J.nbits;
+        word |= (uint32_t)v << (8 * b);
+      }
+    }
+    out[(int64_t)xi * qpp] = word;
+  }
+}
+
+size_t fused_cost_lds(int D, int cw, int ch) {
+  (void)D;
+  // codes: kSeg left + (kSeg + 255) right; rows: ch x (kSeg + cw - 1) left and
+  // ch x (kSeg + 255 + cw - 1) right
+  return (size_t)(2 * kSeg + 256) * 8 + (size_t)ch * (kSeg + cw - 1) + (size_t)ch * (kSeg + 255 + cw - 1);
+}
+
+void launch_census_cost(std::vector<FusedCostJob> jobs, hipStream_t s) {
+  size_t lds = 0;
+  for (auto &j : jobs) lds = std::max(lds, fused_cost_lds(j.D, j.cw, j.ch));
+  for_each_table(
+      jobs, [](const FusedCostJob &j) { return (long)j.H * ((j.W + kSeg - 1) / kSeg); },
+      [&](const JobTable<FusedCostJob> &t, int blocks) {
+        hipLaunchKernelGGL(census_cost_kernel, dim3(blocks), dim3(256), lds, s, t);
+      });
+}
+
 void launch_cost(std::vector<CostJob> jobs, hipStream_t s) {
   for (auto &j : jobs) j.chunks_x = (j.W + kCostChunk - 1) / kCostChunk;
   for_each_table(

@@ -32,15 +32,22 @@ __device__ __forceinline__ void load_sums(const DispJob &J, int64_t pix, int dba
   } else if (IN == 1) {
     const int64_t slot = (int64_t)J.H * J.W * J.Dp;
     const uint8_t *b = reinterpret_cast<const uint8_t *>(J.lr) + pix * J.Dp + dbase;
+    // issue the loads of all P (<= 8) slots before summing, so their
+    // latencies overlap
+    U32N<K / 4> v[8];
+#pragma unroll
+    for (int p = 0; p < 8; ++p)
+      if (p < J.P) v[p] = *reinterpret_cast<const U32N<K / 4> *>(b + p * slot);
     uint32_t ev[K / 4], od[K / 4];
 #pragma unroll
     for (int q = 0; q < K / 4; ++q) ev[q] = od[q] = 0;
-    for (int p = 0; p < J.P; ++p) {
-      const U32N<K / 4> v = *reinterpret_cast<const U32N<K / 4> *>(b + p * slot);
+#pragma unroll
+    for (int p = 0; p < 8; ++p) {
+      if (p >= J.P) break;
 #pragma unroll
       for (int q = 0; q < K / 4; ++q) {
-        ev[q] += v.v[q] & 0x00FF00FFu;         // d = 4q, 4q+2 in the low/high half
-        od[q] += (v.v[q] >> 8) & 0x00FF00FFu;  // d = 4q+1, 4q+3
+        ev[q] += v[p].v[q] & 0x00FF00FFu;         // d = 4q, 4q+2 in the low/high half
+        od[q] += (v[p].v[q] >> 8) & 0x00FF00FFu;  // d = 4q+1, 4q+3
       }
     }
 #pragma unroll
@@ -53,13 +60,18 @@ __device__ __forceinline__ void load_sums(const DispJob &J, int64_t pix, int dba
   } else {
     const int64_t slot = (int64_t)J.H * J.W * J.Dp;
     const uint16_t *b = reinterpret_cast<const uint16_t *>(J.lr) + pix * J.Dp + dbase;
+    U32N<K / 2> v[8];
+#pragma unroll
+    for (int p = 0; p < 8; ++p)
+      if (p < J.P) v[p] = *reinterpret_cast<const U32N<K / 2> *>(b + p * slot);
     uint32_t acc[K / 2];
 #pragma unroll
     for (int q = 0; q < K / 2; ++q) acc[q] = 0;
-    for (int p = 0; p < J.P; ++p) {
-      const U32N<K / 2> v = *reinterpret_cast<const U32N<K / 2> *>(b + p * slot);
 #pragma unroll
-      for (int q = 0; q < K / 2; ++q) acc[q] += v.v[q];  // two 16-bit sums per word
+    for (int p = 0; p < 8; ++p) {
+      if (p >= J.P) break;
+#pragma unroll
+      for (int q = 0; q < K / 2; ++q) acc[q] += v[p].v[q];  // two 16-bit sums per word
     }
 #pragma unroll
     for (int q = 0; q < K / 2; ++q) {
@@ -84,22 +96,32 @@ __global__ __launch_bounds__(kDispThreads) void disp_kernel(JobTable<DispJob> t)
   const int j = threadIdx.x & 15;
   const int dbase = j * K;
   const int dvalid = min(K, max(0, D - dbase));
-  for (int x = (int)(threadIdx.x >> 4); x < W; x += kDispThreads / 16) {
-    const int64_t pix = (int64_t)y * W + x;
-    uint32_t S[K];
-    load_sums<K, IN>(J, pix, dbase, dvalid, S);
-    uint32_t best = 0xFFFFFFFFu;
+  // two pixels per 16-lane row per sweep (their loads overlap)
+  constexpr int kRows = kDispThreads / 16;
+  for (int x0 = (int)(threadIdx.x >> 4); x0 < W; x0 += 2 * kRows) {
+    uint32_t S[2][K];
 #pragma unroll
-    for (int k = 0; k < K; ++k) {
-      if (k < dvalid) {
-        const int d = dbase + k;
-        const uint32_t key = (S[k] << 8) | (uint32_t)d;
-        best = min(best, key);
-        if (J.lr_check && x >= d) atomicMin(&keyR[x - d], key);
-      }
+    for (int h = 0; h < 2; ++h) {
+      const int x = min(x0 + h * kRows, W - 1);  // clamped: a duplicate pixel is harmless
+      load_sums<K, IN>(J, (int64_t)y * W + x, dbase, dvalid, S[h]);
     }
-    best = row16_allmin_u32(best);
-    if (j == 0) dl[x] = (uint16_t)(best & 0xFF);
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int x = x0 + h * kRows;
+      if (x >= W) break;  // uniform over the 16-lane row
+      uint32_t best = 0xFFFFFFFFu;
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        if (k < dvalid) {
+          const int d = dbase + k;
+          const uint32_t key = (S[h][k] << 8) | (uint32_t)d;
+          best = min(best, key);
+          if (J.lr_check && x >= d) atomicMin(&keyR[x - d], key);
+        }
+      }
+      best = row16_allmin_u32(best);
+      if (j == 0) dl[x] = (uint16_t)(best & 0xFF);
+    }
   }
   __syncthreads();
   uint16_t *out = J.out + (int64_t)y * W;

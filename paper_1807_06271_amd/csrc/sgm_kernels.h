@@ -39,6 +39,21 @@ struct CostJob {
 };
 void launch_cost(std::vector<CostJob> jobs, hipStream_t s);
 
+// Census of both views and the padded uint8 costs of one row segment per
+// block (LDS holds the segment's codes and the image rows of the window),
+// and clears the U-map (if given) for the accumulation at the end of the batch.
+struct FusedCostJob {
+  const uint8_t *left, *right;
+  int64_t pitch;
+  uint8_t *out8;    // [H][W][Dp]
+  uint16_t *umap;   // [D][W] or null
+  int W, H, D, Dp, nbits, cw, ch;
+  int blk0;
+};
+// LDS bytes of the fused kernel (at most ~75 KiB for a 65-row window).
+size_t fused_cost_lds(int D, int cw, int ch);
+void launch_census_cost(std::vector<FusedCostJob> jobs, hipStream_t s);
+
 // ----------------------------------------------------------- aggregation
 // Disparities per lane for D (16 lanes per scanline): 4, 8, 12 or 16.
 int agg_k(int D);
@@ -97,13 +112,22 @@ struct MedianJob {
 void launch_median(std::vector<MedianJob> jobs, hipStream_t s);
 
 // --------------------------------------------------------------- U/V maps
+// U must be zero before the launch (it is accumulated with atomics) and
+// 4-byte aligned.
 struct UVJob {
   const uint16_t *disp;
   uint16_t *U, *V;  // [D][W], [H][D]
   int W, H, D;
   int blk0;         // first block; blocks [blk0, blk0+H) build V rows,
-  int ublocks;      // then `ublocks` blocks of 64 columns build U
+  int ublocks;      // then `ublocks` blocks (64 columns x 64 rows) add into U
 };
 void launch_uv(std::vector<UVJob> jobs, hipStream_t s);
+
+struct ZeroJob {
+  uint16_t *p;
+  int64_t n;
+  int blk0;
+};
+void launch_zero(std::vector<ZeroJob> jobs, hipStream_t s);
 
 }  // namespace sgmk

@@ -1,7 +1,7 @@
 """Summaries of rocprofv3 CSV output for the profiles/ directory.
 
     python -m paper_1807_06271_amd.profiling stats  <kernel_stats.csv> <out.txt> "<command>" \
-        [<kernel_trace.csv> <kernel name part> <first N dispatches>]
+        [<kernel_trace.csv> <kernel name part> <N dispatches> [<skip>]]
     python -m paper_1807_06271_amd.profiling traffic <fetch_counter_collection.csv> \
         <write_counter_collection.csv> <out.json> "<fetch command>" "<write command>"
 
@@ -40,10 +40,10 @@ def short_name(name: str) -> str:
 
 
 def stats(csv_path: str, out_path: str, command: str, trace_csv: str | None = None,
-          kernel: str | None = None, first: int = 0) -> None:
-    """Kernel statistics; with trace_csv/kernel/first, also the average of the
-    first `first` dispatches of `kernel` (the benchmark's serial timed loop,
-    warm-up included, which precedes its overlapped-streams loop)."""
+          kernel: str | None = None, first: int = 0, skip: int = 0) -> None:
+    """Kernel statistics; with trace_csv/kernel/first, also the average of
+    dispatches skip .. skip+first-1 of `kernel` (the benchmark's serial loops,
+    after the autotuner's runs and before the overlapped-streams loop)."""
     rows = list(csv.DictReader(open(csv_path)))
     lines = ["# rocprofv3 kernel statistics", "# command: " + command, "#",
              "%-100s %6s %12s %12s %12s %7s" % ("kernel", "calls", "avg_us", "min_us", "max_us", "pct")]
@@ -53,9 +53,9 @@ def stats(csv_path: str, out_path: str, command: str, trace_csv: str | None = No
             float(r["MaxNs"]) / 1e3, float(r["Percentage"])))
     if trace_csv and kernel and first:
         d = [(int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3
-             for r in csv.DictReader(open(trace_csv)) if kernel in r["Kernel_Name"]][:first]
-        lines += ["#", "# first %d dispatches of %s (serial timed loop): avg %.1f us, min %.1f, max %.1f"
-                  % (len(d), kernel, sum(d) / len(d), min(d), max(d))]
+             for r in csv.DictReader(open(trace_csv)) if kernel in r["Kernel_Name"]][skip:skip + first]
+        lines += ["#", "# dispatches %d..%d of %s (serial loops): avg %.1f us, min %.1f, max %.1f"
+                  % (skip, skip + len(d) - 1, kernel, sum(d) / len(d), min(d), max(d))]
     open(out_path, "w").write("\n".join(lines) + "\n")
 
 
@@ -108,7 +108,8 @@ def traffic(fetch_csv: str, write_csv: str, out_path: str, fetch_cmd: str, write
 
 if __name__ == "__main__":
     if sys.argv[1] == "stats":
-        stats(sys.argv[2], sys.argv[3], sys.argv[4], *(sys.argv[5:7] + [int(sys.argv[7])] if len(sys.argv) > 7 else []))
+        extra = sys.argv[5:7] + [int(v) for v in sys.argv[7:9]] if len(sys.argv) > 7 else []
+        stats(sys.argv[2], sys.argv[3], sys.argv[4], *extra)
     elif sys.argv[1] == "traffic":
         traffic(sys.argv[2], sys.argv[3], sys.argv[4], sys.argv[5], sys.argv[6])
     else:

@@ -35,7 +35,7 @@ EXPORTS = ["sgm_validate", "sgm_create", "sgm_destroy", "sgm_last_error", "sgm_c
            "sgm_aggregate",
            "sgm_disparity", "uv_maps", "sgm_submit", "sgm_poll", "sgm_wait", "sgm_memory", "sgm_profile",
            "sgm_profile_read", "sgm_set_streams", "sgm_set_schedule", "sgm_get_schedule",
-           "sgm_autotune"]
+           "sgm_autotune", "sgm_set_graphs", "sgm_graph_stats"]
 STAGES = ["census", "aggregate", "disparity", "median", "uv"]
 
 
@@ -129,6 +129,8 @@ def lib():
         L.sgm_memory.argtypes = [vp, P(ctypes.c_size_t), P(ctypes.c_size_t)]
         L.sgm_profile.argtypes = [vp, i32]
         L.sgm_set_streams.argtypes = [vp, i32]
+        L.sgm_set_graphs.argtypes = [vp, i32]
+        L.sgm_graph_stats.argtypes = [vp, P(ctypes.c_uint64), P(ctypes.c_uint64)]
         L.sgm_set_schedule.argtypes = [vp, P(sgm_params), P(sgm_schedule)]
         L.sgm_get_schedule.argtypes = [vp, P(sgm_params), P(sgm_schedule)]
         L.sgm_autotune.argtypes = [vp, P(sgm_frame), i32, P(sgm_schedule), P(ctypes.c_float), i32]
@@ -337,6 +339,17 @@ def sgm_autotune(ctx: Context, sample: "Frame", reps: int = 5):
     f = sample.c()
     _check(lib().sgm_autotune(ctx.handle, ctypes.byref(f), reps, ctypes.byref(best), ms, 3), "sgm_autotune")
     return best.h_lanes, {h: ms[i] for i, h in enumerate((16, 32, 64)) if ms[i] >= 0}
+
+
+def sgm_set_graphs(ctx: Context, on: bool) -> None:
+    _check(lib().sgm_set_graphs(ctx.handle, int(bool(on))), "sgm_set_graphs")
+
+
+def sgm_graph_stats(ctx: Context):
+    """(hits, misses) of the batch graph cache."""
+    h, m = ctypes.c_uint64(), ctypes.c_uint64()
+    _check(lib().sgm_graph_stats(ctx.handle, ctypes.byref(h), ctypes.byref(m)), "sgm_graph_stats")
+    return h.value, m.value
 
 
 def sgm_set_streams(ctx: Context, n: int) -> None:

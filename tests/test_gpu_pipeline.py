@@ -87,6 +87,9 @@ def test_mixed_batch_matches_alone_and_oracle(env):
         ("small", 15, 64, 48, 16, dict(census_w=3, census_h=3, path_mask=0x0F, lr_check=0, median=0)),
         ("kitti", 16, 1, 1, 1, dict(census_w=3, census_h=3)),
         ("kitti", 17, 256, 9, 256, dict(census_w=9, census_h=7, invalid=65535)),
+        # wide and short: many row segments in the Census + cost kernel
+        ("kitti", 18, 3000, 12, 64, dict(census_w=9, census_h=7)),
+        ("kitti", 19, 40, 30, 16, dict(census_w=13, census_h=5, path_mask=0x81)),
     ]
     frames, inputs = [], []
     for recipe, seed, W, H, D, kw in specs:
@@ -142,7 +145,7 @@ def test_admission_busy_and_unknown_ticket(env):
     left, right, _ = synthetic.make_pair("small", 5, W, H, D)
     L, R = to_dev(torch, left), to_dev(torch, right)
     # a budget that holds one such batch but not two
-    one = (2 * W * H * 8 + W * H * D * 8 + W * H * 2) + 4096
+    one = (W * H * 64 + W * H * 64 * 8 + W * H * 2) + 4096
     with sgm.Context(0, hbm_budget_bytes=int(one * 1.5)) as small:
         f1, f2 = sgm.Frame.alloc(p, L, R), sgm.Frame.alloc(p, L, R)
         t1 = sgm.sgm_submit(small, [f1])
