@@ -225,8 +225,8 @@ __device__ __forceinline__ void agg_wave(const AggJob &J, int slot, int wave_in_
     for (int q = 1; q < NP; ++q) Nb[q] = as_pair(__builtin_amdgcn_alignbit(as_u32(Lp[q]), as_u32(Lp[q - 1]), 16));
     Nb[NP] = as_pair(__builtin_amdgcn_alignbit(next, as_u32(Lp[NP - 1]), 16));
     const u16x2 M = {(unsigned short)mp, (unsigned short)mp};
-    const u16x2 MP2 = padd_sat(M, P2);
     u16x2 Lc[NP];
+    const u16x2 MP2 = padd_sat(M, P2);
 #pragma unroll
     for (int q = 0; q < NP; ++q) {
       u16x2 best = padd_sat(pmin(Nb[q], Nb[q + 1]), P1);

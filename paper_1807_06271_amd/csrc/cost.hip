@@ -70,6 +70,10 @@ __global__ __launch_bounds__(256) void cost_kernel(JobTable<CostJob> t) {
 // d = y, y + H, ... (the U-map kernel accumulates into it at the end).
 
 constexpr int kSeg = 256;
+// LDS slots for the swizzled right-view codes: swz(kSeg + 255 - 1) + 1
+constexpr int kCodeRSlots = (kSeg + 255) + (kSeg + 255) / 4 + 1;
+
+__device__ __forceinline__ int swz(int i) { return i + (i >> 2); }
 
 template <int CW, int CH>
 __device__ __forceinline__ uint64_t census_fixed(const uint8_t *rows, int stride, int x) {
@@ -118,15 +122,37 @@ __global__ __launch_bounds__(256) void census_cost_kernel(JobTable<FusedCostJob>
   const int nr = x0 + nx - xr0;         // right-view codes needed
   const int rx = J.cw / 2, ry = J.ch / 2;
   const int sl = nx + 2 * rx, sr = nr + 2 * rx;  // staged row lengths
+  // right-view codes are stored at swz(i) = i + i/4: the cost loop's lanes
+  // read codes 4 apart, and the padding spreads them over all LDS banks
   uint64_t *codeL = lds64;            // [nx]   codes of x0 ..
-  uint64_t *codeR = lds64 + kSeg;     // [nr]   codes of xr0 ..
-  uint8_t *rowsL = reinterpret_cast<uint8_t *>(lds64 + 2 * kSeg + 256);  // [ch][sl]
+  uint64_t *codeR = lds64 + kSeg;     // [swz(nr)] codes of xr0 ..
+  uint8_t *rowsL = reinterpret_cast<uint8_t *>(lds64 + kSeg + kCodeRSlots);  // [ch][sl]
   uint8_t *rowsR = rowsL + J.ch * (kSeg + 2 * rx);                       // [ch][sr]
-  for (int r = 0; r < J.ch; ++r) {
-    const int64_t gy = min(max(y - ry + r, 0), H - 1) * J.pitch;
-    for (int c = threadIdx.x; c < sr; c += blockDim.x) {
-      rowsR[r * sr + c] = J.right[gy + min(max(xr0 - rx + c, 0), W - 1)];
-      if (c < sl) rowsL[r * sl + c] = J.left[gy + min(max(x0 - rx + c, 0), W - 1)];
+  {
+    // all staged bytes of both views, enumerated as one flat index space;
+    // each thread issues its loads in groups of 8 before storing to LDS so
+    // their latencies overlap
+    const int nR = J.ch * sr, nAll = nR + J.ch * sl;
+    for (int base = threadIdx.x; base < nAll; base += 8 * blockDim.x) {
+      uint8_t v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int i = base + u * blockDim.x;
+        if (i < nAll) {
+          const bool isR = i < nR;
+          const int k = isR ? i : i - nR;
+          const int len = isR ? sr : sl;
+          const int r = k / len, c = k - r * len;
+          const int64_t gy = (int64_t)min(max(y - ry + r, 0), H - 1) * J.pitch;
+          const int gx = min(max((isR ? xr0 : x0) - rx + c, 0), W - 1);
+          v[u] = (isR ? J.right : J.left)[gy + gx];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int i = base + u * blockDim.x;
+        if (i < nAll) (i < nR ? rowsR[i] : rowsL[i - nR]) = v[u];
+      }
     }
   }
   if (J.umap && x0 == 0)
@@ -134,7 +160,7 @@ __global__ __launch_bounds__(256) void census_cost_kernel(JobTable<FusedCostJob>
       for (int x = threadIdx.x; x < W; x += blockDim.x) J.umap[(int64_t)d * W + x] = 0;
   __syncthreads();
   for (int i = threadIdx.x; i < nr; i += blockDim.x) {
-    codeR[i] = census_at(rowsR, sr, i, J.cw, J.ch);
+    codeR[swz(i)] = census_at(rowsR, sr, i, J.cw, J.ch);
     if (i < nx) codeL[i] = census_at(rowsL, sl, i, J.cw, J.ch);
   }
   __syncthreads();
@@ -154,14 +180,14 @@ __global__ __launch_bounds__(256) void census_cost_kernel(JobTable<FusedCostJob>
     const uint64_t cl = codeL[xi];
     uint32_t word = 0;
     if (full && xi >= xs) {
-      const uint64_t *cr = codeR + (x - d0 - xr0);  // cr[-b] is the code at x - d0 - b
+      const int i0 = x - d0 - xr0;  // index of the code at x - d0
 #pragma unroll
-      for (int b = 0; b < 4; ++b) word |= (uint32_t)__popcll(cl ^ cr[-b]) << (8 * b);
+      for (int b = 0; b < 4; ++b) word |= (uint32_t)__popcll(cl ^ codeR[swz(i0 - b)]) << (8 * b);
     } else {
 #pragma unroll
       for (int b = 0; b < 4; ++b) {
         const int d = d0 + b;
-        const int v = (d < D && x >= d) ? __popcll(cl ^ codeR[max(x - d - xr0, 0)]) : J.nbits;
+        const int v = (d < D && x >= d) ? __popcll(cl ^ codeR[swz(max(x - d - xr0, 0))]) : J.nbits;
         word |= (uint32_t)v << (8 * b);
       }
     }
@@ -171,9 +197,10 @@ __global__ __launch_bounds__(256) void census_cost_kernel(JobTable<FusedCostJob>
 
 size_t fused_cost_lds(int D, int cw, int ch) {
   (void)D;
-  // codes: kSeg left + (kSeg + 255) right; rows: ch x (kSeg + cw - 1) left and
+  // codes: kSeg left + kCodeRSlots right; rows: ch x (kSeg + cw - 1) left and
   // ch x (kSeg + 255 + cw - 1) right
-  return (size_t)(2 * kSeg + 256) * 8 + (size_t)ch * (kSeg + cw - 1) + (size_t)ch * (kSeg + 255 + cw - 1);
+  return (size_t)(kSeg + kCodeRSlots) * 8 + (size_t)ch * (kSeg + cw - 1) +
+         (size_t)ch * (kSeg + 255 + cw - 1);
 }
 
 void launch_census_cost(std::vector<FusedCostJob> jobs, hipStream_t s) {

@@ -18,26 +18,48 @@
 
 namespace sgmk {
 
-constexpr int kDispThreads = 1024;
+__device__ __forceinline__ int kswz(int i) { return i + (i >> 3); }
 
-// Summed costs S of the lane's K disparities (d >= D lanes get garbage that
-// is never used).
+// Raw words of one pixel for one lane: IN 0 = K values of the caller's S
+// (one per word); IN 1 = K bytes of each of the P (<= 8) uint8 path-cost
+// slots; IN 2 = K 16-bit values of each uint16 slot.  Loading and summing are
+// separate so that a pixel's loads can be issued one sweep ahead.
 template <int K, int IN>
-__device__ __forceinline__ void load_sums(const DispJob &J, int64_t pix, int dbase, int dvalid,
-                                          uint32_t (&S)[K]) {
+struct RawSums {
+  static constexpr int NW = IN == 0 ? K : IN == 1 ? 8 * (K / 4) : 8 * (K / 2);
+  uint32_t w[NW];
+};
+
+template <int K, int IN>
+__device__ __forceinline__ void load_raw(const DispJob &J, int64_t pix, int dbase, int dvalid,
+                                         RawSums<K, IN> &r) {
   if (IN == 0) {
     const uint16_t *q = J.S + pix * J.D + dbase;
 #pragma unroll
-    for (int k = 0; k < K; ++k) S[k] = k < dvalid ? q[k] : 0u;
-  } else if (IN == 1) {
-    const int64_t slot = (int64_t)J.H * J.W * J.Dp;
-    const uint8_t *b = reinterpret_cast<const uint8_t *>(J.lr) + pix * J.Dp + dbase;
-    // issue the loads of all P (<= 8) slots before summing, so their
-    // latencies overlap
-    U32N<K / 4> v[8];
+    for (int k = 0; k < K; ++k) r.w[k] = k < dvalid ? q[k] : 0u;
+  } else {
+    constexpr int WPS = IN == 1 ? K / 4 : K / 2;  // words per slot
+    const int64_t slot = (int64_t)J.H * J.W * J.Dp * (IN == 1 ? 1 : 2);
+    const char *b = reinterpret_cast<const char *>(J.lr) + (pix * J.Dp + dbase) * (IN == 1 ? 1 : 2);
 #pragma unroll
     for (int p = 0; p < 8; ++p)
-      if (p < J.P) v[p] = *reinterpret_cast<const U32N<K / 4> *>(b + p * slot);
+      if (p < J.P) {
+        const U32N<WPS> v = *reinterpret_cast<const U32N<WPS> *>(b + p * slot);
+#pragma unroll
+        for (int i = 0; i < WPS; ++i) r.w[p * WPS + i] = v.v[i];
+      }
+  }
+}
+
+// Summed costs S of the lane's K disparities (d >= D lanes get garbage that
+// is never used).  Path-cost slots are summed as packed 16-bit fields (two
+// cells per 32-bit word, no carries: S <= 65535 by the parameter check).
+template <int K, int IN>
+__device__ __forceinline__ void sum_raw(const DispJob &J, const RawSums<K, IN> &r, uint32_t (&S)[K]) {
+  if (IN == 0) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) S[k] = r.w[k];
+  } else if (IN == 1) {
     uint32_t ev[K / 4], od[K / 4];
 #pragma unroll
     for (int q = 0; q < K / 4; ++q) ev[q] = od[q] = 0;
@@ -46,8 +68,9 @@ __device__ __forceinline__ void load_sums(const DispJob &J, int64_t pix, int dba
       if (p >= J.P) break;
 #pragma unroll
       for (int q = 0; q < K / 4; ++q) {
-        ev[q] += v[p].v[q] & 0x00FF00FFu;         // d = 4q, 4q+2 in the low/high half
-        od[q] += (v[p].v[q] >> 8) & 0x00FF00FFu;  // d = 4q+1, 4q+3
+        const uint32_t v = r.w[p * (K / 4) + q];
+        ev[q] += v & 0x00FF00FFu;         // d = 4q, 4q+2 in the low/high half
+        od[q] += (v >> 8) & 0x00FF00FFu;  // d = 4q+1, 4q+3
       }
     }
 #pragma unroll
@@ -58,12 +81,6 @@ __device__ __forceinline__ void load_sums(const DispJob &J, int64_t pix, int dba
       S[4 * q + 3] = od[q] >> 16;
     }
   } else {
-    const int64_t slot = (int64_t)J.H * J.W * J.Dp;
-    const uint16_t *b = reinterpret_cast<const uint16_t *>(J.lr) + pix * J.Dp + dbase;
-    U32N<K / 2> v[8];
-#pragma unroll
-    for (int p = 0; p < 8; ++p)
-      if (p < J.P) v[p] = *reinterpret_cast<const U32N<K / 2> *>(b + p * slot);
     uint32_t acc[K / 2];
 #pragma unroll
     for (int q = 0; q < K / 2; ++q) acc[q] = 0;
@@ -71,7 +88,7 @@ __device__ __forceinline__ void load_sums(const DispJob &J, int64_t pix, int dba
     for (int p = 0; p < 8; ++p) {
       if (p >= J.P) break;
 #pragma unroll
-      for (int q = 0; q < K / 2; ++q) acc[q] += v[p].v[q];  // two 16-bit sums per word
+      for (int q = 0; q < K / 2; ++q) acc[q] += r.w[p * (K / 2) + q];  // two 16-bit sums per word
     }
 #pragma unroll
     for (int q = 0; q < K / 2; ++q) {
@@ -81,47 +98,69 @@ __device__ __forceinline__ void load_sums(const DispJob &J, int64_t pix, int dba
   }
 }
 
+// Pixels per 16-lane row per sweep and threads per block, sized so that the
+// raw words of the current and the next sweep stay in registers.
 template <int K, int IN>
-__global__ __launch_bounds__(kDispThreads) void disp_kernel(JobTable<DispJob> t) {
+struct DispShape {
+  static constexpr int RAW = RawSums<K, IN>::NW;
+  static constexpr int NPX = RAW <= 16 ? 2 : 1;
+  static constexpr int THREADS = (K < 16 && 2 * NPX * RAW <= 64) ? 1024 : 512;
+};
+
+template <int K, int IN>
+__global__ __launch_bounds__((DispShape<K, IN>::THREADS)) void disp_kernel(JobTable<DispJob> t) {
+  constexpr int NPX = DispShape<K, IN>::NPX;
   extern __shared__ uint32_t smem[];
   const int ji = find_job(t.j, t.n, (int)blockIdx.x);
   const DispJob &J = t.j[ji];
   const int y = (int)blockIdx.x - J.blk0;
   const int W = J.W, D = J.D;
-  uint32_t *keyR = smem;                                  // [W]
-  uint16_t *dl = reinterpret_cast<uint16_t *>(smem + W);  // [W]
+  // D_R keys of x_r live at kswz(x_r) = x_r + x_r/8: a row's lanes update
+  // slots K apart, and the padding spreads them over the LDS banks
+  uint32_t *keyR = smem;                                               // [kswz(W)]
+  uint16_t *dl = reinterpret_cast<uint16_t *>(smem + W + W / 8 + 1);  // [W]
   if (J.lr_check)
-    for (int i = threadIdx.x; i < W; i += blockDim.x) keyR[i] = 0xFFFFFFFFu;
+    for (int i = threadIdx.x; i < W + W / 8 + 1; i += blockDim.x) keyR[i] = 0xFFFFFFFFu;
   __syncthreads();
   const int j = threadIdx.x & 15;
   const int dbase = j * K;
   const int dvalid = min(K, max(0, D - dbase));
-  // two pixels per 16-lane row per sweep (their loads overlap)
-  constexpr int kRows = kDispThreads / 16;
-  for (int x0 = (int)(threadIdx.x >> 4); x0 < W; x0 += 2 * kRows) {
-    uint32_t S[2][K];
+  // NPX pixels per 16-lane row per sweep, and the next sweep's loads are
+  // issued before this sweep's keys are reduced (software pipeline)
+  const int kRows = (int)blockDim.x / 16;
+  const int xfirst = (int)(threadIdx.x >> 4);
+  RawSums<K, IN> raw[NPX], rawn[NPX];
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      const int x = min(x0 + h * kRows, W - 1);  // clamped: a duplicate pixel is harmless
-      load_sums<K, IN>(J, (int64_t)y * W + x, dbase, dvalid, S[h]);
+  for (int h = 0; h < NPX; ++h)
+    load_raw<K, IN>(J, (int64_t)y * W + min(xfirst + h * kRows, W - 1), dbase, dvalid, raw[h]);
+  for (int x0 = xfirst; x0 < W; x0 += NPX * kRows) {
+    const int xn = x0 + NPX * kRows;
+    if (xn < W) {
+#pragma unroll
+      for (int h = 0; h < NPX; ++h)
+        load_raw<K, IN>(J, (int64_t)y * W + min(xn + h * kRows, W - 1), dbase, dvalid, rawn[h]);
     }
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
+    for (int h = 0; h < NPX; ++h) {
       const int x = x0 + h * kRows;
       if (x >= W) break;  // uniform over the 16-lane row
+      uint32_t S[K];
+      sum_raw<K, IN>(J, raw[h], S);
       uint32_t best = 0xFFFFFFFFu;
 #pragma unroll
       for (int k = 0; k < K; ++k) {
         if (k < dvalid) {
           const int d = dbase + k;
-          const uint32_t key = (S[h][k] << 8) | (uint32_t)d;
+          const uint32_t key = (S[k] << 8) | (uint32_t)d;
           best = min(best, key);
-          if (J.lr_check && x >= d) atomicMin(&keyR[x - d], key);
+          if (J.lr_check && x >= d) atomicMin(&keyR[kswz(x - d)], key);
         }
       }
       best = row16_allmin_u32(best);
       if (j == 0) dl[x] = (uint16_t)(best & 0xFF);
     }
+#pragma unroll
+    for (int h = 0; h < NPX; ++h) raw[h] = rawn[h];
   }
   __syncthreads();
   uint16_t *out = J.out + (int64_t)y * W;
@@ -132,7 +171,7 @@ __global__ __launch_bounds__(kDispThreads) void disp_kernel(JobTable<DispJob> t)
       v = J.invalid;
       const int xr = x - d;
       if (xr >= 0) {
-        const int dr = (int)(keyR[xr] & 0xFF);
+        const int dr = (int)(keyR[kswz(xr)] & 0xFF);
         if (abs(d - dr) <= J.max_diff) v = d;
       }
     }
@@ -143,11 +182,16 @@ __global__ __launch_bounds__(kDispThreads) void disp_kernel(JobTable<DispJob> t)
 template <int K>
 static void launch_disp_k(int in_kind, const JobTable<DispJob> &t, int blocks, size_t lds,
                           hipStream_t s) {
-  const dim3 b(kDispThreads);
   switch (in_kind) {
-    case 0: hipLaunchKernelGGL((disp_kernel<K, 0>), dim3(blocks), b, lds, s, t); break;
-    case 1: hipLaunchKernelGGL((disp_kernel<K, 1>), dim3(blocks), b, lds, s, t); break;
-    default: hipLaunchKernelGGL((disp_kernel<K, 2>), dim3(blocks), b, lds, s, t); break;
+    case 0:
+      hipLaunchKernelGGL((disp_kernel<K, 0>), dim3(blocks), dim3(DispShape<K, 0>::THREADS), lds, s, t);
+      break;
+    case 1:
+      hipLaunchKernelGGL((disp_kernel<K, 1>), dim3(blocks), dim3(DispShape<K, 1>::THREADS), lds, s, t);
+      break;
+    default:
+      hipLaunchKernelGGL((disp_kernel<K, 2>), dim3(blocks), dim3(DispShape<K, 2>::THREADS), lds, s, t);
+      break;
   }
 }
 
@@ -162,7 +206,7 @@ void launch_disparity(std::vector<DispJob> jobs, int in_kind, hipStream_t s) {
         maxw = std::max(maxw, j.W);
       }
     if (sub.empty()) continue;
-    const size_t lds = (size_t)maxw * 6;
+    const size_t lds = (size_t)(maxw + maxw / 8 + 1) * 4 + (size_t)maxw * 2;
     for_each_table(
         sub, [](const DispJob &j) { return (long)j.H; },
         [&](const JobTable<DispJob> &t, int blocks) {
