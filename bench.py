@@ -366,7 +366,9 @@ def main():
     if not args.no_cpu:
         log("cpu baseline")
         cpu = cpu_baseline(left, right, p, args.cpu_seconds)
-    traffic = measured_traffic("agg_kernel<8, 0, unsigned char")
+    # the aggregation kernel instance the schedule selects: K = 8 disparities
+    # per lane over 16 lanes (D = 128), K * 16 / h_lanes on the horizontal paths
+    traffic = measured_traffic("agg_kernel<8, %d, %d, 0, unsigned char" % (128 // h_lanes, h_lanes))
 
     line = {
         "metric": "SGM Mdisp-evals/s (W*H*D*paths), whole path census..U/V maps",
@@ -390,7 +392,8 @@ def main():
         "stage_avg_ms": {k: round(v, 5) for k, v in stage_avg_ms.items()},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                     "kernel": "agg_kernel (8 directions, uint8 costs, uint8 path costs)",
+                     "kernel": "agg_kernel<8, %d, %d, 0, unsigned char> (8 directions, uint8 costs, uint8 path costs)"
+                               % (128 // h_lanes, h_lanes),
                      "alg_bytes_per_launch": ALG_BYTES_PER_EVAL * evals,
                      "avg_launch_ms": round(agg_ms, 5), "launches": prof["aggregate"][1],
                      "batches_profiled": n_batches},
