@@ -71,11 +71,17 @@ enum {
 #define SGM_PATHS_HV4 (SGM_PATH_L2R | SGM_PATH_R2L | SGM_PATH_T2B | SGM_PATH_B2T)
 #define SGM_PATHS_ALL8 0xFFu
 
+/* Matching cost (section 3.1.2): Census transform + Hamming distance, or the
+ * sum of absolute differences over the census_w x census_h support region. */
+enum { SGM_COST_CENSUS = 0, SGM_COST_SAD = 1 };
+
 /* Parameters of one frame.  Validated by every call:
  *   1 <= width, height <= 16384;  1 <= max_disp (D) <= 256;
- *   census_w, census_h odd and >= 1 with 1 <= census_w*census_h - 1 <= 64;
+ *   census_w, census_h odd and >= 1; the largest cost Cmax is N_b =
+ *   census_w*census_h - 1 (Census, 1 <= N_b <= 64) or census_w*census_h*255
+ *   (SAD, <= 65535);
  *   path_mask a nonzero subset of SGM_PATH_*;  p1 <= p2;
- *   popcount(path_mask) * (N_b + p2) <= 65535 (no 16-bit overflow of S);
+ *   popcount(path_mask) * (Cmax + p2) <= 65535 (no 16-bit overflow of S);
  *   lr_check 0 or 1, lr_max_diff >= 0;  median 0 (off), 3 or 5;
  *   invalid >= D (255 is the usual value for D <= 255, 65535 above);
  *   width * height * Dp * 2 < 4 GiB, with Dp = D rounded up to 64, 128, 192
@@ -90,7 +96,7 @@ typedef struct {
   int32_t lr_max_diff;
   int32_t median;
   uint16_t invalid;
-  uint16_t reserved; /* must be 0 */
+  uint16_t cost;     /* SGM_COST_CENSUS (0) or SGM_COST_SAD (1) */
 } sgm_params;
 
 typedef struct sgm_ctx sgm_ctx;
@@ -121,6 +127,14 @@ const char *sgm_last_error(void);
 int sgm_census(sgm_ctx *ctx, const sgm_params *p, const uint8_t *img, int64_t pitch,
                uint64_t *census, void *stream);
 
+/* SAD matching cost volume, equation (1) with the SAD similarity (p->cost
+ * must be SGM_COST_SAD): cost(x,y,d) = sum over the census_w x census_h
+ * window of |I_L(x+dx,y+dy) - I_R(x-d+dx,y+dy)|, every coordinate clamped
+ * to the image, and census_w*census_h*255 where x < d.  left, right: device
+ * uint8 [H][pitch]; cost: device uint16 [H][W][D]. */
+int sgm_cost_sad(sgm_ctx *ctx, const sgm_params *p, const uint8_t *left, const uint8_t *right,
+                 int64_t pitch, uint16_t *cost, void *stream);
+
 /* Matching cost volume, equation (1) with the Census/Hamming similarity:
  * cost(x,y,d) = popcount(cl(x,y) XOR cr(x-d,y)) for x >= d, else N_b.
  * cl, cr: device uint64 [H][W]; cost: device uint16 [H][W][D]. */
@@ -131,8 +145,9 @@ int sgm_cost(sgm_ctx *ctx, const sgm_params *p, const uint64_t *cl, const uint64
  * path recurrence): for each path r in path_mask,
  *   L_r(p,d) = C(p,d) + min(L_r(p-r,d), L_r(p-r,d+-1) + P1, m + P2) - m,
  *   m = min_k L_r(p-r,k);  L_r(p,d) = C(p,d) at the first pixel of a path;
- * and aggr = S = sum_r L_r.  cost values must be <= N_b (as sgm_cost makes
- * them); larger values give unspecified (but memory-safe) results.
+ * and aggr = S = sum_r L_r.  cost values must be <= Cmax (as sgm_cost and
+ * sgm_cost_sad make them); larger values give unspecified (but memory-safe)
+ * results.
  * cost, aggr: device uint16 [H][W][D]; may not alias. */
 int sgm_aggregate(sgm_ctx *ctx, const sgm_params *p, const uint16_t *cost, uint16_t *aggr,
                   void *stream);

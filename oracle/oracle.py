@@ -61,6 +61,7 @@ def _declare(L):
     i = ctypes.c_int
     L.oracle_census.argtypes = [u8p, i, i, ctypes.c_int64, i, i, u64p]
     L.oracle_cost.argtypes = [u64p, u64p, i, i, i, i, u16p]
+    L.oracle_sad_cost.argtypes = [u8p, u8p, i, i, ctypes.c_int64, i, i, i, u16p]
     L.oracle_aggregate.argtypes = [u16p, i, i, i, ctypes.c_uint32, i, i, u16p]
     L.oracle_wta.argtypes = [u16p, i, i, i, u16p]
     L.oracle_wta.restype = None
@@ -113,6 +114,16 @@ def cost(cl: np.ndarray, cr: np.ndarray, d_max: int, nbits: int) -> np.ndarray:
     out = np.zeros((h, w, d_max), np.uint16)
     _check(lib().oracle_cost(_p(cl, ctypes.c_uint64), _p(cr, ctypes.c_uint64), w, h, d_max, nbits,
                              _p(out, ctypes.c_uint16)), "cost")
+    return out
+
+
+def sad_cost(left: np.ndarray, right: np.ndarray, ww: int, wh: int, d_max: int) -> np.ndarray:
+    left = np.ascontiguousarray(left, np.uint8)
+    right = np.ascontiguousarray(right, np.uint8)
+    h, w = left.shape
+    out = np.zeros((h, w, d_max), np.uint16)
+    _check(lib().oracle_sad_cost(_p(left, ctypes.c_uint8), _p(right, ctypes.c_uint8), w, h, w, ww, wh, d_max,
+                                 _p(out, ctypes.c_uint16)), "sad_cost")
     return out
 
 
@@ -175,17 +186,24 @@ def default_invalid(d_max: int) -> int:
 
 
 def sgm(left, right, d_max, census_w, census_h, mask, p1, p2, lr_check_on=True,
-        lr_max_diff=1, median_k=3, invalid=None):
+        lr_max_diff=1, median_k=3, invalid=None, cost_kind=0):
     """The whole path: census -> cost -> aggregate -> WTA -> (right disparity,
-    LR check) -> median -> U/V maps.  Returns a dict of every stage output."""
+    LR check) -> median -> U/V maps, or with cost_kind = 1 the SAD cost over
+    the census_w x census_h window instead of census + Hamming.  Returns a
+    dict of every stage output."""
     invalid = default_invalid(d_max) if invalid is None else invalid
-    nbits = census_w * census_h - 1
-    cl = census(left, census_w, census_h)
-    cr = census(right, census_w, census_h)
-    c = cost(cl, cr, d_max, nbits)
+    if cost_kind == 1:
+        c = sad_cost(left, right, census_w, census_h, d_max)
+        out = {"cost": c}
+    else:
+        nbits = census_w * census_h - 1
+        cl = census(left, census_w, census_h)
+        cr = census(right, census_w, census_h)
+        c = cost(cl, cr, d_max, nbits)
+        out = {"census_l": cl, "census_r": cr, "cost": c}
     s = aggregate(c, mask, p1, p2)
     dl = wta(s)
-    out = {"census_l": cl, "census_r": cr, "cost": c, "aggr": s, "disp_l": dl}
+    out.update(aggr=s, disp_l=dl)
     if lr_check_on:
         dr = right_disparity(s)
         dlr = lr_check(dl, dr, lr_max_diff, invalid)

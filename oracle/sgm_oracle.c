@@ -99,6 +99,38 @@ int oracle_cost(const uint64_t *cl, const uint64_t *cr, int w, int h, int d_max,
     return ORACLE_OK;
 }
 
+/* SAD matching cost (section 3.1.2, the sum of absolute differences over a
+ * ww x wh support region, section 4.1): for 0 <= d < d_max,
+ *   C(x,y,d) = sum over window offsets (dx,dy) of
+ *              |I_L(x+dx, y+dy) - I_R(x-d+dx, y+dy)|
+ * with every coordinate clamped to the image (each view on its own), and
+ * C = ww*wh*255 (maximally dissimilar) where x - d < 0.  cost is
+ * [h][w][d_max] uint16. */
+int oracle_sad_cost(const uint8_t *left, const uint8_t *right, int w, int h, int64_t pitch, int ww,
+                    int wh, int d_max, uint16_t *cost) {
+    if (w < 1 || h < 1 || d_max < 1 || ww < 1 || wh < 1 || !(ww & 1) || !(wh & 1) || ww * wh * 255 > 65535)
+        return ORACLE_EINVAL;
+    int rx = ww / 2, ry = wh / 2;
+    for (int y = 0; y < h; ++y)
+        for (int x = 0; x < w; ++x)
+            for (int d = 0; d < d_max; ++d) {
+                int c = 0;
+                if (x - d < 0) {
+                    c = ww * wh * 255;
+                } else {
+                    for (int dy = -ry; dy <= ry; ++dy)
+                        for (int dx = -rx; dx <= rx; ++dx) {
+                            int yy = clampi(y + dy, 0, h - 1);
+                            int a = left[(int64_t)yy * pitch + clampi(x + dx, 0, w - 1)];
+                            int b = right[(int64_t)yy * pitch + clampi(x - d + dx, 0, w - 1)];
+                            c += a > b ? a - b : b - a;
+                        }
+                }
+                cost[((int64_t)y * w + x) * d_max + d] = (uint16_t)c;
+            }
+    return ORACLE_OK;
+}
+
 /* Path directions r = (dx, dy), in the bit order of the path mask:
  * left-to-right, right-to-left, top-to-bottom, bottom-to-top, and the four
  * diagonals towards bottom-right, top-left, bottom-left, top-right. */

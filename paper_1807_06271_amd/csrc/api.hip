@@ -48,23 +48,27 @@ int validate(const sgm_params *p) {
   if (p->census_w < 1 || p->census_h < 1 || !(p->census_w & 1) || !(p->census_h & 1))
     return fail(SGM_EINVAL, "census window must have odd sides >= 1 (got %d x %d)", p->census_w,
                 p->census_h);
-  const int nb = p->census_w * p->census_h - 1;
-  if (nb < 1 || nb > 64)
-    return fail(SGM_EINVAL, "census_w*census_h-1 must be in [1, 64] (got %d)", nb);
+  if (p->cost != SGM_COST_CENSUS && p->cost != SGM_COST_SAD)
+    return fail(SGM_EINVAL, "cost must be SGM_COST_CENSUS or SGM_COST_SAD (got %u)", p->cost);
+  const long nb = (long)p->census_w * p->census_h - 1;
+  if (p->cost == SGM_COST_CENSUS && (nb < 1 || nb > 64))
+    return fail(SGM_EINVAL, "census_w*census_h-1 must be in [1, 64] (got %ld)", nb);
+  if (p->cost == SGM_COST_SAD && (nb + 1) * 255 > 65535)
+    return fail(SGM_EINVAL, "SAD window too large: census_w*census_h*255 must be <= 65535");
   if (p->path_mask == 0 || (p->path_mask & ~0xFFu))
     return fail(SGM_EINVAL, "path_mask must be a nonzero subset of the 8 directions (got 0x%x)",
                 p->path_mask);
   if (p->p1 > p->p2) return fail(SGM_EINVAL, "p1 must be <= p2 (got %u > %u)", p->p1, p->p2);
-  if ((long)popcount8(p->path_mask) * (nb + p->p2) > 65535)
-    return fail(SGM_EINVAL, "paths*(N_b+p2) = %ld exceeds 65535: S could overflow 16 bits",
-                (long)popcount8(p->path_mask) * (nb + p->p2));
+  const long cmax = p->cost == SGM_COST_SAD ? (nb + 1) * 255 : nb;
+  if ((long)popcount8(p->path_mask) * (cmax + p->p2) > 65535)
+    return fail(SGM_EINVAL, "paths*(Cmax+p2) = %ld exceeds 65535: S could overflow 16 bits",
+                (long)popcount8(p->path_mask) * (cmax + p->p2));
   if (p->lr_check != 0 && p->lr_check != 1) return fail(SGM_EINVAL, "lr_check must be 0 or 1");
   if (p->lr_max_diff < 0) return fail(SGM_EINVAL, "lr_max_diff must be >= 0");
   if (p->median != 0 && p->median != 3 && p->median != 5)
     return fail(SGM_EINVAL, "median must be 0, 3 or 5 (got %d)", p->median);
   if (p->invalid < p->max_disp)
     return fail(SGM_EINVAL, "invalid (%u) must be >= max_disp (%d)", p->invalid, p->max_disp);
-  if (p->reserved != 0) return fail(SGM_EINVAL, "reserved must be 0");
   // the kernels address one path-cost volume (padded disparity stride, up to
   // 2 bytes per cell) with 32-bit offsets
   const int64_t dp = 16 * (int64_t)agg_k(p->max_disp);
@@ -75,12 +79,15 @@ int validate(const sgm_params *p) {
 }
 
 int nbits_of(const sgm_params &p) { return p.census_w * p.census_h - 1; }
+bool is_sad(const sgm_params &p) { return p.cost == SGM_COST_SAD; }
+// Largest matching cost: N_b for Census/Hamming, window * 255 for SAD.
+int cmax_of(const sgm_params &p) { return is_sad(p) ? p.census_w * p.census_h * 255 : nbits_of(p); }
 // Disparities per lane of the aggregation / selection kernels, and the
 // padded disparity stride of the internal volumes.
 int k_of(const sgm_params &p) { return agg_k(p.max_disp); }
 int dp_of(const sgm_params &p) { return 16 * k_of(p); }
-// Path costs fit in 8 bits when C + P2 <= 255 (C <= N_b, L_r <= C + P2).
-int lr_bytes_of(const sgm_params &p) { return nbits_of(p) + p.p2 <= 255 ? 1 : 2; }
+// Path costs fit in 8 bits when Cmax + P2 <= 255 (L_r <= C + P2).
+int lr_bytes_of(const sgm_params &p) { return cmax_of(p) + p.p2 <= 255 ? 1 : 2; }
 
 int fill_dirs(uint32_t mask, int *dirs) {
   int n = 0;
@@ -243,7 +250,8 @@ FramePlan plan_frame(const sgm_params &p, size_t base) {
   const size_t dp = (size_t)dp_of(p);
   FramePlan f;
   f.off_cost = base;
-  f.off_lr = f.off_cost + align256(px * dp);
+  // Census costs: padded uint8 [H][W][Dp]; SAD costs: uint16 [H][W][D]
+  f.off_lr = f.off_cost + align256(is_sad(p) ? px * p.max_disp * 2 : px * dp);
   f.off_dlr = f.off_lr + align256(px * dp * (size_t)popcount8(p.path_mask) * lr_bytes_of(p));
   f.bytes = f.off_dlr + align256(px * 2) - base;
   return f;
@@ -322,10 +330,28 @@ int enqueue_frames(const sgm_frame *fr, int n, const std::vector<FramePlan> &pla
                    const std::vector<int> &hlps, char *mem, hipStream_t s,
                    std::vector<StageEvents> *prof) {
   StageMark mark{prof, s};
-  // Census of both views + padded uint8 costs, one launch for all frames
+  // Census of both views + padded uint8 costs (one launch for all Census
+  // frames); SAD costs (one launch for all SAD frames, U-maps cleared apart)
   std::vector<FusedCostJob> fj;
+  std::vector<SadJob> sj;
+  std::vector<ZeroJob> zj;
   for (int i = 0; i < n; ++i) {
     const sgm_params &p = fr[i].p;
+    if (is_sad(p)) {
+      SadJob j{};
+      j.left = fr[i].left;
+      j.right = fr[i].right;
+      j.pitch = fr[i].pitch;
+      j.out = reinterpret_cast<uint16_t *>(mem + plans[i].off_cost);
+      j.W = p.width;
+      j.H = p.height;
+      j.D = p.max_disp;
+      j.ww = p.census_w;
+      j.wh = p.census_h;
+      sj.push_back(j);
+      if (fr[i].umap) zj.push_back(ZeroJob{fr[i].umap, (int64_t)p.max_disp * p.width, 0});
+      continue;
+    }
     FusedCostJob j{};
     j.left = fr[i].left;
     j.right = fr[i].right;
@@ -342,21 +368,35 @@ int enqueue_frames(const sgm_frame *fr, int n, const std::vector<FramePlan> &pla
     fj.push_back(j);
   }
   CHECK(mark.begin(SGM_STAGE_CENSUS));
-  launch_census_cost(fj, s);
-  CHECK(check_launch());
-  CHECK(mark.end(1));
+  int launches = 0;
+  if (!fj.empty()) {
+    launch_census_cost(fj, s);
+    CHECK(check_launch());
+    ++launches;
+  }
+  if (!sj.empty()) {
+    launch_sad(sj, s);
+    launch_zero(zj, s);
+    CHECK(check_launch());
+    launches += 2;
+  }
+  CHECK(mark.end(launches));
   // aggregation, one launch per (disparities per lane, path-cost width)
   CHECK(mark.begin(SGM_STAGE_AGGREGATE));
   int groups = 0;
+  for (int sad = 0; sad <= 1; ++sad)
   for (int K : {4, 8, 12, 16})
     for (int lb = 1; lb <= 2; ++lb)
     for (int c_hlps : {16, 32, 64}) {
       std::vector<AggJob> aj;
       for (int i = 0; i < n; ++i) {
         const sgm_params &p = fr[i].p;
-        if (k_of(p) != K || lr_bytes_of(p) != lb || hlps[i] != c_hlps) continue;
+        if ((int)is_sad(p) != sad || k_of(p) != K || lr_bytes_of(p) != lb) continue;
+        if (!sad && hlps[i] != c_hlps) continue;
+        if (sad && c_hlps != 16) continue;  // SAD costs: 16-lane layout only
         AggJob j{};
-        j.cost8 = reinterpret_cast<const uint8_t *>(mem + plans[i].off_cost);
+        if (sad) j.cost16 = reinterpret_cast<const uint16_t *>(mem + plans[i].off_cost);
+        else j.cost8 = reinterpret_cast<const uint8_t *>(mem + plans[i].off_cost);
         j.lr = mem + plans[i].off_lr;
         j.W = p.width;
         j.H = p.height;
@@ -368,7 +408,7 @@ int enqueue_frames(const sgm_frame *fr, int n, const std::vector<FramePlan> &pla
         aj.push_back(j);
       }
       if (!aj.empty()) {
-        launch_aggregate(aj, false, K, c_hlps, lb, s);
+        launch_aggregate(aj, sad != 0, K, c_hlps, lb, s);
         CHECK(check_launch());
         ++groups;
       }
@@ -551,6 +591,7 @@ int sgm_census(sgm_ctx *c, const sgm_params *p, const uint8_t *img, int64_t pitc
                void *stream) {
   if (!c) return fail(SGM_EINVAL, "ctx is null");
   CHECK(validate(p));
+  if (is_sad(*p)) return fail(SGM_EINVAL, "sgm_census needs p->cost == SGM_COST_CENSUS");
   if (pitch < p->width) return fail(SGM_EINVAL, "pitch %lld < width %d", (long long)pitch, p->width);
   std::lock_guard<std::mutex> lk(c->mu);
   DeviceGuard g(c->device);
@@ -572,6 +613,7 @@ int sgm_cost(sgm_ctx *c, const sgm_params *p, const uint64_t *cl, const uint64_t
              void *stream) {
   if (!c) return fail(SGM_EINVAL, "ctx is null");
   CHECK(validate(p));
+  if (is_sad(*p)) return fail(SGM_EINVAL, "sgm_cost takes Census codes: use sgm_cost_sad for SAD");
   std::lock_guard<std::mutex> lk(c->mu);
   DeviceGuard g(c->device);
   CHECK(check_dev_ptr(cl, c->device, "cl"));
@@ -587,6 +629,31 @@ int sgm_cost(sgm_ctx *c, const sgm_params *p, const uint64_t *cl, const uint64_t
   j.Dp = dp_of(*p);
   j.nbits = nbits_of(*p);
   launch_cost({j}, (hipStream_t)stream);
+  return check_launch();
+}
+
+int sgm_cost_sad(sgm_ctx *c, const sgm_params *p, const uint8_t *left, const uint8_t *right,
+                 int64_t pitch, uint16_t *cost, void *stream) {
+  if (!c) return fail(SGM_EINVAL, "ctx is null");
+  CHECK(validate(p));
+  if (!is_sad(*p)) return fail(SGM_EINVAL, "sgm_cost_sad needs p->cost == SGM_COST_SAD");
+  if (pitch < p->width) return fail(SGM_EINVAL, "pitch %lld < width %d", (long long)pitch, p->width);
+  std::lock_guard<std::mutex> lk(c->mu);
+  DeviceGuard g(c->device);
+  CHECK(check_dev_ptr(left, c->device, "left"));
+  CHECK(check_dev_ptr(right, c->device, "right"));
+  CHECK(check_dev_ptr(cost, c->device, "cost"));
+  SadJob j{};
+  j.left = left;
+  j.right = right;
+  j.pitch = pitch;
+  j.out = cost;
+  j.W = p->width;
+  j.H = p->height;
+  j.D = p->max_disp;
+  j.ww = p->census_w;
+  j.wh = p->census_h;
+  launch_sad({j}, (hipStream_t)stream);
   return check_launch();
 }
 

@@ -213,6 +213,82 @@ void launch_census_cost(std::vector<FusedCostJob> jobs, hipStream_t s) {
       });
 }
 
+// ------------------------------------------------------------ SAD cost
+// One block per (row, 64-pixel chunk): the window rows of both views around
+// y are staged in LDS (clamped; the right view D - 1 pixels further left),
+// then each thread takes cells (x, d) of the chunk and sums |L - R| over the
+// window.  Output: the uint16 [H][W][D] volume.
+
+template <int WW, int WH>
+__device__ __forceinline__ uint32_t sad_fixed(const uint8_t *l, int sl, const uint8_t *r, int sr) {
+  uint32_t acc = 0;
+#pragma unroll
+  for (int dy = 0; dy < WH; ++dy)
+#pragma unroll
+    for (int dx = 0; dx < WW; ++dx) acc += (uint32_t)abs((int)l[dy * sl + dx] - (int)r[dy * sr + dx]);
+  return acc;
+}
+
+__device__ __forceinline__ uint32_t sad_any(const uint8_t *l, int sl, const uint8_t *r, int sr, int ww,
+                                            int wh) {
+  uint32_t acc = 0;
+  for (int dy = 0; dy < wh; ++dy)
+    for (int dx = 0; dx < ww; ++dx) acc += (uint32_t)abs((int)l[dy * sl + dx] - (int)r[dy * sr + dx]);
+  return acc;
+}
+
+__global__ __launch_bounds__(256) void sad_kernel(JobTable<SadJob> t) {
+  extern __shared__ uint8_t srows[];
+  const int ji = find_job(t.j, t.n, (int)blockIdx.x);
+  const SadJob &J = t.j[ji];
+  const int tb = (int)blockIdx.x - J.blk0;
+  const int y = tb / J.chunks_x;
+  const int x0 = (tb % J.chunks_x) * kCostChunk;
+  const int W = J.W, H = J.H, D = J.D;
+  const int nx = min(kCostChunk, W - x0);
+  const int rx = J.ww / 2, ry = J.wh / 2;
+  const int sl = nx + 2 * rx;          // left: pixels x0 - rx .. x0 + nx - 1 + rx
+  const int sr = nx + D - 1 + 2 * rx;  // right: pixels x0 - D + 1 - rx ..
+  uint8_t *L = srows, *R = srows + J.wh * (kCostChunk + 2 * rx);
+  for (int i = threadIdx.x; i < J.wh * sr; i += blockDim.x) {
+    const int r = i / sr, c = i - r * sr;
+    const int64_t gy = (int64_t)min(max(y - ry + r, 0), H - 1) * J.pitch;
+    R[r * sr + c] = J.right[gy + min(max(x0 - D + 1 - rx + c, 0), W - 1)];
+    if (c < sl) L[r * sl + c] = J.left[gy + min(max(x0 - rx + c, 0), W - 1)];
+  }
+  __syncthreads();
+  const uint32_t cmax = (uint32_t)J.ww * J.wh * 255u;
+  uint16_t *out = J.out + ((int64_t)y * W + x0) * D;
+  for (int c = threadIdx.x; c < nx * D; c += blockDim.x) {
+    const int xi = c / D, d = c - xi * D;
+    uint32_t v = cmax;
+    if (x0 + xi >= d) {
+      // right pixel x - d + dx sits at column xi - d + (D - 1) + (dx + rx) of R
+      const uint8_t *l = L + xi, *r = R + xi - d + D - 1;
+      if (J.ww == 5 && J.wh == 5) v = sad_fixed<5, 5>(l, sl, r, sr);
+      else v = sad_any(l, sl, r, sr, J.ww, J.wh);
+    }
+    out[c] = (uint16_t)v;
+  }
+}
+
+size_t sad_lds(int D, int ww, int wh) {
+  return (size_t)wh * (kCostChunk + ww - 1) + (size_t)wh * (kCostChunk + D - 1 + ww - 1);
+}
+
+void launch_sad(std::vector<SadJob> jobs, hipStream_t s) {
+  size_t lds = 0;
+  for (auto &j : jobs) {
+    j.chunks_x = (j.W + kCostChunk - 1) / kCostChunk;
+    lds = std::max(lds, sad_lds(j.D, j.ww, j.wh));
+  }
+  for_each_table(
+      jobs, [](const SadJob &j) { return (long)j.chunks_x * j.H; },
+      [&](const JobTable<SadJob> &t, int blocks) {
+        hipLaunchKernelGGL(sad_kernel, dim3(blocks), dim3(256), lds, s, t);
+      });
+}
+
 void launch_cost(std::vector<CostJob> jobs, hipStream_t s) {
   for (auto &j : jobs) j.chunks_x = (j.W + kCostChunk - 1) / kCostChunk;
   for_each_table(

@@ -54,6 +54,18 @@ struct FusedCostJob {
 size_t fused_cost_lds(int D, int cw, int ch);
 void launch_census_cost(std::vector<FusedCostJob> jobs, hipStream_t s);
 
+// SAD costs over a ww x wh window into the uint16 [H][W][D] volume.
+struct SadJob {
+  const uint8_t *left, *right;
+  int64_t pitch;
+  uint16_t *out;
+  int W, H, D, ww, wh;
+  int blk0, chunks_x;
+};
+// LDS bytes of the SAD kernel (window rows of both views for one chunk).
+size_t sad_lds(int D, int ww, int wh);
+void launch_sad(std::vector<SadJob> jobs, hipStream_t s);
+
 // ----------------------------------------------------------- aggregation
 // Disparities per lane for D (16 lanes per scanline): 4, 8, 12 or 16.
 int agg_k(int D);

@@ -30,8 +30,10 @@ PATH_TL2BR, PATH_BR2TL, PATH_TR2BL, PATH_BL2TR = 16, 32, 64, 128
 PATHS_PAPER4 = PATH_L2R | PATH_TL2BR | PATH_T2B | PATH_TR2BL
 PATHS_HV4 = PATH_L2R | PATH_R2L | PATH_T2B | PATH_B2T
 PATHS_ALL8 = 0xFF
+COST_CENSUS, COST_SAD = 0, 1
 
 EXPORTS = ["sgm_validate", "sgm_create", "sgm_destroy", "sgm_last_error", "sgm_census", "sgm_cost",
+           "sgm_cost_sad",
            "sgm_aggregate",
            "sgm_disparity", "uv_maps", "sgm_submit", "sgm_poll", "sgm_wait", "sgm_memory", "sgm_profile",
            "sgm_profile_read", "sgm_set_streams", "sgm_set_schedule", "sgm_get_schedule",
@@ -51,7 +53,7 @@ class sgm_params(ctypes.Structure):
                 ("path_mask", ctypes.c_uint32), ("p1", ctypes.c_uint16), ("p2", ctypes.c_uint16),
                 ("lr_check", ctypes.c_int32), ("lr_max_diff", ctypes.c_int32),
                 ("median", ctypes.c_int32), ("invalid", ctypes.c_uint16),
-                ("reserved", ctypes.c_uint16)]
+                ("cost", ctypes.c_uint16)]
 
 
 class sgm_schedule(ctypes.Structure):
@@ -79,10 +81,16 @@ class Params:
     lr_max_diff: int = 1
     median: int = 3
     invalid: int | None = None
+    cost: int = COST_CENSUS  # or COST_SAD (census_w x census_h support region)
 
     @property
     def nbits(self) -> int:
         return self.census_w * self.census_h - 1
+
+    @property
+    def cmax(self) -> int:
+        """Largest matching cost: N_b (Census) or window * 255 (SAD)."""
+        return self.census_w * self.census_h * 255 if self.cost == COST_SAD else self.nbits
 
     @property
     def paths(self) -> int:
@@ -94,7 +102,7 @@ class Params:
     def c(self) -> sgm_params:
         return sgm_params(self.width, self.height, self.max_disp, self.census_w, self.census_h,
                           self.path_mask, self.p1, self.p2, self.lr_check, self.lr_max_diff,
-                          self.median, self.inv(), 0)
+                          self.median, self.inv(), self.cost)
 
     def disp_evals(self) -> int:
         """W*H*D*paths: the unit of the throughput metric."""
@@ -120,6 +128,7 @@ def lib():
         L.sgm_last_error.restype = ctypes.c_char_p
         L.sgm_census.argtypes = [vp, P(sgm_params), vp, ctypes.c_int64, vp, vp]
         L.sgm_cost.argtypes = [vp, P(sgm_params), vp, vp, vp, vp]
+        L.sgm_cost_sad.argtypes = [vp, P(sgm_params), vp, vp, ctypes.c_int64, vp, vp]
         L.sgm_aggregate.argtypes = [vp, P(sgm_params), vp, vp, vp]
         L.sgm_disparity.argtypes = [vp, P(sgm_params), vp, vp, vp]
         L.uv_maps.argtypes = [vp, P(sgm_params), vp, vp, vp, vp]
@@ -223,6 +232,18 @@ def sgm_cost(ctx: Context, p: Params, cl, cr, cost, stream=None):
     _need(cost, (p.height, p.width, p.max_disp), torch.uint16, "cost")
     _check(lib().sgm_cost(ctx.handle, ctypes.byref(p.c()), _ptr(cl), _ptr(cr), _ptr(cost),
                           _stream(stream)), "sgm_cost")
+
+
+def sgm_cost_sad(ctx: Context, p: Params, left, right, cost, stream=None):
+    for t, n in ((left, "left"), (right, "right")):
+        if t.dtype != torch.uint8 or t.dim() != 2 or t.shape[0] != p.height or t.shape[1] < p.width \
+                or t.stride(1) != 1:
+            raise ValueError("%s must be uint8 [H][pitch >= W] with contiguous rows" % n)
+    if left.stride(0) != right.stride(0):
+        raise ValueError("left and right must share one pitch")
+    _need(cost, (p.height, p.width, p.max_disp), torch.uint16, "cost")
+    _check(lib().sgm_cost_sad(ctx.handle, ctypes.byref(p.c()), left.data_ptr(), right.data_ptr(), left.stride(0),
+                              _ptr(cost), _stream(stream)), "sgm_cost_sad")
 
 
 def sgm_aggregate(ctx: Context, p: Params, cost, aggr, stream=None):
@@ -380,9 +401,12 @@ def run_stages(ctx: Context, p: Params, left, right, stream=None, keep=False):
     disp = torch.empty((H, W), dtype=torch.uint16, device=dev)
     u = torch.empty((D, W), dtype=torch.uint16, device=dev)
     v = torch.empty((H, D), dtype=torch.uint16, device=dev)
-    sgm_census(ctx, p, left, cl, stream)
-    sgm_census(ctx, p, right, cr, stream)
-    sgm_cost(ctx, p, cl, cr, cost, stream)
+    if p.cost == COST_SAD:
+        sgm_cost_sad(ctx, p, left, right, cost, stream)
+    else:
+        sgm_census(ctx, p, left, cl, stream)
+        sgm_census(ctx, p, right, cr, stream)
+        sgm_cost(ctx, p, cl, cr, cost, stream)
     sgm_aggregate(ctx, p, cost, aggr, stream)
     sgm_disparity(ctx, p, aggr, disp, stream)
     uv_maps(ctx, p, disp, u, v, stream)

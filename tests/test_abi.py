@@ -44,7 +44,7 @@ def test_params_struct_layout_matches_header(sgm):
     # 5 int32, uint32, 2 uint16, 3 int32, 2 uint16 = 44 bytes, no hidden padding
     assert ctypes.sizeof(sgm.sgm_params) == 44
     assert sgm.sgm_params.p1.offset == 24 and sgm.sgm_params.lr_check.offset == 28
-    assert sgm.sgm_params.invalid.offset == 40
+    assert sgm.sgm_params.invalid.offset == 40 and sgm.sgm_params.cost.offset == 42
     assert ctypes.sizeof(sgm.sgm_frame) == 8 * 3 + 48 + 8 * 3
 
 
@@ -59,6 +59,7 @@ def good(sgm, **kw):
     ("width", 0), ("height", 0), ("width", 16385), ("max_disp", 0), ("max_disp", 257),
     ("census_w", 4), ("census_h", 0), ("census_w", 11), ("path_mask", 0), ("path_mask", 0x100),
     ("p1", 130), ("p2", 9000), ("lr_check", 2), ("lr_max_diff", -1), ("median", 7), ("invalid", 10),
+    ("cost", 2),
 ])
 def test_validation_rejects(sgm, field, value):
     with pytest.raises(sgm.SgmError) as e:
@@ -71,9 +72,19 @@ def test_validation_rejects(sgm, field, value):
     {"max_disp": 256, "invalid": 65535}, {"census_w": 65, "census_h": 1}, {"width": 1, "height": 1},
     {"max_disp": 60, "census_w": 5, "census_h": 5, "p1": 8, "p2": 32, "median": 5, "path_mask": 0x55},
     {"p1": 200, "p2": 8000, "path_mask": 0x01},
+    {"cost": 1, "census_w": 5, "census_h": 5, "p1": 200, "p2": 800},   # the paper's SAD setting
 ])
 def test_validation_accepts(sgm, kw):
     sgm.sgm_validate(good(sgm, **kw))
+
+
+def test_sad_overflow_rule_uses_window_times_255(sgm):
+    # 8 * (25 * 255 + p2) <= 65535  <=>  p2 <= 1816
+    sgm.sgm_validate(good(sgm, cost=1, census_w=5, census_h=5, p1=200, p2=1816))
+    with pytest.raises(sgm.SgmError):
+        sgm.sgm_validate(good(sgm, cost=1, census_w=5, census_h=5, p1=200, p2=1817))
+    with pytest.raises(sgm.SgmError):  # 17 x 17 * 255 > 65535
+        sgm.sgm_validate(good(sgm, cost=1, census_w=17, census_h=17, p1=0, p2=0, path_mask=1))
 
 
 def test_overflow_rule_is_paths_times_nbits_plus_p2(sgm):

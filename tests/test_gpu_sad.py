@@ -1,0 +1,78 @@
+"""SAD matching cost (section 3.1.2; 5x5 support, P1 = 200, P2 = 800 in
+section 4.1) on the GPU: the stage call and the whole path, alone and mixed
+with Census frames in one batch, bit-exact against the oracle."""
+import pytest
+
+from gen import synthetic
+from gpu_util import announce, assert_equal, gpu_or_skip, to_dev, to_np
+from oracle import oracle as O
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def env():
+    torch = gpu_or_skip()
+    from paper_1807_06271_amd import sgm
+    ctx = sgm.Context(0)
+    yield torch, sgm, ctx
+    torch.cuda.synchronize()
+    ctx.close()
+
+
+@pytest.mark.parametrize("W,H,D,ww,wh", [(1, 1, 1, 5, 5), (70, 9, 60, 5, 5), (130, 17, 128, 5, 5),
+                                         (40, 6, 64, 3, 3), (33, 8, 70, 1, 3), (50, 11, 16, 7, 5)])
+def test_sad_cost_stage(env, W, H, D, ww, wh):
+    torch, sgm, ctx = env
+    announce("sad cost", W, H, D, ww, wh)
+    left, right, _ = synthetic.make_pair("kitti", W + H + D, W, H, D)
+    p = sgm.Params(width=W, height=H, max_disp=D, census_w=ww, census_h=wh, cost=sgm.COST_SAD,
+                   p1=200, p2=800, path_mask=0x55)
+    out = torch.empty((H, W, D), dtype=torch.uint16, device="cuda")
+    sgm.sgm_cost_sad(ctx, p, to_dev(torch, left), to_dev(torch, right), out)
+    torch.cuda.synchronize()
+    assert_equal(to_np(out), O.sad_cost(left, right, ww, wh, D), "SAD cost")
+
+
+def paper_sad(sgm, W=640, H=360, D=60):
+    return sgm.Params(width=W, height=H, max_disp=D, census_w=5, census_h=5, cost=sgm.COST_SAD,
+                      path_mask=sgm.PATHS_PAPER4, p1=200, p2=800, lr_check=1, median=5)
+
+
+def test_paper_sad_configuration_whole_path(env):
+    torch, sgm, ctx = env
+    announce("paper SAD 640x360")
+    left, right, _ = synthetic.make_pair("paper", 71)
+    p = paper_sad(sgm)
+    want = O.sgm(left, right, 60, 5, 5, sgm.PATHS_PAPER4, 200, 800, True, 1, 5, cost_kind=1)
+    staged = sgm.run_stages(ctx, p, to_dev(torch, left), to_dev(torch, right), keep=True)
+    torch.cuda.synchronize()
+    assert_equal(to_np(staged["cost"]), want["cost"], "cost")
+    assert_equal(to_np(staged["aggr"]), want["aggr"], "aggr")
+    assert_equal(to_np(staged["disp"]), want["disp"], "disp (stages)")
+    f = sgm.Frame.alloc(p, to_dev(torch, left), to_dev(torch, right))
+    sgm.sgm_wait(ctx, sgm.sgm_submit(ctx, [f]))
+    assert_equal(to_np(f.disp), want["disp"], "disp (submit)")
+    assert_equal(to_np(f.umap), want["umap"], "umap")
+    assert_equal(to_np(f.vmap), want["vmap"], "vmap")
+
+
+def test_sad_and_census_frames_in_one_batch(env):
+    torch, sgm, ctx = env
+    announce("sad + census batch")
+    items = []
+    for i, (W, H, D, sad) in enumerate([(200, 60, 64, True), (200, 60, 64, False), (97, 31, 100, True),
+                                        (320, 40, 128, False)]):
+        left, right, _ = synthetic.make_pair("kitti", 300 + i, W, H, D)
+        if sad:
+            p = sgm.Params(width=W, height=H, max_disp=D, census_w=5, census_h=5, cost=sgm.COST_SAD,
+                           p1=200, p2=800, path_mask=0xFF)
+        else:
+            p = sgm.Params(width=W, height=H, max_disp=D)
+        items.append((p, left, right, sgm.Frame.alloc(p, to_dev(torch, left), to_dev(torch, right))))
+    sgm.sgm_wait(ctx, sgm.sgm_submit(ctx, [f for *_, f in items]))
+    for p, left, right, f in items:
+        want = O.sgm(left, right, p.max_disp, p.census_w, p.census_h, p.path_mask, p.p1, p.p2, True, 1, 3,
+                     cost_kind=p.cost)
+        assert_equal(to_np(f.disp), want["disp"], "disp %s" % ("SAD" if p.cost else "Census"))
+        assert_equal(to_np(f.umap), want["umap"], "umap")

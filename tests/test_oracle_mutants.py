@@ -88,3 +88,34 @@ def test_pins_catch_planted_mistake(tmp_path, restore_oracle, name, old, new):
     finally:
         O.load()
     assert caught, "no pin caught the planted mistake: " + name
+
+
+SAD_MUTANTS = [
+    ("SAD clamps the right view with the left coordinate",
+     "int b = right[(int64_t)yy * pitch + clampi(x - d + dx, 0, w - 1)];",
+     "int b = right[(int64_t)yy * pitch + clampi(x + dx, 0, w - 1) - d * (x + dx >= d)];"),
+    ("SAD zero left of the image", "c = ww * wh * 255;", "c = 0;"),
+    ("SAD signed difference", "c += a > b ? a - b : b - a;", "c += a - b;"),
+]
+
+
+@pytest.mark.parametrize("name,old,new", SAD_MUTANTS, ids=[m[0] for m in SAD_MUTANTS])
+def test_sad_pins_catch_planted_mistake(tmp_path, restore_oracle, name, old, new):
+    src = open(O.SRC).read()
+    assert src.count(old) == 1, name
+    c_path = tmp_path / "mutant.c"
+    so_path = tmp_path / "libmutant.so"
+    c_path.write_text(src.replace(old, new))
+    subprocess.check_call(["gcc", "-O1", "-std=c11", "-shared", "-fPIC", "-o", str(so_path), str(c_path)])
+    O.load(str(so_path))
+    caught = []
+    try:
+        for fn in (pins.test_sad_worked_example, pins.test_sad_matches_brute_force_loops,
+                   pins.test_sad_zero_at_true_shift_and_on_constant_images):
+            try:
+                fn()
+            except (AssertionError, O.OracleError):
+                caught.append(fn.__name__)
+    finally:
+        O.load()
+    assert caught, "no pin caught: " + name

@@ -377,3 +377,57 @@ def test_synthetic_scene_sanity_statistics():
     both = valid & has_gt
     correct = (np.abs(disp[both] - gt[both]) < 3).mean()
     assert density > 0.6 and correct > 0.8, (density, correct)
+
+
+# ------------------------------------------------------- SAD cost (3.1.2)
+
+def test_sad_worked_example():
+    g = load_golden("sad_1x4.json")
+    c = O.sad_cost(np.array(g["left"], np.uint8), np.array(g["right"], np.uint8), *g["window"], g["max_disp"])
+    assert c.tolist() == g["cost"]
+
+
+def test_sad_matches_brute_force_loops():
+    rng = np.random.default_rng(31)
+    for (H, W, D, ww, wh) in [(3, 7, 4, 3, 3), (5, 6, 8, 5, 5), (4, 9, 3, 1, 3)]:
+        L = synthetic.random_image(rng, H, W)
+        R = synthetic.random_image(rng, H, W)
+        c = O.sad_cost(L, R, ww, wh, D)
+        rx, ry = ww // 2, wh // 2
+        for y in range(H):
+            for x in range(W):
+                for d in range(D):
+                    if x < d:
+                        want = ww * wh * 255
+                    else:
+                        want = 0
+                        for dy in range(-ry, ry + 1):
+                            for dx in range(-rx, rx + 1):
+                                yy = min(max(y + dy, 0), H - 1)
+                                a = int(L[yy, min(max(x + dx, 0), W - 1)])
+                                b = int(R[yy, min(max(x - d + dx, 0), W - 1)])
+                                want += abs(a - b)
+                    assert int(c[y, x, d]) == want
+
+
+def test_sad_zero_at_true_shift_and_on_constant_images():
+    rng = np.random.default_rng(8)
+    H, W, d0 = 12, 40, 4
+    base = synthetic.random_image(rng, H, W + d0)
+    left, right = base[:, :W], base[:, d0:W + d0]
+    c = O.sad_cost(left, right, 5, 5, 8)
+    assert not c[:, d0 + 2:W - 2, d0].any()
+    flat = np.full((6, 10), 9, np.uint8)
+    c = O.sad_cost(flat, flat, 5, 5, 4)
+    for x in range(10):
+        for d in range(4):
+            assert (c[:, x, d] == (0 if d <= x else 25 * 255)).all()
+
+
+def test_sad_pipeline_on_fronto_parallel_shift():
+    # the paper's SAD setting (5x5, P1 = 200, P2 = 800) recovers a plain shift
+    rng = np.random.default_rng(21)
+    H, W, D, d0 = 40, 96, 16, 6
+    base = np.rint(synthetic.fractal_texture(rng, H, W + d0)).clip(0, 255).astype(np.uint8)
+    out = O.sgm(base[:, :W], base[:, d0:W + d0], D, 5, 5, 0x55, 200, 800, True, 1, 5, cost_kind=1)
+    assert (out["disp_l"][4:-4, D + 4:-4] == d0).mean() >= 0.99
