@@ -40,7 +40,7 @@ import numpy as np
 
 __all__ = [
     "fractal_texture", "Scene", "render_pair", "make_pair", "mixed_batch_specs",
-    "camera_frame", "random_image", "random_cost", "poisson_trace", "RECIPES",
+    "camera_frame", "random_image", "random_cost", "poisson_trace", "RECIPES", "rectification_maps",
 ]
 
 # (width, height, max_disp) of each named workload.
@@ -259,6 +259,30 @@ def poisson_trace(n_cameras: int, fps: float, seconds: float, seed: int):
             k += 1
     ev.sort()
     return ev
+
+
+def rectification_maps(w: int, h: int, src_w: int, src_h: int, seed: int, angle_deg: float = 1.5,
+                       k1: float = -0.05):
+    """Integer remap tables (uint16 [h][w] source column, source row) of a
+    synthetic calibration: a small rotation about the image centre, a radial
+    distortion term k1 and a random sub-pixel offset, rounded to the nearest
+    source pixel.  Entries that fall outside the raw image are set to 65535
+    (no source pixel)."""
+    rng = np.random.default_rng(seed)
+    ys, xs = np.mgrid[0:h, 0:w].astype(np.float64)
+    cx, cy = (w - 1) / 2.0, (h - 1) / 2.0
+    u, v = (xs - cx) / max(cx, 1.0), (ys - cy) / max(cy, 1.0)
+    r2 = u * u + v * v
+    t = np.deg2rad(angle_deg * float(rng.uniform(0.5, 1.0)))
+    ud = (u * np.cos(t) - v * np.sin(t)) * (1 + k1 * r2)
+    vd = (u * np.sin(t) + v * np.cos(t)) * (1 + k1 * r2)
+    sx = ud * (src_w - 1) / 2.0 + (src_w - 1) / 2.0 + float(rng.uniform(-0.5, 0.5))
+    sy = vd * (src_h - 1) / 2.0 + (src_h - 1) / 2.0 + float(rng.uniform(-0.5, 0.5))
+    mx, my = np.rint(sx), np.rint(sy)
+    out = (mx < 0) | (my < 0) | (mx >= src_w) | (my >= src_h)
+    mx[out] = 65535
+    my[out] = 65535
+    return mx.astype(np.uint16), my.astype(np.uint16)
 
 
 def random_image(rng: np.random.Generator, h: int, w: int, levels: int = 256) -> np.ndarray:

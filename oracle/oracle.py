@@ -61,6 +61,7 @@ def _declare(L):
     i = ctypes.c_int
     L.oracle_census.argtypes = [u8p, i, i, ctypes.c_int64, i, i, u64p]
     L.oracle_cost.argtypes = [u64p, u64p, i, i, i, i, u16p]
+    L.oracle_rectify.argtypes = [u8p, i, i, ctypes.c_int64, u16p, u16p, i, i, u8p]
     L.oracle_sad_cost.argtypes = [u8p, u8p, i, i, ctypes.c_int64, i, i, i, u16p]
     L.oracle_aggregate.argtypes = [u16p, i, i, i, ctypes.c_uint32, i, i, u16p]
     L.oracle_wta.argtypes = [u16p, i, i, i, u16p]
@@ -114,6 +115,18 @@ def cost(cl: np.ndarray, cr: np.ndarray, d_max: int, nbits: int) -> np.ndarray:
     out = np.zeros((h, w, d_max), np.uint16)
     _check(lib().oracle_cost(_p(cl, ctypes.c_uint64), _p(cr, ctypes.c_uint64), w, h, d_max, nbits,
                              _p(out, ctypes.c_uint16)), "cost")
+    return out
+
+
+def rectify(src: np.ndarray, map_x: np.ndarray, map_y: np.ndarray) -> np.ndarray:
+    src = np.ascontiguousarray(src, np.uint8)
+    map_x = np.ascontiguousarray(map_x, np.uint16)
+    map_y = np.ascontiguousarray(map_y, np.uint16)
+    sh, sw = src.shape
+    h, w = map_x.shape
+    out = np.zeros((h, w), np.uint8)
+    _check(lib().oracle_rectify(_p(src, ctypes.c_uint8), sw, sh, sw, _p(map_x, ctypes.c_uint16),
+                                _p(map_y, ctypes.c_uint16), w, h, _p(out, ctypes.c_uint8)), "rectify")
     return out
 
 

@@ -80,6 +80,21 @@ static int popcount64(uint64_t v) {
     return n;
 }
 
+/* Rectification by precomputed maps (section 3.1.1): for each pixel p of the
+ * w x h rectified image, I_rect(p) = I(M_x(p), M_y(p)), where (M_x, M_y) are
+ * integer source coordinates into the src_w x src_h raw image.  A map entry
+ * outside the raw image gives 0 (no source pixel).  maps are [h][w]. */
+int oracle_rectify(const uint8_t *src, int src_w, int src_h, int64_t src_pitch, const uint16_t *map_x,
+                   const uint16_t *map_y, int w, int h, uint8_t *out) {
+    if (src_w < 1 || src_h < 1 || w < 1 || h < 1) return ORACLE_EINVAL;
+    for (int y = 0; y < h; ++y)
+        for (int x = 0; x < w; ++x) {
+            int sx = map_x[(int64_t)y * w + x], sy = map_y[(int64_t)y * w + x];
+            out[(int64_t)y * w + x] = (sx < src_w && sy < src_h) ? src[(int64_t)sy * src_pitch + sx] : 0;
+        }
+    return ORACLE_OK;
+}
+
 /* Matching cost volume, equation (1): C(p, d) compares left pixel p with right
  * pixel (p_x - d, p_y) by the Hamming distance of their Census codes.
  * cost is [h][w][d_max]. */

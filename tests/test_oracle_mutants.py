@@ -119,3 +119,32 @@ def test_sad_pins_catch_planted_mistake(tmp_path, restore_oracle, name, old, new
     finally:
         O.load()
     assert caught, "no pin caught: " + name
+
+
+RECTIFY_MUTANTS = [
+    ("rectify swaps the two maps", "int sx = map_x[(int64_t)y * w + x], sy = map_y[(int64_t)y * w + x];",
+     "int sx = map_y[(int64_t)y * w + x], sy = map_x[(int64_t)y * w + x];"),
+    ("rectify reads one column beyond the image", "(sx < src_w && sy < src_h)", "(sx <= src_w && sy < src_h)"),
+    ("rectify fills with the first pixel", "+ sx] : 0;", "+ sx] : src[0];"),
+]
+
+
+@pytest.mark.parametrize("name,old,new", RECTIFY_MUTANTS, ids=[m[0] for m in RECTIFY_MUTANTS])
+def test_rectify_pins_catch_planted_mistake(tmp_path, restore_oracle, name, old, new):
+    src = open(O.SRC).read()
+    assert src.count(old) == 1, name
+    c_path = tmp_path / "mutant.c"
+    so_path = tmp_path / "libmutant.so"
+    c_path.write_text(src.replace(old, new))
+    subprocess.check_call(["gcc", "-O1", "-std=c11", "-shared", "-fPIC", "-o", str(so_path), str(c_path)])
+    O.load(str(so_path))
+    caught = []
+    try:
+        for fn in (pins.test_rectify_identity_flip_and_out_of_range, pins.test_rectify_is_a_gather):
+            try:
+                fn()
+            except (AssertionError, O.OracleError):
+                caught.append(fn.__name__)
+    finally:
+        O.load()
+    assert caught, "no pin caught: " + name

@@ -431,3 +431,35 @@ def test_sad_pipeline_on_fronto_parallel_shift():
     base = np.rint(synthetic.fractal_texture(rng, H, W + d0)).clip(0, 255).astype(np.uint8)
     out = O.sgm(base[:, :W], base[:, d0:W + d0], D, 5, 5, 0x55, 200, 800, True, 1, 5, cost_kind=1)
     assert (out["disp_l"][4:-4, D + 4:-4] == d0).mean() >= 0.99
+
+
+# --------------------------------------------------- rectification (3.1.1)
+
+def test_rectify_identity_flip_and_out_of_range():
+    rng = np.random.default_rng(40)
+    src = synthetic.random_image(rng, 7, 11)
+    ys, xs = np.mgrid[0:7, 0:11]
+    assert (O.rectify(src, xs.astype(np.uint16), ys.astype(np.uint16)) == src).all()
+    flip = O.rectify(src, (10 - xs).astype(np.uint16), ys.astype(np.uint16))
+    assert (flip == src[:, ::-1]).all()
+    mx = xs.astype(np.uint16).copy()
+    mx[2, 3] = 11      # one column beyond the raw image
+    my = ys.astype(np.uint16).copy()
+    my[4, 5] = 65535   # "no source pixel"
+    out = O.rectify(src, mx, my)
+    assert out[2, 3] == 0 and out[4, 5] == 0
+    mask = np.ones_like(src, bool)
+    mask[2, 3] = mask[4, 5] = False
+    assert (out[mask] == src[mask]).all()
+
+
+def test_rectify_is_a_gather():
+    # against NumPy fancy indexing on a raw image of another size
+    rng = np.random.default_rng(41)
+    src = synthetic.random_image(rng, 40, 50)
+    mx, my = synthetic.rectification_maps(33, 21, 50, 40, seed=3)
+    want = np.zeros((21, 33), np.uint8)
+    ok = (mx < 50) & (my < 40)
+    want[ok] = src[my[ok].astype(int), mx[ok].astype(int)]
+    assert (O.rectify(src, mx, my) == want).all()
+    assert ok.mean() > 0.8
