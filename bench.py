@@ -104,6 +104,28 @@ def bench_small(torch, sgm, ctx, synthetic, steps=200):
     return res
 
 
+def bench_paper_settings(torch, sgm, ctx, synthetic, steps=100):
+    """The paper's own setting (640x360, D in [0,60), 5x5 support, the four
+    forward paths of its figure 2, LR check, 5x5 median; section 4.1) with
+    the Census cost (P1=8, P2=32) and with SAD (P1=200, P2=800): one pair per
+    step on one stream.  The paper's FPGA ran this at 29 Hz (section 4.1)."""
+    L, R, _ = synthetic.make_pair("paper", 7)
+    Lt, Rt = torch.from_numpy(L).cuda(), torch.from_numpy(R).cuda()
+    res = {"paper_fpga_hz": 29.0}
+    sgm.sgm_profile(ctx, False)
+    sgm.sgm_set_streams(ctx, 1)
+    for name, kw in (("census", dict(cost=sgm.COST_CENSUS, p1=8, p2=32)),
+                     ("sad", dict(cost=sgm.COST_SAD, p1=200, p2=800))):
+        p = sgm.Params(width=640, height=360, max_disp=60, census_w=5, census_h=5,
+                       path_mask=sgm.PATHS_PAPER4, lr_check=1, median=5, **kw)
+        sgm.sgm_autotune(ctx, sgm.Frame.alloc(p, Lt, Rt), reps=3)
+        dt, _ = time_submit_stream(torch, sgm, ctx, lambda i: [sgm.Frame.alloc(p, Lt, Rt)], steps, 10)
+        res[name] = {"fps": steps / dt, "mdisp_evals_per_s": p.disp_evals() * steps / dt / 1e6,
+                     "ms_per_frame": dt / steps * 1e3}
+    sgm.sgm_profile(ctx, True)
+    return res
+
+
 def bench_batch32(torch, sgm, ctx, synthetic):
     specs = synthetic.mixed_batch_specs(32, seed=2000)
     frames = []
@@ -353,6 +375,8 @@ def main():
     if args.extras in ("batch", "all"):
         log("320x240 D=64 5x5 4 paths, WTA only")
         extras["small_320x240_d64_4path_wta"] = bench_small(torch, sgm, ctx, synthetic)
+        log("paper settings 640x360 D=60, Census and SAD")
+        extras["paper_640x360_d60_4path"] = bench_paper_settings(torch, sgm, ctx, synthetic)
         log("batch of 32 mixed pairs")
         extras["batch32_mixed"] = bench_batch32(torch, sgm, ctx, synthetic)
         log("batch of 8 1920x1080 D=256")
