@@ -122,8 +122,60 @@ def bench_paper_settings(torch, sgm, ctx, synthetic, steps=100):
         dt, _ = time_submit_stream(torch, sgm, ctx, lambda i: [sgm.Frame.alloc(p, Lt, Rt)], steps, 10)
         res[name] = {"fps": steps / dt, "mdisp_evals_per_s": p.disp_evals() * steps / dt / 1e6,
                      "ms_per_frame": dt / steps * 1e3}
+    res["census_rectified"] = bench_rectified(torch, sgm, ctx, synthetic, steps)
     sgm.sgm_profile(ctx, True)
     return res
+
+
+def bench_rectified(torch, sgm, ctx, synthetic, steps):
+    """Raw 672x380 pairs rectified to 640x360 by synthetic calibration maps
+    (section 3.1.1), then the paper's Census setting: sgm_submit_rectify per
+    pair, and the rectification kernel alone (both views, one launch) timed
+    with events on the stream it runs on."""
+    w, h, D, sw, sh = 640, 360, 60, 672, 380
+    raw_l, raw_r, _ = synthetic.make_pair("paper", 8, sw, sh, D)
+    RL, RR = torch.from_numpy(raw_l).cuda(), torch.from_numpy(raw_r).cuda()
+    maps = [tuple(torch.from_numpy(m).cuda() for m in synthetic.rectification_maps(w, h, sw, sh, seed=s))
+            for s in (1, 2)]
+    p = sgm.Params(width=w, height=h, max_disp=D, census_w=5, census_h=5, path_mask=sgm.PATHS_PAPER4,
+                   lr_check=1, median=5, p1=8, p2=32)
+    frames = [sgm.Frame.alloc(p, torch.empty((h, w), dtype=torch.uint8, device="cuda"),
+                              torch.empty((h, w), dtype=torch.uint8, device="cuda")) for _ in range(8)]
+    remaps = [(RL, *maps[0]), (RR, *maps[1])]
+
+    def run(n):
+        inflight = []
+        for s in range(n):
+            if len(inflight) >= 8:
+                sgm.sgm_wait(ctx, inflight.pop(0))
+            inflight.append(sgm.sgm_submit_rectify(ctx, [frames[s % 8]], remaps))
+        for t in inflight:
+            sgm.sgm_wait(ctx, t)
+
+    run(10)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    run(steps)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    jobs = [sgm.remap_job(RL, *maps[0], frames[0].left), sgm.remap_job(RR, *maps[1], frames[0].right)]
+    stream = torch.cuda.current_stream()
+    for _ in range(10):
+        sgm.sgm_rectify(ctx, jobs, stream)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = 200
+    e0.record(stream)
+    for _ in range(reps):
+        sgm.sgm_rectify(ctx, jobs, stream)
+    e1.record(stream)
+    e1.synchronize()
+    us = e0.elapsed_time(e1) * 1e3 / reps
+    # algorithmic bytes of one launch: per rectified pixel two 16-bit map
+    # entries and one output byte, plus each raw image read once
+    algo = 2 * (w * h * 5 + sw * sh)
+    return {"fps": steps / dt, "ms_per_frame": dt / steps * 1e3, "raw": "%dx%d" % (sw, sh),
+            "rectify_us_per_pair": us, "rectify_algorithmic_bytes": algo,
+            "rectify_gb_per_s": algo / (us * 1e-6) / 1e9}
 
 
 def bench_batch32(torch, sgm, ctx, synthetic):

@@ -120,6 +120,35 @@ int sgm_destroy(sgm_ctx *ctx);
  * library, valid until the thread's next call. */
 const char *sgm_last_error(void);
 
+/* One image to rectify (section 3.1.1).  For each pixel p = (x, y) of the
+ * w x h rectified image, out(p) = src(map_x(p), map_y(p)): the maps hold, per
+ * rectified pixel, the integer column and row of the raw image pixel it shows
+ * (maps precomputed once from the calibration).  An entry with map_x >= src_w
+ * or map_y >= src_h (e.g. 65535) means "no source pixel" and gives 0.
+ *   src:   device uint8  [src_h][src_pitch], src_pitch >= src_w
+ *   map_x, map_y: device uint16 [h][w] (16-byte aligned maps are read with
+ *          wider loads; any alignment is accepted)
+ *   out:   device uint8  [h][out_pitch], out_pitch >= w; must not overlap
+ *          src or the maps.
+ * Limits: 1 <= w, h <= 16384; 1 <= src_w, src_h <= 65535. */
+typedef struct {
+  const uint8_t *src;
+  const uint16_t *map_x;
+  const uint16_t *map_y;
+  uint8_t *out;
+  int64_t src_pitch;
+  int64_t out_pitch;
+  int32_t src_w, src_h;
+  int32_t w, h;
+} sgm_remap;
+
+/* Rectify n >= 0 images (e.g. the left and right raw images of several
+ * frames, each with its own maps) with one kernel launch per 24 images,
+ * enqueued on `stream`.  n = 0 enqueues nothing.  Every job is checked
+ * before anything is enqueued; SGM_EINVAL names the first bad job.  Uses no
+ * scratch memory, so calls on different streams may overlap. */
+int sgm_rectify(sgm_ctx *ctx, const sgm_remap *jobs, int n, void *stream);
+
 /* Census transform (section 3.1.2): for each pixel p, an N_b-bit code of the
  * comparisons [I(q) < I(p)] over the census_w x census_h window, neighbours in
  * raster order with the first one in bit N_b-1, coordinates clamped to the
@@ -193,6 +222,19 @@ int sgm_submit(sgm_ctx *ctx, const sgm_frame *frames, int n, uint64_t *ticket);
  * with more, a batch can start while earlier ones still run. */
 int sgm_set_streams(sgm_ctx *ctx, int n);
 
+/* sgm_submit with rectification (section 3.1.1) as the batch's first
+ * stage: remaps[2i] and remaps[2i+1] turn frame i's raw left and right images
+ * into frames[i].left and frames[i].right, on the batch's own stream, so raw
+ * pairs go through the whole path without a host wait.  Each remap's out,
+ * out_pitch, w and h must be the frame's view buffer, pitch, width and height
+ * (SGM_EINVAL otherwise).  The raw images and the maps must stay valid until
+ * the ticket is done; everything else is as for sgm_submit.  (sgm_submit
+ * itself does not wait for work the caller enqueued on other streams:
+ * results of sgm_rectify on a caller's stream must be complete before the
+ * frames are submitted.) */
+int sgm_submit_rectify(sgm_ctx *ctx, const sgm_frame *frames, const sgm_remap *remaps, int n,
+                       uint64_t *ticket);
+
 /* Graph mode for sgm_submit (0 = off, the default after sgm_create; 1 = on).
  * When on, a batch's launches are captured into a HIP graph; graphs are
  * cached by batch composition (frame shapes, parameters and schedules), and
@@ -249,7 +291,8 @@ enum {
   SGM_STAGE_DISPARITY = 2,
   SGM_STAGE_MEDIAN = 3,
   SGM_STAGE_UV = 4,
-  SGM_NSTAGES = 5
+  SGM_STAGE_RECTIFY = 5,  /* sgm_submit_rectify only */
+  SGM_NSTAGES = 6
 };
 int sgm_profile(sgm_ctx *ctx, int enable);
 /* ms[SGM_NSTAGES]: summed milliseconds; count[SGM_NSTAGES]: launches summed

@@ -283,9 +283,45 @@ int resolve_hlps(const sgm_ctx *c, const sgm_params &p) {
 
 // Everything that decides a batch's launch sequence (kernels, grids, LDS):
 // the frames' parameters and schedules, in order.
-std::string composition_key(const sgm_frame *fr, int n, const std::vector<int> &hlps) {
+// Check one sgm_remap (sizes, pitches, device pointers) and build its job.
+int check_remap(const sgm_remap &r, int i, int dev, RemapJob *out) {
+  if (r.w < 1 || r.h < 1 || r.w > 16384 || r.h > 16384)
+    return fail(SGM_EINVAL, "job %d: rectified size %dx%d outside 1..16384", i, r.w, r.h);
+  if (r.src_w < 1 || r.src_h < 1 || r.src_w > 65535 || r.src_h > 65535)
+    return fail(SGM_EINVAL, "job %d: raw size %dx%d outside 1..65535", i, r.src_w, r.src_h);
+  if (r.src_pitch < r.src_w) return fail(SGM_EINVAL, "job %d: src_pitch < src_w", i);
+  if (r.out_pitch < r.w) return fail(SGM_EINVAL, "job %d: out_pitch < w", i);
+  const void *ptrs[4] = {r.src, r.map_x, r.map_y, r.out};
+  const char *names[4] = {"src", "map_x", "map_y", "out"};
+  char name[32];
+  for (int k = 0; k < 4; ++k) {
+    snprintf(name, sizeof(name), "job %d: %s", i, names[k]);
+    CHECK(check_dev_ptr(ptrs[k], dev, name));
+  }
+  RemapJob j{};
+  j.src = r.src;
+  j.mx = r.map_x;
+  j.my = r.map_y;
+  j.out = r.out;
+  j.src_pitch = r.src_pitch;
+  j.out_pitch = r.out_pitch;
+  j.src_w = r.src_w;
+  j.src_h = r.src_h;
+  j.w = r.w;
+  j.h = r.h;
+  j.vec = ((reinterpret_cast<uintptr_t>(r.map_x) | reinterpret_cast<uintptr_t>(r.map_y)) & 15) == 0;
+  *out = j;
+  return SGM_OK;
+}
+
+std::string composition_key(const sgm_frame *fr, int n, const std::vector<int> &hlps,
+                            const std::vector<RemapJob> &rect) {
   std::string k;
   char buf[160];
+  for (const RemapJob &r : rect) {
+    snprintf(buf, sizeof buf, "R%d,%d,%d,%d,%d;", r.w, r.h, r.src_w, r.src_h, r.vec);
+    k += buf;
+  }
   for (int i = 0; i < n; ++i) {
     const sgm_params &p = fr[i].p;
     snprintf(buf, sizeof buf, "%d,%d,%d,%d,%d,%u,%u,%u,%d,%d,%d,%u,%d,%d;", p.width, p.height,
@@ -327,9 +363,17 @@ struct StageMark {
 };
 
 int enqueue_frames(const sgm_frame *fr, int n, const std::vector<FramePlan> &plans,
-                   const std::vector<int> &hlps, char *mem, hipStream_t s,
-                   std::vector<StageEvents> *prof) {
+                   const std::vector<int> &hlps, const std::vector<RemapJob> &rect, char *mem,
+                   hipStream_t s, std::vector<StageEvents> *prof) {
   StageMark mark{prof, s};
+  // rectification of the raw views into the frames' input buffers (one
+  // launch for every view of the batch)
+  if (!rect.empty()) {
+    CHECK(mark.begin(SGM_STAGE_RECTIFY));
+    launch_rectify(rect, s);
+    CHECK(check_launch());
+    CHECK(mark.end((int)((rect.size() + kMaxJobs - 1) / kMaxJobs)));
+  }
   // Census of both views + padded uint8 costs (one launch for all Census
   // frames); SAD costs (one launch for all SAD frames, U-maps cleared apart)
   std::vector<FusedCostJob> fj;
@@ -494,9 +538,10 @@ void destroy_events(Batch &b) {
 // the cached executable graph of the same composition (updated with this
 // batch's buffers), instantiating one on a miss.
 int enqueue_graph(sgm_ctx *c, const sgm_frame *fr, int n, const std::vector<FramePlan> &plans,
-                  const std::vector<int> &hlps, char *mem, hipStream_t s) {
+                  const std::vector<int> &hlps, const std::vector<RemapJob> &rect, char *mem,
+                  hipStream_t s) {
   HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed));
-  int rc = enqueue_frames(fr, n, plans, hlps, mem, s, nullptr);
+  int rc = enqueue_frames(fr, n, plans, hlps, rect, mem, s, nullptr);
   hipGraph_t g = nullptr;
   hipError_t e = hipStreamEndCapture(s, &g);
   if (rc != SGM_OK) {
@@ -504,7 +549,7 @@ int enqueue_graph(sgm_ctx *c, const sgm_frame *fr, int n, const std::vector<Fram
     return rc;
   }
   if (e != hipSuccess) return fail(SGM_EHIP, "graph capture: %s", hipGetErrorString(e));
-  const std::string key = composition_key(fr, n, hlps);
+  const std::string key = composition_key(fr, n, hlps, rect);
   auto it = c->graph_cache.find(key);
   hipGraphExec_t ex = nullptr;
   if (it != c->graph_cache.end()) {
@@ -585,6 +630,19 @@ int sgm_destroy(sgm_ctx *c) {
   }
   delete c;
   return rc;
+}
+
+int sgm_rectify(sgm_ctx *c, const sgm_remap *jobs, int n, void *stream) {
+  if (!c) return fail(SGM_EINVAL, "ctx is null");
+  if (n < 0) return fail(SGM_EINVAL, "n = %d < 0", n);
+  if (n > 0 && !jobs) return fail(SGM_EINVAL, "jobs is null");
+  std::lock_guard<std::mutex> lk(c->mu);
+  DeviceGuard g(c->device);
+  std::vector<RemapJob> rj(n);
+  for (int i = 0; i < n; ++i) CHECK(check_remap(jobs[i], i, c->device, &rj[i]));
+  if (rj.empty()) return SGM_OK;
+  launch_rectify(rj, (hipStream_t)stream);
+  return check_launch();
 }
 
 int sgm_census(sgm_ctx *c, const sgm_params *p, const uint8_t *img, int64_t pitch, uint64_t *census,
@@ -759,7 +817,8 @@ int uv_maps(sgm_ctx *c, const sgm_params *p, const uint16_t *disp, uint16_t *uma
   return check_launch();
 }
 
-int sgm_submit(sgm_ctx *c, const sgm_frame *frames, int n, uint64_t *ticket) {
+static int submit_impl(sgm_ctx *c, const sgm_frame *frames, const sgm_remap *remaps, int n,
+                       uint64_t *ticket) {
   if (!c) return fail(SGM_EINVAL, "ctx is null");
   if (!frames || n < 1 || !ticket) return fail(SGM_EINVAL, "need frames, n >= 1 and a ticket pointer");
   std::vector<FramePlan> plans(n);
@@ -784,6 +843,19 @@ int sgm_submit(sgm_ctx *c, const sgm_frame *frames, int n, uint64_t *ticket) {
       CHECK(check_dev_ptr(frames[i].vmap, c->device, "vmap"));
       if (reinterpret_cast<uintptr_t>(frames[i].umap) & 3)
         return fail(SGM_EINVAL, "frame %d: umap must be 4-byte aligned", i);
+    }
+  }
+  std::vector<RemapJob> rect;
+  if (remaps) {
+    rect.resize(2 * (size_t)n);
+    for (int i = 0; i < 2 * n; ++i) {
+      CHECK(check_remap(remaps[i], i, c->device, &rect[i]));
+      const sgm_frame &f = frames[i / 2];
+      const uint8_t *dst = (i & 1) ? f.right : f.left;
+      if (remaps[i].out != dst || remaps[i].out_pitch != f.pitch || remaps[i].w != f.p.width ||
+          remaps[i].h != f.p.height)
+        return fail(SGM_EINVAL, "job %d: out, out_pitch, w, h must be frame %d's %s view, pitch and size", i,
+                    i / 2, (i & 1) ? "right" : "left");
     }
   }
   total = align256(total);
@@ -816,9 +888,9 @@ int sgm_submit(sgm_ctx *c, const sgm_frame *frames, int n, uint64_t *ticket) {
   for (int i = 0; i < n; ++i) hl[i] = resolve_hlps(c, frames[i].p);
   int rc = SGM_OK;
   if (c->graphs && !c->profiling) {
-    rc = enqueue_graph(c, frames, n, plans, hl, reinterpret_cast<char *>(blk.ptr), s);
+    rc = enqueue_graph(c, frames, n, plans, hl, rect, reinterpret_cast<char *>(blk.ptr), s);
   } else {
-    rc = enqueue_frames(frames, n, plans, hl, reinterpret_cast<char *>(blk.ptr), s,
+    rc = enqueue_frames(frames, n, plans, hl, rect, reinterpret_cast<char *>(blk.ptr), s,
                         c->profiling ? &b.prof : nullptr);
   }
   if (rc == SGM_OK && hipEventCreateWithFlags(&b.done, hipEventDisableTiming) != hipSuccess)
@@ -833,6 +905,16 @@ int sgm_submit(sgm_ctx *c, const sgm_frame *frames, int n, uint64_t *ticket) {
   *ticket = c->next_ticket++;
   c->inflight[*ticket] = b;
   return SGM_OK;
+}
+
+int sgm_submit(sgm_ctx *c, const sgm_frame *frames, int n, uint64_t *ticket) {
+  return submit_impl(c, frames, nullptr, n, ticket);
+}
+
+int sgm_submit_rectify(sgm_ctx *c, const sgm_frame *frames, const sgm_remap *remaps, int n,
+                       uint64_t *ticket) {
+  if (!remaps) return fail(SGM_EINVAL, "remaps is null");
+  return submit_impl(c, frames, remaps, n, ticket);
 }
 
 static int poll_locked(sgm_ctx *c, uint64_t ticket, int *done, bool block) {

@@ -142,4 +142,19 @@ struct ZeroJob {
 };
 void launch_zero(std::vector<ZeroJob> jobs, hipStream_t s);
 
+// ------------------------------------------------------------ rectify
+// Gather through integer remap maps (section 3.1.1).  Pixels are taken in
+// groups of kRectPx consecutive entries of the [h][w] maps.
+constexpr int kRectPx = 8;
+struct RemapJob {
+  const uint8_t *src;
+  const uint16_t *mx, *my;  // [h][w]
+  uint8_t *out;             // [h][out_pitch]
+  int64_t src_pitch, out_pitch;
+  int src_w, src_h, w, h;
+  int vec;                  // maps 16-byte aligned: 128-bit map loads
+  int blk0;
+};
+void launch_rectify(std::vector<RemapJob> jobs, hipStream_t s);
+
 }  // namespace sgmk

@@ -37,8 +37,9 @@ EXPORTS = ["sgm_validate", "sgm_create", "sgm_destroy", "sgm_last_error", "sgm_c
            "sgm_aggregate",
            "sgm_disparity", "uv_maps", "sgm_submit", "sgm_poll", "sgm_wait", "sgm_memory", "sgm_profile",
            "sgm_profile_read", "sgm_set_streams", "sgm_set_schedule", "sgm_get_schedule",
-           "sgm_autotune", "sgm_set_graphs", "sgm_graph_stats"]
-STAGES = ["census", "aggregate", "disparity", "median", "uv"]
+           "sgm_autotune", "sgm_set_graphs", "sgm_graph_stats", "sgm_rectify",
+           "sgm_submit_rectify"]
+STAGES = ["census", "aggregate", "disparity", "median", "uv", "rectify"]
 
 
 class SgmError(RuntimeError):
@@ -58,6 +59,13 @@ class sgm_params(ctypes.Structure):
 
 class sgm_schedule(ctypes.Structure):
     _fields_ = [("h_lanes", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
+
+
+class sgm_remap(ctypes.Structure):
+    _fields_ = [("src", ctypes.c_void_p), ("map_x", ctypes.c_void_p), ("map_y", ctypes.c_void_p),
+                ("out", ctypes.c_void_p), ("src_pitch", ctypes.c_int64), ("out_pitch", ctypes.c_int64),
+                ("src_w", ctypes.c_int32), ("src_h", ctypes.c_int32), ("w", ctypes.c_int32),
+                ("h", ctypes.c_int32)]
 
 
 class sgm_frame(ctypes.Structure):
@@ -127,6 +135,8 @@ def lib():
         L.sgm_last_error.argtypes = []
         L.sgm_last_error.restype = ctypes.c_char_p
         L.sgm_census.argtypes = [vp, P(sgm_params), vp, ctypes.c_int64, vp, vp]
+        L.sgm_rectify.argtypes = [vp, P(sgm_remap), i32, vp]
+        L.sgm_submit_rectify.argtypes = [vp, P(sgm_frame), P(sgm_remap), i32, P(ctypes.c_uint64)]
         L.sgm_cost.argtypes = [vp, P(sgm_params), vp, vp, vp, vp]
         L.sgm_cost_sad.argtypes = [vp, P(sgm_params), vp, vp, ctypes.c_int64, vp, vp]
         L.sgm_aggregate.argtypes = [vp, P(sgm_params), vp, vp, vp]
@@ -213,6 +223,31 @@ class Context:
             self.close()
         except Exception:
             pass
+
+
+def _rows(t, name, dtype):
+    if t.dtype != dtype or t.dim() != 2 or t.stride(1) != 1 or not t.is_cuda:
+        raise ValueError("%s must be a CUDA %s [rows][pitch] tensor with contiguous rows" % (name, dtype))
+
+
+def remap_job(src, map_x, map_y, out) -> sgm_remap:
+    """One sgm_remap from tensors: src uint8 [src_h][src_w] (row pitch from its
+    stride), map_x/map_y contiguous uint16 [h][w], out uint8 [h][w] (pitch from
+    its stride)."""
+    _rows(src, "src", torch.uint8)
+    _rows(out, "out", torch.uint8)
+    _need(map_x, tuple(out.shape), torch.uint16, "map_x")
+    _need(map_y, tuple(out.shape), torch.uint16, "map_y")
+    h, w = out.shape
+    return sgm_remap(src.data_ptr(), _ptr(map_x), _ptr(map_y), out.data_ptr(), src.stride(0), out.stride(0),
+                     src.shape[1], src.shape[0], w, h)
+
+
+def sgm_rectify(ctx: Context, jobs, stream=None):
+    """Rectify every (src, map_x, map_y, out) of `jobs` (tuples or sgm_remap)."""
+    rj = [j if isinstance(j, sgm_remap) else remap_job(*j) for j in jobs]
+    arr = (sgm_remap * max(len(rj), 1))(*rj)
+    _check(lib().sgm_rectify(ctx.handle, arr, len(rj), _stream(stream)), "sgm_rectify")
 
 
 def sgm_census(ctx: Context, p: Params, img, census, stream=None):
@@ -309,6 +344,26 @@ def sgm_submit(ctx: Context, frames) -> int:
     arr = (sgm_frame * len(frames))(*[f.c() for f in frames])
     t = ctypes.c_uint64()
     _check(lib().sgm_submit(ctx.handle, arr, len(frames), ctypes.byref(t)), "sgm_submit")
+    return t.value
+
+
+def sgm_submit_rectify(ctx: Context, frames, remaps) -> int:
+    """sgm_submit with rectification first: remaps[2i] / remaps[2i+1]
+    ((src, map_x, map_y) tuples, or sgm_remap) fill frame i's left / right
+    buffers from raw images on the batch's stream.  Returns the ticket."""
+    if len(remaps) != 2 * len(frames):
+        raise ValueError("need two remaps (left, right) per frame")
+    rj = []
+    for i, r in enumerate(remaps):
+        if not isinstance(r, sgm_remap):
+            f = frames[i // 2]
+            view = f.right if i & 1 else f.left
+            r = remap_job(r[0], r[1], r[2], view[:, :f.p.width])
+        rj.append(r)
+    arr = (sgm_frame * len(frames))(*[f.c() for f in frames])
+    rarr = (sgm_remap * len(rj))(*rj)
+    t = ctypes.c_uint64()
+    _check(lib().sgm_submit_rectify(ctx.handle, arr, rarr, len(frames), ctypes.byref(t)), "sgm_submit_rectify")
     return t.value
 
 

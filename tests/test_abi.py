@@ -48,6 +48,17 @@ def test_params_struct_layout_matches_header(sgm):
     assert ctypes.sizeof(sgm.sgm_frame) == 8 * 3 + 48 + 8 * 3
 
 
+def test_remap_struct_layout_matches_header(sgm):
+    # 4 pointers, 2 int64 pitches, 4 int32 sizes = 64 bytes
+    assert ctypes.sizeof(sgm.sgm_remap) == 64
+    assert sgm.sgm_remap.src_pitch.offset == 32 and sgm.sgm_remap.src_w.offset == 48
+    assert sgm.sgm_remap.h.offset == 60
+
+
+def test_rectify_rejects_null_context_without_a_gpu(sgm):
+    assert sgm.lib().sgm_rectify(None, None, 0, None) == sgm.SGM_EINVAL
+
+
 def good(sgm, **kw):
     p = sgm.Params(width=64, height=48, max_disp=64)
     for k, v in kw.items():
