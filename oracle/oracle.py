@@ -72,6 +72,7 @@ def _declare(L):
     L.oracle_lr_check.restype = None
     L.oracle_median.argtypes = [u16p, i, i, i, u16p]
     L.oracle_uv_maps.argtypes = [u16p, i, i, i, u16p, u16p]
+    L.oracle_uv_filter.argtypes = [u16p, i, i, i, i, i, i, i, i, i, u8p]
     L.oracle_set_threads.argtypes = [i]
     L.oracle_set_threads.restype = None
     L.oracle_threads.argtypes = []
@@ -192,6 +193,19 @@ def uv_maps(disp: np.ndarray, d_max: int):
     _check(lib().oracle_uv_maps(_p(disp, ctypes.c_uint16), w, h, d_max, _p(u, ctypes.c_uint16),
                                 _p(v, ctypes.c_uint16)), "uv_maps")
     return u, v
+
+
+def uv_filter(m: np.ndarray, thr: int, dil_r: int, blur_r: int, roi=None) -> np.ndarray:
+    """Threshold, dilation, binomial Gaussian and region of interest of one
+    U- or V-map (uint16 [rows][cols]) -> uint8 [rows][cols].  roi = (r0, r1,
+    c0, c1), default the whole map."""
+    m = np.ascontiguousarray(m, np.uint16)
+    rows, cols = m.shape
+    r0, r1, c0, c1 = roi if roi is not None else (0, rows, 0, cols)
+    out = np.zeros((rows, cols), np.uint8)
+    _check(lib().oracle_uv_filter(_p(m, ctypes.c_uint16), rows, cols, thr, dil_r, blur_r, r0, r1, c0, c1,
+                                  _p(out, ctypes.c_uint8)), "uv_filter")
+    return out
 
 
 def default_invalid(d_max: int) -> int:

@@ -325,6 +325,60 @@ int oracle_uv_maps(const uint16_t *disp, int w, int h, int d_max, uint16_t *umap
     return rc;
 }
 
+/* Obstacle-map filtering of a U- or V-map (section 3.2), in the paper's order:
+ *  1. threshold:  b = 255 where count >= thr, else 0 (a binary map);
+ *  2. dilation:   the maximum of b over the (2*dil_r+1)^2 square around each
+ *                 cell, cells outside the map ignored;
+ *  3. Gaussian:   the binomial kernel of size 2*blur_r+1 (weights
+ *                 C(2*blur_r, blur_r+k), total 4^blur_r per axis) applied along
+ *                 both axes with replicated borders, the 2-D sum rounded half up
+ *                 after division by 4^(2*blur_r);
+ *  4. region of interest: cells outside rows [roi_r0, roi_r1) and columns
+ *                 [roi_c0, roi_c1) set to 0.
+ * map: uint16 [rows][cols]; out: uint8 [rows][cols]. */
+static int64_t binom(int n, int k) {
+    int64_t c = 1;
+    for (int i = 1; i <= k; ++i) c = c * (n - k + i) / i;
+    return c;
+}
+
+int oracle_uv_filter(const uint16_t *map, int rows, int cols, int thr, int dil_r, int blur_r, int roi_r0,
+                     int roi_r1, int roi_c0, int roi_c1, uint8_t *out) {
+    if (rows < 1 || cols < 1 || dil_r < 0 || blur_r < 0 || blur_r > 4) return ORACLE_EINVAL;
+    int64_t n = (int64_t)rows * cols;
+    uint8_t *b = (uint8_t *)malloc((size_t)n), *dl = (uint8_t *)malloc((size_t)n);
+    if (!b || !dl) { free(b); free(dl); return ORACLE_ENOMEM; }
+    for (int64_t i = 0; i < n; ++i) b[i] = map[i] >= thr ? 255 : 0;
+    for (int y = 0; y < rows; ++y)
+        for (int x = 0; x < cols; ++x) {
+            uint8_t m = 0;
+            for (int dy = -dil_r; dy <= dil_r; ++dy)
+                for (int dx = -dil_r; dx <= dil_r; ++dx) {
+                    int yy = y + dy, xx = x + dx;
+                    if (yy < 0 || yy >= rows || xx < 0 || xx >= cols) continue;
+                    if (b[(int64_t)yy * cols + xx] > m) m = b[(int64_t)yy * cols + xx];
+                }
+            dl[(int64_t)y * cols + x] = m;
+        }
+    const int shift = 4 * blur_r;  /* log2 of 4^(2*blur_r) */
+    for (int y = 0; y < rows; ++y)
+        for (int x = 0; x < cols; ++x) {
+            int64_t acc = 0;
+            for (int i = -blur_r; i <= blur_r; ++i)
+                for (int j = -blur_r; j <= blur_r; ++j) {
+                    int yy = clampi(y + i, 0, rows - 1), xx = clampi(x + j, 0, cols - 1);
+                    acc += binom(2 * blur_r, blur_r + i) * binom(2 * blur_r, blur_r + j) *
+                           dl[(int64_t)yy * cols + xx];
+                }
+            int64_t g = shift ? (acc + ((int64_t)1 << (shift - 1))) >> shift : acc;
+            int in_roi = y >= roi_r0 && y < roi_r1 && x >= roi_c0 && x < roi_c1;
+            out[(int64_t)y * cols + x] = in_roi ? (uint8_t)g : 0;
+        }
+    free(b);
+    free(dl);
+    return ORACLE_OK;
+}
+
 /* Number of threads OpenMP would use (1 when built without OpenMP). */
 int oracle_threads(void) {
 #ifdef _OPENMP

@@ -148,3 +148,40 @@ def test_rectify_pins_catch_planted_mistake(tmp_path, restore_oracle, name, old,
     finally:
         O.load()
     assert caught, "no pin caught: " + name
+
+
+UV_FILTER_MUTANTS = [
+    ("threshold strict", "b[i] = map[i] >= thr ? 255 : 0;", "b[i] = map[i] > thr ? 255 : 0;"),
+    ("dilation one short on one side", "for (int dy = -dil_r; dy <= dil_r; ++dy)", "for (int dy = -dil_r; dy < dil_r; ++dy)"),
+    ("blur truncates", "(acc + ((int64_t)1 << (shift - 1))) >> shift", "acc >> shift"),
+    ("blur box weights", "binom(2 * blur_r, blur_r + i) * binom(2 * blur_r, blur_r + j)",
+     "binom(2 * blur_r, blur_r) * binom(2 * blur_r, blur_r)"),
+    ("blur border wraps to zero", "int yy = clampi(y + i, 0, rows - 1), xx = clampi(x + j, 0, cols - 1);",
+     "int yy = clampi(y + i, 0, rows - 1), xx = clampi(x + j, 0, cols - 1);\n"
+     "                    if (y + i < 0 || y + i >= rows) continue;"),
+    ("ROI end inclusive", "y < roi_r1 && x >= roi_c0", "y <= roi_r1 && x >= roi_c0"),
+]
+
+
+@pytest.mark.parametrize("name,old,new", UV_FILTER_MUTANTS, ids=[m[0] for m in UV_FILTER_MUTANTS])
+def test_uv_filter_pins_catch_planted_mistake(tmp_path, restore_oracle, name, old, new):
+    src = open(O.SRC).read()
+    assert src.count(old) == 1, name
+    c_path = tmp_path / "mutant.c"
+    so_path = tmp_path / "libmutant.so"
+    c_path.write_text(src.replace(old, new))
+    subprocess.check_call(["gcc", "-O1", "-std=c11", "-shared", "-fPIC", "-o", str(so_path), str(c_path)])
+    O.load(str(so_path))
+    caught = []
+    try:
+        for fn in (pins.test_uv_filter_threshold_is_inclusive, pins.test_uv_filter_dilation_matches_scipy,
+                   pins.test_uv_filter_gaussian_matches_scipy,
+                   pins.test_uv_filter_impulse_response_is_the_binomial_outer_product,
+                   pins.test_uv_filter_dilation_then_blur_and_region_of_interest):
+            try:
+                fn()
+            except (AssertionError, O.OracleError):
+                caught.append(fn.__name__)
+    finally:
+        O.load()
+    assert caught, "no pin caught: " + name

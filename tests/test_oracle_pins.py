@@ -463,3 +463,62 @@ def test_rectify_is_a_gather():
     want[ok] = src[my[ok].astype(int), mx[ok].astype(int)]
     assert (O.rectify(src, mx, my) == want).all()
     assert ok.mean() > 0.8
+
+
+# ------------------------------------------- U/V map filtering (section 3.2)
+
+def test_uv_filter_threshold_is_inclusive():
+    m = np.array([[0, 4, 5, 6], [65535, 5, 1, 0]], np.uint16)
+    assert O.uv_filter(m, 5, 0, 0).tolist() == [[0, 0, 255, 255], [255, 255, 0, 0]]
+
+
+def test_uv_filter_dilation_matches_scipy():
+    from scipy import ndimage
+    rng = np.random.default_rng(50)
+    m = rng.integers(0, 40, size=(23, 31)).astype(np.uint16)
+    b = m >= 36
+    for r in range(4):
+        want = ndimage.binary_dilation(b, structure=np.ones((2 * r + 1, 2 * r + 1), bool), border_value=0)
+        assert (O.uv_filter(m, 36, r, 0) == want.astype(np.uint8) * 255).all(), r
+
+
+def test_uv_filter_gaussian_matches_scipy():
+    # binomial weights from scipy.special.comb, replicated borders from
+    # ndimage's "nearest" mode, exact float64 sums, rounding half up
+    from scipy import ndimage, special
+    rng = np.random.default_rng(51)
+    m = rng.integers(0, 10, size=(19, 26)).astype(np.uint16)
+    b = (m >= 7).astype(np.float64) * 255
+    for g in range(1, 4):
+        w = special.comb(2 * g, np.arange(2 * g + 1), exact=False)
+        s = ndimage.correlate(b, np.outer(w, w), mode="nearest")
+        want = np.floor((s + 2.0 ** (4 * g - 1)) / 2.0 ** (4 * g)).astype(np.uint8)
+        assert (O.uv_filter(m, 7, 0, g) == want).all(), g
+
+
+def test_uv_filter_impulse_response_is_the_binomial_outer_product():
+    import math
+    m = np.zeros((11, 13), np.uint16)
+    m[5, 6] = 9
+    out = O.uv_filter(m, 1, 0, 2)
+    want = np.zeros((11, 13), np.uint8)
+    for i in range(-2, 3):
+        for j in range(-2, 3):
+            want[5 + i, 6 + j] = (255 * math.comb(4, 2 + i) * math.comb(4, 2 + j) + 128) // 256
+    assert (out == want).all()
+    assert out[5, 6] == 36 and out[5, 4] == 6 and out[3, 4] == 1   # 255*36/256, 255*6/256, 255/256
+
+
+def test_uv_filter_dilation_then_blur_and_region_of_interest():
+    m = np.zeros((9, 9), np.uint16)
+    m[4, 4] = 3
+    # dilation by 1 makes a 3x3 block; a [1,2,1] blur of it has a flat 255 centre
+    out = O.uv_filter(m, 3, 1, 1)
+    assert out[4, 4] == 255 and out[3, 3] == (255 * (4 + 2 + 2 + 1) + 8) // 16
+    assert out[0, 0] == 0 and out[4, 1] == 0
+    full = O.uv_filter(np.full((6, 8), 10, np.uint16), 5, 2, 3)
+    assert (full == 255).all()
+    roi = O.uv_filter(np.full((6, 8), 10, np.uint16), 5, 2, 3, roi=(1, 3, 2, 5))
+    want = np.zeros((6, 8), np.uint8)
+    want[1:3, 2:5] = 255
+    assert (roi == want).all()
