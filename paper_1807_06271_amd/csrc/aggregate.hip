@@ -18,6 +18,8 @@
 //
 // Internal volumes (costs and path costs) are stored [H][W][Dp] with the
 // disparity stride padded to Dp = 16*K; cells with d >= D are never read.
+#include <type_traits>
+
 #include "device_util.h"
 
 namespace sgmk {
@@ -74,9 +76,10 @@ __device__ __forceinline__ u16x2 padd_sat(u16x2 a, u16x2 b) { return __builtin_e
 
 constexpr uint32_t kInfPair = 0xFFFFFFFFu;
 
-// Cost words of one pixel for one lane: SRC kCost8 = K bytes (K/4 dwords) of
-// the padded uint8 volume; SRC kCost16 = K values of the caller's unpadded
-// uint16 volume, two per word.
+// Cost words of one pixel for one lane: K values of a padded volume (the
+// uint8 volume for SRC kCost8, four per word; the uint16 one for kCost16, two
+// per word).  Every lane reads its K cells with one vector load; cells with
+// d >= D hold unspecified values that the recurrence masks out.
 enum { kCost8 = 0, kCost16 = 1 };
 
 template <int K, int SRC>
@@ -86,29 +89,20 @@ struct CostWords {
 };
 
 template <int K, int SRC>
-__device__ __forceinline__ void load_cost(CostWords<K, SRC> &cw, const char *p, int dvalid) {
-  if (SRC == kCost8) {
-    if (K % 4 == 0) {  // dword-aligned (Dp and K are multiples of 4)
-      const U32N<K / 4> v = *reinterpret_cast<const U32N<K / 4> *>(p);
-#pragma unroll
-      for (int i = 0; i < K / 4; ++i) cw.w[i] = v.v[i];
-    } else {  // K = 2 or 6: 2-byte aligned, one 16-bit load per pair
-      const uint16_t *q = reinterpret_cast<const uint16_t *>(p);
-#pragma unroll
-      for (int i = 0; i < (K + 3) / 4; ++i) {
-        const uint32_t lo = q[2 * i];
-        const uint32_t hi = 2 * i + 1 < K / 2 ? (uint32_t)q[2 * i + 1] : 0u;
-        cw.w[i] = lo | hi << 16;
-      }
-    }
-  } else {
+__device__ __forceinline__ void load_cost(CostWords<K, SRC> &cw, const char *p) {
+  if (SRC == kCost8 && K % 4 != 0) {  // K = 2 or 6: 2-byte aligned, one 16-bit load per pair
     const uint16_t *q = reinterpret_cast<const uint16_t *>(p);
 #pragma unroll
-    for (int i = 0; i < K / 2; ++i) {
-      const uint32_t lo = 2 * i < dvalid ? q[2 * i] : 0u;
-      const uint32_t hi = 2 * i + 1 < dvalid ? q[2 * i + 1] : 0u;
+    for (int i = 0; i < (K + 3) / 4; ++i) {
+      const uint32_t lo = q[2 * i];
+      const uint32_t hi = 2 * i + 1 < K / 2 ? (uint32_t)q[2 * i + 1] : 0u;
       cw.w[i] = lo | hi << 16;
     }
+  } else {  // dword-aligned: Dp and K are even, the volumes 256-byte aligned
+    constexpr int N = CostWords<K, SRC>::N;
+    const U32N<N> v = *reinterpret_cast<const U32N<N> *>(p);
+#pragma unroll
+    for (int i = 0; i < N; ++i) cw.w[i] = v.v[i];
   }
 }
 
@@ -155,9 +149,12 @@ __device__ __forceinline__ void agg_wave(const AggJob &J, int slot, int wave_in_
   int sx = 0, sy = 0, len = 0;
   if (line < agg_lines(dir, W, H)) line_start(dir, line, W, H, sx, sy, len);
   // the wave runs until its longest scanline is done
-  int maxlen = __builtin_amdgcn_readlane(len, 0);
+  int maxlen = __builtin_amdgcn_readlane(len, 0), minlen = maxlen;
 #pragma unroll
-  for (int r = 1; r < SPW; ++r) maxlen = max(maxlen, __builtin_amdgcn_readlane(len, r * LPS));
+  for (int r = 1; r < SPW; ++r) {
+    maxlen = max(maxlen, __builtin_amdgcn_readlane(len, r * LPS));
+    minlen = min(minlen, __builtin_amdgcn_readlane(len, r * LPS));
+  }
   const int64_t step = (int64_t)kDirDy[dir] * W + kDirDx[dir];  // pixel index step (uniform)
   const int64_t pix0 = (int64_t)sy * W + sx;
   const int dbase = j * K;
@@ -177,7 +174,7 @@ __device__ __forceinline__ void agg_wave(const AggJob &J, int slot, int wave_in_
   // Addresses are a wave-uniform base that advances by a uniform step per
   // pixel plus a per-lane 32-bit offset that stays fixed along the scanline.
   constexpr int CB = SRC == kCost8 ? 1 : 2;  // bytes per cost element
-  const int cpp = SRC == kCost8 ? Dp : D;    // cost elements per pixel
+  const int cpp = Dp;                        // cost elements per pixel (padded)
   const char *cbase = SRC == kCost8 ? reinterpret_cast<const char *>(J.cost8)
                                     : reinterpret_cast<const char *>(J.cost16);
   const uint32_t coff = (uint32_t)((pix0 * cpp + dbase) * CB);
@@ -189,7 +186,7 @@ __device__ __forceinline__ void agg_wave(const AggJob &J, int slot, int wave_in_
   CostWords<K, SRC> ring[PF];
 #pragma unroll
   for (int s = 0; s < PF; ++s)
-    if (s < len) load_cost<K, SRC>(ring[s], cbase + s * cstep + coff, dvalid);
+    if (s < len) load_cost<K, SRC>(ring[s], cbase + s * cstep + coff);
 
   // A path's first pixel behaves as if its predecessor had all-zero path
   // costs: then every candidate is >= 0 = m, so L = C.
@@ -198,9 +195,12 @@ __device__ __forceinline__ void agg_wave(const AggJob &J, int slot, int wave_in_
   for (int i = 0; i < NP; ++i) Lp[i] = as_pair(padmask[i]);
   uint32_t mp = 0;  // the predecessor's minimum (uniform over the lane group)
 
-  auto pixel = [&](int i, CostWords<K, SRC> &rs) {
+  // GUARD = false: every scanline of the wave has pixels i and i + PF, so
+  // the load and the store need no per-lane test
+  auto pixel = [&](auto guard, int i, CostWords<K, SRC> &rs) {
+    constexpr bool GUARD = decltype(guard)::value;
     const CostWords<K, SRC> cw = rs;
-    if (i + PF < len) load_cost<K, SRC>(rs, cbase + (int64_t)(i + PF) * cstep + coff, dvalid);
+    if (!GUARD || i + PF < len) load_cost<K, SRC>(rs, cbase + (int64_t)(i + PF) * cstep + coff);
     // neighbour pairs: Nb[q] = (L[2q-1], L[2q]) for q = 0..NP, so that pair q
     // has its d-1 values in Nb[q] and its d+1 values in Nb[q+1]
     uint32_t prev, next;
@@ -235,7 +235,7 @@ __device__ __forceinline__ void agg_wave(const AggJob &J, int slot, int wave_in_
       if (PAD) v = as_pair(as_u32(v) | padmask[q]);
       Lc[q] = v;
     }
-    if (i < len) {
+    if (!GUARD || i < len) {
       char *o = obase + (int64_t)i * ostep + ooff;
       if (sizeof(LT) == 1) {
         if (K % 4 == 0) {
@@ -265,14 +265,20 @@ __device__ __forceinline__ void agg_wave(const AggJob &J, int slot, int wave_in_
     for (int q = 0; q < NP; ++q) Lp[q] = Lc[q];
   };
 
+  using Guarded = std::integral_constant<bool, true>;
+  using Unguarded = std::integral_constant<bool, false>;
   int i0 = 0;
+  for (; i0 + 2 * PF <= minlen; i0 += PF) {  // whole blocks, all scanlines long enough
+#pragma unroll
+    for (int s = 0; s < PF; ++s) pixel(Unguarded{}, i0 + s, ring[s]);
+  }
   for (; i0 + PF <= maxlen; i0 += PF) {  // whole blocks of PF pixels
 #pragma unroll
-    for (int s = 0; s < PF; ++s) pixel(i0 + s, ring[s]);
+    for (int s = 0; s < PF; ++s) pixel(Guarded{}, i0 + s, ring[s]);
   }
 #pragma unroll
   for (int s = 0; s < PF; ++s)  // remaining < PF pixels
-    if (i0 + s < maxlen) pixel(i0 + s, ring[s]);
+    if (i0 + s < maxlen) pixel(Guarded{}, i0 + s, ring[s]);
 }
 
 // Scanlines per wave of direction `dir` under a schedule whose horizontal
@@ -303,22 +309,12 @@ __global__ __launch_bounds__(256) void agg_kernel(JobTable<AggJob> t) {
 
 template <int K, int KH, int HLPS, int SRC, typename LT>
 static void launch_one(const JobTable<AggJob> &t, int waves, hipStream_t s) {
-  constexpr int PF = SRC == kCost8 ? 8 : 4;
+  constexpr int PF = SRC == kCost8 || K <= 8 ? 8 : 4;
   const int blocks = (waves + 3) / 4;
   bool pad = false;  // some frame's D is not a multiple of 16*K: mask the tail lanes
   for (int i = 0; i < t.n; ++i) pad |= t.j[i].D != 16 * K;
   if (pad) hipLaunchKernelGGL((agg_kernel<K, KH, HLPS, SRC, LT, PF, true>), dim3(blocks), dim3(256), 0, s, t);
   else hipLaunchKernelGGL((agg_kernel<K, KH, HLPS, SRC, LT, PF, false>), dim3(blocks), dim3(256), 0, s, t);
-}
-
-template <typename LT>
-static void launch_one_cost16(int K, const JobTable<AggJob> &t, int waves, hipStream_t s) {
-  switch (K) {
-    case 4: launch_one<4, 4, 16, kCost16, LT>(t, waves, s); break;
-    case 8: launch_one<8, 8, 16, kCost16, LT>(t, waves, s); break;
-    case 12: launch_one<12, 12, 16, kCost16, LT>(t, waves, s); break;
-    default: launch_one<16, 16, 16, kCost16, LT>(t, waves, s); break;
-  }
 }
 
 // Lanes per horizontal scanline available for a disparity width K (16 lanes):
@@ -347,7 +343,7 @@ static void launch_k(int K, int hlps, const JobTable<AggJob> &t, int waves, hipS
 
 void launch_aggregate(std::vector<AggJob> jobs, bool from_cost16, int K, int hlps, int lr_bytes,
                       hipStream_t s) {
-  if (from_cost16 || !agg_hlps_ok(K, hlps)) hlps = 16;
+  if (!agg_hlps_ok(K, hlps)) hlps = 16;
   for (auto &j : jobs) {
     int total = 0;
     for (int k = 0; k < j.ndirs; ++k) {
@@ -364,8 +360,8 @@ void launch_aggregate(std::vector<AggJob> jobs, bool from_cost16, int K, int hlp
           if (lr_bytes == 1) launch_k<kCost8, uint8_t>(K, hlps, t, waves, s);
           else launch_k<kCost8, uint16_t>(K, hlps, t, waves, s);
         } else {
-          if (lr_bytes == 1) launch_one_cost16<uint8_t>(K, t, waves, s);
-          else launch_one_cost16<uint16_t>(K, t, waves, s);
+          if (lr_bytes == 1) launch_k<kCost16, uint8_t>(K, hlps, t, waves, s);
+          else launch_k<kCost16, uint16_t>(K, hlps, t, waves, s);
         }
       });
 }
@@ -427,6 +423,20 @@ void launch_sum(std::vector<SumJob> jobs, int lr_bytes, hipStream_t s) {
         if (lr_bytes == 1) hipLaunchKernelGGL(sum_kernel<uint8_t>, dim3(blocks), dim3(256), 0, s, t);
         else hipLaunchKernelGGL(sum_kernel<uint16_t>, dim3(blocks), dim3(256), 0, s, t);
       });
+}
+
+__global__ __launch_bounds__(256) void pad16_kernel(const uint16_t *src, uint16_t *dst, int64_t px, int D,
+                                                    int Dp) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= px * Dp) return;
+  const int64_t pix = i / Dp;
+  const int d = (int)(i - pix * Dp);
+  dst[i] = d < D ? src[pix * D + d] : (uint16_t)0;
+}
+
+void launch_pad16(const uint16_t *src, uint16_t *dst, int64_t px, int D, int Dp, hipStream_t s) {
+  const int64_t n = px * Dp;
+  hipLaunchKernelGGL(pad16_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, src, dst, px, D, Dp);
 }
 
 }  // namespace sgmk

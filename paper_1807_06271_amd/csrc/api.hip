@@ -250,8 +250,8 @@ FramePlan plan_frame(const sgm_params &p, size_t base) {
   const size_t dp = (size_t)dp_of(p);
   FramePlan f;
   f.off_cost = base;
-  // Census costs: padded uint8 [H][W][Dp]; SAD costs: uint16 [H][W][D]
-  f.off_lr = f.off_cost + align256(is_sad(p) ? px * p.max_disp * 2 : px * dp);
+  // Census costs: padded uint8 [H][W][Dp]; SAD costs: padded uint16 [H][W][Dp]
+  f.off_lr = f.off_cost + align256(is_sad(p) ? px * dp * 2 : px * dp);
   f.off_dlr = f.off_lr + align256(px * dp * (size_t)popcount8(p.path_mask) * lr_bytes_of(p));
   f.bytes = f.off_dlr + align256(px * 2) - base;
   return f;
@@ -392,6 +392,7 @@ int enqueue_frames(const sgm_frame *fr, int n, const std::vector<FramePlan> &pla
       j.D = p.max_disp;
       j.ww = p.census_w;
       j.wh = p.census_h;
+      j.ostride = dp_of(p);
       sj.push_back(j);
       if (fr[i].umap) zj.push_back(ZeroJob{fr[i].umap, (int64_t)p.max_disp * p.width, 0});
       continue;
@@ -436,8 +437,7 @@ int enqueue_frames(const sgm_frame *fr, int n, const std::vector<FramePlan> &pla
       for (int i = 0; i < n; ++i) {
         const sgm_params &p = fr[i].p;
         if ((int)is_sad(p) != sad || k_of(p) != K || lr_bytes_of(p) != lb) continue;
-        if (!sad && hlps[i] != c_hlps) continue;
-        if (sad && c_hlps != 16) continue;  // SAD costs: 16-lane layout only
+        if (hlps[i] != c_hlps) continue;
         AggJob j{};
         if (sad) j.cost16 = reinterpret_cast<const uint16_t *>(mem + plans[i].off_cost);
         else j.cost8 = reinterpret_cast<const uint8_t *>(mem + plans[i].off_cost);
@@ -711,6 +711,7 @@ int sgm_cost_sad(sgm_ctx *c, const sgm_params *p, const uint8_t *left, const uin
   j.D = p->max_disp;
   j.ww = p->census_w;
   j.wh = p->census_h;
+  j.ostride = p->max_disp;
   launch_sad({j}, (hipStream_t)stream);
   return check_launch();
 }
@@ -729,10 +730,17 @@ int sgm_aggregate(sgm_ctx *c, const sgm_params *p, const uint16_t *cost, uint16_
   const int P = popcount8(p->path_mask);
   const int Dp = dp_of(*p);
   const int64_t px = (int64_t)p->width * p->height;
-  void *lr = nullptr;
-  CHECK(stage_scratch(c, (size_t)px * Dp * P * lb, s, &lr));
+  // scratch: the costs repacked with the padded disparity stride, then the
+  // P path-cost volumes
+  void *mem = nullptr;
+  const size_t cbytes = align256((size_t)px * Dp * 2);
+  CHECK(stage_scratch(c, cbytes + (size_t)px * Dp * P * lb, s, &mem));
+  uint16_t *cpad = reinterpret_cast<uint16_t *>(mem);
+  void *lr = reinterpret_cast<char *>(mem) + cbytes;
+  launch_pad16(cost, cpad, px, p->max_disp, Dp, s);
+  CHECK(check_launch());
   AggJob j{};
-  j.cost16 = cost;
+  j.cost16 = cpad;
   j.lr = lr;
   j.W = p->width;
   j.H = p->height;
@@ -741,7 +749,7 @@ int sgm_aggregate(sgm_ctx *c, const sgm_params *p, const uint16_t *cost, uint16_
   j.p1 = p->p1;
   j.p2 = p->p2;
   j.ndirs = fill_dirs(p->path_mask, j.dirs);
-  launch_aggregate({j}, true, k_of(*p), 16, lb, s);
+  launch_aggregate({j}, true, k_of(*p), resolve_hlps(c, *p), lb, s);
   CHECK(check_launch());
   SumJob sj{};
   sj.lr = lr;

@@ -215,26 +215,55 @@ void launch_census_cost(std::vector<FusedCostJob> jobs, hipStream_t s) {
 
 // ------------------------------------------------------------ SAD cost
 // One block per (row, 64-pixel chunk): the window rows of both views around
-// y are staged in LDS (clamped; the right view D - 1 pixels further left),
-// then each thread takes cells (x, d) of the chunk and sums |L - R| over the
-// window.  Output: the uint16 [H][W][D] volume.
+// y are staged in LDS (clamped; the right view D - 1 pixels further left).
+//
+// With u = x + dx the window column, the left pixel is clamp(u) and the right
+// one clamp(u - d): both depend on u and d only.  So with the column sums
+//   V_d(u) = sum_dy |I_L(clamp(u), y+dy) - I_R(clamp(u - d), y+dy)|
+// the cost is the sum of V_d over the ww columns u = x-rx .. x+rx, and one
+// thread per (d, run of kSadRun pixels) forms the run's column sums once and
+// slides the window over them.  Output: a uint16 [H][W][stride] volume
+// (stride D for the caller's volume, Dp for the padded internal one).
+constexpr int kSadRun = 16;
+
+__device__ __forceinline__ uint32_t absdiff(uint32_t a, uint32_t b) { return a > b ? a - b : b - a; }
 
 template <int WW, int WH>
-__device__ __forceinline__ uint32_t sad_fixed(const uint8_t *l, int sl, const uint8_t *r, int sr) {
+__device__ __forceinline__ void sad_run(const uint8_t *L, int sl, const uint8_t *R, int sr, int xs, int nrun,
+                                        int d, int D, int os, int x0, uint32_t cmax, uint16_t *out) {
+  uint32_t V[kSadRun + WW - 1];
+#pragma unroll
+  for (int c = 0; c < kSadRun + WW - 1; ++c) {
+    uint32_t v = 0;
+#pragma unroll
+    for (int dy = 0; dy < WH; ++dy) v += absdiff(L[dy * sl + xs + c], R[dy * sr + xs + c - d + D - 1]);
+    V[c] = v;
+  }
   uint32_t acc = 0;
 #pragma unroll
-  for (int dy = 0; dy < WH; ++dy)
+  for (int c = 0; c < WW - 1; ++c) acc += V[c];
 #pragma unroll
-    for (int dx = 0; dx < WW; ++dx) acc += (uint32_t)abs((int)l[dy * sl + dx] - (int)r[dy * sr + dx]);
-  return acc;
+  for (int k = 0; k < kSadRun; ++k) {
+    acc += V[k + WW - 1];
+    if (k < nrun) out[(int64_t)(xs + k) * os] = (uint16_t)(x0 + xs + k >= d ? acc : cmax);
+    acc -= V[k];
+  }
 }
 
-__device__ __forceinline__ uint32_t sad_any(const uint8_t *l, int sl, const uint8_t *r, int sr, int ww,
-                                            int wh) {
-  uint32_t acc = 0;
-  for (int dy = 0; dy < wh; ++dy)
-    for (int dx = 0; dx < ww; ++dx) acc += (uint32_t)abs((int)l[dy * sl + dx] - (int)r[dy * sr + dx]);
-  return acc;
+// Any window: the direct sum per cell.
+__device__ __forceinline__ void sad_run_any(const uint8_t *L, int sl, const uint8_t *R, int sr, int xs,
+                                            int nrun, int d, int D, int os, int x0, uint32_t cmax, int ww,
+                                            int wh, uint16_t *out) {
+  for (int k = 0; k < nrun; ++k) {
+    uint32_t acc = cmax;
+    if (x0 + xs + k >= d) {
+      acc = 0;
+      for (int dy = 0; dy < wh; ++dy)
+        for (int dx = 0; dx < ww; ++dx)
+          acc += absdiff(L[dy * sl + xs + k + dx], R[dy * sr + xs + k + dx - d + D - 1]);
+    }
+    out[(int64_t)(xs + k) * os] = (uint16_t)acc;
+  }
 }
 
 __global__ __launch_bounds__(256) void sad_kernel(JobTable<SadJob> t) {
@@ -247,9 +276,11 @@ __global__ __launch_bounds__(256) void sad_kernel(JobTable<SadJob> t) {
   const int W = J.W, H = J.H, D = J.D;
   const int nx = min(kCostChunk, W - x0);
   const int rx = J.ww / 2, ry = J.wh / 2;
-  const int sl = nx + 2 * rx;          // left: pixels x0 - rx .. x0 + nx - 1 + rx
-  const int sr = nx + D - 1 + 2 * rx;  // right: pixels x0 - D + 1 - rx ..
-  uint8_t *L = srows, *R = srows + J.wh * (kCostChunk + 2 * rx);
+  // rows of the full chunk width (clamped past the image), so that every
+  // column a run touches is staged
+  const int sl = kCostChunk + 2 * rx;          // left: pixels x0 - rx .. x0 + 63 + rx
+  const int sr = kCostChunk + D - 1 + 2 * rx;  // right: pixels x0 - D + 1 - rx ..
+  uint8_t *L = srows, *R = srows + J.wh * sl;
   for (int i = threadIdx.x; i < J.wh * sr; i += blockDim.x) {
     const int r = i / sr, c = i - r * sr;
     const int64_t gy = (int64_t)min(max(y - ry + r, 0), H - 1) * J.pitch;
@@ -258,21 +289,25 @@ __global__ __launch_bounds__(256) void sad_kernel(JobTable<SadJob> t) {
   }
   __syncthreads();
   const uint32_t cmax = (uint32_t)J.ww * J.wh * 255u;
-  uint16_t *out = J.out + ((int64_t)y * W + x0) * D;
-  for (int c = threadIdx.x; c < nx * D; c += blockDim.x) {
-    const int xi = c / D, d = c - xi * D;
-    uint32_t v = cmax;
-    if (x0 + xi >= d) {
-      // right pixel x - d + dx sits at column xi - d + (D - 1) + (dx + rx) of R
-      const uint8_t *l = L + xi, *r = R + xi - d + D - 1;
-      if (J.ww == 5 && J.wh == 5) v = sad_fixed<5, 5>(l, sl, r, sr);
-      else v = sad_any(l, sl, r, sr, J.ww, J.wh);
-    }
-    out[c] = (uint16_t)v;
+  const int os = J.ostride;
+  uint16_t *row = J.out + ((int64_t)y * W + x0) * os;
+  const int nruns = (nx + kSadRun - 1) / kSadRun;
+  // consecutive threads take consecutive d of one run: coalesced stores
+  for (int task = threadIdx.x; task < nruns * D; task += blockDim.x) {
+    const int run = task / D, d = task - run * D;
+    const int xs = run * kSadRun, nrun = min(kSadRun, nx - xs);
+    uint16_t *o = row + d;  // cell (x0 + xs + k, d) is o[(xs + k) * os]
+    if (J.ww == 5 && J.wh == 5) sad_run<5, 5>(L, sl, R, sr, xs, nrun, d, D, os, x0, cmax, o);
+    else if (J.ww == 3 && J.wh == 3) sad_run<3, 3>(L, sl, R, sr, xs, nrun, d, D, os, x0, cmax, o);
+    else if (J.ww == 7 && J.wh == 7) sad_run<7, 7>(L, sl, R, sr, xs, nrun, d, D, os, x0, cmax, o);
+    else if (J.ww == 9 && J.wh == 7) sad_run<9, 7>(L, sl, R, sr, xs, nrun, d, D, os, x0, cmax, o);
+    else sad_run_any(L, sl, R, sr, xs, nrun, d, D, os, x0, cmax, J.ww, J.wh, o);
   }
 }
 
 size_t sad_lds(int D, int ww, int wh) {
+  // each run reads up to kSadRun + ww - 1 columns from its start; the last
+  // run starts at kCostChunk - kSadRun, so rows of kCostChunk + ww - 1 suffice
   return (size_t)wh * (kCostChunk + ww - 1) + (size_t)wh * (kCostChunk + D - 1 + ww - 1);
 }
 

@@ -58,8 +58,9 @@ void launch_census_cost(std::vector<FusedCostJob> jobs, hipStream_t s);
 struct SadJob {
   const uint8_t *left, *right;
   int64_t pitch;
-  uint16_t *out;
+  uint16_t *out;       // [H][W][ostride], cells d < D written
   int W, H, D, ww, wh;
+  int ostride;         // D (the caller's volume) or Dp (internal, padded)
   int blk0, chunks_x;
 };
 // LDS bytes of the SAD kernel (window rows of both views for one chunk).
@@ -74,7 +75,7 @@ __host__ __device__ int agg_lines(int dir, int W, int H);
 
 struct AggJob {
   const uint8_t *cost8;          // internal padded uint8 costs [H][W][Dp], or
-  const uint16_t *cost16;        // the caller's uint16 costs [H][W][D]
+  const uint16_t *cost16;        // internal padded uint16 costs [H][W][Dp]
   void *lr;                      // path costs [P][H][W][Dp], uint8 or uint16
   int W, H, D, Dp, p1, p2;
   int ndirs;                     // P = number of active directions
@@ -87,6 +88,8 @@ struct AggJob {
 void launch_aggregate(std::vector<AggJob> jobs, bool from_cost16, int K, int hlps, int lr_bytes,
                       hipStream_t s);
 bool agg_hlps_ok(int K, int hlps);
+// Copy uint16 costs [px][D] into the padded layout [px][Dp] (pad cells 0).
+void launch_pad16(const uint16_t *src, uint16_t *dst, int64_t px, int D, int Dp, hipStream_t s);
 
 // S (unpadded uint16 [H][W][D]) = sum over the P slots of the padded path costs.
 struct SumJob {

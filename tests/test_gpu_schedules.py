@@ -18,6 +18,9 @@ SHAPES = [  # W, H, D, census, mask, p1, p2
     (131, 47, 60, (5, 5), 0x55, 8, 32),     # padded disparity rows
     (90, 25, 100, (9, 7), 0xFF, 20, 300),   # padded, 16-bit path costs
 ]
+# SAD costs (16-bit cost volume, 16-bit path costs): W, H, D, window, mask
+SAD_SHAPES = [(160, 40, 60, (5, 5), 0x55), (97, 21, 128, (5, 5), 0x0F), (70, 30, 64, (3, 3), 0xFF),
+              (50, 12, 200, (5, 5), 0x03)]
 
 
 @pytest.fixture(scope="module")
@@ -47,6 +50,23 @@ def test_every_lane_layout_matches_oracle(env, shape, h_lanes):
     assert_equal(to_np(f.disp), want["disp"], "disp h_lanes=%d" % h_lanes)
     assert_equal(to_np(f.umap), want["umap"], "umap")
     assert_equal(to_np(f.vmap), want["vmap"], "vmap")
+
+
+@pytest.mark.parametrize("shape", SAD_SHAPES)
+@pytest.mark.parametrize("h_lanes", [16, 32, 64])
+def test_every_lane_layout_matches_oracle_sad(env, shape, h_lanes):
+    torch, sgm, ctx = env
+    W, H, D, (cw, ch), mask = shape
+    announce("schedule sad", h_lanes, shape)
+    left, right, _ = synthetic.make_pair("kitti", W + D + mask + 1, W, H, D)
+    p = sgm.Params(width=W, height=H, max_disp=D, census_w=cw, census_h=ch, path_mask=mask, p1=200, p2=800,
+                   cost=sgm.COST_SAD, median=5)
+    sgm.sgm_set_schedule(ctx, p, h_lanes)
+    f = sgm.Frame.alloc(p, to_dev(torch, left), to_dev(torch, right))
+    sgm.sgm_wait(ctx, sgm.sgm_submit(ctx, [f]))
+    want = O.sgm(left, right, D, cw, ch, mask, 200, 800, True, 1, 5, p.inv(), cost_kind=1)
+    assert_equal(to_np(f.disp), want["disp"], "disp h_lanes=%d" % h_lanes)
+    assert_equal(to_np(f.umap), want["umap"], "umap")
 
 
 def test_autotune_keeps_a_valid_schedule(env):

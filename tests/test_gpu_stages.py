@@ -77,6 +77,24 @@ def test_aggregate_single_path(env, bit, W, H, D):
     assert_equal(to_np(out), O.aggregate(c, 1 << bit, 7, 90), "L_r dir %d" % bit)
 
 
+@pytest.mark.parametrize("D", [64, 60, 61])
+def test_aggregate_cost_at_odd_address(env, D):
+    # a uint16 cost volume starting 2 bytes past a 4-byte boundary: the
+    # aggregation must not take its vector cost loads there
+    torch, sgm, ctx = env
+    W, H = 45, 19
+    announce("aggregate odd address", W, H, D)
+    rng = np.random.default_rng(D)
+    p = params(sgm, W, H, D, path_mask=0xFF, p1=7, p2=90)
+    c = synthetic.random_cost(rng, H, W, D, p.nbits)
+    flat = torch.zeros(H * W * D + 1, dtype=torch.uint16, device="cuda")
+    flat[1:] = to_dev(torch, c).view(-1)
+    out = torch.empty((H, W, D), dtype=torch.uint16, device="cuda")
+    sgm.sgm_aggregate(ctx, p, flat[1:].view(H, W, D), out)
+    torch.cuda.synchronize()
+    assert_equal(to_np(out), O.aggregate(c, 0xFF, 7, 90), "S")
+
+
 @pytest.mark.parametrize("mask", [0x0F, 0xFF, 0x55, 0xF0, 0x03])
 @pytest.mark.parametrize("W,H,D,cw,ch,p1,p2", [
     (97, 61, 64, 5, 5, 10, 120),
