@@ -123,8 +123,37 @@ def bench_paper_settings(torch, sgm, ctx, synthetic, steps=100):
         res[name] = {"fps": steps / dt, "mdisp_evals_per_s": p.disp_evals() * steps / dt / 1e6,
                      "ms_per_frame": dt / steps * 1e3}
     res["census_rectified"] = bench_rectified(torch, sgm, ctx, synthetic, steps)
+    res["uv_filter"] = bench_uv_filter(torch, sgm, ctx, synthetic)
     sgm.sgm_profile(ctx, True)
     return res
+
+
+def bench_uv_filter(torch, sgm, ctx, synthetic, reps=200):
+    """Obstacle-map filtering (threshold, 3x3 dilation, 5x5 binomial blur,
+    region of interest) of one frame's U-map [60][640] and V-map [360][60]
+    in one launch, timed with events on the stream it runs on."""
+    L, R, _ = synthetic.make_pair("paper", 7)
+    p = sgm.Params(width=640, height=360, max_disp=60, census_w=5, census_h=5, path_mask=sgm.PATHS_PAPER4,
+                   lr_check=1, median=5, p1=8, p2=32)
+    f = sgm.Frame.alloc(p, torch.from_numpy(L).cuda(), torch.from_numpy(R).cuda())
+    sgm.sgm_wait(ctx, sgm.sgm_submit(ctx, [f]))
+    u_out = torch.empty((60, 640), dtype=torch.uint8, device="cuda")
+    v_out = torch.empty((360, 60), dtype=torch.uint8, device="cuda")
+    jobs = [sgm.filter_job(f.umap, u_out, 20, 1, 2, (1, 60, 0, 640)),
+            sgm.filter_job(f.vmap, v_out, 30, 1, 2, (120, 360, 0, 60))]
+    stream = torch.cuda.current_stream()
+    for _ in range(10):
+        sgm.uv_filter(ctx, jobs, stream)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        sgm.uv_filter(ctx, jobs, stream)
+    e1.record(stream)
+    e1.synchronize()
+    us = e0.elapsed_time(e1) * 1e3 / reps
+    cells = 60 * 640 + 360 * 60
+    return {"us_per_frame": us, "cells": cells, "algorithmic_bytes": 3 * cells,
+            "gb_per_s": 3 * cells / (us * 1e-6) / 1e9}
 
 
 def bench_rectified(torch, sgm, ctx, synthetic, steps):

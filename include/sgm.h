@@ -198,6 +198,37 @@ int sgm_disparity(sgm_ctx *ctx, const sgm_params *p, const uint16_t *aggr, uint1
 int uv_maps(sgm_ctx *ctx, const sgm_params *p, const uint16_t *disp, uint16_t *umap,
             uint16_t *vmap, void *stream);
 
+/* Obstacle-map filtering of one U- or V-map (section 3.2), in the paper's
+ * order; the paper names the steps but gives no sizes, so they are inputs:
+ *  1. threshold:  a cell is an obstacle cell when its count >= threshold
+ *                 (binary value 255, else 0);
+ *  2. dilation:   the maximum over the (2*dilate_r+1)^2 square around each
+ *                 cell, cells outside the map ignored;
+ *  3. Gaussian:   the binomial kernel of size 2*blur_r+1 (weights
+ *                 C(2*blur_r, blur_r+k)) along both axes, borders replicated,
+ *                 the exact 2-D sum divided by 4^(2*blur_r) and rounded half up;
+ *  4. region of interest: cells outside rows [roi_r0, roi_r1) and columns
+ *                 [roi_c0, roi_c1) become 0 (e.g. V-map rows above the horizon).
+ *   map: device uint16 [rows][cols] (a U-map [D][W] or a V-map [H][D]);
+ *   out: device uint8  [rows][cols], must not overlap map.
+ * Limits: 1 <= rows, cols <= 16384; dilate_r <= 8; blur_r <= 4;
+ * 0 <= roi_r0 <= roi_r1 <= rows; 0 <= roi_c0 <= roi_c1 <= cols. */
+typedef struct {
+  const uint16_t *map;
+  uint8_t *out;
+  int32_t rows, cols;
+  uint16_t threshold;
+  uint16_t dilate_r;
+  uint16_t blur_r;
+  uint16_t reserved;  /* must be 0 */
+  int32_t roi_r0, roi_r1, roi_c0, roi_c1;
+} uv_filter_job;
+
+/* Filter n >= 0 maps with one kernel launch per 24 maps, enqueued on
+ * `stream`.  Every job is checked before anything is enqueued; SGM_EINVAL
+ * names the first bad job.  Uses no scratch memory. */
+int uv_filter(sgm_ctx *ctx, const uv_filter_job *jobs, int n, void *stream);
+
 /* One frame of the whole path for sgm_submit.  left/right: device uint8
  * [H][pitch] sharing one pitch; disp, umap, vmap: device outputs as above
  * (umap 4-byte aligned; umap and vmap may both be NULL to skip the

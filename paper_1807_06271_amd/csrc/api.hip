@@ -915,6 +915,48 @@ static int submit_impl(sgm_ctx *c, const sgm_frame *frames, const sgm_remap *rem
   return SGM_OK;
 }
 
+int uv_filter(sgm_ctx *c, const uv_filter_job *jobs, int n, void *stream) {
+  if (!c) return fail(SGM_EINVAL, "ctx is null");
+  if (n < 0) return fail(SGM_EINVAL, "n = %d < 0", n);
+  if (n > 0 && !jobs) return fail(SGM_EINVAL, "jobs is null");
+  std::lock_guard<std::mutex> lk(c->mu);
+  DeviceGuard g(c->device);
+  std::vector<UVFilterJob> fj(n);
+  for (int i = 0; i < n; ++i) {
+    const uv_filter_job &q = jobs[i];
+    if (q.rows < 1 || q.cols < 1 || q.rows > 16384 || q.cols > 16384)
+      return fail(SGM_EINVAL, "job %d: map size %d x %d outside 1..16384", i, q.rows, q.cols);
+    if (q.dilate_r > kUVFMaxDil) return fail(SGM_EINVAL, "job %d: dilate_r %u > %d", i, q.dilate_r, kUVFMaxDil);
+    if (q.blur_r > kUVFMaxBlur) return fail(SGM_EINVAL, "job %d: blur_r %u > %d", i, q.blur_r, kUVFMaxBlur);
+    if (q.reserved) return fail(SGM_EINVAL, "job %d: reserved must be 0", i);
+    if (q.roi_r0 < 0 || q.roi_r0 > q.roi_r1 || q.roi_r1 > q.rows || q.roi_c0 < 0 || q.roi_c0 > q.roi_c1 ||
+        q.roi_c1 > q.cols)
+      return fail(SGM_EINVAL, "job %d: region of interest rows [%d,%d) cols [%d,%d) outside the map", i,
+                  q.roi_r0, q.roi_r1, q.roi_c0, q.roi_c1);
+    char name[32];
+    snprintf(name, sizeof(name), "job %d: map", i);
+    CHECK(check_dev_ptr(q.map, c->device, name));
+    snprintf(name, sizeof(name), "job %d: out", i);
+    CHECK(check_dev_ptr(q.out, c->device, name));
+    UVFilterJob &j = fj[i];
+    j = UVFilterJob{};
+    j.map = q.map;
+    j.out = q.out;
+    j.rows = q.rows;
+    j.cols = q.cols;
+    j.thr = q.threshold;
+    j.dil = q.dilate_r;
+    j.blur = q.blur_r;
+    j.r0 = q.roi_r0;
+    j.r1 = q.roi_r1;
+    j.c0 = q.roi_c0;
+    j.c1 = q.roi_c1;
+  }
+  if (fj.empty()) return SGM_OK;
+  launch_uv_filter(fj, (hipStream_t)stream);
+  return check_launch();
+}
+
 int sgm_submit(sgm_ctx *c, const sgm_frame *frames, int n, uint64_t *ticket) {
   return submit_impl(c, frames, nullptr, n, ticket);
 }

@@ -145,6 +145,19 @@ struct ZeroJob {
 };
 void launch_zero(std::vector<ZeroJob> jobs, hipStream_t s);
 
+// -------------------------------------------------------- U/V filtering
+// Threshold, dilation, binomial Gaussian and region of interest of one map
+// (section 3.2), one block per 64 x 16 output tile.
+constexpr int kUVFMaxDil = 8, kUVFMaxBlur = 4;
+struct UVFilterJob {
+  const uint16_t *map;
+  uint8_t *out;
+  int rows, cols, thr, dil, blur;
+  int r0, r1, c0, c1;
+  int tiles_x, blk0;
+};
+void launch_uv_filter(std::vector<UVFilterJob> jobs, hipStream_t s);
+
 // ------------------------------------------------------------ rectify
 // Gather through integer remap maps (section 3.1.1).  Pixels are taken in
 // groups of kRectPx consecutive entries of the [h][w] maps.

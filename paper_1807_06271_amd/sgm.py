@@ -38,7 +38,7 @@ EXPORTS = ["sgm_validate", "sgm_create", "sgm_destroy", "sgm_last_error", "sgm_c
            "sgm_disparity", "uv_maps", "sgm_submit", "sgm_poll", "sgm_wait", "sgm_memory", "sgm_profile",
            "sgm_profile_read", "sgm_set_streams", "sgm_set_schedule", "sgm_get_schedule",
            "sgm_autotune", "sgm_set_graphs", "sgm_graph_stats", "sgm_rectify",
-           "sgm_submit_rectify"]
+           "sgm_submit_rectify", "uv_filter"]
 STAGES = ["census", "aggregate", "disparity", "median", "uv", "rectify"]
 
 
@@ -66,6 +66,13 @@ class sgm_remap(ctypes.Structure):
                 ("out", ctypes.c_void_p), ("src_pitch", ctypes.c_int64), ("out_pitch", ctypes.c_int64),
                 ("src_w", ctypes.c_int32), ("src_h", ctypes.c_int32), ("w", ctypes.c_int32),
                 ("h", ctypes.c_int32)]
+
+
+class uv_filter_job(ctypes.Structure):
+    _fields_ = [("map", ctypes.c_void_p), ("out", ctypes.c_void_p), ("rows", ctypes.c_int32),
+                ("cols", ctypes.c_int32), ("threshold", ctypes.c_uint16), ("dilate_r", ctypes.c_uint16),
+                ("blur_r", ctypes.c_uint16), ("reserved", ctypes.c_uint16), ("roi_r0", ctypes.c_int32),
+                ("roi_r1", ctypes.c_int32), ("roi_c0", ctypes.c_int32), ("roi_c1", ctypes.c_int32)]
 
 
 class sgm_frame(ctypes.Structure):
@@ -136,6 +143,7 @@ def lib():
         L.sgm_last_error.restype = ctypes.c_char_p
         L.sgm_census.argtypes = [vp, P(sgm_params), vp, ctypes.c_int64, vp, vp]
         L.sgm_rectify.argtypes = [vp, P(sgm_remap), i32, vp]
+        L.uv_filter.argtypes = [vp, P(uv_filter_job), i32, vp]
         L.sgm_submit_rectify.argtypes = [vp, P(sgm_frame), P(sgm_remap), i32, P(ctypes.c_uint64)]
         L.sgm_cost.argtypes = [vp, P(sgm_params), vp, vp, vp, vp]
         L.sgm_cost_sad.argtypes = [vp, P(sgm_params), vp, vp, ctypes.c_int64, vp, vp]
@@ -233,7 +241,8 @@ def _rows(t, name, dtype):
 def remap_job(src, map_x, map_y, out) -> sgm_remap:
     """One sgm_remap from tensors: src uint8 [src_h][src_w] (row pitch from its
     stride), map_x/map_y contiguous uint16 [h][w], out uint8 [h][w] (pitch from
-    its stride)."""
+    its stride).  The struct holds raw device pointers: keep the tensors alive
+    until the work is done."""
     _rows(src, "src", torch.uint8)
     _rows(out, "out", torch.uint8)
     _need(map_x, tuple(out.shape), torch.uint16, "map_x")
@@ -248,6 +257,26 @@ def sgm_rectify(ctx: Context, jobs, stream=None):
     rj = [j if isinstance(j, sgm_remap) else remap_job(*j) for j in jobs]
     arr = (sgm_remap * max(len(rj), 1))(*rj)
     _check(lib().sgm_rectify(ctx.handle, arr, len(rj), _stream(stream)), "sgm_rectify")
+
+
+def filter_job(m, out, threshold: int, dilate_r: int = 1, blur_r: int = 2, roi=None) -> uv_filter_job:
+    """One uv_filter_job: m uint16 [rows][cols] (a U- or V-map), out uint8
+    [rows][cols]; roi = (r0, r1, c0, c1), default the whole map.  The struct
+    holds raw device pointers: keep m and out alive until the work is done."""
+    _need(out, tuple(m.shape), torch.uint8, "out")
+    if m.dtype != torch.uint16 or m.dim() != 2:
+        raise ValueError("map must be uint16 [rows][cols]")
+    rows, cols = m.shape
+    r0, r1, c0, c1 = roi if roi is not None else (0, rows, 0, cols)
+    return uv_filter_job(_ptr(m), _ptr(out), rows, cols, threshold, dilate_r, blur_r, 0, r0, r1, c0, c1)
+
+
+def uv_filter(ctx: Context, jobs, stream=None):
+    """Threshold, dilate, blur and crop every map of `jobs` (uv_filter_job or
+    (map, out, threshold, dilate_r, blur_r[, roi]) tuples) in one launch."""
+    fj = [j if isinstance(j, uv_filter_job) else filter_job(*j) for j in jobs]
+    arr = (uv_filter_job * max(len(fj), 1))(*fj)
+    _check(lib().uv_filter(ctx.handle, arr, len(fj), _stream(stream)), "uv_filter")
 
 
 def sgm_census(ctx: Context, p: Params, img, census, stream=None):

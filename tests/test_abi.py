@@ -55,8 +55,15 @@ def test_remap_struct_layout_matches_header(sgm):
     assert sgm.sgm_remap.h.offset == 60
 
 
+def test_uv_filter_job_layout_matches_header(sgm):
+    # 2 pointers, 2 int32, 4 uint16, 4 int32 = 48 bytes
+    assert ctypes.sizeof(sgm.uv_filter_job) == 48
+    assert sgm.uv_filter_job.threshold.offset == 24 and sgm.uv_filter_job.roi_r0.offset == 32
+
+
 def test_rectify_rejects_null_context_without_a_gpu(sgm):
     assert sgm.lib().sgm_rectify(None, None, 0, None) == sgm.SGM_EINVAL
+    assert sgm.lib().uv_filter(None, None, 0, None) == sgm.SGM_EINVAL
 
 
 def good(sgm, **kw):
