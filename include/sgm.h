@@ -292,7 +292,15 @@ typedef struct {
    * 64; 0 = the library's default for the shape.  Wider rows shorten the
    * dependent chain along the long image rows; other paths use 16 lanes. */
   int32_t h_lanes;
-  int32_t reserved[3]; /* must be 0 */
+  /* 1: run eligible frames of the shape through the single-pass row sweep
+   * (the paper's forward path set computed in one top-down pass per frame,
+   * section 3.1.3, figure 2: one block per frame, nothing but the disparity
+   * maps written).  Eligible: Census cost with N_b <= 32, max_disp <= 64,
+   * path_mask within SGM_PATHS_PAPER4, N_b + p2 <= 255; other frames ignore
+   * the flag.  Pays off on batches of many frames; 0 (default) = the
+   * per-direction kernels. */
+  int32_t sweep;
+  int32_t reserved[2]; /* must be 0 */
 } sgm_schedule;
 
 /* Set the schedule used by sgm_submit for frames of the shape of `shape`

@@ -245,11 +245,19 @@ struct FramePlan {
 
 // Scratch of one frame of a batch: the padded uint8 cost volume, the P
 // padded path-cost volumes and the LR-checked map before the median.
-FramePlan plan_frame(const sgm_params &p, size_t base) {
+FramePlan plan_frame(const sgm_params &p, size_t base, bool sweep) {
   const size_t px = (size_t)p.width * p.height;
   const size_t dp = (size_t)dp_of(p);
   FramePlan f;
   f.off_cost = base;
+  if (sweep) {
+    // Census codes of both views; D_L and D_R; the band-boundary carry rows;
+    // the LR-checked map before the median
+    f.off_lr = f.off_cost + align256(2 * px * 8);
+    f.off_dlr = f.off_lr + align256(2 * px * 2) + align256((size_t)2 * p.width * kSweepCarry);
+    f.bytes = f.off_dlr + align256(px * 2) - base;
+    return f;
+  }
   // Census costs: padded uint8 [H][W][Dp]; SAD costs: padded uint16 [H][W][Dp]
   f.off_lr = f.off_cost + align256(is_sad(p) ? px * dp * 2 : px * dp);
   f.off_dlr = f.off_lr + align256(px * dp * (size_t)popcount8(p.path_mask) * lr_bytes_of(p));
@@ -281,8 +289,20 @@ int resolve_hlps(const sgm_ctx *c, const sgm_params &p) {
   return 16;
 }
 
-// Everything that decides a batch's launch sequence (kernels, grids, LDS):
-// the frames' parameters and schedules, in order.
+// Frames the single-pass sweep handles: Census costs with codes of at most
+// 32 bits, at most 64 disparities (16 lanes x 4), only forward paths, and
+// path costs that fit 8 bits.
+bool sweep_ok(const sgm_params &p) {
+  return !is_sad(p) && nbits_of(p) <= 32 && p.max_disp <= 64 && (p.path_mask & ~0x55u) == 0 &&
+         lr_bytes_of(p) == 1;
+}
+
+int resolve_sweep(const sgm_ctx *c, const sgm_params &p) {
+  auto it = c->tuned.find(shape_key(p));
+  const int want = it != c->tuned.end() ? it->second.sweep : c->dflt.sweep;
+  return want && sweep_ok(p) ? 1 : 0;
+}
+
 // Check one sgm_remap (sizes, pitches, device pointers) and build its job.
 int check_remap(const sgm_remap &r, int i, int dev, RemapJob *out) {
   if (r.w < 1 || r.h < 1 || r.w > 16384 || r.h > 16384)
@@ -314,8 +334,10 @@ int check_remap(const sgm_remap &r, int i, int dev, RemapJob *out) {
   return SGM_OK;
 }
 
+// Everything that decides a batch's launch sequence (kernels, grids, LDS):
+// the frames' parameters and schedules, in order.
 std::string composition_key(const sgm_frame *fr, int n, const std::vector<int> &hlps,
-                            const std::vector<RemapJob> &rect) {
+                            const std::vector<int> &sweep, const std::vector<RemapJob> &rect) {
   std::string k;
   char buf[160];
   for (const RemapJob &r : rect) {
@@ -326,7 +348,7 @@ std::string composition_key(const sgm_frame *fr, int n, const std::vector<int> &
     const sgm_params &p = fr[i].p;
     snprintf(buf, sizeof buf, "%d,%d,%d,%d,%d,%u,%u,%u,%d,%d,%d,%u,%d,%d;", p.width, p.height,
              p.max_disp, p.census_w, p.census_h, p.path_mask, p.p1, p.p2, p.lr_check, p.lr_max_diff,
-             p.median, p.invalid, hlps[i], fr[i].umap ? 1 : 0);
+             p.median, p.invalid, hlps[i] | sweep[i] << 8, fr[i].umap ? 1 : 0);
     k += buf;
   }
   return k;
@@ -336,7 +358,8 @@ int check_schedule(const sgm_schedule *s) {
   if (!s) return fail(SGM_EINVAL, "schedule is null");
   if (s->h_lanes != 0 && s->h_lanes != 16 && s->h_lanes != 32 && s->h_lanes != 64)
     return fail(SGM_EINVAL, "h_lanes must be 0, 16, 32 or 64 (got %d)", s->h_lanes);
-  if (s->reserved[0] || s->reserved[1] || s->reserved[2]) return fail(SGM_EINVAL, "reserved must be 0");
+  if (s->sweep != 0 && s->sweep != 1) return fail(SGM_EINVAL, "sweep must be 0 or 1 (got %d)", s->sweep);
+  if (s->reserved[0] || s->reserved[1]) return fail(SGM_EINVAL, "reserved must be 0");
   return SGM_OK;
 }
 
@@ -363,8 +386,9 @@ struct StageMark {
 };
 
 int enqueue_frames(const sgm_frame *fr, int n, const std::vector<FramePlan> &plans,
-                   const std::vector<int> &hlps, const std::vector<RemapJob> &rect, char *mem,
-                   hipStream_t s, std::vector<StageEvents> *prof) {
+                   const std::vector<int> &hlps, const std::vector<int> &sweep,
+                   const std::vector<RemapJob> &rect, char *mem, hipStream_t s,
+                   std::vector<StageEvents> *prof) {
   StageMark mark{prof, s};
   // rectification of the raw views into the frames' input buffers (one
   // launch for every view of the batch)
@@ -379,8 +403,25 @@ int enqueue_frames(const sgm_frame *fr, int n, const std::vector<FramePlan> &pla
   std::vector<FusedCostJob> fj;
   std::vector<SadJob> sj;
   std::vector<ZeroJob> zj;
+  std::vector<CensusJob> cj;  // sweep frames: Census codes of both views
   for (int i = 0; i < n; ++i) {
     const sgm_params &p = fr[i].p;
+    if (sweep[i]) {
+      const size_t px = (size_t)p.width * p.height;
+      for (int v = 0; v < 2; ++v) {
+        CensusJob j{};
+        j.img = v ? fr[i].right : fr[i].left;
+        j.pitch = fr[i].pitch;
+        j.out = reinterpret_cast<uint64_t *>(mem + plans[i].off_cost) + v * px;
+        j.W = p.width;
+        j.H = p.height;
+        j.cw = p.census_w;
+        j.ch = p.census_h;
+        cj.push_back(j);
+      }
+      if (fr[i].umap) zj.push_back(ZeroJob{fr[i].umap, (int64_t)p.max_disp * p.width, 0});
+      continue;
+    }
     if (is_sad(p)) {
       SadJob j{};
       j.left = fr[i].left;
@@ -421,9 +462,18 @@ int enqueue_frames(const sgm_frame *fr, int n, const std::vector<FramePlan> &pla
   }
   if (!sj.empty()) {
     launch_sad(sj, s);
+    CHECK(check_launch());
+    ++launches;
+  }
+  if (!cj.empty()) {
+    launch_census(cj, s);
+    CHECK(check_launch());
+    ++launches;
+  }
+  if (!zj.empty()) {  // U-maps of frames whose cost kernel does not clear them
     launch_zero(zj, s);
     CHECK(check_launch());
-    launches += 2;
+    ++launches;
   }
   CHECK(mark.end(launches));
   // aggregation, one launch per (disparities per lane, path-cost width)
@@ -436,7 +486,7 @@ int enqueue_frames(const sgm_frame *fr, int n, const std::vector<FramePlan> &pla
       std::vector<AggJob> aj;
       for (int i = 0; i < n; ++i) {
         const sgm_params &p = fr[i].p;
-        if ((int)is_sad(p) != sad || k_of(p) != K || lr_bytes_of(p) != lb) continue;
+        if (sweep[i] || (int)is_sad(p) != sad || k_of(p) != K || lr_bytes_of(p) != lb) continue;
         if (hlps[i] != c_hlps) continue;
         AggJob j{};
         if (sad) j.cost16 = reinterpret_cast<const uint16_t *>(mem + plans[i].off_cost);
@@ -457,14 +507,64 @@ int enqueue_frames(const sgm_frame *fr, int n, const std::vector<FramePlan> &pla
         ++groups;
       }
     }
+  {
+    std::vector<SweepJob> wj;
+    for (int i = 0; i < n; ++i) {
+      if (!sweep[i]) continue;
+      const sgm_params &p = fr[i].p;
+      const size_t px = (size_t)p.width * p.height;
+      SweepJob j{};
+      j.cl = reinterpret_cast<const uint64_t *>(mem + plans[i].off_cost);
+      j.cr = j.cl + px;
+      j.dl = reinterpret_cast<uint16_t *>(mem + plans[i].off_lr);
+      j.dr = j.dl + px;
+      j.carry = reinterpret_cast<uint8_t *>(mem + plans[i].off_lr + align256(2 * px * 2));
+      j.W = p.width;
+      j.H = p.height;
+      j.D = p.max_disp;
+      j.nbits = nbits_of(p);
+      j.p1 = p.p1;
+      j.p2 = p.p2;
+      j.mask = p.path_mask;
+      wj.push_back(j);
+    }
+    if (!wj.empty()) {
+      launch_sweep(wj, s);
+      CHECK(check_launch());
+      ++groups;
+    }
+  }
   CHECK(mark.end(groups));
   CHECK(mark.begin(SGM_STAGE_DISPARITY));
   groups = 0;
+  {
+    std::vector<LRJob> lj;
+    for (int i = 0; i < n; ++i) {
+      if (!sweep[i]) continue;
+      const sgm_params &p = fr[i].p;
+      const size_t px = (size_t)p.width * p.height;
+      LRJob j{};
+      j.dl = reinterpret_cast<const uint16_t *>(mem + plans[i].off_lr);
+      j.dr = j.dl + px;
+      j.out = p.median ? reinterpret_cast<uint16_t *>(mem + plans[i].off_dlr) : fr[i].disp;
+      j.W = p.width;
+      j.H = p.height;
+      j.lr_check = p.lr_check;
+      j.max_diff = p.lr_max_diff;
+      j.invalid = p.invalid;
+      lj.push_back(j);
+    }
+    if (!lj.empty()) {
+      launch_lr(lj, s);
+      CHECK(check_launch());
+      ++groups;
+    }
+  }
   for (int lb = 1; lb <= 2; ++lb) {
     std::vector<DispJob> dj;
     for (int i = 0; i < n; ++i) {
       const sgm_params &p = fr[i].p;
-      if (lr_bytes_of(p) != lb) continue;
+      if (sweep[i] || lr_bytes_of(p) != lb) continue;
       DispJob j{};
       j.lr = mem + plans[i].off_lr;
       j.P = popcount8(p.path_mask);
@@ -538,10 +638,10 @@ void destroy_events(Batch &b) {
 // the cached executable graph of the same composition (updated with this
 // batch's buffers), instantiating one on a miss.
 int enqueue_graph(sgm_ctx *c, const sgm_frame *fr, int n, const std::vector<FramePlan> &plans,
-                  const std::vector<int> &hlps, const std::vector<RemapJob> &rect, char *mem,
-                  hipStream_t s) {
+                  const std::vector<int> &hlps, const std::vector<int> &sweep,
+                  const std::vector<RemapJob> &rect, char *mem, hipStream_t s) {
   HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed));
-  int rc = enqueue_frames(fr, n, plans, hlps, rect, mem, s, nullptr);
+  int rc = enqueue_frames(fr, n, plans, hlps, sweep, rect, mem, s, nullptr);
   hipGraph_t g = nullptr;
   hipError_t e = hipStreamEndCapture(s, &g);
   if (rc != SGM_OK) {
@@ -549,7 +649,7 @@ int enqueue_graph(sgm_ctx *c, const sgm_frame *fr, int n, const std::vector<Fram
     return rc;
   }
   if (e != hipSuccess) return fail(SGM_EHIP, "graph capture: %s", hipGetErrorString(e));
-  const std::string key = composition_key(fr, n, hlps, rect);
+  const std::string key = composition_key(fr, n, hlps, sweep, rect);
   auto it = c->graph_cache.find(key);
   hipGraphExec_t ex = nullptr;
   if (it != c->graph_cache.end()) {
@@ -829,18 +929,23 @@ static int submit_impl(sgm_ctx *c, const sgm_frame *frames, const sgm_remap *rem
                        uint64_t *ticket) {
   if (!c) return fail(SGM_EINVAL, "ctx is null");
   if (!frames || n < 1 || !ticket) return fail(SGM_EINVAL, "need frames, n >= 1 and a ticket pointer");
-  std::vector<FramePlan> plans(n);
-  size_t total = 0;
   for (int i = 0; i < n; ++i) {
     int rc = validate(&frames[i].p);
     if (rc) return fail(rc, "frame %d: %s", i, g_err.c_str());
     if (frames[i].pitch < frames[i].p.width) return fail(SGM_EINVAL, "frame %d: pitch < width", i);
     if ((frames[i].umap == nullptr) != (frames[i].vmap == nullptr))
       return fail(SGM_EINVAL, "frame %d: give both umap and vmap, or neither", i);
-    plans[i] = plan_frame(frames[i].p, total);
-    total += plans[i].bytes;
   }
   std::lock_guard<std::mutex> lk(c->mu);
+  std::vector<int> hl(n), sw(n);
+  std::vector<FramePlan> plans(n);
+  size_t total = 0;
+  for (int i = 0; i < n; ++i) {
+    hl[i] = resolve_hlps(c, frames[i].p);
+    sw[i] = resolve_sweep(c, frames[i].p);
+    plans[i] = plan_frame(frames[i].p, total, sw[i] != 0);
+    total += plans[i].bytes;
+  }
   DeviceGuard g(c->device);
   for (int i = 0; i < n; ++i) {
     CHECK(check_dev_ptr(frames[i].left, c->device, "left"));
@@ -892,13 +997,11 @@ static int submit_impl(sgm_ctx *c, const sgm_frame *frames, const sgm_remap *rem
   b.stream = c->next_stream;
   c->next_stream = (c->next_stream + 1) % c->nstreams;
   hipStream_t s = c->streams[b.stream];
-  std::vector<int> hl(n);
-  for (int i = 0; i < n; ++i) hl[i] = resolve_hlps(c, frames[i].p);
   int rc = SGM_OK;
   if (c->graphs && !c->profiling) {
-    rc = enqueue_graph(c, frames, n, plans, hl, rect, reinterpret_cast<char *>(blk.ptr), s);
+    rc = enqueue_graph(c, frames, n, plans, hl, sw, rect, reinterpret_cast<char *>(blk.ptr), s);
   } else {
-    rc = enqueue_frames(frames, n, plans, hl, rect, reinterpret_cast<char *>(blk.ptr), s,
+    rc = enqueue_frames(frames, n, plans, hl, sw, rect, reinterpret_cast<char *>(blk.ptr), s,
                         c->profiling ? &b.prof : nullptr);
   }
   if (rc == SGM_OK && hipEventCreateWithFlags(&b.done, hipEventDisableTiming) != hipSuccess)
@@ -1021,6 +1124,7 @@ int sgm_get_schedule(sgm_ctx *c, const sgm_params *shape, sgm_schedule *sc) {
   std::lock_guard<std::mutex> lk(c->mu);
   *sc = sgm_schedule{};
   sc->h_lanes = resolve_hlps(c, *shape);
+  sc->sweep = resolve_sweep(c, *shape);
   return SGM_OK;
 }
 

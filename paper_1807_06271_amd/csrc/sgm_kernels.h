@@ -145,6 +145,31 @@ struct ZeroJob {
 };
 void launch_zero(std::vector<ZeroJob> jobs, hipStream_t s);
 
+// ----------------------------------------------------- single-pass sweep
+// The forward path set {L2R, TL2BR, T2B, TR2BL} (all predecessors lie above
+// or to the left) in one top-down sweep per frame: costs from the Census
+// codes, S, D_L and D_R formed on chip; only the disparity maps are written.
+// Eligible frames: Census cost with N_b <= 32, D <= 64, forward paths only,
+// uint8 path costs (N_b + P2 <= 255).
+constexpr int kSweepCarry = 256;  // bytes per pixel of a band-boundary row
+struct SweepJob {
+  const uint64_t *cl, *cr;  // Census codes [H][W]
+  uint16_t *dl, *dr;        // D_L and D_R [H][W]
+  uint8_t *carry;           // [2][W][kSweepCarry]
+  int W, H, D, nbits, p1, p2;
+  uint32_t mask;
+  int blk0;
+};
+void launch_sweep(std::vector<SweepJob> jobs, hipStream_t s);
+// Left-right check of D_L against D_R (or D_L itself when lr_check = 0).
+struct LRJob {
+  const uint16_t *dl, *dr;
+  uint16_t *out;
+  int W, H, lr_check, max_diff, invalid;
+  int blk0;
+};
+void launch_lr(std::vector<LRJob> jobs, hipStream_t s);
+
 // -------------------------------------------------------- U/V filtering
 // Threshold, dilation, binomial Gaussian and region of interest of one map
 // (section 3.2), one block per 64 x 16 output tile.

@@ -1,0 +1,316 @@
+// Single-pass row sweep for the forward path set of the paper's design
+// (section 3.1.3, figure 2: the paths at 0, 45, 90 and 135 degrees all take
+// their predecessor from the current row's left or the row above, so one
+// top-down sweep computes them together, as the FPGA pipeline does).
+//
+// One block of 1024 threads per frame.  Row groups of 16 lanes each own one
+// image row at a time; lane j holds the disparities 4j .. 4j+3 (D <= 64).
+// The 64 groups of a block take rows y = 64k + g in bands of 64, and group g
+// starts its row two steps after group g-1, so at step t group g works on
+// pixel x = t - 2g - k*P of its row: it then finds
+//   - its own L2R predecessor (x-1, y) in registers,
+//   - the T2B, TL2BR and TR2BL predecessors (x, y-1), (x-1, y-1), (x+1, y-1)
+//     in a 4-slot LDS ring that group g-1 wrote one to three steps earlier
+//     (for group 0, in a carry row that group 63 of the previous band wrote
+//     to global memory),
+// all separated from the writes by the per-step block barrier.  Costs come
+// from the Census codes: the right-view codes for x-d slide through the
+// lanes (each step shifts them one disparity up, DPP row_shr), and the
+// codes are prefetched kPF steps ahead.  Each step forms S(x, y, .) = sum of
+// the path costs, the winner-takes-all D_L(x, y), and advances a systolic
+// argmin for the right view: the candidate for x_r moves one disparity per
+// step, meets S(x_r + d, y, d) in the lane that holds d, and is final when d
+// reaches D-1 (or the row ends).  Ties go to the smaller disparity, since
+// candidates are compared as (S << 8 | d).  Nothing but D_L and D_R leaves
+// the chip.
+#include <type_traits>
+
+#include "device_util.h"
+
+namespace sgmk {
+
+namespace {
+
+typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ u16x2 as_pair(uint32_t v) { return __builtin_bit_cast(u16x2, v); }
+__device__ __forceinline__ uint32_t as_u32(u16x2 v) { return __builtin_bit_cast(uint32_t, v); }
+__device__ __forceinline__ u16x2 pmin(u16x2 a, u16x2 b) { return __builtin_elementwise_min(a, b); }
+__device__ __forceinline__ u16x2 padd_sat(u16x2 a, u16x2 b) { return __builtin_elementwise_add_sat(a, b); }
+
+constexpr int kG = 64;    // row groups per block
+constexpr int kPF = 4;    // prefetch depth in steps
+constexpr uint32_t kInf = 0xFFFFFFFFu;
+
+// One step of the path recurrence for a 16-lane group (4 disparities per
+// lane as two packed pairs): Lp = predecessor's path costs, mp its minimum.
+__device__ __forceinline__ void path_step(const u16x2 Lp[2], uint32_t mp, const u16x2 C[2], u16x2 P1, u16x2 P2,
+                                          const uint32_t pad[2], u16x2 Lc[2]) {
+  const uint32_t prev =
+      (uint32_t)__builtin_amdgcn_update_dpp((int)kInf, (int)as_u32(Lp[1]), kDppRowShr1, 0xF, 0xF, false);
+  const uint32_t next =
+      (uint32_t)__builtin_amdgcn_update_dpp((int)kInf, (int)as_u32(Lp[0]), kDppRowShl1, 0xF, 0xF, false);
+  // Nb[q] = (L[2q-1], L[2q]) of the lane's disparities
+  const u16x2 Nb0 = as_pair(__builtin_amdgcn_alignbit(as_u32(Lp[0]), prev, 16));
+  const u16x2 Nb1 = as_pair(__builtin_amdgcn_alignbit(as_u32(Lp[1]), as_u32(Lp[0]), 16));
+  const u16x2 Nb2 = as_pair(__builtin_amdgcn_alignbit(next, as_u32(Lp[1]), 16));
+  const u16x2 M = {(unsigned short)mp, (unsigned short)mp};
+  const u16x2 MP2 = padd_sat(M, P2);
+  u16x2 b0 = pmin(pmin(padd_sat(pmin(Nb0, Nb1), P1), Lp[0]), MP2);
+  u16x2 b1 = pmin(pmin(padd_sat(pmin(Nb1, Nb2), P1), Lp[1]), MP2);
+  Lc[0] = as_pair(as_u32(b0 - M + C[0]) | pad[0]);
+  Lc[1] = as_pair(as_u32(b1 - M + C[1]) | pad[1]);
+}
+
+__device__ __forceinline__ uint32_t pair_min(const u16x2 L[2]) {
+  const u16x2 m = pmin(L[0], L[1]);
+  return row16_allmin_u32(min((uint32_t)m.x, (uint32_t)m.y));
+}
+
+// four path-cost bytes of the lane (low bytes of the four 16-bit values)
+__device__ __forceinline__ uint32_t pack_bytes(const u16x2 L[2]) {
+  return __builtin_amdgcn_perm(as_u32(L[1]), as_u32(L[0]), 0x06040200u);
+}
+__device__ __forceinline__ void unpack_bytes(uint32_t b, u16x2 L[2]) {
+  L[0] = as_pair(__builtin_amdgcn_perm(0u, b, 0x0c010c00u));
+  L[1] = as_pair(__builtin_amdgcn_perm(0u, b, 0x0c030c02u));
+}
+
+}  // namespace
+
+__global__ __launch_bounds__(1024) void sweep_kernel(JobTable<SweepJob> t) {
+  __shared__ uint32_t ring[kG][4][3][16];  // [group][x % 4][path][lane]: path-cost bytes
+  __shared__ uint32_t rmin[kG][4][3];      // their minima over d
+  // the job's fields in registers (the job table lives in the kernel
+  // arguments; indexing it by block would reload them inside the loop)
+  const SweepJob &JT = t.j[blockIdx.x];
+  const uint64_t *const Jcl = JT.cl, *const Jcr = JT.cr;
+  uint16_t *const Jdl = JT.dl, *const Jdr = JT.dr;
+  uint8_t *const Jcarry = JT.carry;
+  const int W = JT.W, H = JT.H, D = JT.D;
+  const uint32_t nbits = (uint32_t)JT.nbits, mask = JT.mask;
+  const int jp1 = JT.p1, jp2 = JT.p2;
+  const int g = (int)threadIdx.x >> 4, j = (int)threadIdx.x & 15;
+  // steps between the rows of a group: the row (W), two steps so that group
+  // g+1 has read the ring before group g refills it, and at least enough for
+  // the 2-step skew of 64 groups plus the carry prefetch distance
+  const int P = max(W + 2, 2 * kG + kPF + 1);
+  const int T = 2 * ((H - 1) % kG) + P * ((H - 1) / kG) + W;
+  const int dbase = 4 * j;
+  const int dvalid = min(4, max(0, D - dbase));
+  uint32_t pad[2];
+#pragma unroll
+  for (int q = 0; q < 2; ++q)
+    pad[q] = (2 * q < dvalid ? 0u : 0xFFFFu) | (2 * q + 1 < dvalid ? 0u : 0xFFFF0000u);
+  const u16x2 P1 = {(unsigned short)jp1, (unsigned short)jp1};
+  const u16x2 P2 = {(unsigned short)jp2, (unsigned short)jp2};
+  const bool pL = mask & 0x01, pT = mask & 0x04, pTL = mask & 0x10, pTR = mask & 0x40;
+  const bool vert = pT || pTL || pTR;
+  const int dlast = D - 1;  // the candidate holding d = D-1 is final
+
+  // (band, x) of the step being processed and of the prefetch target
+  int band = 0, x = -2 * g, bandf = 0, xf = -2 * g;
+  auto advance = [&](int &b, int &xx) {
+    if (++xx == P) {
+      xx = 0;
+      ++b;
+    }
+  };
+  // prefetch ring: Census words at (x, y) and, for group 0, the carry row's
+  // path bytes and minima of the three predecessors
+  uint32_t rcl[kPF], rcr[kPF], rcv0[kPF], rcv1[kPF], rcv2[kPF], rcm0[kPF], rcm1[kPF], rcm2[kPF];
+  auto prefetch = [&](auto stag, int b, int xx) {
+    constexpr int S_ = decltype(stag)::value;
+    const int y = b * kG + g;
+    if (xx < 0 || xx >= W || y >= H) return;
+    const int64_t o = (int64_t)y * W + xx;
+    rcl[S_] = *reinterpret_cast<const uint32_t *>(Jcl + o);
+    rcr[S_] = *reinterpret_cast<const uint32_t *>(Jcr + o);
+    if (g == 0 && b > 0 && vert) {
+      const uint8_t *cb = Jcarry + (size_t)((b - 1) & 1) * W * kSweepCarry;
+      rcv0[S_] = *reinterpret_cast<const uint32_t *>(cb + (size_t)xx * kSweepCarry + dbase);
+      rcm0[S_] = *reinterpret_cast<const uint32_t *>(cb + (size_t)xx * kSweepCarry + 192);
+      if (xx > 0) {
+        rcv1[S_] = *reinterpret_cast<const uint32_t *>(cb + (size_t)(xx - 1) * kSweepCarry + 64 + dbase);
+        rcm1[S_] = *reinterpret_cast<const uint32_t *>(cb + (size_t)(xx - 1) * kSweepCarry + 196);
+      }
+      if (xx + 1 < W) {
+        rcv2[S_] = *reinterpret_cast<const uint32_t *>(cb + (size_t)(xx + 1) * kSweepCarry + 128 + dbase);
+        rcm2[S_] = *reinterpret_cast<const uint32_t *>(cb + (size_t)(xx + 1) * kSweepCarry + 200);
+      }
+    }
+  };
+
+#pragma unroll
+  for (int s = 0; s < kPF; ++s) {
+    rcl[s] = rcr[s] = rcv0[s] = rcv1[s] = rcv2[s] = rcm0[s] = rcm1[s] = rcm2[s] = 0;
+  }
+  prefetch(std::integral_constant<int, 0>{}, bandf, xf);
+  advance(bandf, xf);
+  prefetch(std::integral_constant<int, 1>{}, bandf, xf);
+  advance(bandf, xf);
+  prefetch(std::integral_constant<int, 2>{}, bandf, xf);
+  advance(bandf, xf);
+  prefetch(std::integral_constant<int, 3>{}, bandf, xf);
+  advance(bandf, xf);
+  u16x2 Lh[2] = {as_pair(pad[0]), as_pair(pad[1])};
+  uint32_t mh = 0;
+  uint32_t crs[4] = {0u, 0u, 0u, 0u};     // cr(x - 4j - k)
+  uint32_t cand[4] = {kInf, kInf, kInf, kInf};  // right-view candidate of x - 4j - k
+
+  static_assert(kPF == 4, "the prefetch slots below are spelled out for kPF = 4");
+  auto step = [&](auto stag) {
+      constexpr int S_ = decltype(stag)::value;
+      const uint32_t ccl = rcl[S_], ccr = rcr[S_];
+      const uint32_t cv0 = rcv0[S_], cv1 = rcv1[S_], cv2 = rcv2[S_];
+      const uint32_t cm0 = rcm0[S_], cm1 = rcm1[S_], cm2 = rcm2[S_];
+      prefetch(stag, bandf, xf);  // the step kPF ahead uses the same slot
+      advance(bandf, xf);
+      const int y = band * kG + g;
+      if (x >= 0 && x < W && y < H) {
+        if (x == 0) {  // row start: the L2R path and the right-view candidates begin anew
+          Lh[0] = as_pair(pad[0]);
+          Lh[1] = as_pair(pad[1]);
+          mh = 0;
+#pragma unroll
+          for (int k = 0; k < 4; ++k) cand[k] = kInf;
+        }
+        // right-view codes move one disparity up; lane 0 takes cr(x)
+        const uint32_t in = (uint32_t)__builtin_amdgcn_update_dpp((int)ccr, (int)crs[3], kDppRowShr1, 0xF,
+                                                                  0xF, false);
+        crs[3] = crs[2];
+        crs[2] = crs[1];
+        crs[1] = crs[0];
+        crs[0] = in;
+        // matching costs of equation (1), N_b left of the image
+        u16x2 C[2];
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+          const int d0 = dbase + 2 * q;
+          const uint32_t h0 = (uint32_t)__builtin_popcount(ccl ^ crs[2 * q]);
+          const uint32_t h1 = (uint32_t)__builtin_popcount(ccl ^ crs[2 * q + 1]);
+          const uint32_t c0 = x >= d0 ? h0 : nbits;
+          const uint32_t c1 = x >= d0 + 1 ? h1 : nbits;
+          C[q] = as_pair(c0 | c1 << 16);
+        }
+        u16x2 S[2] = {as_pair(0u), as_pair(0u)};
+        if (pL) {
+          u16x2 Lc[2];
+          path_step(Lh, mh, C, P1, P2, pad, Lc);
+          mh = pair_min(Lc);
+          Lh[0] = Lc[0];
+          Lh[1] = Lc[1];
+          S[0] = S[0] + Lc[0];
+          S[1] = S[1] + Lc[1];
+        }
+        if (vert) {
+          const int slot = x & 3;
+          uint8_t *carry_out = g == kG - 1 ? Jcarry + (size_t)(band & 1) * W * kSweepCarry +
+                                                 (size_t)x * kSweepCarry
+                                           : nullptr;
+          // path V (0: T2B, 1: TL2BR, 2: TR2BL) with its predecessor at
+          // (x, y-1), (x-1, y-1) or (x+1, y-1)
+          auto vpath = [&](auto vtag, bool on, bool has, int px, uint32_t carry_bytes, uint32_t carry_min) {
+            constexpr int V = decltype(vtag)::value;
+            if (!on) return;
+            u16x2 Lp[2] = {as_pair(pad[0]), as_pair(pad[1])};
+            uint32_t mp = 0;
+            if (has) {
+              uint32_t bytes = carry_bytes, m = carry_min;
+              if (g > 0) {
+                bytes = ring[g - 1][px & 3][V][j];
+                m = rmin[g - 1][px & 3][V];
+              }
+              unpack_bytes(bytes, Lp);
+              Lp[0] = as_pair(as_u32(Lp[0]) | pad[0]);
+              Lp[1] = as_pair(as_u32(Lp[1]) | pad[1]);
+              mp = m;
+            }
+            u16x2 Lc[2];
+            path_step(Lp, mp, C, P1, P2, pad, Lc);
+            const uint32_t mc = pair_min(Lc);
+            const uint32_t b = pack_bytes(Lc);
+            ring[g][slot][V][j] = b;
+            if (j == 0) rmin[g][slot][V] = mc;
+            if (carry_out) {
+              *reinterpret_cast<uint32_t *>(carry_out + 64 * V + dbase) = b;
+              if (j == 0) *reinterpret_cast<uint32_t *>(carry_out + 192 + 4 * V) = mc;
+            }
+            S[0] = S[0] + Lc[0];
+            S[1] = S[1] + Lc[1];
+          };
+          vpath(std::integral_constant<int, 0>{}, pT, y > 0, x, cv0, cm0);
+          vpath(std::integral_constant<int, 1>{}, pTL, y > 0 && x > 0, x - 1, cv1, cm1);
+          vpath(std::integral_constant<int, 2>{}, pTR, y > 0 && x + 1 < W, x + 1, cv2, cm2);
+        }
+        // winner-takes-all and the right-view candidates, as (S << 8 | d)
+        uint32_t key[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          const uint32_t sv = (k & 1) ? (uint32_t)S[k >> 1].y : (uint32_t)S[k >> 1].x;
+          key[k] = k < dvalid ? (sv << 8 | (uint32_t)(dbase + k)) : kInf;
+        }
+        const uint32_t best = row16_allmin_u32(min(min(key[0], key[1]), min(key[2], key[3])));
+        const int64_t row = (int64_t)y * W;
+        if (j == 0) Jdl[row + x] = (uint16_t)(best & 0xFF);
+        // candidates move one disparity up, the new one (x_r = x) enters at d = 0
+        const uint32_t cin = (uint32_t)__builtin_amdgcn_update_dpp((int)kInf, (int)cand[3], kDppRowShr1, 0xF,
+                                                                   0xF, false);
+        cand[3] = cand[2];
+        cand[2] = cand[1];
+        cand[1] = cand[0];
+        cand[0] = cin;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          cand[k] = min(cand[k], key[k]);
+          const int d = dbase + k;
+          // final when d = D-1, or at the row end for every d (x_r + d' >= W beyond)
+          if (d <= dlast && x >= d && (d == dlast || x == W - 1)) Jdr[row + x - d] = (uint16_t)(cand[k] & 0xFF);
+        }
+      }
+      advance(band, x);
+      __syncthreads();
+  };
+  for (int t0 = 0; t0 < T; t0 += kPF) {
+    step(std::integral_constant<int, 0>{});
+    step(std::integral_constant<int, 1>{});
+    step(std::integral_constant<int, 2>{});
+    step(std::integral_constant<int, 3>{});
+  }
+}
+
+__global__ __launch_bounds__(256) void lr_kernel(JobTable<LRJob> t) {
+  const int ji = find_job(t.j, t.n, (int)blockIdx.x);
+  const LRJob &J = t.j[ji];
+  const int64_t i = (int64_t)((int)blockIdx.x - J.blk0) * 256 + threadIdx.x;
+  const int64_t n = (int64_t)J.W * J.H;
+  if (i >= n) return;
+  const int dl = J.dl[i];
+  uint16_t v = (uint16_t)dl;
+  if (J.lr_check) {
+    const int x = (int)(i % J.W);
+    v = (uint16_t)J.invalid;
+    if (x - dl >= 0) {
+      const int dr = J.dr[i - dl];
+      if (abs(dl - dr) <= J.max_diff) v = (uint16_t)dl;
+    }
+  }
+  J.out[i] = v;
+}
+
+void launch_sweep(std::vector<SweepJob> jobs, hipStream_t s) {
+  for_each_table(
+      jobs, [](const SweepJob &) { return 1L; },
+      [&](const JobTable<SweepJob> &t, int blocks) {
+        hipLaunchKernelGGL(sweep_kernel, dim3(blocks), dim3(1024), 0, s, t);
+      });
+}
+
+void launch_lr(std::vector<LRJob> jobs, hipStream_t s) {
+  for_each_table(
+      jobs, [](const LRJob &j) { return (long)(((int64_t)j.W * j.H + 255) / 256); },
+      [&](const JobTable<LRJob> &t, int blocks) {
+        hipLaunchKernelGGL(lr_kernel, dim3(blocks), dim3(256), 0, s, t);
+      });
+}
+
+}  // namespace sgmk

@@ -58,7 +58,7 @@ class sgm_params(ctypes.Structure):
 
 
 class sgm_schedule(ctypes.Structure):
-    _fields_ = [("h_lanes", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
+    _fields_ = [("h_lanes", ctypes.c_int32), ("sweep", ctypes.c_int32), ("reserved", ctypes.c_int32 * 2)]
 
 
 class sgm_remap(ctypes.Structure):
@@ -423,17 +423,25 @@ def sgm_memory(ctx: Context):
     return a.value, b.value
 
 
-def sgm_set_schedule(ctx: Context, p: Params | None, h_lanes: int) -> None:
-    """Schedule for frames of p's shape (p=None: the default)."""
-    sc = sgm_schedule(h_lanes)
+def sgm_set_schedule(ctx: Context, p: Params | None, h_lanes: int, sweep: bool = False) -> None:
+    """Schedule for frames of p's shape (p=None: the default): lanes per
+    horizontal scanline, and whether eligible frames use the single-pass
+    sweep."""
+    sc = sgm_schedule(h_lanes, int(bool(sweep)))
     _check(lib().sgm_set_schedule(ctx.handle, ctypes.byref(p.c()) if p is not None else None,
                                   ctypes.byref(sc)), "sgm_set_schedule")
 
 
 def sgm_get_schedule(ctx: Context, p: Params) -> int:
+    """Lanes per horizontal scanline that sgm_submit would use for p's shape."""
+    return schedule_of(ctx, p)[0]
+
+
+def schedule_of(ctx: Context, p: Params):
+    """(h_lanes, sweep) that sgm_submit would use for frames like p."""
     sc = sgm_schedule()
     _check(lib().sgm_get_schedule(ctx.handle, ctypes.byref(p.c()), ctypes.byref(sc)), "sgm_get_schedule")
-    return sc.h_lanes
+    return sc.h_lanes, bool(sc.sweep)
 
 
 def sgm_autotune(ctx: Context, sample: "Frame", reps: int = 5):
