@@ -526,6 +526,21 @@ int enqueue_frames(const sgm_frame *fr, int n, const std::vector<FramePlan> &pla
       j.p1 = p.p1;
       j.p2 = p.p2;
       j.mask = p.path_mask;
+      j.count = 1;
+      j.stride = 0;
+      // frames with the same parameters whose scratch follows at a fixed
+      // distance share one entry (a launch holds any number of them)
+      if (!wj.empty()) {
+        SweepJob &q = wj.back();
+        const int64_t step = reinterpret_cast<const char *>(j.cl) - reinterpret_cast<const char *>(q.cl);
+        const bool same = q.W == j.W && q.H == j.H && q.D == j.D && q.nbits == j.nbits && q.p1 == j.p1 &&
+                          q.p2 == j.p2 && q.mask == j.mask;
+        if (same && (q.count == 1 ? step > 0 : step == (int64_t)q.count * q.stride)) {
+          if (q.count == 1) q.stride = step;
+          ++q.count;
+          continue;
+        }
+      }
       wj.push_back(j);
     }
     if (!wj.empty()) {

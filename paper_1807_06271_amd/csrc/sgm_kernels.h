@@ -156,6 +156,8 @@ struct SweepJob {
   const uint64_t *cl, *cr;  // Census codes [H][W]
   uint16_t *dl, *dr;        // D_L and D_R [H][W]
   uint8_t *carry;           // [2][W][kSweepCarry]
+  int64_t stride;           // bytes between the buffers of consecutive frames
+  int count;                // frames of this job (one block each)
   int W, H, D, nbits, p1, p2;
   uint32_t mask;
   int blk0;

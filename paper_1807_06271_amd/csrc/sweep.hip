@@ -5,8 +5,8 @@
 //
 // One block of 1024 threads per frame.  Row groups of 16 lanes each own one
 // image row at a time; lane j holds the disparities 4j .. 4j+3 (D <= 64).
-// The 64 groups of a block take rows y = 64k + g in bands of 64, and group g
-// starts its row two steps after group g-1, so at step t group g works on
+// The 60 groups of waves 0-14 take rows y = 60k + g in bands of 60, and group
+// g starts its row two steps after group g-1, so at step t group g works on
 // pixel x = t - 2g - k*P of its row: it then finds
 //   - its own L2R predecessor (x-1, y) in registers,
 //   - the T2B, TL2BR and TR2BL predecessors (x, y-1), (x-1, y-1), (x+1, y-1)
@@ -23,6 +23,10 @@
 // reaches D-1 (or the row ends).  Ties go to the smaller disparity, since
 // candidates are compared as (S << 8 | d).  Nothing but D_L and D_R leaves
 // the chip.
+//
+// The computing waves issue only loads (unconditionally, so the waits for a
+// prefetched value never wait for later memory operations); their outputs
+// go to LDS, and wave 15 writes them to global memory one step later.
 #include <type_traits>
 
 #include "device_util.h"
@@ -37,7 +41,7 @@ __device__ __forceinline__ uint32_t as_u32(u16x2 v) { return __builtin_bit_cast(
 __device__ __forceinline__ u16x2 pmin(u16x2 a, u16x2 b) { return __builtin_elementwise_min(a, b); }
 __device__ __forceinline__ u16x2 padd_sat(u16x2 a, u16x2 b) { return __builtin_elementwise_add_sat(a, b); }
 
-constexpr int kG = 64;    // row groups per block
+constexpr int kG = 60;    // computing row groups per block (waves 0-14)
 constexpr int kPF = 4;    // prefetch depth in steps
 constexpr uint32_t kInf = 0xFFFFFFFFu;
 
@@ -80,21 +84,34 @@ __device__ __forceinline__ void unpack_bytes(uint32_t b, u16x2 L[2]) {
 __global__ __launch_bounds__(1024) void sweep_kernel(JobTable<SweepJob> t) {
   __shared__ uint32_t ring[kG][4][3][16];  // [group][x % 4][path][lane]: path-cost bytes
   __shared__ uint32_t rmin[kG][4][3];      // their minima over d
+  // outputs of the last two steps (by step parity) for the writer wave:
+  // D_L per group, the right-view candidates per group and disparity, and
+  // the carry bytes of the band's last group
+  __shared__ uint8_t st_dl[2][kG];
+  __shared__ uint32_t st_dr[2][kG][16];
+  __shared__ uint32_t st_carry[2][kSweepCarry / 4];
   // the job's fields in registers (the job table lives in the kernel
   // arguments; indexing it by block would reload them inside the loop)
-  const SweepJob &JT = t.j[blockIdx.x];
-  const uint64_t *const Jcl = JT.cl, *const Jcr = JT.cr;
-  uint16_t *const Jdl = JT.dl, *const Jdr = JT.dr;
-  uint8_t *const Jcarry = JT.carry;
+  const SweepJob &JT = t.j[find_job(t.j, t.n, (int)blockIdx.x)];
+  // frame (blockIdx.x - blk0) of the job: its buffers lie `stride` bytes apart
+  const int64_t off = (int64_t)((int)blockIdx.x - JT.blk0) * JT.stride;
+  const uint64_t *const Jcl = reinterpret_cast<const uint64_t *>(reinterpret_cast<const char *>(JT.cl) + off);
+  const uint64_t *const Jcr = reinterpret_cast<const uint64_t *>(reinterpret_cast<const char *>(JT.cr) + off);
+  uint16_t *const Jdl = reinterpret_cast<uint16_t *>(reinterpret_cast<char *>(JT.dl) + off);
+  uint16_t *const Jdr = reinterpret_cast<uint16_t *>(reinterpret_cast<char *>(JT.dr) + off);
+  uint8_t *const Jcarry = JT.carry + off;
   const int W = JT.W, H = JT.H, D = JT.D;
   const uint32_t nbits = (uint32_t)JT.nbits, mask = JT.mask;
   const int jp1 = JT.p1, jp2 = JT.p2;
   const int g = (int)threadIdx.x >> 4, j = (int)threadIdx.x & 15;
+  const bool writer = threadIdx.x >= 64 * 15;  // wave 15 (wave-uniform)
   // steps between the rows of a group: the row (W), two steps so that group
   // g+1 has read the ring before group g refills it, and at least enough for
-  // the 2-step skew of 64 groups plus the carry prefetch distance
-  const int P = max(W + 2, 2 * kG + kPF + 1);
-  const int T = 2 * ((H - 1) % kG) + P * ((H - 1) / kG) + W;
+  // the 2-step skew of kG groups plus the writer's step and the carry
+  // prefetch distance
+  const int P = max(W + 2, 2 * kG + kPF + 2);
+  // steps until the last row's last pixel, plus one for the writer
+  const int T = 2 * ((H - 1) % kG) + P * ((H - 1) / kG) + W + 1;
   const int dbase = 4 * j;
   const int dvalid = min(4, max(0, D - dbase));
   uint32_t pad[2];
@@ -108,7 +125,8 @@ __global__ __launch_bounds__(1024) void sweep_kernel(JobTable<SweepJob> t) {
   const int dlast = D - 1;  // the candidate holding d = D-1 is final
 
   // (band, x) of the step being processed and of the prefetch target
-  int band = 0, x = -2 * g, bandf = 0, xf = -2 * g;
+  // the writer's lane gg tracks group gg one step late
+  int band = 0, x = writer ? -2 * ((int)threadIdx.x & 63) - 1 : -2 * g, bandf = 0, xf = -2 * g;
   auto advance = [&](int &b, int &xx) {
     if (++xx == P) {
       xx = 0;
@@ -118,25 +136,29 @@ __global__ __launch_bounds__(1024) void sweep_kernel(JobTable<SweepJob> t) {
   // prefetch ring: Census words at (x, y) and, for group 0, the carry row's
   // path bytes and minima of the three predecessors
   uint32_t rcl[kPF], rcr[kPF], rcv0[kPF], rcv1[kPF], rcv2[kPF], rcm0[kPF], rcm1[kPF], rcm2[kPF];
+  // Loads are issued unconditionally by every wave (an out-of-image target
+  // reads pixel 0), so the ring registers are plain loop-carried values and
+  // the waits for them stay kPF steps behind the loads.
   auto prefetch = [&](auto stag, int b, int xx) {
     constexpr int S_ = decltype(stag)::value;
     const int y = b * kG + g;
-    if (xx < 0 || xx >= W || y >= H) return;
-    const int64_t o = (int64_t)y * W + xx;
+    const bool ok = !writer && xx >= 0 && xx < W && y < H;
+    const int64_t o = ok ? (int64_t)y * W + xx : 0;
     rcl[S_] = *reinterpret_cast<const uint32_t *>(Jcl + o);
     rcr[S_] = *reinterpret_cast<const uint32_t *>(Jcr + o);
-    if (g == 0 && b > 0 && vert) {
-      const uint8_t *cb = Jcarry + (size_t)((b - 1) & 1) * W * kSweepCarry;
-      rcv0[S_] = *reinterpret_cast<const uint32_t *>(cb + (size_t)xx * kSweepCarry + dbase);
-      rcm0[S_] = *reinterpret_cast<const uint32_t *>(cb + (size_t)xx * kSweepCarry + 192);
-      if (xx > 0) {
-        rcv1[S_] = *reinterpret_cast<const uint32_t *>(cb + (size_t)(xx - 1) * kSweepCarry + 64 + dbase);
-        rcm1[S_] = *reinterpret_cast<const uint32_t *>(cb + (size_t)(xx - 1) * kSweepCarry + 196);
-      }
-      if (xx + 1 < W) {
-        rcv2[S_] = *reinterpret_cast<const uint32_t *>(cb + (size_t)(xx + 1) * kSweepCarry + 128 + dbase);
-        rcm2[S_] = *reinterpret_cast<const uint32_t *>(cb + (size_t)(xx + 1) * kSweepCarry + 200);
-      }
+    {  // only group 0 uses the carry row; every wave loads it so that all
+       // paths through a step issue the same loads
+      const int xc = min(max(xx, 0), W - 1);
+      const uint8_t *cb = Jcarry + (size_t)((max(b, 1) - 1) & 1) * W * kSweepCarry;
+      const uint8_t *c0 = cb + (size_t)xc * kSweepCarry;
+      const uint8_t *cm = cb + (size_t)max(xc - 1, 0) * kSweepCarry;
+      const uint8_t *cp = cb + (size_t)min(xc + 1, W - 1) * kSweepCarry;
+      rcv0[S_] = *reinterpret_cast<const uint32_t *>(c0 + dbase);
+      rcm0[S_] = *reinterpret_cast<const uint32_t *>(c0 + 192);
+      rcv1[S_] = *reinterpret_cast<const uint32_t *>(cm + 64 + dbase);
+      rcm1[S_] = *reinterpret_cast<const uint32_t *>(cm + 196);
+      rcv2[S_] = *reinterpret_cast<const uint32_t *>(cp + 128 + dbase);
+      rcm2[S_] = *reinterpret_cast<const uint32_t *>(cp + 200);
     }
   };
 
@@ -163,10 +185,42 @@ __global__ __launch_bounds__(1024) void sweep_kernel(JobTable<SweepJob> t) {
       const uint32_t ccl = rcl[S_], ccr = rcr[S_];
       const uint32_t cv0 = rcv0[S_], cv1 = rcv1[S_], cv2 = rcv2[S_];
       const uint32_t cm0 = rcm0[S_], cm1 = rcm1[S_], cm2 = rcm2[S_];
-      prefetch(stag, bandf, xf);  // the step kPF ahead uses the same slot
-      advance(bandf, xf);
+      constexpr int buf = S_ & 1;         // this step's staging (t0 is a multiple of kPF)
+      constexpr int wbuf = (S_ + 1) & 1;  // the previous step's
+      if (writer) {
+        // outputs of the previous step: lane gg follows group gg, whose
+        // position then was (band, x) one step back
+        const int gg = (int)threadIdx.x & 63;
+        const int y = band * kG + gg;
+        const bool act = gg < kG && x >= 0 && x < W && y < H;
+        const int64_t row = (int64_t)y * W;
+        if (act) {
+          Jdl[row + x] = st_dl[wbuf][gg];
+          if (x >= dlast)
+            Jdr[row + x - dlast] = (uint16_t)(reinterpret_cast<const uint8_t *>(st_dr[wbuf][gg])[dlast]);
+        }
+        // groups that finished a row: their remaining candidates x_r = W-1-d
+        uint64_t ends = __ballot(act && x == W - 1);
+        while (ends) {
+          const int ge = __builtin_ctzll(ends);
+          ends &= ends - 1;
+          const int ye = __builtin_amdgcn_readlane(y, ge);
+          const int d = gg;
+          if (d < dlast && W - 1 - d >= 0)
+            Jdr[(int64_t)ye * W + W - 1 - d] = (uint16_t)(reinterpret_cast<const uint8_t *>(st_dr[wbuf][ge])[d]);
+        }
+        // the band's last group: its path bytes become the carry row
+        const int xl = __builtin_amdgcn_readlane(x, kG - 1);
+        const int yl = __builtin_amdgcn_readlane(y, kG - 1);
+        const int bl = __builtin_amdgcn_readlane(band, kG - 1);
+        if (vert && xl >= 0 && xl < W && yl < H && gg < 52)
+          *reinterpret_cast<uint32_t *>(Jcarry + (size_t)(bl & 1) * W * kSweepCarry + (size_t)xl * kSweepCarry +
+                                        4 * gg) = st_carry[wbuf][gg];
+      }
+      // the writer follows each group one step late: its counters start one
+      // step behind (see the set-up below)
       const int y = band * kG + g;
-      if (x >= 0 && x < W && y < H) {
+      if (!writer && x >= 0 && x < W && y < H) {
         if (x == 0) {  // row start: the L2R path and the right-view candidates begin anew
           Lh[0] = as_pair(pad[0]);
           Lh[1] = as_pair(pad[1]);
@@ -204,9 +258,7 @@ __global__ __launch_bounds__(1024) void sweep_kernel(JobTable<SweepJob> t) {
         }
         if (vert) {
           const int slot = x & 3;
-          uint8_t *carry_out = g == kG - 1 ? Jcarry + (size_t)(band & 1) * W * kSweepCarry +
-                                                 (size_t)x * kSweepCarry
-                                           : nullptr;
+          const bool carry_out = g == kG - 1;
           // path V (0: T2B, 1: TL2BR, 2: TR2BL) with its predecessor at
           // (x, y-1), (x-1, y-1) or (x+1, y-1)
           auto vpath = [&](auto vtag, bool on, bool has, int px, uint32_t carry_bytes, uint32_t carry_min) {
@@ -232,8 +284,8 @@ __global__ __launch_bounds__(1024) void sweep_kernel(JobTable<SweepJob> t) {
             ring[g][slot][V][j] = b;
             if (j == 0) rmin[g][slot][V] = mc;
             if (carry_out) {
-              *reinterpret_cast<uint32_t *>(carry_out + 64 * V + dbase) = b;
-              if (j == 0) *reinterpret_cast<uint32_t *>(carry_out + 192 + 4 * V) = mc;
+              st_carry[buf][16 * V + j] = b;
+              if (j == 0) st_carry[buf][48 + V] = mc;
             }
             S[0] = S[0] + Lc[0];
             S[1] = S[1] + Lc[1];
@@ -250,8 +302,7 @@ __global__ __launch_bounds__(1024) void sweep_kernel(JobTable<SweepJob> t) {
           key[k] = k < dvalid ? (sv << 8 | (uint32_t)(dbase + k)) : kInf;
         }
         const uint32_t best = row16_allmin_u32(min(min(key[0], key[1]), min(key[2], key[3])));
-        const int64_t row = (int64_t)y * W;
-        if (j == 0) Jdl[row + x] = (uint16_t)(best & 0xFF);
+        if (j == 0) st_dl[buf][g] = (uint8_t)(best & 0xFF);
         // candidates move one disparity up, the new one (x_r = x) enters at d = 0
         const uint32_t cin = (uint32_t)__builtin_amdgcn_update_dpp((int)kInf, (int)cand[3], kDppRowShr1, 0xF,
                                                                    0xF, false);
@@ -260,13 +311,15 @@ __global__ __launch_bounds__(1024) void sweep_kernel(JobTable<SweepJob> t) {
         cand[1] = cand[0];
         cand[0] = cin;
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-          cand[k] = min(cand[k], key[k]);
-          const int d = dbase + k;
-          // final when d = D-1, or at the row end for every d (x_r + d' >= W beyond)
-          if (d <= dlast && x >= d && (d == dlast || x == W - 1)) Jdr[row + x - d] = (uint16_t)(cand[k] & 0xFF);
-        }
+        for (int k = 0; k < 4; ++k) cand[k] = min(cand[k], key[k]);
+        // the candidate holding d = D-1 is final (x_r = x - D + 1), and at the
+        // row end every candidate is (x_r + d' >= W beyond): stage them all
+        st_dr[buf][g][j] = (cand[0] & 0xFF) | (cand[1] & 0xFF) << 8 | (cand[2] & 0xFF) << 16 | (cand[3] & 0xFF) << 24;
       }
+      // refill the slot for the step kPF ahead once this step is done with
+      // it, so that the slot's old and new values can share registers
+      prefetch(stag, bandf, xf);
+      advance(bandf, xf);
       advance(band, x);
       __syncthreads();
   };
@@ -299,7 +352,7 @@ __global__ __launch_bounds__(256) void lr_kernel(JobTable<LRJob> t) {
 
 void launch_sweep(std::vector<SweepJob> jobs, hipStream_t s) {
   for_each_table(
-      jobs, [](const SweepJob &) { return 1L; },
+      jobs, [](const SweepJob &j) { return (long)j.count; },
       [&](const JobTable<SweepJob> &t, int blocks) {
         hipLaunchKernelGGL(sweep_kernel, dim3(blocks), dim3(1024), 0, s, t);
       });
