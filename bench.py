@@ -122,6 +122,7 @@ def bench_paper_settings(torch, sgm, ctx, synthetic, steps=100):
         dt, _ = time_submit_stream(torch, sgm, ctx, lambda i: [sgm.Frame.alloc(p, Lt, Rt)], steps, 10)
         res[name] = {"fps": steps / dt, "mdisp_evals_per_s": p.disp_evals() * steps / dt / 1e6,
                      "ms_per_frame": dt / steps * 1e3}
+    res["census_sweep"] = bench_sweep(torch, sgm, ctx, synthetic)
     res["census_rectified"] = bench_rectified(torch, sgm, ctx, synthetic, steps)
     res["uv_filter"] = bench_uv_filter(torch, sgm, ctx, synthetic)
     sgm.sgm_profile(ctx, True)
@@ -154,6 +155,39 @@ def bench_uv_filter(torch, sgm, ctx, synthetic, reps=200):
     cells = 60 * 640 + 360 * 60
     return {"us_per_frame": us, "cells": cells, "algorithmic_bytes": 3 * cells,
             "gb_per_s": 3 * cells / (us * 1e-6) / 1e9}
+
+
+def bench_sweep(torch, sgm, ctx, synthetic, batch=256, reps=3):
+    """The paper's Census setting through the single-pass sweep (one block
+    per frame, nothing but the disparity maps written) against the
+    per-direction kernels: one frame per submit, and batches of `batch`
+    frames (a frame per CU)."""
+    L, R, _ = synthetic.make_pair("paper", 7)
+    Lt, Rt = torch.from_numpy(L).cuda(), torch.from_numpy(R).cuda()
+    p = sgm.Params(width=640, height=360, max_disp=60, census_w=5, census_h=5, path_mask=sgm.PATHS_PAPER4,
+                   lr_check=1, median=5, p1=8, p2=32)
+    h = sgm.sgm_get_schedule(ctx, p)
+    res = {"batch": batch}
+    for name, sweep in (("direction_kernels", False), ("sweep", True)):
+        sgm.sgm_set_schedule(ctx, p, h, sweep=sweep)
+        one = [sgm.Frame.alloc(p, Lt, Rt)]
+        sgm.sgm_wait(ctx, sgm.sgm_submit(ctx, one))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            sgm.sgm_wait(ctx, sgm.sgm_submit(ctx, one))
+        single_ms = (time.perf_counter() - t0) / reps * 1e3
+        frames = [sgm.Frame.alloc(p, Lt, Rt) for _ in range(batch)]
+        sgm.sgm_wait(ctx, sgm.sgm_submit(ctx, frames))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            sgm.sgm_wait(ctx, sgm.sgm_submit(ctx, frames))
+        dt = (time.perf_counter() - t0) / reps
+        res[name] = {"single_frame_ms": single_ms, "batch_ms": dt * 1e3, "batch_fps": batch / dt}
+        del frames
+    sgm.sgm_set_schedule(ctx, p, h, sweep=False)
+    return res
 
 
 def bench_rectified(torch, sgm, ctx, synthetic, steps):
