@@ -240,7 +240,7 @@ int check_dev_ptr(const void *ptr, int dev, const char *name) {
 // ------------------------------------------------------ whole-frame plan
 
 struct FramePlan {
-  size_t off_cost, off_lr, off_dlr, bytes;
+  size_t off_cost, off_lr, off_dlr, off_dl, off_part, bytes;
 };
 
 // Scratch of one frame of a batch: the padded uint8 cost volume, the P
@@ -255,13 +255,17 @@ FramePlan plan_frame(const sgm_params &p, size_t base, bool sweep) {
     // the LR-checked map before the median
     f.off_lr = f.off_cost + align256(2 * px * 8);
     f.off_dlr = f.off_lr + align256(2 * px * 2) + align256((size_t)2 * p.width * kSweepCarry);
+    f.off_dl = f.off_part = 0;
     f.bytes = f.off_dlr + align256(px * 2) - base;
     return f;
   }
   // Census costs: padded uint8 [H][W][Dp]; SAD costs: padded uint16 [H][W][Dp]
   f.off_lr = f.off_cost + align256(is_sad(p) ? px * dp * 2 : px * dp);
   f.off_dlr = f.off_lr + align256(px * dp * (size_t)popcount8(p.path_mask) * lr_bytes_of(p));
-  f.bytes = f.off_dlr + align256(px * 2) - base;
+  // D_L and the row segments' right-view keys (left-right check)
+  f.off_dl = f.off_dlr + align256(px * 2);
+  f.off_part = f.off_dl + align256(px * 2);
+  f.bytes = f.off_part + align256(disp_part_bytes(p.width, p.height, p.max_disp)) - base;
   return f;
 }
 
@@ -583,18 +587,41 @@ int enqueue_frames(const sgm_frame *fr, int n, const std::vector<FramePlan> &pla
       DispJob j{};
       j.lr = mem + plans[i].off_lr;
       j.P = popcount8(p.path_mask);
-      j.out = p.median ? reinterpret_cast<uint16_t *>(mem + plans[i].off_dlr) : fr[i].disp;
+      uint16_t *final_map = p.median ? reinterpret_cast<uint16_t *>(mem + plans[i].off_dlr) : fr[i].disp;
+      j.out = p.lr_check ? reinterpret_cast<uint16_t *>(mem + plans[i].off_dl) : final_map;
+      j.part = reinterpret_cast<uint32_t *>(mem + plans[i].off_part);
       j.W = p.width;
       j.H = p.height;
       j.D = p.max_disp;
       j.Dp = dp_of(p);
       j.lr_check = p.lr_check;
-      j.max_diff = p.lr_max_diff;
-      j.invalid = p.invalid;
       dj.push_back(j);
     }
     if (!dj.empty()) {
       launch_disparity(dj, lb, s);
+      CHECK(check_launch());
+      ++groups;
+    }
+  }
+  {
+    std::vector<LRSegJob> lj;
+    for (int i = 0; i < n; ++i) {
+      const sgm_params &p = fr[i].p;
+      if (sweep[i] || !p.lr_check) continue;
+      LRSegJob j{};
+      j.dl = reinterpret_cast<const uint16_t *>(mem + plans[i].off_dl);
+      j.part = reinterpret_cast<const uint32_t *>(mem + plans[i].off_part);
+      j.out = p.median ? reinterpret_cast<uint16_t *>(mem + plans[i].off_dlr) : fr[i].disp;
+      j.W = p.width;
+      j.H = p.height;
+      j.D = p.max_disp;
+      disp_segments(p.width, p.max_disp, &j.nseg, &j.seglen);
+      j.max_diff = p.lr_max_diff;
+      j.invalid = p.invalid;
+      lj.push_back(j);
+    }
+    if (!lj.empty()) {
+      launch_lr_seg(lj, s);
       CHECK(check_launch());
       ++groups;
     }
@@ -886,25 +913,41 @@ int sgm_disparity(sgm_ctx *c, const sgm_params *p, const uint16_t *aggr, uint16_
   CHECK(check_dev_ptr(aggr, c->device, "aggr"));
   CHECK(check_dev_ptr(disp, c->device, "disp"));
   hipStream_t s = (hipStream_t)stream;
-  uint16_t *tmp = nullptr;
-  if (p->median) {
-    void *v = nullptr;
-    CHECK(stage_scratch(c, (size_t)p->width * p->height * 2, s, &v));
-    tmp = reinterpret_cast<uint16_t *>(v);
-  }
+  // scratch: the pre-median map, D_L and the segments' right-view keys
+  const size_t px = (size_t)p->width * p->height;
+  const size_t m2 = align256(px * 2);
+  void *v = nullptr;
+  CHECK(stage_scratch(c, 2 * m2 + disp_part_bytes(p->width, p->height, p->max_disp), s, &v));
+  uint16_t *tmp = reinterpret_cast<uint16_t *>(v);
+  uint16_t *dlmap = reinterpret_cast<uint16_t *>(reinterpret_cast<char *>(v) + m2);
+  uint32_t *part = reinterpret_cast<uint32_t *>(reinterpret_cast<char *>(v) + 2 * m2);
+  uint16_t *final_map = p->median ? tmp : disp;
   DispJob j{};
   j.S = aggr;
   j.P = popcount8(p->path_mask);
-  j.out = p->median ? tmp : disp;
+  j.out = p->lr_check ? dlmap : final_map;
+  j.part = part;
   j.W = p->width;
   j.H = p->height;
   j.D = p->max_disp;
   j.Dp = dp_of(*p);
   j.lr_check = p->lr_check;
-  j.max_diff = p->lr_max_diff;
-  j.invalid = p->invalid;
   launch_disparity({j}, 0, s);
   CHECK(check_launch());
+  if (p->lr_check) {
+    LRSegJob l{};
+    l.dl = dlmap;
+    l.part = part;
+    l.out = final_map;
+    l.W = p->width;
+    l.H = p->height;
+    l.D = p->max_disp;
+    disp_segments(p->width, p->max_disp, &l.nseg, &l.seglen);
+    l.max_diff = p->lr_max_diff;
+    l.invalid = p->invalid;
+    launch_lr_seg({l}, s);
+    CHECK(check_launch());
+  }
   if (p->median) {
     MedianJob m{};
     m.in = tmp;

@@ -1,16 +1,19 @@
 // Disparity selection from the aggregated volume (sections 3.1.3 to 3.1.5).
 //
-// disp_kernel: one 1024-thread block per image row.  Each 16-lane DPP row
-// takes one pixel at a time, lane j owning K contiguous disparities (the
-// same lane layout as the aggregation).  With path-cost volumes as input the
-// P uint8 (or uint16) volumes are read with one vector load per slot and
-// summed as packed 16-bit fields (two cells per 32-bit word, no carries:
-// S <= 65535 by the parameter check).  A cell's 32-bit key (S << 8) | d
-// orders by cost, then by disparity, so an unsigned minimum picks the
-// smallest-d argmin: D_L is the minimum key over d (DPP row butterfly), and
-// D_R(x_r) = argmin_d S(x_r + d, d) collects the same keys by LDS atomicMin
-// into slot x - d.  After a barrier the row's left-right check reads both
-// maps from LDS.
+// disp_kernel: one block per (row, segment).  Each 16-lane DPP row takes one
+// pixel at a time, lane j owning K contiguous disparities (the same lane
+// layout as the aggregation).  With path-cost volumes as input the P uint8
+// (or uint16) volumes are read with one vector load per slot and summed as
+// packed 16-bit fields (two cells per 32-bit word, no carries: S <= 65535 by
+// the parameter check).  A cell's 32-bit key (S << 8) | d orders by cost,
+// then by disparity, so an unsigned minimum picks the smallest-d argmin: D_L
+// is the minimum key over d (DPP row butterfly), and D_R(x_r) =
+// argmin_d S(x_r + d, d) collects the same keys by LDS atomicMin into slot
+// x - d.  A segment [x0, x0 + n) reaches the right-view pixels of its zone
+// [x0 - D + 1, x0 + n); it writes its D_L and its zone's keys, and
+// lr_seg_kernel takes for each x_r the minimum over the (at most two)
+// segments whose zones hold it, then checks left against right.  Splitting
+// rows keeps every CU busy on a single frame.
 //
 // median_kernel: k x k median with clamped borders by an odd-even
 // transposition network on k*k registers.
@@ -107,20 +110,35 @@ struct DispShape {
   static constexpr int THREADS = (K < 16 && 2 * NPX * RAW <= 64) ? 1024 : 512;
 };
 
+void disp_segments(int W, int D, int *nseg, int *seglen) {
+  const int target = std::max(256, 2 * D);
+  const int n = std::max(1, W / target);
+  *nseg = n;
+  *seglen = (W + n - 1) / n;
+}
+
+size_t disp_part_bytes(int W, int H, int D) {
+  int nseg, seglen;
+  disp_segments(W, D, &nseg, &seglen);
+  return (size_t)H * nseg * (seglen + D - 1) * 4;
+}
+
 template <int K, int IN>
 __global__ __launch_bounds__((DispShape<K, IN>::THREADS)) void disp_kernel(JobTable<DispJob> t) {
   constexpr int NPX = DispShape<K, IN>::NPX;
   extern __shared__ uint32_t smem[];
   const int ji = find_job(t.j, t.n, (int)blockIdx.x);
   const DispJob &J = t.j[ji];
-  const int y = (int)blockIdx.x - J.blk0;
+  const int b = (int)blockIdx.x - J.blk0;
+  const int y = b / J.nseg, sgi = b - y * J.nseg;
   const int W = J.W, D = J.D;
-  // D_R keys of x_r live at kswz(x_r) = x_r + x_r/8: a row's lanes update
+  const int xa = sgi * J.seglen, xe = min(W, xa + J.seglen);  // the segment [xa, xe)
+  const int zr = xa - D + 1, zn = xe - zr;                     // its right-view zone
+  // D_R keys of zone slot i live at kswz(i) = i + i/8: a row's lanes update
   // slots K apart, and the padding spreads them over the LDS banks
-  uint32_t *keyR = smem;                                               // [kswz(W)]
-  uint16_t *dl = reinterpret_cast<uint16_t *>(smem + W + W / 8 + 1);  // [W]
+  uint32_t *keyR = smem;  // [kswz(zn)]
   if (J.lr_check)
-    for (int i = threadIdx.x; i < W + W / 8 + 1; i += blockDim.x) keyR[i] = 0xFFFFFFFFu;
+    for (int i = threadIdx.x; i < zn + zn / 8 + 1; i += blockDim.x) keyR[i] = 0xFFFFFFFFu;
   __syncthreads();
   const int j = threadIdx.x & 15;
   const int dbase = j * K;
@@ -128,22 +146,22 @@ __global__ __launch_bounds__((DispShape<K, IN>::THREADS)) void disp_kernel(JobTa
   // NPX pixels per 16-lane row per sweep, and the next sweep's loads are
   // issued before this sweep's keys are reduced (software pipeline)
   const int kRows = (int)blockDim.x / 16;
-  const int xfirst = (int)(threadIdx.x >> 4);
+  const int xfirst = xa + (int)(threadIdx.x >> 4);
   RawSums<K, IN> raw[NPX], rawn[NPX];
 #pragma unroll
   for (int h = 0; h < NPX; ++h)
-    load_raw<K, IN>(J, (int64_t)y * W + min(xfirst + h * kRows, W - 1), dbase, dvalid, raw[h]);
-  for (int x0 = xfirst; x0 < W; x0 += NPX * kRows) {
+    load_raw<K, IN>(J, (int64_t)y * W + min(xfirst + h * kRows, xe - 1), dbase, dvalid, raw[h]);
+  for (int x0 = xfirst; x0 < xe; x0 += NPX * kRows) {
     const int xn = x0 + NPX * kRows;
-    if (xn < W) {
+    if (xn < xe) {
 #pragma unroll
       for (int h = 0; h < NPX; ++h)
-        load_raw<K, IN>(J, (int64_t)y * W + min(xn + h * kRows, W - 1), dbase, dvalid, rawn[h]);
+        load_raw<K, IN>(J, (int64_t)y * W + min(xn + h * kRows, xe - 1), dbase, dvalid, rawn[h]);
     }
 #pragma unroll
     for (int h = 0; h < NPX; ++h) {
       const int x = x0 + h * kRows;
-      if (x >= W) break;  // uniform over the 16-lane row
+      if (x >= xe) break;  // uniform over the 16-lane row
       uint32_t S[K];
       sum_raw<K, IN>(J, raw[h], S);
       uint32_t best = 0xFFFFFFFFu;
@@ -153,30 +171,50 @@ __global__ __launch_bounds__((DispShape<K, IN>::THREADS)) void disp_kernel(JobTa
           const int d = dbase + k;
           const uint32_t key = (S[k] << 8) | (uint32_t)d;
           best = min(best, key);
-          if (J.lr_check && x >= d) atomicMin(&keyR[kswz(x - d)], key);
+          if (J.lr_check && x >= d) atomicMin(&keyR[kswz(x - d - zr)], key);
         }
       }
       best = row16_allmin_u32(best);
-      if (j == 0) dl[x] = (uint16_t)(best & 0xFF);
+      if (j == 0) J.out[(int64_t)y * W + x] = (uint16_t)(best & 0xFF);
     }
 #pragma unroll
     for (int h = 0; h < NPX; ++h) raw[h] = rawn[h];
   }
+  if (!J.lr_check) return;
   __syncthreads();
-  uint16_t *out = J.out + (int64_t)y * W;
-  for (int x = threadIdx.x; x < W; x += blockDim.x) {
-    const int d = dl[x];
-    int v = d;
-    if (J.lr_check) {
-      v = J.invalid;
-      const int xr = x - d;
-      if (xr >= 0) {
-        const int dr = (int)(keyR[kswz(xr)] & 0xFF);
-        if (abs(d - dr) <= J.max_diff) v = d;
-      }
-    }
-    out[x] = (uint16_t)v;
+  uint32_t *part = J.part + ((int64_t)y * J.nseg + sgi) * (J.seglen + D - 1);
+  for (int i = threadIdx.x; i < zn; i += blockDim.x) part[i] = keyR[kswz(i)];
+}
+
+// Left-right check (section 3.1.4): D_R(x_r) is the smallest key over the
+// segments whose zones hold x_r.
+__global__ __launch_bounds__(256) void lr_seg_kernel(JobTable<LRSegJob> t) {
+  const int ji = find_job(t.j, t.n, (int)blockIdx.x);
+  const LRSegJob &J = t.j[ji];
+  const int64_t i = (int64_t)((int)blockIdx.x - J.blk0) * 256 + threadIdx.x;
+  if (i >= (int64_t)J.W * J.H) return;
+  const int y = (int)(i / J.W), x = (int)(i - (int64_t)y * J.W);
+  const int dl = J.dl[i];
+  int v = J.invalid;
+  const int xr = x - dl;
+  if (xr >= 0) {
+    const int zs = J.seglen + J.D - 1;
+    const int sa = xr / J.seglen, sb = min((xr + J.D - 1) / J.seglen, J.nseg - 1);
+    uint32_t key = 0xFFFFFFFFu;
+    for (int sg = sa; sg <= sb; ++sg)
+      key = min(key, J.part[((int64_t)y * J.nseg + sg) * zs + xr - (sg * J.seglen - J.D + 1)]);
+    const int dr = (int)(key & 0xFF);
+    if (abs(dl - dr) <= J.max_diff) v = dl;
   }
+  J.out[i] = (uint16_t)v;
+}
+
+void launch_lr_seg(std::vector<LRSegJob> jobs, hipStream_t s) {
+  for_each_table(
+      jobs, [](const LRSegJob &j) { return (long)(((int64_t)j.W * j.H + 255) / 256); },
+      [&](const JobTable<LRSegJob> &t, int blocks) {
+        hipLaunchKernelGGL(lr_seg_kernel, dim3(blocks), dim3(256), 0, s, t);
+      });
 }
 
 template <int K>
@@ -199,16 +237,17 @@ void launch_disparity(std::vector<DispJob> jobs, int in_kind, hipStream_t s) {
   // one launch per disparities-per-lane width K
   for (int K : {4, 8, 12, 16}) {
     std::vector<DispJob> sub;
-    int maxw = 0;
+    int maxz = 0;
     for (auto &j : jobs)
       if (agg_k(j.D) == K) {
+        disp_segments(j.W, j.D, &j.nseg, &j.seglen);
         sub.push_back(j);
-        maxw = std::max(maxw, j.W);
+        maxz = std::max(maxz, std::min(j.W, j.seglen) + j.D - 1);
       }
     if (sub.empty()) continue;
-    const size_t lds = (size_t)(maxw + maxw / 8 + 1) * 4 + (size_t)maxw * 2;
+    const size_t lds = (size_t)(maxz + maxz / 8 + 1) * 4;
     for_each_table(
-        sub, [](const DispJob &j) { return (long)j.H; },
+        sub, [](const DispJob &j) { return (long)j.H * j.nseg; },
         [&](const JobTable<DispJob> &t, int blocks) {
           switch (K) {
             case 4: launch_disp_k<4>(in_kind, t, blocks, lds, s); break;

@@ -109,12 +109,27 @@ struct DispJob {
   const uint16_t *S;  // [H][W][D] or null
   const void *lr;     // [P][H][W][Dp] or null
   int P;
-  uint16_t *out;      // [H][W]: LR-checked map (or D_L when lr_check = 0)
+  uint16_t *out;      // [H][W]: D_L (the LR pass's input when lr_check = 1)
+  uint32_t *part;     // lr_check: per row segment, the right-view keys of its zone
   int W, H, D, Dp;
-  int lr_check, max_diff;
-  int invalid;
+  int lr_check;
+  int nseg, seglen;   // row segments (disp_segments)
   int blk0;
 };
+// Rows are split into nseg segments of seglen pixels (seglen >= D - 1 unless
+// one segment covers the row) so that a frame gives many blocks.
+void disp_segments(int W, int D, int *nseg, int *seglen);
+// Bytes of DispJob::part for a frame.
+size_t disp_part_bytes(int W, int H, int D);
+// Left-right check from D_L and the segments' right-view keys.
+struct LRSegJob {
+  const uint16_t *dl;
+  const uint32_t *part;
+  uint16_t *out;
+  int W, H, D, nseg, seglen, max_diff, invalid;
+  int blk0;
+};
+void launch_lr_seg(std::vector<LRSegJob> jobs, hipStream_t s);
 // in_kind: 0 = S, 1 = uint8 path costs, 2 = uint16 path costs
 void launch_disparity(std::vector<DispJob> jobs, int in_kind, hipStream_t s);
 

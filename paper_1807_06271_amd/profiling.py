@@ -4,8 +4,15 @@
         [<kernel_trace.csv> <kernel name part> <N dispatches> [<skip>]]
     python -m paper_1807_06271_amd.profiling traffic <fetch_counter_collection.csv> \
         <write_counter_collection.csv> <out.json> "<fetch command>" "<write command>"
+    python -m paper_1807_06271_amd.profiling counters <counter_collection.csv> <kernel_trace.csv> \
+        <out.txt> "<command>"
 
 `stats` keeps the per-kernel call count and average / min / max durations.
+`counters` keeps the median per dispatch of each SQ counter of each kernel and
+derives the VALU issue utilisation: SQ_INSTS_VALU (wave instructions) over
+what the chip can issue in the kernel's median duration (from the kernel
+trace of the same run): one wave64 VALU instruction per clock per CU (four
+SIMDs, each 16 lanes wide), 256 CUs at 2.4 GHz.
 `traffic` turns FETCH_SIZE and WRITE_SIZE (KiB per dispatch) into bytes per
 launch of each kernel, scaled by what the same counter reads for the plain
 copy kernel of known size that the profiled run also executes (bench.py
@@ -106,11 +113,39 @@ def traffic(fetch_csv: str, write_csv: str, out_path: str, fetch_cmd: str, write
     return out
 
 
+CUS, CLOCK_HZ = 256, 2.4e9
+
+
+def counters(csv_path: str, trace_csv: str, out_path: str, command: str) -> None:
+    dur = defaultdict(list)
+    for r in csv.DictReader(open(trace_csv)):
+        dur[short_name(r["Kernel_Name"])].append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
+    acc = defaultdict(lambda: defaultdict(list))
+    for r in csv.DictReader(open(csv_path)):
+        acc[short_name(r["Kernel_Name"])][r["Counter_Name"]].append(float(r["Counter_Value"]))
+    lines = ["# rocprofv3 counters (median per dispatch) and VALU issue utilisation",
+             "# command: " + command,
+             "# VALU util = SQ_INSTS_VALU / (%d CUs x %.1f GHz x median duration of the same run's dispatches)"
+             % (CUS, CLOCK_HZ / 1e9), "#"]
+    for k in sorted(acc, key=lambda k: -max(acc[k].get("SQ_INSTS_VALU", [0]))):
+        med = {c: sorted(v)[len(v) // 2] for c, v in acc[k].items()}
+        util = ""
+        if dur.get(k) and "SQ_INSTS_VALU" in med:
+            us = sorted(dur[k])[len(dur[k]) // 2]
+            util = "  VALU util %.2f (median %.1f us, %d dispatches)" % (
+                med["SQ_INSTS_VALU"] / (CUS * CLOCK_HZ * us * 1e-6), us, len(dur[k]))
+        lines.append(k + util)
+        lines.append("    " + ", ".join("%s %d" % (c, v) for c, v in sorted(med.items())))
+    open(out_path, "w").write("\n".join(lines) + "\n")
+
+
 if __name__ == "__main__":
     if sys.argv[1] == "stats":
         extra = sys.argv[5:7] + [int(v) for v in sys.argv[7:9]] if len(sys.argv) > 7 else []
         stats(sys.argv[2], sys.argv[3], sys.argv[4], *extra)
     elif sys.argv[1] == "traffic":
         traffic(sys.argv[2], sys.argv[3], sys.argv[4], sys.argv[5], sys.argv[6])
+    elif sys.argv[1] == "counters":
+        counters(sys.argv[2], sys.argv[3], sys.argv[4], sys.argv[5])
     else:
         raise SystemExit(__doc__)
