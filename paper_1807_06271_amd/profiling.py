@@ -33,11 +33,28 @@ CALIBRATION_BYTES = 1 << 30  # 1 GiB device-to-device copy
 PKG = os.path.dirname(os.path.abspath(__file__))
 
 
-def source_hash(files=("aggregate.hip", "device_util.h", "sgm_kernels.h")) -> str:
+def _header_section(name: str, marker: str) -> bytes:
+    """The shared preamble of a kernel header plus one of its "// ---- name"
+    sections (what a kernel's code depends on in that header)."""
+    text = open(os.path.join(PKG, "csrc", name), encoding="utf-8").read()
+    cuts = [i for i in range(len(text)) if text.startswith("// ---", i) and (i == 0 or text[i - 1] == "\n")]
+    pre = text[:cuts[0]] if cuts else text
+    body = ""
+    for a, b in zip(cuts, cuts[1:] + [len(text)]):
+        if marker in text[a:text.index("\n", a)]:
+            body = text[a:b]
+    return (pre + body).encode()
+
+
+def source_hash(files=("aggregate.hip", "device_util.h")) -> str:
+    """Hash of the aggregation kernel's sources: its file, the device helpers
+    and the aggregation section of the kernel header (changes elsewhere in
+    the header do not touch the kernel)."""
     h = hashlib.sha256()
     for f in files:
         with open(os.path.join(PKG, "csrc", f), "rb") as fh:
             h.update(fh.read())
+    h.update(_header_section("sgm_kernels.h", "aggregation"))
     return h.hexdigest()[:16]
 
 
@@ -107,7 +124,9 @@ def traffic(fetch_csv: str, write_csv: str, out_path: str, fetch_cmd: str, write
     out = {"calibration": {"kernel": short_name(cname), "bytes": CALIBRATION_BYTES,
                            "fetch_kib": cfetch, "write_kib": cwrite,
                            "fetch_factor": fetch_factor, "write_factor": write_factor},
-           "source_hash": source_hash(), "fetch_command": fetch_cmd, "write_command": write_cmd,
+           "source_hash": source_hash(),
+           "source_hash_covers": "aggregate.hip, device_util.h and the aggregation section of sgm_kernels.h",
+           "fetch_command": fetch_cmd, "write_command": write_cmd,
            "kernels": kernels}
     json.dump(out, open(out_path, "w"), indent=1)
     return out
