@@ -556,6 +556,12 @@ int enqueue_frames(const sgm_frame *fr, int n, const std::vector<FramePlan> &pla
   CHECK(mark.end(groups));
   CHECK(mark.begin(SGM_STAGE_DISPARITY));
   groups = 0;
+  // split image rows across blocks only when the batch's rows are too few to
+  // fill the chip on their own
+  int disp_rows = 0;
+  for (int i = 0; i < n; ++i)
+    if (!sweep[i]) disp_rows += fr[i].p.height;
+  const bool split = disp_rows < kDispSplitRows;
   {
     std::vector<LRJob> lj;
     for (int i = 0; i < n; ++i) {
@@ -595,6 +601,7 @@ int enqueue_frames(const sgm_frame *fr, int n, const std::vector<FramePlan> &pla
       j.D = p.max_disp;
       j.Dp = dp_of(p);
       j.lr_check = p.lr_check;
+      disp_segments(p.width, p.max_disp, split, &j.nseg, &j.seglen);
       dj.push_back(j);
     }
     if (!dj.empty()) {
@@ -615,7 +622,7 @@ int enqueue_frames(const sgm_frame *fr, int n, const std::vector<FramePlan> &pla
       j.W = p.width;
       j.H = p.height;
       j.D = p.max_disp;
-      disp_segments(p.width, p.max_disp, &j.nseg, &j.seglen);
+      disp_segments(p.width, p.max_disp, split, &j.nseg, &j.seglen);
       j.max_diff = p.lr_max_diff;
       j.invalid = p.invalid;
       lj.push_back(j);
@@ -932,6 +939,8 @@ int sgm_disparity(sgm_ctx *c, const sgm_params *p, const uint16_t *aggr, uint16_
   j.D = p->max_disp;
   j.Dp = dp_of(*p);
   j.lr_check = p->lr_check;
+  const bool split = p->height < kDispSplitRows;
+  disp_segments(p->width, p->max_disp, split, &j.nseg, &j.seglen);
   launch_disparity({j}, 0, s);
   CHECK(check_launch());
   if (p->lr_check) {
@@ -942,7 +951,7 @@ int sgm_disparity(sgm_ctx *c, const sgm_params *p, const uint16_t *aggr, uint16_
     l.W = p->width;
     l.H = p->height;
     l.D = p->max_disp;
-    disp_segments(p->width, p->max_disp, &l.nseg, &l.seglen);
+    disp_segments(p->width, p->max_disp, split, &l.nseg, &l.seglen);
     l.max_diff = p->lr_max_diff;
     l.invalid = p->invalid;
     launch_lr_seg({l}, s);

@@ -110,16 +110,17 @@ struct DispShape {
   static constexpr int THREADS = (K < 16 && 2 * NPX * RAW <= 64) ? 1024 : 512;
 };
 
-void disp_segments(int W, int D, int *nseg, int *seglen) {
+void disp_segments(int W, int D, bool split, int *nseg, int *seglen) {
   const int target = std::max(256, 2 * D);
-  const int n = std::max(1, W / target);
+  const int n = split ? std::max(1, W / target) : 1;
   *nseg = n;
   *seglen = (W + n - 1) / n;
 }
 
 size_t disp_part_bytes(int W, int H, int D) {
+  // H * nseg * (seglen + D - 1) grows with nseg: size for the split case
   int nseg, seglen;
-  disp_segments(W, D, &nseg, &seglen);
+  disp_segments(W, D, true, &nseg, &seglen);
   return (size_t)H * nseg * (seglen + D - 1) * 4;
 }
 
@@ -239,8 +240,7 @@ void launch_disparity(std::vector<DispJob> jobs, int in_kind, hipStream_t s) {
     std::vector<DispJob> sub;
     int maxz = 0;
     for (auto &j : jobs)
-      if (agg_k(j.D) == K) {
-        disp_segments(j.W, j.D, &j.nseg, &j.seglen);
+      if (agg_k(j.D) == K) {  // nseg / seglen chosen by the caller
         sub.push_back(j);
         maxz = std::max(maxz, std::min(j.W, j.seglen) + j.D - 1);
       }

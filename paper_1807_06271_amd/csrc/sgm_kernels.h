@@ -116,10 +116,13 @@ struct DispJob {
   int nseg, seglen;   // row segments (disp_segments)
   int blk0;
 };
-// Rows are split into nseg segments of seglen pixels (seglen >= D - 1 unless
-// one segment covers the row) so that a frame gives many blocks.
-void disp_segments(int W, int D, int *nseg, int *seglen);
-// Bytes of DispJob::part for a frame.
+// Row segments of the disparity kernel: with split, nseg segments of seglen
+// pixels (seglen >= D - 1 unless one segment covers the row), so that a
+// frame alone gives enough blocks; without, whole rows.  Batches whose rows
+// already fill the chip use whole rows (fewer, longer blocks).
+void disp_segments(int W, int D, bool split, int *nseg, int *seglen);
+constexpr int kDispSplitRows = 1024;  // split rows when a launch has fewer
+// Bytes of DispJob::part for a frame (enough for either choice).
 size_t disp_part_bytes(int W, int H, int D);
 // Left-right check from D_L and the segments' right-view keys.
 struct LRSegJob {

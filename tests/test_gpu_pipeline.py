@@ -111,6 +111,24 @@ def test_mixed_batch_matches_alone_and_oracle(env):
         assert_equal(to_np(alone["disp"]), to_np(f.disp), "alone vs batch " + tag)
 
 
+def test_batch_with_many_rows_uses_whole_rows_and_matches_oracle(env):
+    # more than 1024 image rows in one batch: disparity selection runs on
+    # whole rows (one block per row) instead of row segments
+    torch, sgm, ctx = env
+    announce("batch of 5 x 300x220 (1100 rows)")
+    frames, inputs = [], []
+    for k in range(5):
+        left, right, _ = synthetic.make_pair("kitti", 300 + k, 300, 220, 64)
+        p = sgm.Params(width=300, height=220, max_disp=64, census_w=9, census_h=7, median=3 if k % 2 else 0)
+        frames.append(sgm.Frame.alloc(p, to_dev(torch, left), to_dev(torch, right)))
+        inputs.append((p, left, right))
+    sgm.sgm_wait(ctx, sgm.sgm_submit(ctx, frames))
+    for (p, left, right), f in zip(inputs, frames):
+        want = oracle_for(p, left, right)
+        assert_equal(to_np(f.disp), want["disp"], "disp")
+        assert_equal(to_np(f.umap), want["umap"], "umap")
+
+
 def test_constant_images_give_zero_disparity(env):
     torch, sgm, ctx = env
     announce("constant images")

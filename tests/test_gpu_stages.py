@@ -115,8 +115,11 @@ def test_aggregate_masks(env, mask, W, H, D, cw, ch, p1, p2):
     assert_equal(to_np(out), O.aggregate(c, mask, p1, p2), "S mask %x" % mask)
 
 
+# the wide shapes split rows into 2, 3 and 4 segments (the last one ragged);
+# the right-view keys of pixels near a segment border come from two segments
 @pytest.mark.parametrize("W,H,D", [(1, 1, 1), (5, 4, 16), (97, 13, 60), (64, 9, 64), (100, 7, 100),
-                                   (131, 11, 128), (77, 5, 256), (3, 6, 40)])
+                                   (131, 11, 128), (77, 5, 256), (3, 6, 40), (600, 5, 32), (1100, 3, 128),
+                                   (1601, 2, 200)])
 @pytest.mark.parametrize("lr,med", [(0, 0), (1, 0), (1, 3), (1, 5), (0, 5)])
 def test_disparity(env, W, H, D, lr, med):
     torch, sgm, ctx = env
