@@ -243,7 +243,7 @@ __device__ __forceinline__ void agg_wave(const AggJob &J, int slot, int wave_in_
 #pragma unroll
           for (int q = 0; q < K / 4; ++q)  // low bytes of the four 16-bit values
             pk.v[q] = __builtin_amdgcn_perm(as_u32(Lc[2 * q + 1]), as_u32(Lc[2 * q]), 0x06040200u);
-          *reinterpret_cast<U32N<K / 4> *>(o) = pk;
+          store_nt<K / 4>(o, pk);  // read once, by the disparity kernel
         } else {  // K = 2 or 6: 2-byte aligned, one 16-bit store per pair
 #pragma unroll
           for (int q = 0; q < NP; ++q)
@@ -254,7 +254,7 @@ __device__ __forceinline__ void agg_wave(const AggJob &J, int slot, int wave_in_
         U32N<NP> pk;
 #pragma unroll
         for (int q = 0; q < NP; ++q) pk.v[q] = as_u32(Lc[q]);
-        *reinterpret_cast<U32N<NP> *>(o) = pk;
+        store_nt<NP>(o, pk);
       }
     }
     u16x2 lm = Lc[0];

@@ -81,6 +81,53 @@ struct alignas(4) U32N {
   uint32_t v[N];
 };
 
+// Non-temporal (streaming) vector store / load of N consecutive words, for
+// data written once and read once by a later kernel: the path-cost volumes
+// then do not linger as dirty lines in the caches, whose write-back would
+// compete with the next kernel's reads.  Word alignment is enough.
+typedef uint32_t u32x2a __attribute__((ext_vector_type(2), aligned(4)));
+typedef uint32_t u32x4a __attribute__((ext_vector_type(4), aligned(4)));
+
+template <int N>
+__device__ __forceinline__ void store_nt(void *p, const U32N<N> &v) {
+  if constexpr (N == 2) {
+    __builtin_nontemporal_store(u32x2a{v.v[0], v.v[1]}, reinterpret_cast<u32x2a *>(p));
+  } else if constexpr (N == 4) {
+    __builtin_nontemporal_store(u32x4a{v.v[0], v.v[1], v.v[2], v.v[3]}, reinterpret_cast<u32x4a *>(p));
+  } else if constexpr (N % 4 == 0) {
+#pragma unroll
+    for (int i = 0; i < N; i += 4)
+      __builtin_nontemporal_store(u32x4a{v.v[i], v.v[i + 1], v.v[i + 2], v.v[i + 3]},
+                                  reinterpret_cast<u32x4a *>(p) + i / 4);
+  } else {
+#pragma unroll
+    for (int i = 0; i < N; ++i) __builtin_nontemporal_store(v.v[i], reinterpret_cast<uint32_t *>(p) + i);
+  }
+}
+
+template <int N>
+__device__ __forceinline__ U32N<N> load_nt(const void *p) {
+  U32N<N> r;
+  if constexpr (N == 2) {
+    const u32x2a a = __builtin_nontemporal_load(reinterpret_cast<const u32x2a *>(p));
+    r.v[0] = a.x;
+    r.v[1] = a.y;
+  } else if constexpr (N % 4 == 0) {
+#pragma unroll
+    for (int i = 0; i < N; i += 4) {
+      const u32x4a a = __builtin_nontemporal_load(reinterpret_cast<const u32x4a *>(p) + i / 4);
+      r.v[i] = a.x;
+      r.v[i + 1] = a.y;
+      r.v[i + 2] = a.z;
+      r.v[i + 3] = a.w;
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < N; ++i) r.v[i] = __builtin_nontemporal_load(reinterpret_cast<const uint32_t *>(p) + i);
+  }
+  return r;
+}
+
 __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
 // Index of the job owning global block (or wave) index `b`: the last job with

@@ -47,7 +47,7 @@ __device__ __forceinline__ void load_raw(const DispJob &J, int64_t pix, int dbas
 #pragma unroll
     for (int p = 0; p < 8; ++p)
       if (p < J.P) {
-        const U32N<WPS> v = *reinterpret_cast<const U32N<WPS> *>(b + p * slot);
+        const U32N<WPS> v = load_nt<WPS>(b + p * slot);  // each path cost is read once
 #pragma unroll
         for (int i = 0; i < WPS; ++i) r.w[p * WPS + i] = v.v[i];
       }
