@@ -77,17 +77,24 @@ __device__ __forceinline__ int swz(int i) { return i + (i >> 2); }
 
 template <int CW, int CH>
 __device__ __forceinline__ uint64_t census_fixed(const uint8_t *rows, int stride, int x) {
-  constexpr int RX = CW / 2, RY = CH / 2;
-  const uint8_t c = rows[RY * stride + x + RX];
-  uint64_t code = 0;
+  constexpr int RX = CW / 2, RY = CH / 2, NB = CW * CH - 1;
+  const uint32_t c = rows[RY * stride + x + RX];
+  // neighbour n (raster order, centre skipped) goes to bit NB - 1 - n: the
+  // positions are compile-time constants, so each bit is a compare and a
+  // select into one of two 32-bit halves
+  uint32_t lo = 0, hi = 0;
+  int n = 0;
 #pragma unroll
   for (int dy = 0; dy < CH; ++dy)
 #pragma unroll
     for (int dx = 0; dx < CW; ++dx) {
       if (dy == RY && dx == RX) continue;
-      code = (code << 1) | (uint64_t)(rows[dy * stride + x + dx] < c);
+      const int bit = NB - 1 - n++;
+      const bool lt = rows[dy * stride + x + dx] < c;
+      if (bit >= 32) hi |= lt ? 1u << (bit - 32) : 0u;
+      else lo |= lt ? 1u << bit : 0u;
     }
-  return code;
+  return (uint64_t)hi << 32 | lo;
 }
 
 __device__ __forceinline__ uint64_t census_any(const uint8_t *rows, int stride, int x, int cw, int ch) {
@@ -129,29 +136,21 @@ __global__ __launch_bounds__(256) void census_cost_kernel(JobTable<FusedCostJob>
   uint8_t *rowsL = reinterpret_cast<uint8_t *>(lds64 + kSeg + kCodeRSlots);  // [ch][sl]
   uint8_t *rowsR = rowsL + J.ch * (kSeg + 2 * rx);                       // [ch][sr]
   {
-    // all staged bytes of both views, enumerated as one flat index space;
-    // each thread issues its loads in groups of 8 before storing to LDS so
-    // their latencies overlap
-    const int nR = J.ch * sr, nAll = nR + J.ch * sl;
-    for (int base = threadIdx.x; base < nAll; base += 8 * blockDim.x) {
-      uint8_t v[8];
-#pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const int i = base + u * blockDim.x;
-        if (i < nAll) {
-          const bool isR = i < nR;
-          const int k = isR ? i : i - nR;
-          const int len = isR ? sr : sl;
-          const int r = k / len, c = k - r * len;
-          const int64_t gy = (int64_t)min(max(y - ry + r, 0), H - 1) * J.pitch;
-          const int gx = min(max((isR ? xr0 : x0) - rx + c, 0), W - 1);
-          v[u] = (isR ? J.right : J.left)[gy + gx];
-        }
-      }
-#pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const int i = base + u * blockDim.x;
-        if (i < nAll) (i < nR ? rowsR[i] : rowsL[i - nR]) = v[u];
+    // the window rows of both views, row by row (no index division); each
+    // thread issues a row's loads of both views before storing them
+    for (int r = 0; r < J.ch; ++r) {
+      const int64_t gy = (int64_t)min(max(y - ry + r, 0), H - 1) * J.pitch;
+      const uint8_t *li = J.left + gy, *ri = J.right + gy;
+      for (int c0 = threadIdx.x; c0 < sr; c0 += 2 * blockDim.x) {
+        const int c1 = c0 + blockDim.x;
+        const uint8_t vr0 = ri[min(max(xr0 - rx + c0, 0), W - 1)];
+        const uint8_t vr1 = c1 < sr ? ri[min(max(xr0 - rx + c1, 0), W - 1)] : 0;
+        const uint8_t vl0 = c0 < sl ? li[min(max(x0 - rx + c0, 0), W - 1)] : 0;
+        const uint8_t vl1 = c1 < sl ? li[min(max(x0 - rx + c1, 0), W - 1)] : 0;
+        rowsR[r * sr + c0] = vr0;
+        if (c1 < sr) rowsR[r * sr + c1] = vr1;
+        if (c0 < sl) rowsL[r * sl + c0] = vl0;
+        if (c1 < sl) rowsL[r * sl + c1] = vl1;
       }
     }
   }
@@ -165,33 +164,45 @@ __global__ __launch_bounds__(256) void census_cost_kernel(JobTable<FusedCostJob>
   }
   __syncthreads();
   // each thread keeps one 4-disparity group q of the padded row and walks
-  // the segment's pixels: no division in the loop
+  // the segment 4 pixels at a time: the 16 cells of pixels x..x+3 and
+  // disparities d0..d0+3 use the 7 right-view codes x-d0-3 .. x-d0+3
   const int qpp = Dp >> 2;               // dwords per pixel (16..64)
-  const int groups = blockDim.x / qpp;   // pixels per sweep
+  const int groups = blockDim.x / qpp;   // 4-pixel groups per sweep
   const int q = threadIdx.x % qpp, g = threadIdx.x / qpp;
   if (g >= groups) return;
   const int d0 = q * 4;
   uint32_t *out = reinterpret_cast<uint32_t *>(J.out8 + ((int64_t)y * W + x0) * Dp) + q;
-  // pixels x >= d0 + 3 with all four disparities below D need no checks
+  // groups with x >= d0 + 3 and all four disparities below D need no checks
   const bool full = d0 + 3 < D;
-  const int xs = max(0, d0 + 3 - x0);  // first segment pixel with x >= d0 + 3
-  for (int xi = g; xi < nx; xi += groups) {
+  for (int xi = 4 * g; xi < nx; xi += 4 * groups) {
     const int x = x0 + xi;
-    const uint64_t cl = codeL[xi];
-    uint32_t word = 0;
-    if (full && xi >= xs) {
+    if (full && x >= d0 + 3 && xi + 3 < nx) {
       const int i0 = x - d0 - xr0;  // index of the code at x - d0
+      uint64_t r[7];
 #pragma unroll
-      for (int b = 0; b < 4; ++b) word |= (uint32_t)__popcll(cl ^ codeR[swz(i0 - b)]) << (8 * b);
+      for (int k = 0; k < 7; ++k) r[k] = codeR[swz(i0 - 3 + k)];
+#pragma unroll
+      for (int p = 0; p < 4; ++p) {
+        const uint64_t cl = codeL[xi + p];
+        uint32_t word = 0;
+#pragma unroll
+        for (int b = 0; b < 4; ++b) word |= (uint32_t)__popcll(cl ^ r[p - b + 3]) << (8 * b);
+        out[(int64_t)(xi + p) * qpp] = word;
+      }
     } else {
+      for (int p = 0; p < 4 && xi + p < nx; ++p) {
+        const int xp = x + p;
+        const uint64_t cl = codeL[xi + p];
+        uint32_t word = 0;
 #pragma unroll
-      for (int b = 0; b < 4; ++b) {
-        const int d = d0 + b;
-        const int v = (d < D && x >= d) ? __popcll(cl ^ codeR[swz(max(x - d - xr0, 0))]) : J.nbits;
-        word |= (uint32_t)v << (8 * b);
+        for (int b = 0; b < 4; ++b) {
+          const int d = d0 + b;
+          const int v = (d < D && xp >= d) ? __popcll(cl ^ codeR[swz(max(xp - d - xr0, 0))]) : J.nbits;
+          word |= (uint32_t)v << (8 * b);
+        }
+        out[(int64_t)(xi + p) * qpp] = word;
       }
     }
-    out[(int64_t)xi * qpp] = word;
   }
 }
 
