@@ -129,6 +129,26 @@ def test_batch_with_many_rows_uses_whole_rows_and_matches_oracle(env):
         assert_equal(to_np(f.umap), want["umap"], "umap")
 
 
+@pytest.mark.parametrize("W,H,D,mask", [(16384, 2, 64, 0xFF), (2, 16384, 16, 0xFF), (100, 3, 256, 0x0F),
+                                        (700, 1, 128, 0x03)])
+def test_extreme_shapes_match_oracle(env, W, H, D, mask):
+    # the widest and tallest frames the parameter check accepts, D larger
+    # than the width, and a single row
+    torch, sgm, ctx = env
+    announce("extreme shape", W, H, D, hex(mask))
+    rng = np.random.default_rng(W + H + D)
+    left = synthetic.random_image(rng, H, W)
+    right = np.roll(left, -3, axis=1)
+    p = sgm.Params(width=W, height=H, max_disp=D, census_w=5, census_h=5, path_mask=mask, median=3,
+                   invalid=65535 if D == 256 else 255)
+    f = sgm.Frame.alloc(p, to_dev(torch, left), to_dev(torch, right))
+    sgm.sgm_wait(ctx, sgm.sgm_submit(ctx, [f]))
+    want = oracle_for(p, left, right)
+    assert_equal(to_np(f.disp), want["disp"], "disp")
+    assert_equal(to_np(f.umap), want["umap"], "umap")
+    assert_equal(to_np(f.vmap), want["vmap"], "vmap")
+
+
 def test_constant_images_give_zero_disparity(env):
     torch, sgm, ctx = env
     announce("constant images")
