@@ -193,8 +193,8 @@ int sgm_disparity(sgm_ctx *ctx, const sgm_params *p, const uint16_t *aggr, uint1
 
 /* U-/V-maps (section 3.2): per-column and per-row disparity histograms of
  * disp; values >= D (the invalid marker) are not counted.  disp: device
- * uint16 [H][W]; umap: device uint16 [D][W], 4-byte aligned (SGM_EINVAL
- * otherwise); vmap: device uint16 [H][D]. */
+ * uint16 [H][W]; umap: device uint16 [D][W]; vmap: device uint16 [H][D].
+ * Every count is written (the maps need no clearing beforehand). */
 int uv_maps(sgm_ctx *ctx, const sgm_params *p, const uint16_t *disp, uint16_t *umap,
             uint16_t *vmap, void *stream);
 
@@ -231,8 +231,7 @@ int uv_filter(sgm_ctx *ctx, const uv_filter_job *jobs, int n, void *stream);
 
 /* One frame of the whole path for sgm_submit.  left/right: device uint8
  * [H][pitch] sharing one pitch; disp, umap, vmap: device outputs as above
- * (umap 4-byte aligned; umap and vmap may both be NULL to skip the
- * histograms). */
+ * (umap and vmap may both be NULL to skip the histograms). */
 typedef struct {
   const uint8_t *left, *right;
   int64_t pitch;

@@ -406,7 +406,6 @@ int enqueue_frames(const sgm_frame *fr, int n, const std::vector<FramePlan> &pla
   // frames); SAD costs (one launch for all SAD frames, U-maps cleared apart)
   std::vector<FusedCostJob> fj;
   std::vector<SadJob> sj;
-  std::vector<ZeroJob> zj;
   std::vector<CensusJob> cj;  // sweep frames: Census codes of both views
   for (int i = 0; i < n; ++i) {
     const sgm_params &p = fr[i].p;
@@ -423,7 +422,6 @@ int enqueue_frames(const sgm_frame *fr, int n, const std::vector<FramePlan> &pla
         j.ch = p.census_h;
         cj.push_back(j);
       }
-      if (fr[i].umap) zj.push_back(ZeroJob{fr[i].umap, (int64_t)p.max_disp * p.width, 0});
       continue;
     }
     if (is_sad(p)) {
@@ -439,7 +437,6 @@ int enqueue_frames(const sgm_frame *fr, int n, const std::vector<FramePlan> &pla
       j.wh = p.census_h;
       j.ostride = dp_of(p);
       sj.push_back(j);
-      if (fr[i].umap) zj.push_back(ZeroJob{fr[i].umap, (int64_t)p.max_disp * p.width, 0});
       continue;
     }
     FusedCostJob j{};
@@ -447,7 +444,6 @@ int enqueue_frames(const sgm_frame *fr, int n, const std::vector<FramePlan> &pla
     j.right = fr[i].right;
     j.pitch = fr[i].pitch;
     j.out8 = reinterpret_cast<uint8_t *>(mem + plans[i].off_cost);
-    j.umap = fr[i].umap;
     j.W = p.width;
     j.H = p.height;
     j.D = p.max_disp;
@@ -471,11 +467,6 @@ int enqueue_frames(const sgm_frame *fr, int n, const std::vector<FramePlan> &pla
   }
   if (!cj.empty()) {
     launch_census(cj, s);
-    CHECK(check_launch());
-    ++launches;
-  }
-  if (!zj.empty()) {  // U-maps of frames whose cost kernel does not clear them
-    launch_zero(zj, s);
     CHECK(check_launch());
     ++launches;
   }
@@ -979,8 +970,6 @@ int uv_maps(sgm_ctx *c, const sgm_params *p, const uint16_t *disp, uint16_t *uma
   CHECK(check_dev_ptr(disp, c->device, "disp"));
   CHECK(check_dev_ptr(umap, c->device, "umap"));
   CHECK(check_dev_ptr(vmap, c->device, "vmap"));
-  if (reinterpret_cast<uintptr_t>(umap) & 3) return fail(SGM_EINVAL, "umap must be 4-byte aligned");
-  launch_zero({ZeroJob{umap, (int64_t)p->max_disp * p->width, 0}}, (hipStream_t)stream);
   UVJob j{};
   j.disp = disp;
   j.U = umap;
@@ -1021,8 +1010,6 @@ static int submit_impl(sgm_ctx *c, const sgm_frame *frames, const sgm_remap *rem
     if (frames[i].umap) {
       CHECK(check_dev_ptr(frames[i].umap, c->device, "umap"));
       CHECK(check_dev_ptr(frames[i].vmap, c->device, "vmap"));
-      if (reinterpret_cast<uintptr_t>(frames[i].umap) & 3)
-        return fail(SGM_EINVAL, "frame %d: umap must be 4-byte aligned", i);
     }
   }
   std::vector<RemapJob> rect;

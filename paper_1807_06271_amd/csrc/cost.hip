@@ -66,8 +66,7 @@ __global__ __launch_bounds__(256) void cost_kernel(JobTable<CostJob> t) {
 // into LDS, then writes the segment's padded uint8 costs.  Saves the Census
 // round trip through HBM and two launches per batch; the right-view codes of
 // the D - 1 halo pixels are computed twice (by this and the previous
-// segment).  Blocks of segment 0 also clear the caller's U-map rows
-// d = y, y + H, ... (the U-map kernel accumulates into it at the end).
+// segment).
 
 constexpr int kSeg = 256;
 // LDS slots for the swizzled right-view codes: swz(kSeg + 255 - 1) + 1
@@ -154,9 +153,6 @@ __global__ __launch_bounds__(256) void census_cost_kernel(JobTable<FusedCostJob>
       }
     }
   }
-  if (J.umap && x0 == 0)
-    for (int d = y; d < D; d += H)
-      for (int x = threadIdx.x; x < W; x += blockDim.x) J.umap[(int64_t)d * W + x] = 0;
   __syncthreads();
   for (int i = threadIdx.x; i < nr; i += blockDim.x) {
     codeR[swz(i)] = census_at(rowsR, sr, i, J.cw, J.ch);

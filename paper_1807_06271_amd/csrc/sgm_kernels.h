@@ -40,13 +40,11 @@ struct CostJob {
 void launch_cost(std::vector<CostJob> jobs, hipStream_t s);
 
 // Census of both views and the padded uint8 costs of one row segment per
-// block (LDS holds the segment's codes and the image rows of the window),
-// and clears the U-map (if given) for the accumulation at the end of the batch.
+// block (LDS holds the segment's codes and the image rows of the window).
 struct FusedCostJob {
   const uint8_t *left, *right;
   int64_t pitch;
   uint8_t *out8;    // [H][W][Dp]
-  uint16_t *umap;   // [D][W] or null
   int W, H, D, Dp, nbits, cw, ch;
   int blk0;
 };
@@ -152,16 +150,10 @@ struct UVJob {
   uint16_t *U, *V;  // [D][W], [H][D]
   int W, H, D;
   int blk0;         // first block; blocks [blk0, blk0+H) build V rows,
-  int ublocks;      // then `ublocks` blocks (64 columns x 64 rows) add into U
+  int ublocks;      // then `ublocks` blocks build 16-column strips of U
 };
 void launch_uv(std::vector<UVJob> jobs, hipStream_t s);
 
-struct ZeroJob {
-  uint16_t *p;
-  int64_t n;
-  int blk0;
-};
-void launch_zero(std::vector<ZeroJob> jobs, hipStream_t s);
 
 // ----------------------------------------------------- single-pass sweep
 // The forward path set {L2R, TL2BR, T2B, TR2BL} (all predecessors lie above
