@@ -65,7 +65,20 @@ def time_submit_stream(torch, sgm, ctx, frames_fn, steps, warmup, depth=8):
     return time.perf_counter() - t0, outs
 
 
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(left, right, p, seconds_target=12.0):
+    """The oracle on the host: whole pairs with OpenMP over scanlines on all
+    the cores it gets (the reported value), then one thread on a 94-row crop
+    of the same pair (a bounded sample, scaled to the same unit)."""
     from oracle import oracle as O
     threads = O.threads()
     runs, t_total = 0, 0.0
@@ -77,10 +90,23 @@ def cpu_baseline(left, right, p, seconds_target=12.0):
         runs += 1
         if runs >= 5:
             break
+    rows = min(94, p.height)
+    O.set_threads(1)
+    try:
+        t0 = time.perf_counter()
+        O.sgm(left[:rows], right[:rows], p.max_disp, p.census_w, p.census_h, p.path_mask, p.p1, p.p2, True,
+              p.lr_max_diff, p.median, p.inv())
+        t1 = time.perf_counter() - t0
+    finally:
+        O.set_threads(threads)
+    one = p.width * rows * p.max_disp * bin(p.path_mask).count("1") / t1 / 1e6
     return {"value": round(runs * p.disp_evals() / t_total / 1e6, 2), "unit": "Mdisp-evals/s",
             "cores": threads, "kind": "oracle",
             "sample": "%d full %dx%d D=%d 8-path pairs through the C oracle (-O2, OpenMP over "
-                      "scanlines), %.1f s" % (runs, p.width, p.height, p.max_disp, t_total)}
+                      "scanlines), %.1f s" % (runs, p.width, p.height, p.max_disp, t_total),
+            "single_thread": {"value": round(one, 2), "sample": "one %dx%d crop, one thread, %.1f s"
+                              % (p.width, rows, t1)},
+            "cpu_model": cpu_model(), "host_cpus": os.cpu_count()}
 
 
 def bench_small(torch, sgm, ctx, synthetic, steps=200):
@@ -308,6 +334,11 @@ def bench_batch32(torch, sgm, ctx, synthetic):
 
 
 def bench_large(torch, sgm, ctx, synthetic, nframes=8):
+    """Eight 1920x1080 D=256 pairs (8 paths, LR, 3x3 median, U/V): one submit
+    of all eight vs eight sequential one-frame submits on the same inputs
+    (outputs compared), and the aggregation kernel's roofline position, with
+    the HBM bytes it actually moves when the committed counter record for
+    this workload matches the kernel sources."""
     frames = []
     for i in range(nframes):
         L, R, _ = synthetic.make_pair("large", 4000 + i)
@@ -317,6 +348,7 @@ def bench_large(torch, sgm, ctx, synthetic, nframes=8):
     evals = sum(f.p.disp_evals() for f in frames)
     h_lanes = sgm.sgm_autotune(ctx, frames[0], reps=2)[0]
     sgm.sgm_wait(ctx, sgm.sgm_submit(ctx, frames))
+    batched = [f.disp.clone() for f in frames]
     sgm.sgm_profile_read(ctx, reset=True)
     torch.cuda.synchronize()
     reps = 2
@@ -329,12 +361,31 @@ def bench_large(torch, sgm, ctx, synthetic, nframes=8):
     agg_ms, agg_n = prof["aggregate"]
     agg_avg = agg_ms / max(agg_n, 1)
     achieved = ALG_BYTES_PER_EVAL * evals / (agg_avg * 1e-3) / 1e9
-    return {"frames": nframes, "width": 1920, "height": 1080, "max_disp": 256, "paths": 8,
-            "h_lanes": h_lanes,
-            "batch_ms": t * 1e3, "mdisp_evals_per_s": evals / t / 1e6, "fps": nframes / t,
-            "aggregate_launch_ms": agg_avg,
-            "aggregate_alg_GBs": achieved, "aggregate_hbm_frac": achieved / HBM_PEAK_GBS,
-            "stage_ms_per_batch": {k: v[0] / reps for k, v in prof.items()}}
+    # the same frames one submit at a time (queued back to back)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        ts = [sgm.sgm_submit(ctx, [f]) for f in frames]
+        for tk in ts:
+            sgm.sgm_wait(ctx, tk)
+    torch.cuda.synchronize()
+    tseq = (time.perf_counter() - t0) / reps
+    same = all(torch.equal(a, f.disp) for a, f in zip(batched, frames))
+    res = {"frames": nframes, "width": 1920, "height": 1080, "max_disp": 256, "paths": 8,
+           "h_lanes": h_lanes,
+           "batch_ms": t * 1e3, "mdisp_evals_per_s": evals / t / 1e6, "fps": nframes / t,
+           "sequential_submits_ms": tseq * 1e3, "sequential_mdisp_evals_per_s": evals / tseq / 1e6,
+           "batched_equals_sequential": bool(same),
+           "aggregate_launch_ms": agg_avg,
+           "aggregate_alg_GBs": achieved, "aggregate_hbm_frac": achieved / HBM_PEAK_GBS,
+           "stage_ms_per_batch": {k: v[0] / reps for k, v in prof.items()}}
+    moved = measured_traffic("agg_kernel<16, %d, %d, 0, unsigned char" % (256 // h_lanes, h_lanes),
+                             "traffic_agg_1920x1080_d256_batch8.json")
+    if moved is not None:
+        res["aggregate_measured_bytes"] = moved
+        res["aggregate_measured_GBs"] = moved / (agg_avg * 1e-3) / 1e9
+        res["aggregate_measured_hbm_frac"] = res["aggregate_measured_GBs"] / HBM_PEAK_GBS
+    return res
 
 
 def bench_serve(torch, sgm, synthetic, seconds, stress_cameras=48, stress_seconds=4.0):
@@ -372,11 +423,11 @@ def bench_serve(torch, sgm, synthetic, seconds, stress_cameras=48, stress_second
     return out
 
 
-def measured_traffic(kernel_prefix):
-    """HBM bytes per launch of the aggregation kernel from the committed
-    FETCH_SIZE / WRITE_SIZE counter runs (scaled by a copy of known size), or
+def measured_traffic(kernel_prefix, record="traffic_agg_1242x375_d128.json"):
+    """HBM bytes per launch of an aggregation kernel from a committed
+    FETCH_SIZE / WRITE_SIZE counter record (scaled by a copy of known size), or
     None when the kernel sources changed since the counters were taken."""
-    path = os.path.join(ROOT, "profiles", "traffic_agg_1242x375_d128.json")
+    path = os.path.join(ROOT, "profiles", record)
     if not os.path.exists(path):
         return None
     from paper_1807_06271_amd.profiling import source_hash
@@ -394,7 +445,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--extras", choices=["none", "batch", "all"], default="all")
+    ap.add_argument("--extras", choices=["none", "large", "batch", "all"], default="all",
+                    help="secondary measurements: none; large (the 8 x 1920x1080 batch only); "
+                         "batch (all batch forms); all (batch forms and the request loop)")
     ap.add_argument("--serve-seconds", type=float, default=10.0)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
@@ -494,6 +547,7 @@ def main():
         extras["paper_640x360_d60_4path"] = bench_paper_settings(torch, sgm, ctx, synthetic)
         log("batch of 32 mixed pairs")
         extras["batch32_mixed"] = bench_batch32(torch, sgm, ctx, synthetic)
+    if args.extras in ("large", "batch", "all"):
         log("batch of 8 1920x1080 D=256")
         extras["batch8_1920x1080_d256"] = bench_large(torch, sgm, ctx, synthetic)
     if args.extras == "all":

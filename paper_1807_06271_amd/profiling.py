@@ -3,7 +3,7 @@
     python -m paper_1807_06271_amd.profiling stats  <kernel_stats.csv> <out.txt> "<command>" \
         [<kernel_trace.csv> <kernel name part> <N dispatches> [<skip>]]
     python -m paper_1807_06271_amd.profiling traffic <fetch_counter_collection.csv> \
-        <write_counter_collection.csv> <out.json> "<fetch command>" "<write command>"
+        <write_counter_collection.csv> <out.json> "<fetch command>" "<write command>" [median|max]
     python -m paper_1807_06271_amd.profiling counters <counter_collection.csv> <kernel_trace.csv> \
         <out.txt> "<command>"
 
@@ -93,7 +93,10 @@ def _per_kernel(csv_path: str, counter: str):
     return acc
 
 
-def traffic(fetch_csv: str, write_csv: str, out_path: str, fetch_cmd: str, write_cmd: str) -> dict:
+def traffic(fetch_csv: str, write_csv: str, out_path: str, fetch_cmd: str, write_cmd: str,
+            pick: str = "median") -> dict:
+    """pick: "median" of each kernel's dispatches (all dispatches of one size),
+    or "max" (the largest dispatch, e.g. a whole batch among single frames)."""
     f = _per_kernel(fetch_csv, "FETCH_SIZE")
     w = _per_kernel(write_csv, "WRITE_SIZE")
     copy = [k for k in f if "copy" in k.lower() or "elementwise" in k.lower()]
@@ -113,11 +116,12 @@ def traffic(fetch_csv: str, write_csv: str, out_path: str, fetch_cmd: str, write
     for k in f:
         if k == cname:
             continue
-        fv = sorted(f[k])[len(f[k]) // 2]
-        wv = sorted(w.get(k, [0.0]))[len(w.get(k, [0.0])) // 2]
+        fs, ws = sorted(f[k]), sorted(w.get(k, [0.0]))
+        fv = fs[-1] if pick == "max" else fs[len(fs) // 2]
+        wv = ws[-1] if pick == "max" else ws[len(ws) // 2]
         kernels[short_name(k)] = {
             "dispatches": len(f[k]),
-            "fetch_kib_median": fv, "write_kib_median": wv,
+            "fetch_kib": fv, "write_kib": wv, "pick": pick,
             "fetch_bytes": fv * 1024.0 * fetch_factor,
             "write_bytes": wv * 1024.0 * (write_factor or 1.0),
         }
@@ -163,7 +167,7 @@ if __name__ == "__main__":
         extra = sys.argv[5:7] + [int(v) for v in sys.argv[7:9]] if len(sys.argv) > 7 else []
         stats(sys.argv[2], sys.argv[3], sys.argv[4], *extra)
     elif sys.argv[1] == "traffic":
-        traffic(sys.argv[2], sys.argv[3], sys.argv[4], sys.argv[5], sys.argv[6])
+        traffic(sys.argv[2], sys.argv[3], sys.argv[4], sys.argv[5], sys.argv[6], *sys.argv[7:8])
     elif sys.argv[1] == "counters":
         counters(sys.argv[2], sys.argv[3], sys.argv[4], sys.argv[5])
     else:
