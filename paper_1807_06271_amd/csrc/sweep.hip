@@ -143,22 +143,24 @@ __global__ __launch_bounds__(1024) void sweep_kernel(JobTable<SweepJob> t) {
     constexpr int S_ = decltype(stag)::value;
     const int y = b * kG + g;
     const bool ok = !writer && xx >= 0 && xx < W && y < H;
-    const int64_t o = ok ? (int64_t)y * W + xx : 0;
-    rcl[S_] = *reinterpret_cast<const uint32_t *>(Jcl + o);
-    rcr[S_] = *reinterpret_cast<const uint32_t *>(Jcr + o);
+    // byte offsets from block-uniform bases fit 32 bits (W*H*8 < 2^28 for
+    // an eligible frame; the carry rows are 2*W*256 bytes)
+    const uint32_t o = ok ? (uint32_t)(y * W + xx) * 8u : 0u;
+    rcl[S_] = *reinterpret_cast<const uint32_t *>(reinterpret_cast<const char *>(Jcl) + o);
+    rcr[S_] = *reinterpret_cast<const uint32_t *>(reinterpret_cast<const char *>(Jcr) + o);
     {  // only group 0 uses the carry row; every wave loads it so that all
        // paths through a step issue the same loads
       const int xc = min(max(xx, 0), W - 1);
-      const uint8_t *cb = Jcarry + (size_t)((max(b, 1) - 1) & 1) * W * kSweepCarry;
-      const uint8_t *c0 = cb + (size_t)xc * kSweepCarry;
-      const uint8_t *cm = cb + (size_t)max(xc - 1, 0) * kSweepCarry;
-      const uint8_t *cp = cb + (size_t)min(xc + 1, W - 1) * kSweepCarry;
-      rcv0[S_] = *reinterpret_cast<const uint32_t *>(c0 + dbase);
-      rcm0[S_] = *reinterpret_cast<const uint32_t *>(c0 + 192);
-      rcv1[S_] = *reinterpret_cast<const uint32_t *>(cm + 64 + dbase);
-      rcm1[S_] = *reinterpret_cast<const uint32_t *>(cm + 196);
-      rcv2[S_] = *reinterpret_cast<const uint32_t *>(cp + 128 + dbase);
-      rcm2[S_] = *reinterpret_cast<const uint32_t *>(cp + 200);
+      const uint32_t cb = (uint32_t)((max(b, 1) - 1) & 1) * (uint32_t)W * kSweepCarry;
+      const uint32_t c0 = cb + (uint32_t)xc * kSweepCarry;
+      const uint32_t cm = cb + (uint32_t)max(xc - 1, 0) * kSweepCarry;
+      const uint32_t cp = cb + (uint32_t)min(xc + 1, W - 1) * kSweepCarry;
+      rcv0[S_] = *reinterpret_cast<const uint32_t *>(Jcarry + (c0 + dbase));
+      rcm0[S_] = *reinterpret_cast<const uint32_t *>(Jcarry + (c0 + 192));
+      rcv1[S_] = *reinterpret_cast<const uint32_t *>(Jcarry + (cm + 64 + dbase));
+      rcm1[S_] = *reinterpret_cast<const uint32_t *>(Jcarry + (cm + 196));
+      rcv2[S_] = *reinterpret_cast<const uint32_t *>(Jcarry + (cp + 128 + dbase));
+      rcm2[S_] = *reinterpret_cast<const uint32_t *>(Jcarry + (cp + 200));
     }
   };
 
@@ -176,8 +178,8 @@ __global__ __launch_bounds__(1024) void sweep_kernel(JobTable<SweepJob> t) {
   advance(bandf, xf);
   u16x2 Lh[2] = {as_pair(pad[0]), as_pair(pad[1])};
   uint32_t mh = 0;
-  uint32_t crs[4] = {0u, 0u, 0u, 0u};     // cr(x - 4j - k)
-  uint32_t cand[4] = {kInf, kInf, kInf, kInf};  // right-view candidate of x - 4j - k
+  uint32_t crs[4] = {0u, 0u, 0u, 0u};           // cr(x - 4j - k), renamed per step
+  uint32_t cand[4] = {kInf, kInf, kInf, kInf};  // right-view candidate of x - 4j - k, likewise
 
   static_assert(kPF == 4, "the prefetch slots below are spelled out for kPF = 4");
   auto step = [&](auto stag) {
@@ -221,27 +223,29 @@ __global__ __launch_bounds__(1024) void sweep_kernel(JobTable<SweepJob> t) {
       // step behind (see the set-up below)
       const int y = band * kG + g;
       if (!writer && x >= 0 && x < W && y < H) {
-        if (x == 0) {  // row start: the L2R path and the right-view candidates begin anew
-          Lh[0] = as_pair(pad[0]);
-          Lh[1] = as_pair(pad[1]);
-          mh = 0;
+        // row start: the L2R path and the right-view candidates begin anew
+        const bool rs = x == 0;
+        Lh[0] = rs ? as_pair(pad[0]) : Lh[0];
+        Lh[1] = rs ? as_pair(pad[1]) : Lh[1];
+        mh = rs ? 0u : mh;
 #pragma unroll
-          for (int k = 0; k < 4; ++k) cand[k] = kInf;
-        }
-        // right-view codes move one disparity up; lane 0 takes cr(x)
-        const uint32_t in = (uint32_t)__builtin_amdgcn_update_dpp((int)ccr, (int)crs[3], kDppRowShr1, 0xF,
+        for (int k = 0; k < 4; ++k) cand[k] = rs ? kInf : cand[k];
+        // Right-view codes move one disparity up per step, lane 0 taking
+        // cr(x).  The four slots are renamed instead of moved: at step S_ of
+        // an unrolled group, slot k lives in crs[(k - S_) & 3], so the new
+        // slot 0 takes the register of the old slot 3 (the same for cand).
+        constexpr int R0 = (0 - S_) & 3;
+        const uint32_t in = (uint32_t)__builtin_amdgcn_update_dpp((int)ccr, (int)crs[R0], kDppRowShr1, 0xF,
                                                                   0xF, false);
-        crs[3] = crs[2];
-        crs[2] = crs[1];
-        crs[1] = crs[0];
-        crs[0] = in;
+        crs[R0] = in;
+        auto CR = [&](int k) -> uint32_t { return crs[(k - S_) & 3]; };
         // matching costs of equation (1), N_b left of the image
         u16x2 C[2];
 #pragma unroll
         for (int q = 0; q < 2; ++q) {
           const int d0 = dbase + 2 * q;
-          const uint32_t h0 = (uint32_t)__builtin_popcount(ccl ^ crs[2 * q]);
-          const uint32_t h1 = (uint32_t)__builtin_popcount(ccl ^ crs[2 * q + 1]);
+          const uint32_t h0 = (uint32_t)__builtin_popcount(ccl ^ CR(2 * q));
+          const uint32_t h1 = (uint32_t)__builtin_popcount(ccl ^ CR(2 * q + 1));
           const uint32_t c0 = x >= d0 ? h0 : nbits;
           const uint32_t c1 = x >= d0 + 1 ? h1 : nbits;
           C[q] = as_pair(c0 | c1 << 16);
@@ -264,19 +268,16 @@ __global__ __launch_bounds__(1024) void sweep_kernel(JobTable<SweepJob> t) {
           auto vpath = [&](auto vtag, bool on, bool has, int px, uint32_t carry_bytes, uint32_t carry_min) {
             constexpr int V = decltype(vtag)::value;
             if (!on) return;
-            u16x2 Lp[2] = {as_pair(pad[0]), as_pair(pad[1])};
-            uint32_t mp = 0;
-            if (has) {
-              uint32_t bytes = carry_bytes, m = carry_min;
-              if (g > 0) {
-                bytes = ring[g - 1][px & 3][V][j];
-                m = rmin[g - 1][px & 3][V];
-              }
-              unpack_bytes(bytes, Lp);
-              Lp[0] = as_pair(as_u32(Lp[0]) | pad[0]);
-              Lp[1] = as_pair(as_u32(Lp[1]) | pad[1]);
-              mp = m;
-            }
+            // the ring of the group above (group 0: the carry row); without a
+            // predecessor the path starts from all-zero costs
+            const int ga = max(g - 1, 0);
+            const uint32_t rb = ring[ga][px & 3][V][j], rm = rmin[ga][px & 3][V];
+            const uint32_t bytes = g > 0 ? rb : carry_bytes, m = g > 0 ? rm : carry_min;
+            u16x2 Lp[2];
+            unpack_bytes(bytes, Lp);
+            Lp[0] = as_pair(has ? as_u32(Lp[0]) | pad[0] : pad[0]);
+            Lp[1] = as_pair(has ? as_u32(Lp[1]) | pad[1] : pad[1]);
+            const uint32_t mp = has ? m : 0u;
             u16x2 Lc[2];
             path_step(Lp, mp, C, P1, P2, pad, Lc);
             const uint32_t mc = pair_min(Lc);
@@ -304,17 +305,13 @@ __global__ __launch_bounds__(1024) void sweep_kernel(JobTable<SweepJob> t) {
         const uint32_t best = row16_allmin_u32(min(min(key[0], key[1]), min(key[2], key[3])));
         if (j == 0) st_dl[buf][g] = (uint8_t)(best & 0xFF);
         // candidates move one disparity up, the new one (x_r = x) enters at d = 0
-        const uint32_t cin = (uint32_t)__builtin_amdgcn_update_dpp((int)kInf, (int)cand[3], kDppRowShr1, 0xF,
-                                                                   0xF, false);
-        cand[3] = cand[2];
-        cand[2] = cand[1];
-        cand[1] = cand[0];
-        cand[0] = cin;
+        cand[R0] = (uint32_t)__builtin_amdgcn_update_dpp((int)kInf, (int)cand[R0], kDppRowShr1, 0xF, 0xF, false);
 #pragma unroll
-        for (int k = 0; k < 4; ++k) cand[k] = min(cand[k], key[k]);
+        for (int k = 0; k < 4; ++k) cand[(k - S_) & 3] = min(cand[(k - S_) & 3], key[k]);
         // the candidate holding d = D-1 is final (x_r = x - D + 1), and at the
         // row end every candidate is (x_r + d' >= W beyond): stage them all
-        st_dr[buf][g][j] = (cand[0] & 0xFF) | (cand[1] & 0xFF) << 8 | (cand[2] & 0xFF) << 16 | (cand[3] & 0xFF) << 24;
+        st_dr[buf][g][j] = (cand[(0 - S_) & 3] & 0xFF) | (cand[(1 - S_) & 3] & 0xFF) << 8 |
+                           (cand[(2 - S_) & 3] & 0xFF) << 16 | (cand[(3 - S_) & 3] & 0xFF) << 24;
       }
       // refill the slot for the step kPF ahead once this step is done with
       // it, so that the slot's old and new values can share registers
