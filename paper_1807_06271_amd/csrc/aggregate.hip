@@ -137,7 +137,10 @@ __device__ __forceinline__ uint32_t group_allmin_u32(uint32_t v) {
 
 // One wave's share of one direction: 64/LPS scanlines side by side, LPS lanes
 // per scanline, K disparities per lane (K * LPS = Dp).
-template <int K, int LPS, int SRC, typename LT, int PF, bool PAD>
+// HS = +1 / -1: the wave runs a horizontal direction (L->R / R->L), whose
+// pixel step is known at compile time, so that every address of an unrolled
+// block is one base plus immediate offsets; HS = 0: any direction.
+template <int K, int LPS, int SRC, typename LT, int PF, bool PAD, int HS>
 __device__ __forceinline__ void agg_wave(const AggJob &J, int slot, int wave_in_slot) {
   constexpr int NP = K / 2;       // packed pairs per lane
   constexpr int SPW = 64 / LPS;   // scanlines per wave
@@ -155,7 +158,7 @@ __device__ __forceinline__ void agg_wave(const AggJob &J, int slot, int wave_in_
     maxlen = max(maxlen, __builtin_amdgcn_readlane(len, r * LPS));
     minlen = min(minlen, __builtin_amdgcn_readlane(len, r * LPS));
   }
-  const int64_t step = (int64_t)kDirDy[dir] * W + kDirDx[dir];  // pixel index step (uniform)
+  const int64_t step = HS ? HS : (int64_t)kDirDy[dir] * W + kDirDx[dir];  // pixel index step (uniform)
   const int64_t pix0 = (int64_t)sy * W + sx;
   const int dbase = j * K;
   // disparities of this lane below D (all K unless the row is padded, PAD)
@@ -178,15 +181,21 @@ __device__ __forceinline__ void agg_wave(const AggJob &J, int slot, int wave_in_
   const char *cbase = SRC == kCost8 ? reinterpret_cast<const char *>(J.cost8)
                                     : reinterpret_cast<const char *>(J.cost16);
   const uint32_t coff = (uint32_t)((pix0 * cpp + dbase) * CB);
-  const int64_t cstep = step * cpp * CB;
+  const int64_t cstep = HS ? (int64_t)HS * K * LPS * CB : step * cpp * CB;  // Dp = K * LPS
   char *obase = reinterpret_cast<char *>(J.lr) + (int64_t)slot * H * W * Dp * (int64_t)sizeof(LT);
   const uint32_t ooff = (uint32_t)((pix0 * Dp + dbase) * (int64_t)sizeof(LT));
-  const int64_t ostep = step * Dp * (int64_t)sizeof(LT);
+  const int64_t ostep = HS ? (int64_t)HS * K * LPS * (int64_t)sizeof(LT) : step * Dp * (int64_t)sizeof(LT);
 
+  // Loads are unconditional (a lane past its scanline's end re-reads the
+  // last pixel, a lane without a scanline pixel 0): a conditional load here
+  // would make the compiler wait for every outstanding access in the loops.
+  const int last = max(len - 1, 0);
   CostWords<K, SRC> ring[PF];
 #pragma unroll
-  for (int s = 0; s < PF; ++s)
-    if (s < len) load_cost<K, SRC>(ring[s], cbase + s * cstep + coff);
+  for (int s = 0; s < PF; ++s) {  // in ring order, which the waits in the loop assume
+    load_cost<K, SRC>(ring[s], cbase + min(s, last) * cstep + coff);
+    __builtin_amdgcn_sched_barrier(0);
+  }
 
   // A path's first pixel behaves as if its predecessor had all-zero path
   // costs: then every candidate is >= 0 = m, so L = C.
@@ -199,8 +208,9 @@ __device__ __forceinline__ void agg_wave(const AggJob &J, int slot, int wave_in_
   // the load and the store need no per-lane test
   auto pixel = [&](auto guard, int i, CostWords<K, SRC> &rs) {
     constexpr bool GUARD = decltype(guard)::value;
-    const CostWords<K, SRC> cw = rs;
-    if (!GUARD || i + PF < len) load_cost<K, SRC>(rs, cbase + (int64_t)(i + PF) * cstep + coff);
+    // keep each pixel's instructions together: hoisting the unpacking of
+    // later pixels' costs would wait on loads issued one pixel ago
+    __builtin_amdgcn_sched_barrier(0);
     // neighbour pairs: Nb[q] = (L[2q-1], L[2q]) for q = 0..NP, so that pair q
     // has its d-1 values in Nb[q] and its d+1 values in Nb[q+1]
     uint32_t prev, next;
@@ -231,10 +241,12 @@ __device__ __forceinline__ void agg_wave(const AggJob &J, int slot, int wave_in_
     for (int q = 0; q < NP; ++q) {
       u16x2 best = padd_sat(pmin(Nb[q], Nb[q + 1]), P1);
       best = pmin(pmin(best, Lp[q]), MP2);
-      u16x2 v = best - M + cost_pair<K, SRC>(cw, q);
+      u16x2 v = best - M + cost_pair<K, SRC>(rs, q);
       if (PAD) v = as_pair(as_u32(v) | padmask[q]);
       Lc[q] = v;
     }
+    // the slot's costs are used: refill it PF pixels ahead
+    load_cost<K, SRC>(rs, cbase + (int64_t)(GUARD ? min(i + PF, last) : i + PF) * cstep + coff);
     if (!GUARD || i < len) {
       char *o = obase + (int64_t)i * ostep + ooff;
       if (sizeof(LT) == 1) {
@@ -301,10 +313,13 @@ __global__ __launch_bounds__(256) void agg_kernel(JobTable<AggJob> t) {
   const int wave_in_slot = w - J.line0[slot];
   // Wider lane groups finish a pixel in fewer instructions, so they prefetch
   // proportionally further ahead to cover the same memory latency.
-  if (HLPS != 16 && J.dirs[slot] < 2)
-    agg_wave<KH, HLPS, SRC, LT, PF * HLPS / 16, PAD>(J, slot, wave_in_slot);
+  const int dir = J.dirs[slot];
+  if (dir == 0)
+    agg_wave<KH, HLPS, SRC, LT, PF * HLPS / 16, PAD, +1>(J, slot, wave_in_slot);
+  else if (dir == 1)
+    agg_wave<KH, HLPS, SRC, LT, PF * HLPS / 16, PAD, -1>(J, slot, wave_in_slot);
   else
-    agg_wave<K, 16, SRC, LT, PF, PAD>(J, slot, wave_in_slot);
+    agg_wave<K, 16, SRC, LT, PF, PAD, 0>(J, slot, wave_in_slot);
 }
 
 template <int K, int KH, int HLPS, int SRC, typename LT>
