@@ -69,8 +69,11 @@ __global__ __launch_bounds__(256) void cost_kernel(JobTable<CostJob> t) {
 // segment).
 
 constexpr int kSeg = 256;
-// LDS slots for the swizzled right-view codes: swz(kSeg + 255 - 1) + 1
-constexpr int kCodeRSlots = (kSeg + 255) + (kSeg + 255) / 4 + 1;
+// Right-view codes a segment reaches: kSeg + D - 1, plus up to 3 more because
+// the first one is aligned down to a multiple of 4; LDS slots for them,
+// swizzled: swz(kRightMax - 1) + 1
+constexpr int kRightMax = kSeg + 255 + 3;
+constexpr int kCodeRSlots = (kRightMax - 1) + (kRightMax - 1) / 4 + 1;
 
 __device__ __forceinline__ int swz(int i) { return i + (i >> 2); }
 
@@ -78,9 +81,12 @@ template <int CW, int CH>
 __device__ __forceinline__ uint64_t census_fixed(const uint8_t *rows, int stride, int x) {
   constexpr int RX = CW / 2, RY = CH / 2, NB = CW * CH - 1;
   const uint32_t c = rows[RY * stride + x + RX];
-  // neighbour n (raster order, centre skipped) goes to bit NB - 1 - n: the
-  // positions are compile-time constants, so each bit is a compare and a
-  // select into one of two 32-bit halves
+  // neighbour n (raster order, centre skipped) goes to bit NB - 1 - n, so
+  // the bits enter MSB first: the first NB - 32 neighbours shift into the high
+  // half, the last 32 (or all, for NB <= 32) into the low half.  n - c is
+  // negative exactly when I(q) < I(p), and v_alignbit({half, n - c}, 31)
+  // shifts the half left by one and appends that sign bit: one subtract and
+  // one alignbit per neighbour.
   uint32_t lo = 0, hi = 0;
   int n = 0;
 #pragma unroll
@@ -89,9 +95,9 @@ __device__ __forceinline__ uint64_t census_fixed(const uint8_t *rows, int stride
     for (int dx = 0; dx < CW; ++dx) {
       if (dy == RY && dx == RX) continue;
       const int bit = NB - 1 - n++;
-      const bool lt = rows[dy * stride + x + dx] < c;
-      if (bit >= 32) hi |= lt ? 1u << (bit - 32) : 0u;
-      else lo |= lt ? 1u << bit : 0u;
+      const uint32_t diff = (uint32_t)rows[dy * stride + x + dx] - c;
+      if (bit >= 32) hi = __builtin_amdgcn_alignbit(hi, diff, 31);
+      else lo = __builtin_amdgcn_alignbit(lo, diff, 31);
     }
   return (uint64_t)hi << 32 | lo;
 }
@@ -124,7 +130,9 @@ __global__ __launch_bounds__(256) void census_cost_kernel(JobTable<FusedCostJob>
   const int x0 = (tb - y * segs) * kSeg;
   const int W = J.W, H = J.H, D = J.D, Dp = J.Dp;
   const int nx = min(kSeg, W - x0);
-  const int xr0 = max(0, x0 - D + 1);  // first right-view pixel the segment reaches
+  // first right-view pixel the segment reaches, aligned down to a multiple of
+  // 4 so that the cost loop's code indices are 0 mod 4 (fixed LDS offsets)
+  const int xr0 = max(0, x0 - D + 1) & ~3;
   const int nr = x0 + nx - xr0;         // right-view codes needed
   const int rx = J.cw / 2, ry = J.ch / 2;
   const int sl = nx + 2 * rx, sr = nr + 2 * rx;  // staged row lengths
@@ -173,10 +181,13 @@ __global__ __launch_bounds__(256) void census_cost_kernel(JobTable<FusedCostJob>
   for (int xi = 4 * g; xi < nx; xi += 4 * groups) {
     const int x = x0 + xi;
     if (full && x >= d0 + 3 && xi + 3 < nx) {
-      const int i0 = x - d0 - xr0;  // index of the code at x - d0
+      // codes x - d0 - 3 .. x - d0 + 3 at indices a .. a + 6, a = i0 - 3 = 1
+      // (mod 4): swz(a + k) = swz(a) + k + (1 + k) / 4, one base address
+      const int a = x - d0 - xr0 - 3;
+      const uint64_t *cb = codeR + swz(a);
       uint64_t r[7];
 #pragma unroll
-      for (int k = 0; k < 7; ++k) r[k] = codeR[swz(i0 - 3 + k)];
+      for (int k = 0; k < 7; ++k) r[k] = cb[k + ((1 + k) >> 2)];
 #pragma unroll
       for (int p = 0; p < 4; ++p) {
         const uint64_t cl = codeL[xi + p];
@@ -205,9 +216,9 @@ __global__ __launch_bounds__(256) void census_cost_kernel(JobTable<FusedCostJob>
 size_t fused_cost_lds(int D, int cw, int ch) {
   (void)D;
   // codes: kSeg left + kCodeRSlots right; rows: ch x (kSeg + cw - 1) left and
-  // ch x (kSeg + 255 + cw - 1) right
+  // ch x (kRightMax + cw - 1) right
   return (size_t)(kSeg + kCodeRSlots) * 8 + (size_t)ch * (kSeg + cw - 1) +
-         (size_t)ch * (kSeg + 255 + cw - 1);
+         (size_t)ch * (kRightMax + cw - 1);
 }
 
 void launch_census_cost(std::vector<FusedCostJob> jobs, hipStream_t s) {
