@@ -47,8 +47,10 @@ constexpr uint32_t kInf = 0xFFFFFFFFu;
 
 // One step of the path recurrence for a 16-lane group (4 disparities per
 // lane as two packed pairs): Lp = predecessor's path costs, mp its minimum.
+// Cells with d >= D carry C = 0xFFFF, so the saturating final add keeps them
+// at 0xFFFF (every candidate is >= mp, so best - mp does not wrap).
 __device__ __forceinline__ void path_step(const u16x2 Lp[2], uint32_t mp, const u16x2 C[2], u16x2 P1, u16x2 P2,
-                                          const uint32_t pad[2], u16x2 Lc[2]) {
+                                          u16x2 Lc[2]) {
   const uint32_t prev =
       (uint32_t)__builtin_amdgcn_update_dpp((int)kInf, (int)as_u32(Lp[1]), kDppRowShr1, 0xF, 0xF, false);
   const uint32_t next =
@@ -61,8 +63,8 @@ __device__ __forceinline__ void path_step(const u16x2 Lp[2], uint32_t mp, const 
   const u16x2 MP2 = padd_sat(M, P2);
   u16x2 b0 = pmin(pmin(padd_sat(pmin(Nb0, Nb1), P1), Lp[0]), MP2);
   u16x2 b1 = pmin(pmin(padd_sat(pmin(Nb1, Nb2), P1), Lp[1]), MP2);
-  Lc[0] = as_pair(as_u32(b0 - M + C[0]) | pad[0]);
-  Lc[1] = as_pair(as_u32(b1 - M + C[1]) | pad[1]);
+  Lc[0] = padd_sat(b0 - M, C[0]);
+  Lc[1] = padd_sat(b1 - M, C[1]);
 }
 
 __device__ __forceinline__ uint32_t pair_min(const u16x2 L[2]) {
@@ -74,9 +76,11 @@ __device__ __forceinline__ uint32_t pair_min(const u16x2 L[2]) {
 __device__ __forceinline__ uint32_t pack_bytes(const u16x2 L[2]) {
   return __builtin_amdgcn_perm(as_u32(L[1]), as_u32(L[0]), 0x06040200u);
 }
-__device__ __forceinline__ void unpack_bytes(uint32_t b, u16x2 L[2]) {
-  L[0] = as_pair(__builtin_amdgcn_perm(0u, b, 0x0c010c00u));
-  L[1] = as_pair(__builtin_amdgcn_perm(0u, b, 0x0c030c02u));
+// and back: sel[] are the lane's byte selectors, whose high byte of a cell
+// with d >= D is 0xFF (v_perm selector 13) so that the cell reads 0xFFFF
+__device__ __forceinline__ void unpack_bytes(uint32_t b, const uint32_t sel[2], u16x2 L[2]) {
+  L[0] = as_pair(__builtin_amdgcn_perm(0u, b, sel[0]));
+  L[1] = as_pair(__builtin_amdgcn_perm(0u, b, sel[1]));
 }
 
 }  // namespace
@@ -114,10 +118,15 @@ __global__ __launch_bounds__(1024) void sweep_kernel(JobTable<SweepJob> t) {
   const int T = 2 * ((H - 1) % kG) + P * ((H - 1) / kG) + W + 1;
   const int dbase = 4 * j;
   const int dvalid = min(4, max(0, D - dbase));
-  uint32_t pad[2];
+  uint32_t pad[2], usel[2];
 #pragma unroll
-  for (int q = 0; q < 2; ++q)
+  for (int q = 0; q < 2; ++q) {
     pad[q] = (2 * q < dvalid ? 0u : 0xFFFFu) | (2 * q + 1 < dvalid ? 0u : 0xFFFF0000u);
+    // bytes 2q and 2q+1 into the low bytes of the two halves; high bytes 0x00,
+    // or 0xFF for cells with d >= D
+    usel[q] = (uint32_t)(2 * q) | (2 * q < dvalid ? 0x0Cu : 0x0Du) << 8 | (uint32_t)(2 * q + 1) << 16 |
+              (2 * q + 1 < dvalid ? 0x0Cu : 0x0Du) << 24;
+  }
   const u16x2 P1 = {(unsigned short)jp1, (unsigned short)jp1};
   const u16x2 P2 = {(unsigned short)jp2, (unsigned short)jp2};
   const bool pL = mask & 0x01, pT = mask & 0x04, pTL = mask & 0x10, pTR = mask & 0x40;
@@ -241,19 +250,27 @@ __global__ __launch_bounds__(1024) void sweep_kernel(JobTable<SweepJob> t) {
         auto CR = [&](int k) -> uint32_t { return crs[(k - S_) & 3]; };
         // matching costs of equation (1), N_b left of the image
         u16x2 C[2];
+        uint32_t h[4];
 #pragma unroll
-        for (int q = 0; q < 2; ++q) {
-          const int d0 = dbase + 2 * q;
-          const uint32_t h0 = (uint32_t)__builtin_popcount(ccl ^ CR(2 * q));
-          const uint32_t h1 = (uint32_t)__builtin_popcount(ccl ^ CR(2 * q + 1));
-          const uint32_t c0 = x >= d0 ? h0 : nbits;
-          const uint32_t c1 = x >= d0 + 1 ? h1 : nbits;
-          C[q] = as_pair(c0 | c1 << 16);
+        for (int k = 0; k < 4; ++k) h[k] = (uint32_t)__builtin_popcount(ccl ^ CR(k));
+        if (__builtin_amdgcn_ballot_w64(x < dbase + 3) == 0) {
+          // every active lane is at least 4j + 3 pixels into its row (the
+          // common case, taken by the whole wave): no cell is left of the image
+#pragma unroll
+          for (int q = 0; q < 2; ++q) C[q] = as_pair((h[2 * q] | h[2 * q + 1] << 16) | pad[q]);  // 0xFFFF for d >= D
+        } else {
+#pragma unroll
+          for (int q = 0; q < 2; ++q) {
+            const int d0 = dbase + 2 * q;
+            const uint32_t c0 = x >= d0 ? h[2 * q] : nbits;
+            const uint32_t c1 = x >= d0 + 1 ? h[2 * q + 1] : nbits;
+            C[q] = as_pair((c0 | c1 << 16) | pad[q]);
+          }
         }
         u16x2 S[2] = {as_pair(0u), as_pair(0u)};
         if (pL) {
           u16x2 Lc[2];
-          path_step(Lh, mh, C, P1, P2, pad, Lc);
+          path_step(Lh, mh, C, P1, P2, Lc);
           mh = pair_min(Lc);
           Lh[0] = Lc[0];
           Lh[1] = Lc[1];
@@ -274,12 +291,12 @@ __global__ __launch_bounds__(1024) void sweep_kernel(JobTable<SweepJob> t) {
             const uint32_t rb = ring[ga][px & 3][V][j], rm = rmin[ga][px & 3][V];
             const uint32_t bytes = g > 0 ? rb : carry_bytes, m = g > 0 ? rm : carry_min;
             u16x2 Lp[2];
-            unpack_bytes(bytes, Lp);
-            Lp[0] = as_pair(has ? as_u32(Lp[0]) | pad[0] : pad[0]);
-            Lp[1] = as_pair(has ? as_u32(Lp[1]) | pad[1] : pad[1]);
+            unpack_bytes(bytes, usel, Lp);
+            Lp[0] = has ? Lp[0] : as_pair(pad[0]);
+            Lp[1] = has ? Lp[1] : as_pair(pad[1]);
             const uint32_t mp = has ? m : 0u;
             u16x2 Lc[2];
-            path_step(Lp, mp, C, P1, P2, pad, Lc);
+            path_step(Lp, mp, C, P1, P2, Lc);
             const uint32_t mc = pair_min(Lc);
             const uint32_t b = pack_bytes(Lc);
             ring[g][slot][V][j] = b;
