@@ -109,6 +109,7 @@ __global__ __launch_bounds__(1024) void sweep_kernel(JobTable<SweepJob> t) {
   const int jp1 = JT.p1, jp2 = JT.p2;
   const int g = (int)threadIdx.x >> 4, j = (int)threadIdx.x & 15;
   const bool writer = threadIdx.x >= 64 * 15;  // wave 15 (wave-uniform)
+  const bool wave0 = threadIdx.x < 64;          // groups 0-3 (wave-uniform)
   // steps between the rows of a group: the row (W), two steps so that group
   // g+1 has read the ring before group g refills it, and at least enough for
   // the 2-step skew of kG groups plus the writer's step and the carry
@@ -150,20 +151,25 @@ __global__ __launch_bounds__(1024) void sweep_kernel(JobTable<SweepJob> t) {
   // the waits for them stay kPF steps behind the loads.
   auto prefetch = [&](auto stag, int b, int xx) {
     constexpr int S_ = decltype(stag)::value;
-    const int y = b * kG + g;
-    const bool ok = !writer && xx >= 0 && xx < W && y < H;
-    // byte offsets from block-uniform bases fit 32 bits (W*H*8 < 2^28 for
-    // an eligible frame; the carry rows are 2*W*256 bytes)
-    const uint32_t o = ok ? (uint32_t)(y * W + xx) * 8u : 0u;
+    // a target outside the image reads a clamped pixel, whose value the
+    // step then ignores; byte offsets from block-uniform bases fit 32 bits
+    // (W*H*8 < 2^28 for an eligible frame; the carry rows are 2*W*256 bytes)
+    const int xc = min(max(xx, 0), W - 1);
+    const int yc = min(b * kG + g, H - 1);
+    const uint32_t o = (uint32_t)(yc * W + xc) * 8u;
     rcl[S_] = *reinterpret_cast<const uint32_t *>(reinterpret_cast<const char *>(Jcl) + o);
     rcr[S_] = *reinterpret_cast<const uint32_t *>(reinterpret_cast<const char *>(Jcr) + o);
-    {  // only group 0 uses the carry row; every wave loads it so that all
-       // paths through a step issue the same loads
-      const int xc = min(max(xx, 0), W - 1);
-      const uint32_t cb = (uint32_t)((max(b, 1) - 1) & 1) * (uint32_t)W * kSweepCarry;
-      const uint32_t c0 = cb + (uint32_t)xc * kSweepCarry;
-      const uint32_t cm = cb + (uint32_t)max(xc - 1, 0) * kSweepCarry;
-      const uint32_t cp = cb + (uint32_t)min(xc + 1, W - 1) * kSweepCarry;
+    {  // only group 0 (wave 0) uses the carry row: the other waves skip the
+       // address arithmetic (a uniform branch) and load from offset 0, but
+       // every wave issues the loads, so that all paths through a step issue
+       // the same ones
+      uint32_t c0 = 0, cm = 0, cp = 0;
+      if (wave0) {
+        const uint32_t cb = (uint32_t)((max(b, 1) - 1) & 1) * (uint32_t)W * kSweepCarry;
+        c0 = cb + (uint32_t)xc * kSweepCarry;
+        cm = cb + (uint32_t)max(xc - 1, 0) * kSweepCarry;
+        cp = cb + (uint32_t)min(xc + 1, W - 1) * kSweepCarry;
+      }
       rcv0[S_] = *reinterpret_cast<const uint32_t *>(Jcarry + (c0 + dbase));
       rcm0[S_] = *reinterpret_cast<const uint32_t *>(Jcarry + (c0 + 192));
       rcv1[S_] = *reinterpret_cast<const uint32_t *>(Jcarry + (cm + 64 + dbase));
@@ -232,13 +238,6 @@ __global__ __launch_bounds__(1024) void sweep_kernel(JobTable<SweepJob> t) {
       // step behind (see the set-up below)
       const int y = band * kG + g;
       if (!writer && x >= 0 && x < W && y < H) {
-        // row start: the L2R path and the right-view candidates begin anew
-        const bool rs = x == 0;
-        Lh[0] = rs ? as_pair(pad[0]) : Lh[0];
-        Lh[1] = rs ? as_pair(pad[1]) : Lh[1];
-        mh = rs ? 0u : mh;
-#pragma unroll
-        for (int k = 0; k < 4; ++k) cand[k] = rs ? kInf : cand[k];
         // Right-view codes move one disparity up per step, lane 0 taking
         // cr(x).  The four slots are renamed instead of moved: at step S_ of
         // an unrolled group, slot k lives in crs[(k - S_) & 3], so the new
@@ -329,6 +328,14 @@ __global__ __launch_bounds__(1024) void sweep_kernel(JobTable<SweepJob> t) {
         // row end every candidate is (x_r + d' >= W beyond): stage them all
         st_dr[buf][g][j] = (cand[(0 - S_) & 3] & 0xFF) | (cand[(1 - S_) & 3] & 0xFF) << 8 |
                            (cand[(2 - S_) & 3] & 0xFF) << 16 | (cand[(3 - S_) & 3] & 0xFF) << 24;
+      } else if (!writer) {
+        // between rows (a group spends at least two steps outside its row):
+        // the next row's L2R path and right-view candidates begin anew
+        Lh[0] = as_pair(pad[0]);
+        Lh[1] = as_pair(pad[1]);
+        mh = 0u;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) cand[k] = kInf;
       }
       // refill the slot for the step kPF ahead once this step is done with
       // it, so that the slot's old and new values can share registers
