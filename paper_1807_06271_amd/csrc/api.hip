@@ -254,7 +254,7 @@ FramePlan plan_frame(const sgm_params &p, size_t base, bool sweep) {
     // Census codes of both views; D_L and D_R; the band-boundary carry rows;
     // the LR-checked map before the median
     f.off_lr = f.off_cost + align256(2 * px * 8);
-    f.off_dlr = f.off_lr + align256(2 * px * 2) + align256((size_t)2 * p.width * kSweepCarry);
+    f.off_dlr = f.off_lr + align256(2 * px * 2) + align256((size_t)2 * (p.width + 2) * kSweepCarry);
     f.off_dl = f.off_part = 0;
     f.bytes = f.off_dlr + align256(px * 2) - base;
     return f;

@@ -165,7 +165,7 @@ constexpr int kSweepCarry = 256;  // bytes per pixel of a band-boundary row
 struct SweepJob {
   const uint64_t *cl, *cr;  // Census codes [H][W]
   uint16_t *dl, *dr;        // D_L and D_R [H][W]
-  uint8_t *carry;           // [2][W][kSweepCarry]
+  uint8_t *carry;           // [2][W + 2][kSweepCarry]: columns for pixels -1 .. W
   int64_t stride;           // bytes between the buffers of consecutive frames
   int count;                // frames of this job (one block each)
   int W, H, D, nbits, p1, p2;

@@ -11,8 +11,8 @@
 //   - its own L2R predecessor (x-1, y) in registers,
 //   - the T2B, TL2BR and TR2BL predecessors (x, y-1), (x-1, y-1), (x+1, y-1)
 //     in a 4-slot LDS ring that group g-1 wrote one to three steps earlier
-//     (for group 0, in a carry row that group 63 of the previous band wrote
-//     to global memory),
+//     (for group 0, in a carry row that the last group of the previous band
+//     wrote to global memory),
 // all separated from the writes by the per-step block barrier.  Costs come
 // from the Census codes: the right-view codes for x-d slide through the
 // lanes (each step shifts them one disparity up, DPP row_shr), and the
@@ -110,6 +110,7 @@ __global__ __launch_bounds__(1024) void sweep_kernel(JobTable<SweepJob> t) {
   const int g = (int)threadIdx.x >> 4, j = (int)threadIdx.x & 15;
   const bool writer = threadIdx.x >= 64 * 15;  // wave 15 (wave-uniform)
   const bool wave0 = threadIdx.x < 64;          // groups 0-3 (wave-uniform)
+  const int gsh = 2 * (g & 1);                  // -2g mod 4
   // steps between the rows of a group: the row (W), two steps so that group
   // g+1 has read the ring before group g refills it, and at least enough for
   // the 2-step skew of kG groups plus the writer's step and the carry
@@ -153,7 +154,8 @@ __global__ __launch_bounds__(1024) void sweep_kernel(JobTable<SweepJob> t) {
     constexpr int S_ = decltype(stag)::value;
     // a target outside the image reads a clamped pixel, whose value the
     // step then ignores; byte offsets from block-uniform bases fit 32 bits
-    // (W*H*8 < 2^28 for an eligible frame; the carry rows are 2*W*256 bytes)
+    // (W*H*8 < 2^28 for an eligible frame; the carry rows are 2*(W+2)*256
+    // bytes)
     const int xc = min(max(xx, 0), W - 1);
     const int yc = min(b * kG + g, H - 1);
     const uint32_t o = (uint32_t)(yc * W + xc) * 8u;
@@ -164,11 +166,11 @@ __global__ __launch_bounds__(1024) void sweep_kernel(JobTable<SweepJob> t) {
        // every wave issues the loads, so that all paths through a step issue
        // the same ones
       uint32_t c0 = 0, cm = 0, cp = 0;
-      if (wave0) {
-        const uint32_t cb = (uint32_t)((max(b, 1) - 1) & 1) * (uint32_t)W * kSweepCarry;
-        c0 = cb + (uint32_t)xc * kSweepCarry;
-        cm = cb + (uint32_t)max(xc - 1, 0) * kSweepCarry;
-        cp = cb + (uint32_t)min(xc + 1, W - 1) * kSweepCarry;
+      if (wave0) {  // carry column i holds pixel i - 1 (columns 0 and W + 1 stay zero)
+        const uint32_t cb = (uint32_t)((max(b, 1) - 1) & 1) * (uint32_t)(W + 2) * kSweepCarry;
+        cm = cb + (uint32_t)xc * kSweepCarry;
+        c0 = cm + kSweepCarry;
+        cp = c0 + kSweepCarry;
       }
       rcv0[S_] = *reinterpret_cast<const uint32_t *>(Jcarry + (c0 + dbase));
       rcm0[S_] = *reinterpret_cast<const uint32_t *>(Jcarry + (c0 + 192));
@@ -179,6 +181,27 @@ __global__ __launch_bounds__(1024) void sweep_kernel(JobTable<SweepJob> t) {
     }
   };
 
+  if (vert) {
+    // The first band's carry row (buffer 0) and the border columns of buffer
+    // 1 read as zero path costs (no predecessor); the scratch holds whatever
+    // an earlier frame left.  The first prefetch below reads them.
+    uint32_t *const c32 = reinterpret_cast<uint32_t *>(Jcarry);
+    constexpr int kCol = kSweepCarry / 4;  // dwords per carry column
+    const int n0 = (W + 2) * kCol;
+    for (int i = (int)threadIdx.x; i < n0; i += (int)blockDim.x) c32[i] = 0u;
+    for (int i = (int)threadIdx.x; i < 2 * kCol; i += (int)blockDim.x)
+      c32[n0 + (i < kCol ? 0 : (W + 1) * kCol) + i % kCol] = 0u;
+  }
+  // Group 0 starts its first row at x = 0, so no step of it zeroes the ring
+  // slot of position -1 that group 1 reads at its first pixel: start from a
+  // zeroed ring.
+  for (int i = (int)threadIdx.x; i < kG * 4 * 3 * 16; i += (int)blockDim.x) (&ring[0][0][0][0])[i] = 0u;
+  for (int i = (int)threadIdx.x; i < kG * 4 * 3; i += (int)blockDim.x) (&rmin[0][0][0])[i] = 0u;
+  // the stores complete before any wave reads the carry; an explicit wait
+  // for every counter also tells the compiler that nothing is outstanding,
+  // so that its waits in the loop still count only the prefetch loads
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
 #pragma unroll
   for (int s = 0; s < kPF; ++s) {
     rcl[s] = rcr[s] = rcv0[s] = rcv1[s] = rcv2[s] = rcm0[s] = rcm1[s] = rcm2[s] = 0;
@@ -204,6 +227,12 @@ __global__ __launch_bounds__(1024) void sweep_kernel(JobTable<SweepJob> t) {
       const uint32_t cm0 = rcm0[S_], cm1 = rcm1[S_], cm2 = rcm2[S_];
       constexpr int buf = S_ & 1;         // this step's staging (t0 is a multiple of kPF)
       constexpr int wbuf = (S_ + 1) & 1;  // the previous step's
+      // Ring slots of the positions x, x - 1 and x + 1: the group's absolute
+      // position t0 + S_ - 2g mod 4, which runs on across rows (so that a
+      // position outside the row, whose slot is zeroed, precedes and follows
+      // the row's ends); t0 is a multiple of 4 and -2g mod 4 = gsh, and
+      // adding 0 or 2 mod 4 is an xor.
+      const int slot = S_ ^ gsh, slot_m = ((S_ + 3) & 3) ^ gsh, slot_p = ((S_ + 1) & 3) ^ gsh;
       if (writer) {
         // outputs of the previous step: lane gg follows group gg, whose
         // position then was (band, x) one step back
@@ -231,8 +260,8 @@ __global__ __launch_bounds__(1024) void sweep_kernel(JobTable<SweepJob> t) {
         const int yl = __builtin_amdgcn_readlane(y, kG - 1);
         const int bl = __builtin_amdgcn_readlane(band, kG - 1);
         if (vert && xl >= 0 && xl < W && yl < H && gg < 52)
-          *reinterpret_cast<uint32_t *>(Jcarry + (size_t)(bl & 1) * W * kSweepCarry + (size_t)xl * kSweepCarry +
-                                        4 * gg) = st_carry[wbuf][gg];
+          *reinterpret_cast<uint32_t *>(Jcarry + (size_t)(bl & 1) * (W + 2) * kSweepCarry +
+                                        (size_t)(xl + 1) * kSweepCarry + 4 * gg) = st_carry[wbuf][gg];
       }
       // the writer follows each group one step late: its counters start one
       // step behind (see the set-up below)
@@ -277,23 +306,24 @@ __global__ __launch_bounds__(1024) void sweep_kernel(JobTable<SweepJob> t) {
           S[1] = S[1] + Lc[1];
         }
         if (vert) {
-          const int slot = x & 3;
           const bool carry_out = g == kG - 1;
           // path V (0: T2B, 1: TL2BR, 2: TR2BL) with its predecessor at
           // (x, y-1), (x-1, y-1) or (x+1, y-1)
-          auto vpath = [&](auto vtag, bool on, bool has, int px, uint32_t carry_bytes, uint32_t carry_min) {
+          auto vpath = [&](auto vtag, bool on, int rslot, uint32_t carry_bytes, uint32_t carry_min) {
             constexpr int V = decltype(vtag)::value;
             if (!on) return;
-            // the ring of the group above (group 0: the carry row); without a
-            // predecessor the path starts from all-zero costs
+            // the ring of the group above (group 0: the carry row).  Where
+            // there is no predecessor (the first row, x - 1 < 0, x + 1 >= W)
+            // these read zero path costs with minimum 0, so the path starts
+            // as the recurrence's first pixel does (L = C): the carry row of
+            // the first band and the carry columns -1 and W are zero, and a
+            // group writes zeros into its ring at the positions outside its
+            // row.
             const int ga = max(g - 1, 0);
-            const uint32_t rb = ring[ga][px & 3][V][j], rm = rmin[ga][px & 3][V];
-            const uint32_t bytes = g > 0 ? rb : carry_bytes, m = g > 0 ? rm : carry_min;
+            const uint32_t rb = ring[ga][rslot][V][j], rm = rmin[ga][rslot][V];
+            const uint32_t bytes = g > 0 ? rb : carry_bytes, mp = g > 0 ? rm : carry_min;
             u16x2 Lp[2];
             unpack_bytes(bytes, usel, Lp);
-            Lp[0] = has ? Lp[0] : as_pair(pad[0]);
-            Lp[1] = has ? Lp[1] : as_pair(pad[1]);
-            const uint32_t mp = has ? m : 0u;
             u16x2 Lc[2];
             path_step(Lp, mp, C, P1, P2, Lc);
             const uint32_t mc = pair_min(Lc);
@@ -307,9 +337,9 @@ __global__ __launch_bounds__(1024) void sweep_kernel(JobTable<SweepJob> t) {
             S[0] = S[0] + Lc[0];
             S[1] = S[1] + Lc[1];
           };
-          vpath(std::integral_constant<int, 0>{}, pT, y > 0, x, cv0, cm0);
-          vpath(std::integral_constant<int, 1>{}, pTL, y > 0 && x > 0, x - 1, cv1, cm1);
-          vpath(std::integral_constant<int, 2>{}, pTR, y > 0 && x + 1 < W, x + 1, cv2, cm2);
+          vpath(std::integral_constant<int, 0>{}, pT, slot, cv0, cm0);
+          vpath(std::integral_constant<int, 1>{}, pTL, slot_m, cv1, cm1);
+          vpath(std::integral_constant<int, 2>{}, pTR, slot_p, cv2, cm2);
         }
         // winner-takes-all and the right-view candidates, as (S << 8 | d)
         uint32_t key[4];
@@ -329,13 +359,19 @@ __global__ __launch_bounds__(1024) void sweep_kernel(JobTable<SweepJob> t) {
         st_dr[buf][g][j] = (cand[(0 - S_) & 3] & 0xFF) | (cand[(1 - S_) & 3] & 0xFF) << 8 |
                            (cand[(2 - S_) & 3] & 0xFF) << 16 | (cand[(3 - S_) & 3] & 0xFF) << 24;
       } else if (!writer) {
-        // between rows (a group spends at least two steps outside its row):
-        // the next row's L2R path and right-view candidates begin anew
+        // outside the row (at least two steps between rows): the next row's
+        // L2R path and right-view candidates begin anew, and the ring slot of
+        // this position reads as "no predecessor" for the group below
         Lh[0] = as_pair(pad[0]);
         Lh[1] = as_pair(pad[1]);
         mh = 0u;
 #pragma unroll
         for (int k = 0; k < 4; ++k) cand[k] = kInf;
+        if (vert) {
+#pragma unroll
+          for (int v = 0; v < 3; ++v) ring[g][slot][v][j] = 0u;
+          if (j < 3) rmin[g][slot][j] = 0u;
+        }
       }
       // refill the slot for the step kPF ahead once this step is done with
       // it, so that the slot's old and new values can share registers
