@@ -302,8 +302,8 @@ __global__ __launch_bounds__(1024) void sweep_kernel(JobTable<SweepJob> t) {
           mh = pair_min(Lc);
           Lh[0] = Lc[0];
           Lh[1] = Lc[1];
-          S[0] = S[0] + Lc[0];
-          S[1] = S[1] + Lc[1];
+          S[0] = padd_sat(S[0], Lc[0]);
+          S[1] = padd_sat(S[1], Lc[1]);
         }
         if (vert) {
           const bool carry_out = g == kG - 1;
@@ -334,8 +334,8 @@ __global__ __launch_bounds__(1024) void sweep_kernel(JobTable<SweepJob> t) {
               st_carry[buf][16 * V + j] = b;
               if (j == 0) st_carry[buf][48 + V] = mc;
             }
-            S[0] = S[0] + Lc[0];
-            S[1] = S[1] + Lc[1];
+            S[0] = padd_sat(S[0], Lc[0]);
+            S[1] = padd_sat(S[1], Lc[1]);
           };
           vpath(std::integral_constant<int, 0>{}, pT, slot, cv0, cm0);
           vpath(std::integral_constant<int, 1>{}, pTL, slot_m, cv1, cm1);
@@ -346,7 +346,10 @@ __global__ __launch_bounds__(1024) void sweep_kernel(JobTable<SweepJob> t) {
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
           const uint32_t sv = (k & 1) ? (uint32_t)S[k >> 1].y : (uint32_t)S[k >> 1].x;
-          key[k] = k < dvalid ? (sv << 8 | (uint32_t)(dbase + k)) : kInf;
+          // cells with d >= D: S saturates at 0xFFFF (their path costs are
+          // 0xFFFF; valid sums stay <= 4 * 255), so their keys lose to every
+          // valid one
+          key[k] = sv << 8 | (uint32_t)(dbase + k);
         }
         const uint32_t best = row16_allmin_u32(min(min(key[0], key[1]), min(key[2], key[3])));
         if (j == 0) st_dl[buf][g] = (uint8_t)(best & 0xFF);
