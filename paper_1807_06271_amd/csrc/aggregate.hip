@@ -256,11 +256,11 @@ __device__ __forceinline__ void agg_wave(const AggJob &J, int slot, int wave_in_
           for (int q = 0; q < K / 4; ++q)  // low bytes of the four 16-bit values
             pk.v[q] = __builtin_amdgcn_perm(as_u32(Lc[2 * q + 1]), as_u32(Lc[2 * q]), 0x06040200u);
           store_nt<K / 4>(o, pk);  // read once, by the disparity kernel
-        } else {  // K = 2 or 6: 2-byte aligned, one 16-bit store per pair
+        } else {  // K = 2 or 6: 2-byte aligned, one non-temporal 16-bit store per pair
 #pragma unroll
           for (int q = 0; q < NP; ++q)
-            reinterpret_cast<uint16_t *>(o)[q] =
-                (uint16_t)__builtin_amdgcn_perm(0u, as_u32(Lc[q]), 0x0c0c0200u);
+            __builtin_nontemporal_store((uint16_t)__builtin_amdgcn_perm(0u, as_u32(Lc[q]), 0x0c0c0200u),
+                                        reinterpret_cast<uint16_t *>(o) + q);
         }
       } else {
         U32N<NP> pk;
