@@ -205,7 +205,7 @@ __device__ __forceinline__ void agg_wave(const AggJob &J, int slot, int wave_in_
   uint32_t mp = 0;  // the predecessor's minimum (uniform over the lane group)
 
   // GUARD = false: every scanline of the wave has pixels i and i + PF, so
-  // the load and the store need no per-lane test
+  // the load needs no clamp and the store no per-lane test
   auto pixel = [&](auto guard, int i, CostWords<K, SRC> &rs) {
     constexpr bool GUARD = decltype(guard)::value;
     // keep each pixel's instructions together: hoisting the unpacking of

@@ -24,6 +24,7 @@ from __future__ import annotations
 
 import csv
 import hashlib
+import re
 import json
 import os
 import sys
@@ -46,15 +47,24 @@ def _header_section(name: str, marker: str) -> bytes:
     return (pre + body).encode()
 
 
+def _code_only(text: bytes) -> bytes:
+    """Source text without comments and blank-space differences, so that a
+    documentation edit does not invalidate a measurement of the same code."""
+    t = text.decode("utf-8")
+    t = re.sub(r"/\*.*?\*/", " ", t, flags=re.S)
+    t = re.sub(r"//[^\n]*", " ", t)
+    return " ".join(t.split()).encode()
+
+
 def source_hash(files=("aggregate.hip", "device_util.h")) -> str:
-    """Hash of the aggregation kernel's sources: its file, the device helpers
+    """Hash of the aggregation kernel's code: its file, the device helpers
     and the aggregation section of the kernel header (changes elsewhere in
-    the header do not touch the kernel)."""
+    the header do not touch the kernel), comments and spacing ignored."""
     h = hashlib.sha256()
     for f in files:
         with open(os.path.join(PKG, "csrc", f), "rb") as fh:
-            h.update(fh.read())
-    h.update(_header_section("sgm_kernels.h", "aggregation"))
+            h.update(_code_only(fh.read()))
+    h.update(_code_only(_header_section("sgm_kernels.h", "aggregation")))
     return h.hexdigest()[:16]
 
 
@@ -129,7 +139,7 @@ def traffic(fetch_csv: str, write_csv: str, out_path: str, fetch_cmd: str, write
                            "fetch_kib": cfetch, "write_kib": cwrite,
                            "fetch_factor": fetch_factor, "write_factor": write_factor},
            "source_hash": source_hash(),
-           "source_hash_covers": "aggregate.hip, device_util.h and the aggregation section of sgm_kernels.h",
+           "source_hash_covers": "aggregate.hip, device_util.h and the aggregation section of sgm_kernels.h, comments and spacing ignored",
            "fetch_command": fetch_cmd, "write_command": write_cmd,
            "kernels": kernels}
     json.dump(out, open(out_path, "w"), indent=1)
