@@ -101,14 +101,22 @@ __device__ __forceinline__ void sum_raw(const DispJob &J, const RawSums<K, IN> &
   }
 }
 
-// Pixels per 16-lane row per sweep and threads per block, sized so that the
-// raw words of the current and the next sweep stay in registers.
+// Pixels per 16-lane row per sweep, sized so that the raw words of the
+// current and the next sweep stay in registers.
 template <int K, int IN>
 struct DispShape {
   static constexpr int RAW = RawSums<K, IN>::NW;
   static constexpr int NPX = RAW <= 16 ? 2 : 1;
-  static constexpr int THREADS = (K < 16 && 2 * NPX * RAW <= 64) ? 1024 : 512;
 };
+
+// Threads per block for a launch of `blocks` (row, segment) blocks: small
+// blocks when there are many, so that several share a CU and one block's
+// barrier and tail overlap another's loads; large ones when there are few, so
+// that the launch still fills the chip.  Measured on MI355X: 1242x375 D=128
+// (1 500 blocks) 43 / 45 / 54 us with 256 / 512 / 1024 threads, 640x360
+// D=60 (720) 12.1 / 10.5 / 13.1 us, 320x240 D=64 (240) 18.1 / 11.8 /
+// 10.2 us.
+inline int disp_threads(long blocks) { return blocks >= 1024 ? 256 : blocks >= 512 ? 512 : 1024; }
 
 void disp_segments(int W, int D, bool split, int *nseg, int *seglen) {
   const int target = std::max(256, 2 * D);
@@ -124,8 +132,8 @@ size_t disp_part_bytes(int W, int H, int D) {
   return (size_t)H * nseg * (seglen + D - 1) * 4;
 }
 
-template <int K, int IN>
-__global__ __launch_bounds__((DispShape<K, IN>::THREADS)) void disp_kernel(JobTable<DispJob> t) {
+template <int K, int IN, int THREADS>
+__global__ __launch_bounds__(THREADS) void disp_kernel(JobTable<DispJob> t) {
   constexpr int NPX = DispShape<K, IN>::NPX;
   extern __shared__ uint32_t smem[];
   const int ji = find_job(t.j, t.n, (int)blockIdx.x);
@@ -218,19 +226,28 @@ void launch_lr_seg(std::vector<LRSegJob> jobs, hipStream_t s) {
       });
 }
 
+template <int K, int IN>
+static void launch_disp_ki(const JobTable<DispJob> &t, int blocks, size_t lds, hipStream_t s) {
+  // 1024 threads leave 128 registers per lane: too few for two sweeps of
+  // raw words beyond 64 of them
+  constexpr bool fits1024 = K < 16 && 2 * DispShape<K, IN>::NPX * DispShape<K, IN>::RAW <= 64;
+  const int threads = disp_threads(blocks);
+  if (threads == 256) {
+    hipLaunchKernelGGL((disp_kernel<K, IN, 256>), dim3(blocks), dim3(256), lds, s, t);
+  } else if (threads == 512 || !fits1024) {
+    hipLaunchKernelGGL((disp_kernel<K, IN, 512>), dim3(blocks), dim3(512), lds, s, t);
+  } else if constexpr (fits1024) {
+    hipLaunchKernelGGL((disp_kernel<K, IN, 1024>), dim3(blocks), dim3(1024), lds, s, t);
+  }
+}
+
 template <int K>
 static void launch_disp_k(int in_kind, const JobTable<DispJob> &t, int blocks, size_t lds,
                           hipStream_t s) {
   switch (in_kind) {
-    case 0:
-      hipLaunchKernelGGL((disp_kernel<K, 0>), dim3(blocks), dim3(DispShape<K, 0>::THREADS), lds, s, t);
-      break;
-    case 1:
-      hipLaunchKernelGGL((disp_kernel<K, 1>), dim3(blocks), dim3(DispShape<K, 1>::THREADS), lds, s, t);
-      break;
-    default:
-      hipLaunchKernelGGL((disp_kernel<K, 2>), dim3(blocks), dim3(DispShape<K, 2>::THREADS), lds, s, t);
-      break;
+    case 0: launch_disp_ki<K, 0>(t, blocks, lds, s); break;
+    case 1: launch_disp_ki<K, 1>(t, blocks, lds, s); break;
+    default: launch_disp_ki<K, 2>(t, blocks, lds, s); break;
   }
 }
 
