@@ -605,11 +605,12 @@ int enqueue_frames(const sgm_frame *fr, int n, const std::vector<FramePlan> &pla
     std::vector<LRSegJob> lj;
     for (int i = 0; i < n; ++i) {
       const sgm_params &p = fr[i].p;
-      if (sweep[i] || !p.lr_check) continue;
+      // with a median, the median kernel forms the LR check itself
+      if (sweep[i] || !p.lr_check || p.median) continue;
       LRSegJob j{};
       j.dl = reinterpret_cast<const uint16_t *>(mem + plans[i].off_dl);
       j.part = reinterpret_cast<const uint32_t *>(mem + plans[i].off_part);
-      j.out = p.median ? reinterpret_cast<uint16_t *>(mem + plans[i].off_dlr) : fr[i].disp;
+      j.out = fr[i].disp;
       j.W = p.width;
       j.H = p.height;
       j.D = p.max_disp;
@@ -635,6 +636,15 @@ int enqueue_frames(const sgm_frame *fr, int n, const std::vector<FramePlan> &pla
     j.W = p.width;
     j.H = p.height;
     j.k = p.median;
+    if (!sweep[i] && p.lr_check) {  // D_L and the segments' keys from the disparity stage
+      j.lr = 1;
+      j.dl = reinterpret_cast<const uint16_t *>(mem + plans[i].off_dl);
+      j.part = reinterpret_cast<const uint32_t *>(mem + plans[i].off_part);
+      j.D = p.max_disp;
+      disp_segments(p.width, p.max_disp, split, &j.nseg, &j.seglen);
+      j.max_diff = p.lr_max_diff;
+      j.invalid = p.invalid;
+    }
     mj.push_back(j);
   }
   if (!mj.empty()) {

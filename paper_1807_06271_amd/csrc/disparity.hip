@@ -16,7 +16,8 @@
 // rows keeps every CU busy on a single frame.
 //
 // median_kernel: k x k median with clamped borders by an odd-even
-// transposition network on k*k registers.
+// transposition network on k*k registers; with the LR check in front of it,
+// it forms the checked values of its tile and halo itself.
 #include "device_util.h"
 
 namespace sgmk {
@@ -197,25 +198,30 @@ __global__ __launch_bounds__(THREADS) void disp_kernel(JobTable<DispJob> t) {
 
 // Left-right check (section 3.1.4): D_R(x_r) is the smallest key over the
 // segments whose zones hold x_r.
+// The LR-checked value at (x, y): D_L if the right view's disparity at
+// x - D_L, the smallest key over the segments whose zones hold it, is within
+// max_diff, else the invalid value.
+__device__ __forceinline__ int lr_value(const uint16_t *dl_map, const uint32_t *part, int W, int D, int nseg,
+                                        int seglen, int max_diff, int invalid, int x, int y) {
+  const int dl = dl_map[(int64_t)y * W + x];
+  const int xr = x - dl;
+  if (xr < 0) return invalid;
+  const int zs = seglen + D - 1;
+  const int sa = xr / seglen, sb = min((xr + D - 1) / seglen, nseg - 1);
+  uint32_t key = 0xFFFFFFFFu;
+  for (int sg = sa; sg <= sb; ++sg)
+    key = min(key, part[((int64_t)y * nseg + sg) * zs + xr - (sg * seglen - D + 1)]);
+  const int dr = (int)(key & 0xFF);
+  return abs(dl - dr) <= max_diff ? dl : invalid;
+}
+
 __global__ __launch_bounds__(256) void lr_seg_kernel(JobTable<LRSegJob> t) {
   const int ji = find_job(t.j, t.n, (int)blockIdx.x);
   const LRSegJob &J = t.j[ji];
   const int64_t i = (int64_t)((int)blockIdx.x - J.blk0) * 256 + threadIdx.x;
   if (i >= (int64_t)J.W * J.H) return;
   const int y = (int)(i / J.W), x = (int)(i - (int64_t)y * J.W);
-  const int dl = J.dl[i];
-  int v = J.invalid;
-  const int xr = x - dl;
-  if (xr >= 0) {
-    const int zs = J.seglen + J.D - 1;
-    const int sa = xr / J.seglen, sb = min((xr + J.D - 1) / J.seglen, J.nseg - 1);
-    uint32_t key = 0xFFFFFFFFu;
-    for (int sg = sa; sg <= sb; ++sg)
-      key = min(key, J.part[((int64_t)y * J.nseg + sg) * zs + xr - (sg * J.seglen - J.D + 1)]);
-    const int dr = (int)(key & 0xFF);
-    if (abs(dl - dr) <= J.max_diff) v = dl;
-  }
-  J.out[i] = (uint16_t)v;
+  J.out[i] = (uint16_t)lr_value(J.dl, J.part, J.W, J.D, J.nseg, J.seglen, J.max_diff, J.invalid, x, y);
 }
 
 void launch_lr_seg(std::vector<LRSegJob> jobs, hipStream_t s) {
@@ -293,23 +299,45 @@ __device__ __forceinline__ void oddeven_sort(uint32_t (&v)[N]) {
   }
 }
 
-template <int KS>
+// LR = false: the median of the map J.in.  LR = true: the LR check and the
+// median in one pass; the block first forms the LR-checked values of its
+// tile and clamped halo in LDS from D_L and the segments' right-view keys
+// (as lr_seg_kernel does per pixel), so the checked map never goes through
+// memory.
+template <int KS, bool LR>
 __global__ __launch_bounds__(256) void median_kernel(JobTable<MedianJob> t) {
+  constexpr int R = KS / 2, TW = kMedTile + 2 * R;
+  __shared__ uint16_t tile[LR ? TW * TW : 1];
   const int ji = find_job(t.j, t.n, (int)blockIdx.x);
   const MedianJob &J = t.j[ji];
   const int tb = (int)blockIdx.x - J.blk0;
-  const int x = (tb % J.tiles_x) * kMedTile + (int)(threadIdx.x & (kMedTile - 1));
-  const int y = (tb / J.tiles_x) * kMedTile + (int)(threadIdx.x >> 4);
-  if (x >= J.W || y >= J.H) return;
-  constexpr int R = KS / 2;
+  const int x0 = (tb % J.tiles_x) * kMedTile, y0 = (tb / J.tiles_x) * kMedTile;
+  const int x = x0 + (int)(threadIdx.x & (kMedTile - 1));
+  const int y = y0 + (int)(threadIdx.x >> 4);
   uint32_t v[KS * KS];
+  if (LR) {
+    for (int i = (int)threadIdx.x; i < TW * TW; i += 256) {
+      const int xx = min(max(x0 - R + i % TW, 0), J.W - 1);
+      const int yy = min(max(y0 - R + i / TW, 0), J.H - 1);
+      tile[i] = (uint16_t)lr_value(J.dl, J.part, J.W, J.D, J.nseg, J.seglen, J.max_diff, J.invalid, xx, yy);
+    }
+    __syncthreads();
+    if (x >= J.W || y >= J.H) return;
+    const int tx = x - x0, ty = y - y0;
 #pragma unroll
-  for (int dy = -R; dy <= R; ++dy) {
-    const int yy = min(max(y + dy, 0), J.H - 1);
+    for (int dy = 0; dy < KS; ++dy)
 #pragma unroll
-    for (int dx = -R; dx <= R; ++dx) {
-      const int xx = min(max(x + dx, 0), J.W - 1);
-      v[(dy + R) * KS + dx + R] = J.in[(int64_t)yy * J.W + xx];
+      for (int dx = 0; dx < KS; ++dx) v[dy * KS + dx] = tile[(ty + dy) * TW + tx + dx];
+  } else {
+    if (x >= J.W || y >= J.H) return;
+#pragma unroll
+    for (int dy = -R; dy <= R; ++dy) {
+      const int yy = min(max(y + dy, 0), J.H - 1);
+#pragma unroll
+      for (int dx = -R; dx <= R; ++dx) {
+        const int xx = min(max(x + dx, 0), J.W - 1);
+        v[(dy + R) * KS + dx + R] = J.in[(int64_t)yy * J.W + xx];
+      }
     }
   }
   oddeven_sort<KS * KS>(v);
@@ -317,21 +345,24 @@ __global__ __launch_bounds__(256) void median_kernel(JobTable<MedianJob> t) {
 }
 
 void launch_median(std::vector<MedianJob> jobs, hipStream_t s) {
-  for (int K : {3, 5}) {
-    std::vector<MedianJob> sub;
-    for (auto &j : jobs)
-      if (j.k == K) {
-        j.tiles_x = (j.W + kMedTile - 1) / kMedTile;
-        sub.push_back(j);
-      }
-    if (sub.empty()) continue;
-    for_each_table(
-        sub, [](const MedianJob &j) { return (long)j.tiles_x * ((j.H + kMedTile - 1) / kMedTile); },
-        [&](const JobTable<MedianJob> &t, int blocks) {
-          if (K == 3) hipLaunchKernelGGL(median_kernel<3>, dim3(blocks), dim3(256), 0, s, t);
-          else hipLaunchKernelGGL(median_kernel<5>, dim3(blocks), dim3(256), 0, s, t);
-        });
-  }
+  for (int K : {3, 5})
+    for (int lr : {0, 1}) {
+      std::vector<MedianJob> sub;
+      for (auto &j : jobs)
+        if (j.k == K && (j.lr != 0) == (lr != 0)) {
+          j.tiles_x = (j.W + kMedTile - 1) / kMedTile;
+          sub.push_back(j);
+        }
+      if (sub.empty()) continue;
+      for_each_table(
+          sub, [](const MedianJob &j) { return (long)j.tiles_x * ((j.H + kMedTile - 1) / kMedTile); },
+          [&](const JobTable<MedianJob> &t, int blocks) {
+            if (K == 3 && lr) hipLaunchKernelGGL((median_kernel<3, true>), dim3(blocks), dim3(256), 0, s, t);
+            else if (K == 3) hipLaunchKernelGGL((median_kernel<3, false>), dim3(blocks), dim3(256), 0, s, t);
+            else if (lr) hipLaunchKernelGGL((median_kernel<5, true>), dim3(blocks), dim3(256), 0, s, t);
+            else hipLaunchKernelGGL((median_kernel<5, false>), dim3(blocks), dim3(256), 0, s, t);
+          });
+    }
 }
 
 }  // namespace sgmk

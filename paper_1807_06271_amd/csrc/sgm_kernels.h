@@ -135,9 +135,15 @@ void launch_lr_seg(std::vector<LRSegJob> jobs, hipStream_t s);
 void launch_disparity(std::vector<DispJob> jobs, int in_kind, hipStream_t s);
 
 struct MedianJob {
-  const uint16_t *in;
+  const uint16_t *in;  // the map to filter (lr == 0)
   uint16_t *out;
   int W, H, k;
+  // lr == 1: the input is the LR check of D_L against the segments' keys,
+  // formed in the median kernel (the fields of LRSegJob)
+  int lr;
+  const uint16_t *dl;
+  const uint32_t *part;
+  int D, nseg, seglen, max_diff, invalid;
   int blk0, tiles_x;
 };
 void launch_median(std::vector<MedianJob> jobs, hipStream_t s);
