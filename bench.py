@@ -415,6 +415,7 @@ def bench_serve(torch, sgm, synthetic, seconds, stress_cameras=48, stress_second
             maps = {}
             for mode, cont in (("continuous_batching", True), ("per_frame", False)):
                 stats, done = serve.serve(ctx, cams, trace, continuous=cont)
+                log("served %s %s: p50 %.3f ms, p99 %.3f ms" % (label, mode, stats["p50_ms"], stats["p99_ms"]))
                 res[mode] = stats
                 maps[mode] = done
             a, b = maps["continuous_batching"], maps["per_frame"]
@@ -445,9 +446,10 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--extras", choices=["none", "large", "batch", "all"], default="all",
+    ap.add_argument("--extras", choices=["none", "large", "batch", "serve", "all"], default="all",
                     help="secondary measurements: none; large (the 8 x 1920x1080 batch only); "
-                         "batch (all batch forms); all (batch forms and the request loop)")
+                         "batch (all batch forms); serve (the request loop only); "
+                         "all (batch forms and the request loop)")
     ap.add_argument("--serve-seconds", type=float, default=10.0)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
@@ -550,7 +552,7 @@ def main():
     if args.extras in ("large", "batch", "all"):
         log("batch of 8 1920x1080 D=256")
         extras["batch8_1920x1080_d256"] = bench_large(torch, sgm, ctx, synthetic)
-    if args.extras == "all":
+    if args.extras in ("serve", "all"):
         log("request loop, 4 cameras,", args.serve_seconds, "s per mode")
         extras["served"] = bench_serve(torch, sgm, synthetic, args.serve_seconds)
     ctx.close()

@@ -5,9 +5,10 @@ arriving pair is copied host-to-device from pinned memory and queued.  The
 loop then does continuous batching: whenever frames are queued it submits
 them (as many as the context's memory budget admits next to the batches
 still on the GPU), polls the batches in flight, and records each frame's
-latency from its scheduled arrival to the moment a poll sees it finished.
-Batches go to the context's own streams, so work of a batch submitted while
-others run overlaps on the device.
+latency from its scheduled arrival to the moment a poll sees it finished
+(the loop polls without sleeping while batches are in flight).  Batches go
+to the context's own streams, so work of a batch submitted while others run
+overlaps on the device.
 
 The per-frame baseline serves the identical trace one frame at a time: each
 frame is submitted alone and waited for before the next one starts.
@@ -105,12 +106,14 @@ def serve(ctx: sgm.Context, cameras, trace, continuous: bool = True, max_batch: 
                         finished += 1
                 continue
         if not queued and not inflight and i < n:
-            # idle until the next arrival
+            # idle until the next arrival: sleep until shortly before it,
+            # then poll, so that a late wake-up of the host thread does not
+            # delay the frame
             dt = trace[i][0] - (time.perf_counter() - t0)
-            if dt > 0.0005:
-                time.sleep(dt - 0.0003)
-        elif inflight:
-            time.sleep(0.00005)
+            if dt > 0.003:
+                time.sleep(dt - 0.002)
+        # with batches in flight the loop polls without sleeping: a sleep
+        # of the host thread adds its wake-up delay to every latency
     wall = time.perf_counter() - t0
     stats = _percentiles(lat)
     stats.update(frames=finished, wall_s=wall, fps=finished / wall,
