@@ -16,6 +16,7 @@ frame is submitted alone and waited for before the next one starts.
 from __future__ import annotations
 
 import collections
+import gc
 import time
 
 import numpy as np
@@ -52,9 +53,12 @@ def serve(ctx: sgm.Context, cameras, trace, continuous: bool = True, max_batch: 
     lat, done_frames = [], {}
     i = 0
     n = len(trace)
-    t0 = time.perf_counter()
     finished = 0
     evals = 0
+    # no garbage-collector pauses inside the timed loop
+    gc_was_enabled = gc.isenabled()
+    gc.disable()
+    t0 = time.perf_counter()
 
     def arrive(ev):
         t, ci, k = ev
@@ -67,53 +71,57 @@ def serve(ctx: sgm.Context, cameras, trace, continuous: bool = True, max_batch: 
         f = sgm.Frame.alloc(cam.p, L, R)
         return (t, ci, k, f)
 
-    while finished < n:
-        now = time.perf_counter() - t0
-        # arrivals
-        while i < n and trace[i][0] <= now:
-            queued.append(arrive(trace[i]))
-            i += 1
-        # completions
-        still = []
-        for ticket, items in inflight:
-            if sgm.sgm_poll(ctx, ticket):
-                tdone = time.perf_counter() - t0
-                for (ta, ci, k, f) in items:
-                    lat.append(tdone - ta)
-                    done_frames[(ci, k)] = f.disp
-                    evals += f.p.disp_evals()
-                    finished += 1
-            else:
-                still.append((ticket, items))
-        inflight = still
-        # admission
-        if queued and (continuous or not inflight):
-            take = min(len(queued), max_batch if continuous else 1)
-            items = [queued[j] for j in range(take)]
-            ticket = sgm.try_submit(ctx, [it[3] for it in items])
-            if ticket is not None:
-                for _ in range(take):
-                    queued.popleft()
-                if continuous:
-                    inflight.append((ticket, items))
-                else:
-                    sgm.sgm_wait(ctx, ticket)
+    try:
+        while finished < n:
+            now = time.perf_counter() - t0
+            # arrivals
+            while i < n and trace[i][0] <= now:
+                queued.append(arrive(trace[i]))
+                i += 1
+            # completions
+            still = []
+            for ticket, items in inflight:
+                if sgm.sgm_poll(ctx, ticket):
                     tdone = time.perf_counter() - t0
                     for (ta, ci, k, f) in items:
                         lat.append(tdone - ta)
                         done_frames[(ci, k)] = f.disp
                         evals += f.p.disp_evals()
                         finished += 1
-                continue
-        if not queued and not inflight and i < n:
-            # idle until the next arrival: sleep until shortly before it,
-            # then poll, so that a late wake-up of the host thread does not
-            # delay the frame
-            dt = trace[i][0] - (time.perf_counter() - t0)
-            if dt > 0.003:
-                time.sleep(dt - 0.002)
-        # with batches in flight the loop polls without sleeping: a sleep
-        # of the host thread adds its wake-up delay to every latency
+                else:
+                    still.append((ticket, items))
+            inflight = still
+            # admission
+            if queued and (continuous or not inflight):
+                take = min(len(queued), max_batch if continuous else 1)
+                items = [queued[j] for j in range(take)]
+                ticket = sgm.try_submit(ctx, [it[3] for it in items])
+                if ticket is not None:
+                    for _ in range(take):
+                        queued.popleft()
+                    if continuous:
+                        inflight.append((ticket, items))
+                    else:
+                        sgm.sgm_wait(ctx, ticket)
+                        tdone = time.perf_counter() - t0
+                        for (ta, ci, k, f) in items:
+                            lat.append(tdone - ta)
+                            done_frames[(ci, k)] = f.disp
+                            evals += f.p.disp_evals()
+                            finished += 1
+                    continue
+            if not queued and not inflight and i < n:
+                # idle until the next arrival: sleep until shortly before it,
+                # then poll, so that a late wake-up of the host thread does not
+                # delay the frame
+                dt = trace[i][0] - (time.perf_counter() - t0)
+                if dt > 0.003:
+                    time.sleep(dt - 0.002)
+            # with batches in flight the loop polls without sleeping: a sleep
+            # of the host thread adds its wake-up delay to every latency
+    finally:
+        if gc_was_enabled:
+            gc.enable()
     wall = time.perf_counter() - t0
     stats = _percentiles(lat)
     stats.update(frames=finished, wall_s=wall, fps=finished / wall,
