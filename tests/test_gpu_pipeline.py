@@ -199,3 +199,28 @@ def test_admission_busy_and_unknown_ticket(env):
         with pytest.raises(sgm.SgmError) as e:
             sgm.sgm_poll(small, 123456)
         assert e.value.status == sgm.SGM_ENOTFOUND
+
+
+def test_frames_in_flight_on_four_streams_match_oracle(env):
+    # the benchmark's launch configuration: one frame per submit, the
+    # context's four streams, up to eight submits in flight (consecutive
+    # frames overlap on the GPU); every frame must still equal the oracle
+    torch, sgm, ctx = env
+    announce("8 one-frame submits in flight on 4 streams")
+    sgm.sgm_set_streams(ctx, 4)
+    items = []
+    for k in range(8):
+        W, H, D = (1242, 375, 128) if k == 0 else (240 + 16 * k, 90 + 5 * k, 64 if k % 2 else 128)
+        left, right, _ = synthetic.make_pair("kitti", 500 + k, W, H, D)
+        p = sgm.Params(width=W, height=H, max_disp=D, census_w=9, census_h=7, path_mask=0xFF,
+                       p1=10, p2=120, lr_check=1, median=3)
+        items.append((p, left, right, sgm.Frame.alloc(p, to_dev(torch, left), to_dev(torch, right))))
+    tickets = [sgm.sgm_submit(ctx, [f]) for *_, f in items]
+    for t in tickets:
+        sgm.sgm_wait(ctx, t)
+    for p, left, right, f in items:
+        want = oracle_for(p, left, right)
+        tag = "%dx%d D%d" % (p.width, p.height, p.max_disp)
+        assert_equal(to_np(f.disp), want["disp"], "disp " + tag)
+        assert_equal(to_np(f.umap), want["umap"], "umap " + tag)
+        assert_equal(to_np(f.vmap), want["vmap"], "vmap " + tag)
