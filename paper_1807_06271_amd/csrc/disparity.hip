@@ -10,9 +10,10 @@
 // is the minimum key over d (DPP row butterfly), and D_R(x_r) =
 // argmin_d S(x_r + d, d) collects the same keys by LDS atomicMin into slot
 // x - d.  A segment [x0, x0 + n) reaches the right-view pixels of its zone
-// [x0 - D + 1, x0 + n); it writes its D_L and its zone's keys, and
-// lr_seg_kernel takes for each x_r the minimum over the (at most two)
-// segments whose zones hold it, then checks left against right.  Splitting
+// [x0 - D + 1, x0 + n); it writes its D_L and its zone's keys, and the LR
+// check (lr_value) takes for each x_r the minimum over the (at most two)
+// segments whose zones hold it, then checks left against right: in
+// lr_seg_kernel, or inside median_kernel when a median follows.  Splitting
 // rows keeps every CU busy on a single frame.
 //
 // median_kernel: k x k median with clamped borders by an odd-even
