@@ -127,7 +127,11 @@ __global__ __launch_bounds__(256) void census_cost_kernel(JobTable<FusedCostJob>
   const int tb = (int)blockIdx.x - J.blk0;
   const int segs = (J.W + kSeg - 1) / kSeg;
   const int y = tb / segs;
-  const int x0 = (tb - y * segs) * kSeg;
+  // Blocks are dealt to the 8 XCDs round robin, so with a multiple of 8
+  // segments per row the same segment of every row would run on the same XCD
+  // -- the first one, whose cells near the left edge take the slower checked
+  // path, always on XCD 0.  Rotating the segment order by the row spreads it.
+  const int x0 = ((tb - y * segs + y) % segs) * kSeg;
   const int W = J.W, H = J.H, D = J.D, Dp = J.Dp;
   const int nx = min(kSeg, W - x0);
   // first right-view pixel the segment reaches, aligned down to a multiple of
