@@ -531,7 +531,6 @@ def main():
     sgm.sgm_set_graphs(ctx, False)
     # the secondary measurements below choose their own stream counts; the
     # batch comparisons run on one stream
-    sgm.sgm_profile(ctx, True)  # the extras read stage times too
     evals = p.disp_evals()
     value = evals * args.steps / dt / 1e6
     # per-stage averages over the profiled loop (warm-up + timed steps)
@@ -540,9 +539,10 @@ def main():
     agg_ms = stage_avg_ms["aggregate"]
     achieved = ALG_BYTES_PER_EVAL * evals / (agg_ms * 1e-3) / 1e9
 
-    # frame latency of the fused path, one frame at a time
+    # frame latency of the fused path, one frame at a time (no stage
+    # markers: they would add their own cost to every frame)
     lat = []
-    for _ in range(20):
+    for _ in range(200):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         sgm.sgm_wait(ctx, sgm.sgm_submit(ctx, outs[0]))
@@ -560,6 +560,7 @@ def main():
     torch.cuda.synchronize()
     stage_path = evals * nst / (time.perf_counter() - t0) / 1e6
 
+    sgm.sgm_profile(ctx, True)  # the extras read stage times
     extras = {}
     if args.extras in ("batch", "all"):
         log("320x240 D=64 5x5 4 paths, WTA only")

@@ -281,7 +281,10 @@ int sgm_graph_stats(sgm_ctx *ctx, uint64_t *hits, uint64_t *misses);
  * ticket forgotten), else 0.  SGM_ENOTFOUND for an unknown ticket. */
 int sgm_poll(sgm_ctx *ctx, uint64_t ticket, int *done);
 
-/* Block until the ticket's batch has finished, then behave as sgm_poll. */
+/* Block until the ticket's batch has finished, then behave as sgm_poll.  The
+ * calling thread polls; the context stays usable by other threads meanwhile.
+ * A ticket is consumed by the first sgm_poll / sgm_wait that finds it done
+ * (a later call on it returns SGM_ENOTFOUND). */
 int sgm_wait(sgm_ctx *ctx, uint64_t ticket);
 
 /* Work schedule of the whole-path kernels for one frame shape.  Only the

@@ -9,6 +9,7 @@
 #include <map>
 #include <mutex>
 #include <string>
+#include <thread>
 #include <tuple>
 #include <vector>
 
@@ -1134,10 +1135,10 @@ int sgm_submit_rectify(sgm_ctx *c, const sgm_frame *frames, const sgm_remap *rem
   return submit_impl(c, frames, remaps, n, ticket);
 }
 
-static int poll_locked(sgm_ctx *c, uint64_t ticket, int *done, bool block) {
+static int poll_locked(sgm_ctx *c, uint64_t ticket, int *done) {
   auto it = c->inflight.find(ticket);
   if (it == c->inflight.end()) return fail(SGM_ENOTFOUND, "unknown ticket %llu", (unsigned long long)ticket);
-  hipError_t e = block ? hipEventSynchronize(it->second.done) : hipEventQuery(it->second.done);
+  hipError_t e = hipEventQuery(it->second.done);
   if (e == hipErrorNotReady) {
     *done = 0;
     return SGM_OK;
@@ -1161,15 +1162,24 @@ int sgm_poll(sgm_ctx *c, uint64_t ticket, int *done) {
   if (!c || !done) return fail(SGM_EINVAL, "ctx and done must be non-null");
   std::lock_guard<std::mutex> lk(c->mu);
   DeviceGuard g(c->device);
-  return poll_locked(c, ticket, done, false);
+  return poll_locked(c, ticket, done);
 }
 
 int sgm_wait(sgm_ctx *c, uint64_t ticket) {
   if (!c) return fail(SGM_EINVAL, "ctx is null");
-  std::lock_guard<std::mutex> lk(c->mu);
-  DeviceGuard g(c->device);
-  int done = 0;
-  return poll_locked(c, ticket, &done, true);
+  // Poll, releasing the context's lock between polls: a blocking wait under
+  // the lock would hold up every other thread's submit and poll until this
+  // batch is done.
+  for (;;) {
+    int done = 0;
+    {
+      std::lock_guard<std::mutex> lk(c->mu);
+      DeviceGuard g(c->device);
+      CHECK(poll_locked(c, ticket, &done));
+    }
+    if (done) return SGM_OK;
+    std::this_thread::yield();
+  }
 }
 
 int sgm_set_schedule(sgm_ctx *c, const sgm_params *shape, const sgm_schedule *sc) {

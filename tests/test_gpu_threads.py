@@ -4,6 +4,7 @@ stage calls on two streams at once, give the same results as the frames run
 one at a time.  The C entry points serialise on a per-context lock and every
 batch has its own scratch, so results must not depend on the interleaving."""
 import threading
+import time
 
 import numpy as np
 import pytest
@@ -101,3 +102,52 @@ def test_two_contexts_stage_calls_on_two_streams():
         torch.cuda.synchronize()
         for c in ctxs:
             c.close()
+
+
+def test_wait_does_not_hold_up_other_threads():
+    # while one thread waits on a long batch, another thread's submit must
+    # return at once (the waiting thread polls without holding the context's
+    # lock), and both results must still equal the frames run alone
+    torch = gpu_or_skip()
+    from paper_1807_06271_amd import sgm
+    announce("sgm_wait on a 16-frame batch while another thread submits")
+    big = frames_for(torch, sgm, 1)
+    W, H, D = 1242, 375, 128
+    left, right, _ = synthetic.make_pair("kitti", 950, W, H, D)
+    pb = sgm.Params(width=W, height=H, max_disp=D, census_w=9, census_h=7, path_mask=0xFF, median=3)
+    Lb, Rb = to_dev(torch, left), to_dev(torch, right)
+    with sgm.Context(0) as ctx:
+        ref_big = sgm.Frame.alloc(pb, Lb, Rb)
+        sgm.sgm_wait(ctx, sgm.sgm_submit(ctx, [ref_big]))
+        ref_small = sgm.Frame.alloc(*big)
+        sgm.sgm_wait(ctx, sgm.sgm_submit(ctx, [ref_small]))
+        torch.cuda.synchronize()
+        batch = [sgm.Frame.alloc(pb, Lb, Rb) for _ in range(16)]
+        small = sgm.Frame.alloc(*big)
+        submitted = threading.Event()
+        times, errors = {}, []
+
+        def waiter():
+            try:
+                tk = sgm.sgm_submit(ctx, batch)
+                submitted.set()
+                sgm.sgm_wait(ctx, tk)
+                times["wait_returned"] = time.perf_counter()
+            except Exception as e:  # reported below, in the main thread
+                errors.append(repr(e))
+                submitted.set()
+
+        th = threading.Thread(target=waiter)
+        th.start()
+        assert submitted.wait(60)
+        time.sleep(0.0005)  # the waiter is inside sgm_wait by now
+        tk = sgm.sgm_submit(ctx, [small])
+        times["submit_returned"] = time.perf_counter()
+        sgm.sgm_wait(ctx, tk)
+        th.join(timeout=120)
+        assert not th.is_alive(), "the waiting thread did not finish"
+        assert not errors, errors
+        assert times["submit_returned"] < times["wait_returned"], "submit waited for the other thread's batch"
+        for f in batch:
+            assert_equal(to_np(f.disp), to_np(ref_big.disp), "batch frame disp")
+        assert_equal(to_np(small.disp), to_np(ref_small.disp), "small frame disp")
