@@ -224,3 +224,30 @@ def test_frames_in_flight_on_four_streams_match_oracle(env):
         assert_equal(to_np(f.disp), want["disp"], "disp " + tag)
         assert_equal(to_np(f.umap), want["umap"], "umap " + tag)
         assert_equal(to_np(f.vmap), want["vmap"], "vmap " + tag)
+
+
+@pytest.mark.parametrize("batched", [True, False])
+def test_lr_and_median_combinations_match_oracle(env, batched):
+    # every combination of the LR check and the median: the median alone on
+    # D_L, the LR check alone, and both (the check formed inside the median
+    # kernel), in one batch and one frame per submit
+    torch, sgm, ctx = env
+    announce("LR x median combinations, batched" if batched else "LR x median combinations, one per submit")
+    items = []
+    for k, (lr, med) in enumerate([(0, 3), (0, 5), (1, 0), (1, 3), (1, 5), (0, 0)]):
+        W, H, D = (150, 61, 64) if k % 2 else (97, 40, 32)
+        left, right, _ = synthetic.make_pair("kitti", 700 + k, W, H, D)
+        p = sgm.Params(width=W, height=H, max_disp=D, census_w=9, census_h=7, path_mask=0xFF,
+                       lr_check=lr, median=med)
+        items.append((p, left, right, sgm.Frame.alloc(p, to_dev(torch, left), to_dev(torch, right))))
+    if batched:
+        sgm.sgm_wait(ctx, sgm.sgm_submit(ctx, [f for *_, f in items]))
+    else:
+        for *_, f in items:
+            sgm.sgm_wait(ctx, sgm.sgm_submit(ctx, [f]))
+    for p, left, right, f in items:
+        want = oracle_for(p, left, right)
+        tag = "lr %d median %d" % (p.lr_check, p.median)
+        assert_equal(to_np(f.disp), want["disp"], "disp " + tag)
+        assert_equal(to_np(f.umap), want["umap"], "umap " + tag)
+        assert_equal(to_np(f.vmap), want["vmap"], "vmap " + tag)
