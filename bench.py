@@ -468,8 +468,8 @@ def main():
                     help="also run one plain device copy of a known size (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(frames would shard across GPUs with no exchange; see the design notes)",
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
+              "(frames would shard across GPUs with no exchange between them)",
               file=sys.stderr)
         sys.exit(2)
 
