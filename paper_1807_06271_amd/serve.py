@@ -1,7 +1,9 @@
 """Multi-camera request loop over sgm_submit / sgm_poll.
 
 Simulated cameras deliver frame pairs at seeded Poisson arrival times.  Each
-arriving pair is copied host-to-device from pinned memory and queued.  The
+arriving pair is copied host-to-device from pinned memory, in one copy, into
+a free slot of its camera's device buffers (input pair and output maps,
+allocated once and reused) and queued.  The
 loop then does continuous batching: whenever frames are queued it submits
 them (as many as the context's memory budget admits next to the batches
 still on the GPU), polls the batches in flight, and records each frame's
@@ -26,14 +28,35 @@ from . import sgm
 
 
 class Camera:
-    """Pre-rendered, pinned frame pairs of one camera, replayed cyclically."""
+    """Pre-rendered frame pairs of one camera, replayed cyclically; each pair
+    is one pinned [2][H][W] buffer (left, right), so that one copy moves both
+    views."""
 
     def __init__(self, params: sgm.Params, pairs):
         self.p = params
-        self.host = [(torch.from_numpy(l).pin_memory(), torch.from_numpy(r).pin_memory()) for l, r in pairs]
+        self.host = []
+        for l, r in pairs:
+            t = torch.empty((2,) + tuple(l.shape), dtype=torch.uint8, pin_memory=True)
+            t[0].copy_(torch.from_numpy(l))
+            t[1].copy_(torch.from_numpy(r))
+            self.host.append(t)
 
     def pair(self, k: int):
-        return self.host[k % len(self.host)]
+        t = self.host[k % len(self.host)]
+        return t[0], t[1]
+
+
+class _Slot:
+    """Device buffers for one frame of a camera: the input pair, the output
+    maps, and the marshalled sgm_frame that points at them."""
+
+    __slots__ = ("inp", "frame", "args", "reuse_after")
+
+    def __init__(self, p: sgm.Params, dev):
+        self.inp = torch.empty((2, p.height, p.width), dtype=torch.uint8, device=dev)
+        self.frame = sgm.Frame.alloc(p, self.inp[0], self.inp[1])
+        self.args = self.frame.c()
+        self.reuse_after = None  # event after the last read of the outputs
 
 
 def _percentiles(lat_s):
@@ -42,14 +65,19 @@ def _percentiles(lat_s):
             "mean_ms": float(a.mean()), "max_ms": float(a.max())}
 
 
-def serve(ctx: sgm.Context, cameras, trace, continuous: bool = True, max_batch: int = 8):
+def serve(ctx: sgm.Context, cameras, trace, continuous: bool = True, max_batch: int = 8,
+          keep_maps: bool = True):
     """Replay `trace` [(t, camera, frame)] in real time.  Returns statistics
-    and, per (camera, frame), the disparity map computed (on the GPU, not
-    copied back) for later comparison."""
+    and, with keep_maps, per (camera, frame) a device copy of the disparity
+    map computed, for later comparison (the copy is taken after the frame's
+    latency is recorded)."""
     dev = torch.device("cuda", ctx.device)
     copy_stream = torch.cuda.Stream(device=dev)
-    queued = collections.deque()   # (t_arrival, cam, k, Frame)
-    inflight = []                  # (ticket, [(t_arrival, cam, k, Frame)])
+    queued = collections.deque()   # (t_arrival, cam, k, slot)
+    inflight = []                  # (ticket, [(t_arrival, cam, k, slot)])
+    # idle slots per camera: a few allocated up front, more only if a camera
+    # has more frames queued or in flight at once
+    free = [[_Slot(cam.p, dev) for _ in range(4)] for cam in cameras]
     lat, done_frames = [], {}
     i = 0
     n = len(trace)
@@ -63,13 +91,26 @@ def serve(ctx: sgm.Context, cameras, trace, continuous: bool = True, max_batch: 
     def arrive(ev):
         t, ci, k = ev
         cam = cameras[ci]
-        hl, hr = cam.pair(k)
+        slot = free[ci].pop() if free[ci] else _Slot(cam.p, dev)
         with torch.cuda.stream(copy_stream):
-            L = hl.to(dev, non_blocking=True)
-            R = hr.to(dev, non_blocking=True)
+            if slot.reuse_after is not None:  # the last copy of its outputs
+                copy_stream.wait_event(slot.reuse_after)
+            slot.inp.copy_(cam.host[k % len(cam.host)], non_blocking=True)
         copy_stream.synchronize()
-        f = sgm.Frame.alloc(cam.p, L, R)
-        return (t, ci, k, f)
+        return (t, ci, k, slot)
+
+    def finish(items, tdone):
+        nonlocal evals, finished
+        for (ta, ci, k, slot) in items:
+            lat.append(tdone - ta)
+            evals += slot.frame.p.disp_evals()
+            finished += 1
+        for (ta, ci, k, slot) in items:
+            if keep_maps:
+                done_frames[(ci, k)] = slot.frame.disp.clone()
+                slot.reuse_after = torch.cuda.Event()
+                slot.reuse_after.record()
+            free[ci].append(slot)
 
     try:
         while finished < n:
@@ -82,12 +123,7 @@ def serve(ctx: sgm.Context, cameras, trace, continuous: bool = True, max_batch: 
             still = []
             for ticket, items in inflight:
                 if sgm.sgm_poll(ctx, ticket):
-                    tdone = time.perf_counter() - t0
-                    for (ta, ci, k, f) in items:
-                        lat.append(tdone - ta)
-                        done_frames[(ci, k)] = f.disp
-                        evals += f.p.disp_evals()
-                        finished += 1
+                    finish(items, time.perf_counter() - t0)
                 else:
                     still.append((ticket, items))
             inflight = still
@@ -95,7 +131,7 @@ def serve(ctx: sgm.Context, cameras, trace, continuous: bool = True, max_batch: 
             if queued and (continuous or not inflight):
                 take = min(len(queued), max_batch if continuous else 1)
                 items = [queued[j] for j in range(take)]
-                ticket = sgm.try_submit(ctx, [it[3] for it in items])
+                ticket = sgm.try_submit(ctx, [it[3].args for it in items])
                 if ticket is not None:
                     for _ in range(take):
                         queued.popleft()
@@ -103,12 +139,7 @@ def serve(ctx: sgm.Context, cameras, trace, continuous: bool = True, max_batch: 
                         inflight.append((ticket, items))
                     else:
                         sgm.sgm_wait(ctx, ticket)
-                        tdone = time.perf_counter() - t0
-                        for (ta, ci, k, f) in items:
-                            lat.append(tdone - ta)
-                            done_frames[(ci, k)] = f.disp
-                            evals += f.p.disp_evals()
-                            finished += 1
+                        finish(items, time.perf_counter() - t0)
                     continue
             if not queued and not inflight and i < n:
                 # idle until the next arrival: sleep until shortly before it,

@@ -397,8 +397,11 @@ def sgm_submit_rectify(ctx: Context, frames, remaps) -> int:
 
 
 def try_submit(ctx: Context, frames) -> int | None:
-    """Like sgm_submit, but returns None instead of raising on SGM_EBUSY."""
-    arr = (sgm_frame * len(frames))(*[f.c() for f in frames])
+    """Like sgm_submit, but returns None instead of raising on SGM_EBUSY.
+    `frames` may hold Frame objects or their already marshalled sgm_frame
+    structs (Frame.c()), which a caller that resubmits the same buffers can
+    keep."""
+    arr = (sgm_frame * len(frames))(*[f if isinstance(f, sgm_frame) else f.c() for f in frames])
     t = ctypes.c_uint64()
     rc = lib().sgm_submit(ctx.handle, arr, len(frames), ctypes.byref(t))
     if rc == SGM_EBUSY:
