@@ -16,9 +16,11 @@
 // lr_seg_kernel, or inside median_kernel when a median follows.  Splitting
 // rows keeps every CU busy on a single frame.
 //
-// median_kernel: k x k median with clamped borders by an odd-even
-// transposition network on k*k registers; with the LR check in front of it,
+// median_kernel: k x k median with clamped borders by a pruned sorting
+// network on k*k registers; with the LR check in front of it,
 // it forms the checked values of its tile and halo itself.
+#include <utility>
+
 #include "device_util.h"
 
 namespace sgmk {
@@ -287,17 +289,50 @@ void launch_disparity(std::vector<DispJob> jobs, int in_kind, hipStream_t s) {
 
 constexpr int kMedTile = 16;
 
+// Median of N values by a pruned sorting network: Batcher's odd-even merge
+// sort on the next power of two P >= N, the inputs padded with +infinity on
+// wires N .. P-1.  A compare-exchange that touches a padding wire leaves the
+// real wires unchanged (the padding is never smaller), so only those between
+// two real wires are kept (5x5: 140 instead of the 300 of an odd-even
+// transposition sort); wire N/2 then holds the median, and the compiler drops
+// every min or max whose result does not reach it.
+struct CeNet {
+  int n;
+  unsigned char a[256], b[256];
+};
+
+constexpr CeNet batcher_net(int n) {
+  CeNet r{};
+  int P = 1;
+  while (P < n) P <<= 1;
+  for (int p = 1; p < P; p <<= 1)
+    for (int k = p; k >= 1; k >>= 1)
+      for (int j = k % p; j + k < P; j += 2 * k)
+        for (int i = 0; i < k && i + j + k < P; ++i)
+          if ((i + j) / (2 * p) == (i + j + k) / (2 * p) && i + j + k < n) {
+            r.a[r.n] = (unsigned char)(i + j);
+            r.b[r.n] = (unsigned char)(i + j + k);
+            ++r.n;
+          }
+  return r;
+}
+
+__device__ __forceinline__ void compare_exchange(uint32_t &x, uint32_t &y) {
+  const uint32_t lo = min(x, y), hi = max(x, y);
+  x = lo;
+  y = hi;
+}
+
+template <int N, int... I>
+__device__ __forceinline__ void apply_net(uint32_t (&v)[N], std::integer_sequence<int, I...>) {
+  constexpr CeNet net = batcher_net(N);
+  (compare_exchange(v[net.a[I]], v[net.b[I]]), ...);
+}
+
 template <int N>
-__device__ __forceinline__ void oddeven_sort(uint32_t (&v)[N]) {
-#pragma unroll
-  for (int pass = 0; pass < N; ++pass) {
-#pragma unroll
-    for (int i = pass & 1; i + 1 < N; i += 2) {
-      const uint32_t a = v[i], b = v[i + 1];
-      v[i] = min(a, b);
-      v[i + 1] = max(a, b);
-    }
-  }
+__device__ __forceinline__ uint32_t median_of(uint32_t (&v)[N]) {
+  apply_net(v, std::make_integer_sequence<int, batcher_net(N).n>{});
+  return v[N / 2];
 }
 
 // LR = false: the median of the map J.in.  LR = true: the LR check and the
@@ -341,8 +376,7 @@ __global__ __launch_bounds__(256) void median_kernel(JobTable<MedianJob> t) {
       }
     }
   }
-  oddeven_sort<KS * KS>(v);
-  J.out[(int64_t)y * J.W + x] = (uint16_t)v[(KS * KS) / 2];
+  J.out[(int64_t)y * J.W + x] = (uint16_t)median_of<KS * KS>(v);
 }
 
 void launch_median(std::vector<MedianJob> jobs, hipStream_t s) {
