@@ -202,7 +202,6 @@ __device__ __forceinline__ void agg_wave(const AggJob &J, int slot, int wave_in_
   u16x2 Lp[NP];
 #pragma unroll
   for (int i = 0; i < NP; ++i) Lp[i] = as_pair(padmask[i]);
-  uint32_t mp = 0;  // the predecessor's minimum (uniform over the lane group)
 
   // GUARD = false: every scanline of the wave has pixels i and i + PF, so
   // the load needs no clamp and the store no per-lane test
@@ -234,14 +233,24 @@ __device__ __forceinline__ void agg_wave(const AggJob &J, int slot, int wave_in_
 #pragma unroll
     for (int q = 1; q < NP; ++q) Nb[q] = as_pair(__builtin_amdgcn_alignbit(as_u32(Lp[q]), as_u32(Lp[q - 1]), 16));
     Nb[NP] = as_pair(__builtin_amdgcn_alignbit(next, as_u32(Lp[NP - 1]), 16));
+    // the candidates that do not involve the predecessor's minimum
+    u16x2 A[NP];
+#pragma unroll
+    for (int q = 0; q < NP; ++q) A[q] = pmin(padd_sat(pmin(Nb[q], Nb[q + 1]), P1), Lp[q]);
+    // the predecessor's minimum over d, reduced here rather than at the end
+    // of the previous pixel: in the same scheduling region as the lines
+    // above, its dependent DPP steps interleave with them instead of
+    // running ahead of them in issue order
+    u16x2 lm = Lp[0];
+#pragma unroll
+    for (int q = 1; q < NP; ++q) lm = pmin(lm, Lp[q]);
+    const uint32_t mp = group_allmin_u32<LPS>(min((uint32_t)lm.x, (uint32_t)lm.y));
     const u16x2 M = {(unsigned short)mp, (unsigned short)mp};
     u16x2 Lc[NP];
     const u16x2 MP2 = padd_sat(M, P2);
 #pragma unroll
     for (int q = 0; q < NP; ++q) {
-      u16x2 best = padd_sat(pmin(Nb[q], Nb[q + 1]), P1);
-      best = pmin(pmin(best, Lp[q]), MP2);
-      u16x2 v = best - M + cost_pair<K, SRC>(rs, q);
+      u16x2 v = pmin(A[q], MP2) - M + cost_pair<K, SRC>(rs, q);
       if (PAD) v = as_pair(as_u32(v) | padmask[q]);
       Lc[q] = v;
     }
@@ -269,10 +278,6 @@ __device__ __forceinline__ void agg_wave(const AggJob &J, int slot, int wave_in_
         store_nt<NP>(o, pk);
       }
     }
-    u16x2 lm = Lc[0];
-#pragma unroll
-    for (int q = 1; q < NP; ++q) lm = pmin(lm, Lc[q]);
-    mp = group_allmin_u32<LPS>(min((uint32_t)lm.x, (uint32_t)lm.y));
 #pragma unroll
     for (int q = 0; q < NP; ++q) Lp[q] = Lc[q];
   };
