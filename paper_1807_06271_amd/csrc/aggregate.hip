@@ -210,49 +210,94 @@ __device__ __forceinline__ void agg_wave(const AggJob &J, int slot, int wave_in_
     // keep each pixel's instructions together: hoisting the unpacking of
     // later pixels' costs would wait on loads issued one pixel ago
     __builtin_amdgcn_sched_barrier(0);
-    // neighbour pairs: Nb[q] = (L[2q-1], L[2q]) for q = 0..NP, so that pair q
-    // has its d-1 values in Nb[q] and its d+1 values in Nb[q+1]
-    uint32_t prev, next;
-    if (LPS == 16) {
-      prev = (uint32_t)__builtin_amdgcn_update_dpp((int)kInfPair, (int)as_u32(Lp[NP - 1]), kDppRowShr1,
-                                                   0xF, 0xF, false);
-      next = (uint32_t)__builtin_amdgcn_update_dpp((int)kInfPair, (int)as_u32(Lp[0]), kDppRowShl1,
-                                                   0xF, 0xF, false);
-    } else {
-      prev = (uint32_t)__builtin_amdgcn_update_dpp((int)kInfPair, (int)as_u32(Lp[NP - 1]), kDppWaveShr1,
-                                                   0xF, 0xF, false);
-      next = (uint32_t)__builtin_amdgcn_update_dpp((int)kInfPair, (int)as_u32(Lp[0]), kDppWaveShl1,
-                                                   0xF, 0xF, false);
+    u16x2 Lc[NP];
+    if constexpr (NP == 1 && LPS >= 32) {
+      // One pair per lane (the wide horizontal layouts, whose scanlines are
+      // the longest dependent chains).  The reduction of the predecessor's
+      // minimum and the neighbour candidates are independent chains of
+      // dependent instructions; they are issued alternately (the barriers fix
+      // the order), so each DPP step's wait states hold the other chain's
+      // instructions rather than idle cycles.
+      const uint32_t l0 = as_u32(Lp[0]);
+      uint32_t m = min(l0 & 0xFFFFu, l0 >> 16);
+      uint32_t prev = (uint32_t)__builtin_amdgcn_update_dpp((int)kInfPair, (int)l0, kDppWaveShr1, 0xF, 0xF, false);
+      uint32_t next = (uint32_t)__builtin_amdgcn_update_dpp((int)kInfPair, (int)l0, kDppWaveShl1, 0xF, 0xF, false);
+      __builtin_amdgcn_sched_barrier(0);
+      m = min(m, (uint32_t)__builtin_amdgcn_mov_dpp((int)m, kDppRowRor8, 0xF, 0xF, true));
       if (LPS < 64) {
         prev = first_lane ? kInfPair : prev;
         next = last_lane ? kInfPair : next;
       }
-    }
-    u16x2 Nb[NP + 1];
-    Nb[0] = as_pair(__builtin_amdgcn_alignbit(as_u32(Lp[0]), prev, 16));
+      const u16x2 nb0 = as_pair(__builtin_amdgcn_alignbit(l0, prev, 16));
+      __builtin_amdgcn_sched_barrier(0);
+      m = min(m, (uint32_t)__builtin_amdgcn_mov_dpp((int)m, kDppRowRor4, 0xF, 0xF, true));
+      const u16x2 nb1 = as_pair(__builtin_amdgcn_alignbit(next, l0, 16));
+      const u16x2 c0 = cost_pair<K, SRC>(rs, 0);
+      __builtin_amdgcn_sched_barrier(0);
+      m = min(m, (uint32_t)__builtin_amdgcn_mov_dpp((int)m, kDppRowRor2, 0xF, 0xF, true));
+      u16x2 a = pmin(nb0, nb1);
+      __builtin_amdgcn_sched_barrier(0);
+      m = min(m, (uint32_t)__builtin_amdgcn_mov_dpp((int)m, kDppRowRor1, 0xF, 0xF, true));
+      a = padd_sat(a, P1);
+      __builtin_amdgcn_sched_barrier(0);
+      {  // rows (0,1) and (2,3) exchange their minima
+        const auto r = __builtin_amdgcn_permlane16_swap(m, m, false, false);
+        m = min((uint32_t)r[0], (uint32_t)r[1]);
+      }
+      a = pmin(a, Lp[0]);
+      if (LPS == 64) {  // and the two wave halves
+        __builtin_amdgcn_sched_barrier(0);
+        const auto r = __builtin_amdgcn_permlane32_swap(m, m, false, false);
+        m = min((uint32_t)r[0], (uint32_t)r[1]);
+      }
+      const u16x2 M = {(unsigned short)m, (unsigned short)m};
+      u16x2 v = pmin(a, padd_sat(M, P2)) - M + c0;
+      if (PAD) v = as_pair(as_u32(v) | padmask[0]);
+      Lc[0] = v;
+    } else {
+      // neighbour pairs: Nb[q] = (L[2q-1], L[2q]) for q = 0..NP, so that pair
+      // q has its d-1 values in Nb[q] and its d+1 values in Nb[q+1]
+      uint32_t prev, next;
+      if (LPS == 16) {
+        prev = (uint32_t)__builtin_amdgcn_update_dpp((int)kInfPair, (int)as_u32(Lp[NP - 1]), kDppRowShr1,
+                                                     0xF, 0xF, false);
+        next = (uint32_t)__builtin_amdgcn_update_dpp((int)kInfPair, (int)as_u32(Lp[0]), kDppRowShl1,
+                                                     0xF, 0xF, false);
+      } else {
+        prev = (uint32_t)__builtin_amdgcn_update_dpp((int)kInfPair, (int)as_u32(Lp[NP - 1]), kDppWaveShr1,
+                                                     0xF, 0xF, false);
+        next = (uint32_t)__builtin_amdgcn_update_dpp((int)kInfPair, (int)as_u32(Lp[0]), kDppWaveShl1,
+                                                     0xF, 0xF, false);
+        if (LPS < 64) {
+          prev = first_lane ? kInfPair : prev;
+          next = last_lane ? kInfPair : next;
+        }
+      }
+      u16x2 Nb[NP + 1];
+      Nb[0] = as_pair(__builtin_amdgcn_alignbit(as_u32(Lp[0]), prev, 16));
 #pragma unroll
-    for (int q = 1; q < NP; ++q) Nb[q] = as_pair(__builtin_amdgcn_alignbit(as_u32(Lp[q]), as_u32(Lp[q - 1]), 16));
-    Nb[NP] = as_pair(__builtin_amdgcn_alignbit(next, as_u32(Lp[NP - 1]), 16));
-    // the candidates that do not involve the predecessor's minimum
-    u16x2 A[NP];
+      for (int q = 1; q < NP; ++q) Nb[q] = as_pair(__builtin_amdgcn_alignbit(as_u32(Lp[q]), as_u32(Lp[q - 1]), 16));
+      Nb[NP] = as_pair(__builtin_amdgcn_alignbit(next, as_u32(Lp[NP - 1]), 16));
+      // the candidates that do not involve the predecessor's minimum
+      u16x2 A[NP];
 #pragma unroll
-    for (int q = 0; q < NP; ++q) A[q] = pmin(padd_sat(pmin(Nb[q], Nb[q + 1]), P1), Lp[q]);
-    // the predecessor's minimum over d, reduced here rather than at the end
-    // of the previous pixel: in the same scheduling region as the lines
-    // above, its dependent DPP steps interleave with them instead of
-    // running ahead of them in issue order
-    u16x2 lm = Lp[0];
+      for (int q = 0; q < NP; ++q) A[q] = pmin(padd_sat(pmin(Nb[q], Nb[q + 1]), P1), Lp[q]);
+      // the predecessor's minimum over d, reduced here rather than at the end
+      // of the previous pixel: in the same scheduling region as the lines
+      // above, its dependent DPP steps interleave with them instead of
+      // running ahead of them in issue order
+      u16x2 lm = Lp[0];
 #pragma unroll
-    for (int q = 1; q < NP; ++q) lm = pmin(lm, Lp[q]);
-    const uint32_t mp = group_allmin_u32<LPS>(min((uint32_t)lm.x, (uint32_t)lm.y));
-    const u16x2 M = {(unsigned short)mp, (unsigned short)mp};
-    u16x2 Lc[NP];
-    const u16x2 MP2 = padd_sat(M, P2);
+      for (int q = 1; q < NP; ++q) lm = pmin(lm, Lp[q]);
+      const uint32_t mp = group_allmin_u32<LPS>(min((uint32_t)lm.x, (uint32_t)lm.y));
+      const u16x2 M = {(unsigned short)mp, (unsigned short)mp};
+      const u16x2 MP2 = padd_sat(M, P2);
 #pragma unroll
-    for (int q = 0; q < NP; ++q) {
-      u16x2 v = pmin(A[q], MP2) - M + cost_pair<K, SRC>(rs, q);
-      if (PAD) v = as_pair(as_u32(v) | padmask[q]);
-      Lc[q] = v;
+      for (int q = 0; q < NP; ++q) {
+        u16x2 v = pmin(A[q], MP2) - M + cost_pair<K, SRC>(rs, q);
+        if (PAD) v = as_pair(as_u32(v) | padmask[q]);
+        Lc[q] = v;
+      }
     }
     // the slot's costs are used: refill it PF pixels ahead
     load_cost<K, SRC>(rs, cbase + (int64_t)(GUARD ? min(i + PF, last) : i + PF) * cstep + coff);
