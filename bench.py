@@ -389,7 +389,7 @@ def bench_large(torch, sgm, ctx, synthetic, nframes=8):
     return res
 
 
-def bench_serve(torch, sgm, synthetic, seconds, stress_cameras=48, stress_seconds=4.0):
+def bench_serve(torch, sgm, synthetic, ctx, seconds, stress_cameras=48, stress_seconds=4.0):
     """The 4-camera request loop at 30 fps per camera (640x480 and 1242x375,
     D=128, 8 paths), continuous batching vs one frame at a time on the
     identical trace; then the same with `stress_cameras` cameras, a load at
@@ -403,25 +403,24 @@ def bench_serve(torch, sgm, synthetic, seconds, stress_cameras=48, stress_second
         p = kitti_params(sgm, sc.width, sc.height, 128)
         base.append((p, pairs))
     out = {}
-    with sgm.Context(0) as ctx:
-        # autotune both frame shapes once (kept by the context)
-        for p, pairs in base[1:3]:
-            f = sgm.Frame.alloc(p, torch.from_numpy(pairs[0][0]).cuda(), torch.from_numpy(pairs[0][1]).cuda())
-            sgm.sgm_autotune(ctx, f, reps=3)
-        for label, ncam, secs in (("4cams_30fps", 4, seconds), ("%dcams_30fps" % stress_cameras, stress_cameras, stress_seconds)):
-            cams = [serve.Camera(base[c % 4][0], base[c % 4][1]) for c in range(ncam)]
-            trace = synthetic.poisson_trace(ncam, 30.0, secs, seed=3000 + ncam)
-            serve.serve(ctx, cams, [(0.0, c, 0) for c in range(min(ncam, 8))], continuous=True)  # warm-up
-            res = {"cameras": ncam, "fps_per_camera": 30, "seconds": secs, "frames": len(trace)}
-            maps = {}
-            for mode, cont in (("continuous_batching", True), ("per_frame", False)):
-                stats, done = serve.serve(ctx, cams, trace, continuous=cont)
-                log("served %s %s: p50 %.3f ms, p99 %.3f ms" % (label, mode, stats["p50_ms"], stats["p99_ms"]))
-                res[mode] = stats
-                maps[mode] = done
-            a, b = maps["continuous_batching"], maps["per_frame"]
-            res["mix_equals_alone"] = bool(a.keys() == b.keys() and all(torch.equal(a[k], b[k]) for k in a))
-            out[label] = res
+    # autotune both frame shapes once (kept by the context)
+    for p, pairs in base[1:3]:
+        f = sgm.Frame.alloc(p, torch.from_numpy(pairs[0][0]).cuda(), torch.from_numpy(pairs[0][1]).cuda())
+        sgm.sgm_autotune(ctx, f, reps=3)
+    for label, ncam, secs in (("4cams_30fps", 4, seconds), ("%dcams_30fps" % stress_cameras, stress_cameras, stress_seconds)):
+        cams = [serve.Camera(base[c % 4][0], base[c % 4][1]) for c in range(ncam)]
+        trace = synthetic.poisson_trace(ncam, 30.0, secs, seed=3000 + ncam)
+        serve.serve(ctx, cams, [(0.0, c, 0) for c in range(min(ncam, 8))], continuous=True)  # warm-up
+        res = {"cameras": ncam, "fps_per_camera": 30, "seconds": secs, "frames": len(trace)}
+        maps = {}
+        for mode, cont in (("continuous_batching", True), ("per_frame", False)):
+            stats, done = serve.serve(ctx, cams, trace, continuous=cont)
+            log("served %s %s: p50 %.3f ms, p99 %.3f ms" % (label, mode, stats["p50_ms"], stats["p99_ms"]))
+            res[mode] = stats
+            maps[mode] = done
+        a, b = maps["continuous_batching"], maps["per_frame"]
+        res["mix_equals_alone"] = bool(a.keys() == b.keys() and all(torch.equal(a[k], b[k]) for k in a))
+        out[label] = res
     return out
 
 
@@ -481,6 +480,13 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
     sgm.lib()  # raises if libsgm.so is missing: no fallback
+    # The library's contexts are created before torch puts anything on the
+    # device: the HIP runtime spreads streams over its hardware queues (4 per
+    # process by default) in the order they appear, and contexts created
+    # after torch's own streams had two of their four streams on one queue,
+    # which cost the four-stream loop ~10 % (0.27 instead of 0.24 ms/frame).
+    ctx = sgm.Context(0)
+    serve_ctx = sgm.Context(0)
 
     left, right, _ = synthetic.make_pair("kitti", 1001)
     p = kitti_params(sgm)
@@ -493,7 +499,6 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    ctx = sgm.Context(0)
 
     # autotune the schedule of this shape once (the winner stays in the context)
     h_lanes, tune_ms = sgm.sgm_autotune(ctx, sgm.Frame.alloc(p, L, R), reps=5)
@@ -574,8 +579,9 @@ def main():
         extras["batch8_1920x1080_d256"] = bench_large(torch, sgm, ctx, synthetic)
     if args.extras in ("serve", "all"):
         log("request loop, 4 cameras,", args.serve_seconds, "s per mode")
-        extras["served"] = bench_serve(torch, sgm, synthetic, args.serve_seconds)
+        extras["served"] = bench_serve(torch, sgm, synthetic, serve_ctx, args.serve_seconds)
     ctx.close()
+    serve_ctx.close()
 
     cpu = None
     if not args.no_cpu:
