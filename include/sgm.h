@@ -249,7 +249,12 @@ int sgm_submit(sgm_ctx *ctx, const sgm_frame *frames, int n, uint64_t *ticket);
 
 /* Number of internal streams that consecutive batches rotate over (1 to 8;
  * 4 after sgm_create).  With 1, batches run one after another on the GPU;
- * with more, a batch can start while earlier ones still run. */
+ * with more, a batch can start while earlier ones still run.  The streams
+ * are created by sgm_create; the HIP runtime maps a process's streams onto a
+ * few hardware queues (GPU_MAX_HW_QUEUES, 4 by default) in the order they
+ * appear, so a context created after other streams of the process may get
+ * two of its streams on one queue and overlap less: create it early, or
+ * raise GPU_MAX_HW_QUEUES. */
 int sgm_set_streams(sgm_ctx *ctx, int n);
 
 /* sgm_submit with rectification (section 3.1.1) as the batch's first
