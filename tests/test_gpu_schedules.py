@@ -17,6 +17,7 @@ SHAPES = [  # W, H, D, census, mask, p1, p2
     (120, 30, 192, (9, 7), 0xFF, 10, 120),
     (131, 47, 60, (5, 5), 0x55, 8, 32),     # padded disparity rows
     (90, 25, 100, (9, 7), 0xFF, 20, 300),   # padded, 16-bit path costs
+    (140, 37, 100, (9, 7), 0xFF, 10, 120),  # padded, 8-bit path costs (one pair per lane at 64 lanes)
 ]
 # SAD costs (16-bit cost volume, 16-bit path costs): W, H, D, window, mask
 SAD_SHAPES = [(160, 40, 60, (5, 5), 0x55), (97, 21, 128, (5, 5), 0x0F), (70, 30, 64, (3, 3), 0xFF),
