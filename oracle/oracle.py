@@ -212,25 +212,15 @@ def default_invalid(d_max: int) -> int:
     return 255 if d_max <= 255 else 65535
 
 
-def sgm(left, right, d_max, census_w, census_h, mask, p1, p2, lr_check_on=True,
-        lr_max_diff=1, median_k=3, invalid=None, cost_kind=0):
-    """The whole path: census -> cost -> aggregate -> WTA -> (right disparity,
-    LR check) -> median -> U/V maps, or with cost_kind = 1 the SAD cost over
-    the census_w x census_h window instead of census + Hamming.  Returns a
-    dict of every stage output."""
+def select(s, d_max, lr_check_on=True, lr_max_diff=1, median_k=3, invalid=None):
+    """Disparity selection from the aggregated volume S [H][W][D], in the
+    paper's order: winner-takes-all (section 3.1.3), right-view disparity and
+    left-right check (section 3.1.4), k x k median of the checked map
+    (section 3.1.5), U-/V-maps of the final map (section 3.2).  Returns a dict
+    of every intermediate map."""
     invalid = default_invalid(d_max) if invalid is None else invalid
-    if cost_kind == 1:
-        c = sad_cost(left, right, census_w, census_h, d_max)
-        out = {"cost": c}
-    else:
-        nbits = census_w * census_h - 1
-        cl = census(left, census_w, census_h)
-        cr = census(right, census_w, census_h)
-        c = cost(cl, cr, d_max, nbits)
-        out = {"census_l": cl, "census_r": cr, "cost": c}
-    s = aggregate(c, mask, p1, p2)
     dl = wta(s)
-    out.update(aggr=s, disp_l=dl)
+    out = {"disp_l": dl}
     if lr_check_on:
         dr = right_disparity(s)
         dlr = lr_check(dl, dr, lr_max_diff, invalid)
@@ -241,4 +231,25 @@ def sgm(left, right, d_max, census_w, census_h, mask, p1, p2, lr_check_on=True,
     disp = median(dlr, median_k) if median_k else dlr
     u, v = uv_maps(disp, d_max)
     out.update(disp=disp, umap=u, vmap=v)
+    return out
+
+
+def sgm(left, right, d_max, census_w, census_h, mask, p1, p2, lr_check_on=True,
+        lr_max_diff=1, median_k=3, invalid=None, cost_kind=0):
+    """The whole path: census -> cost -> aggregate -> WTA -> (right disparity,
+    LR check) -> median -> U/V maps, or with cost_kind = 1 the SAD cost over
+    the census_w x census_h window instead of census + Hamming.  Returns a
+    dict of every stage output."""
+    if cost_kind == 1:
+        c = sad_cost(left, right, census_w, census_h, d_max)
+        out = {"cost": c}
+    else:
+        nbits = census_w * census_h - 1
+        cl = census(left, census_w, census_h)
+        cr = census(right, census_w, census_h)
+        c = cost(cl, cr, d_max, nbits)
+        out = {"census_l": cl, "census_r": cr, "cost": c}
+    s = aggregate(c, mask, p1, p2)
+    out["aggr"] = s
+    out.update(select(s, d_max, lr_check_on, lr_max_diff, median_k, invalid))
     return out

@@ -38,6 +38,8 @@ MUTANTS = [
     ("median picks the wrong rank", "out[(int64_t)y * w + x] = win[n / 2];",
      "out[(int64_t)y * w + x] = win[n / 2 + (n > 1)];"),
     ("V-map skips d = 0", "v[(int64_t)y * d_max + d] += 1;", "v[(int64_t)y * d_max + d] += (d > 0);"),
+    ("popcount of the low 32 bits only", "while (v) { v &= v - 1; ++n; }",
+     "v &= 0xFFFFFFFFu; while (v) { v &= v - 1; ++n; }"),
 ]
 
 PIN_CALLS = [
@@ -46,6 +48,7 @@ PIN_CALLS = [
     (pins.test_census_one_dark_pixel_sets_one_bit_per_neighbour, {"cw": 5, "ch": 5}),
     (pins.test_census_uses_strict_less_than_and_clamped_borders, {}),
     (pins.test_cost_is_popcount_of_xor_and_nbits_left_of_image, {}),
+    (pins.test_cost_popcount_over_the_full_code_width, {"nb": 62}),
     (pins.test_cost_constant_images, {}),
     (pins.test_cost_zero_at_true_shift, {}),
     (pins.test_aggregation_worked_example, {}),
@@ -59,6 +62,9 @@ PIN_CALLS = [
     (pins.test_lr_check_hand_built_cases, {}),
     (pins.test_median_matches_scipy, {"k": 3}),
     (pins.test_uv_maps_are_histograms, {}),
+    (pins.test_selection_chain_worked_example, {}),
+    (pins.test_whole_path_stages_chain_in_the_paper_order, {}),
+    (pins.test_constant_images_give_zero_disparity_everywhere, {}),
 ]
 
 
@@ -185,3 +191,53 @@ def test_uv_filter_pins_catch_planted_mistake(tmp_path, restore_oracle, name, ol
     finally:
         O.load()
     assert caught, "no pin caught: " + name
+
+
+# Mistakes in the composition of the whole path (oracle.py): the order of
+# the stages after aggregation (sections 3.1.3 to 3.2) and what each stage
+# consumes.  The mutated module is loaded under another name and put in place
+# of the oracle module that the pins call; it shares the C library.
+PY_MUTANTS = [
+    ("median of D_L instead of the checked map", "disp = median(dlr, median_k) if median_k else dlr",
+     "disp = median(dl, median_k) if median_k else dlr"),
+    ("U/V maps of the map before the median", "u, v = uv_maps(disp, d_max)", "u, v = uv_maps(dlr, d_max)"),
+    ("U/V maps of D_L", "u, v = uv_maps(disp, d_max)", "u, v = uv_maps(dl, d_max)"),
+    ("LR check skipped", "dlr = lr_check(dl, dr, lr_max_diff, invalid)", "dlr = dl"),
+    ("WTA of the cost volume instead of S", "out.update(select(s, d_max,", "out.update(select(c, d_max,"),
+    ("right-view disparity from the cost volume", "dr = right_disparity(s)", "dr = right_disparity(s[:, :, ::-1])"),
+]
+
+PY_PIN_CALLS = [
+    pins.test_selection_chain_worked_example,
+    pins.test_whole_path_stages_chain_in_the_paper_order,
+    pins.test_constant_images_give_zero_disparity_everywhere,
+    pins.test_fronto_parallel_shift_is_recovered,
+    pins.test_synthetic_scene_sanity_statistics,
+]
+
+
+@pytest.mark.parametrize("name,old,new", PY_MUTANTS, ids=[m[0] for m in PY_MUTANTS])
+def test_pins_catch_planted_composition_mistake(name, old, new, monkeypatch):
+    import importlib.util
+    import sys
+    path = os.path.join(os.path.dirname(O.SRC), "oracle.py")
+    src = open(path).read()
+    assert src.count(old) == 1, "mutation site not found: " + name
+    spec = importlib.util.spec_from_loader("oracle_mutant", loader=None)
+    mod = importlib.util.module_from_spec(spec)
+    mod.__file__ = path
+    sys.modules["oracle_mutant"] = mod
+    try:
+        exec(compile(src.replace(old, new), path, "exec"), mod.__dict__)
+        mod._lib, mod._lib_path = O.lib(), O._lib_path
+        monkeypatch.setattr(pins, "O", mod)
+        caught = []
+        for fn in PY_PIN_CALLS:
+            kw = {"d0": 3} if fn is pins.test_fronto_parallel_shift_is_recovered else {}
+            try:
+                fn(**kw)
+            except (AssertionError, mod.OracleError):
+                caught.append(fn.__name__)
+    finally:
+        del sys.modules["oracle_mutant"]
+    assert caught, "no pin caught the planted mistake: " + name

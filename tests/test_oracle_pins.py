@@ -92,6 +92,40 @@ def test_cost_is_popcount_of_xor_and_nbits_left_of_image():
                 assert int(c[y, x, d]) == want
 
 
+@pytest.mark.parametrize("nb", [24, 31, 33, 48, 62, 64])
+def test_cost_popcount_over_the_full_code_width(nb):
+    # Equation (1) with the Hamming distance of N_b-bit codes: the 9x7 window
+    # of the workloads gives 62-bit codes, so every bit position up to N_b - 1
+    # must count (a popcount of the low 32 bits alone would pass 24-bit codes).
+    # Codes are uniform over all N_b bits; Python's bin().count is the
+    # reference.
+    rng = np.random.default_rng(nb)
+    H, W, D = 4, 13, 7
+    raw = np.frombuffer(rng.bytes(8 * H * W * 2), np.uint64).reshape(2, H, W)
+    mask = np.uint64((1 << nb) - 1) if nb < 64 else np.uint64(0xFFFFFFFFFFFFFFFF)
+    cl, cr = raw[0] & mask, raw[1] & mask
+    # codes with every bit set, and pairs that differ only above bit 31
+    cl[0, 0] = mask
+    cr[0, 0] = 0
+    if nb > 32:
+        cl[1, 3] = np.uint64(1 << (nb - 1)) | np.uint64(5)
+        cr[1, 3] = np.uint64(5)
+    c = O.cost(cl, cr, D, nb)
+    assert int(c[0, 0, 0]) == nb
+    if nb > 32:
+        assert int(c[1, 3, 0]) == 1
+    hi = 0
+    for y in range(H):
+        for x in range(W):
+            for d in range(D):
+                want = bf.popcount(int(cl[y, x]) ^ int(cr[y, x - d])) if x >= d else nb
+                assert int(c[y, x, d]) == want
+                if x >= d:
+                    hi += bf.popcount((int(cl[y, x]) ^ int(cr[y, x - d])) >> 32)
+    if nb > 32:
+        assert hi > 0  # the high word took part
+
+
 def test_cost_constant_images():
     # identical constant images: C = 0 where the right pixel exists, else N_b
     img = np.full((6, 20), 50, np.uint8)
@@ -311,6 +345,56 @@ def test_lr_check_hand_built_cases():
     # would be within 1 of 2).
     assert O.lr_check(np.array([[0, 2]], np.uint16), np.array([[1, 0]], np.uint16), 1, inv).tolist() \
         == [[0, inv]]
+
+
+def test_selection_chain_worked_example():
+    # WTA -> right-view disparity -> LR check -> 3x3 median -> U/V maps, in
+    # the order of sections 3.1.3 to 3.2, on a hand-worked 3 x 5 volume in
+    # which the check invalidates pixels, and where a median of D_L or U/V of
+    # the pre-median map would give other values (see the fixture).
+    g = load_golden("chain_3x5.json")
+    H, W, D = g["height"], g["width"], g["max_disp"]
+    s = np.full((H, W, D), 10, np.uint16)
+    for y in range(H):
+        for x in range(W):
+            s[y, x, g["disp_l_defining_s"][y][x]] = 0
+    out = O.select(s, D, True, g["lr_max_diff"], g["median"], g["invalid"])
+    assert out["disp_l"].tolist() == g["disp_l_defining_s"]
+    assert out["disp_r"].tolist() == g["disp_r"]
+    assert out["disp_lr"].tolist() == g["disp_lr"]
+    assert out["disp"].tolist() == g["disp"]
+    assert out["umap"].tolist() == g["umap"]
+    assert out["vmap"].tolist() == g["vmap"]
+
+
+def test_whole_path_stages_chain_in_the_paper_order():
+    # Every stage of the whole path consumes the previous stage's output
+    # (sections 3.1.2 to 3.2), checked with library routines: the WTA map is
+    # numpy.argmin of S, the final map is scipy's 3x3 median of the
+    # LR-checked map, and U/V are numpy.bincount of the final map.  The input
+    # is chosen so that each wrong order would show: the check invalidates
+    # pixels, the median changes pixels, and the median of D_L differs from
+    # the median of the checked map.
+    left, right, _ = synthetic.make_pair("kitti", 31, 96, 40, 32)
+    out = O.sgm(left, right, 32, 9, 7, 0xFF, 10, 120, True, 1, 3)
+    dl, dlr, disp = out["disp_l"], out["disp_lr"], out["disp"]
+    assert (dl == np.argmin(out["aggr"], axis=-1)).all()
+    big = np.full(out["aggr"].shape, np.iinfo(np.int64).max, np.int64)
+    for d in range(32):
+        big[:, : 96 - d, d] = out["aggr"][:, d:, d]
+    assert (out["disp_r"] == np.argmin(big, axis=-1)).all()
+    assert (disp == scipy.ndimage.median_filter(dlr, size=3, mode="nearest")).all()
+    for x in range(96):
+        col = disp[:, x]
+        assert (out["umap"][:, x] == np.bincount(col[col < 32], minlength=32)).all()
+    for y in range(40):
+        row = disp[y]
+        assert (out["vmap"][y] == np.bincount(row[row < 32], minlength=32)).all()
+    # kept pixels keep D_L; invalidated ones carry the invalid value
+    assert ((dlr == dl) | (dlr == 255)).all()
+    assert (dlr == 255).sum() > 20
+    assert (disp != dlr).sum() > 20
+    assert (scipy.ndimage.median_filter(dl, size=3, mode="nearest") != disp).any()
 
 
 # ------------------------------------------------------------ median (3.1.5)
