@@ -419,7 +419,8 @@ def bench_serve(torch, sgm, synthetic, ctx, seconds, stress_cameras=48, stress_s
             res[mode] = stats
             maps[mode] = done
         a, b = maps["continuous_batching"], maps["per_frame"]
-        res["mix_equals_alone"] = bool(a.keys() == b.keys() and all(torch.equal(a[k], b[k]) for k in a))
+        res["mix_equals_alone"] = bool(a.keys() == b.keys() and all(
+            all(torch.equal(x, y) for x, y in zip(a[k], b[k])) for k in a))
         out[label] = res
     return out
 

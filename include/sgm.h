@@ -247,6 +247,18 @@ typedef struct {
  * can never fit, SGM_ENOMEM.  On success *ticket identifies the batch. */
 int sgm_submit(sgm_ctx *ctx, const sgm_frame *frames, int n, uint64_t *ticket);
 
+/* sgm_submit whose batch first waits, on the GPU, for `n_events` HIP events
+ * (hipEvent_t passed as void*, recorded by the caller on any stream of the
+ * context's device, e.g. after an asynchronous host-to-device copy of the
+ * frames' inputs): the batch's stream waits for each event before its first
+ * launch, so the caller need not block the host until its copies finish.
+ * n_events = 0 (events may then be NULL) behaves as sgm_submit.  SGM_EINVAL
+ * for n_events < 0 or a null event; everything else as for sgm_submit.
+ * (Used by the request loop of section 3.2's real-time use: frames arrive
+ * while earlier ones run.) */
+int sgm_submit_after(sgm_ctx *ctx, const sgm_frame *frames, int n, void *const *events, int n_events,
+                     uint64_t *ticket);
+
 /* Number of internal streams that consecutive batches rotate over (1 to 8;
  * 4 after sgm_create).  With 1, batches run one after another on the GPU;
  * with more, a batch can start while earlier ones still run.  The streams

@@ -351,9 +351,11 @@ std::string composition_key(const sgm_frame *fr, int n, const std::vector<int> &
   }
   for (int i = 0; i < n; ++i) {
     const sgm_params &p = fr[i].p;
-    snprintf(buf, sizeof buf, "%d,%d,%d,%d,%d,%u,%u,%u,%d,%d,%d,%u,%d,%d;", p.width, p.height,
+    // the cost kind and the path-cost width select other kernels and
+    // argument layouts
+    snprintf(buf, sizeof buf, "%d,%d,%d,%d,%d,%u,%u,%u,%d,%d,%d,%u,%u,%d,%d,%d;", p.width, p.height,
              p.max_disp, p.census_w, p.census_h, p.path_mask, p.p1, p.p2, p.lr_check, p.lr_max_diff,
-             p.median, p.invalid, hlps[i] | sweep[i] << 8, fr[i].umap ? 1 : 0);
+             p.median, p.invalid, p.cost, lr_bytes_of(p), hlps[i] | sweep[i] << 8, fr[i].umap ? 1 : 0);
     k += buf;
   }
   return k;
@@ -993,9 +995,12 @@ int uv_maps(sgm_ctx *c, const sgm_params *p, const uint16_t *disp, uint16_t *uma
 }
 
 static int submit_impl(sgm_ctx *c, const sgm_frame *frames, const sgm_remap *remaps, int n,
-                       uint64_t *ticket) {
+                       uint64_t *ticket, void *const *events = nullptr, int n_events = 0) {
   if (!c) return fail(SGM_EINVAL, "ctx is null");
   if (!frames || n < 1 || !ticket) return fail(SGM_EINVAL, "need frames, n >= 1 and a ticket pointer");
+  if (n_events < 0 || (n_events > 0 && !events)) return fail(SGM_EINVAL, "need n_events >= 0 events");
+  for (int i = 0; i < n_events; ++i)
+    if (!events[i]) return fail(SGM_EINVAL, "event %d is null", i);
   for (int i = 0; i < n; ++i) {
     int rc = validate(&frames[i].p);
     if (rc) return fail(rc, "frame %d: %s", i, g_err.c_str());
@@ -1063,6 +1068,14 @@ static int submit_impl(sgm_ctx *c, const sgm_frame *frames, const sgm_remap *rem
   c->next_stream = (c->next_stream + 1) % c->nstreams;
   hipStream_t s = c->streams[b.stream];
   int rc = SGM_OK;
+  // the caller's events gate the batch's first launch (on the GPU)
+  for (int i = 0; i < n_events && rc == SGM_OK; ++i)
+    if (hipStreamWaitEvent(s, (hipEvent_t)events[i], 0) != hipSuccess)
+      rc = fail(SGM_EHIP, "hipStreamWaitEvent on event %d failed", i);
+  if (rc != SGM_OK) {
+    c->idle.push_back(blk);
+    return rc;
+  }
   if (c->graphs && !c->profiling) {
     rc = enqueue_graph(c, frames, n, plans, hl, sw, rect, reinterpret_cast<char *>(blk.ptr), s);
   } else {
@@ -1127,6 +1140,11 @@ int uv_filter(sgm_ctx *c, const uv_filter_job *jobs, int n, void *stream) {
 
 int sgm_submit(sgm_ctx *c, const sgm_frame *frames, int n, uint64_t *ticket) {
   return submit_impl(c, frames, nullptr, n, ticket);
+}
+
+int sgm_submit_after(sgm_ctx *c, const sgm_frame *frames, int n, void *const *events, int n_events,
+                     uint64_t *ticket) {
+  return submit_impl(c, frames, nullptr, n, ticket, events, n_events);
 }
 
 int sgm_submit_rectify(sgm_ctx *c, const sgm_frame *frames, const sgm_remap *remaps, int n,
@@ -1222,9 +1240,13 @@ int sgm_autotune(sgm_ctx *c, const sgm_frame *sample, int reps, sgm_schedule *be
     HIP_TRY(hipEventCreate(&e0));
     HIP_TRY(hipEventCreate(&e1));
     hipStream_t s0 = c->streams[0];
-    const int saved = c->nstreams;
-    c->nstreams = 1;
-    c->next_stream = 0;
+    int saved;
+    {  // time on one stream: every repetition runs back to back on stream 0
+      std::lock_guard<std::mutex> lk(c->mu);
+      saved = c->nstreams;
+      c->nstreams = 1;
+      c->next_stream = 0;
+    }
     int rc = hipEventRecord(e0, s0) == hipSuccess ? SGM_OK : fail(SGM_EHIP, "event record");
     std::vector<uint64_t> tk;
     for (int r = 0; r < reps && rc == SGM_OK; ++r) {
@@ -1236,7 +1258,11 @@ int sgm_autotune(sgm_ctx *c, const sgm_frame *sample, int reps, sgm_schedule *be
       int r2 = sgm_wait(c, k);
       if (rc == SGM_OK) rc = r2;
     }
-    c->nstreams = saved;
+    {
+      std::lock_guard<std::mutex> lk(c->mu);
+      c->nstreams = saved;
+      c->next_stream = 0;
+    }
     float el = 0.f;
     if (rc == SGM_OK && hipEventSynchronize(e1) != hipSuccess) rc = fail(SGM_EHIP, "event sync");
     if (rc == SGM_OK && hipEventElapsedTime(&el, e0, e1) != hipSuccess) rc = fail(SGM_EHIP, "elapsed");

@@ -1,9 +1,11 @@
 """Multi-camera request loop over sgm_submit / sgm_poll.
 
 Simulated cameras deliver frame pairs at seeded Poisson arrival times.  Each
-arriving pair is copied host-to-device from pinned memory, in one copy, into
-a free slot of its camera's device buffers (input pair and output maps,
-allocated once and reused) and queued.  The
+arriving pair is copied host-to-device from pinned memory, in one
+asynchronous copy, into a free slot of its camera's device buffers (input
+pair and output maps, allocated once and reused) and queued with an event
+recorded after the copy; the batch that takes the frame waits for that event
+on the GPU (sgm_submit_after), so the host never blocks on a copy.  The
 loop then does continuous batching: whenever frames are queued it submits
 them (as many as the context's memory budget admits next to the batches
 still on the GPU), polls the batches in flight, and records each frame's
@@ -68,13 +70,13 @@ def _percentiles(lat_s):
 def serve(ctx: sgm.Context, cameras, trace, continuous: bool = True, max_batch: int = 8,
           keep_maps: bool = True):
     """Replay `trace` [(t, camera, frame)] in real time.  Returns statistics
-    and, with keep_maps, per (camera, frame) a device copy of the disparity
-    map computed, for later comparison (the copy is taken after the frame's
-    latency is recorded)."""
+    and, with keep_maps, per (camera, frame) device copies (disparity map,
+    U-map, V-map) of the maps computed, for later comparison (the copies are
+    taken after the frame's latency is recorded)."""
     dev = torch.device("cuda", ctx.device)
     copy_stream = torch.cuda.Stream(device=dev)
-    queued = collections.deque()   # (t_arrival, cam, k, slot)
-    inflight = []                  # (ticket, [(t_arrival, cam, k, slot)])
+    queued = collections.deque()   # (t_arrival, cam, k, slot, input-ready event)
+    inflight = []                  # (ticket, [(t_arrival, cam, k, slot, event)])
     # idle slots per camera: a few allocated up front, more only if a camera
     # has more frames queued or in flight at once
     free = [[_Slot(cam.p, dev) for _ in range(4)] for cam in cameras]
@@ -92,22 +94,24 @@ def serve(ctx: sgm.Context, cameras, trace, continuous: bool = True, max_batch: 
         t, ci, k = ev
         cam = cameras[ci]
         slot = free[ci].pop() if free[ci] else _Slot(cam.p, dev)
+        ready = torch.cuda.Event()
         with torch.cuda.stream(copy_stream):
             if slot.reuse_after is not None:  # the last copy of its outputs
                 copy_stream.wait_event(slot.reuse_after)
             slot.inp.copy_(cam.host[k % len(cam.host)], non_blocking=True)
-        copy_stream.synchronize()
-        return (t, ci, k, slot)
+            ready.record(copy_stream)
+        return (t, ci, k, slot, ready)
 
     def finish(items, tdone):
         nonlocal evals, finished
-        for (ta, ci, k, slot) in items:
+        for (ta, ci, k, slot, _) in items:
             lat.append(tdone - ta)
             evals += slot.frame.p.disp_evals()
             finished += 1
-        for (ta, ci, k, slot) in items:
+        for (ta, ci, k, slot, _) in items:
             if keep_maps:
-                done_frames[(ci, k)] = slot.frame.disp.clone()
+                f = slot.frame
+                done_frames[(ci, k)] = (f.disp.clone(), f.umap.clone(), f.vmap.clone())
                 slot.reuse_after = torch.cuda.Event()
                 slot.reuse_after.record()
             free[ci].append(slot)
@@ -131,7 +135,7 @@ def serve(ctx: sgm.Context, cameras, trace, continuous: bool = True, max_batch: 
             if queued and (continuous or not inflight):
                 take = min(len(queued), max_batch if continuous else 1)
                 items = [queued[j] for j in range(take)]
-                ticket = sgm.try_submit(ctx, [it[3].args for it in items])
+                ticket = sgm.try_submit(ctx, [it[3].args for it in items], after=[it[4] for it in items])
                 if ticket is not None:
                     for _ in range(take):
                         queued.popleft()

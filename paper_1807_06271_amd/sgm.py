@@ -38,7 +38,7 @@ EXPORTS = ["sgm_validate", "sgm_create", "sgm_destroy", "sgm_last_error", "sgm_c
            "sgm_disparity", "uv_maps", "sgm_submit", "sgm_poll", "sgm_wait", "sgm_memory", "sgm_profile",
            "sgm_profile_read", "sgm_set_streams", "sgm_set_schedule", "sgm_get_schedule",
            "sgm_autotune", "sgm_set_graphs", "sgm_graph_stats", "sgm_rectify",
-           "sgm_submit_rectify", "uv_filter"]
+           "sgm_submit_rectify", "uv_filter", "sgm_submit_after"]
 STAGES = ["census", "aggregate", "disparity", "median", "uv", "rectify"]
 
 
@@ -151,6 +151,7 @@ def lib():
         L.sgm_disparity.argtypes = [vp, P(sgm_params), vp, vp, vp]
         L.uv_maps.argtypes = [vp, P(sgm_params), vp, vp, vp, vp]
         L.sgm_submit.argtypes = [vp, P(sgm_frame), i32, P(ctypes.c_uint64)]
+        L.sgm_submit_after.argtypes = [vp, P(sgm_frame), i32, P(vp), i32, P(ctypes.c_uint64)]
         L.sgm_poll.argtypes = [vp, ctypes.c_uint64, P(i32)]
         L.sgm_wait.argtypes = [vp, ctypes.c_uint64]
         L.sgm_memory.argtypes = [vp, P(ctypes.c_size_t), P(ctypes.c_size_t)]
@@ -396,14 +397,34 @@ def sgm_submit_rectify(ctx: Context, frames, remaps) -> int:
     return t.value
 
 
-def try_submit(ctx: Context, frames) -> int | None:
-    """Like sgm_submit, but returns None instead of raising on SGM_EBUSY.
-    `frames` may hold Frame objects or their already marshalled sgm_frame
-    structs (Frame.c()), which a caller that resubmits the same buffers can
-    keep."""
+def _events(after):
+    """ctypes array of raw HIP event handles of torch.cuda.Event objects."""
+    ev = [e.cuda_event if hasattr(e, "cuda_event") else int(e) for e in after]
+    return (ctypes.c_void_p * len(ev))(*ev), len(ev)
+
+
+def sgm_submit_after(ctx: Context, frames, after) -> int:
+    """sgm_submit whose batch waits on the GPU for the events `after`
+    (torch.cuda.Event, recorded) before its first launch."""
+    arr = (sgm_frame * len(frames))(*[f if isinstance(f, sgm_frame) else f.c() for f in frames])
+    ev, n = _events(after)
+    t = ctypes.c_uint64()
+    _check(lib().sgm_submit_after(ctx.handle, arr, len(frames), ev, n, ctypes.byref(t)), "sgm_submit_after")
+    return t.value
+
+
+def try_submit(ctx: Context, frames, after=()) -> int | None:
+    """Like sgm_submit (sgm_submit_after when events are given in `after`),
+    but returns None instead of raising on SGM_EBUSY.  `frames` may hold
+    Frame objects or their already marshalled sgm_frame structs (Frame.c()),
+    which a caller that resubmits the same buffers can keep."""
     arr = (sgm_frame * len(frames))(*[f if isinstance(f, sgm_frame) else f.c() for f in frames])
     t = ctypes.c_uint64()
-    rc = lib().sgm_submit(ctx.handle, arr, len(frames), ctypes.byref(t))
+    if after:
+        ev, n = _events(after)
+        rc = lib().sgm_submit_after(ctx.handle, arr, len(frames), ev, n, ctypes.byref(t))
+    else:
+        rc = lib().sgm_submit(ctx.handle, arr, len(frames), ctypes.byref(t))
     if rc == SGM_EBUSY:
         return None
     _check(rc, "sgm_submit")

@@ -1,0 +1,120 @@
+"""Oracle parity of the whole path at the full sizes of the benchmark
+workloads (GPU required), in the launch configurations the benchmark uses:
+
+* eight 1920x1080 pairs, D = 256, Census 9x7, 8 paths, LR check, 3x3
+  median, U/V maps, all in one sgm_submit;
+* the batch of 32 pairs of mixed sizes (320x240, 640x480, 1242x375,
+  1280x720) and disparity ranges (64, 128) in one sgm_submit;
+* the four-camera request loop (640x480 and 1242x375 cameras, D = 128),
+  every served frame in both serving modes.
+
+Every frame's disparity map, U-map and V-map must equal the oracle's bit for
+bit (sections 3.1.2 to 3.2).  The oracle needs ~13 s per 1920x1080 D=256
+frame on 16 host threads, so the first test runs for about two minutes.
+"""
+import numpy as np
+import pytest
+
+from gen import synthetic
+from gpu_util import announce, assert_equal, gpu_or_skip, to_dev, to_np
+from oracle import oracle as O
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def env():
+    torch = gpu_or_skip()
+    from paper_1807_06271_amd import sgm
+    ctx = sgm.Context(0)
+    yield torch, sgm, ctx
+    torch.cuda.synchronize()
+    ctx.close()
+
+
+def full_path_params(sgm, W, H, D):
+    return sgm.Params(width=W, height=H, max_disp=D, census_w=9, census_h=7, path_mask=0xFF,
+                      p1=10, p2=120, lr_check=1, median=3, invalid=65535 if D > 255 else 255)
+
+
+def oracle_maps(p, left, right):
+    O.set_threads(16)
+    out = O.sgm(left, right, p.max_disp, p.census_w, p.census_h, p.path_mask, p.p1, p.p2,
+                bool(p.lr_check), p.lr_max_diff, p.median, p.inv())
+    return out["disp"], out["umap"], out["vmap"]
+
+
+def check_frame(f, want, tag):
+    disp, umap, vmap = want
+    assert_equal(to_np(f.disp), disp, "disp " + tag)
+    assert_equal(to_np(f.umap), umap, "umap " + tag)
+    assert_equal(to_np(f.vmap), vmap, "vmap " + tag)
+
+
+@pytest.mark.timeout(900)
+def test_eight_1920x1080_d256_pairs_in_one_submit_match_oracle(env):
+    torch, sgm, ctx = env
+    frames, inputs = [], []
+    for i in range(8):
+        left, right, _ = synthetic.make_pair("large", 4000 + i)
+        p = full_path_params(sgm, 1920, 1080, 256)
+        frames.append(sgm.Frame.alloc(p, to_dev(torch, left), to_dev(torch, right)))
+        inputs.append((p, left, right))
+    announce("8 x 1920x1080 D=256 in one submit")
+    sgm.sgm_wait(ctx, sgm.sgm_submit(ctx, frames))
+    torch.cuda.synchronize()
+    for i, ((p, left, right), f) in enumerate(zip(inputs, frames)):
+        announce("oracle frame", i)
+        check_frame(f, oracle_maps(p, left, right), "1920x1080 frame %d" % i)
+        # the maps are far from trivial: most pixels valid, many disparities
+        d = to_np(f.disp)
+        assert (d < 256).mean() > 0.5 and len(np.unique(d)) > 50
+
+
+@pytest.mark.timeout(600)
+def test_batch_of_32_mixed_pairs_matches_oracle(env):
+    torch, sgm, ctx = env
+    specs = synthetic.mixed_batch_specs(32, seed=2000)
+    assert {(w, h) for w, h, _, _ in specs} == {(320, 240), (640, 480), (1242, 375), (1280, 720)}
+    assert {d for _, _, d, _ in specs} == {64, 128}
+    frames, inputs = [], []
+    for (W, H, D, seed) in specs:
+        left, right, _ = synthetic.make_pair("kitti", seed, W, H, D)
+        p = full_path_params(sgm, W, H, D)
+        frames.append(sgm.Frame.alloc(p, to_dev(torch, left), to_dev(torch, right)))
+        inputs.append((p, left, right))
+    announce("32 mixed pairs in one submit")
+    sgm.sgm_wait(ctx, sgm.sgm_submit(ctx, frames))
+    torch.cuda.synchronize()
+    for i, ((p, left, right), f) in enumerate(zip(inputs, frames)):
+        check_frame(f, oracle_maps(p, left, right), "pair %d %dx%d D%d" % (i, p.width, p.height, p.max_disp))
+
+
+@pytest.mark.timeout(600)
+def test_four_camera_request_loop_serves_oracle_maps(env):
+    # the served workload's two frame shapes, each camera replaying three
+    # pre-rendered pairs; a short trace at the real 30 fps per camera, then a
+    # burst at 240 fps per camera so that frames queue and share batches
+    torch, sgm, ctx = env
+    from paper_1807_06271_amd import serve
+    cams, want = [], {}
+    for c in range(4):
+        sc = synthetic.camera_scene(c)
+        pairs = [synthetic.render_pair(sc, k)[:2] for k in range(3)]
+        p = full_path_params(sgm, sc.width, sc.height, 128)
+        cams.append(serve.Camera(p, pairs))
+        for k, (left, right) in enumerate(pairs):
+            want[(c, k)] = oracle_maps(p, left, right)
+    assert {(cam.p.width, cam.p.height) for cam in cams} == {(640, 480), (1242, 375)}
+    for label, fps, secs in (("30 fps", 30.0, 0.5), ("240 fps", 240.0, 0.25)):
+        trace = synthetic.poisson_trace(4, fps, secs, seed=3004)
+        for continuous in (True, False):
+            announce("serve", label, "continuous" if continuous else "per frame", len(trace), "frames")
+            stats, done = serve.serve(ctx, cams, trace, continuous=continuous)
+            assert stats["frames"] == len(trace) and len(done) == len(trace)
+            for (c, k), (disp, umap, vmap) in done.items():
+                w = want[(c, k % 3)]
+                tag = "camera %d frame %d (%s)" % (c, k, label)
+                assert_equal(to_np(disp), w[0], "disp " + tag)
+                assert_equal(to_np(umap), w[1], "umap " + tag)
+                assert_equal(to_np(vmap), w[2], "vmap " + tag)

@@ -64,3 +64,36 @@ def test_graph_replays_match_direct_launches_and_oracle(env):
     assert m1 - m0 == 1 and h1 - h0 == 3
     assert float(scratch[0]) == 4.0
     sgm.sgm_set_graphs(ctx, False)
+
+
+def test_graph_cache_keeps_census_and_sad_batches_apart(env):
+    # two batches identical in every parameter but the cost kind: they launch
+    # different kernels, so each must get its own cached graph, and replays
+    # in turn must keep matching the oracle
+    torch, sgm, ctx = env
+    announce("graphs: Census and SAD batches of one shape")
+    W, H, D = 192, 64, 64
+    items = {}
+    for kind, seed in ((sgm.COST_CENSUS, 610), (sgm.COST_SAD, 611)):
+        left, right, _ = synthetic.make_pair("kitti", seed, W, H, D)
+        p = sgm.Params(width=W, height=H, max_disp=D, census_w=5, census_h=5, path_mask=sgm.PATHS_PAPER4,
+                       p1=200, p2=800, lr_check=1, median=5, cost=kind)
+        o = O.sgm(left, right, D, 5, 5, p.path_mask, 200, 800, True, 1, 5, cost_kind=kind)
+        items[kind] = (p, to_dev(torch, left), to_dev(torch, right), o)
+    sgm.sgm_set_graphs(ctx, True)
+    try:
+        h0, m0 = sgm.sgm_graph_stats(ctx)
+        for rep in range(3):
+            for kind in (sgm.COST_CENSUS, sgm.COST_SAD):
+                p, L, R, o = items[kind]
+                f = sgm.Frame.alloc(p, L, R)
+                sgm.sgm_wait(ctx, sgm.sgm_submit(ctx, [f]))
+                torch.cuda.synchronize()
+                tag = "replay %d cost %d" % (rep, kind)
+                assert_equal(to_np(f.disp), o["disp"], "disp " + tag)
+                assert_equal(to_np(f.umap), o["umap"], "umap " + tag)
+                assert_equal(to_np(f.vmap), o["vmap"], "vmap " + tag)
+        h1, m1 = sgm.sgm_graph_stats(ctx)
+        assert m1 - m0 == 2 and h1 - h0 == 4
+    finally:
+        sgm.sgm_set_graphs(ctx, False)

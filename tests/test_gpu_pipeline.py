@@ -154,6 +154,8 @@ def test_constant_images_give_zero_disparity(env):
     announce("constant images")
     W, H, D = 300, 100, 64
     img = torch.full((H, W), 90, dtype=torch.uint8, device="cuda")
+    # the fill runs on torch's stream; sgm_submit does not wait for it
+    torch.cuda.synchronize()
     p = sgm.Params(width=W, height=H, max_disp=D)
     f = sgm.Frame.alloc(p, img, img)
     sgm.sgm_wait(ctx, sgm.sgm_submit(ctx, [f]))

@@ -154,6 +154,8 @@ def test_rectified_pair_through_the_whole_path(env):
 
     L2 = torch.zeros((h, w + 32), dtype=torch.uint8, device="cuda")   # pitched view buffers
     R2 = torch.zeros((h, w + 32), dtype=torch.uint8, device="cuda")
+    # the fills run on torch's stream; sgm_submit_rectify does not wait for it
+    torch.cuda.synchronize()
     g = sgm.Frame.alloc(p, L2, R2)
     sgm.sgm_wait(ctx, sgm.sgm_submit_rectify(ctx, [g], [(RL, *dmaps[0]), (RR, *dmaps[1])]))
     assert_equal(to_np(L2)[:, :w], left, "rectified left (in batch)")

@@ -32,12 +32,20 @@ def test_continuous_batching_equals_per_frame_and_oracle():
     assert a_stats["frames"] == b_stats["frames"] == len(trace)
     assert a.keys() == b.keys() and len(a) == len({(c, k) for _, c, k in trace})
     for key in a:
-        assert torch.equal(a[key], b[key]), key
-    cam, k = next(iter(a))
-    left, right = (t.numpy() for t in cams[cam].pair(k))
-    p = cams[cam].p
-    want = O.sgm(left, right, p.max_disp, p.census_w, p.census_h, p.path_mask, p.p1, p.p2, True, 1, 3)
-    assert_equal(to_np(a[(cam, k)]), want["disp"], "served frame vs oracle")
+        for x, y in zip(a[key], b[key]):
+            assert torch.equal(x, y), key
+    # every served frame against the oracle (two pre-rendered pairs per camera)
+    want = {}
+    for (cam, k), (disp, umap, vmap) in a.items():
+        if (cam, k % 2) not in want:
+            left, right = (t.numpy() for t in cams[cam].pair(k))
+            p = cams[cam].p
+            want[(cam, k % 2)] = O.sgm(left, right, p.max_disp, p.census_w, p.census_h, p.path_mask,
+                                       p.p1, p.p2, True, 1, 3)
+        w = want[(cam, k % 2)]
+        assert_equal(to_np(disp), w["disp"], "served disp vs oracle %s" % ((cam, k),))
+        assert_equal(to_np(umap), w["umap"], "served umap vs oracle %s" % ((cam, k),))
+        assert_equal(to_np(vmap), w["vmap"], "served vmap vs oracle %s" % ((cam, k),))
 
 
 def test_back_pressure_from_a_small_budget():
