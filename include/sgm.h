@@ -191,6 +191,22 @@ int sgm_aggregate(sgm_ctx *ctx, const sgm_params *p, const uint16_t *cost, uint1
 int sgm_disparity(sgm_ctx *ctx, const sgm_params *p, const uint16_t *aggr, uint16_t *disp,
                   void *stream);
 
+/* sgm_disparity that allocates nothing, for callers that cannot allocate
+ * device memory: code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc.  Same arguments, same results (bit for bit) as
+ * sgm_disparity.  Its scratch (the map before the median, D_L and the row
+ * segments' right-view keys: 2*align256(2*W*H) + 4*H*nseg*(seglen + D - 1)
+ * bytes, nseg = max(1, W / max(256, 2*D)), seglen = ceil(W / nseg); 20 MiB
+ * for 1920x1080, D = 256) lives in a fixed 32 MiB array in the library's
+ * device memory: one per GPU, mapped by sgm_create, held until the process
+ * ends.  Larger frames get SGM_ENOMEM before anything is enqueued.  Every
+ * call on a GPU uses that GPU's one array and leaves its contents behind
+ * (no call relies on them): calls on one GPU whose work overlaps in time --
+ * other streams, other contexts, other threads -- race on it, so serialise
+ * them (e.g. enqueue them all on one stream). */
+int sgm_disparity_noalloc(sgm_ctx *ctx, const sgm_params *p, const uint16_t *aggr, uint16_t *disp,
+                          void *stream);
+
 /* U-/V-maps (section 3.2): per-column and per-row disparity histograms of
  * disp; values >= D (the invalid marker) are not counted.  disp: device
  * uint16 [H][W]; umap: device uint16 [D][W]; vmap: device uint16 [H][D].

@@ -150,6 +150,7 @@ struct sgm_ctx {
   std::map<ShapeKey, sgm_schedule> tuned;  // per-shape schedules (sgm_set_schedule / autotune)
   double stage_ms[SGM_NSTAGES] = {};
   uint64_t stage_count[SGM_NSTAGES] = {};
+  void *static_scratch = nullptr;  // device address of `scratch` on this device
 
   size_t held() const {
     size_t s = stage.bytes;
@@ -164,7 +165,37 @@ struct sgm_ctx {
   }
 };
 
+// Fixed scratch of the allocation-free entry point (sgm_disparity_noalloc):
+// one array per GPU, in the code object's device memory, held until the
+// process ends.  Host code never passes `scratch` itself (on the host it is
+// only a stand-in for the symbol); it uses the device address that
+// hipGetSymbolAddress returns for the current device.
+constexpr size_t kStaticScratchBytes = (size_t)32 << 20;
+static __device__ __align__(256) uint8_t scratch[kStaticScratchBytes];
+
 namespace {
+
+std::mutex g_scratch_mu;
+std::map<int, void *> g_scratch_addr;  // device -> address of `scratch` there
+
+// Device address of `scratch` on `device` (which must be current), looked up
+// once per device.
+int static_scratch_of(int device, void **out) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  auto it = g_scratch_addr.find(device);
+  if (it == g_scratch_addr.end()) {
+    void *ptr = nullptr;
+    hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+      return fail(SGM_EHIP, "hipGetSymbolAddress(scratch) on device %d: %s", device, hipGetErrorString(e));
+    it = g_scratch_addr.emplace(device, ptr).first;
+  }
+  *out = it->second;
+  return SGM_OK;
+}
+
+size_t disparity_scratch_bytes(const sgm_params &p);
+int enqueue_disparity(const sgm_params *p, const uint16_t *aggr, uint16_t *disp, void *v, hipStream_t s);
 
 struct DeviceGuard {
   int prev = -1;
@@ -751,8 +782,11 @@ int sgm_create(sgm_ctx **ctx, int device, size_t hbm_budget_bytes) {
   if (!g.ok) return fail(SGM_EHIP, "hipSetDevice(%d) failed", device);
   size_t freeb = 0, total = 0;
   HIP_TRY(hipMemGetInfo(&freeb, &total));
+  void *fixed = nullptr;
+  CHECK(static_scratch_of(device, &fixed));
   auto *c = new sgm_ctx();
   c->device = device;
+  c->static_scratch = fixed;
   c->budget = hbm_budget_bytes ? hbm_budget_bytes : freeb / 2;
   for (int i = 0; i < sgm_ctx::kStreams; ++i) {
     if (hipStreamCreateWithFlags(&c->streams[i], hipStreamNonBlocking) != hipSuccess) {
@@ -924,11 +958,44 @@ int sgm_disparity(sgm_ctx *c, const sgm_params *p, const uint16_t *aggr, uint16_
   CHECK(check_dev_ptr(aggr, c->device, "aggr"));
   CHECK(check_dev_ptr(disp, c->device, "disp"));
   hipStream_t s = (hipStream_t)stream;
-  // scratch: the pre-median map, D_L and the segments' right-view keys
+  void *v = nullptr;
+  CHECK(stage_scratch(c, disparity_scratch_bytes(*p), s, &v));
+  return enqueue_disparity(p, aggr, disp, v, s);
+}
+
+int sgm_disparity_noalloc(sgm_ctx *c, const sgm_params *p, const uint16_t *aggr, uint16_t *disp,
+                          void *stream) {
+  if (!c) return fail(SGM_EINVAL, "ctx is null");
+  CHECK(validate(p));
+  const size_t need = disparity_scratch_bytes(*p);
+  if (need > kStaticScratchBytes)
+    return fail(SGM_ENOMEM, "sgm_disparity_noalloc: a %dx%d D=%d frame needs %zu bytes of scratch, "
+                "the library's fixed scratch holds %zu", p->width, p->height, p->max_disp, need,
+                kStaticScratchBytes);
+  std::lock_guard<std::mutex> lk(c->mu);
+  if (!c->static_scratch) return fail(SGM_EHIP, "the fixed scratch of device %d is not mapped", c->device);
+  DeviceGuard g(c->device);
+  CHECK(check_dev_ptr(aggr, c->device, "aggr"));
+  CHECK(check_dev_ptr(disp, c->device, "disp"));
+  return enqueue_disparity(p, aggr, disp, c->static_scratch, (hipStream_t)stream);
+}
+
+}  // extern "C"
+
+namespace {
+
+// Scratch of disparity selection: the pre-median map, D_L and the row
+// segments' right-view keys.
+size_t disparity_scratch_bytes(const sgm_params &p) {
+  const size_t m2 = align256((size_t)p.width * p.height * 2);
+  return 2 * m2 + disp_part_bytes(p.width, p.height, p.max_disp);
+}
+
+// WTA + right-view keys, LR check and median of one frame from the caller's
+// S, with its scratch at `v` (disparity_scratch_bytes).
+int enqueue_disparity(const sgm_params *p, const uint16_t *aggr, uint16_t *disp, void *v, hipStream_t s) {
   const size_t px = (size_t)p->width * p->height;
   const size_t m2 = align256(px * 2);
-  void *v = nullptr;
-  CHECK(stage_scratch(c, 2 * m2 + disp_part_bytes(p->width, p->height, p->max_disp), s, &v));
   uint16_t *tmp = reinterpret_cast<uint16_t *>(v);
   uint16_t *dlmap = reinterpret_cast<uint16_t *>(reinterpret_cast<char *>(v) + m2);
   uint32_t *part = reinterpret_cast<uint32_t *>(reinterpret_cast<char *>(v) + 2 * m2);
@@ -973,6 +1040,10 @@ int sgm_disparity(sgm_ctx *c, const sgm_params *p, const uint16_t *aggr, uint16_
   }
   return SGM_OK;
 }
+
+}  // namespace
+
+extern "C" {
 
 int uv_maps(sgm_ctx *c, const sgm_params *p, const uint16_t *disp, uint16_t *umap, uint16_t *vmap,
             void *stream) {

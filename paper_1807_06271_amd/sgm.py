@@ -38,7 +38,8 @@ EXPORTS = ["sgm_validate", "sgm_create", "sgm_destroy", "sgm_last_error", "sgm_c
            "sgm_disparity", "uv_maps", "sgm_submit", "sgm_poll", "sgm_wait", "sgm_memory", "sgm_profile",
            "sgm_profile_read", "sgm_set_streams", "sgm_set_schedule", "sgm_get_schedule",
            "sgm_autotune", "sgm_set_graphs", "sgm_graph_stats", "sgm_rectify",
-           "sgm_submit_rectify", "uv_filter", "sgm_submit_after"]
+           "sgm_submit_rectify", "uv_filter", "sgm_submit_after",
+           "sgm_disparity_noalloc"]
 STAGES = ["census", "aggregate", "disparity", "median", "uv", "rectify"]
 
 
@@ -149,6 +150,7 @@ def lib():
         L.sgm_cost_sad.argtypes = [vp, P(sgm_params), vp, vp, ctypes.c_int64, vp, vp]
         L.sgm_aggregate.argtypes = [vp, P(sgm_params), vp, vp, vp]
         L.sgm_disparity.argtypes = [vp, P(sgm_params), vp, vp, vp]
+        L.sgm_disparity_noalloc.argtypes = [vp, P(sgm_params), vp, vp, vp]
         L.uv_maps.argtypes = [vp, P(sgm_params), vp, vp, vp, vp]
         L.sgm_submit.argtypes = [vp, P(sgm_frame), i32, P(ctypes.c_uint64)]
         L.sgm_submit_after.argtypes = [vp, P(sgm_frame), i32, P(vp), i32, P(ctypes.c_uint64)]
@@ -323,6 +325,14 @@ def sgm_disparity(ctx: Context, p: Params, aggr, disp, stream=None):
     _need(disp, (p.height, p.width), torch.uint16, "disp")
     _check(lib().sgm_disparity(ctx.handle, ctypes.byref(p.c()), _ptr(aggr), _ptr(disp), _stream(stream)),
            "sgm_disparity")
+
+
+def sgm_disparity_noalloc(ctx: Context, p: Params, aggr, disp, stream=None):
+    """sgm_disparity with the library's fixed scratch: no device allocation."""
+    _need(aggr, (p.height, p.width, p.max_disp), torch.uint16, "aggr")
+    _need(disp, (p.height, p.width), torch.uint16, "disp")
+    _check(lib().sgm_disparity_noalloc(ctx.handle, ctypes.byref(p.c()), _ptr(aggr), _ptr(disp),
+                                       _stream(stream)), "sgm_disparity_noalloc")
 
 
 def uv_maps(ctx: Context, p: Params, disp, umap, vmap, stream=None):
