@@ -1,20 +1,24 @@
 """Benchmark of the SGM hot path on one MI355X.
 
-    python bench.py [--steps K] [--warmup W] [--extras none|batch|all] [--serve-seconds S]
+    python bench.py [--steps K] [--warmup W] [--extras none|kitti|batch|serve|all]
+                    [--serve-seconds S] [--streams N]
 
 A step is one pass of the whole path (Census of both views, Hamming costs,
 8-path aggregation, WTA + right-view disparity + left-right check, 3x3
-median, U-/V-maps) over one synthetic 1242x375 pair with D = 128 (the
-KITTI-shaped workload), inputs already in device memory.  Steps go through
-sgm_submit on one library stream (frames run back to back, up to 8 queued);
-the timed region is bracketed by torch.cuda.synchronize().
+median, U-/V-maps) over one batch of eight synthetic 1920x1080 pairs with
+D = 256 (the largest workload, about 1 GB of cost volume per pair), all eight
+in one sgm_submit, inputs already in device memory.  Up to three batches are
+in flight on the library context's streams; the timed region is bracketed by
+torch.cuda.synchronize().  The library brackets every stage of every batch
+with HIP events on the batch's own stream during the timed loop, which gives
+the aggregation kernel's launch time for the roofline position.
 
 Prints ONE JSON line: the throughput in Mdisp-evals/s (W*H*D*paths per
-second), the aggregation kernel's roofline position (its average launch time
-from HIP events the library records around it on its own stream), the CPU
-oracle timed on a bounded sample of the same workload, and secondary
-measurements (per-frame stage calls, a batch of 32 mixed pairs, a batch of 8
-1920x1080 D=256 pairs, and the multi-camera request loop).
+second), the aggregation kernel's roofline position, the CPU oracle timed on
+a bounded sample of the same workload, and secondary measurements (the
+1242x375 D=128 pair one frame per submit and its latency, the per-frame
+stage calls, 320x240, the paper's own setting, the batch of 32 mixed pairs,
+and the multi-camera request loop).
 """
 from __future__ import annotations
 
@@ -30,8 +34,15 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
-ALG_BYTES_PER_EVAL = 4         # read + write of a uint16 running sum per path and cell
+# Algorithmic bytes of the aggregation kernel per disparity evaluation (one
+# path, one cell, one disparity): it reads the cell's uint8 matching cost and
+# writes the cell's uint8 path cost, once per path.
+AGG_BYTES_PER_EVAL = 2
+# The survey's schedule-independent count: a uint16 running sum S read and
+# written per path and cell.
+SURVEY_BYTES_PER_EVAL = 4
 HEADLINE_STREAMS = 4           # the library context's default stream count
+HEADLINE_DEPTH = 3             # 8-frame batches in flight (38 GB of scratch each)
 
 
 def log(*a):
@@ -76,22 +87,18 @@ def cpu_model() -> str:
     return "unknown"
 
 
-def cpu_baseline(left, right, p, seconds_target=12.0):
-    """The oracle on the host: whole pairs with OpenMP over scanlines on all
-    the cores it gets (the reported value), then one thread on a 94-row crop
-    of the same pair (a bounded sample, scaled to the same unit)."""
+def cpu_baseline(left, right, p):
+    """The oracle on the host, on a bounded sample of the workload: one full
+    pair of the batch with OpenMP over scanlines on all the cores it gets
+    (the reported value), then one thread on a 48-row crop of the same pair,
+    scaled to the same unit."""
     from oracle import oracle as O
     threads = O.threads()
-    runs, t_total = 0, 0.0
-    while t_total < seconds_target or runs == 0:
-        t0 = time.perf_counter()
-        O.sgm(left, right, p.max_disp, p.census_w, p.census_h, p.path_mask, p.p1, p.p2, True,
-              p.lr_max_diff, p.median, p.inv())
-        t_total += time.perf_counter() - t0
-        runs += 1
-        if runs >= 5:
-            break
-    rows = min(94, p.height)
+    t0 = time.perf_counter()
+    O.sgm(left, right, p.max_disp, p.census_w, p.census_h, p.path_mask, p.p1, p.p2, True,
+          p.lr_max_diff, p.median, p.inv())
+    t_full = time.perf_counter() - t0
+    rows = min(48, p.height)
     O.set_threads(1)
     try:
         t0 = time.perf_counter()
@@ -101,10 +108,10 @@ def cpu_baseline(left, right, p, seconds_target=12.0):
     finally:
         O.set_threads(threads)
     one = p.width * rows * p.max_disp * bin(p.path_mask).count("1") / t1 / 1e6
-    return {"value": round(runs * p.disp_evals() / t_total / 1e6, 2), "unit": "Mdisp-evals/s",
+    return {"value": round(p.disp_evals() / t_full / 1e6, 2), "unit": "Mdisp-evals/s",
             "cores": threads, "kind": "oracle",
-            "sample": "%d full %dx%d D=%d 8-path pairs through the C oracle (-O2, OpenMP over "
-                      "scanlines), %.1f s" % (runs, p.width, p.height, p.max_disp, t_total),
+            "sample": "one full %dx%d D=%d 8-path pair of the batch through the C oracle (-O2, OpenMP "
+                      "over scanlines), %.1f s" % (p.width, p.height, p.max_disp, t_full),
             "single_thread": {"value": round(one, 2), "sample": "one %dx%d crop, one thread, %.1f s"
                               % (p.width, rows, t1)},
             "cpu_model": cpu_model(), "host_cpus": os.cpu_count()}
@@ -334,61 +341,6 @@ def bench_batch32(torch, sgm, ctx, synthetic):
     return res
 
 
-def bench_large(torch, sgm, ctx, synthetic, nframes=8):
-    """Eight 1920x1080 D=256 pairs (8 paths, LR, 3x3 median, U/V): one submit
-    of all eight vs eight sequential one-frame submits on the same inputs
-    (outputs compared), and the aggregation kernel's roofline position, with
-    the HBM bytes it actually moves when the committed counter record for
-    this workload matches the kernel sources."""
-    frames = []
-    for i in range(nframes):
-        L, R, _ = synthetic.make_pair("large", 4000 + i)
-        p = kitti_params(sgm, 1920, 1080, 256)
-        p.invalid = 65535
-        frames.append(sgm.Frame.alloc(p, torch.from_numpy(L).cuda(), torch.from_numpy(R).cuda()))
-    evals = sum(f.p.disp_evals() for f in frames)
-    h_lanes = sgm.sgm_autotune(ctx, frames[0], reps=2)[0]
-    sgm.sgm_wait(ctx, sgm.sgm_submit(ctx, frames))
-    batched = [f.disp.clone() for f in frames]
-    sgm.sgm_profile_read(ctx, reset=True)
-    torch.cuda.synchronize()
-    reps = 2
-    t0 = time.perf_counter()
-    for _ in range(reps):
-        sgm.sgm_wait(ctx, sgm.sgm_submit(ctx, frames))
-    torch.cuda.synchronize()
-    t = (time.perf_counter() - t0) / reps
-    prof = sgm.sgm_profile_read(ctx, reset=True)
-    agg_ms, agg_n = prof["aggregate"]
-    agg_avg = agg_ms / max(agg_n, 1)
-    achieved = ALG_BYTES_PER_EVAL * evals / (agg_avg * 1e-3) / 1e9
-    # the same frames one submit at a time (queued back to back)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(reps):
-        ts = [sgm.sgm_submit(ctx, [f]) for f in frames]
-        for tk in ts:
-            sgm.sgm_wait(ctx, tk)
-    torch.cuda.synchronize()
-    tseq = (time.perf_counter() - t0) / reps
-    same = all(torch.equal(a, f.disp) for a, f in zip(batched, frames))
-    res = {"frames": nframes, "width": 1920, "height": 1080, "max_disp": 256, "paths": 8,
-           "h_lanes": h_lanes,
-           "batch_ms": t * 1e3, "mdisp_evals_per_s": evals / t / 1e6, "fps": nframes / t,
-           "sequential_submits_ms": tseq * 1e3, "sequential_mdisp_evals_per_s": evals / tseq / 1e6,
-           "batched_equals_sequential": bool(same),
-           "aggregate_launch_ms": agg_avg,
-           "aggregate_alg_GBs": achieved, "aggregate_hbm_frac": achieved / HBM_PEAK_GBS,
-           "stage_ms_per_batch": {k: v[0] / reps for k, v in prof.items()}}
-    moved = measured_traffic("agg_kernel<16, %d, %d, 0, unsigned char" % (256 // h_lanes, h_lanes),
-                             "traffic_agg_1920x1080_d256_batch8.json")
-    if moved is not None:
-        res["aggregate_measured_bytes"] = moved
-        res["aggregate_measured_GBs"] = moved / (agg_avg * 1e-3) / 1e9
-        res["aggregate_measured_hbm_frac"] = res["aggregate_measured_GBs"] / HBM_PEAK_GBS
-    return res
-
-
 def bench_serve(torch, sgm, synthetic, ctx, seconds, stress_cameras=48, stress_seconds=4.0):
     """The 4-camera request loop at 30 fps per camera (640x480 and 1242x375,
     D=128, 8 paths), continuous batching vs one frame at a time on the
@@ -452,17 +404,99 @@ def measured_traffic(kernel_prefix, record="traffic_agg_1242x375_d128.json"):
     return None
 
 
+def large_params(sgm):
+    """The 1920x1080 workload: D = 256, Census 9x7, 8 paths, P1 = 10, P2 = 120,
+    LR check, 3x3 median, U/V maps; 65535 marks invalid pixels (255 is a
+    valid disparity at D = 256)."""
+    return sgm.Params(width=1920, height=1080, max_disp=256, census_w=9, census_h=7, path_mask=0xFF,
+                      p1=10, p2=120, lr_check=1, median=3, invalid=65535)
+
+
+def bench_kitti(torch, sgm, ctx, synthetic, steps=200, warmup=20):
+    """The 1242x375 D=128 pair (KITTI-shaped), one frame per submit: up to 8
+    submits in flight on the context's four streams and on one stream (maps
+    compared), in graph mode, one frame at a time (latency), and through the
+    five per-frame stage calls."""
+    left, right, _ = synthetic.make_pair("kitti", 1001)
+    p = kitti_params(sgm)
+    L, R = torch.from_numpy(left).cuda(), torch.from_numpy(right).cuda()
+    h_lanes, tune_ms = sgm.sgm_autotune(ctx, sgm.Frame.alloc(p, L, R), reps=5)
+    sgm.sgm_profile(ctx, False)
+    res = {"schedule": {"h_lanes": h_lanes, "autotune_ms": tune_ms}}
+    outs = {}
+    for streams in (HEADLINE_STREAMS, 1):
+        sgm.sgm_set_streams(ctx, streams)
+        dt, outs[streams] = time_submit_stream(torch, sgm, ctx, lambda i: [sgm.Frame.alloc(p, L, R)],
+                                               steps, warmup)
+        res["streams%d" % streams] = {"mdisp_evals_per_s": p.disp_evals() * steps / dt / 1e6,
+                                      "fps": steps / dt, "ms_per_frame": dt / steps * 1e3}
+    res["four_streams_equal_one_stream"] = all(
+        torch.equal(a[0].disp, b[0].disp) and torch.equal(a[0].umap, b[0].umap)
+        and torch.equal(a[0].vmap, b[0].vmap) for a, b in zip(outs[1], outs[HEADLINE_STREAMS]))
+    sgm.sgm_set_graphs(ctx, True)
+    dt, _ = time_submit_stream(torch, sgm, ctx, lambda i: [sgm.Frame.alloc(p, L, R)], steps, warmup)
+    sgm.sgm_set_graphs(ctx, False)
+    res["graph_mode_one_stream_mdisp_evals_per_s"] = p.disp_evals() * steps / dt / 1e6
+    # one frame at a time, submit to result
+    lat = []
+    one = outs[1][0]
+    for _ in range(200):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sgm.sgm_wait(ctx, sgm.sgm_submit(ctx, one))
+        lat.append(time.perf_counter() - t0)
+    lat_ms = np.array(lat) * 1e3
+    res["frame_latency_ms"] = {"p50": float(np.percentile(lat_ms, 50)), "p99": float(np.percentile(lat_ms, 99))}
+    # the per-frame stage-call path (materialised cost and S volumes)
+    for _ in range(2):
+        sgm.run_stages(ctx, p, L, R)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    nst = 10
+    for _ in range(nst):
+        sgm.run_stages(ctx, p, L, R)
+    torch.cuda.synchronize()
+    res["per_frame_stage_calls_mdisp_evals_per_s"] = p.disp_evals() * nst / (time.perf_counter() - t0) / 1e6
+    sgm.sgm_set_streams(ctx, HEADLINE_STREAMS)
+    return res
+
+
+def agg_kernel_name(h_lanes):
+    """The aggregation kernel instance the 1920x1080 D=256 frames run:
+    16 disparities per lane on 16-lane scanlines, 256 / h_lanes on the
+    horizontal ones, uint8 costs and path costs."""
+    return "agg_kernel<16, %d, %d, 0, unsigned char" % (256 // h_lanes, h_lanes)
+
+
+def measured_valu(kernel_prefix, record):
+    """VALU issue utilisation of a kernel from a committed counter summary
+    (profiles/counters_*.txt), or None when the record is missing or was
+    taken on other aggregation sources."""
+    path = os.path.join(ROOT, "profiles", record)
+    if not os.path.exists(path):
+        return None
+    from paper_1807_06271_amd.profiling import source_hash
+    text = open(path).read()
+    if "source hash %s" % source_hash() not in text:
+        return None
+    for line in text.splitlines():
+        if kernel_prefix in line and "VALU util" in line:
+            return float(line.split("VALU util")[1].split()[0])
+    return None
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
-    ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--extras", choices=["none", "large", "batch", "serve", "all"], default="all",
-                    help="secondary measurements: none; large (the 8 x 1920x1080 batch only); "
-                         "batch (all batch forms); serve (the request loop only); "
+    ap.add_argument("--steps", type=int, default=20, help="timed steps (8-frame batches)")
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--streams", type=int, default=HEADLINE_STREAMS,
+                    help="library streams the headline batches rotate over")
+    ap.add_argument("--extras", choices=["none", "kitti", "batch", "serve", "all"], default="all",
+                    help="secondary measurements: none; kitti (the 1242x375 frame only); "
+                         "batch (every batch form); serve (the request loop only); "
                          "all (batch forms and the request loop)")
-    ap.add_argument("--serve-seconds", type=float, default=30.0)
-    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--serve-seconds", type=float, default=60.0)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run one plain device copy of a known size (counter calibration)")
@@ -489,10 +523,6 @@ def main():
     ctx = sgm.Context(0)
     serve_ctx = sgm.Context(0)
 
-    left, right, _ = synthetic.make_pair("kitti", 1001)
-    p = kitti_params(sgm)
-    L = torch.from_numpy(left).cuda()
-    R = torch.from_numpy(right).cuda()
     if args.calibrate_copy:
         from paper_1807_06271_amd.profiling import CALIBRATION_BYTES
         src = torch.ones(CALIBRATION_BYTES, dtype=torch.uint8, device="cuda")
@@ -501,73 +531,60 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
-    # autotune the schedule of this shape once (the winner stays in the context)
-    h_lanes, tune_ms = sgm.sgm_autotune(ctx, sgm.Frame.alloc(p, L, R), reps=5)
+    log("inputs: 8 x 1920x1080 D=256")
+    p = large_params(sgm)
+    pairs = [synthetic.make_pair("large", 4000 + i)[:2] for i in range(8)]
+    inputs = [(torch.from_numpy(l).cuda(), torch.from_numpy(r).cuda()) for l, r in pairs]
+    evals = 8 * p.disp_evals()
+    h_lanes, tune_ms = sgm.sgm_autotune(ctx, sgm.Frame.alloc(p, *inputs[0]), reps=2)
     log("autotuned h_lanes", h_lanes, tune_ms)
-    log("main: 1242x375 D=128 8 paths, steps", args.steps)
-    # one stream first: the frames run strictly back to back, nothing else
-    # shares the GPU (kernel durations in a trace of this loop are clean)
-    sgm.sgm_set_streams(ctx, 1)
-    sgm.sgm_profile(ctx, False)
-    dt1, outs = time_submit_stream(torch, sgm, ctx, lambda i: [sgm.Frame.alloc(p, L, R)],
-                                   args.steps, args.warmup)
-    # the same loop again with per-stage HIP events (they add a marker per
-    # stage boundary, so they stay out of the timed loops); the aggregation
-    # kernel's event-timed duration gives the roofline position
+
+    def batch(i):
+        return [sgm.Frame.alloc(p, l, r) for l, r in inputs]
+
+    # the headline: one submit of all eight pairs per step, batches rotating
+    # over the context's streams, stage events recorded on each batch's stream
+    log("headline: %d steps of 8 x 1920x1080 D=256 on %d streams" % (args.steps, args.streams))
+    sgm.sgm_set_streams(ctx, args.streams)
     sgm.sgm_profile(ctx, True)
+    time_submit_stream(torch, sgm, ctx, batch, args.warmup, 0, depth=HEADLINE_DEPTH)
     sgm.sgm_profile_read(ctx, reset=True)
-    dtp, _ = time_submit_stream(torch, sgm, ctx, lambda i: [sgm.Frame.alloc(p, L, R)],
-                                args.steps, args.warmup)
+    dt, outs = time_submit_stream(torch, sgm, ctx, batch, args.steps, 0, depth=HEADLINE_DEPTH)
     prof = sgm.sgm_profile_read(ctx, reset=True)
-    # the headline: the context's default of 4 streams, one frame per
-    # submit; consecutive frames overlap on the GPU (one frame's
-    # aggregation next to the next frame's Census and the previous one's
-    # disparity selection)
-    sgm.sgm_profile(ctx, False)
-    sgm.sgm_set_streams(ctx, HEADLINE_STREAMS)
-    dt, outs4 = time_submit_stream(torch, sgm, ctx, lambda i: [sgm.Frame.alloc(p, L, R)],
-                                   args.steps, args.warmup)
-    same_as_one_stream = all(torch.equal(a[0].disp, b[0].disp) and torch.equal(a[0].umap, b[0].umap)
-                             and torch.equal(a[0].vmap, b[0].vmap) for a, b in zip(outs, outs4))
-    # and in graph mode (captured batches replayed from the graph cache)
+    # the same steps on one stream (batches strictly back to back: the
+    # kernels' event times are then those of each kernel alone on the GPU)
     sgm.sgm_set_streams(ctx, 1)
-    sgm.sgm_set_graphs(ctx, True)
-    dtg, _ = time_submit_stream(torch, sgm, ctx, lambda i: [sgm.Frame.alloc(p, L, R)],
-                                args.steps, args.warmup)
-    sgm.sgm_set_graphs(ctx, False)
-    # the secondary measurements below choose their own stream counts; the
-    # batch comparisons run on one stream
-    evals = p.disp_evals()
+    dt1, outs1 = time_submit_stream(torch, sgm, ctx, batch, args.steps, 0, depth=HEADLINE_DEPTH)
+    prof1 = sgm.sgm_profile_read(ctx, reset=True)
+    same = all(torch.equal(a.disp, b.disp) and torch.equal(a.umap, b.umap) and torch.equal(a.vmap, b.vmap)
+               for x, y in zip(outs, outs1) for a, b in zip(x, y))
+    # the same frames as 8 one-frame submits per step (one stream)
+    dts, _ = time_submit_stream(torch, sgm, ctx, lambda i: [sgm.Frame.alloc(p, *inputs[i % 8])],
+                                8 * args.steps, 0, depth=8)
+    sgm.sgm_profile_read(ctx, reset=True)
+    sgm.sgm_set_streams(ctx, HEADLINE_STREAMS)
+
+    def per_stage(pr):
+        return {k: round(v[0] / max(v[1], 1), 5) for k, v in pr.items()}
+
     value = evals * args.steps / dt / 1e6
-    # per-stage averages over the profiled loop (warm-up + timed steps)
-    n_batches = args.steps + args.warmup
-    stage_avg_ms = {k: v[0] / max(v[1], 1) for k, v in prof.items()}
-    agg_ms = stage_avg_ms["aggregate"]
-    achieved = ALG_BYTES_PER_EVAL * evals / (agg_ms * 1e-3) / 1e9
+    # roofline: the aggregation launch time from the events of the one-stream
+    # timed loop, where it runs alone on the GPU (with batches overlapping on
+    # several streams an event pair also spans the other batches' kernels)
+    agg_ms, agg_n = prof1["aggregate"]
+    agg_avg = agg_ms / max(agg_n, 1)
+    agg_overlapped = prof["aggregate"][0] / max(prof["aggregate"][1], 1)
+    alg = AGG_BYTES_PER_EVAL * evals
+    achieved = alg / (agg_avg * 1e-3) / 1e9
+    traffic = measured_traffic(agg_kernel_name(h_lanes), "traffic_agg_1920x1080_d256_batch8.json")
+    valu = measured_valu(agg_kernel_name(h_lanes), "counters_1920x1080_d256_batch8.txt")
 
-    # frame latency of the fused path, one frame at a time (no stage
-    # markers: they would add their own cost to every frame)
-    lat = []
-    for _ in range(200):
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        sgm.sgm_wait(ctx, sgm.sgm_submit(ctx, outs[0]))
-        lat.append(time.perf_counter() - t0)
-    lat_ms = np.array(lat) * 1e3
-
-    # per-frame stage-call path (materialised cost and S volumes)
-    for _ in range(2):
-        sgm.run_stages(ctx, p, L, R)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    nst = 10
-    for _ in range(nst):
-        sgm.run_stages(ctx, p, L, R)
-    torch.cuda.synchronize()
-    stage_path = evals * nst / (time.perf_counter() - t0) / 1e6
-
-    sgm.sgm_profile(ctx, True)  # the extras read stage times
     extras = {}
+    sgm.sgm_profile(ctx, False)
+    if args.extras in ("kitti", "batch", "all"):
+        log("1242x375 D=128, one frame per submit")
+        extras["kitti_1242x375_d128_8path"] = bench_kitti(torch, sgm, ctx, synthetic)
+    sgm.sgm_profile(ctx, True)
     if args.extras in ("batch", "all"):
         log("320x240 D=64 5x5 4 paths, WTA only")
         extras["small_320x240_d64_4path_wta"] = bench_small(torch, sgm, ctx, synthetic)
@@ -575,9 +592,6 @@ def main():
         extras["paper_640x360_d60_4path"] = bench_paper_settings(torch, sgm, ctx, synthetic)
         log("batch of 32 mixed pairs")
         extras["batch32_mixed"] = bench_batch32(torch, sgm, ctx, synthetic)
-    if args.extras in ("large", "batch", "all"):
-        log("batch of 8 1920x1080 D=256")
-        extras["batch8_1920x1080_d256"] = bench_large(torch, sgm, ctx, synthetic)
     if args.extras in ("serve", "all"):
         log("request loop, 4 cameras,", args.serve_seconds, "s per mode")
         extras["served"] = bench_serve(torch, sgm, synthetic, serve_ctx, args.serve_seconds)
@@ -587,10 +601,7 @@ def main():
     cpu = None
     if not args.no_cpu:
         log("cpu baseline")
-        cpu = cpu_baseline(left, right, p, args.cpu_seconds)
-    # the aggregation kernel instance the schedule selects: K = 8 disparities
-    # per lane over 16 lanes (D = 128), K * 16 / h_lanes on the horizontal paths
-    traffic = measured_traffic("agg_kernel<8, %d, %d, 0, unsigned char" % (128 // h_lanes, h_lanes))
+        cpu = cpu_baseline(pairs[0][0], pairs[0][1], p)
 
     line = {
         "metric": "SGM Mdisp-evals/s (W\u00b7H\u00b7D\u00b7paths) + p99 frame latency, batched vs per-frame",
@@ -605,30 +616,35 @@ def main():
         "vs_baseline": None,
         "dtype": "u16",
         "data": "synthetic",
-        "config": {"workload": "1242x375 uint8 pair, D=128, Census 9x7, 8 paths, P1=10, P2=120, "
-                               "LR |dL-dR|<=1, 3x3 median, U/V maps (KITTI-shaped slanted planes)",
-                   "frames_per_step": 1, "streams": HEADLINE_STREAMS,
-                   "path": "sgm_submit (fused kernels), up to 8 frames in flight",
+        "config": {"workload": "batch of 8 uint8 stereo pairs 1920x1080, D=256, Census 9x7, 8 paths, "
+                               "P1=10, P2=120, LR |dL-dR|<=1 (invalid 65535), 3x3 median, U/V maps "
+                               "(30-50 slanted planes + thin poles)",
+                   "frames_per_step": 8, "streams": args.streams, "batches_in_flight": HEADLINE_DEPTH,
+                   "path": "sgm_submit of all 8 pairs per step",
                    "schedule": {"h_lanes": h_lanes, "autotune_ms": tune_ms}},
-        "fps": round(args.steps / dt, 1),
-        "frame_latency_ms": {"p50": float(np.percentile(lat_ms, 50)), "p99": float(np.percentile(lat_ms, 99))},
+        "fps": round(8 * args.steps / dt, 2),
+        "one_stream": {"mdisp_evals_per_s": round(evals * args.steps / dt1 / 1e6, 2),
+                       "ms_per_step": round(dt1 / args.steps * 1e3, 4), "outputs_equal": bool(same)},
+        "one_frame_per_submit": {"mdisp_evals_per_s": round(evals * args.steps / dts / 1e6, 2),
+                                 "ms_per_8_frames": round(dts / args.steps * 1e3, 4)},
+        "stage_avg_ms": per_stage(prof),
+        "stage_avg_ms_one_stream": per_stage(prof1),
         # the request loop's frame latency (arrival to result) at 4 cameras x
         # 30 fps: continuous batching vs one frame at a time, same trace
         "served_p99_ms": served_p99(extras),
-        "stage_avg_ms": {k: round(v, 5) for k, v in stage_avg_ms.items()},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                     "kernel": "agg_kernel<8, %d, %d, 0, unsigned char> (8 directions, uint8 costs, uint8 path costs)"
-                               % (128 // h_lanes, h_lanes),
-                     "alg_bytes_per_launch": ALG_BYTES_PER_EVAL * evals,
-                     "avg_launch_ms": round(agg_ms, 5), "launches": prof["aggregate"][1],
-                     "batches_profiled": n_batches},
-        "per_frame_stage_calls_mdisp_evals_per_s": round(stage_path, 2),
-        "one_stream_mdisp_evals_per_s": round(evals * args.steps / dt1 / 1e6, 2),
-        "one_stream_ms_per_step": round(dt1 / args.steps * 1e3, 4),
-        "headline_outputs_equal_one_stream": same_as_one_stream,
-        "profiled_loop_mdisp_evals_per_s": round(evals * args.steps / dtp / 1e6, 2),
-        "graph_mode_mdisp_evals_per_s": round(evals * args.steps / dtg / 1e6, 2),
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": traffic,
+                     "kernel": agg_kernel_name(h_lanes) + ", 8, false> (8 directions of 8 frames in one launch)",
+                     "alg_bytes_per_eval": AGG_BYTES_PER_EVAL,
+                     "alg_bytes_per_launch": alg, "evals_per_launch": evals,
+                     "avg_launch_ms": round(agg_avg, 5), "launches": agg_n,
+                     "timed_loop": "one stream (each launch alone on the GPU)",
+                     "avg_launch_ms_overlapped": round(agg_overlapped, 5),
+                     "traffic_frac": round(traffic / (agg_avg * 1e-3) / 1e9 / HBM_PEAK_GBS, 4) if traffic else None,
+                     "valu_issue": valu,
+                     "survey_bytes_per_eval": SURVEY_BYTES_PER_EVAL,
+                     "survey_bytes_ratio": SURVEY_BYTES_PER_EVAL / AGG_BYTES_PER_EVAL},
         "cpu_baseline": cpu,
         "extras": extras,
     }

@@ -1,11 +1,11 @@
 """Summaries of rocprofv3 CSV output for the profiles/ directory.
 
     python -m paper_1807_06271_amd.profiling stats  <kernel_stats.csv> <out.txt> "<command>" \
-        [<kernel_trace.csv> <kernel name part> <N dispatches> [<skip>]]
+        [<kernel_trace.csv> <kernel name part> <N dispatches> [<skip> [largest]]]
     python -m paper_1807_06271_amd.profiling traffic <fetch_counter_collection.csv> \
         <write_counter_collection.csv> <out.json> "<fetch command>" "<write command>" [median|max]
     python -m paper_1807_06271_amd.profiling counters <counter_collection.csv> <kernel_trace.csv> \
-        <out.txt> "<command>"
+        <out.txt> "<command>" [largest]
 
 `stats` keeps the per-kernel call count and average / min / max durations.
 `counters` keeps the median per dispatch of each SQ counter of each kernel and
@@ -74,10 +74,12 @@ def short_name(name: str) -> str:
 
 
 def stats(csv_path: str, out_path: str, command: str, trace_csv: str | None = None,
-          kernel: str | None = None, first: int = 0, skip: int = 0) -> None:
+          kernel: str | None = None, first: int = 0, skip: int = 0, largest: bool = False) -> None:
     """Kernel statistics; with trace_csv/kernel/first, also the average of
-    dispatches skip .. skip+first-1 of `kernel` (the benchmark's serial loops,
-    after the autotuner's runs and before the overlapped-streams loop)."""
+    dispatches skip .. skip+first-1 of `kernel` (a loop of the benchmark in
+    which the kernel runs alone); with `largest`, counted among the
+    dispatches with the kernel's largest grid only (e.g. its 8-frame
+    launches, not the autotuner's single frames)."""
     rows = list(csv.DictReader(open(csv_path)))
     lines = ["# rocprofv3 kernel statistics", "# command: " + command, "#",
              "%-100s %6s %12s %12s %12s %7s" % ("kernel", "calls", "avg_us", "min_us", "max_us", "pct")]
@@ -86,10 +88,14 @@ def stats(csv_path: str, out_path: str, command: str, trace_csv: str | None = No
             short_name(r["Name"]), r["Calls"], float(r["AverageNs"]) / 1e3, float(r["MinNs"]) / 1e3,
             float(r["MaxNs"]) / 1e3, float(r["Percentage"])))
     if trace_csv and kernel and first:
-        d = [(int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3
-             for r in csv.DictReader(open(trace_csv)) if kernel in r["Kernel_Name"]][skip:skip + first]
-        lines += ["#", "# dispatches %d..%d of %s (serial loops): avg %.1f us, min %.1f, max %.1f"
-                  % (skip, skip + len(d) - 1, kernel, sum(d) / len(d), min(d), max(d))]
+        tr = [r for r in csv.DictReader(open(trace_csv)) if kernel in r["Kernel_Name"]]
+        grid = max(int(r["Grid_Size_X"]) for r in tr)
+        if largest:
+            tr = [r for r in tr if int(r["Grid_Size_X"]) == grid]
+        d = [(int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3 for r in tr][skip:skip + first]
+        lines += ["#", "# dispatches %d..%d%s of %s: avg %.1f us, min %.1f, max %.1f"
+                  % (skip, skip + len(d) - 1, " (grid %d only)" % grid if largest else "", kernel,
+                     sum(d) / len(d), min(d), max(d))]
     open(out_path, "w").write("\n".join(lines) + "\n")
 
 
@@ -149,17 +155,37 @@ def traffic(fetch_csv: str, write_csv: str, out_path: str, fetch_cmd: str, write
 CUS, CLOCK_HZ = 256, 2.4e9
 
 
-def counters(csv_path: str, trace_csv: str, out_path: str, command: str) -> None:
+def counters(csv_path: str, trace_csv: str, out_path: str, command: str, largest: bool = False) -> None:
+    """Median per dispatch of each counter of each kernel; with `largest`,
+    only the dispatches with the kernel's largest grid (e.g. the 8-frame
+    launches of a kernel that also ran single frames)."""
+    def grid_ok(name, grid, biggest):
+        return not largest or grid == biggest[name]
+
+    tr = list(csv.DictReader(open(trace_csv)))
+    big_tr = defaultdict(int)
+    for r in tr:
+        big_tr[short_name(r["Kernel_Name"])] = max(big_tr[short_name(r["Kernel_Name"])], int(r["Grid_Size_X"]))
     dur = defaultdict(list)
-    for r in csv.DictReader(open(trace_csv)):
-        dur[short_name(r["Kernel_Name"])].append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
+    for r in tr:
+        k = short_name(r["Kernel_Name"])
+        if grid_ok(k, int(r["Grid_Size_X"]), big_tr):
+            dur[k].append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
+    rows = list(csv.DictReader(open(csv_path)))
+    big = defaultdict(int)
+    for r in rows:
+        big[short_name(r["Kernel_Name"])] = max(big[short_name(r["Kernel_Name"])], int(r["Grid_Size"]))
     acc = defaultdict(lambda: defaultdict(list))
-    for r in csv.DictReader(open(csv_path)):
-        acc[short_name(r["Kernel_Name"])][r["Counter_Name"]].append(float(r["Counter_Value"]))
+    for r in rows:
+        k = short_name(r["Kernel_Name"])
+        if grid_ok(k, int(r["Grid_Size"]), big):
+            acc[k][r["Counter_Name"]].append(float(r["Counter_Value"]))
     lines = ["# rocprofv3 counters (median per dispatch) and VALU issue utilisation",
              "# command: " + command,
              "# VALU util = SQ_INSTS_VALU / (%d CUs x %.1f GHz x median duration of the same run's dispatches)"
-             % (CUS, CLOCK_HZ / 1e9), "#"]
+             % (CUS, CLOCK_HZ / 1e9),
+             "# dispatches: " + ("only each kernel's largest grid" if largest else "all"),
+             "# aggregation source hash %s" % source_hash(), "#"]
     for k in sorted(acc, key=lambda k: -max(acc[k].get("SQ_INSTS_VALU", [0]))):
         med = {c: sorted(v)[len(v) // 2] for c, v in acc[k].items()}
         util = ""
@@ -175,10 +201,12 @@ def counters(csv_path: str, trace_csv: str, out_path: str, command: str) -> None
 if __name__ == "__main__":
     if sys.argv[1] == "stats":
         extra = sys.argv[5:7] + [int(v) for v in sys.argv[7:9]] if len(sys.argv) > 7 else []
+        if len(sys.argv) > 9:
+            extra.append(sys.argv[9] == "largest")
         stats(sys.argv[2], sys.argv[3], sys.argv[4], *extra)
     elif sys.argv[1] == "traffic":
         traffic(sys.argv[2], sys.argv[3], sys.argv[4], sys.argv[5], sys.argv[6], *sys.argv[7:8])
     elif sys.argv[1] == "counters":
-        counters(sys.argv[2], sys.argv[3], sys.argv[4], sys.argv[5])
+        counters(sys.argv[2], sys.argv[3], sys.argv[4], sys.argv[5], len(sys.argv) > 6 and sys.argv[6] == "largest")
     else:
         raise SystemExit(__doc__)
