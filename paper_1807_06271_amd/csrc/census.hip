@@ -31,16 +31,7 @@ __global__ __launch_bounds__(256) void census_kernel(JobTable<CensusJob> t) {
   for (int ty = threadIdx.x >> 6; ty < kCTH; ty += 4) {
     const int y = y0 + ty;
     if (y >= J.H) break;
-    const uint8_t c = tile[(ty + ry) * tw + tx + rx];
-    uint64_t code = 0;
-    for (int dy = 0; dy < J.ch; ++dy) {
-      const uint8_t *row = tile + (ty + dy) * tw + tx;
-      for (int dx = 0; dx < J.cw; ++dx) {
-        if (dy == ry && dx == rx) continue;
-        code = (code << 1) | (uint64_t)(row[dx] < c);
-      }
-    }
-    J.out[(int64_t)y * J.W + x] = code;
+    J.out[(int64_t)y * J.ostride + x] = census_at(tile + ty * tw, tw, tx, J.cw, J.ch);
   }
 }
 

@@ -77,49 +77,6 @@ constexpr int kCodeRSlots = (kRightMax - 1) + (kRightMax - 1) / 4 + 1;
 
 __device__ __forceinline__ int swz(int i) { return i + (i >> 2); }
 
-template <int CW, int CH>
-__device__ __forceinline__ uint64_t census_fixed(const uint8_t *rows, int stride, int x) {
-  constexpr int RX = CW / 2, RY = CH / 2, NB = CW * CH - 1;
-  const uint32_t c = rows[RY * stride + x + RX];
-  // neighbour n (raster order, centre skipped) goes to bit NB - 1 - n, so
-  // the bits enter MSB first: the first NB - 32 neighbours shift into the high
-  // half, the last 32 (or all, for NB <= 32) into the low half.  n - c is
-  // negative exactly when I(q) < I(p), and v_alignbit({half, n - c}, 31)
-  // shifts the half left by one and appends that sign bit: one subtract and
-  // one alignbit per neighbour.
-  uint32_t lo = 0, hi = 0;
-  int n = 0;
-#pragma unroll
-  for (int dy = 0; dy < CH; ++dy)
-#pragma unroll
-    for (int dx = 0; dx < CW; ++dx) {
-      if (dy == RY && dx == RX) continue;
-      const int bit = NB - 1 - n++;
-      const uint32_t diff = (uint32_t)rows[dy * stride + x + dx] - c;
-      if (bit >= 32) hi = __builtin_amdgcn_alignbit(hi, diff, 31);
-      else lo = __builtin_amdgcn_alignbit(lo, diff, 31);
-    }
-  return (uint64_t)hi << 32 | lo;
-}
-
-__device__ __forceinline__ uint64_t census_any(const uint8_t *rows, int stride, int x, int cw, int ch) {
-  const int rx = cw / 2, ry = ch / 2;
-  const uint8_t c = rows[ry * stride + x + rx];
-  uint64_t code = 0;
-  for (int dy = 0; dy < ch; ++dy)
-    for (int dx = 0; dx < cw; ++dx) {
-      if (dy == ry && dx == rx) continue;
-      code = (code << 1) | (uint64_t)(rows[dy * stride + x + dx] < c);
-    }
-  return code;
-}
-
-__device__ __forceinline__ uint64_t census_at(const uint8_t *rows, int stride, int x, int cw, int ch) {
-  if (cw == 9 && ch == 7) return census_fixed<9, 7>(rows, stride, x);
-  if (cw == 5 && ch == 5) return census_fixed<5, 5>(rows, stride, x);
-  return census_any(rows, stride, x, cw, ch);
-}
-
 __global__ __launch_bounds__(256) void census_cost_kernel(JobTable<FusedCostJob> t) {
   extern __shared__ uint64_t lds64[];
   const int ji = find_job(t.j, t.n, (int)blockIdx.x);
