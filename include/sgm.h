@@ -335,19 +335,8 @@ typedef struct {
    * the flag.  Pays off on batches of many frames; 0 (default) = the
    * per-direction kernels. */
   int32_t sweep;
-  /* Where the aggregation takes the matching costs of equation (1) from:
-   * SGM_COSTS_DEFAULT (0) = the library's default for the shape;
-   * SGM_COSTS_VOLUME (1) = a uint8 cost volume [H][W][D] that a fused
-   * Census + cost kernel writes and every path reads;
-   * SGM_COSTS_CENSUS (2) = the Hamming distances computed inside the
-   * aggregation from the two views' Census codes, with no cost volume.
-   * Only Census frames whose path costs fit 8 bits (N_b + p2 <= 255) and
-   * whose code buffers stay below 2 GiB (2 * H * (W + 256) * 8 bytes) can
-   * take SGM_COSTS_CENSUS; other frames use the volume. */
-  int32_t cost_source;
-  int32_t reserved; /* must be 0 */
+  int32_t reserved[2]; /* must be 0 */
 } sgm_schedule;
-enum { SGM_COSTS_DEFAULT = 0, SGM_COSTS_VOLUME = 1, SGM_COSTS_CENSUS = 2 };
 
 /* Set the schedule used by sgm_submit for frames of the shape of `shape`
  * (width, height, max_disp, path_mask and the path-cost width it implies);

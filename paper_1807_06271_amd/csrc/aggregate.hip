@@ -78,33 +78,18 @@ constexpr uint32_t kInfPair = 0xFFFFFFFFu;
 
 // Cost words of one pixel for one lane: K values of a padded volume (the
 // uint8 volume for SRC kCost8, four per word; the uint16 one for kCost16, two
-// per word), or for kCensus the K right-view Census codes the lane's
-// disparities compare with (2K words) followed by the pixel's left-view code.
-// Every lane reads its K cells (codes) with vector loads; cells with d >= D
-// hold unspecified values that the recurrence masks out.
-enum { kCost8 = kSrcCost8, kCost16 = kSrcCost16, kCensus = kSrcCensus };
+// per word).  Every lane reads its K cells with one vector load; cells with
+// d >= D hold unspecified values that the recurrence masks out.
+enum { kCost8 = 0, kCost16 = 1 };
 
 template <int K, int SRC>
 struct CostWords {
-  static constexpr int N = SRC == kCost8 ? (K + 3) / 4 : SRC == kCost16 ? K / 2 : 2 * K + 2;
+  static constexpr int N = SRC == kCost8 ? (K + 3) / 4 : K / 2;
   uint32_t w[N];
 };
 
-// p: the lane's cells of the pixel; for kCensus, the first of the K
-// consecutive right-view codes x - dbase - K + 1 .. x - dbase, and the
-// left-view code of x at p + ldelta.
 template <int K, int SRC>
-__device__ __forceinline__ void load_cost(CostWords<K, SRC> &cw, const char *p, int32_t ldelta) {
-  if constexpr (SRC == kCensus) {
-    const U32N<2 * K> v = *reinterpret_cast<const U32N<2 * K> *>(p);
-#pragma unroll
-    for (int i = 0; i < 2 * K; ++i) cw.w[i] = v.v[i];
-    const U32N<2> l = *reinterpret_cast<const U32N<2> *>(p + ldelta);
-    cw.w[2 * K] = l.v[0];
-    cw.w[2 * K + 1] = l.v[1];
-    return;
-  }
-  (void)ldelta;
+__device__ __forceinline__ void load_cost(CostWords<K, SRC> &cw, const char *p) {
   if (SRC == kCost8 && K % 4 != 0) {  // K = 2 or 6: 2-byte aligned, one 16-bit load per pair
     const uint16_t *q = reinterpret_cast<const uint16_t *>(p);
 #pragma unroll
@@ -121,31 +106,9 @@ __device__ __forceinline__ void load_cost(CostWords<K, SRC> &cw, const char *p, 
   }
 }
 
-// Hamming distance (equation (1), section 3.1.2) of the left-view code and
-// the right-view code at run position m (disparity dbase + K - 1 - m).
-template <int K>
-__device__ __forceinline__ uint32_t census_cost(const CostWords<K, kCensus> &cw, int m) {
-  return (uint32_t)__builtin_popcount(cw.w[2 * m] ^ cw.w[2 * K]) +
-         (uint32_t)__builtin_popcount(cw.w[2 * m + 1] ^ cw.w[2 * K + 1]);
-}
-
-// Costs of disparities (2i, 2i+1) as a packed pair.  For kCensus, r is the
-// pixel's x - dbase: disparity dbase + k has its right-view pixel in the
-// image iff k <= r, else its cost is N_b (edge = false: every k is inside).
+// Costs of disparities (2i, 2i+1) as a packed pair.
 template <int K, int SRC>
-__device__ __forceinline__ u16x2 cost_pair(const CostWords<K, SRC> &cw, int i, bool edge = false, int r = 0,
-                                           uint32_t nbits = 0) {
-  if constexpr (SRC == kCensus) {
-    uint32_t c0 = census_cost<K>(cw, K - 1 - 2 * i), c1 = census_cost<K>(cw, K - 2 - 2 * i);
-    if (edge) {
-      c0 = 2 * i <= r ? c0 : nbits;
-      c1 = 2 * i + 1 <= r ? c1 : nbits;
-    }
-    return as_pair(c0 | c1 << 16);
-  }
-  (void)edge;
-  (void)r;
-  (void)nbits;
+__device__ __forceinline__ u16x2 cost_pair(const CostWords<K, SRC> &cw, int i) {
   if (SRC == kCost8) {
     // bytes 2i and 2i+1 of the lane's K bytes, zero-extended into 16-bit halves
     const uint32_t sel = (i & 1) ? 0x0c030c02u : 0x0c010c00u;
@@ -217,22 +180,8 @@ __device__ __forceinline__ void agg_wave(const AggJob &J, int slot, int wave_in_
   const int cpp = Dp;                        // cost elements per pixel (padded)
   const char *cbase = SRC == kCost8 ? reinterpret_cast<const char *>(J.cost8)
                                     : reinterpret_cast<const char *>(J.cost16);
-  uint32_t coff = (uint32_t)((pix0 * cpp + dbase) * CB);
-  int64_t cstep = HS ? (int64_t)HS * K * LPS * CB : step * cpp * CB;  // Dp = K * LPS
-  int32_t ldelta = 0;
-  if constexpr (SRC == kCensus) {
-    // the lane's run of K right-view codes starts at x - dbase - K + 1 (the
-    // codes left of a row are readable padding), the left-view code of x
-    // lies ldelta bytes further on
-    const int64_t cs = J.cstride;
-    // offsets from the padding before row 0 (Dp codes), so they stay >= 0
-    cbase = reinterpret_cast<const char *>(J.cr - Dp);
-    coff = (uint32_t)((sy * cs + sx + Dp - dbase - K + 1) * 8);
-    cstep = HS ? (int64_t)HS * 8 : ((int64_t)kDirDy[dir] * cs + kDirDx[dir]) * 8;
-    ldelta = J.cl_delta + (dbase + K - 1) * 8;
-  }
-  const int dxs = HS ? HS : kDirDx[dir];  // column step per pixel
-  const uint32_t nbits = (uint32_t)J.nbits;
+  const uint32_t coff = (uint32_t)((pix0 * cpp + dbase) * CB);
+  const int64_t cstep = HS ? (int64_t)HS * K * LPS * CB : step * cpp * CB;  // Dp = K * LPS
   char *obase = reinterpret_cast<char *>(J.lr) + (int64_t)slot * H * W * Dp * (int64_t)sizeof(LT);
   const uint32_t ooff = (uint32_t)((pix0 * Dp + dbase) * (int64_t)sizeof(LT));
   const int64_t ostep = HS ? (int64_t)HS * K * LPS * (int64_t)sizeof(LT) : step * Dp * (int64_t)sizeof(LT);
@@ -244,7 +193,7 @@ __device__ __forceinline__ void agg_wave(const AggJob &J, int slot, int wave_in_
   CostWords<K, SRC> ring[PF];
 #pragma unroll
   for (int s = 0; s < PF; ++s) {  // in ring order, which the waits in the loop assume
-    load_cost<K, SRC>(ring[s], cbase + min(s, last) * cstep + coff, ldelta);
+    load_cost<K, SRC>(ring[s], cbase + min(s, last) * cstep + coff);
     __builtin_amdgcn_sched_barrier(0);
   }
 
@@ -261,16 +210,6 @@ __device__ __forceinline__ void agg_wave(const AggJob &J, int slot, int wave_in_
     // keep each pixel's instructions together: hoisting the unpacking of
     // later pixels' costs would wait on loads issued one pixel ago
     __builtin_amdgcn_sched_barrier(0);
-    // Census costs: disparities whose right-view pixel lies left of the
-    // image cost N_b; the wave takes the checked path only while one of its
-    // scanlines is that close to the left border
-    bool edge = false;
-    int r = 0;
-    if constexpr (SRC == kCensus) {
-      r = sx + (GUARD ? min(i, last) : i) * dxs - dbase;
-      const bool ok = (GUARD && i >= len) || dvalid == 0 || r >= dvalid - 1;
-      edge = __builtin_amdgcn_ballot_w64(!ok) != 0;
-    }
     u16x2 Lc[NP];
     if constexpr (NP == 1 && LPS >= 32) {
       // One pair per lane (the wide horizontal layouts, whose scanlines are
@@ -293,7 +232,7 @@ __device__ __forceinline__ void agg_wave(const AggJob &J, int slot, int wave_in_
       __builtin_amdgcn_sched_barrier(0);
       m = min(m, (uint32_t)__builtin_amdgcn_mov_dpp((int)m, kDppRowRor4, 0xF, 0xF, true));
       const u16x2 nb1 = as_pair(__builtin_amdgcn_alignbit(next, l0, 16));
-      const u16x2 c0 = cost_pair<K, SRC>(rs, 0, edge, r, nbits);
+      const u16x2 c0 = cost_pair<K, SRC>(rs, 0);
       __builtin_amdgcn_sched_barrier(0);
       m = min(m, (uint32_t)__builtin_amdgcn_mov_dpp((int)m, kDppRowRor2, 0xF, 0xF, true));
       u16x2 a = pmin(nb0, nb1);
@@ -355,13 +294,13 @@ __device__ __forceinline__ void agg_wave(const AggJob &J, int slot, int wave_in_
       const u16x2 MP2 = padd_sat(M, P2);
 #pragma unroll
       for (int q = 0; q < NP; ++q) {
-        u16x2 v = pmin(A[q], MP2) - M + cost_pair<K, SRC>(rs, q, edge, r, nbits);
+        u16x2 v = pmin(A[q], MP2) - M + cost_pair<K, SRC>(rs, q);
         if (PAD) v = as_pair(as_u32(v) | padmask[q]);
         Lc[q] = v;
       }
     }
     // the slot's costs are used: refill it PF pixels ahead
-    load_cost<K, SRC>(rs, cbase + (int64_t)(GUARD ? min(i + PF, last) : i + PF) * cstep + coff, ldelta);
+    load_cost<K, SRC>(rs, cbase + (int64_t)(GUARD ? min(i + PF, last) : i + PF) * cstep + coff);
     if (!GUARD || i < len) {
       char *o = obase + (int64_t)i * ostep + ooff;
       if (sizeof(LT) == 1) {
@@ -408,10 +347,6 @@ __device__ __forceinline__ void agg_wave(const AggJob &J, int slot, int wave_in_
 // directions use `hlps` lanes per scanline (all others use 16).
 __host__ __device__ inline int lanes_per_scanline(int dir, int hlps) { return dir < 2 ? hlps : 16; }
 
-// Pixels of Census codes in flight per lane: 2 to 8 ring slots of 2K + 2
-// words (at most ~70 registers).
-constexpr int census_pf(int K) { return K >= 12 ? 2 : K >= 6 ? 4 : 8; }
-
 // Each wave finds its job and direction slot, then runs that direction's
 // scanlines with the lane layout of the schedule: KH disparities per lane
 // over HLPS lanes for horizontal paths, K over 16 lanes for the others.
@@ -427,17 +362,14 @@ __global__ __launch_bounds__(256) void agg_kernel(JobTable<AggJob> t) {
     if (w >= J.line0[k]) slot = k;
   const int wave_in_slot = w - J.line0[slot];
   // Wider lane groups finish a pixel in fewer instructions, so they prefetch
-  // proportionally further ahead to cover the same memory latency; a Census
-  // ring slot holds 2K + 2 words, which bounds its depth.
-  constexpr int PFH = SRC == kCensus ? census_pf(KH) : PF * HLPS / 16;
-  constexpr int PFV = SRC == kCensus ? census_pf(K) : PF;
+  // proportionally further ahead to cover the same memory latency.
   const int dir = J.dirs[slot];
   if (dir == 0)
-    agg_wave<KH, HLPS, SRC, LT, PFH, PAD, +1>(J, slot, wave_in_slot);
+    agg_wave<KH, HLPS, SRC, LT, PF * HLPS / 16, PAD, +1>(J, slot, wave_in_slot);
   else if (dir == 1)
-    agg_wave<KH, HLPS, SRC, LT, PFH, PAD, -1>(J, slot, wave_in_slot);
+    agg_wave<KH, HLPS, SRC, LT, PF * HLPS / 16, PAD, -1>(J, slot, wave_in_slot);
   else
-    agg_wave<K, 16, SRC, LT, PFV, PAD, 0>(J, slot, wave_in_slot);
+    agg_wave<K, 16, SRC, LT, PF, PAD, 0>(J, slot, wave_in_slot);
 }
 
 template <int K, int KH, int HLPS, int SRC, typename LT>
@@ -474,7 +406,8 @@ static void launch_k(int K, int hlps, const JobTable<AggJob> &t, int waves, hipS
   }
 }
 
-void launch_aggregate(std::vector<AggJob> jobs, int src, int K, int hlps, int lr_bytes, hipStream_t s) {
+void launch_aggregate(std::vector<AggJob> jobs, bool from_cost16, int K, int hlps, int lr_bytes,
+                      hipStream_t s) {
   if (!agg_hlps_ok(K, hlps)) hlps = 16;
   for (auto &j : jobs) {
     int total = 0;
@@ -488,9 +421,7 @@ void launch_aggregate(std::vector<AggJob> jobs, int src, int K, int hlps, int lr
   for_each_table(
       jobs, [](const AggJob &j) { return (long)j.line0[j.ndirs]; },
       [&](const JobTable<AggJob> &t, int waves) {
-        if (src == kSrcCensus) {  // uint8 path costs only (the caller checks N_b + P2 <= 255)
-          launch_k<kCensus, uint8_t>(K, hlps, t, waves, s);
-        } else if (src == kSrcCost8) {
+        if (!from_cost16) {
           if (lr_bytes == 1) launch_k<kCost8, uint8_t>(K, hlps, t, waves, s);
           else launch_k<kCost8, uint16_t>(K, hlps, t, waves, s);
         } else {

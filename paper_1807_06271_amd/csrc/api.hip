@@ -40,9 +40,6 @@ int fail(int code, const char *fmt, ...) {
 
 int popcount8(uint32_t m) { return __builtin_popcount(m & 0xFFu); }
 
-// Cost source of shapes without a tuned or context schedule.
-constexpr int kDefaultCosts = SGM_COSTS_VOLUME;
-
 int validate(const sgm_params *p) {
   if (!p) return fail(SGM_EINVAL, "params is null");
   if (p->width < 1 || p->height < 1 || p->width > 16384 || p->height > 16384)
@@ -280,11 +277,7 @@ struct FramePlan {
 
 // Scratch of one frame of a batch: the padded uint8 cost volume, the P
 // padded path-cost volumes and the LR-checked map before the median.
-// Bytes of one view's Census codes laid out for the aggregation's code
-// source: rows of Dp readable padding codes followed by the W codes.
-size_t code_view_bytes(const sgm_params &p) { return (size_t)p.height * (p.width + dp_of(p)) * 8; }
-
-FramePlan plan_frame(const sgm_params &p, size_t base, bool sweep, bool census_codes) {
+FramePlan plan_frame(const sgm_params &p, size_t base, bool sweep) {
   const size_t px = (size_t)p.width * p.height;
   const size_t dp = (size_t)dp_of(p);
   FramePlan f;
@@ -298,11 +291,8 @@ FramePlan plan_frame(const sgm_params &p, size_t base, bool sweep, bool census_c
     f.bytes = f.off_dlr + align256(px * 2) - base;
     return f;
   }
-  // Census costs: padded uint8 [H][W][Dp], or the Census codes of both views
-  // (right view first) when the aggregation computes the costs; SAD costs:
-  // padded uint16 [H][W][Dp]
-  const size_t cost_bytes = census_codes ? 2 * code_view_bytes(p) : is_sad(p) ? px * dp * 2 : px * dp;
-  f.off_lr = f.off_cost + align256(cost_bytes);
+  // Census costs: padded uint8 [H][W][Dp]; SAD costs: padded uint16 [H][W][Dp]
+  f.off_lr = f.off_cost + align256(is_sad(p) ? px * dp * 2 : px * dp);
   f.off_dlr = f.off_lr + align256(px * dp * (size_t)popcount8(p.path_mask) * lr_bytes_of(p));
   // D_L and the row segments' right-view keys (left-right check)
   f.off_dl = f.off_dlr + align256(px * 2);
@@ -349,22 +339,6 @@ int resolve_sweep(const sgm_ctx *c, const sgm_params &p) {
   return want && sweep_ok(p) ? 1 : 0;
 }
 
-// Frames whose costs the aggregation can compute from Census codes: Census
-// cost, uint8 path costs, and code buffers whose byte offsets fit 31 bits.
-bool census_codes_ok(const sgm_params &p) {
-  return !is_sad(p) && lr_bytes_of(p) == 1 && 2 * code_view_bytes(p) < ((size_t)1 << 31);
-}
-
-// Cost source of a frame (SGM_COSTS_VOLUME or SGM_COSTS_CENSUS): the tuned
-// entry for its shape, else the context default, else the library's default.
-int resolve_costs(const sgm_ctx *c, const sgm_params &p) {
-  auto it = c->tuned.find(shape_key(p));
-  int want = it != c->tuned.end() ? it->second.cost_source : 0;
-  if (want == SGM_COSTS_DEFAULT) want = c->dflt.cost_source;
-  if (want == SGM_COSTS_DEFAULT) want = kDefaultCosts;
-  return want == SGM_COSTS_CENSUS && census_codes_ok(p) ? SGM_COSTS_CENSUS : SGM_COSTS_VOLUME;
-}
-
 // Check one sgm_remap (sizes, pitches, device pointers) and build its job.
 int check_remap(const sgm_remap &r, int i, int dev, RemapJob *out) {
   if (r.w < 1 || r.h < 1 || r.w > 16384 || r.h > 16384)
@@ -399,8 +373,7 @@ int check_remap(const sgm_remap &r, int i, int dev, RemapJob *out) {
 // Everything that decides a batch's launch sequence (kernels, grids, LDS):
 // the frames' parameters and schedules, in order.
 std::string composition_key(const sgm_frame *fr, int n, const std::vector<int> &hlps,
-                            const std::vector<int> &sweep, const std::vector<int> &costs,
-                            const std::vector<RemapJob> &rect) {
+                            const std::vector<int> &sweep, const std::vector<RemapJob> &rect) {
   std::string k;
   char buf[160];
   for (const RemapJob &r : rect) {
@@ -413,8 +386,7 @@ std::string composition_key(const sgm_frame *fr, int n, const std::vector<int> &
     // argument layouts
     snprintf(buf, sizeof buf, "%d,%d,%d,%d,%d,%u,%u,%u,%d,%d,%d,%u,%u,%d,%d,%d;", p.width, p.height,
              p.max_disp, p.census_w, p.census_h, p.path_mask, p.p1, p.p2, p.lr_check, p.lr_max_diff,
-             p.median, p.invalid, p.cost, lr_bytes_of(p), hlps[i] | sweep[i] << 8 | costs[i] << 9,
-             fr[i].umap ? 1 : 0);
+             p.median, p.invalid, p.cost, lr_bytes_of(p), hlps[i] | sweep[i] << 8, fr[i].umap ? 1 : 0);
     k += buf;
   }
   return k;
@@ -425,9 +397,7 @@ int check_schedule(const sgm_schedule *s) {
   if (s->h_lanes != 0 && s->h_lanes != 16 && s->h_lanes != 32 && s->h_lanes != 64)
     return fail(SGM_EINVAL, "h_lanes must be 0, 16, 32 or 64 (got %d)", s->h_lanes);
   if (s->sweep != 0 && s->sweep != 1) return fail(SGM_EINVAL, "sweep must be 0 or 1 (got %d)", s->sweep);
-  if (s->cost_source < SGM_COSTS_DEFAULT || s->cost_source > SGM_COSTS_CENSUS)
-    return fail(SGM_EINVAL, "cost_source must be 0, 1 or 2 (got %d)", s->cost_source);
-  if (s->reserved) return fail(SGM_EINVAL, "reserved must be 0");
+  if (s->reserved[0] || s->reserved[1]) return fail(SGM_EINVAL, "reserved must be 0");
   return SGM_OK;
 }
 
@@ -455,8 +425,8 @@ struct StageMark {
 
 int enqueue_frames(const sgm_frame *fr, int n, const std::vector<FramePlan> &plans,
                    const std::vector<int> &hlps, const std::vector<int> &sweep,
-                   const std::vector<int> &costs, const std::vector<RemapJob> &rect, char *mem,
-                   hipStream_t s, std::vector<StageEvents> *prof) {
+                   const std::vector<RemapJob> &rect, char *mem, hipStream_t s,
+                   std::vector<StageEvents> *prof) {
   StageMark mark{prof, s};
   // rectification of the raw views into the frames' input buffers (one
   // launch for every view of the batch)
@@ -485,23 +455,6 @@ int enqueue_frames(const sgm_frame *fr, int n, const std::vector<FramePlan> &pla
         j.cw = p.census_w;
         j.ch = p.census_h;
         j.ostride = p.width;
-        cj.push_back(j);
-      }
-      continue;
-    }
-    if (costs[i] == SGM_COSTS_CENSUS) {
-      // codes of both views, right view first, rows padded on the left
-      const size_t vb = code_view_bytes(p);
-      for (int v = 0; v < 2; ++v) {
-        CensusJob j{};
-        j.img = v ? fr[i].left : fr[i].right;
-        j.pitch = fr[i].pitch;
-        j.out = reinterpret_cast<uint64_t *>(mem + plans[i].off_cost + v * vb) + dp_of(p);
-        j.W = p.width;
-        j.H = p.height;
-        j.cw = p.census_w;
-        j.ch = p.census_h;
-        j.ostride = p.width + dp_of(p);
         cj.push_back(j);
       }
       continue;
@@ -556,28 +509,18 @@ int enqueue_frames(const sgm_frame *fr, int n, const std::vector<FramePlan> &pla
   // aggregation, one launch per (disparities per lane, path-cost width)
   CHECK(mark.begin(SGM_STAGE_AGGREGATE));
   int groups = 0;
-  for (int src : {kSrcCost8, kSrcCost16, kSrcCensus})
+  for (int sad = 0; sad <= 1; ++sad)
   for (int K : {4, 8, 12, 16})
     for (int lb = 1; lb <= 2; ++lb)
     for (int c_hlps : {16, 32, 64}) {
       std::vector<AggJob> aj;
       for (int i = 0; i < n; ++i) {
         const sgm_params &p = fr[i].p;
-        const int fsrc = is_sad(p) ? kSrcCost16 : costs[i] == SGM_COSTS_CENSUS ? kSrcCensus : kSrcCost8;
-        if (sweep[i] || fsrc != src || k_of(p) != K || lr_bytes_of(p) != lb) continue;
+        if (sweep[i] || (int)is_sad(p) != sad || k_of(p) != K || lr_bytes_of(p) != lb) continue;
         if (hlps[i] != c_hlps) continue;
         AggJob j{};
-        if (src == kSrcCost16) {
-          j.cost16 = reinterpret_cast<const uint16_t *>(mem + plans[i].off_cost);
-        } else if (src == kSrcCensus) {
-          const size_t vb = code_view_bytes(p);
-          j.cr = reinterpret_cast<const uint64_t *>(mem + plans[i].off_cost) + dp_of(p);
-          j.cl_delta = (int32_t)vb;
-          j.cstride = p.width + dp_of(p);
-          j.nbits = nbits_of(p);
-        } else {
-          j.cost8 = reinterpret_cast<const uint8_t *>(mem + plans[i].off_cost);
-        }
+        if (sad) j.cost16 = reinterpret_cast<const uint16_t *>(mem + plans[i].off_cost);
+        else j.cost8 = reinterpret_cast<const uint8_t *>(mem + plans[i].off_cost);
         j.lr = mem + plans[i].off_lr;
         j.W = p.width;
         j.H = p.height;
@@ -589,7 +532,7 @@ int enqueue_frames(const sgm_frame *fr, int n, const std::vector<FramePlan> &pla
         aj.push_back(j);
       }
       if (!aj.empty()) {
-        launch_aggregate(aj, src, K, c_hlps, lb, s);
+        launch_aggregate(aj, sad != 0, K, c_hlps, lb, s);
         CHECK(check_launch());
         ++groups;
       }
@@ -780,10 +723,10 @@ void destroy_events(Batch &b) {
 // the cached executable graph of the same composition (updated with this
 // batch's buffers), instantiating one on a miss.
 int enqueue_graph(sgm_ctx *c, const sgm_frame *fr, int n, const std::vector<FramePlan> &plans,
-                  const std::vector<int> &hlps, const std::vector<int> &sweep, const std::vector<int> &costs,
+                  const std::vector<int> &hlps, const std::vector<int> &sweep,
                   const std::vector<RemapJob> &rect, char *mem, hipStream_t s) {
   HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed));
-  int rc = enqueue_frames(fr, n, plans, hlps, sweep, costs, rect, mem, s, nullptr);
+  int rc = enqueue_frames(fr, n, plans, hlps, sweep, rect, mem, s, nullptr);
   hipGraph_t g = nullptr;
   hipError_t e = hipStreamEndCapture(s, &g);
   if (rc != SGM_OK) {
@@ -791,7 +734,7 @@ int enqueue_graph(sgm_ctx *c, const sgm_frame *fr, int n, const std::vector<Fram
     return rc;
   }
   if (e != hipSuccess) return fail(SGM_EHIP, "graph capture: %s", hipGetErrorString(e));
-  const std::string key = composition_key(fr, n, hlps, sweep, costs, rect);
+  const std::string key = composition_key(fr, n, hlps, sweep, rect);
   auto it = c->graph_cache.find(key);
   hipGraphExec_t ex = nullptr;
   if (it != c->graph_cache.end()) {
@@ -995,7 +938,7 @@ int sgm_aggregate(sgm_ctx *c, const sgm_params *p, const uint16_t *cost, uint16_
   j.p1 = p->p1;
   j.p2 = p->p2;
   j.ndirs = fill_dirs(p->path_mask, j.dirs);
-  launch_aggregate({j}, kSrcCost16, k_of(*p), resolve_hlps(c, *p), lb, s);
+  launch_aggregate({j}, true, k_of(*p), resolve_hlps(c, *p), lb, s);
   CHECK(check_launch());
   SumJob sj{};
   sj.lr = lr;
@@ -1139,14 +1082,13 @@ static int submit_impl(sgm_ctx *c, const sgm_frame *frames, const sgm_remap *rem
       return fail(SGM_EINVAL, "frame %d: give both umap and vmap, or neither", i);
   }
   std::lock_guard<std::mutex> lk(c->mu);
-  std::vector<int> hl(n), sw(n), cs(n);
+  std::vector<int> hl(n), sw(n);
   std::vector<FramePlan> plans(n);
   size_t total = 0;
   for (int i = 0; i < n; ++i) {
     hl[i] = resolve_hlps(c, frames[i].p);
     sw[i] = resolve_sweep(c, frames[i].p);
-    cs[i] = resolve_costs(c, frames[i].p);
-    plans[i] = plan_frame(frames[i].p, total, sw[i] != 0, cs[i] == SGM_COSTS_CENSUS);
+    plans[i] = plan_frame(frames[i].p, total, sw[i] != 0);
     total += plans[i].bytes;
   }
   DeviceGuard g(c->device);
@@ -1208,9 +1150,9 @@ static int submit_impl(sgm_ctx *c, const sgm_frame *frames, const sgm_remap *rem
     return rc;
   }
   if (c->graphs && !c->profiling) {
-    rc = enqueue_graph(c, frames, n, plans, hl, sw, cs, rect, reinterpret_cast<char *>(blk.ptr), s);
+    rc = enqueue_graph(c, frames, n, plans, hl, sw, rect, reinterpret_cast<char *>(blk.ptr), s);
   } else {
-    rc = enqueue_frames(frames, n, plans, hl, sw, cs, rect, reinterpret_cast<char *>(blk.ptr), s,
+    rc = enqueue_frames(frames, n, plans, hl, sw, rect, reinterpret_cast<char *>(blk.ptr), s,
                         c->profiling ? &b.prof : nullptr);
   }
   if (rc == SGM_OK && hipEventCreateWithFlags(&b.done, hipEventDisableTiming) != hipSuccess)
@@ -1348,7 +1290,6 @@ int sgm_get_schedule(sgm_ctx *c, const sgm_params *shape, sgm_schedule *sc) {
   *sc = sgm_schedule{};
   sc->h_lanes = resolve_hlps(c, *shape);
   sc->sweep = resolve_sweep(c, *shape);
-  sc->cost_source = resolve_costs(c, *shape);
   return SGM_OK;
 }
 

@@ -74,12 +74,7 @@ __host__ __device__ int agg_lines(int dir, int W, int H);
 
 struct AggJob {
   const uint8_t *cost8;          // internal padded uint8 costs [H][W][Dp], or
-  const uint16_t *cost16;        // internal padded uint16 costs [H][W][Dp], or
-  const uint64_t *cr;            // Census codes of the right view: the code of
-                                 // (x, y) at cr[y * cstride + x], with Dp - 1
-                                 // readable (unused) codes left of every row
-  int32_t cl_delta;              // byte offset of the left view's codes from cr
-  int cstride, nbits;            // codes per row (>= W + Dp); N_b
+  const uint16_t *cost16;        // internal padded uint16 costs [H][W][Dp]
   void *lr;                      // path costs [P][H][W][Dp], uint8 or uint16
   int W, H, D, Dp, p1, p2;
   int ndirs;                     // P = number of active directions
@@ -87,13 +82,10 @@ struct AggJob {
   int line0[9];                  // first wave of each slot; line0[P] = waves of the job
   int blk0;                      // first global wave of this job
 };
-// Source of the matching costs: a padded uint8 or uint16 cost volume, or the
-// Hamming distances of the Census codes computed inside the aggregation.
-enum { kSrcCost8 = 0, kSrcCost16 = 1, kSrcCensus = 2 };
 // K = agg_k(D) of every job; hlps: lanes per horizontal scanline (16, 32 or
-// 64; falls back to 16 where the layout does not fit K); lr_bytes: 1 or 2
-// (kSrcCensus: 1 only).
-void launch_aggregate(std::vector<AggJob> jobs, int src, int K, int hlps, int lr_bytes, hipStream_t s);
+// 64; falls back to 16 where the layout does not fit K); lr_bytes: 1 or 2.
+void launch_aggregate(std::vector<AggJob> jobs, bool from_cost16, int K, int hlps, int lr_bytes,
+                      hipStream_t s);
 bool agg_hlps_ok(int K, int hlps);
 // Copy uint16 costs [px][D] into the padded layout [px][Dp] (pad cells 0).
 void launch_pad16(const uint16_t *src, uint16_t *dst, int64_t px, int D, int Dp, hipStream_t s);

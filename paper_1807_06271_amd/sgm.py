@@ -31,7 +31,6 @@ PATHS_PAPER4 = PATH_L2R | PATH_TL2BR | PATH_T2B | PATH_TR2BL
 PATHS_HV4 = PATH_L2R | PATH_R2L | PATH_T2B | PATH_B2T
 PATHS_ALL8 = 0xFF
 COST_CENSUS, COST_SAD = 0, 1
-COSTS_DEFAULT, COSTS_VOLUME, COSTS_CENSUS = 0, 1, 2
 
 EXPORTS = ["sgm_validate", "sgm_create", "sgm_destroy", "sgm_last_error", "sgm_census", "sgm_cost",
            "sgm_cost_sad",
@@ -60,8 +59,7 @@ class sgm_params(ctypes.Structure):
 
 
 class sgm_schedule(ctypes.Structure):
-    _fields_ = [("h_lanes", ctypes.c_int32), ("sweep", ctypes.c_int32), ("cost_source", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+    _fields_ = [("h_lanes", ctypes.c_int32), ("sweep", ctypes.c_int32), ("reserved", ctypes.c_int32 * 2)]
 
 
 class sgm_remap(ctypes.Structure):
@@ -459,12 +457,11 @@ def sgm_memory(ctx: Context):
     return a.value, b.value
 
 
-def sgm_set_schedule(ctx: Context, p: Params | None, h_lanes: int, sweep: bool = False,
-                     cost_source: int = COSTS_DEFAULT) -> None:
+def sgm_set_schedule(ctx: Context, p: Params | None, h_lanes: int, sweep: bool = False) -> None:
     """Schedule for frames of p's shape (p=None: the default): lanes per
-    horizontal scanline, whether eligible frames use the single-pass sweep,
-    and where the aggregation takes its costs from (COSTS_*)."""
-    sc = sgm_schedule(h_lanes, int(bool(sweep)), int(cost_source))
+    horizontal scanline, and whether eligible frames use the single-pass
+    sweep."""
+    sc = sgm_schedule(h_lanes, int(bool(sweep)))
     _check(lib().sgm_set_schedule(ctx.handle, ctypes.byref(p.c()) if p is not None else None,
                                   ctypes.byref(sc)), "sgm_set_schedule")
 
@@ -475,11 +472,10 @@ def sgm_get_schedule(ctx: Context, p: Params) -> int:
 
 
 def schedule_of(ctx: Context, p: Params):
-    """(h_lanes, sweep, cost_source) that sgm_submit would use for frames
-    like p."""
+    """(h_lanes, sweep) that sgm_submit would use for frames like p."""
     sc = sgm_schedule()
     _check(lib().sgm_get_schedule(ctx.handle, ctypes.byref(p.c()), ctypes.byref(sc)), "sgm_get_schedule")
-    return sc.h_lanes, bool(sc.sweep), sc.cost_source
+    return sc.h_lanes, bool(sc.sweep)
 
 
 def sgm_autotune(ctx: Context, sample: "Frame", reps: int = 5):

@@ -10,9 +10,7 @@ workloads (GPU required), in the launch configurations the benchmark uses:
 
 Every frame's disparity map, U-map and V-map must equal the oracle's bit for
 bit (sections 3.1.2 to 3.2).  The oracle needs ~13 s per 1920x1080 D=256
-frame on 16 host threads, so the first test runs for about two minutes.  The
-batches run with each cost source (cost volume, Census codes in the
-aggregation) against the same oracle maps.
+frame on 16 host threads, so the first test runs for about two minutes.
 """
 import numpy as np
 import pytest
@@ -62,26 +60,14 @@ def test_eight_1920x1080_d256_pairs_in_one_submit_match_oracle(env):
         p = full_path_params(sgm, 1920, 1080, 256)
         frames.append(sgm.Frame.alloc(p, to_dev(torch, left), to_dev(torch, right)))
         inputs.append((p, left, right))
-    # the batch with each cost source (a cost volume; Hamming costs computed
-    # inside the aggregation from the Census codes)
-    p = inputs[0][0]
-    runs = []
-    for src in (sgm.COSTS_VOLUME, sgm.COSTS_CENSUS):
-        sgm.sgm_set_schedule(ctx, p, 0, cost_source=src)
-        assert sgm.schedule_of(ctx, p)[2] == src
-        fr = [sgm.Frame.alloc(q, f.left, f.right) for (q, _, _), f in zip(inputs, frames)]
-        announce("8 x 1920x1080 D=256 in one submit, cost source", src)
-        sgm.sgm_wait(ctx, sgm.sgm_submit(ctx, fr))
-        runs.append(fr)
+    announce("8 x 1920x1080 D=256 in one submit")
+    sgm.sgm_wait(ctx, sgm.sgm_submit(ctx, frames))
     torch.cuda.synchronize()
-    sgm.sgm_set_schedule(ctx, p, 0)
-    for i, (p, left, right) in enumerate(inputs):
+    for i, ((p, left, right), f) in enumerate(zip(inputs, frames)):
         announce("oracle frame", i)
-        want = oracle_maps(p, left, right)
-        for src, fr in zip(("volume", "census codes"), runs):
-            check_frame(fr[i], want, "1920x1080 frame %d, costs from the %s" % (i, src))
+        check_frame(f, oracle_maps(p, left, right), "1920x1080 frame %d" % i)
         # the maps are far from trivial: most pixels valid, many disparities
-        d = to_np(runs[0][i].disp)
+        d = to_np(f.disp)
         assert (d < 256).mean() > 0.5 and len(np.unique(d)) > 50
 
 
@@ -97,20 +83,11 @@ def test_batch_of_32_mixed_pairs_matches_oracle(env):
         p = full_path_params(sgm, W, H, D)
         frames.append(sgm.Frame.alloc(p, to_dev(torch, left), to_dev(torch, right)))
         inputs.append((p, left, right))
-    runs = []
-    for src in (sgm.COSTS_VOLUME, sgm.COSTS_CENSUS):
-        sgm.sgm_set_schedule(ctx, None, 0, cost_source=src)
-        fr = [sgm.Frame.alloc(q, f.left, f.right) for (q, _, _), f in zip(inputs, frames)]
-        announce("32 mixed pairs in one submit, cost source", src)
-        sgm.sgm_wait(ctx, sgm.sgm_submit(ctx, fr))
-        runs.append(fr)
+    announce("32 mixed pairs in one submit")
+    sgm.sgm_wait(ctx, sgm.sgm_submit(ctx, frames))
     torch.cuda.synchronize()
-    sgm.sgm_set_schedule(ctx, None, 0)
-    for i, (p, left, right) in enumerate(inputs):
-        want = oracle_maps(p, left, right)
-        for src, fr in zip(("volume", "census codes"), runs):
-            check_frame(fr[i], want, "pair %d %dx%d D%d, costs from the %s" % (i, p.width, p.height,
-                                                                              p.max_disp, src))
+    for i, ((p, left, right), f) in enumerate(zip(inputs, frames)):
+        check_frame(f, oracle_maps(p, left, right), "pair %d %dx%d D%d" % (i, p.width, p.height, p.max_disp))
 
 
 @pytest.mark.timeout(600)
