@@ -124,10 +124,10 @@ def bench_small(torch, sgm, ctx, synthetic, steps=200):
     p = sgm.Params(width=320, height=240, max_disp=64, census_w=5, census_h=5, path_mask=0x0F,
                    p1=10, p2=120, lr_check=0, median=0)
     Lt, Rt = torch.from_numpy(L).cuda(), torch.from_numpy(R).cuda()
-    h = sgm.sgm_autotune(ctx, sgm.Frame.alloc(p, Lt, Rt), reps=5)[0]
+    sched = sgm.sgm_autotune(ctx, sgm.Frame.alloc(p, Lt, Rt), reps=5)[0]
     prof_on = True
     sgm.sgm_profile(ctx, False)
-    res = {"h_lanes": h}
+    res = {"schedule": sched}
     for streams in (1, 4):
         sgm.sgm_set_streams(ctx, streams)
         dt, _ = time_submit_stream(torch, sgm, ctx, lambda i: [sgm.Frame.alloc(p, Lt, Rt)], steps, 10)
@@ -275,7 +275,24 @@ def bench_rectified(torch, sgm, ctx, synthetic, steps):
             "rectify_gb_per_s": algo / (us * 1e-6) / 1e9}
 
 
+def _timed(torch, fn, reps=5, warm=2):
+    for _ in range(warm):
+        fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / reps
+
+
 def bench_batch32(torch, sgm, ctx, synthetic):
+    """The batch of 32 pairs of mixed sizes and disparity ranges (each shape
+    autotuned once): one sgm_submit of all 32 (the batched form), the same
+    submit with its frames split over 2 and 4 of the context's streams,
+    4 submits of 8 in flight, graph mode, and 32 one-frame submits waited
+    one by one (the per-frame path), in flight, and as stage calls; every
+    variant's maps are compared with the first."""
     specs = synthetic.mixed_batch_specs(32, seed=2000)
     frames = []
     for (W, H, D, seed) in specs:
@@ -283,8 +300,9 @@ def bench_batch32(torch, sgm, ctx, synthetic):
         p = kitti_params(sgm, W, H, D)
         frames.append(sgm.Frame.alloc(p, torch.from_numpy(L).cuda(), torch.from_numpy(R).cuda()))
     evals = sum(f.p.disp_evals() for f in frames)
-    res = {}
+    res = {"frames": 32, "disp_evals": evals}
     sgm.sgm_profile(ctx, False)
+    sgm.sgm_set_streams(ctx, HEADLINE_STREAMS)
     # autotune each distinct shape once on its first frame
     tuned = {}
     for f in frames:
@@ -292,51 +310,52 @@ def bench_batch32(torch, sgm, ctx, synthetic):
         if key not in tuned:
             tuned[key] = sgm.sgm_autotune(ctx, f, reps=3)[0]
     res["schedules"] = {"%dx%d D%d" % k: v for k, v in tuned.items()}
-    # one submit of all 32
-    for _ in range(2):
+
+    def one_submit():
         sgm.sgm_wait(ctx, sgm.sgm_submit(ctx, frames))
-    torch.cuda.synchronize()
-    reps = 5
-    t0 = time.perf_counter()
-    for _ in range(reps):
-        sgm.sgm_wait(ctx, sgm.sgm_submit(ctx, frames))
-    torch.cuda.synchronize()
-    tb = (time.perf_counter() - t0) / reps
-    batched = [f.disp.clone() for f in frames]
+
+    def in_flight(groups):
+        def run():
+            for t in [sgm.sgm_submit(ctx, g) for g in groups]:
+                sgm.sgm_wait(ctx, t)
+        return run
+
+    ref = None
+    same = True
+
+    def record(name, fn):
+        nonlocal ref, same
+        dt = _timed(torch, fn)
+        maps = [f.disp.clone() for f in frames]
+        if ref is None:
+            ref = maps
+        same = same and all(torch.equal(a, b) for a, b in zip(ref, maps))
+        res[name] = {"ms": dt * 1e3, "mdisp_evals_per_s": evals / dt / 1e6}
+
+    record("one_submit", one_submit)
+    for split in (2, 4):
+        sgm.sgm_set_split(ctx, split)
+        record("one_submit_split%d" % split, one_submit)
+    sgm.sgm_set_split(ctx, 1)
+    record("four_submits_of_8_in_flight", in_flight([frames[i:i + 8] for i in range(0, 32, 8)]))
+    record("32_one_frame_submits_in_flight", in_flight([[f] for f in frames]))
     sgm.sgm_set_graphs(ctx, True)
-    for _ in range(2):
-        sgm.sgm_wait(ctx, sgm.sgm_submit(ctx, frames))
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(reps):
-        sgm.sgm_wait(ctx, sgm.sgm_submit(ctx, frames))
-    torch.cuda.synchronize()
-    tg = (time.perf_counter() - t0) / reps
+    record("one_submit_graph_mode", one_submit)
     sgm.sgm_set_graphs(ctx, False)
-    same_graph = all(torch.equal(a, f.disp) for a, f in zip(batched, frames))
-    # 32 sequential per-frame submits, each waited for
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(reps):
+
+    def waited_one_by_one():
         for f in frames:
             sgm.sgm_wait(ctx, sgm.sgm_submit(ctx, [f]))
-    torch.cuda.synchronize()
-    ts = (time.perf_counter() - t0) / reps
-    same = all(torch.equal(a, f.disp) for a, f in zip(batched, frames))
-    # 32 sequential per-frame stage-call pipelines
-    torch.cuda.synchronize()
+
+    record("32_one_frame_submits_waited", waited_one_by_one)
     t0 = time.perf_counter()
     for f in frames:
         sgm.run_stages(ctx, f.p, f.left, f.right)
     torch.cuda.synchronize()
     tst = time.perf_counter() - t0
-    res.update(frames=32, disp_evals=evals, batched_ms=tb * 1e3,
-               batched_mdisp_evals_per_s=evals / tb / 1e6,
-               sequential_submit_ms=ts * 1e3, sequential_submit_mdisp_evals_per_s=evals / ts / 1e6,
-               sequential_stage_calls_ms=tst * 1e3,
-               sequential_stage_calls_mdisp_evals_per_s=evals / tst / 1e6,
-               batched_equals_sequential=bool(same), graph_batched_ms=tg * 1e3,
-               graph_batched_mdisp_evals_per_s=evals / tg / 1e6, graph_equals_direct=bool(same_graph))
+    res["32_stage_call_pipelines"] = {"ms": tst * 1e3, "mdisp_evals_per_s": evals / tst / 1e6}
+    res["all_variants_equal"] = bool(same)
+    res["autotuned_batch_ms"] = res["one_submit"]["ms"]
     sgm.sgm_profile(ctx, True)
     return res
 
@@ -420,9 +439,9 @@ def bench_kitti(torch, sgm, ctx, synthetic, steps=200, warmup=20):
     left, right, _ = synthetic.make_pair("kitti", 1001)
     p = kitti_params(sgm)
     L, R = torch.from_numpy(left).cuda(), torch.from_numpy(right).cuda()
-    h_lanes, tune_ms = sgm.sgm_autotune(ctx, sgm.Frame.alloc(p, L, R), reps=5)
+    sched, tune_ms = sgm.sgm_autotune(ctx, sgm.Frame.alloc(p, L, R), reps=5)
     sgm.sgm_profile(ctx, False)
-    res = {"schedule": {"h_lanes": h_lanes, "autotune_ms": tune_ms}}
+    res = {"schedule": sched, "autotune_ms": tune_ms}
     outs = {}
     for streams in (HEADLINE_STREAMS, 1):
         sgm.sgm_set_streams(ctx, streams)
@@ -536,8 +555,9 @@ def main():
     pairs = [synthetic.make_pair("large", 4000 + i)[:2] for i in range(8)]
     inputs = [(torch.from_numpy(l).cuda(), torch.from_numpy(r).cuda()) for l, r in pairs]
     evals = 8 * p.disp_evals()
-    h_lanes, tune_ms = sgm.sgm_autotune(ctx, sgm.Frame.alloc(p, *inputs[0]), reps=2)
-    log("autotuned h_lanes", h_lanes, tune_ms)
+    sched, tune_ms = sgm.sgm_autotune(ctx, sgm.Frame.alloc(p, *inputs[0]), reps=2)
+    h_lanes = sched["h_lanes"]
+    log("autotuned schedule", sched, tune_ms)
 
     def batch(i):
         return [sgm.Frame.alloc(p, l, r) for l, r in inputs]
@@ -621,7 +641,7 @@ def main():
                                "(30-50 slanted planes + thin poles)",
                    "frames_per_step": 8, "streams": args.streams, "batches_in_flight": HEADLINE_DEPTH,
                    "path": "sgm_submit of all 8 pairs per step",
-                   "schedule": {"h_lanes": h_lanes, "autotune_ms": tune_ms}},
+                   "schedule": sched, "autotune_ms": tune_ms},
         "fps": round(8 * args.steps / dt, 2),
         "one_stream": {"mdisp_evals_per_s": round(evals * args.steps / dt1 / 1e6, 2),
                        "ms_per_step": round(dt1 / args.steps * 1e3, 4), "outputs_equal": bool(same)},

@@ -285,6 +285,16 @@ int sgm_submit_after(sgm_ctx *ctx, const sgm_frame *frames, int n, void *const *
  * raise GPU_MAX_HW_QUEUES. */
 int sgm_set_streams(sgm_ctx *ctx, int n);
 
+/* Number of the context's streams one batch's frames are spread over (1 to
+ * 8; 1 after sgm_create): with n > 1 a batch of several frames is split into
+ * up to n groups of about equal work (W*H*D*paths), each enqueued on its own
+ * stream, so that stages of different frames overlap on the GPU (one
+ * frame's Census next to another's aggregation); the ticket completes when
+ * every group has.  Limited by sgm_set_streams; results are identical.
+ * Graph mode captures batches on one stream and ignores the split; with
+ * stage profiling on, stage times are summed over the groups. */
+int sgm_set_split(sgm_ctx *ctx, int n);
+
 /* sgm_submit with rectification (section 3.1.1) as the batch's first
  * stage: remaps[2i] and remaps[2i+1] turn frame i's raw left and right images
  * into frames[i].left and frames[i].right, on the batch's own stream, so raw
@@ -335,7 +345,11 @@ typedef struct {
    * the flag.  Pays off on batches of many frames; 0 (default) = the
    * per-direction kernels. */
   int32_t sweep;
-  int32_t reserved[2]; /* must be 0 */
+  /* threads per block of the disparity-selection kernel (one block per image
+   * row or row segment): 256, 512 or 1024; 0 = chosen by the launch's block
+   * count (small blocks when there are many rows, large when few). */
+  int32_t disp_threads;
+  int32_t reserved; /* must be 0 */
 } sgm_schedule;
 
 /* Set the schedule used by sgm_submit for frames of the shape of `shape`
@@ -344,13 +358,17 @@ typedef struct {
 int sgm_set_schedule(sgm_ctx *ctx, const sgm_params *shape, const sgm_schedule *s);
 /* The schedule sgm_submit would use for `shape` (after defaults). */
 int sgm_get_schedule(sgm_ctx *ctx, const sgm_params *shape, sgm_schedule *s);
-/* Autotuner: run `sample` (one frame, inputs and outputs as for sgm_submit)
- * under every candidate schedule, `reps` timed repetitions each after one
- * warm-up, keep the fastest for the sample's shape (as sgm_set_schedule) and
- * return it in *best (may be NULL).  Blocks until done.  `ms`, if non-NULL,
+/* Autotuner: time `sample` (one frame, inputs and outputs as for
+ * sgm_submit) under candidate schedules, `reps` timed repetitions each after
+ * one warm-up, on one stream, and keep the fastest for the sample's shape (as
+ * sgm_set_schedule); return it in *best (may be NULL).  The search is by
+ * coordinates: h_lanes 16, 32, 64 (disp_threads 0); then, with the best
+ * h_lanes, disp_threads 256, 512, 1024; then, for frames the single-pass
+ * sweep can take, the sweep.  Blocks until done.  `ms`, if non-NULL,
  * receives per-candidate milliseconds for up to `n_ms` candidates in the
- * order 16, 32, 64 lanes (-1 where a candidate does not apply).  Must not
- * run concurrently with other submissions on the same context. */
+ * order h_lanes 16, 32, 64, disp_threads 256, 512, 1024, sweep (-1 where a
+ * candidate does not apply).  Must not run concurrently with other
+ * submissions on the same context. */
 int sgm_autotune(sgm_ctx *ctx, const sgm_frame *sample, int reps, sgm_schedule *best, float *ms,
                  int n_ms);
 

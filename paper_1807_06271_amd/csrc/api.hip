@@ -3,6 +3,7 @@
 // sgm_submit / sgm_poll path.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -117,6 +118,7 @@ struct Batch {
   Block mem;
   int stream = 0;
   std::vector<StageEvents> prof;  // empty unless profiling
+  std::vector<hipEvent_t> joins;  // fork / join events of a batch split over streams
 };
 
 }  // namespace
@@ -142,6 +144,7 @@ struct sgm_ctx {
   hipStream_t streams[kStreams] = {};
   int nstreams = 4;  // streams in use (round robin)
   int next_stream = 0;
+  int split = 1;     // streams one batch's frames are spread over
   bool profiling = false;
   bool graphs = false;
   std::map<std::string, hipGraphExec_t> graph_cache;  // by batch composition
@@ -339,6 +342,13 @@ int resolve_sweep(const sgm_ctx *c, const sgm_params &p) {
   return want && sweep_ok(p) ? 1 : 0;
 }
 
+// Disparity-selection block size for a frame (0: by the launch's block count).
+int resolve_disp_threads(const sgm_ctx *c, const sgm_params &p) {
+  auto it = c->tuned.find(shape_key(p));
+  const int t = it != c->tuned.end() ? it->second.disp_threads : 0;
+  return t ? t : c->dflt.disp_threads;
+}
+
 // Check one sgm_remap (sizes, pitches, device pointers) and build its job.
 int check_remap(const sgm_remap &r, int i, int dev, RemapJob *out) {
   if (r.w < 1 || r.h < 1 || r.w > 16384 || r.h > 16384)
@@ -387,6 +397,7 @@ std::string composition_key(const sgm_frame *fr, int n, const std::vector<int> &
     snprintf(buf, sizeof buf, "%d,%d,%d,%d,%d,%u,%u,%u,%d,%d,%d,%u,%u,%d,%d,%d;", p.width, p.height,
              p.max_disp, p.census_w, p.census_h, p.path_mask, p.p1, p.p2, p.lr_check, p.lr_max_diff,
              p.median, p.invalid, p.cost, lr_bytes_of(p), hlps[i] | sweep[i] << 8, fr[i].umap ? 1 : 0);
+    // (hlps carries the disparity block size above bit 16)
     k += buf;
   }
   return k;
@@ -397,7 +408,9 @@ int check_schedule(const sgm_schedule *s) {
   if (s->h_lanes != 0 && s->h_lanes != 16 && s->h_lanes != 32 && s->h_lanes != 64)
     return fail(SGM_EINVAL, "h_lanes must be 0, 16, 32 or 64 (got %d)", s->h_lanes);
   if (s->sweep != 0 && s->sweep != 1) return fail(SGM_EINVAL, "sweep must be 0 or 1 (got %d)", s->sweep);
-  if (s->reserved[0] || s->reserved[1]) return fail(SGM_EINVAL, "reserved must be 0");
+  if (s->disp_threads != 0 && s->disp_threads != 256 && s->disp_threads != 512 && s->disp_threads != 1024)
+    return fail(SGM_EINVAL, "disp_threads must be 0, 256, 512 or 1024 (got %d)", s->disp_threads);
+  if (s->reserved) return fail(SGM_EINVAL, "reserved must be 0");
   return SGM_OK;
 }
 
@@ -426,7 +439,7 @@ struct StageMark {
 int enqueue_frames(const sgm_frame *fr, int n, const std::vector<FramePlan> &plans,
                    const std::vector<int> &hlps, const std::vector<int> &sweep,
                    const std::vector<RemapJob> &rect, char *mem, hipStream_t s,
-                   std::vector<StageEvents> *prof) {
+                   std::vector<StageEvents> *prof, hipEvent_t census_done = nullptr) {
   StageMark mark{prof, s};
   // rectification of the raw views into the frames' input buffers (one
   // launch for every view of the batch)
@@ -506,6 +519,7 @@ int enqueue_frames(const sgm_frame *fr, int n, const std::vector<FramePlan> &pla
     ++launches;
   }
   CHECK(mark.end(launches));
+  if (census_done) HIP_TRY(hipEventRecord(census_done, s));
   // aggregation, one launch per (disparities per lane, path-cost width)
   CHECK(mark.begin(SGM_STAGE_AGGREGATE));
   int groups = 0;
@@ -517,7 +531,7 @@ int enqueue_frames(const sgm_frame *fr, int n, const std::vector<FramePlan> &pla
       for (int i = 0; i < n; ++i) {
         const sgm_params &p = fr[i].p;
         if (sweep[i] || (int)is_sad(p) != sad || k_of(p) != K || lr_bytes_of(p) != lb) continue;
-        if (hlps[i] != c_hlps) continue;
+        if ((hlps[i] & 0xFFFF) != c_hlps) continue;
         AggJob j{};
         if (sad) j.cost16 = reinterpret_cast<const uint16_t *>(mem + plans[i].off_cost);
         else j.cost8 = reinterpret_cast<const uint8_t *>(mem + plans[i].off_cost);
@@ -627,6 +641,7 @@ int enqueue_frames(const sgm_frame *fr, int n, const std::vector<FramePlan> &pla
       j.D = p.max_disp;
       j.Dp = dp_of(p);
       j.lr_check = p.lr_check;
+      j.threads = hlps[i] >> 16;
       disp_segments(p.width, p.max_disp, split, &j.nseg, &j.seglen);
       dj.push_back(j);
     }
@@ -715,8 +730,77 @@ void destroy_events(Batch &b) {
     if (e.end) (void)hipEventDestroy(e.end);
   }
   b.prof.clear();
+  for (hipEvent_t e : b.joins) (void)hipEventDestroy(e);
+  b.joins.clear();
   if (b.done) (void)hipEventDestroy(b.done);
   b.done = nullptr;
+}
+
+// Spread the frames of one batch over `groups` of the context's streams --
+// largest frames first, each to the group with the least work so far -- so
+// that the stages of different frames overlap on the GPU.  Group g starts
+// when group g - 1 has finished its Census stage, so its Census (bound by
+// the ALUs) runs next to the previous group's aggregation and disparity
+// selection (bound by HBM) rather than next to the other groups' Census.
+// The batch's own stream waits for every group before its done event.
+// Results do not depend on the split.
+int enqueue_split(sgm_ctx *c, Batch &b, const sgm_frame *fr, int n, const std::vector<FramePlan> &plans,
+                  const std::vector<int> &hl, const std::vector<int> &sw, const std::vector<RemapJob> &rect,
+                  char *mem, int groups, std::vector<StageEvents> *prof) {
+  std::vector<int> order(n);
+  for (int i = 0; i < n; ++i) order[i] = i;
+  auto work = [&](int i) {
+    const sgm_params &p = fr[i].p;
+    return (double)p.width * p.height * p.max_disp * popcount8(p.path_mask);
+  };
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b2) { return work(a) > work(b2); });
+  std::vector<std::vector<int>> part(groups);
+  std::vector<double> load(groups, 0.0);
+  for (int i : order) {
+    int g = 0;
+    for (int k = 1; k < groups; ++k)
+      if (load[k] < load[g]) g = k;
+    part[g].push_back(i);
+    load[g] += work(i);
+  }
+  hipStream_t s0 = c->streams[b.stream];
+  hipEvent_t fork = nullptr;  // where the next group may start
+  HIP_TRY(hipEventCreateWithFlags(&fork, hipEventDisableTiming));
+  b.joins.push_back(fork);
+  HIP_TRY(hipEventRecord(fork, s0));
+  for (int g = 0; g < groups; ++g) {
+    if (part[g].empty()) continue;
+    std::sort(part[g].begin(), part[g].end());  // frames keep their batch order
+    hipStream_t sg = c->streams[(b.stream + g) % c->nstreams];
+    HIP_TRY(hipStreamWaitEvent(sg, fork, 0));
+    hipEvent_t next = nullptr;
+    HIP_TRY(hipEventCreateWithFlags(&next, hipEventDisableTiming));
+    b.joins.push_back(next);
+    fork = next;
+    std::vector<sgm_frame> f;
+    std::vector<FramePlan> pl;
+    std::vector<int> h, w;
+    std::vector<RemapJob> r;
+    for (int i : part[g]) {
+      f.push_back(fr[i]);
+      pl.push_back(plans[i]);
+      h.push_back(hl[i]);
+      w.push_back(sw[i]);
+      if (!rect.empty()) {
+        r.push_back(rect[2 * i]);
+        r.push_back(rect[2 * i + 1]);
+      }
+    }
+    CHECK(enqueue_frames(f.data(), (int)f.size(), pl, h, w, r, mem, sg, prof, fork));
+    if (sg != s0) {
+      hipEvent_t join = nullptr;
+      HIP_TRY(hipEventCreateWithFlags(&join, hipEventDisableTiming));
+      b.joins.push_back(join);
+      HIP_TRY(hipEventRecord(join, sg));
+      HIP_TRY(hipStreamWaitEvent(s0, join, 0));
+    }
+  }
+  return SGM_OK;
 }
 
 // Capture the batch's launches on `s` into a graph, then replay it through
@@ -1086,7 +1170,8 @@ static int submit_impl(sgm_ctx *c, const sgm_frame *frames, const sgm_remap *rem
   std::vector<FramePlan> plans(n);
   size_t total = 0;
   for (int i = 0; i < n; ++i) {
-    hl[i] = resolve_hlps(c, frames[i].p);
+    // lanes per horizontal scanline, with the disparity block size above bit 16
+    hl[i] = resolve_hlps(c, frames[i].p) | resolve_disp_threads(c, frames[i].p) << 16;
     sw[i] = resolve_sweep(c, frames[i].p);
     plans[i] = plan_frame(frames[i].p, total, sw[i] != 0);
     total += plans[i].bytes;
@@ -1149,8 +1234,12 @@ static int submit_impl(sgm_ctx *c, const sgm_frame *frames, const sgm_remap *rem
     c->idle.push_back(blk);
     return rc;
   }
+  const int groups = std::min(std::min(c->split, c->nstreams), n);
   if (c->graphs && !c->profiling) {
     rc = enqueue_graph(c, frames, n, plans, hl, sw, rect, reinterpret_cast<char *>(blk.ptr), s);
+  } else if (groups > 1) {
+    rc = enqueue_split(c, b, frames, n, plans, hl, sw, rect, reinterpret_cast<char *>(blk.ptr), groups,
+                       c->profiling ? &b.prof : nullptr);
   } else {
     rc = enqueue_frames(frames, n, plans, hl, sw, rect, reinterpret_cast<char *>(blk.ptr), s,
                         c->profiling ? &b.prof : nullptr);
@@ -1159,7 +1248,9 @@ static int submit_impl(sgm_ctx *c, const sgm_frame *frames, const sgm_remap *rem
     rc = fail(SGM_EHIP, "hipEventCreate failed");
   if (rc == SGM_OK && hipEventRecord(b.done, s) != hipSuccess) rc = fail(SGM_EHIP, "hipEventRecord failed");
   if (rc != SGM_OK) {
-    (void)hipStreamSynchronize(s);
+    // work already enqueued (on every stream a split batch used) must end
+    // before the block can be reused
+    for (int g = 0; g < std::max(groups, 1); ++g) (void)hipStreamSynchronize(c->streams[(b.stream + g) % c->nstreams]);
     destroy_events(b);
     c->idle.push_back(blk);
     return rc;
@@ -1290,6 +1381,57 @@ int sgm_get_schedule(sgm_ctx *c, const sgm_params *shape, sgm_schedule *sc) {
   *sc = sgm_schedule{};
   sc->h_lanes = resolve_hlps(c, *shape);
   sc->sweep = resolve_sweep(c, *shape);
+  sc->disp_threads = resolve_disp_threads(c, *shape);
+  return SGM_OK;
+}
+
+// Milliseconds per submit of `sample` under schedule `sc` (set for the
+// sample's shape): one warm-up, then `reps` submits back to back on stream 0.
+static int time_schedule(sgm_ctx *c, const sgm_frame *sample, int reps, const sgm_schedule &sc, float *out) {
+  CHECK(sgm_set_schedule(c, &sample->p, &sc));
+  uint64_t t = 0;
+  CHECK(sgm_submit(c, sample, 1, &t));  // warm-up (also sizes the scratch)
+  CHECK(sgm_wait(c, t));
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  HIP_TRY(hipEventCreate(&e0));
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return fail(SGM_EHIP, "hipEventCreate failed");
+  }
+  hipStream_t s0 = c->streams[0];
+  int saved_streams, saved_split;
+  {  // every repetition runs back to back on stream 0, unsplit
+    std::lock_guard<std::mutex> lk(c->mu);
+    saved_streams = c->nstreams;
+    saved_split = c->split;
+    c->nstreams = 1;
+    c->split = 1;
+    c->next_stream = 0;
+  }
+  int rc = hipEventRecord(e0, s0) == hipSuccess ? SGM_OK : fail(SGM_EHIP, "event record");
+  std::vector<uint64_t> tk;
+  for (int r = 0; r < reps && rc == SGM_OK; ++r) {
+    rc = sgm_submit(c, sample, 1, &t);
+    if (rc == SGM_OK) tk.push_back(t);
+  }
+  if (rc == SGM_OK && hipEventRecord(e1, s0) != hipSuccess) rc = fail(SGM_EHIP, "event record");
+  for (uint64_t k : tk) {
+    int r2 = sgm_wait(c, k);
+    if (rc == SGM_OK) rc = r2;
+  }
+  {
+    std::lock_guard<std::mutex> lk(c->mu);
+    c->nstreams = saved_streams;
+    c->split = saved_split;
+    c->next_stream = 0;
+  }
+  float el = 0.f;
+  if (rc == SGM_OK && hipEventSynchronize(e1) != hipSuccess) rc = fail(SGM_EHIP, "event sync");
+  if (rc == SGM_OK && hipEventElapsedTime(&el, e0, e1) != hipSuccess) rc = fail(SGM_EHIP, "elapsed");
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc) return rc;
+  *out = el / reps;
   return SGM_OK;
 }
 
@@ -1298,58 +1440,46 @@ int sgm_autotune(sgm_ctx *c, const sgm_frame *sample, int reps, sgm_schedule *be
   if (!c || !sample) return fail(SGM_EINVAL, "ctx and sample must be non-null");
   if (reps < 1) return fail(SGM_EINVAL, "reps must be >= 1");
   CHECK(validate(&sample->p));
-  const int cands[3] = {16, 32, 64};
-  float times[3] = {-1.f, -1.f, -1.f};
-  int bi = -1;
-  for (int ci = 0; ci < 3; ++ci) {
-    if (!agg_hlps_ok(k_of(sample->p), cands[ci])) continue;
-    sgm_schedule sc{};
-    sc.h_lanes = cands[ci];
-    CHECK(sgm_set_schedule(c, &sample->p, &sc));
-    hipEvent_t e0 = nullptr, e1 = nullptr;
-    uint64_t t = 0;
-    CHECK(sgm_submit(c, sample, 1, &t));  // warm-up (also sizes the scratch)
-    CHECK(sgm_wait(c, t));
-    HIP_TRY(hipEventCreate(&e0));
-    HIP_TRY(hipEventCreate(&e1));
-    hipStream_t s0 = c->streams[0];
-    int saved;
-    {  // time on one stream: every repetition runs back to back on stream 0
-      std::lock_guard<std::mutex> lk(c->mu);
-      saved = c->nstreams;
-      c->nstreams = 1;
-      c->next_stream = 0;
-    }
-    int rc = hipEventRecord(e0, s0) == hipSuccess ? SGM_OK : fail(SGM_EHIP, "event record");
-    std::vector<uint64_t> tk;
-    for (int r = 0; r < reps && rc == SGM_OK; ++r) {
-      rc = sgm_submit(c, sample, 1, &t);
-      if (rc == SGM_OK) tk.push_back(t);
-    }
-    if (rc == SGM_OK && hipEventRecord(e1, s0) != hipSuccess) rc = fail(SGM_EHIP, "event record");
-    for (uint64_t k : tk) {
-      int r2 = sgm_wait(c, k);
-      if (rc == SGM_OK) rc = r2;
-    }
-    {
-      std::lock_guard<std::mutex> lk(c->mu);
-      c->nstreams = saved;
-      c->next_stream = 0;
-    }
-    float el = 0.f;
-    if (rc == SGM_OK && hipEventSynchronize(e1) != hipSuccess) rc = fail(SGM_EHIP, "event sync");
-    if (rc == SGM_OK && hipEventElapsedTime(&el, e0, e1) != hipSuccess) rc = fail(SGM_EHIP, "elapsed");
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
-    if (rc) return rc;
-    times[ci] = el / reps;
-    if (bi < 0 || times[ci] < times[bi]) bi = ci;
-  }
+  constexpr int kCands = 7;  // h_lanes 16, 32, 64; disp_threads 256, 512, 1024; sweep
+  float times[kCands];
+  for (float &t : times) t = -1.f;
   sgm_schedule win{};
-  win.h_lanes = bi >= 0 ? cands[bi] : 16;
+  float win_ms = -1.f;
+  auto consider = [&](int slot, const sgm_schedule &sc) -> int {
+    float t = 0.f;
+    CHECK(time_schedule(c, sample, reps, sc, &t));
+    times[slot] = t;
+    if (win_ms < 0.f || t < win_ms) {
+      win = sc;
+      win_ms = t;
+    }
+    return SGM_OK;
+  };
+  // 1. lanes per horizontal scanline
+  const int lanes[3] = {16, 32, 64};
+  for (int ci = 0; ci < 3; ++ci) {
+    if (!agg_hlps_ok(k_of(sample->p), lanes[ci])) continue;
+    sgm_schedule sc{};
+    sc.h_lanes = lanes[ci];
+    CHECK(consider(ci, sc));
+  }
+  // 2. disparity-selection block size, with the best lane layout
+  const int threads[3] = {256, 512, 1024};
+  const sgm_schedule base = win;
+  for (int ci = 0; ci < 3; ++ci) {
+    sgm_schedule sc = base;
+    sc.disp_threads = threads[ci];
+    CHECK(consider(3 + ci, sc));
+  }
+  // 3. the single-pass sweep, for frames it can take
+  if (sweep_ok(sample->p)) {
+    sgm_schedule sc = win;
+    sc.sweep = 1;
+    CHECK(consider(6, sc));
+  }
   CHECK(sgm_set_schedule(c, &sample->p, &win));
   if (best) *best = win;
-  for (int i = 0; ms && i < n_ms && i < 3; ++i) ms[i] = times[i];
+  for (int i = 0; ms && i < n_ms && i < kCands; ++i) ms[i] = times[i];
   return SGM_OK;
 }
 
@@ -1365,6 +1495,14 @@ int sgm_set_graphs(sgm_ctx *c, int on) {
   if (!c) return fail(SGM_EINVAL, "ctx is null");
   std::lock_guard<std::mutex> lk(c->mu);
   c->graphs = on != 0;
+  return SGM_OK;
+}
+
+int sgm_set_split(sgm_ctx *c, int n) {
+  if (!c) return fail(SGM_EINVAL, "ctx is null");
+  if (n < 1 || n > sgm_ctx::kStreams) return fail(SGM_EINVAL, "split must be in [1, %d]", sgm_ctx::kStreams);
+  std::lock_guard<std::mutex> lk(c->mu);
+  c->split = n;
   return SGM_OK;
 }
 

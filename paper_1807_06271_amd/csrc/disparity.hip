@@ -236,11 +236,11 @@ void launch_lr_seg(std::vector<LRSegJob> jobs, hipStream_t s) {
 }
 
 template <int K, int IN>
-static void launch_disp_ki(const JobTable<DispJob> &t, int blocks, size_t lds, hipStream_t s) {
+static void launch_disp_ki(const JobTable<DispJob> &t, int blocks, int want, size_t lds, hipStream_t s) {
   // 1024 threads leave 128 registers per lane: too few for two sweeps of
   // raw words beyond 64 of them
   constexpr bool fits1024 = K < 16 && 2 * DispShape<K, IN>::NPX * DispShape<K, IN>::RAW <= 64;
-  const int threads = disp_threads(blocks);
+  const int threads = want ? want : disp_threads(blocks);
   if (threads == 256) {
     hipLaunchKernelGGL((disp_kernel<K, IN, 256>), dim3(blocks), dim3(256), lds, s, t);
   } else if (threads == 512 || !fits1024) {
@@ -251,38 +251,39 @@ static void launch_disp_ki(const JobTable<DispJob> &t, int blocks, size_t lds, h
 }
 
 template <int K>
-static void launch_disp_k(int in_kind, const JobTable<DispJob> &t, int blocks, size_t lds,
+static void launch_disp_k(int in_kind, const JobTable<DispJob> &t, int blocks, int want, size_t lds,
                           hipStream_t s) {
   switch (in_kind) {
-    case 0: launch_disp_ki<K, 0>(t, blocks, lds, s); break;
-    case 1: launch_disp_ki<K, 1>(t, blocks, lds, s); break;
-    default: launch_disp_ki<K, 2>(t, blocks, lds, s); break;
+    case 0: launch_disp_ki<K, 0>(t, blocks, want, lds, s); break;
+    case 1: launch_disp_ki<K, 1>(t, blocks, want, lds, s); break;
+    default: launch_disp_ki<K, 2>(t, blocks, want, lds, s); break;
   }
 }
 
 void launch_disparity(std::vector<DispJob> jobs, int in_kind, hipStream_t s) {
-  // one launch per disparities-per-lane width K
-  for (int K : {4, 8, 12, 16}) {
-    std::vector<DispJob> sub;
-    int maxz = 0;
-    for (auto &j : jobs)
-      if (agg_k(j.D) == K) {  // nseg / seglen chosen by the caller
-        sub.push_back(j);
-        maxz = std::max(maxz, std::min(j.W, j.seglen) + j.D - 1);
-      }
-    if (sub.empty()) continue;
-    const size_t lds = (size_t)(maxz + maxz / 8 + 1) * 4;
-    for_each_table(
-        sub, [](const DispJob &j) { return (long)j.H * j.nseg; },
-        [&](const JobTable<DispJob> &t, int blocks) {
-          switch (K) {
-            case 4: launch_disp_k<4>(in_kind, t, blocks, lds, s); break;
-            case 8: launch_disp_k<8>(in_kind, t, blocks, lds, s); break;
-            case 12: launch_disp_k<12>(in_kind, t, blocks, lds, s); break;
-            default: launch_disp_k<16>(in_kind, t, blocks, lds, s); break;
-          }
-        });
-  }
+  // one launch per disparities-per-lane width K and requested block size
+  for (int K : {4, 8, 12, 16})
+    for (int want : {0, 256, 512, 1024}) {
+      std::vector<DispJob> sub;
+      int maxz = 0;
+      for (auto &j : jobs)
+        if (agg_k(j.D) == K && j.threads == want) {  // nseg / seglen chosen by the caller
+          sub.push_back(j);
+          maxz = std::max(maxz, std::min(j.W, j.seglen) + j.D - 1);
+        }
+      if (sub.empty()) continue;
+      const size_t lds = (size_t)(maxz + maxz / 8 + 1) * 4;
+      for_each_table(
+          sub, [](const DispJob &j) { return (long)j.H * j.nseg; },
+          [&](const JobTable<DispJob> &t, int blocks) {
+            switch (K) {
+              case 4: launch_disp_k<4>(in_kind, t, blocks, want, lds, s); break;
+              case 8: launch_disp_k<8>(in_kind, t, blocks, want, lds, s); break;
+              case 12: launch_disp_k<12>(in_kind, t, blocks, want, lds, s); break;
+              default: launch_disp_k<16>(in_kind, t, blocks, want, lds, s); break;
+            }
+          });
+    }
 }
 
 // ------------------------------------------------------------- median

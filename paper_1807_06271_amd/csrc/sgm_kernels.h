@@ -113,6 +113,7 @@ struct DispJob {
   int W, H, D, Dp;
   int lr_check;
   int nseg, seglen;   // row segments (disp_segments)
+  int threads;        // block size (256, 512, 1024), 0: chosen by the launch's block count
   int blk0;
 };
 // Row segments of the disparity kernel: with split, nseg segments of seglen

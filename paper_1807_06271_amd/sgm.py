@@ -39,7 +39,7 @@ EXPORTS = ["sgm_validate", "sgm_create", "sgm_destroy", "sgm_last_error", "sgm_c
            "sgm_profile_read", "sgm_set_streams", "sgm_set_schedule", "sgm_get_schedule",
            "sgm_autotune", "sgm_set_graphs", "sgm_graph_stats", "sgm_rectify",
            "sgm_submit_rectify", "uv_filter", "sgm_submit_after",
-           "sgm_disparity_noalloc"]
+           "sgm_disparity_noalloc", "sgm_set_split"]
 STAGES = ["census", "aggregate", "disparity", "median", "uv", "rectify"]
 
 
@@ -59,7 +59,8 @@ class sgm_params(ctypes.Structure):
 
 
 class sgm_schedule(ctypes.Structure):
-    _fields_ = [("h_lanes", ctypes.c_int32), ("sweep", ctypes.c_int32), ("reserved", ctypes.c_int32 * 2)]
+    _fields_ = [("h_lanes", ctypes.c_int32), ("sweep", ctypes.c_int32), ("disp_threads", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 class sgm_remap(ctypes.Structure):
@@ -159,6 +160,7 @@ def lib():
         L.sgm_memory.argtypes = [vp, P(ctypes.c_size_t), P(ctypes.c_size_t)]
         L.sgm_profile.argtypes = [vp, i32]
         L.sgm_set_streams.argtypes = [vp, i32]
+        L.sgm_set_split.argtypes = [vp, i32]
         L.sgm_set_graphs.argtypes = [vp, i32]
         L.sgm_graph_stats.argtypes = [vp, P(ctypes.c_uint64), P(ctypes.c_uint64)]
         L.sgm_set_schedule.argtypes = [vp, P(sgm_params), P(sgm_schedule)]
@@ -457,11 +459,12 @@ def sgm_memory(ctx: Context):
     return a.value, b.value
 
 
-def sgm_set_schedule(ctx: Context, p: Params | None, h_lanes: int, sweep: bool = False) -> None:
+def sgm_set_schedule(ctx: Context, p: Params | None, h_lanes: int, sweep: bool = False,
+                     disp_threads: int = 0) -> None:
     """Schedule for frames of p's shape (p=None: the default): lanes per
-    horizontal scanline, and whether eligible frames use the single-pass
-    sweep."""
-    sc = sgm_schedule(h_lanes, int(bool(sweep)))
+    horizontal scanline, whether eligible frames use the single-pass sweep,
+    and the disparity-selection block size (0: by block count)."""
+    sc = sgm_schedule(h_lanes, int(bool(sweep)), int(disp_threads))
     _check(lib().sgm_set_schedule(ctx.handle, ctypes.byref(p.c()) if p is not None else None,
                                   ctypes.byref(sc)), "sgm_set_schedule")
 
@@ -472,20 +475,30 @@ def sgm_get_schedule(ctx: Context, p: Params) -> int:
 
 
 def schedule_of(ctx: Context, p: Params):
-    """(h_lanes, sweep) that sgm_submit would use for frames like p."""
+    """(h_lanes, sweep, disp_threads) that sgm_submit would use for frames
+    like p."""
     sc = sgm_schedule()
     _check(lib().sgm_get_schedule(ctx.handle, ctypes.byref(p.c()), ctypes.byref(sc)), "sgm_get_schedule")
-    return sc.h_lanes, bool(sc.sweep)
+    return sc.h_lanes, bool(sc.sweep), sc.disp_threads
+
+
+AUTOTUNE_CANDIDATES = ("h_lanes=16", "h_lanes=32", "h_lanes=64", "disp_threads=256", "disp_threads=512",
+                       "disp_threads=1024", "sweep")
 
 
 def sgm_autotune(ctx: Context, sample: "Frame", reps: int = 5):
-    """Time every candidate schedule on `sample`, keep the fastest for its
-    shape; returns (h_lanes, {h_lanes: ms per frame})."""
+    """Time the candidate schedules on `sample` (lanes per horizontal
+    scanline; then the disparity block size; then the sweep where it
+    applies) and keep the fastest for its shape.  Returns (schedule,
+    {candidate: ms per frame}) with schedule = {"h_lanes", "sweep",
+    "disp_threads"}."""
     best = sgm_schedule()
-    ms = (ctypes.c_float * 3)()
+    n = len(AUTOTUNE_CANDIDATES)
+    ms = (ctypes.c_float * n)()
     f = sample.c()
-    _check(lib().sgm_autotune(ctx.handle, ctypes.byref(f), reps, ctypes.byref(best), ms, 3), "sgm_autotune")
-    return best.h_lanes, {h: ms[i] for i, h in enumerate((16, 32, 64)) if ms[i] >= 0}
+    _check(lib().sgm_autotune(ctx.handle, ctypes.byref(f), reps, ctypes.byref(best), ms, n), "sgm_autotune")
+    sched = {"h_lanes": best.h_lanes, "sweep": bool(best.sweep), "disp_threads": best.disp_threads}
+    return sched, {name: ms[i] for i, name in enumerate(AUTOTUNE_CANDIDATES) if ms[i] >= 0}
 
 
 def sgm_set_graphs(ctx: Context, on: bool) -> None:
@@ -501,6 +514,11 @@ def sgm_graph_stats(ctx: Context):
 
 def sgm_set_streams(ctx: Context, n: int) -> None:
     _check(lib().sgm_set_streams(ctx.handle, int(n)), "sgm_set_streams")
+
+
+def sgm_set_split(ctx: Context, n: int) -> None:
+    """Spread each batch's frames over up to n of the context's streams."""
+    _check(lib().sgm_set_split(ctx.handle, int(n)), "sgm_set_split")
 
 
 def sgm_profile(ctx: Context, enable: bool) -> None:

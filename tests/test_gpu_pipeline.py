@@ -253,3 +253,33 @@ def test_lr_and_median_combinations_match_oracle(env, batched):
         assert_equal(to_np(f.disp), want["disp"], "disp " + tag)
         assert_equal(to_np(f.umap), want["umap"], "umap " + tag)
         assert_equal(to_np(f.vmap), want["vmap"], "vmap " + tag)
+
+
+@pytest.mark.parametrize("split", [2, 3, 4])
+def test_batch_split_over_streams_matches_oracle(env, split):
+    # a batch's frames spread over several of the context's streams (largest
+    # first, balanced by work): every frame still equals the oracle, with
+    # stage profiling on as well as off
+    torch, sgm, ctx = env
+    announce("batch split over", split, "streams")
+    items = []
+    for k, (W, H, D) in enumerate([(320, 240, 64), (211, 77, 128), (97, 40, 256), (160, 90, 64), (50, 20, 32)]):
+        left, right, _ = synthetic.make_pair("kitti", 1200 + k, W, H, D)
+        p = sgm.Params(width=W, height=H, max_disp=D, census_w=9, census_h=7, invalid=65535 if D == 256 else 255)
+        items.append((p, left, right, sgm.Frame.alloc(p, to_dev(torch, left), to_dev(torch, right))))
+    sgm.sgm_set_streams(ctx, 4)
+    sgm.sgm_set_split(ctx, split)
+    try:
+        for prof in (False, True):
+            sgm.sgm_profile(ctx, prof)
+            frames = [sgm.Frame.alloc(p, f.left, f.right) for p, _, _, f in items]
+            sgm.sgm_wait(ctx, sgm.sgm_submit(ctx, frames))
+            for (p, left, right, _), f in zip(items, frames):
+                want = oracle_for(p, left, right)
+                tag = "%dx%d D%d split %d profiling %d" % (p.width, p.height, p.max_disp, split, prof)
+                assert_equal(to_np(f.disp), want["disp"], "disp " + tag)
+                assert_equal(to_np(f.umap), want["umap"], "umap " + tag)
+                assert_equal(to_np(f.vmap), want["vmap"], "vmap " + tag)
+    finally:
+        sgm.sgm_profile(ctx, False)
+        sgm.sgm_set_split(ctx, 1)

@@ -78,10 +78,16 @@ def test_autotune_keeps_a_valid_schedule(env):
     p = sgm.Params(width=W, height=H, max_disp=D)
     f = sgm.Frame.alloc(p, to_dev(torch, left), to_dev(torch, right))
     best, ms = sgm.sgm_autotune(ctx, f, reps=2)
-    assert best in ms and set(ms) == {16, 32, 64}
+    # lanes first, then the disparity block size (no sweep: 9x7 codes, D = 128)
+    assert set(ms) == {"h_lanes=16", "h_lanes=32", "h_lanes=64", "disp_threads=256", "disp_threads=512",
+                       "disp_threads=1024"}
     assert all(v > 0 for v in ms.values())
-    assert best == min(ms, key=ms.get)
-    assert sgm.sgm_get_schedule(ctx, p) == best
+    lane_best = min((16, 32, 64), key=lambda h: ms["h_lanes=%d" % h])
+    assert best["h_lanes"] == lane_best and not best["sweep"]
+    overall = min(ms.values())
+    assert ms["h_lanes=%d" % lane_best] == overall if best["disp_threads"] == 0 \
+        else ms["disp_threads=%d" % best["disp_threads"]] == overall
+    assert sgm.schedule_of(ctx, p) == (best["h_lanes"], False, best["disp_threads"])
     sgm.sgm_wait(ctx, sgm.sgm_submit(ctx, [f]))
     want = O.sgm(left, right, D, 9, 7, 0xFF, 10, 120, True, 1, 3)
     assert_equal(to_np(f.disp), want["disp"], "disp after autotune")
