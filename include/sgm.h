@@ -349,8 +349,19 @@ typedef struct {
    * row or row segment): 256, 512 or 1024; 0 = chosen by the launch's block
    * count (small blocks when there are many rows, large when few). */
   int32_t disp_threads;
-  int32_t reserved; /* must be 0 */
+  /* Matching costs of the horizontal scanlines (left-right paths):
+   * SGM_HCOSTS_DEFAULT (0) = the library's default for the shape;
+   * SGM_HCOSTS_VOLUME (1) = read from the cost volume, like every other path;
+   * SGM_HCOSTS_CODES (2) = formed in the aggregation from the Census codes:
+   * a 64-lane row wave holds the right-view codes of all its disparities and
+   * slides them one code per pixel, so the two horizontal paths read 16
+   * bytes per pixel instead of D bytes of cost volume.  Applies to Census
+   * frames with 64 lanes per horizontal scanline, D in (64, 128] or
+   * (192, 256], N_b + p2 <= 255 and W * H * 16 bytes below 2 GiB; other
+   * frames use the volume. */
+  int32_t h_costs;
 } sgm_schedule;
+enum { SGM_HCOSTS_DEFAULT = 0, SGM_HCOSTS_VOLUME = 1, SGM_HCOSTS_CODES = 2 };
 
 /* Set the schedule used by sgm_submit for frames of the shape of `shape`
  * (width, height, max_disp, path_mask and the path-cost width it implies);
@@ -362,13 +373,14 @@ int sgm_get_schedule(sgm_ctx *ctx, const sgm_params *shape, sgm_schedule *s);
  * sgm_submit) under candidate schedules, `reps` timed repetitions each after
  * one warm-up, on one stream, and keep the fastest for the sample's shape (as
  * sgm_set_schedule); return it in *best (may be NULL).  The search is by
- * coordinates: h_lanes 16, 32, 64 (disp_threads 0); then, with the best
- * h_lanes, disp_threads 256, 512, 1024; then, for frames the single-pass
- * sweep can take, the sweep.  Blocks until done.  `ms`, if non-NULL,
- * receives per-candidate milliseconds for up to `n_ms` candidates in the
- * order h_lanes 16, 32, 64, disp_threads 256, 512, 1024, sweep (-1 where a
- * candidate does not apply).  Must not run concurrently with other
- * submissions on the same context. */
+ * coordinates: h_lanes 16, 32, 64 (disp_threads 0, h_costs from the
+ * volume); then, with the best h_lanes, horizontal costs from the Census
+ * codes where that applies; then disp_threads 256, 512, 1024; then, for
+ * frames the single-pass sweep can take, the sweep.  Blocks until done.
+ * `ms`, if non-NULL, receives per-candidate milliseconds for up to `n_ms`
+ * candidates in the order h_lanes 16, 32, 64, h_costs codes, disp_threads
+ * 256, 512, 1024, sweep (-1 where a candidate does not apply).  Must not run
+ * concurrently with other submissions on the same context. */
 int sgm_autotune(sgm_ctx *ctx, const sgm_frame *sample, int reps, sgm_schedule *best, float *ms,
                  int n_ms);
 

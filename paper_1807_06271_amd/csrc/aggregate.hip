@@ -80,16 +80,36 @@ constexpr uint32_t kInfPair = 0xFFFFFFFFu;
 // uint8 volume for SRC kCost8, four per word; the uint16 one for kCost16, two
 // per word).  Every lane reads its K cells with one vector load; cells with
 // d >= D hold unspecified values that the recurrence masks out.
-enum { kCost8 = 0, kCost16 = 1 };
+//
+// kSlide (horizontal scanlines of 64 lanes only): the costs are the Hamming
+// distances of the Census codes (equation (1)), formed in the wave.  The
+// wave holds the right-view codes x - d of all its disparities in registers
+// (lane j: codes x - jK - k, k < K) and slides that window by one code per
+// pixel, so a pixel needs only two codes from memory, the same for every
+// lane: the left-view code of x and the right-view code entering the window.
+// Its ring words are those two codes.
+enum { kCost8 = 0, kCost16 = 1, kSlide = 2 };
 
 template <int K, int SRC>
 struct CostWords {
-  static constexpr int N = SRC == kCost8 ? (K + 3) / 4 : K / 2;
+  static constexpr int N = SRC == kCost8 ? (K + 3) / 4 : SRC == kCost16 ? K / 2 : 4;
   uint32_t w[N];
 };
 
+// kSlide: p is the pixel's code record {left code, right code}; the code
+// entering the window lies rdelta bytes from p.
 template <int K, int SRC>
-__device__ __forceinline__ void load_cost(CostWords<K, SRC> &cw, const char *p) {
+__device__ __forceinline__ void load_cost(CostWords<K, SRC> &cw, const char *p, int32_t rdelta = 0) {
+  if constexpr (SRC == kSlide) {
+    const U32N<2> l = *reinterpret_cast<const U32N<2> *>(p);
+    const U32N<2> r = *reinterpret_cast<const U32N<2> *>(p + rdelta);
+    cw.w[0] = l.v[0];
+    cw.w[1] = l.v[1];
+    cw.w[2] = r.v[0];
+    cw.w[3] = r.v[1];
+    return;
+  }
+  (void)rdelta;
   if (SRC == kCost8 && K % 4 != 0) {  // K = 2 or 6: 2-byte aligned, one 16-bit load per pair
     const uint16_t *q = reinterpret_cast<const uint16_t *>(p);
 #pragma unroll
@@ -180,8 +200,34 @@ __device__ __forceinline__ void agg_wave(const AggJob &J, int slot, int wave_in_
   const int cpp = Dp;                        // cost elements per pixel (padded)
   const char *cbase = SRC == kCost8 ? reinterpret_cast<const char *>(J.cost8)
                                     : reinterpret_cast<const char *>(J.cost16);
-  const uint32_t coff = (uint32_t)((pix0 * cpp + dbase) * CB);
-  const int64_t cstep = HS ? (int64_t)HS * K * LPS * CB : step * cpp * CB;  // Dp = K * LPS
+  uint32_t coff = (uint32_t)((pix0 * cpp + dbase) * CB);
+  int64_t cstep = HS ? (int64_t)HS * K * LPS * CB : step * cpp * CB;  // Dp = K * LPS
+  // kSlide: the code records (16 bytes per pixel); the code entering the
+  // window is x's own right-view code (L->R) or that of x - Dp + 1 (R->L,
+  // which may lie left of the row: the records before row 0 are padding,
+  // and such codes only meet disparities whose cost is N_b anyway)
+  int32_t rdelta = 0;
+  uint32_t sc[2 * K] = {};  // the lane's window: codes x - dbase - k, k < K (lo, hi)
+  const uint32_t nbits = (uint32_t)J.nbits;
+  if constexpr (SRC == kSlide) {
+    static_assert(HS != 0 && LPS == 64, "sliding Census windows are for 64-lane horizontal scanlines");
+    cbase = reinterpret_cast<const char *>(J.codes);
+    coff = (uint32_t)(pix0 * 16);
+    cstep = (int64_t)HS * 16;
+    rdelta = HS > 0 ? 8 : -(Dp - 1) * 16 + 8;
+    if (HS < 0 && len > 0) {
+      // the window before the row's last pixel: codes W - dbase - k (the
+      // first slide moves them to W - 1 - dbase - k)
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        const int xr = min(max(W - dbase - k, 0), W - 1);
+        const U32N<2> c = *reinterpret_cast<const U32N<2> *>(cbase + ((int64_t)sy * W + xr) * 16 + 8);
+        sc[2 * k] = c.v[0];
+        sc[2 * k + 1] = c.v[1];
+      }
+    }
+  }
+  (void)nbits;
   char *obase = reinterpret_cast<char *>(J.lr) + (int64_t)slot * H * W * Dp * (int64_t)sizeof(LT);
   const uint32_t ooff = (uint32_t)((pix0 * Dp + dbase) * (int64_t)sizeof(LT));
   const int64_t ostep = HS ? (int64_t)HS * K * LPS * (int64_t)sizeof(LT) : step * Dp * (int64_t)sizeof(LT);
@@ -193,7 +239,7 @@ __device__ __forceinline__ void agg_wave(const AggJob &J, int slot, int wave_in_
   CostWords<K, SRC> ring[PF];
 #pragma unroll
   for (int s = 0; s < PF; ++s) {  // in ring order, which the waits in the loop assume
-    load_cost<K, SRC>(ring[s], cbase + min(s, last) * cstep + coff);
+    load_cost<K, SRC>(ring[s], cbase + min(s, last) * cstep + coff, rdelta);
     __builtin_amdgcn_sched_barrier(0);
   }
 
@@ -210,6 +256,53 @@ __device__ __forceinline__ void agg_wave(const AggJob &J, int slot, int wave_in_
     // keep each pixel's instructions together: hoisting the unpacking of
     // later pixels' costs would wait on loads issued one pixel ago
     __builtin_amdgcn_sched_barrier(0);
+    u16x2 Cs[NP];  // kSlide: the pixel's cost pairs
+    if constexpr (SRC == kSlide) {
+      // slide the window one code along the row: every code moves one
+      // disparity up (L->R) or down (R->L), across lanes by DPP, and the
+      // code entering at the window's end comes in as the DPP's old value
+      if constexpr (HS > 0) {
+        const uint32_t in_lo = (uint32_t)__builtin_amdgcn_update_dpp((int)rs.w[2], (int)sc[2 * K - 2],
+                                                                     kDppWaveShr1, 0xF, 0xF, false);
+        const uint32_t in_hi = (uint32_t)__builtin_amdgcn_update_dpp((int)rs.w[3], (int)sc[2 * K - 1],
+                                                                     kDppWaveShr1, 0xF, 0xF, false);
+#pragma unroll
+        for (int k = K - 1; k > 0; --k) {
+          sc[2 * k] = sc[2 * k - 2];
+          sc[2 * k + 1] = sc[2 * k - 1];
+        }
+        sc[0] = in_lo;
+        sc[1] = in_hi;
+      } else {
+        const uint32_t in_lo = (uint32_t)__builtin_amdgcn_update_dpp((int)rs.w[2], (int)sc[0], kDppWaveShl1,
+                                                                     0xF, 0xF, false);
+        const uint32_t in_hi = (uint32_t)__builtin_amdgcn_update_dpp((int)rs.w[3], (int)sc[1], kDppWaveShl1,
+                                                                     0xF, 0xF, false);
+#pragma unroll
+        for (int k = 0; k < K - 1; ++k) {
+          sc[2 * k] = sc[2 * k + 2];
+          sc[2 * k + 1] = sc[2 * k + 3];
+        }
+        sc[2 * K - 2] = in_lo;
+        sc[2 * K - 1] = in_hi;
+      }
+      // Hamming costs; right-view pixels left of the image cost N_b (only
+      // while x < Dp - 1, the same x for the whole wave)
+      const int x = sx + (GUARD ? min(i, last) : i) * HS;
+      const bool edge = x < Dp - 1;
+      uint32_t c[K];
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        c[k] = (uint32_t)__builtin_popcount(sc[2 * k] ^ rs.w[0]) + (uint32_t)__builtin_popcount(sc[2 * k + 1] ^ rs.w[1]);
+        if (edge) c[k] = x - dbase - k >= 0 ? c[k] : nbits;
+      }
+#pragma unroll
+      for (int q = 0; q < NP; ++q) Cs[q] = as_pair(c[2 * q] | c[2 * q + 1] << 16);
+    }
+    auto cost_of = [&](int q) -> u16x2 {
+      if constexpr (SRC == kSlide) return Cs[q];
+      else return cost_pair<K, SRC>(rs, q);
+    };
     u16x2 Lc[NP];
     if constexpr (NP == 1 && LPS >= 32) {
       // One pair per lane (the wide horizontal layouts, whose scanlines are
@@ -232,7 +325,7 @@ __device__ __forceinline__ void agg_wave(const AggJob &J, int slot, int wave_in_
       __builtin_amdgcn_sched_barrier(0);
       m = min(m, (uint32_t)__builtin_amdgcn_mov_dpp((int)m, kDppRowRor4, 0xF, 0xF, true));
       const u16x2 nb1 = as_pair(__builtin_amdgcn_alignbit(next, l0, 16));
-      const u16x2 c0 = cost_pair<K, SRC>(rs, 0);
+      const u16x2 c0 = cost_of(0);
       __builtin_amdgcn_sched_barrier(0);
       m = min(m, (uint32_t)__builtin_amdgcn_mov_dpp((int)m, kDppRowRor2, 0xF, 0xF, true));
       u16x2 a = pmin(nb0, nb1);
@@ -294,13 +387,13 @@ __device__ __forceinline__ void agg_wave(const AggJob &J, int slot, int wave_in_
       const u16x2 MP2 = padd_sat(M, P2);
 #pragma unroll
       for (int q = 0; q < NP; ++q) {
-        u16x2 v = pmin(A[q], MP2) - M + cost_pair<K, SRC>(rs, q);
+        u16x2 v = pmin(A[q], MP2) - M + cost_of(q);
         if (PAD) v = as_pair(as_u32(v) | padmask[q]);
         Lc[q] = v;
       }
     }
     // the slot's costs are used: refill it PF pixels ahead
-    load_cost<K, SRC>(rs, cbase + (int64_t)(GUARD ? min(i + PF, last) : i + PF) * cstep + coff);
+    load_cost<K, SRC>(rs, cbase + (int64_t)(GUARD ? min(i + PF, last) : i + PF) * cstep + coff, rdelta);
     if (!GUARD || i < len) {
       char *o = obase + (int64_t)i * ostep + ooff;
       if (sizeof(LT) == 1) {
@@ -350,7 +443,9 @@ __host__ __device__ inline int lanes_per_scanline(int dir, int hlps) { return di
 // Each wave finds its job and direction slot, then runs that direction's
 // scanlines with the lane layout of the schedule: KH disparities per lane
 // over HLPS lanes for horizontal paths, K over 16 lanes for the others.
-template <int K, int KH, int HLPS, int SRC, typename LT, int PF, bool PAD>
+// HSRC: the cost source of the horizontal waves (SRC, or kSlide with
+// 64-lane horizontal scanlines).
+template <int K, int KH, int HLPS, int SRC, typename LT, int PF, bool PAD, int HSRC = SRC>
 __global__ __launch_bounds__(256) void agg_kernel(JobTable<AggJob> t) {
   const int gw = uniform((int)(blockIdx.x * 4 + (threadIdx.x >> 6)));  // global wave
   const int ji = find_job(t.j, t.n, gw);
@@ -362,24 +457,28 @@ __global__ __launch_bounds__(256) void agg_kernel(JobTable<AggJob> t) {
     if (w >= J.line0[k]) slot = k;
   const int wave_in_slot = w - J.line0[slot];
   // Wider lane groups finish a pixel in fewer instructions, so they prefetch
-  // proportionally further ahead to cover the same memory latency.
+  // proportionally further ahead to cover the same memory latency; a sliding
+  // window's ring slot is four words, so it keeps eight pixels in flight.
+  constexpr int PFH = HSRC == kSlide ? 8 : PF * HLPS / 16;
   const int dir = J.dirs[slot];
   if (dir == 0)
-    agg_wave<KH, HLPS, SRC, LT, PF * HLPS / 16, PAD, +1>(J, slot, wave_in_slot);
+    agg_wave<KH, HLPS, HSRC, LT, PFH, PAD, +1>(J, slot, wave_in_slot);
   else if (dir == 1)
-    agg_wave<KH, HLPS, SRC, LT, PF * HLPS / 16, PAD, -1>(J, slot, wave_in_slot);
+    agg_wave<KH, HLPS, HSRC, LT, PFH, PAD, -1>(J, slot, wave_in_slot);
   else
     agg_wave<K, 16, SRC, LT, PF, PAD, 0>(J, slot, wave_in_slot);
 }
 
-template <int K, int KH, int HLPS, int SRC, typename LT>
+template <int K, int KH, int HLPS, int SRC, typename LT, int HSRC = SRC>
 static void launch_one(const JobTable<AggJob> &t, int waves, hipStream_t s) {
   constexpr int PF = SRC == kCost8 || K <= 8 ? 8 : 4;
   const int blocks = (waves + 3) / 4;
   bool pad = false;  // some frame's D is not a multiple of 16*K: mask the tail lanes
   for (int i = 0; i < t.n; ++i) pad |= t.j[i].D != 16 * K;
-  if (pad) hipLaunchKernelGGL((agg_kernel<K, KH, HLPS, SRC, LT, PF, true>), dim3(blocks), dim3(256), 0, s, t);
-  else hipLaunchKernelGGL((agg_kernel<K, KH, HLPS, SRC, LT, PF, false>), dim3(blocks), dim3(256), 0, s, t);
+  if (pad)
+    hipLaunchKernelGGL((agg_kernel<K, KH, HLPS, SRC, LT, PF, true, HSRC>), dim3(blocks), dim3(256), 0, s, t);
+  else
+    hipLaunchKernelGGL((agg_kernel<K, KH, HLPS, SRC, LT, PF, false, HSRC>), dim3(blocks), dim3(256), 0, s, t);
 }
 
 // Lanes per horizontal scanline available for a disparity width K (16 lanes):
@@ -390,8 +489,16 @@ bool agg_hlps_ok(int K, int hlps) {
   return (hlps == 32 || hlps == 64) && kh >= 2 && kh % 2 == 0;
 }
 
+// Horizontal costs from sliding Census windows: 64-lane rows with two or
+// four disparities per lane (D in (64, 128] or (192, 256]), uint8 volumes.
+bool agg_slide_ok(int K, int hlps) { return hlps == 64 && (K == 8 || K == 16); }
+
 template <int SRC, typename LT>
-static void launch_k(int K, int hlps, const JobTable<AggJob> &t, int waves, hipStream_t s) {
+static void launch_k(int K, int hlps, bool slide, const JobTable<AggJob> &t, int waves, hipStream_t s) {
+  if constexpr (SRC == kCost8 && std::is_same<LT, uint8_t>::value) {
+    if (slide && K == 8 && hlps == 64) return launch_one<8, 2, 64, SRC, LT, kSlide>(t, waves, s);
+    if (slide && K == 16 && hlps == 64) return launch_one<16, 4, 64, SRC, LT, kSlide>(t, waves, s);
+  }
   switch (K * 100 + hlps) {
     case 416: launch_one<4, 4, 16, SRC, LT>(t, waves, s); break;
     case 432: launch_one<4, 2, 32, SRC, LT>(t, waves, s); break;
@@ -406,9 +513,10 @@ static void launch_k(int K, int hlps, const JobTable<AggJob> &t, int waves, hipS
   }
 }
 
-void launch_aggregate(std::vector<AggJob> jobs, bool from_cost16, int K, int hlps, int lr_bytes,
+void launch_aggregate(std::vector<AggJob> jobs, bool from_cost16, int K, int hlps, int lr_bytes, bool slide,
                       hipStream_t s) {
   if (!agg_hlps_ok(K, hlps)) hlps = 16;
+  slide = slide && !from_cost16 && lr_bytes == 1 && agg_slide_ok(K, hlps);
   for (auto &j : jobs) {
     int total = 0;
     for (int k = 0; k < j.ndirs; ++k) {
@@ -422,11 +530,11 @@ void launch_aggregate(std::vector<AggJob> jobs, bool from_cost16, int K, int hlp
       jobs, [](const AggJob &j) { return (long)j.line0[j.ndirs]; },
       [&](const JobTable<AggJob> &t, int waves) {
         if (!from_cost16) {
-          if (lr_bytes == 1) launch_k<kCost8, uint8_t>(K, hlps, t, waves, s);
-          else launch_k<kCost8, uint16_t>(K, hlps, t, waves, s);
+          if (lr_bytes == 1) launch_k<kCost8, uint8_t>(K, hlps, slide, t, waves, s);
+          else launch_k<kCost8, uint16_t>(K, hlps, false, t, waves, s);
         } else {
-          if (lr_bytes == 1) launch_k<kCost16, uint8_t>(K, hlps, t, waves, s);
-          else launch_k<kCost16, uint16_t>(K, hlps, t, waves, s);
+          if (lr_bytes == 1) launch_k<kCost16, uint8_t>(K, hlps, false, t, waves, s);
+          else launch_k<kCost16, uint16_t>(K, hlps, false, t, waves, s);
         }
       });
 }

@@ -41,6 +41,9 @@ int fail(int code, const char *fmt, ...) {
 
 int popcount8(uint32_t m) { return __builtin_popcount(m & 0xFFu); }
 
+// Horizontal cost source of shapes without a tuned or context schedule.
+constexpr int kDefaultHCosts = SGM_HCOSTS_VOLUME;
+
 int validate(const sgm_params *p) {
   if (!p) return fail(SGM_EINVAL, "params is null");
   if (p->width < 1 || p->height < 1 || p->width > 16384 || p->height > 16384)
@@ -275,16 +278,21 @@ int check_dev_ptr(const void *ptr, int dev, const char *name) {
 // ------------------------------------------------------ whole-frame plan
 
 struct FramePlan {
-  size_t off_cost, off_lr, off_dlr, off_dl, off_part, bytes;
+  size_t off_cost, off_lr, off_dlr, off_dl, off_part, off_codes, bytes;
 };
 
 // Scratch of one frame of a batch: the padded uint8 cost volume, the P
 // padded path-cost volumes and the LR-checked map before the median.
-FramePlan plan_frame(const sgm_params &p, size_t base, bool sweep) {
+// Bytes of the Census code records of sliding horizontal windows: 16 per
+// pixel plus Dp records of padding before the first.
+size_t code_records_bytes(const sgm_params &p) { return ((size_t)p.width * p.height + dp_of(p)) * 16; }
+
+FramePlan plan_frame(const sgm_params &p, size_t base, bool sweep, bool codes) {
   const size_t px = (size_t)p.width * p.height;
   const size_t dp = (size_t)dp_of(p);
   FramePlan f;
   f.off_cost = base;
+  f.off_codes = 0;
   if (sweep) {
     // Census codes of both views; D_L and D_R; the band-boundary carry rows;
     // the LR-checked map before the median
@@ -301,6 +309,10 @@ FramePlan plan_frame(const sgm_params &p, size_t base, bool sweep) {
   f.off_dl = f.off_dlr + align256(px * 2);
   f.off_part = f.off_dl + align256(px * 2);
   f.bytes = f.off_part + align256(disp_part_bytes(p.width, p.height, p.max_disp)) - base;
+  if (codes) {
+    f.off_codes = base + f.bytes;
+    f.bytes += align256(code_records_bytes(p));
+  }
   return f;
 }
 
@@ -340,6 +352,25 @@ int resolve_sweep(const sgm_ctx *c, const sgm_params &p) {
   auto it = c->tuned.find(shape_key(p));
   const int want = it != c->tuned.end() ? it->second.sweep : c->dflt.sweep;
   return want && sweep_ok(p) ? 1 : 0;
+}
+
+// Horizontal costs from sliding Census windows: Census cost with uint8
+// volumes, a 64-lane horizontal layout of 2 or 4 disparities per lane, and
+// code records whose byte offsets fit 31 bits.
+bool hcodes_ok(const sgm_params &p, int hlps) {
+  return !is_sad(p) && lr_bytes_of(p) == 1 && agg_slide_ok(k_of(p), hlps) &&
+         code_records_bytes(p) < ((size_t)1 << 31);
+}
+
+// SGM_HCOSTS_CODES or SGM_HCOSTS_VOLUME for a frame with `hlps` horizontal
+// lanes: the tuned entry for its shape, else the context default, else the
+// library's default.
+int resolve_hcosts(const sgm_ctx *c, const sgm_params &p, int hlps) {
+  auto it = c->tuned.find(shape_key(p));
+  int want = it != c->tuned.end() ? it->second.h_costs : SGM_HCOSTS_DEFAULT;
+  if (want == SGM_HCOSTS_DEFAULT) want = c->dflt.h_costs;
+  if (want == SGM_HCOSTS_DEFAULT) want = kDefaultHCosts;
+  return want == SGM_HCOSTS_CODES && hcodes_ok(p, hlps) ? SGM_HCOSTS_CODES : SGM_HCOSTS_VOLUME;
 }
 
 // Disparity-selection block size for a frame (0: by the launch's block count).
@@ -396,8 +427,8 @@ std::string composition_key(const sgm_frame *fr, int n, const std::vector<int> &
     // argument layouts
     snprintf(buf, sizeof buf, "%d,%d,%d,%d,%d,%u,%u,%u,%d,%d,%d,%u,%u,%d,%d,%d;", p.width, p.height,
              p.max_disp, p.census_w, p.census_h, p.path_mask, p.p1, p.p2, p.lr_check, p.lr_max_diff,
-             p.median, p.invalid, p.cost, lr_bytes_of(p), hlps[i] | sweep[i] << 8, fr[i].umap ? 1 : 0);
-    // (hlps carries the disparity block size above bit 16)
+             p.median, p.invalid, p.cost, lr_bytes_of(p), hlps[i] | sweep[i] << 12, fr[i].umap ? 1 : 0);
+    // (hlps carries the horizontal cost source and the disparity block size)
     k += buf;
   }
   return k;
@@ -410,7 +441,8 @@ int check_schedule(const sgm_schedule *s) {
   if (s->sweep != 0 && s->sweep != 1) return fail(SGM_EINVAL, "sweep must be 0 or 1 (got %d)", s->sweep);
   if (s->disp_threads != 0 && s->disp_threads != 256 && s->disp_threads != 512 && s->disp_threads != 1024)
     return fail(SGM_EINVAL, "disp_threads must be 0, 256, 512 or 1024 (got %d)", s->disp_threads);
-  if (s->reserved) return fail(SGM_EINVAL, "reserved must be 0");
+  if (s->h_costs < SGM_HCOSTS_DEFAULT || s->h_costs > SGM_HCOSTS_CODES)
+    return fail(SGM_EINVAL, "h_costs must be 0, 1 or 2 (got %d)", s->h_costs);
   return SGM_OK;
 }
 
@@ -499,6 +531,8 @@ int enqueue_frames(const sgm_frame *fr, int n, const std::vector<FramePlan> &pla
     j.nbits = nbits_of(p);
     j.cw = p.census_w;
     j.ch = p.census_h;
+    if (hlps[i] & (1 << 8))  // the records start after Dp padding records
+      j.codes = reinterpret_cast<uint64_t *>(mem + plans[i].off_codes) + 2 * (size_t)dp_of(p);
     fj.push_back(j);
   }
   CHECK(mark.begin(SGM_STAGE_CENSUS));
@@ -526,13 +560,18 @@ int enqueue_frames(const sgm_frame *fr, int n, const std::vector<FramePlan> &pla
   for (int sad = 0; sad <= 1; ++sad)
   for (int K : {4, 8, 12, 16})
     for (int lb = 1; lb <= 2; ++lb)
-    for (int c_hlps : {16, 32, 64}) {
+    for (int c_hlps : {16, 32, 64})
+    for (int slide = 0; slide <= 1; ++slide) {
       std::vector<AggJob> aj;
       for (int i = 0; i < n; ++i) {
         const sgm_params &p = fr[i].p;
         if (sweep[i] || (int)is_sad(p) != sad || k_of(p) != K || lr_bytes_of(p) != lb) continue;
-        if ((hlps[i] & 0xFFFF) != c_hlps) continue;
+        if ((hlps[i] & 0xFF) != c_hlps || ((hlps[i] >> 8) & 1) != slide) continue;
         AggJob j{};
+        if (slide) {
+          j.codes = reinterpret_cast<const uint64_t *>(mem + plans[i].off_codes) + 2 * (size_t)dp_of(p);
+          j.nbits = nbits_of(p);
+        }
         if (sad) j.cost16 = reinterpret_cast<const uint16_t *>(mem + plans[i].off_cost);
         else j.cost8 = reinterpret_cast<const uint8_t *>(mem + plans[i].off_cost);
         j.lr = mem + plans[i].off_lr;
@@ -546,7 +585,7 @@ int enqueue_frames(const sgm_frame *fr, int n, const std::vector<FramePlan> &pla
         aj.push_back(j);
       }
       if (!aj.empty()) {
-        launch_aggregate(aj, sad != 0, K, c_hlps, lb, s);
+        launch_aggregate(aj, sad != 0, K, c_hlps, lb, slide != 0, s);
         CHECK(check_launch());
         ++groups;
       }
@@ -1022,7 +1061,7 @@ int sgm_aggregate(sgm_ctx *c, const sgm_params *p, const uint16_t *cost, uint16_
   j.p1 = p->p1;
   j.p2 = p->p2;
   j.ndirs = fill_dirs(p->path_mask, j.dirs);
-  launch_aggregate({j}, true, k_of(*p), resolve_hlps(c, *p), lb, s);
+  launch_aggregate({j}, true, k_of(*p), resolve_hlps(c, *p), lb, false, s);
   CHECK(check_launch());
   SumJob sj{};
   sj.lr = lr;
@@ -1170,10 +1209,13 @@ static int submit_impl(sgm_ctx *c, const sgm_frame *frames, const sgm_remap *rem
   std::vector<FramePlan> plans(n);
   size_t total = 0;
   for (int i = 0; i < n; ++i) {
-    // lanes per horizontal scanline, with the disparity block size above bit 16
-    hl[i] = resolve_hlps(c, frames[i].p) | resolve_disp_threads(c, frames[i].p) << 16;
+    // lanes per horizontal scanline (low byte), horizontal costs from codes
+    // (bit 8), the disparity block size (above bit 16)
+    const int h = resolve_hlps(c, frames[i].p);
     sw[i] = resolve_sweep(c, frames[i].p);
-    plans[i] = plan_frame(frames[i].p, total, sw[i] != 0);
+    const bool codes = !sw[i] && resolve_hcosts(c, frames[i].p, h) == SGM_HCOSTS_CODES;
+    hl[i] = h | (codes ? 1 << 8 : 0) | resolve_disp_threads(c, frames[i].p) << 16;
+    plans[i] = plan_frame(frames[i].p, total, sw[i] != 0, codes);
     total += plans[i].bytes;
   }
   DeviceGuard g(c->device);
@@ -1382,6 +1424,7 @@ int sgm_get_schedule(sgm_ctx *c, const sgm_params *shape, sgm_schedule *sc) {
   sc->h_lanes = resolve_hlps(c, *shape);
   sc->sweep = resolve_sweep(c, *shape);
   sc->disp_threads = resolve_disp_threads(c, *shape);
+  sc->h_costs = sc->sweep ? SGM_HCOSTS_VOLUME : resolve_hcosts(c, *shape, sc->h_lanes);
   return SGM_OK;
 }
 
@@ -1440,7 +1483,7 @@ int sgm_autotune(sgm_ctx *c, const sgm_frame *sample, int reps, sgm_schedule *be
   if (!c || !sample) return fail(SGM_EINVAL, "ctx and sample must be non-null");
   if (reps < 1) return fail(SGM_EINVAL, "reps must be >= 1");
   CHECK(validate(&sample->p));
-  constexpr int kCands = 7;  // h_lanes 16, 32, 64; disp_threads 256, 512, 1024; sweep
+  constexpr int kCands = 8;  // h_lanes 16, 32, 64; h_costs codes; disp_threads 256, 512, 1024; sweep
   float times[kCands];
   for (float &t : times) t = -1.f;
   sgm_schedule win{};
@@ -1461,21 +1504,28 @@ int sgm_autotune(sgm_ctx *c, const sgm_frame *sample, int reps, sgm_schedule *be
     if (!agg_hlps_ok(k_of(sample->p), lanes[ci])) continue;
     sgm_schedule sc{};
     sc.h_lanes = lanes[ci];
+    sc.h_costs = SGM_HCOSTS_VOLUME;
     CHECK(consider(ci, sc));
   }
-  // 2. disparity-selection block size, with the best lane layout
+  // 2. horizontal costs from sliding Census windows, with the best layout
+  if (hcodes_ok(sample->p, win.h_lanes)) {
+    sgm_schedule sc = win;
+    sc.h_costs = SGM_HCOSTS_CODES;
+    CHECK(consider(3, sc));
+  }
+  // 3. disparity-selection block size
   const int threads[3] = {256, 512, 1024};
   const sgm_schedule base = win;
   for (int ci = 0; ci < 3; ++ci) {
     sgm_schedule sc = base;
     sc.disp_threads = threads[ci];
-    CHECK(consider(3 + ci, sc));
+    CHECK(consider(4 + ci, sc));
   }
-  // 3. the single-pass sweep, for frames it can take
+  // 4. the single-pass sweep, for frames it can take
   if (sweep_ok(sample->p)) {
     sgm_schedule sc = win;
     sc.sweep = 1;
-    CHECK(consider(6, sc));
+    CHECK(consider(7, sc));
   }
   CHECK(sgm_set_schedule(c, &sample->p, &win));
   if (best) *best = win;

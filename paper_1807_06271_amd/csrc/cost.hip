@@ -128,6 +128,12 @@ __global__ __launch_bounds__(256) void census_cost_kernel(JobTable<FusedCostJob>
     if (i < nx) codeL[i] = census_at(rowsL, sl, i, J.cw, J.ch);
   }
   __syncthreads();
+  if (J.codes) {  // the segment's code records {left, right}, for sliding horizontal windows
+    for (int i = threadIdx.x; i < nx; i += blockDim.x) {
+      const uint64_t rec[2] = {codeL[i], codeR[swz(x0 + i - xr0)]};
+      *reinterpret_cast<U32N<4> *>(J.codes + 2 * ((int64_t)y * W + x0 + i)) = *reinterpret_cast<const U32N<4> *>(rec);
+    }
+  }
   // each thread keeps one 4-disparity group q of the padded row and walks
   // the segment 4 pixels at a time: the 16 cells of pixels x..x+3 and
   // disparities d0..d0+3 use the 7 right-view codes x-d0-3 .. x-d0+3

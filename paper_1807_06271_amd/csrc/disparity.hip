@@ -25,7 +25,21 @@
 
 namespace sgmk {
 
-__device__ __forceinline__ int kswz(int i) { return i + (i >> 3); }
+// LDS slot of the right-view key of zone position i.  The 16 lanes of a
+// 16-lane row update positions K apart (one disparity each) and the rows of
+// a wave handle consecutive pixels, i.e. positions one apart.  With two
+// padding slots after every K positions (K a power of two) the lanes of a
+// row land on 16 banks that are all even or all odd, and the next row's on
+// the other 16, so a half wave (two rows) updates 32 different banks; a K
+// boundary between two rows' positions shifts by 2 and keeps the parity.
+template <int K>
+__host__ __device__ constexpr int kswz(int i) {
+  if constexpr ((K & (K - 1)) == 0) return i + 2 * (i / K);
+  else return i + (i >> 3);
+}
+// LDS slots for n zone positions.
+template <int K>
+__host__ __device__ constexpr int kswz_slots(int n) { return n > 0 ? kswz<K>(n - 1) + 1 : 1; }
 
 // Raw words of one pixel for one lane: IN 0 = K values of the caller's S
 // (one per word); IN 1 = K bytes of each of the P (<= 8) uint8 path-cost
@@ -147,11 +161,10 @@ __global__ __launch_bounds__(THREADS) void disp_kernel(JobTable<DispJob> t) {
   const int W = J.W, D = J.D;
   const int xa = sgi * J.seglen, xe = min(W, xa + J.seglen);  // the segment [xa, xe)
   const int zr = xa - D + 1, zn = xe - zr;                     // its right-view zone
-  // D_R keys of zone slot i live at kswz(i) = i + i/8: a row's lanes update
-  // slots K apart, and the padding spreads them over the LDS banks
-  uint32_t *keyR = smem;  // [kswz(zn)]
+  // D_R keys of zone position i live at kswz<K>(i)
+  uint32_t *keyR = smem;  // [kswz_slots<K>(zn)]
   if (J.lr_check)
-    for (int i = threadIdx.x; i < zn + zn / 8 + 1; i += blockDim.x) keyR[i] = 0xFFFFFFFFu;
+    for (int i = threadIdx.x; i < kswz_slots<K>(zn); i += blockDim.x) keyR[i] = 0xFFFFFFFFu;
   __syncthreads();
   const int j = threadIdx.x & 15;
   const int dbase = j * K;
@@ -184,7 +197,7 @@ __global__ __launch_bounds__(THREADS) void disp_kernel(JobTable<DispJob> t) {
           const int d = dbase + k;
           const uint32_t key = (S[k] << 8) | (uint32_t)d;
           best = min(best, key);
-          if (J.lr_check && x >= d) atomicMin(&keyR[kswz(x - d - zr)], key);
+          if (J.lr_check && x >= d) atomicMin(&keyR[kswz<K>(x - d - zr)], key);
         }
       }
       best = row16_allmin_u32(best);
@@ -196,7 +209,7 @@ __global__ __launch_bounds__(THREADS) void disp_kernel(JobTable<DispJob> t) {
   if (!J.lr_check) return;
   __syncthreads();
   uint32_t *part = J.part + ((int64_t)y * J.nseg + sgi) * (J.seglen + D - 1);
-  for (int i = threadIdx.x; i < zn; i += blockDim.x) part[i] = keyR[kswz(i)];
+  for (int i = threadIdx.x; i < zn; i += blockDim.x) part[i] = keyR[kswz<K>(i)];
 }
 
 // Left-right check (section 3.1.4): D_R(x_r) is the smallest key over the
@@ -272,7 +285,9 @@ void launch_disparity(std::vector<DispJob> jobs, int in_kind, hipStream_t s) {
           maxz = std::max(maxz, std::min(j.W, j.seglen) + j.D - 1);
         }
       if (sub.empty()) continue;
-      const size_t lds = (size_t)(maxz + maxz / 8 + 1) * 4;
+      const int slots = K == 4 ? kswz_slots<4>(maxz) : K == 8 ? kswz_slots<8>(maxz)
+                        : K == 12 ? kswz_slots<12>(maxz) : kswz_slots<16>(maxz);
+      const size_t lds = (size_t)slots * 4;
       for_each_table(
           sub, [](const DispJob &j) { return (long)j.H * j.nseg; },
           [&](const JobTable<DispJob> &t, int blocks) {

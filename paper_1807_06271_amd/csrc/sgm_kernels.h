@@ -46,6 +46,7 @@ struct FusedCostJob {
   const uint8_t *left, *right;
   int64_t pitch;
   uint8_t *out8;    // [H][W][Dp]
+  uint64_t *codes;  // or null: the Census code records {left, right} per pixel [H][W]
   int W, H, D, Dp, nbits, cw, ch;
   int blk0;
 };
@@ -75,6 +76,10 @@ __host__ __device__ int agg_lines(int dir, int W, int H);
 struct AggJob {
   const uint8_t *cost8;          // internal padded uint8 costs [H][W][Dp], or
   const uint16_t *cost16;        // internal padded uint16 costs [H][W][Dp]
+  const uint64_t *codes;         // sliding horizontal windows: Census code records
+                                 // {left, right} per pixel [H][W], Dp readable
+                                 // records before the first one
+  int nbits;                     // N_b (sliding windows)
   void *lr;                      // path costs [P][H][W][Dp], uint8 or uint16
   int W, H, D, Dp, p1, p2;
   int ndirs;                     // P = number of active directions
@@ -83,10 +88,14 @@ struct AggJob {
   int blk0;                      // first global wave of this job
 };
 // K = agg_k(D) of every job; hlps: lanes per horizontal scanline (16, 32 or
-// 64; falls back to 16 where the layout does not fit K); lr_bytes: 1 or 2.
-void launch_aggregate(std::vector<AggJob> jobs, bool from_cost16, int K, int hlps, int lr_bytes,
+// 64; falls back to 16 where the layout does not fit K); lr_bytes: 1 or 2;
+// slide: the horizontal waves form their costs from the jobs' Census code
+// records (where agg_slide_ok holds and the volumes are uint8; ignored
+// elsewhere).
+void launch_aggregate(std::vector<AggJob> jobs, bool from_cost16, int K, int hlps, int lr_bytes, bool slide,
                       hipStream_t s);
 bool agg_hlps_ok(int K, int hlps);
+bool agg_slide_ok(int K, int hlps);
 // Copy uint16 costs [px][D] into the padded layout [px][Dp] (pad cells 0).
 void launch_pad16(const uint16_t *src, uint16_t *dst, int64_t px, int D, int Dp, hipStream_t s);
 

@@ -31,6 +31,7 @@ PATHS_PAPER4 = PATH_L2R | PATH_TL2BR | PATH_T2B | PATH_TR2BL
 PATHS_HV4 = PATH_L2R | PATH_R2L | PATH_T2B | PATH_B2T
 PATHS_ALL8 = 0xFF
 COST_CENSUS, COST_SAD = 0, 1
+HCOSTS_DEFAULT, HCOSTS_VOLUME, HCOSTS_CODES = 0, 1, 2
 
 EXPORTS = ["sgm_validate", "sgm_create", "sgm_destroy", "sgm_last_error", "sgm_census", "sgm_cost",
            "sgm_cost_sad",
@@ -60,7 +61,7 @@ class sgm_params(ctypes.Structure):
 
 class sgm_schedule(ctypes.Structure):
     _fields_ = [("h_lanes", ctypes.c_int32), ("sweep", ctypes.c_int32), ("disp_threads", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("h_costs", ctypes.c_int32)]
 
 
 class sgm_remap(ctypes.Structure):
@@ -460,11 +461,12 @@ def sgm_memory(ctx: Context):
 
 
 def sgm_set_schedule(ctx: Context, p: Params | None, h_lanes: int, sweep: bool = False,
-                     disp_threads: int = 0) -> None:
+                     disp_threads: int = 0, h_costs: int = HCOSTS_DEFAULT) -> None:
     """Schedule for frames of p's shape (p=None: the default): lanes per
     horizontal scanline, whether eligible frames use the single-pass sweep,
-    and the disparity-selection block size (0: by block count)."""
-    sc = sgm_schedule(h_lanes, int(bool(sweep)), int(disp_threads))
+    the disparity-selection block size (0: by block count), and where the
+    horizontal scanlines take their costs from (HCOSTS_*)."""
+    sc = sgm_schedule(h_lanes, int(bool(sweep)), int(disp_threads), int(h_costs))
     _check(lib().sgm_set_schedule(ctx.handle, ctypes.byref(p.c()) if p is not None else None,
                                   ctypes.byref(sc)), "sgm_set_schedule")
 
@@ -475,29 +477,30 @@ def sgm_get_schedule(ctx: Context, p: Params) -> int:
 
 
 def schedule_of(ctx: Context, p: Params):
-    """(h_lanes, sweep, disp_threads) that sgm_submit would use for frames
-    like p."""
+    """(h_lanes, sweep, disp_threads, h_costs) that sgm_submit would use for
+    frames like p."""
     sc = sgm_schedule()
     _check(lib().sgm_get_schedule(ctx.handle, ctypes.byref(p.c()), ctypes.byref(sc)), "sgm_get_schedule")
-    return sc.h_lanes, bool(sc.sweep), sc.disp_threads
+    return sc.h_lanes, bool(sc.sweep), sc.disp_threads, sc.h_costs
 
 
-AUTOTUNE_CANDIDATES = ("h_lanes=16", "h_lanes=32", "h_lanes=64", "disp_threads=256", "disp_threads=512",
-                       "disp_threads=1024", "sweep")
+AUTOTUNE_CANDIDATES = ("h_lanes=16", "h_lanes=32", "h_lanes=64", "h_costs=codes", "disp_threads=256",
+                       "disp_threads=512", "disp_threads=1024", "sweep")
 
 
 def sgm_autotune(ctx: Context, sample: "Frame", reps: int = 5):
     """Time the candidate schedules on `sample` (lanes per horizontal
-    scanline; then the disparity block size; then the sweep where it
-    applies) and keep the fastest for its shape.  Returns (schedule,
-    {candidate: ms per frame}) with schedule = {"h_lanes", "sweep",
-    "disp_threads"}."""
+    scanline; horizontal costs from Census codes where that applies; the
+    disparity block size; the sweep where it applies) and keep the fastest
+    for its shape.  Returns (schedule, {candidate: ms per frame}) with
+    schedule = {"h_lanes", "sweep", "disp_threads", "h_costs"}."""
     best = sgm_schedule()
     n = len(AUTOTUNE_CANDIDATES)
     ms = (ctypes.c_float * n)()
     f = sample.c()
     _check(lib().sgm_autotune(ctx.handle, ctypes.byref(f), reps, ctypes.byref(best), ms, n), "sgm_autotune")
-    sched = {"h_lanes": best.h_lanes, "sweep": bool(best.sweep), "disp_threads": best.disp_threads}
+    sched = {"h_lanes": best.h_lanes, "sweep": bool(best.sweep), "disp_threads": best.disp_threads,
+             "h_costs": "codes" if best.h_costs == HCOSTS_CODES else "volume"}
     return sched, {name: ms[i] for i, name in enumerate(AUTOTUNE_CANDIDATES) if ms[i] >= 0}
 
 

@@ -53,6 +53,58 @@ def test_every_lane_layout_matches_oracle(env, shape, h_lanes):
     assert_equal(to_np(f.vmap), want["vmap"], "vmap")
 
 
+# shapes whose horizontal scanlines can form their costs from Census codes
+# (64 lanes, 2 or 4 disparities per lane): W, H, D, census, mask, p1, p2
+HCODE_SHAPES = [
+    (203, 61, 128, (9, 7), 0xFF, 10, 120),
+    (97, 33, 256, (9, 7), 0x03, 10, 120),
+    (140, 37, 100, (9, 7), 0xFF, 10, 120),   # padded disparity rows
+    (300, 20, 250, (9, 7), 0x03, 10, 120),   # padded, D = 250
+    (64, 40, 128, (5, 5), 0x03, 10, 120),    # narrower than D: every pixel near the left border
+    (1, 3, 256, (9, 7), 0x03, 10, 120),
+    (257, 9, 200, (7, 7), 0x02, 7, 90),      # right to left alone
+    (1500, 4, 128, (9, 7), 0x01, 10, 120),   # left to right alone, long rows
+]
+
+
+@pytest.mark.parametrize("shape", HCODE_SHAPES)
+def test_horizontal_costs_from_census_codes_match_oracle(env, shape):
+    torch, sgm, ctx = env
+    W, H, D, (cw, ch), mask, p1, p2 = shape
+    announce("horizontal costs from codes", shape)
+    left, right, _ = synthetic.make_pair("kitti", W + 3 * D + mask, W, H, D)
+    p = sgm.Params(width=W, height=H, max_disp=D, census_w=cw, census_h=ch, path_mask=mask, p1=p1, p2=p2,
+                   invalid=65535 if D == 256 else 255)
+    sgm.sgm_set_schedule(ctx, p, 64, h_costs=sgm.HCOSTS_CODES)
+    assert sgm.schedule_of(ctx, p)[3] == sgm.HCOSTS_CODES
+    f = sgm.Frame.alloc(p, to_dev(torch, left), to_dev(torch, right))
+    sgm.sgm_wait(ctx, sgm.sgm_submit(ctx, [f]))
+    want = O.sgm(left, right, D, cw, ch, mask, p1, p2, True, 1, 3, p.inv())
+    assert_equal(to_np(f.disp), want["disp"], "disp")
+    assert_equal(to_np(f.umap), want["umap"], "umap")
+    assert_equal(to_np(f.vmap), want["vmap"], "vmap")
+
+
+def test_horizontal_code_costs_fall_back_where_they_do_not_apply(env):
+    # 32 lanes, D = 64 (one disparity per lane pair), 16-bit path costs, SAD:
+    # the horizontal scanlines read the cost volume whatever the schedule says
+    torch, sgm, ctx = env
+    announce("horizontal costs fallback")
+    for kw in (dict(width=120, height=30, max_disp=128), dict(width=120, height=30, max_disp=64),
+               dict(width=120, height=30, max_disp=128, p2=300),
+               dict(width=120, height=30, max_disp=128, census_w=5, census_h=5, cost=sgm.COST_SAD, p1=200, p2=800)):
+        p = sgm.Params(**kw)
+        h = 32 if kw["max_disp"] == 128 and "p2" not in kw and "cost" not in kw else 64
+        sgm.sgm_set_schedule(ctx, p, h, h_costs=sgm.HCOSTS_CODES)
+        assert sgm.schedule_of(ctx, p)[3] == sgm.HCOSTS_VOLUME, kw
+        left, right, _ = synthetic.make_pair("kitti", 61, p.width, p.height, p.max_disp)
+        f = sgm.Frame.alloc(p, to_dev(torch, left), to_dev(torch, right))
+        sgm.sgm_wait(ctx, sgm.sgm_submit(ctx, [f]))
+        want = O.sgm(left, right, p.max_disp, p.census_w, p.census_h, p.path_mask, p.p1, p.p2, True, 1, 3,
+                     cost_kind=p.cost)
+        assert_equal(to_np(f.disp), want["disp"], "disp %s" % kw)
+
+
 @pytest.mark.parametrize("shape", SAD_SHAPES)
 @pytest.mark.parametrize("h_lanes", [16, 32, 64])
 def test_every_lane_layout_matches_oracle_sad(env, shape, h_lanes):
@@ -78,16 +130,21 @@ def test_autotune_keeps_a_valid_schedule(env):
     p = sgm.Params(width=W, height=H, max_disp=D)
     f = sgm.Frame.alloc(p, to_dev(torch, left), to_dev(torch, right))
     best, ms = sgm.sgm_autotune(ctx, f, reps=2)
-    # lanes first, then the disparity block size (no sweep: 9x7 codes, D = 128)
-    assert set(ms) == {"h_lanes=16", "h_lanes=32", "h_lanes=64", "disp_threads=256", "disp_threads=512",
-                       "disp_threads=1024"}
-    assert all(v > 0 for v in ms.values())
+    # lanes first, then (with 64 lanes) horizontal costs from the codes, then
+    # the disparity block size; no sweep (9x7 codes, D = 128)
     lane_best = min((16, 32, 64), key=lambda h: ms["h_lanes=%d" % h])
+    want = {"h_lanes=16", "h_lanes=32", "h_lanes=64", "disp_threads=256", "disp_threads=512", "disp_threads=1024"}
+    if lane_best == 64:
+        want.add("h_costs=codes")
+    assert set(ms) == want
+    assert all(v > 0 for v in ms.values())
     assert best["h_lanes"] == lane_best and not best["sweep"]
     overall = min(ms.values())
-    assert ms["h_lanes=%d" % lane_best] == overall if best["disp_threads"] == 0 \
-        else ms["disp_threads=%d" % best["disp_threads"]] == overall
-    assert sgm.schedule_of(ctx, p) == (best["h_lanes"], False, best["disp_threads"])
+    chosen = ("disp_threads=%d" % best["disp_threads"] if best["disp_threads"]
+              else "h_costs=codes" if best["h_costs"] == "codes" else "h_lanes=%d" % lane_best)
+    assert ms[chosen] == overall
+    hc = sgm.HCOSTS_CODES if best["h_costs"] == "codes" else sgm.HCOSTS_VOLUME
+    assert sgm.schedule_of(ctx, p) == (best["h_lanes"], False, best["disp_threads"], hc)
     sgm.sgm_wait(ctx, sgm.sgm_submit(ctx, [f]))
     want = O.sgm(left, right, D, 9, 7, 0xFF, 10, 120, True, 1, 3)
     assert_equal(to_np(f.disp), want["disp"], "disp after autotune")
@@ -97,3 +154,7 @@ def test_schedule_rejects_bad_values(env):
     torch, sgm, ctx = env
     with pytest.raises(sgm.SgmError):
         sgm.sgm_set_schedule(ctx, None, 48)
+    with pytest.raises(sgm.SgmError):
+        sgm.sgm_set_schedule(ctx, None, 0, h_costs=3)
+    with pytest.raises(sgm.SgmError):
+        sgm.sgm_set_schedule(ctx, None, 0, disp_threads=300)
