@@ -369,10 +369,13 @@ enum { SGM_HCOSTS_DEFAULT = 0, SGM_HCOSTS_VOLUME = 1, SGM_HCOSTS_CODES = 2 };
 int sgm_set_schedule(sgm_ctx *ctx, const sgm_params *shape, const sgm_schedule *s);
 /* The schedule sgm_submit would use for `shape` (after defaults). */
 int sgm_get_schedule(sgm_ctx *ctx, const sgm_params *shape, sgm_schedule *s);
-/* Autotuner: time `sample` (one frame, inputs and outputs as for
- * sgm_submit) under candidate schedules, `reps` timed repetitions each after
- * one warm-up, on one stream, and keep the fastest for the sample's shape (as
- * sgm_set_schedule); return it in *best (may be NULL).  The search is by
+/* Autotuner: time the n >= 1 frames `samples` (inputs and outputs as for
+ * sgm_submit; all of one shape -- width, height, max_disp, path_mask and
+ * path-cost width -- else SGM_EINVAL), submitted as one batch, under
+ * candidate schedules, `reps` timed repetitions each after one warm-up, on
+ * one stream, and keep the fastest for their shape (as sgm_set_schedule);
+ * return it in *best (may be NULL).  A batch of the size the caller will
+ * submit finds the schedule for that batch size.  The search is by
  * coordinates: h_lanes 16, 32, 64 (disp_threads 0, h_costs from the
  * volume); then, with the best h_lanes, horizontal costs from the Census
  * codes where that applies; then disp_threads 256, 512, 1024; then, for
@@ -381,7 +384,7 @@ int sgm_get_schedule(sgm_ctx *ctx, const sgm_params *shape, sgm_schedule *s);
  * candidates in the order h_lanes 16, 32, 64, h_costs codes, disp_threads
  * 256, 512, 1024, sweep (-1 where a candidate does not apply).  Must not run
  * concurrently with other submissions on the same context. */
-int sgm_autotune(sgm_ctx *ctx, const sgm_frame *sample, int reps, sgm_schedule *best, float *ms,
+int sgm_autotune(sgm_ctx *ctx, const sgm_frame *samples, int n, int reps, sgm_schedule *best, float *ms,
                  int n_ms);
 
 /* Stage timing of batches (sgm_submit).  While enabled, every stage of a

@@ -41,8 +41,14 @@ int fail(int code, const char *fmt, ...) {
 
 int popcount8(uint32_t m) { return __builtin_popcount(m & 0xFFu); }
 
-// Horizontal cost source of shapes without a tuned or context schedule.
-constexpr int kDefaultHCosts = SGM_HCOSTS_VOLUME;
+// Horizontal cost source of shapes without a tuned or context schedule:
+// Census windows where a 64-lane row holds four disparities per lane
+// (D in (192, 256]; measured faster on MI355X), the cost volume elsewhere
+// (with one disparity pair per lane the window costs more time on the row's
+// dependent chain than the volume reads it saves).
+int default_hcosts(const sgm_params &p, int hlps) {
+  return hlps == 64 && 16 * agg_k(p.max_disp) / hlps == 4 ? SGM_HCOSTS_CODES : SGM_HCOSTS_VOLUME;
+}
 
 int validate(const sgm_params *p) {
   if (!p) return fail(SGM_EINVAL, "params is null");
@@ -369,7 +375,7 @@ int resolve_hcosts(const sgm_ctx *c, const sgm_params &p, int hlps) {
   auto it = c->tuned.find(shape_key(p));
   int want = it != c->tuned.end() ? it->second.h_costs : SGM_HCOSTS_DEFAULT;
   if (want == SGM_HCOSTS_DEFAULT) want = c->dflt.h_costs;
-  if (want == SGM_HCOSTS_DEFAULT) want = kDefaultHCosts;
+  if (want == SGM_HCOSTS_DEFAULT) want = default_hcosts(p, hlps);
   return want == SGM_HCOSTS_CODES && hcodes_ok(p, hlps) ? SGM_HCOSTS_CODES : SGM_HCOSTS_VOLUME;
 }
 
@@ -1428,12 +1434,15 @@ int sgm_get_schedule(sgm_ctx *c, const sgm_params *shape, sgm_schedule *sc) {
   return SGM_OK;
 }
 
-// Milliseconds per submit of `sample` under schedule `sc` (set for the
-// sample's shape): one warm-up, then `reps` submits back to back on stream 0.
-static int time_schedule(sgm_ctx *c, const sgm_frame *sample, int reps, const sgm_schedule &sc, float *out) {
+// Milliseconds per submit of the n `samples` as one batch under schedule
+// `sc` (set for their shape): one warm-up, then `reps` submits back to back
+// on stream 0.
+static int time_schedule(sgm_ctx *c, const sgm_frame *samples, int n, int reps, const sgm_schedule &sc,
+                         float *out) {
+  const sgm_frame *sample = samples;
   CHECK(sgm_set_schedule(c, &sample->p, &sc));
   uint64_t t = 0;
-  CHECK(sgm_submit(c, sample, 1, &t));  // warm-up (also sizes the scratch)
+  CHECK(sgm_submit(c, samples, n, &t));  // warm-up (also sizes the scratch)
   CHECK(sgm_wait(c, t));
   hipEvent_t e0 = nullptr, e1 = nullptr;
   HIP_TRY(hipEventCreate(&e0));
@@ -1454,7 +1463,7 @@ static int time_schedule(sgm_ctx *c, const sgm_frame *sample, int reps, const sg
   int rc = hipEventRecord(e0, s0) == hipSuccess ? SGM_OK : fail(SGM_EHIP, "event record");
   std::vector<uint64_t> tk;
   for (int r = 0; r < reps && rc == SGM_OK; ++r) {
-    rc = sgm_submit(c, sample, 1, &t);
+    rc = sgm_submit(c, samples, n, &t);
     if (rc == SGM_OK) tk.push_back(t);
   }
   if (rc == SGM_OK && hipEventRecord(e1, s0) != hipSuccess) rc = fail(SGM_EHIP, "event record");
@@ -1478,11 +1487,19 @@ static int time_schedule(sgm_ctx *c, const sgm_frame *sample, int reps, const sg
   return SGM_OK;
 }
 
-int sgm_autotune(sgm_ctx *c, const sgm_frame *sample, int reps, sgm_schedule *best, float *ms,
+int sgm_autotune(sgm_ctx *c, const sgm_frame *samples, int n, int reps, sgm_schedule *best, float *ms,
                  int n_ms) {
-  if (!c || !sample) return fail(SGM_EINVAL, "ctx and sample must be non-null");
+  if (!c || !samples || n < 1) return fail(SGM_EINVAL, "ctx, samples and n >= 1 are required");
   if (reps < 1) return fail(SGM_EINVAL, "reps must be >= 1");
+  const sgm_frame *sample = samples;
   CHECK(validate(&sample->p));
+  for (int i = 1; i < n; ++i) {
+    CHECK(validate(&samples[i].p));
+    const sgm_params &a = sample->p, &b = samples[i].p;
+    if (b.width != a.width || b.height != a.height || b.max_disp != a.max_disp || b.path_mask != a.path_mask ||
+        lr_bytes_of(b) != lr_bytes_of(a))
+      return fail(SGM_EINVAL, "sample %d has another shape than sample 0", i);
+  }
   constexpr int kCands = 8;  // h_lanes 16, 32, 64; h_costs codes; disp_threads 256, 512, 1024; sweep
   float times[kCands];
   for (float &t : times) t = -1.f;
@@ -1490,7 +1507,7 @@ int sgm_autotune(sgm_ctx *c, const sgm_frame *sample, int reps, sgm_schedule *be
   float win_ms = -1.f;
   auto consider = [&](int slot, const sgm_schedule &sc) -> int {
     float t = 0.f;
-    CHECK(time_schedule(c, sample, reps, sc, &t));
+    CHECK(time_schedule(c, samples, n, reps, sc, &t));
     times[slot] = t;
     if (win_ms < 0.f || t < win_ms) {
       win = sc;

@@ -166,7 +166,7 @@ def lib():
         L.sgm_graph_stats.argtypes = [vp, P(ctypes.c_uint64), P(ctypes.c_uint64)]
         L.sgm_set_schedule.argtypes = [vp, P(sgm_params), P(sgm_schedule)]
         L.sgm_get_schedule.argtypes = [vp, P(sgm_params), P(sgm_schedule)]
-        L.sgm_autotune.argtypes = [vp, P(sgm_frame), i32, P(sgm_schedule), P(ctypes.c_float), i32]
+        L.sgm_autotune.argtypes = [vp, P(sgm_frame), i32, i32, P(sgm_schedule), P(ctypes.c_float), i32]
         L.sgm_profile_read.argtypes = [vp, P(ctypes.c_double), P(ctypes.c_uint64), i32]
         for name in EXPORTS:
             if name != "sgm_last_error":
@@ -488,17 +488,19 @@ AUTOTUNE_CANDIDATES = ("h_lanes=16", "h_lanes=32", "h_lanes=64", "h_costs=codes"
                        "disp_threads=512", "disp_threads=1024", "sweep")
 
 
-def sgm_autotune(ctx: Context, sample: "Frame", reps: int = 5):
-    """Time the candidate schedules on `sample` (lanes per horizontal
+def sgm_autotune(ctx: Context, sample, reps: int = 5):
+    """Time the candidate schedules on `sample` (a Frame, or a list of
+    Frames of one shape submitted as one batch) (lanes per horizontal
     scanline; horizontal costs from Census codes where that applies; the
     disparity block size; the sweep where it applies) and keep the fastest
     for its shape.  Returns (schedule, {candidate: ms per frame}) with
     schedule = {"h_lanes", "sweep", "disp_threads", "h_costs"}."""
+    frames = list(sample) if isinstance(sample, (list, tuple)) else [sample]
+    arr = (sgm_frame * len(frames))(*[f.c() for f in frames])
     best = sgm_schedule()
     n = len(AUTOTUNE_CANDIDATES)
     ms = (ctypes.c_float * n)()
-    f = sample.c()
-    _check(lib().sgm_autotune(ctx.handle, ctypes.byref(f), reps, ctypes.byref(best), ms, n), "sgm_autotune")
+    _check(lib().sgm_autotune(ctx.handle, arr, len(frames), reps, ctypes.byref(best), ms, n), "sgm_autotune")
     sched = {"h_lanes": best.h_lanes, "sweep": bool(best.sweep), "disp_threads": best.disp_threads,
              "h_costs": "codes" if best.h_costs == HCOSTS_CODES else "volume"}
     return sched, {name: ms[i] for i, name in enumerate(AUTOTUNE_CANDIDATES) if ms[i] >= 0}

@@ -150,6 +150,32 @@ def test_autotune_keeps_a_valid_schedule(env):
     assert_equal(to_np(f.disp), want["disp"], "disp after autotune")
 
 
+def test_autotune_on_a_batch_sample(env):
+    # the sample may be a batch of frames of one shape (tuned as one submit);
+    # frames of another shape are refused
+    torch, sgm, ctx = env
+    announce("autotune on a batch")
+    W, H, D = 260, 70, 256
+    p = sgm.Params(width=W, height=H, max_disp=D, invalid=65535)
+    frames, inputs = [], []
+    for k in range(3):
+        left, right, _ = synthetic.make_pair("kitti", 81 + k, W, H, D)
+        frames.append(sgm.Frame.alloc(p, to_dev(torch, left), to_dev(torch, right)))
+        inputs.append((left, right))
+    best, ms = sgm.sgm_autotune(ctx, frames, reps=1)
+    assert ms and all(v > 0 for v in ms.values()) and best["h_lanes"] in (16, 32, 64)
+    sgm.sgm_wait(ctx, sgm.sgm_submit(ctx, frames))
+    for (left, right), f in zip(inputs, frames):
+        want = O.sgm(left, right, D, 9, 7, 0xFF, 10, 120, True, 1, 3, 65535)
+        assert_equal(to_np(f.disp), want["disp"], "disp after batch autotune")
+    other = sgm.Params(width=W + 1, height=H, max_disp=D, invalid=65535)
+    odd = sgm.Frame.alloc(other, to_dev(torch, synthetic.make_pair("kitti", 90, W + 1, H, D)[0]),
+                          to_dev(torch, synthetic.make_pair("kitti", 90, W + 1, H, D)[1]))
+    with pytest.raises(sgm.SgmError) as e:
+        sgm.sgm_autotune(ctx, [frames[0], odd], reps=1)
+    assert e.value.status == sgm.SGM_EINVAL
+
+
 def test_schedule_rejects_bad_values(env):
     torch, sgm, ctx = env
     with pytest.raises(sgm.SgmError):
