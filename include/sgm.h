@@ -285,14 +285,17 @@ int sgm_submit_after(sgm_ctx *ctx, const sgm_frame *frames, int n, void *const *
  * raise GPU_MAX_HW_QUEUES. */
 int sgm_set_streams(sgm_ctx *ctx, int n);
 
-/* Number of the context's streams one batch's frames are spread over (1 to
- * 8; 1 after sgm_create): with n > 1 a batch of several frames is split into
- * up to n groups of about equal work (W*H*D*paths), each enqueued on its own
- * stream, so that stages of different frames overlap on the GPU (one
- * frame's Census next to another's aggregation); the ticket completes when
- * every group has.  Limited by sgm_set_streams; results are identical.
- * Graph mode captures batches on one stream and ignores the split; with
- * stage profiling on, stage times are summed over the groups. */
+/* Number of the context's streams a batch's frames are spread over (1 to 8;
+ * 4 after sgm_create) when it is submitted while no other batch of the
+ * context is in flight: the batch is split into up to n groups of about
+ * equal work (W*H*D*paths), each enqueued on its own stream and started
+ * when the previous group has finished its Census stage, so that one
+ * group's Census overlaps another's aggregation and disparity selection;
+ * the ticket completes when every group has.  A batch submitted while
+ * others are in flight is not split (it overlaps with them on the streams
+ * already).  Limited by sgm_set_streams; results are identical.  Graph mode
+ * captures batches on one stream and ignores the split; with stage
+ * profiling on, stage times are summed over the groups. */
 int sgm_set_split(sgm_ctx *ctx, int n);
 
 /* sgm_submit with rectification (section 3.1.1) as the batch's first
@@ -376,10 +379,11 @@ int sgm_get_schedule(sgm_ctx *ctx, const sgm_params *shape, sgm_schedule *s);
  * one stream, and keep the fastest for their shape (as sgm_set_schedule);
  * return it in *best (may be NULL).  A batch of the size the caller will
  * submit finds the schedule for that batch size.  The search is by
- * coordinates: h_lanes 16, 32, 64 (disp_threads 0, h_costs from the
- * volume); then, with the best h_lanes, horizontal costs from the Census
- * codes where that applies; then disp_threads 256, 512, 1024; then, for
- * frames the single-pass sweep can take, the sweep.  Blocks until done.
+ * coordinates: h_lanes 16, 32, 64 with horizontal costs from the volume,
+ * and 64 lanes with horizontal costs from the Census codes where that
+ * applies (disp_threads 0); then, with the best of these, disp_threads 256,
+ * 512, 1024; then, for frames the single-pass sweep can take, the sweep.
+ * Blocks until done.
  * `ms`, if non-NULL, receives per-candidate milliseconds for up to `n_ms`
  * candidates in the order h_lanes 16, 32, 64, h_costs codes, disp_threads
  * 256, 512, 1024, sweep (-1 where a candidate does not apply).  Must not run

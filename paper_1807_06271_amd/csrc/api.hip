@@ -153,7 +153,7 @@ struct sgm_ctx {
   hipStream_t streams[kStreams] = {};
   int nstreams = 4;  // streams in use (round robin)
   int next_stream = 0;
-  int split = 1;     // streams one batch's frames are spread over
+  int split = 4;     // streams a batch's frames are spread over when no other batch is in flight
   bool profiling = false;
   bool graphs = false;
   std::map<std::string, hipGraphExec_t> graph_cache;  // by batch composition
@@ -1282,7 +1282,10 @@ static int submit_impl(sgm_ctx *c, const sgm_frame *frames, const sgm_remap *rem
     c->idle.push_back(blk);
     return rc;
   }
-  const int groups = std::min(std::min(c->split, c->nstreams), n);
+  // a batch submitted while others run already overlaps with them on the
+  // context's streams; one submitted to an idle context overlaps its own
+  // frames' stages by the split
+  const int groups = c->inflight.empty() ? std::min(std::min(c->split, c->nstreams), n) : 1;
   if (c->graphs && !c->profiling) {
     rc = enqueue_graph(c, frames, n, plans, hl, sw, rect, reinterpret_cast<char *>(blk.ptr), s);
   } else if (groups > 1) {
@@ -1515,7 +1518,8 @@ int sgm_autotune(sgm_ctx *c, const sgm_frame *samples, int n, int reps, sgm_sche
     }
     return SGM_OK;
   };
-  // 1. lanes per horizontal scanline
+  // 1. lanes per horizontal scanline, horizontal costs from the volume; and
+  //    64 lanes with the costs from sliding Census windows, where it applies
   const int lanes[3] = {16, 32, 64};
   for (int ci = 0; ci < 3; ++ci) {
     if (!agg_hlps_ok(k_of(sample->p), lanes[ci])) continue;
@@ -1524,13 +1528,13 @@ int sgm_autotune(sgm_ctx *c, const sgm_frame *samples, int n, int reps, sgm_sche
     sc.h_costs = SGM_HCOSTS_VOLUME;
     CHECK(consider(ci, sc));
   }
-  // 2. horizontal costs from sliding Census windows, with the best layout
-  if (hcodes_ok(sample->p, win.h_lanes)) {
-    sgm_schedule sc = win;
+  if (hcodes_ok(sample->p, 64)) {
+    sgm_schedule sc{};
+    sc.h_lanes = 64;
     sc.h_costs = SGM_HCOSTS_CODES;
     CHECK(consider(3, sc));
   }
-  // 3. disparity-selection block size
+  // 2. disparity-selection block size
   const int threads[3] = {256, 512, 1024};
   const sgm_schedule base = win;
   for (int ci = 0; ci < 3; ++ci) {
@@ -1538,7 +1542,7 @@ int sgm_autotune(sgm_ctx *c, const sgm_frame *samples, int n, int reps, sgm_sche
     sc.disp_threads = threads[ci];
     CHECK(consider(4 + ci, sc));
   }
-  // 4. the single-pass sweep, for frames it can take
+  // 3. the single-pass sweep, for frames it can take
   if (sweep_ok(sample->p)) {
     sgm_schedule sc = win;
     sc.sweep = 1;

@@ -269,6 +269,8 @@ def test_batch_split_over_streams_matches_oracle(env, split):
         items.append((p, left, right, sgm.Frame.alloc(p, to_dev(torch, left), to_dev(torch, right))))
     sgm.sgm_set_streams(ctx, 4)
     sgm.sgm_set_split(ctx, split)
+    # the split applies to batches submitted while none is in flight
+    assert sgm.sgm_memory(ctx)[0] == 0
     try:
         for prof in (False, True):
             sgm.sgm_profile(ctx, prof)
@@ -282,4 +284,4 @@ def test_batch_split_over_streams_matches_oracle(env, split):
                 assert_equal(to_np(f.vmap), want["vmap"], "vmap " + tag)
     finally:
         sgm.sgm_profile(ctx, False)
-        sgm.sgm_set_split(ctx, 1)
+        sgm.sgm_set_split(ctx, 4)

@@ -130,18 +130,18 @@ def test_autotune_keeps_a_valid_schedule(env):
     p = sgm.Params(width=W, height=H, max_disp=D)
     f = sgm.Frame.alloc(p, to_dev(torch, left), to_dev(torch, right))
     best, ms = sgm.sgm_autotune(ctx, f, reps=2)
-    # lanes first, then (with 64 lanes) horizontal costs from the codes, then
-    # the disparity block size; no sweep (9x7 codes, D = 128)
-    lane_best = min((16, 32, 64), key=lambda h: ms["h_lanes=%d" % h])
-    want = {"h_lanes=16", "h_lanes=32", "h_lanes=64", "disp_threads=256", "disp_threads=512", "disp_threads=1024"}
-    if lane_best == 64:
-        want.add("h_costs=codes")
+    # first lanes (16, 32, 64 with costs from the volume, 64 with costs from
+    # Census windows), then the disparity block size from that winner; no
+    # sweep (9x7 codes, D = 128)
+    stage1 = ("h_lanes=16", "h_lanes=32", "h_lanes=64", "h_costs=codes")
+    want = set(stage1) | {"disp_threads=256", "disp_threads=512", "disp_threads=1024"}
     assert set(ms) == want
     assert all(v > 0 for v in ms.values())
-    assert best["h_lanes"] == lane_best and not best["sweep"]
+    first = min(stage1, key=lambda k: ms[k])
+    assert best["h_lanes"] == (64 if first == "h_costs=codes" else int(first.split("=")[1]))
+    assert (best["h_costs"] == "codes") == (first == "h_costs=codes") and not best["sweep"]
     overall = min(ms.values())
-    chosen = ("disp_threads=%d" % best["disp_threads"] if best["disp_threads"]
-              else "h_costs=codes" if best["h_costs"] == "codes" else "h_lanes=%d" % lane_best)
+    chosen = "disp_threads=%d" % best["disp_threads"] if best["disp_threads"] else first
     assert ms[chosen] == overall
     hc = sgm.HCOSTS_CODES if best["h_costs"] == "codes" else sgm.HCOSTS_VOLUME
     assert sgm.schedule_of(ctx, p) == (best["h_lanes"], False, best["disp_threads"], hc)
