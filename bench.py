@@ -35,9 +35,13 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
 # Algorithmic bytes of the aggregation kernel per disparity evaluation (one
-# path, one cell, one disparity): it reads the cell's uint8 matching cost and
-# writes the cell's uint8 path cost, once per path.
+# path, one cell, one disparity) on a direction that reads the cost volume:
+# the cell's uint8 matching cost read and its uint8 path cost written.  A
+# horizontal direction that forms its costs from sliding Census windows
+# writes the same byte but reads one 16-byte code record per pixel instead
+# of D cost bytes (agg_alg_bytes).
 AGG_BYTES_PER_EVAL = 2
+CODE_RECORD_BYTES = 16
 # The survey's schedule-independent count: a uint16 running sum S read and
 # written per path and cell.
 SURVEY_BYTES_PER_EVAL = 4
@@ -481,11 +485,26 @@ def bench_kitti(torch, sgm, ctx, synthetic, steps=200, warmup=20):
     return res
 
 
-def agg_kernel_name(h_lanes):
+def agg_kernel_name(sched):
     """The aggregation kernel instance the 1920x1080 D=256 frames run:
     16 disparities per lane on 16-lane scanlines, 256 / h_lanes on the
-    horizontal ones, uint8 costs and path costs."""
-    return "agg_kernel<16, %d, %d, 0, unsigned char" % (256 // h_lanes, h_lanes)
+    horizontal ones, uint8 costs and path costs, 8 pixels prefetched, no
+    padded disparity rows; the last argument is the horizontal cost source
+    (0 the cost volume, 2 sliding Census windows)."""
+    return "agg_kernel<16, %d, %d, 0, unsigned char, 8, false, %d>" % (
+        256 // sched["h_lanes"], sched["h_lanes"], 2 if sched["h_costs"] == "codes" else 0)
+
+
+def agg_alg_bytes(p, frames, sched):
+    """Algorithmic HBM bytes of one aggregation launch over `frames` frames of
+    params p (8 paths): every direction writes its uint8 path costs (W*H*D);
+    a direction reading the cost volume reads W*H*D bytes, a horizontal one
+    on Census windows one code record per pixel."""
+    cells = p.width * p.height * p.max_disp
+    horizontal = 2 if sched["h_costs"] == "codes" else 0
+    per_frame = (8 - horizontal) * AGG_BYTES_PER_EVAL * cells + horizontal * (
+        cells + CODE_RECORD_BYTES * p.width * p.height)
+    return frames * per_frame
 
 
 def measured_valu(kernel_prefix, record):
@@ -558,7 +577,6 @@ def main():
     evals = 8 * p.disp_evals()
     # the schedule is tuned on the batch the benchmark submits
     sched, tune_ms = sgm.sgm_autotune(ctx, [sgm.Frame.alloc(p, l, r) for l, r in inputs], reps=2)
-    h_lanes = sched["h_lanes"]
     log("autotuned schedule", sched, tune_ms)
 
     def batch(i):
@@ -596,10 +614,11 @@ def main():
     agg_ms, agg_n = prof1["aggregate"]
     agg_avg = agg_ms / max(agg_n, 1)
     agg_overlapped = prof["aggregate"][0] / max(prof["aggregate"][1], 1)
-    alg = AGG_BYTES_PER_EVAL * evals
+    alg = agg_alg_bytes(p, 8, sched)
     achieved = alg / (agg_avg * 1e-3) / 1e9
-    traffic = measured_traffic(agg_kernel_name(h_lanes), "traffic_agg_1920x1080_d256_batch8.json")
-    valu = measured_valu(agg_kernel_name(h_lanes), "counters_1920x1080_d256_batch8.txt")
+    kname = agg_kernel_name(sched)
+    traffic = measured_traffic(kname, "traffic_agg_1920x1080_d256_batch8.json")
+    valu = measured_valu(kname, "counters_1920x1080_d256_batch8.txt")
 
     extras = {}
     sgm.sgm_profile(ctx, False)
@@ -657,8 +676,8 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic,
-                     "kernel": agg_kernel_name(h_lanes) + ", 8, false> (8 directions of 8 frames in one launch)",
-                     "alg_bytes_per_eval": AGG_BYTES_PER_EVAL,
+                     "kernel": kname + " (8 directions of 8 frames in one launch)",
+                     "alg_bytes_per_eval": round(alg / evals, 4),
                      "alg_bytes_per_launch": alg, "evals_per_launch": evals,
                      "avg_launch_ms": round(agg_avg, 5), "launches": agg_n,
                      "timed_loop": "one stream (each launch alone on the GPU)",
@@ -666,7 +685,7 @@ def main():
                      "traffic_frac": round(traffic / (agg_avg * 1e-3) / 1e9 / HBM_PEAK_GBS, 4) if traffic else None,
                      "valu_issue": valu,
                      "survey_bytes_per_eval": SURVEY_BYTES_PER_EVAL,
-                     "survey_bytes_ratio": SURVEY_BYTES_PER_EVAL / AGG_BYTES_PER_EVAL},
+                     "survey_bytes_ratio": round(SURVEY_BYTES_PER_EVAL * evals / alg, 4)},
         "cpu_baseline": cpu,
         "extras": extras,
     }

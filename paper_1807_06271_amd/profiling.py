@@ -3,7 +3,7 @@
     python -m paper_1807_06271_amd.profiling stats  <kernel_stats.csv> <out.txt> "<command>" \
         [<kernel_trace.csv> <kernel name part> <N dispatches> [<skip> [largest]]]
     python -m paper_1807_06271_amd.profiling traffic <fetch_counter_collection.csv> \
-        <write_counter_collection.csv> <out.json> "<fetch command>" "<write command>" [median|max]
+        <write_counter_collection.csv> <out.json> "<fetch command>" "<write command>" [median|largest|max]
     python -m paper_1807_06271_amd.profiling counters <counter_collection.csv> <kernel_trace.csv> \
         <out.txt> "<command>" [largest]
 
@@ -76,10 +76,10 @@ def short_name(name: str) -> str:
 def stats(csv_path: str, out_path: str, command: str, trace_csv: str | None = None,
           kernel: str | None = None, first: int = 0, skip: int = 0, largest: bool = False) -> None:
     """Kernel statistics; with trace_csv/kernel/first, also the average of
-    dispatches skip .. skip+first-1 of `kernel` (a loop of the benchmark in
-    which the kernel runs alone); with `largest`, counted among the
-    dispatches with the kernel's largest grid only (e.g. its 8-frame
-    launches, not the autotuner's single frames)."""
+    dispatches skip .. skip+first-1 (in start order; skip < 0: the last
+    `first`) of `kernel` (a loop of the benchmark in which the kernel runs
+    alone); with `largest`, counted among the dispatches with the kernel's
+    largest grid only (e.g. its 8-frame launches, not single frames)."""
     rows = list(csv.DictReader(open(csv_path)))
     lines = ["# rocprofv3 kernel statistics", "# command: " + command, "#",
              "%-100s %6s %12s %12s %12s %7s" % ("kernel", "calls", "avg_us", "min_us", "max_us", "pct")]
@@ -89,32 +89,40 @@ def stats(csv_path: str, out_path: str, command: str, trace_csv: str | None = No
             float(r["MaxNs"]) / 1e3, float(r["Percentage"])))
     if trace_csv and kernel and first:
         tr = [r for r in csv.DictReader(open(trace_csv)) if kernel in r["Kernel_Name"]]
+        tr.sort(key=lambda r: int(r["Start_Timestamp"]))
         grid = max(int(r["Grid_Size_X"]) for r in tr)
         if largest:
             tr = [r for r in tr if int(r["Grid_Size_X"]) == grid]
+        if skip < 0:  # the last `first` dispatches
+            skip = len(tr) - first
         d = [(int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3 for r in tr][skip:skip + first]
-        lines += ["#", "# dispatches %d..%d%s of %s: avg %.1f us, min %.1f, max %.1f"
+        lines += ["#", "# dispatches %d..%d (in start order)%s of %s: avg %.1f us, min %.1f, max %.1f"
                   % (skip, skip + len(d) - 1, " (grid %d only)" % grid if largest else "", kernel,
                      sum(d) / len(d), min(d), max(d))]
     open(out_path, "w").write("\n".join(lines) + "\n")
 
 
-def _per_kernel(csv_path: str, counter: str):
-    """{kernel name: [per-dispatch counter values]} from counter_collection.csv."""
+def _per_kernel(csv_path: str, counter: str, largest: bool = False):
+    """{kernel name: [per-dispatch counter values]} from counter_collection.csv;
+    with `largest`, only each kernel's dispatches with its largest grid."""
+    rows = [r for r in csv.DictReader(open(csv_path)) if r.get("Counter_Name") == counter]
+    big = defaultdict(int)
+    for r in rows:
+        big[r["Kernel_Name"]] = max(big[r["Kernel_Name"]], int(r["Grid_Size"]))
     acc = defaultdict(list)
-    for r in csv.DictReader(open(csv_path)):
-        if r.get("Counter_Name") != counter:
-            continue
-        acc[r["Kernel_Name"]].append(float(r["Counter_Value"]))
+    for r in rows:
+        if not largest or int(r["Grid_Size"]) == big[r["Kernel_Name"]]:
+            acc[r["Kernel_Name"]].append(float(r["Counter_Value"]))
     return acc
 
 
 def traffic(fetch_csv: str, write_csv: str, out_path: str, fetch_cmd: str, write_cmd: str,
             pick: str = "median") -> dict:
     """pick: "median" of each kernel's dispatches (all dispatches of one size),
-    or "max" (the largest dispatch, e.g. a whole batch among single frames)."""
-    f = _per_kernel(fetch_csv, "FETCH_SIZE")
-    w = _per_kernel(write_csv, "WRITE_SIZE")
+    "largest" (the median over the dispatches with the kernel's largest grid,
+    e.g. whole batches among single frames), or "max" (the largest dispatch)."""
+    f = _per_kernel(fetch_csv, "FETCH_SIZE", pick == "largest")
+    w = _per_kernel(write_csv, "WRITE_SIZE", pick == "largest")
     copy = [k for k in f if "copy" in k.lower() or "elementwise" in k.lower()]
     # the calibration copy is the dispatch whose fetch is largest among copies
     best = None
@@ -200,7 +208,7 @@ def counters(csv_path: str, trace_csv: str, out_path: str, command: str, largest
 
 if __name__ == "__main__":
     if sys.argv[1] == "stats":
-        extra = sys.argv[5:7] + [int(v) for v in sys.argv[7:9]] if len(sys.argv) > 7 else []
+        extra = sys.argv[5:7] + [int(v) for v in sys.argv[7:9]] if len(sys.argv) > 7 else []  # skip may be -1
         if len(sys.argv) > 9:
             extra.append(sys.argv[9] == "largest")
         stats(sys.argv[2], sys.argv[3], sys.argv[4], *extra)

@@ -13,3 +13,21 @@ def test_bench_refuses_more_than_one_gpu():
     assert r.returncode == 2
     assert "one GPU only" in r.stderr
     assert r.stdout == ""
+
+
+def test_aggregation_bytes_follow_the_schedule():
+    # 8 directions reading the cost volume: 2 bytes per evaluation; with the
+    # horizontal pair on Census windows those two write their byte and read
+    # one 16-byte code record per pixel instead of D cost bytes
+    sys.path.insert(0, ROOT)
+    import bench
+    from paper_1807_06271_amd.sgm import Params
+    p = Params(width=1920, height=1080, max_disp=256)
+    cells = 1920 * 1080 * 256
+    vol = {"h_lanes": 64, "h_costs": "volume"}
+    codes = {"h_lanes": 64, "h_costs": "codes"}
+    assert bench.agg_alg_bytes(p, 8, vol) == 8 * 8 * 2 * cells == 2 * 8 * p.disp_evals()
+    assert bench.agg_alg_bytes(p, 8, codes) == 8 * (6 * 2 * cells + 2 * (cells + 16 * 1920 * 1080))
+    assert bench.agg_kernel_name(codes).endswith("unsigned char, 8, false, 2>")
+    assert bench.agg_kernel_name({"h_lanes": 32, "h_costs": "volume"}) == \
+        "agg_kernel<16, 8, 32, 0, unsigned char, 8, false, 0>"
