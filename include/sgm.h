@@ -363,8 +363,23 @@ typedef struct {
    * (192, 256], N_b + p2 <= 255 and W * H * 16 bytes below 2 GiB; other
    * frames use the volume. */
   int32_t h_costs;
+  /* The vertical and diagonal paths of 8-path frames (section 3.1.3: one
+   * pass over the image, a second from back to front):
+   * SGM_TWOPASS_DEFAULT (0) = the library's default for the shape;
+   * SGM_TWOPASS_OFF (1) = per-direction kernels for all 8 paths, each path's
+   * costs written to memory and summed by the disparity selection;
+   * SGM_TWOPASS_WIDE (2) / SGM_TWOPASS_NARROW (3) = a top-down pass for
+   * T->B and TL->BR writing their uint16 sum, then a bottom-up pass for B->T
+   * and BR->TL that also sums S over all 8 paths and selects the
+   * disparities; both passes walk the rows of 64-column (WIDE) or 32-column
+   * (NARROW) stripes, one workgroup per stripe.  The four other paths run
+   * as per-direction kernels.  Applies to Census frames with all 8 paths
+   * and N_b + p2 <= 255 that do not use the single-pass sweep; other frames
+   * use the per-direction kernels. */
+  int32_t two_pass;
 } sgm_schedule;
 enum { SGM_HCOSTS_DEFAULT = 0, SGM_HCOSTS_VOLUME = 1, SGM_HCOSTS_CODES = 2 };
+enum { SGM_TWOPASS_DEFAULT = 0, SGM_TWOPASS_OFF = 1, SGM_TWOPASS_WIDE = 2, SGM_TWOPASS_NARROW = 3 };
 
 /* Set the schedule used by sgm_submit for frames of the shape of `shape`
  * (width, height, max_disp, path_mask and the path-cost width it implies);
@@ -381,13 +396,16 @@ int sgm_get_schedule(sgm_ctx *ctx, const sgm_params *shape, sgm_schedule *s);
  * submit finds the schedule for that batch size.  The search is by
  * coordinates: h_lanes 16, 32, 64 with horizontal costs from the volume,
  * and 64 lanes with horizontal costs from the Census codes where that
- * applies (disp_threads 0); then, with the best of these, disp_threads 256,
+ * applies (per-direction kernels, disp_threads 0); then, with the best of
+ * these, the two-pass schedule with wide and with narrow stripes where it
+ * applies; then, if the per-direction kernels still win, disp_threads 256,
  * 512, 1024; then, for frames the single-pass sweep can take, the sweep.
  * Blocks until done.
  * `ms`, if non-NULL, receives per-candidate milliseconds for up to `n_ms`
- * candidates in the order h_lanes 16, 32, 64, h_costs codes, disp_threads
- * 256, 512, 1024, sweep (-1 where a candidate does not apply).  Must not run
- * concurrently with other submissions on the same context. */
+ * candidates in the order h_lanes 16, 32, 64, h_costs codes, two_pass wide,
+ * two_pass narrow, disp_threads 256, 512, 1024, sweep (-1 where a candidate
+ * does not apply or was not reached).  Must not run concurrently with other
+ * submissions on the same context. */
 int sgm_autotune(sgm_ctx *ctx, const sgm_frame *samples, int n, int reps, sgm_schedule *best, float *ms,
                  int n_ms);
 

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -285,6 +286,9 @@ int check_dev_ptr(const void *ptr, int dev, const char *name) {
 
 struct FramePlan {
   size_t off_cost, off_lr, off_dlr, off_dl, off_part, off_codes, bytes;
+  // two-pass frames: S_D after the four path-cost slots, the stripes' edge
+  // words and the frame's sync words
+  size_t off_sd, off_bnd, off_sync;
 };
 
 // Scratch of one frame of a batch: the padded uint8 cost volume, the P
@@ -293,12 +297,20 @@ struct FramePlan {
 // pixel plus Dp records of padding before the first.
 size_t code_records_bytes(const sgm_params &p) { return ((size_t)p.width * p.height + dp_of(p)) * 16; }
 
-FramePlan plan_frame(const sgm_params &p, size_t base, bool sweep, bool codes) {
+// Stripe columns of the two-pass schedule with `waves` waves per workgroup.
+int stripe_cols(int waves) { return 4 * waves; }
+int stripes_of(const sgm_params &p, int waves) { return (p.width + stripe_cols(waves) - 1) / stripe_cols(waves); }
+size_t stripe_part_bytes(const sgm_params &p, int waves) {
+  return (size_t)p.height * stripes_of(p, waves) * (stripe_cols(waves) + p.max_disp - 1) * 4;
+}
+
+FramePlan plan_frame(const sgm_params &p, size_t base, bool sweep, bool codes, int tp_waves = 0) {
   const size_t px = (size_t)p.width * p.height;
   const size_t dp = (size_t)dp_of(p);
   FramePlan f;
   f.off_cost = base;
   f.off_codes = 0;
+  f.off_sd = f.off_bnd = f.off_sync = 0;
   if (sweep) {
     // Census codes of both views; D_L and D_R; the band-boundary carry rows;
     // the LR-checked map before the median
@@ -314,10 +326,20 @@ FramePlan plan_frame(const sgm_params &p, size_t base, bool sweep, bool codes) {
   // D_L and the row segments' right-view keys (left-right check)
   f.off_dl = f.off_dlr + align256(px * 2);
   f.off_part = f.off_dl + align256(px * 2);
-  f.bytes = f.off_part + align256(disp_part_bytes(p.width, p.height, p.max_disp)) - base;
+  size_t part = disp_part_bytes(p.width, p.height, p.max_disp);
+  if (tp_waves) part = std::max(part, stripe_part_bytes(p, tp_waves));
+  f.bytes = f.off_part + align256(part) - base;
   if (codes) {
     f.off_codes = base + f.bytes;
     f.bytes += align256(code_records_bytes(p));
+  }
+  if (tp_waves) {
+    // the 8 path-cost slots' room holds the 4 slots and S_D (uint16)
+    f.off_sd = f.off_lr + align256(px * dp * 4);
+    f.off_bnd = base + f.bytes;
+    f.bytes += align256((size_t)stripes_of(p, tp_waves) * p.height * dp * 4);
+    f.off_sync = base + f.bytes;
+    f.bytes += align256(kSyncWords * 4);
   }
   return f;
 }
@@ -377,6 +399,30 @@ int resolve_hcosts(const sgm_ctx *c, const sgm_params &p, int hlps) {
   if (want == SGM_HCOSTS_DEFAULT) want = c->dflt.h_costs;
   if (want == SGM_HCOSTS_DEFAULT) want = default_hcosts(p, hlps);
   return want == SGM_HCOSTS_CODES && hcodes_ok(p, hlps) ? SGM_HCOSTS_CODES : SGM_HCOSTS_VOLUME;
+}
+
+// Frames the two-pass schedule handles: Census costs, all 8 paths, uint8
+// path costs (the four per-direction slots and S_D share the room of eight
+// uint8 slots).
+bool twopass_ok(const sgm_params &p) { return !is_sad(p) && p.path_mask == 0xFF && lr_bytes_of(p) == 1; }
+
+// Waves per stripe workgroup of the two-pass schedule for a frame, 0 when it
+// does not run it: the tuned entry for its shape, else the context default,
+// else the per-direction kernels.
+int resolve_twopass(const sgm_ctx *c, const sgm_params &p) {
+  auto it = c->tuned.find(shape_key(p));
+  int want = it != c->tuned.end() ? it->second.two_pass : SGM_TWOPASS_DEFAULT;
+  if (want == SGM_TWOPASS_DEFAULT) want = c->dflt.two_pass;
+  if (!twopass_ok(p) || resolve_sweep(c, p)) return 0;
+  return want == SGM_TWOPASS_WIDE ? 16 : want == SGM_TWOPASS_NARROW ? 8 : 0;
+}
+
+// A fresh nonzero tag for a stripe launch's edge words.
+uint32_t next_epoch() {
+  static std::atomic<uint32_t> e{0};
+  uint32_t v;
+  do v = e.fetch_add(1) + 1; while (v == 0);
+  return v;
 }
 
 // Disparity-selection block size for a frame (0: by the launch's block count).
@@ -449,6 +495,8 @@ int check_schedule(const sgm_schedule *s) {
     return fail(SGM_EINVAL, "disp_threads must be 0, 256, 512 or 1024 (got %d)", s->disp_threads);
   if (s->h_costs < SGM_HCOSTS_DEFAULT || s->h_costs > SGM_HCOSTS_CODES)
     return fail(SGM_EINVAL, "h_costs must be 0, 1 or 2 (got %d)", s->h_costs);
+  if (s->two_pass < SGM_TWOPASS_DEFAULT || s->two_pass > SGM_TWOPASS_NARROW)
+    return fail(SGM_EINVAL, "two_pass must be 0, 1, 2 or 3 (got %d)", s->two_pass);
   return SGM_OK;
 }
 
@@ -560,9 +608,21 @@ int enqueue_frames(const sgm_frame *fr, int n, const std::vector<FramePlan> &pla
   }
   CHECK(mark.end(launches));
   if (census_done) HIP_TRY(hipEventRecord(census_done, s));
+  // two-pass frames: waves per stripe (0: per-direction kernels only)
+  auto tp_waves = [&](int i) { return (hlps[i] >> 9) & 1 ? ((hlps[i] >> 10) & 1 ? 16 : 8) : 0; };
   // aggregation, one launch per (disparities per lane, path-cost width)
   CHECK(mark.begin(SGM_STAGE_AGGREGATE));
   int groups = 0;
+  {  // the stripes' ticket counters and error flags start at zero
+    std::vector<SyncZeroJob> zj;
+    for (int i = 0; i < n; ++i)
+      if (tp_waves(i)) zj.push_back(SyncZeroJob{reinterpret_cast<uint32_t *>(mem + plans[i].off_sync), kSyncWords, 0});
+    if (!zj.empty()) {
+      launch_zero_sync(zj, s);
+      CHECK(check_launch());
+      ++groups;
+    }
+  }
   for (int sad = 0; sad <= 1; ++sad)
   for (int K : {4, 8, 12, 16})
     for (int lb = 1; lb <= 2; ++lb)
@@ -587,7 +647,8 @@ int enqueue_frames(const sgm_frame *fr, int n, const std::vector<FramePlan> &pla
         j.Dp = dp_of(p);
         j.p1 = p.p1;
         j.p2 = p.p2;
-        j.ndirs = fill_dirs(p.path_mask, j.dirs);
+        // two-pass frames: L->R, R->L, TR->BL, BL->TR here, the others in stripes
+        j.ndirs = fill_dirs(tp_waves(i) ? 0xC3u : p.path_mask, j.dirs);
         aj.push_back(j);
       }
       if (!aj.empty()) {
@@ -638,6 +699,42 @@ int enqueue_frames(const sgm_frame *fr, int n, const std::vector<FramePlan> &pla
       ++groups;
     }
   }
+  // the stripe passes, one launch per (disparities per lane, stripe width)
+  auto stripe_jobs = [&](int K, int waves, uint32_t epoch) {
+    std::vector<StripeJob> sj;
+    for (int i = 0; i < n; ++i) {
+      const sgm_params &p = fr[i].p;
+      if (tp_waves(i) != waves || k_of(p) != K) continue;
+      StripeJob j{};
+      j.cost = reinterpret_cast<const uint8_t *>(mem + plans[i].off_cost);
+      j.sd = reinterpret_cast<uint16_t *>(mem + plans[i].off_sd);
+      j.lr4 = reinterpret_cast<const uint8_t *>(mem + plans[i].off_lr);
+      j.bnd = reinterpret_cast<uint64_t *>(mem + plans[i].off_bnd);
+      j.sync = reinterpret_cast<uint32_t *>(mem + plans[i].off_sync);
+      uint16_t *final_map = p.median ? reinterpret_cast<uint16_t *>(mem + plans[i].off_dlr) : fr[i].disp;
+      j.dl = p.lr_check ? reinterpret_cast<uint16_t *>(mem + plans[i].off_dl) : final_map;
+      j.part = reinterpret_cast<uint32_t *>(mem + plans[i].off_part);
+      j.W = p.width;
+      j.H = p.height;
+      j.D = p.max_disp;
+      j.Dp = dp_of(p);
+      j.p1 = p.p1;
+      j.p2 = p.p2;
+      j.lr_check = p.lr_check;
+      j.epoch = epoch;
+      sj.push_back(j);
+    }
+    return sj;
+  };
+  const uint32_t epoch_down = next_epoch(), epoch_up = next_epoch();
+  for (int K : {4, 8, 12, 16})
+    for (int waves : {8, 16}) {
+      std::vector<StripeJob> sj = stripe_jobs(K, waves, epoch_down);
+      if (sj.empty()) continue;
+      launch_stripes(sj, K, false, waves, s);
+      CHECK(check_launch());
+      ++groups;
+    }
   CHECK(mark.end(groups));
   CHECK(mark.begin(SGM_STAGE_DISPARITY));
   groups = 0;
@@ -670,11 +767,30 @@ int enqueue_frames(const sgm_frame *fr, int n, const std::vector<FramePlan> &pla
       ++groups;
     }
   }
+  for (int K : {4, 8, 12, 16})
+    for (int waves : {8, 16}) {
+      std::vector<StripeJob> sj = stripe_jobs(K, waves, epoch_up);
+      if (sj.empty()) continue;
+      launch_stripes(sj, K, true, waves, s);
+      CHECK(check_launch());
+      ++groups;
+    }
+  // row segments of a frame's right-view keys: the stripes of two-pass
+  // frames, else those of the disparity kernel
+  auto segments = [&](int i, int *nseg, int *seglen) {
+    const sgm_params &p = fr[i].p;
+    if (tp_waves(i)) {
+      *nseg = stripes_of(p, tp_waves(i));
+      *seglen = stripe_cols(tp_waves(i));
+    } else {
+      disp_segments(p.width, p.max_disp, split, nseg, seglen);
+    }
+  };
   for (int lb = 1; lb <= 2; ++lb) {
     std::vector<DispJob> dj;
     for (int i = 0; i < n; ++i) {
       const sgm_params &p = fr[i].p;
-      if (sweep[i] || lr_bytes_of(p) != lb) continue;
+      if (sweep[i] || tp_waves(i) || lr_bytes_of(p) != lb) continue;
       DispJob j{};
       j.lr = mem + plans[i].off_lr;
       j.P = popcount8(p.path_mask);
@@ -709,7 +825,7 @@ int enqueue_frames(const sgm_frame *fr, int n, const std::vector<FramePlan> &pla
       j.W = p.width;
       j.H = p.height;
       j.D = p.max_disp;
-      disp_segments(p.width, p.max_disp, split, &j.nseg, &j.seglen);
+      segments(i, &j.nseg, &j.seglen);
       j.max_diff = p.lr_max_diff;
       j.invalid = p.invalid;
       lj.push_back(j);
@@ -736,7 +852,7 @@ int enqueue_frames(const sgm_frame *fr, int n, const std::vector<FramePlan> &pla
       j.dl = reinterpret_cast<const uint16_t *>(mem + plans[i].off_dl);
       j.part = reinterpret_cast<const uint32_t *>(mem + plans[i].off_part);
       j.D = p.max_disp;
-      disp_segments(p.width, p.max_disp, split, &j.nseg, &j.seglen);
+      segments(i, &j.nseg, &j.seglen);
       j.max_diff = p.lr_max_diff;
       j.invalid = p.invalid;
     }
@@ -1216,12 +1332,15 @@ static int submit_impl(sgm_ctx *c, const sgm_frame *frames, const sgm_remap *rem
   size_t total = 0;
   for (int i = 0; i < n; ++i) {
     // lanes per horizontal scanline (low byte), horizontal costs from codes
-    // (bit 8), the disparity block size (above bit 16)
+    // (bit 8), two-pass stripes (bit 9; bit 10: 16 waves per stripe, else
+    // 8), the disparity block size (above bit 16)
     const int h = resolve_hlps(c, frames[i].p);
     sw[i] = resolve_sweep(c, frames[i].p);
     const bool codes = !sw[i] && resolve_hcosts(c, frames[i].p, h) == SGM_HCOSTS_CODES;
-    hl[i] = h | (codes ? 1 << 8 : 0) | resolve_disp_threads(c, frames[i].p) << 16;
-    plans[i] = plan_frame(frames[i].p, total, sw[i] != 0, codes);
+    const int tp = resolve_twopass(c, frames[i].p);
+    hl[i] = h | (codes ? 1 << 8 : 0) | (tp ? 1 << 9 : 0) | (tp == 16 ? 1 << 10 : 0) |
+            resolve_disp_threads(c, frames[i].p) << 16;
+    plans[i] = plan_frame(frames[i].p, total, sw[i] != 0, codes, tp);
     total += plans[i].bytes;
   }
   DeviceGuard g(c->device);
@@ -1434,6 +1553,8 @@ int sgm_get_schedule(sgm_ctx *c, const sgm_params *shape, sgm_schedule *sc) {
   sc->sweep = resolve_sweep(c, *shape);
   sc->disp_threads = resolve_disp_threads(c, *shape);
   sc->h_costs = sc->sweep ? SGM_HCOSTS_VOLUME : resolve_hcosts(c, *shape, sc->h_lanes);
+  const int tp = resolve_twopass(c, *shape);
+  sc->two_pass = tp == 16 ? SGM_TWOPASS_WIDE : tp == 8 ? SGM_TWOPASS_NARROW : SGM_TWOPASS_OFF;
   return SGM_OK;
 }
 
@@ -1503,7 +1624,9 @@ int sgm_autotune(sgm_ctx *c, const sgm_frame *samples, int n, int reps, sgm_sche
         lr_bytes_of(b) != lr_bytes_of(a))
       return fail(SGM_EINVAL, "sample %d has another shape than sample 0", i);
   }
-  constexpr int kCands = 8;  // h_lanes 16, 32, 64; h_costs codes; disp_threads 256, 512, 1024; sweep
+  // h_lanes 16, 32, 64; h_costs codes; two_pass wide, narrow; disp_threads
+  // 256, 512, 1024; sweep
+  constexpr int kCands = 10;
   float times[kCands];
   for (float &t : times) t = -1.f;
   sgm_schedule win{};
@@ -1520,33 +1643,48 @@ int sgm_autotune(sgm_ctx *c, const sgm_frame *samples, int n, int reps, sgm_sche
   };
   // 1. lanes per horizontal scanline, horizontal costs from the volume; and
   //    64 lanes with the costs from sliding Census windows, where it applies
+  //    (all with the per-direction kernels)
   const int lanes[3] = {16, 32, 64};
   for (int ci = 0; ci < 3; ++ci) {
     if (!agg_hlps_ok(k_of(sample->p), lanes[ci])) continue;
     sgm_schedule sc{};
     sc.h_lanes = lanes[ci];
     sc.h_costs = SGM_HCOSTS_VOLUME;
+    sc.two_pass = SGM_TWOPASS_OFF;
     CHECK(consider(ci, sc));
   }
   if (hcodes_ok(sample->p, 64)) {
     sgm_schedule sc{};
     sc.h_lanes = 64;
     sc.h_costs = SGM_HCOSTS_CODES;
+    sc.two_pass = SGM_TWOPASS_OFF;
     CHECK(consider(3, sc));
   }
-  // 2. disparity-selection block size
-  const int threads[3] = {256, 512, 1024};
-  const sgm_schedule base = win;
-  for (int ci = 0; ci < 3; ++ci) {
-    sgm_schedule sc = base;
-    sc.disp_threads = threads[ci];
-    CHECK(consider(4 + ci, sc));
+  // 2. the two-pass schedule with wide and narrow stripes
+  if (twopass_ok(sample->p)) {
+    const sgm_schedule base = win;
+    const int modes[2] = {SGM_TWOPASS_WIDE, SGM_TWOPASS_NARROW};
+    for (int ci = 0; ci < 2; ++ci) {
+      sgm_schedule sc = base;
+      sc.two_pass = modes[ci];
+      CHECK(consider(4 + ci, sc));
+    }
   }
-  // 3. the single-pass sweep, for frames it can take
+  // 3. disparity-selection block size (the per-direction schedule's kernel)
+  if (win.two_pass == SGM_TWOPASS_OFF) {
+    const int threads[3] = {256, 512, 1024};
+    const sgm_schedule base = win;
+    for (int ci = 0; ci < 3; ++ci) {
+      sgm_schedule sc = base;
+      sc.disp_threads = threads[ci];
+      CHECK(consider(6 + ci, sc));
+    }
+  }
+  // 4. the single-pass sweep, for frames it can take
   if (sweep_ok(sample->p)) {
     sgm_schedule sc = win;
     sc.sweep = 1;
-    CHECK(consider(7, sc));
+    CHECK(consider(9, sc));
   }
   CHECK(sgm_set_schedule(c, &sample->p, &win));
   if (best) *best = win;

@@ -172,6 +172,38 @@ struct UVJob {
 void launch_uv(std::vector<UVJob> jobs, hipStream_t s);
 
 
+// ------------------------------------------------- two-pass stripes
+// The vertical and two diagonal paths of an 8-path frame (T->B and TL->BR in
+// a top-down pass, B->T and BR->TL in a bottom-up pass), one workgroup per
+// stripe of 4 * waves columns; the up pass also sums S over all 8 paths and
+// selects D_L and the right-view keys (disparity kernel layout, segments of
+// one stripe).  Eligible frames: Census costs (uint8 volume), uint8 path
+// costs, all 8 paths.
+struct StripeJob {
+  const uint8_t *cost;  // [H][W][Dp]
+  uint16_t *sd;         // S_D = L_TB + L_TLBR, uint16 [H][W][Dp] (down: written, up: read)
+  const uint8_t *lr4;   // up: the uint8 path costs of L->R, R->L, TR->BL, BL->TR [4][H][W][Dp]
+  uint64_t *bnd;        // [nstripes][H][Dp / 2]: each stripe's published edge pixel per row
+  uint32_t *sync;       // [0] down ticket counter, [1] error flag, [2] up ticket counter
+  uint16_t *dl;         // up: D_L [H][W]
+  uint32_t *part;       // up with lr_check: [H][nstripes][4 * waves + D - 1] zone keys
+  int W, H, D, Dp, p1, p2, lr_check;
+  int nstripes;         // set by launch_stripes
+  uint32_t epoch;       // tag of this launch's edge words (never 0, new per launch)
+  int blk0;
+};
+constexpr int kSyncWords = 4;
+// LDS bytes of a stripe workgroup.
+size_t stripe_lds(int K, int D, int waves);
+// One launch per job table; K = agg_k(D) of every job; waves: 8 or 16.
+void launch_stripes(std::vector<StripeJob> jobs, int K, bool up, int waves, hipStream_t s);
+struct SyncZeroJob {
+  uint32_t *p;
+  int words;
+  int blk0;
+};
+void launch_zero_sync(std::vector<SyncZeroJob> jobs, hipStream_t s);
+
 // ----------------------------------------------------- single-pass sweep
 // The forward path set {L2R, TL2BR, T2B, TR2BL} (all predecessors lie above
 // or to the left) in one top-down sweep per frame: costs from the Census

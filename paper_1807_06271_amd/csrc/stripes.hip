@@ -1,0 +1,404 @@
+// Two-pass schedule of the 8-path aggregation with disparity selection fused
+// into the second pass (section 3.1.3: the forward paths in one pass over the
+// image and the backward paths in a second pass from back to front; equation
+// (2) per path, S the sum over paths, WTA and the right-view disparity of
+// section 3.1.4).
+//
+// The four paths whose predecessor lies in the row above or on the same row
+// to the left or right (L->R, R->L, TR->BL, BL->TR) run as ordinary
+// per-direction waves (agg_kernel) into four uint8 path-cost slots.  The
+// vertical and the two remaining diagonal paths run here, a frame split into
+// stripes of SW = 4 * WAVES columns, one workgroup per stripe walking the
+// rows:
+//
+//   down pass (T->B, TL->BR), rows top to bottom: writes S_D = L_TB + L_TLBR
+//     as uint16 [H][W][Dp];
+//   up pass (B->T, BR->TL), rows bottom to top: S = S_D + L_BT + L_BRTL + the
+//     four slots, then the WTA map D_L and each (row, stripe)'s right-view
+//     keys, in the layout of the disparity kernel's row segments (segment
+//     length SW), so that the LR check and the median read them unchanged.
+//
+// Lane layout: 16 lanes per pixel (a DPP row), lane j owning the K
+// disparities jK .. jK+K-1, four pixels per wave, consecutive pixels in
+// consecutive rows of a wave.  A pixel's vertical predecessor is its own
+// registers; the diagonal predecessor (x -/+ 1 of the previous row) comes
+// from a double-buffered LDS row of the stripe's path costs, and at the
+// stripe's edge from the neighbouring stripe: the edge pixel's path costs of
+// every row are published as 64-bit words {two 16-bit path costs, epoch}
+// with device-scope relaxed atomic stores; the consumer loads them with
+// device-scope atomic loads (one row ahead) and retries until every word
+// carries the launch's epoch.  The epoch in the word makes a stale record
+// of an earlier launch unmistakable, and a 64-bit store is single-copy
+// atomic, so neither fences nor flags are needed.
+//
+// Workgroups take their stripe from a ticket counter (one atomic add each):
+// a stripe waits only for the stripe before it in ticket order, which took
+// its ticket earlier and is therefore running or done, so the waits always
+// end whatever the number of workgroups resident at once.  A wait is also
+// bounded (it then records an error and goes on).
+#include "device_util.h"
+
+namespace sgmk {
+
+namespace {
+
+typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ u16x2 as_pair(uint32_t v) { return __builtin_bit_cast(u16x2, v); }
+__device__ __forceinline__ uint32_t as_u32(u16x2 v) { return __builtin_bit_cast(uint32_t, v); }
+__device__ __forceinline__ u16x2 pmin(u16x2 a, u16x2 b) { return __builtin_elementwise_min(a, b); }
+__device__ __forceinline__ u16x2 padd_sat(u16x2 a, u16x2 b) { return __builtin_elementwise_add_sat(a, b); }
+
+constexpr uint32_t kInf = 0xFFFFFFFFu;
+constexpr int kSpinLimit = 1 << 22;  // boundary polls before a wait gives up
+
+// One pixel of equation (2) for the lane's K disparities (16 lanes per
+// pixel): Lp the predecessor's path costs (packed pairs), c the lane's K
+// uint8 costs (four per word).  Pairs with d >= D are forced to 0xFFFF.
+template <int K, bool PAD>
+__device__ __forceinline__ void recur(const u16x2 (&Lp)[K / 2], const uint32_t (&c)[K / 4], u16x2 P1, u16x2 P2,
+                                      const uint32_t (&padmask)[K / 2], u16x2 (&Lc)[K / 2]) {
+  constexpr int NP = K / 2;
+  const uint32_t prev = (uint32_t)__builtin_amdgcn_update_dpp((int)kInf, (int)as_u32(Lp[NP - 1]), kDppRowShr1,
+                                                              0xF, 0xF, false);
+  const uint32_t next = (uint32_t)__builtin_amdgcn_update_dpp((int)kInf, (int)as_u32(Lp[0]), kDppRowShl1, 0xF,
+                                                              0xF, false);
+  // Nb[q] = (L[2q-1], L[2q]): pair q's d-1 values in Nb[q], its d+1 values in Nb[q+1]
+  u16x2 Nb[NP + 1];
+  Nb[0] = as_pair(__builtin_amdgcn_alignbit(as_u32(Lp[0]), prev, 16));
+#pragma unroll
+  for (int q = 1; q < NP; ++q) Nb[q] = as_pair(__builtin_amdgcn_alignbit(as_u32(Lp[q]), as_u32(Lp[q - 1]), 16));
+  Nb[NP] = as_pair(__builtin_amdgcn_alignbit(next, as_u32(Lp[NP - 1]), 16));
+  u16x2 A[NP];
+#pragma unroll
+  for (int q = 0; q < NP; ++q) A[q] = pmin(padd_sat(pmin(Nb[q], Nb[q + 1]), P1), Lp[q]);
+  u16x2 lm = Lp[0];
+#pragma unroll
+  for (int q = 1; q < NP; ++q) lm = pmin(lm, Lp[q]);
+  const uint32_t mp = row16_allmin_u32(min((uint32_t)lm.x, (uint32_t)lm.y));
+  const u16x2 M = {(unsigned short)mp, (unsigned short)mp};
+  const u16x2 MP2 = padd_sat(M, P2);
+#pragma unroll
+  for (int q = 0; q < NP; ++q) {
+    const uint32_t sel = (q & 1) ? 0x0c030c02u : 0x0c010c00u;  // bytes 2q, 2q+1 of the lane's costs
+    const u16x2 C = as_pair(__builtin_amdgcn_perm(0u, c[q >> 1], sel));
+    u16x2 v = pmin(A[q], MP2) - M + C;
+    if (PAD) v = as_pair(as_u32(v) | padmask[q]);
+    Lc[q] = v;
+  }
+}
+
+// LDS slot of the right-view key of zone position i (two padding slots per K
+// positions: the lanes of a pixel update positions K apart, the pixels of a
+// wave consecutive positions, and a half wave then hits 32 banks).
+template <int K>
+__host__ __device__ constexpr int zslot(int i) {
+  if constexpr ((K & (K - 1)) == 0) return i + 2 * (i / K);
+  else return i + (i >> 3);
+}
+
+}  // namespace
+
+template <int K, bool UP, int WAVES, bool PAD>
+__global__ __launch_bounds__(WAVES * 64) void stripe_kernel(JobTable<StripeJob> t) {
+  constexpr int NP = K / 2, NW = K / 4, SW = 4 * WAVES;
+  constexpr int PFR = UP ? 1 : 4, ER = PFR;  // rows of costs and of edge records in flight
+  extern __shared__ uint32_t lds[];
+  __shared__ int s_ticket;
+  // ticket counters: word 0 (down pass) and word 2 (up pass) of the table's
+  // first job
+  if (threadIdx.x == 0) s_ticket = (int)atomicAdd(t.j[0].sync + (UP ? 2 : 0), 1u);
+  __syncthreads();
+  const int tk = s_ticket;
+  // every workgroup of the grid gets one of the grid's tickets; one beyond
+  // them (counters not cleared) takes no stripe
+  if (tk >= t.j[t.n - 1].blk0 + t.j[t.n - 1].nstripes) return;
+  const int ji = find_job(t.j, t.n, tk);
+  const StripeJob &J = t.j[ji];
+  const int W = J.W, H = J.H, D = J.D, Dp = J.Dp;
+  const int ns = J.nstripes;
+  const int si = tk - J.blk0;
+  const int s = UP ? ns - 1 - si : si;  // up pass: stripes from the right
+  const int x0 = s * SW;
+  const int lane = (int)(threadIdx.x & 63), wave = (int)(threadIdx.x >> 6);
+  const int px = wave * 4 + (lane >> 4), j = lane & 15;
+  const int x = x0 + px;
+  const bool live = x < W;
+  const int xc = min(x, W - 1);  // loads of pixels right of the image read the last column
+  const int dbase = j * K;
+  const int dvalid = PAD ? min(K, max(0, D - dbase)) : K;
+  uint32_t padmask[NP];
+#pragma unroll
+  for (int q = 0; q < NP; ++q)
+    padmask[q] = (2 * q < dvalid ? 0u : 0xFFFFu) | (2 * q + 1 < dvalid ? 0u : 0xFFFF0000u);
+  const u16x2 P1 = {(unsigned short)J.p1, (unsigned short)J.p1};
+  const u16x2 P2 = {(unsigned short)J.p2, (unsigned short)J.p2};
+  const uint32_t epoch = J.epoch;
+
+  // LDS: the diagonal path costs of the stripe's pixels for two rows
+  // ([2][SW][Dp] uint16, as words), then (up pass with the LR check) two
+  // zone key rows
+  uint32_t *dg = lds;
+  const int dg_words = SW * Dp / 2;
+  const int zn = SW + D - 1;  // zone positions of a segment of SW pixels
+  const int zslots = zslot<K>(zn - 1) + 1;
+  uint32_t *zone = lds + 2 * dg_words;
+  // the neighbour's edge pixel of the previous row ([Dp] uint16 as words)
+  uint32_t *eslot = zone + 2 * zslots;
+  const int zr = x0 - D + 1;
+  if (UP && J.lr_check) {
+    for (int i = (int)threadIdx.x; i < 2 * zslots; i += WAVES * 64) zone[i] = kInf;
+  }
+
+  // the stripe's edge: the neighbour whose diagonal predecessor we take
+  // (down: x0 - 1 from stripe s - 1; up: x0 + SW from stripe s + 1), and
+  // the pixel we publish for the stripe on the other side.  The wave that
+  // holds the taking pixel (the edge wave) keeps the neighbour's records of
+  // the next ER rows in flight, two words per lane, and passes each row's
+  // record to the taking pixel through eslot.
+  const bool takes_edge = UP ? (px == SW - 1 && s + 1 < ns) : (px == 0 && s > 0);
+  const bool gives_edge = UP ? (px == 0 && s > 0) : (px == SW - 1 && s + 1 < ns);
+  const bool edge_wave = (UP ? wave == WAVES - 1 : wave == 0) && (UP ? s + 1 < ns : s > 0);
+  const uint64_t *bnd_in = J.bnd + ((int64_t)(UP ? s + 1 : s - 1) * H) * (Dp / 2);
+  uint64_t *bnd_out = J.bnd + ((int64_t)s * H) * (Dp / 2) + dbase / 2;
+  const int ew = 2 * lane;                  // this lane's first word of a record
+  const bool ew_live = ew < Dp / 2;         // Dp / 2 words per record (even)
+  bool failed = false;
+
+  const int ystep = UP ? -1 : 1;
+  const int y_first = UP ? H - 1 : 0;
+  const int64_t row_cells = (int64_t)W * Dp;
+  const uint8_t *cbase = J.cost + (int64_t)xc * Dp + dbase;
+
+  u16x2 Lv[NP];  // vertical path: this pixel's previous row
+#pragma unroll
+  for (int q = 0; q < NP; ++q) Lv[q] = as_pair(padmask[q]);
+  // the edge records of pass rows r .. r + ER - 1 (row r's record is the
+  // predecessor of pass row r + 1)
+  uint64_t erec[ER][2] = {};
+  auto load_rec = [&](int pr, uint64_t (&w)[2]) {
+    const uint64_t *q = bnd_in + (int64_t)(y_first + ystep * pr) * (Dp / 2) + ew;
+    w[0] = __hip_atomic_load(q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    w[1] = __hip_atomic_load(q + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  };
+  if (edge_wave && ew_live) {
+#pragma unroll
+    for (int u = 0; u < ER; ++u) load_rec(min(u, H - 1), erec[u]);
+  }
+  // the costs of the next PFR rows in a register ring (loads are
+  // unconditional: past the last row they re-read it)
+  U32N<NW> ring[PFR];
+#pragma unroll
+  for (int u = 0; u < PFR; ++u)
+    ring[u] = *reinterpret_cast<const U32N<NW> *>(cbase + (int64_t)(y_first + ystep * min(u, H - 1)) * row_cells);
+  __syncthreads();  // zone rows cleared
+
+  auto row = [&](int r, U32N<NW> &slot, uint64_t (&prev_rec)[2]) {
+    const int y = y_first + r * ystep;
+    const int buf = r & 1;
+    // the edge wave: validate the neighbour's record of pass row r - 1 (its
+    // words carry this launch's epoch once written), hand it to the taking
+    // pixel through eslot, and fetch the record of pass row r - 1 + ER
+    if (edge_wave && r > 0) {
+      bool ok = !ew_live || ((uint32_t)(prev_rec[0] >> 32) == epoch && (uint32_t)(prev_rec[1] >> 32) == epoch);
+      for (int n = 0; __builtin_amdgcn_ballot_w64(!ok) != 0 && !failed; ++n) {
+        if (n == kSpinLimit) {
+          failed = true;
+          __hip_atomic_store(J.sync + 1, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          break;
+        }
+        __builtin_amdgcn_s_sleep(2);
+        if (ew_live) {
+          load_rec(r - 1, prev_rec);
+          ok = (uint32_t)(prev_rec[0] >> 32) == epoch && (uint32_t)(prev_rec[1] >> 32) == epoch;
+        }
+      }
+      if (ew_live) {
+        eslot[ew] = (uint32_t)prev_rec[0];
+        eslot[ew + 1] = (uint32_t)prev_rec[1];
+        if (r - 1 + ER < H) load_rec(r - 1 + ER, prev_rec);
+      }
+    }
+    U32N<NW> cw = slot;
+    slot = *reinterpret_cast<const U32N<NW> *>(cbase + (int64_t)(y_first + ystep * min(r + PFR, H - 1)) * row_cells);
+    uint32_t c[NW];
+#pragma unroll
+    for (int i = 0; i < NW; ++i) c[i] = cw.v[i];
+    // up pass: the path-cost slots and S_D of this pixel, loaded early
+    U32N<4 * NW> sl;
+    U32N<NP> sd;
+    const int64_t cell = ((int64_t)y * W + xc) * Dp + dbase;
+    if constexpr (UP) {
+      const int64_t slot = (int64_t)H * row_cells;
+#pragma unroll
+      for (int p = 0; p < 4; ++p) {
+        const U32N<NW> v = load_nt<NW>(J.lr4 + p * slot + cell);
+#pragma unroll
+        for (int i = 0; i < NW; ++i) sl.v[p * NW + i] = v.v[i];
+      }
+      sd = load_nt<NP>(J.sd + cell);
+    }
+
+    // vertical path
+    u16x2 Lcv[NP];
+    recur<K, PAD>(Lv, c, P1, P2, padmask, Lcv);
+    // diagonal path: the predecessor x -/+ 1 of the previous row
+    u16x2 Lp[NP];
+    if (r == 0) {
+#pragma unroll
+      for (int q = 0; q < NP; ++q) Lp[q] = as_pair(padmask[q]);
+    } else {
+      const int pp = UP ? px + 1 : px - 1;  // predecessor pixel in the stripe
+      const bool outside = UP ? (x + 1 >= W) : (x == 0);
+      if (outside) {  // no predecessor: the path starts here
+#pragma unroll
+        for (int q = 0; q < NP; ++q) Lp[q] = as_pair(padmask[q]);
+      } else if (takes_edge) {  // the neighbour stripe's edge pixel (written by this wave)
+        const U32N<NP> v = *reinterpret_cast<const U32N<NP> *>(eslot + dbase / 2);
+#pragma unroll
+        for (int q = 0; q < NP; ++q) Lp[q] = as_pair(v.v[q]);
+      } else {
+        const uint32_t *src = dg + (buf ^ 1) * dg_words + (pp * Dp + dbase) / 2;
+        const U32N<NP> v = *reinterpret_cast<const U32N<NP> *>(src);
+#pragma unroll
+        for (int q = 0; q < NP; ++q) Lp[q] = as_pair(v.v[q]);
+      }
+    }
+    u16x2 Lcd[NP];
+    recur<K, PAD>(Lp, c, P1, P2, padmask, Lcd);
+    {  // this row's diagonal path costs for the next row's predecessors
+      U32N<NP> v;
+#pragma unroll
+      for (int q = 0; q < NP; ++q) v.v[q] = as_u32(Lcd[q]);
+      *reinterpret_cast<U32N<NP> *>(dg + buf * dg_words + (px * Dp + dbase) / 2) = v;
+    }
+    if (gives_edge) {
+#pragma unroll
+      for (int q = 0; q < NP; ++q)
+        __hip_atomic_store(bnd_out + (int64_t)y * (Dp / 2) + q, (uint64_t)as_u32(Lcd[q]) | (uint64_t)epoch << 32,
+                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+#pragma unroll
+    for (int q = 0; q < NP; ++q) Lv[q] = Lcv[q];
+
+    if constexpr (!UP) {
+      if (live) {
+        U32N<NP> o;
+#pragma unroll
+        for (int q = 0; q < NP; ++q) o.v[q] = as_u32(Lcv[q]) + as_u32(Lcd[q]);
+        store_nt<NP>(J.sd + cell, o);
+      }
+    } else {
+      // S over the eight paths as packed 16-bit pairs (no carry reaches a
+      // valid half: every valid sum is below 65536, and padding halves lie
+      // above the valid ones)
+      uint32_t acc[NP];
+#pragma unroll
+      for (int q = 0; q < NP; ++q) acc[q] = sd.v[q] + as_u32(Lcv[q]) + as_u32(Lcd[q]);
+#pragma unroll
+      for (int p = 0; p < 4; ++p)
+#pragma unroll
+        for (int i = 0; i < NW; ++i) {
+          const uint32_t w = sl.v[p * NW + i];
+          acc[2 * i] += __builtin_amdgcn_perm(0u, w, 0x0c010c00u);
+          acc[2 * i + 1] += __builtin_amdgcn_perm(0u, w, 0x0c030c02u);
+        }
+      uint32_t best = kInf;
+      uint32_t *zrow = zone + buf * zslots;
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        if (k < dvalid) {
+          const int d = dbase + k;
+          const uint32_t Sd = (k & 1) ? acc[k >> 1] >> 16 : acc[k >> 1] & 0xFFFFu;
+          const uint32_t key = Sd << 8 | (uint32_t)d;
+          best = min(best, key);
+          if (J.lr_check && live && x >= d) atomicMin(&zrow[zslot<K>(x - d - zr)], key);
+        }
+      }
+      best = row16_allmin_u32(best);
+      if (live && j == 0) J.dl[(int64_t)y * W + x] = (uint16_t)(best & 0xFF);
+    }
+    __syncthreads();
+    if (UP && J.lr_check) {
+      // the row's zone keys out, and the zone row cleared for two rows on
+      uint32_t *zrow = zone + buf * zslots;
+      uint32_t *part = J.part + ((int64_t)y * ns + s) * zn;
+      for (int i = (int)threadIdx.x; i < zn; i += WAVES * 64) {
+        part[i] = zrow[zslot<K>(i)];
+        zrow[zslot<K>(i)] = kInf;
+      }
+    }
+  };
+  // rows in blocks of PFR (= ER): ring slots are compile-time indices
+  int r0 = 0;
+  for (; r0 + PFR <= H; r0 += PFR) {
+#pragma unroll
+    for (int u = 0; u < PFR; ++u) row(r0 + u, ring[u], erec[(u + ER - 1) % ER]);
+  }
+#pragma unroll
+  for (int u = 0; u < PFR; ++u)
+    if (r0 + u < H) row(r0 + u, ring[u], erec[(u + ER - 1) % ER]);
+}
+
+void launch_zero_sync(std::vector<SyncZeroJob> jobs, hipStream_t s);
+
+namespace {
+__global__ __launch_bounds__(256) void zero_kernel(JobTable<SyncZeroJob> t) {
+  const int ji = find_job(t.j, t.n, (int)blockIdx.x);
+  const SyncZeroJob &J = t.j[ji];
+  const int i = ((int)blockIdx.x - J.blk0) * 256 + (int)threadIdx.x;
+  if (i < J.words) J.p[i] = 0;
+}
+}  // namespace
+
+void launch_zero_sync(std::vector<SyncZeroJob> jobs, hipStream_t s) {
+  for_each_table(
+      jobs, [](const SyncZeroJob &j) { return (long)((j.words + 255) / 256); },
+      [&](const JobTable<SyncZeroJob> &t, int blocks) {
+        hipLaunchKernelGGL(zero_kernel, dim3(blocks), dim3(256), 0, s, t);
+      });
+}
+
+size_t stripe_lds(int K, int D, int waves) {
+  const int SW = 4 * waves, Dp = 16 * K;
+  const int zn = SW + D - 1;
+  const int zslots = (K & (K - 1)) == 0 ? zn - 1 + 2 * ((zn - 1) / K) + 1 : zn - 1 + ((zn - 1) >> 3) + 1;
+  return (size_t)2 * SW * Dp * 2 + (size_t)2 * zslots * 4 + (size_t)Dp * 2;
+}
+
+template <int K, bool UP, int WAVES>
+static void launch_kw(const JobTable<StripeJob> &t, int blocks, bool pad, size_t lds, hipStream_t s) {
+  if (pad) hipLaunchKernelGGL((stripe_kernel<K, UP, WAVES, true>), dim3(blocks), dim3(WAVES * 64), lds, s, t);
+  else hipLaunchKernelGGL((stripe_kernel<K, UP, WAVES, false>), dim3(blocks), dim3(WAVES * 64), lds, s, t);
+}
+
+template <int K, bool UP>
+static void launch_k(const JobTable<StripeJob> &t, int blocks, int waves, bool pad, size_t lds, hipStream_t s) {
+  if (waves == 16) launch_kw<K, UP, 16>(t, blocks, pad, lds, s);
+  else launch_kw<K, UP, 8>(t, blocks, pad, lds, s);
+}
+
+void launch_stripes(std::vector<StripeJob> jobs, int K, bool up, int waves, hipStream_t s) {
+  // one launch per table of jobs; the ticket counter of a table lives in its
+  // first job's sync words (the zero kernel cleared it)
+  bool pad = false;
+  int maxd = 1;
+  for (auto &j : jobs) {
+    pad |= j.D != j.Dp;
+    maxd = std::max(maxd, j.D);
+    j.nstripes = (j.W + 4 * waves - 1) / (4 * waves);
+  }
+  const size_t lds = stripe_lds(K, maxd, waves);
+  for_each_table(
+      jobs, [](const StripeJob &j) { return (long)j.nstripes; },
+      [&](const JobTable<StripeJob> &t, int blocks) {
+        switch (K) {
+          case 4: up ? launch_k<4, true>(t, blocks, waves, pad, lds, s) : launch_k<4, false>(t, blocks, waves, pad, lds, s); break;
+          case 8: up ? launch_k<8, true>(t, blocks, waves, pad, lds, s) : launch_k<8, false>(t, blocks, waves, pad, lds, s); break;
+          case 12: up ? launch_k<12, true>(t, blocks, waves, pad, lds, s) : launch_k<12, false>(t, blocks, waves, pad, lds, s); break;
+          default: up ? launch_k<16, true>(t, blocks, waves, pad, lds, s) : launch_k<16, false>(t, blocks, waves, pad, lds, s); break;
+        }
+      });
+}
+
+}  // namespace sgmk

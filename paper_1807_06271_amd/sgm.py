@@ -32,6 +32,7 @@ PATHS_HV4 = PATH_L2R | PATH_R2L | PATH_T2B | PATH_B2T
 PATHS_ALL8 = 0xFF
 COST_CENSUS, COST_SAD = 0, 1
 HCOSTS_DEFAULT, HCOSTS_VOLUME, HCOSTS_CODES = 0, 1, 2
+TWOPASS_DEFAULT, TWOPASS_OFF, TWOPASS_WIDE, TWOPASS_NARROW = 0, 1, 2, 3
 
 EXPORTS = ["sgm_validate", "sgm_create", "sgm_destroy", "sgm_last_error", "sgm_census", "sgm_cost",
            "sgm_cost_sad",
@@ -61,7 +62,7 @@ class sgm_params(ctypes.Structure):
 
 class sgm_schedule(ctypes.Structure):
     _fields_ = [("h_lanes", ctypes.c_int32), ("sweep", ctypes.c_int32), ("disp_threads", ctypes.c_int32),
-                ("h_costs", ctypes.c_int32)]
+                ("h_costs", ctypes.c_int32), ("two_pass", ctypes.c_int32)]
 
 
 class sgm_remap(ctypes.Structure):
@@ -461,12 +462,14 @@ def sgm_memory(ctx: Context):
 
 
 def sgm_set_schedule(ctx: Context, p: Params | None, h_lanes: int, sweep: bool = False,
-                     disp_threads: int = 0, h_costs: int = HCOSTS_DEFAULT) -> None:
+                     disp_threads: int = 0, h_costs: int = HCOSTS_DEFAULT,
+                     two_pass: int = TWOPASS_DEFAULT) -> None:
     """Schedule for frames of p's shape (p=None: the default): lanes per
     horizontal scanline, whether eligible frames use the single-pass sweep,
-    the disparity-selection block size (0: by block count), and where the
-    horizontal scanlines take their costs from (HCOSTS_*)."""
-    sc = sgm_schedule(h_lanes, int(bool(sweep)), int(disp_threads), int(h_costs))
+    the disparity-selection block size (0: by block count), where the
+    horizontal scanlines take their costs from (HCOSTS_*), and whether the
+    vertical and diagonal paths run as two stripe passes (TWOPASS_*)."""
+    sc = sgm_schedule(h_lanes, int(bool(sweep)), int(disp_threads), int(h_costs), int(two_pass))
     _check(lib().sgm_set_schedule(ctx.handle, ctypes.byref(p.c()) if p is not None else None,
                                   ctypes.byref(sc)), "sgm_set_schedule")
 
@@ -477,24 +480,26 @@ def sgm_get_schedule(ctx: Context, p: Params) -> int:
 
 
 def schedule_of(ctx: Context, p: Params):
-    """(h_lanes, sweep, disp_threads, h_costs) that sgm_submit would use for
-    frames like p."""
+    """(h_lanes, sweep, disp_threads, h_costs, two_pass) that sgm_submit
+    would use for frames like p."""
     sc = sgm_schedule()
     _check(lib().sgm_get_schedule(ctx.handle, ctypes.byref(p.c()), ctypes.byref(sc)), "sgm_get_schedule")
-    return sc.h_lanes, bool(sc.sweep), sc.disp_threads, sc.h_costs
+    return sc.h_lanes, bool(sc.sweep), sc.disp_threads, sc.h_costs, sc.two_pass
 
 
-AUTOTUNE_CANDIDATES = ("h_lanes=16", "h_lanes=32", "h_lanes=64", "h_costs=codes", "disp_threads=256",
-                       "disp_threads=512", "disp_threads=1024", "sweep")
+AUTOTUNE_CANDIDATES = ("h_lanes=16", "h_lanes=32", "h_lanes=64", "h_costs=codes", "two_pass=wide",
+                       "two_pass=narrow", "disp_threads=256", "disp_threads=512", "disp_threads=1024", "sweep")
+TWOPASS_NAMES = {TWOPASS_OFF: "off", TWOPASS_WIDE: "wide", TWOPASS_NARROW: "narrow"}
 
 
 def sgm_autotune(ctx: Context, sample, reps: int = 5):
     """Time the candidate schedules on `sample` (a Frame, or a list of
     Frames of one shape submitted as one batch) (lanes per horizontal
     scanline; horizontal costs from Census codes where that applies; the
-    disparity block size; the sweep where it applies) and keep the fastest
-    for its shape.  Returns (schedule, {candidate: ms per frame}) with
-    schedule = {"h_lanes", "sweep", "disp_threads", "h_costs"}."""
+    two-pass stripes where they apply; the disparity block size; the sweep
+    where it applies) and keep the fastest for its shape.  Returns
+    (schedule, {candidate: ms per submit}) with schedule = {"h_lanes",
+    "sweep", "disp_threads", "h_costs", "two_pass"}."""
     frames = list(sample) if isinstance(sample, (list, tuple)) else [sample]
     arr = (sgm_frame * len(frames))(*[f.c() for f in frames])
     best = sgm_schedule()
@@ -502,7 +507,8 @@ def sgm_autotune(ctx: Context, sample, reps: int = 5):
     ms = (ctypes.c_float * n)()
     _check(lib().sgm_autotune(ctx.handle, arr, len(frames), reps, ctypes.byref(best), ms, n), "sgm_autotune")
     sched = {"h_lanes": best.h_lanes, "sweep": bool(best.sweep), "disp_threads": best.disp_threads,
-             "h_costs": "codes" if best.h_costs == HCOSTS_CODES else "volume"}
+             "h_costs": "codes" if best.h_costs == HCOSTS_CODES else "volume",
+             "two_pass": TWOPASS_NAMES.get(best.two_pass, "off")}
     return sched, {name: ms[i] for i, name in enumerate(AUTOTUNE_CANDIDATES) if ms[i] >= 0}
 
 

@@ -131,20 +131,26 @@ def test_autotune_keeps_a_valid_schedule(env):
     f = sgm.Frame.alloc(p, to_dev(torch, left), to_dev(torch, right))
     best, ms = sgm.sgm_autotune(ctx, f, reps=2)
     # first lanes (16, 32, 64 with costs from the volume, 64 with costs from
-    # Census windows), then the disparity block size from that winner; no
-    # sweep (9x7 codes, D = 128)
+    # Census windows), then the two-pass stripes (8 paths, uint8 path
+    # costs), then -- only if the per-direction kernels still win -- the
+    # disparity block size; no sweep (9x7 codes, D = 128)
     stage1 = ("h_lanes=16", "h_lanes=32", "h_lanes=64", "h_costs=codes")
-    want = set(stage1) | {"disp_threads=256", "disp_threads=512", "disp_threads=1024"}
+    want = set(stage1) | {"two_pass=wide", "two_pass=narrow"}
+    if best["two_pass"] == "off":
+        want |= {"disp_threads=256", "disp_threads=512", "disp_threads=1024"}
     assert set(ms) == want
     assert all(v > 0 for v in ms.values())
     first = min(stage1, key=lambda k: ms[k])
     assert best["h_lanes"] == (64 if first == "h_costs=codes" else int(first.split("=")[1]))
     assert (best["h_costs"] == "codes") == (first == "h_costs=codes") and not best["sweep"]
     overall = min(ms.values())
-    chosen = "disp_threads=%d" % best["disp_threads"] if best["disp_threads"] else first
+    if best["two_pass"] != "off":
+        chosen = "two_pass=" + best["two_pass"]
+    else:
+        chosen = "disp_threads=%d" % best["disp_threads"] if best["disp_threads"] else first
     assert ms[chosen] == overall
     hc = sgm.HCOSTS_CODES if best["h_costs"] == "codes" else sgm.HCOSTS_VOLUME
-    assert sgm.schedule_of(ctx, p) == (best["h_lanes"], False, best["disp_threads"], hc)
+    assert sgm.schedule_of(ctx, p)[:4] == (best["h_lanes"], False, best["disp_threads"], hc)
     sgm.sgm_wait(ctx, sgm.sgm_submit(ctx, [f]))
     want = O.sgm(left, right, D, 9, 7, 0xFF, 10, 120, True, 1, 3)
     assert_equal(to_np(f.disp), want["disp"], "disp after autotune")

@@ -1,0 +1,160 @@
+"""The two-pass stripe schedule (GPU required): T->B and TL->BR in a
+top-down pass over stripes of 64 or 32 columns, B->T and BR->TL with the sum
+over all 8 paths and the disparity selection in a bottom-up pass (section
+3.1.3), the four other paths in per-direction kernels.  Every shape -- one
+stripe or many, a ragged last stripe, padded disparity rows, every
+disparities-per-lane width, with and without the LR check and median --
+must give the oracle's disparity map and U/V maps bit for bit."""
+import numpy as np
+import pytest
+
+from gen import synthetic
+from gpu_util import announce, assert_equal, gpu_or_skip, to_dev, to_np
+from oracle import oracle as O
+
+pytestmark = pytest.mark.gpu
+
+# W, H, D, census, p1, p2, lr_check, median
+SHAPES = [
+    (203, 61, 128, (9, 7), 10, 120, 1, 3),     # 4 wide stripes, the last ragged
+    (64, 20, 64, (5, 5), 8, 32, 1, 3),         # exactly one wide stripe
+    (97, 33, 256, (9, 7), 10, 120, 1, 5),
+    (140, 37, 100, (9, 7), 10, 120, 1, 3),     # padded disparity rows
+    (120, 30, 192, (9, 7), 10, 120, 0, 0),     # 12 disparities per lane, no LR, no median
+    (33, 9, 60, (5, 5), 7, 90, 1, 0),          # LR check without a median
+    (1, 5, 64, (5, 5), 10, 120, 1, 3),         # one column
+    (300, 1, 128, (9, 7), 10, 120, 1, 3),      # one row
+    (257, 40, 250, (9, 7), 10, 120, 1, 3),
+]
+
+
+@pytest.fixture(scope="module")
+def env():
+    torch = gpu_or_skip()
+    from paper_1807_06271_amd import sgm
+    ctx = sgm.Context(0)
+    yield torch, sgm, ctx
+    torch.cuda.synchronize()
+    ctx.close()
+
+
+def params(sgm, W, H, D, cw, ch, p1, p2, lr, med):
+    return sgm.Params(width=W, height=H, max_disp=D, census_w=cw, census_h=ch, path_mask=0xFF, p1=p1, p2=p2,
+                      lr_check=lr, median=med, invalid=65535 if D > 255 else 255)
+
+
+def oracle_maps(p, left, right):
+    out = O.sgm(left, right, p.max_disp, p.census_w, p.census_h, p.path_mask, p.p1, p.p2, bool(p.lr_check),
+                p.lr_max_diff, p.median, p.inv())
+    return out["disp"], out["umap"], out["vmap"]
+
+
+def check(f, want, tag):
+    assert_equal(to_np(f.disp), want[0], "disp " + tag)
+    assert_equal(to_np(f.umap), want[1], "umap " + tag)
+    assert_equal(to_np(f.vmap), want[2], "vmap " + tag)
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+@pytest.mark.parametrize("mode", ["wide", "narrow"])
+def test_two_pass_matches_oracle(env, shape, mode):
+    torch, sgm, ctx = env
+    W, H, D, (cw, ch), p1, p2, lr, med = shape
+    announce("two-pass", mode, shape)
+    left, right, _ = synthetic.make_pair("kitti", W + 7 * D + H, W, H, D)
+    p = params(sgm, W, H, D, cw, ch, p1, p2, lr, med)
+    tp = sgm.TWOPASS_WIDE if mode == "wide" else sgm.TWOPASS_NARROW
+    sgm.sgm_set_schedule(ctx, p, 0, two_pass=tp)
+    assert sgm.schedule_of(ctx, p)[4] == tp
+    f = sgm.Frame.alloc(p, to_dev(torch, left), to_dev(torch, right))
+    sgm.sgm_wait(ctx, sgm.sgm_submit(ctx, [f]))
+    check(f, oracle_maps(p, left, right), "%s %s" % (mode, shape))
+
+
+def test_two_pass_does_not_apply_elsewhere(env):
+    # 4 paths, SAD costs, 16-bit path costs: per-direction kernels whatever
+    # the schedule says
+    torch, sgm, ctx = env
+    announce("two-pass fallback")
+    for kw in (dict(width=90, height=20, max_disp=64, path_mask=0x55),
+               dict(width=90, height=20, max_disp=64, census_w=5, census_h=5, cost=sgm.COST_SAD, p1=200, p2=800),
+               dict(width=90, height=20, max_disp=64, p2=300)):
+        p = sgm.Params(**kw)
+        sgm.sgm_set_schedule(ctx, p, 0, two_pass=sgm.TWOPASS_WIDE)
+        assert sgm.schedule_of(ctx, p)[4] == sgm.TWOPASS_OFF, kw
+        left, right, _ = synthetic.make_pair("kitti", 5, p.width, p.height, p.max_disp)
+        f = sgm.Frame.alloc(p, to_dev(torch, left), to_dev(torch, right))
+        sgm.sgm_wait(ctx, sgm.sgm_submit(ctx, [f]))
+        want = O.sgm(left, right, p.max_disp, p.census_w, p.census_h, p.path_mask, p.p1, p.p2, True, 1, 3,
+                     cost_kind=p.cost)
+        assert_equal(to_np(f.disp), want["disp"], "disp %s" % kw)
+
+
+def test_mixed_batch_repeated_split_and_graphs(env):
+    # frames on the two-pass schedule next to frames on the per-direction
+    # kernels in one batch; the same batch again on the same scratch (stale
+    # edge words of the previous launch must never be taken), split over the
+    # context's streams, and replayed in graph mode
+    torch, sgm, ctx = env
+    announce("two-pass mixed batch")
+    specs = [(150, 40, 128, 0xFF, sgm.TWOPASS_WIDE), (150, 40, 64, 0xFF, sgm.TWOPASS_NARROW),
+             (130, 30, 128, 0x0F, sgm.TWOPASS_WIDE), (90, 44, 256, 0xFF, sgm.TWOPASS_OFF),
+             (70, 25, 64, 0xFF, sgm.TWOPASS_WIDE)]
+    frames, want = [], []
+    for i, (W, H, D, mask, tp) in enumerate(specs):
+        left, right, _ = synthetic.make_pair("kitti", 300 + i, W, H, D)
+        p = sgm.Params(width=W, height=H, max_disp=D, path_mask=mask, invalid=65535 if D > 255 else 255)
+        sgm.sgm_set_schedule(ctx, p, 0, two_pass=tp)
+        frames.append(sgm.Frame.alloc(p, to_dev(torch, left), to_dev(torch, right)))
+        o = O.sgm(left, right, D, 9, 7, mask, 10, 120, True, 1, 3, p.inv())
+        want.append((o["disp"], o["umap"], o["vmap"]))
+    try:
+        for split in (1, 4):
+            sgm.sgm_set_split(ctx, split)
+            for rep in range(3):
+                for f in frames:
+                    f.disp.view(torch.int16).fill_(7)
+                torch.cuda.synchronize()
+                sgm.sgm_wait(ctx, sgm.sgm_submit(ctx, frames))
+                for i, f in enumerate(frames):
+                    check(f, want[i], "split %d rep %d frame %d" % (split, rep, i))
+        sgm.sgm_set_split(ctx, 1)
+        sgm.sgm_set_graphs(ctx, True)
+        for rep in range(3):
+            for f in frames:
+                f.disp.view(torch.int16).fill_(7)
+            torch.cuda.synchronize()
+            sgm.sgm_wait(ctx, sgm.sgm_submit(ctx, frames))
+            for i, f in enumerate(frames):
+                check(f, want[i], "graph replay %d frame %d" % (rep, i))
+    finally:
+        sgm.sgm_set_graphs(ctx, False)
+        sgm.sgm_set_split(ctx, 4)
+
+
+def test_many_frames_in_one_launch(env):
+    # 30 frames of two shapes: more stripe workgroups than the chip holds at
+    # once in one launch (tickets keep the waits finite); two tables of jobs
+    torch, sgm, ctx = env
+    announce("two-pass 30 frames")
+    frames, want = [], []
+    for i in range(30):
+        W, H, D = (640, 48, 128) if i % 2 == 0 else (333, 61, 64)
+        left, right, _ = synthetic.make_pair("kitti", 500 + i, W, H, D)
+        p = sgm.Params(width=W, height=H, max_disp=D)
+        sgm.sgm_set_schedule(ctx, p, 0, two_pass=sgm.TWOPASS_NARROW)
+        frames.append(sgm.Frame.alloc(p, to_dev(torch, left), to_dev(torch, right)))
+        if i < 4:
+            o = O.sgm(left, right, D, 9, 7, 0xFF, 10, 120, True, 1, 3)
+            want.append((o["disp"], o["umap"], o["vmap"]))
+    sgm.sgm_wait(ctx, sgm.sgm_submit(ctx, frames))
+    for i in range(4):
+        check(frames[i], want[i], "frame %d" % i)
+    # the rest equal the same frames run alone on the per-direction kernels
+    for i in range(4, 30, 5):
+        f = frames[i]
+        sgm.sgm_set_schedule(ctx, f.p, 0, two_pass=sgm.TWOPASS_OFF)
+        g = sgm.Frame.alloc(f.p, f.left, f.right)
+        sgm.sgm_wait(ctx, sgm.sgm_submit(ctx, [g]))
+        assert np.array_equal(to_np(g.disp), to_np(f.disp)), i
+        assert np.array_equal(to_np(g.umap), to_np(f.umap)), i
