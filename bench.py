@@ -495,6 +495,22 @@ def agg_kernel_name(sched):
         256 // sched["h_lanes"], sched["h_lanes"], 2 if sched["h_costs"] == "codes" else 0)
 
 
+def dominant_kernel(p, frames, sched):
+    """(kernel name, library stage, algorithmic bytes per launch, unit
+    evaluations per launch, description) of the dominant kernel of the
+    schedule: the 8-direction aggregation launch, or -- on the two-pass
+    schedule -- the bottom-up stripe pass, which reads each cell's cost, its
+    uint16 S_D and the four uint8 per-direction path costs (7 B per cell)
+    for its two paths and the selection."""
+    if sched.get("two_pass", "off") == "off":
+        return (agg_kernel_name(sched), "aggregate", agg_alg_bytes(p, frames, sched), frames * p.disp_evals(),
+                "8 directions of %d frames in one launch" % frames)
+    waves = 16 if sched["two_pass"] == "wide" else 8
+    cells = p.width * p.height * p.max_disp
+    return ("stripe_kernel<16, true, %d, false>" % waves, "disparity", frames * 7 * cells, frames * 2 * cells,
+            "bottom-up stripe pass of %d frames: B->T, BR->TL, the 8-path sum and the selection" % frames)
+
+
 def agg_alg_bytes(p, frames, sched):
     """Algorithmic HBM bytes of one aggregation launch over `frames` frames of
     params p (8 paths): every direction writes its uint8 path costs (W*H*D);
@@ -611,12 +627,11 @@ def main():
     # roofline: the aggregation launch time from the events of the one-stream
     # timed loop, where it runs alone on the GPU (with batches overlapping on
     # several streams an event pair also spans the other batches' kernels)
-    agg_ms, agg_n = prof1["aggregate"]
+    kname, kstage, alg, kevals, kdesc = dominant_kernel(p, 8, sched)
+    agg_ms, agg_n = prof1[kstage]
     agg_avg = agg_ms / max(agg_n, 1)
-    agg_overlapped = prof["aggregate"][0] / max(prof["aggregate"][1], 1)
-    alg = agg_alg_bytes(p, 8, sched)
+    agg_overlapped = prof[kstage][0] / max(prof[kstage][1], 1)
     achieved = alg / (agg_avg * 1e-3) / 1e9
-    kname = agg_kernel_name(sched)
     traffic = measured_traffic(kname, "traffic_agg_1920x1080_d256_batch8.json")
     valu = measured_valu(kname, "counters_1920x1080_d256_batch8.txt")
 
@@ -676,16 +691,16 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic,
-                     "kernel": kname + " (8 directions of 8 frames in one launch)",
-                     "alg_bytes_per_eval": round(alg / evals, 4),
-                     "alg_bytes_per_launch": alg, "evals_per_launch": evals,
+                     "kernel": kname + " (" + kdesc + ")",
+                     "alg_bytes_per_eval": round(alg / kevals, 4),
+                     "alg_bytes_per_launch": alg, "evals_per_launch": kevals,
                      "avg_launch_ms": round(agg_avg, 5), "launches": agg_n,
                      "timed_loop": "one stream (each launch alone on the GPU)",
                      "avg_launch_ms_overlapped": round(agg_overlapped, 5),
                      "traffic_frac": round(traffic / (agg_avg * 1e-3) / 1e9 / HBM_PEAK_GBS, 4) if traffic else None,
                      "valu_issue": valu,
                      "survey_bytes_per_eval": SURVEY_BYTES_PER_EVAL,
-                     "survey_bytes_ratio": round(SURVEY_BYTES_PER_EVAL * evals / alg, 4)},
+                     "survey_bytes_ratio": round(SURVEY_BYTES_PER_EVAL * kevals / alg, 4)},
         "cpu_baseline": cpu,
         "extras": extras,
     }

@@ -127,6 +127,7 @@ struct Batch {
   hipEvent_t done = nullptr;
   Block mem;
   int stream = 0;
+  int sync_frames = 0;  // frames with stripe sync words at the start of mem (two-pass frames' slots)
   std::vector<StageEvents> prof;  // empty unless profiling
   std::vector<hipEvent_t> joins;  // fork / join events of a batch split over streams
 };
@@ -284,6 +285,8 @@ int check_dev_ptr(const void *ptr, int dev, const char *name) {
 
 // ------------------------------------------------------ whole-frame plan
 
+constexpr size_t kNoSync = ~(size_t)0;  // FramePlan::off_sync of a batch without a sync header
+
 struct FramePlan {
   size_t off_cost, off_lr, off_dlr, off_dl, off_part, off_codes, bytes;
   // two-pass frames: S_D after the four path-cost slots, the stripes' edge
@@ -338,8 +341,7 @@ FramePlan plan_frame(const sgm_params &p, size_t base, bool sweep, bool codes, i
     f.off_sd = f.off_lr + align256(px * dp * 4);
     f.off_bnd = base + f.bytes;
     f.bytes += align256((size_t)stripes_of(p, tp_waves) * p.height * dp * 4);
-    f.off_sync = base + f.bytes;
-    f.bytes += align256(kSyncWords * 4);
+    // the sync words live in the batch's header (submit_impl sets off_sync)
   }
   return f;
 }
@@ -616,7 +618,8 @@ int enqueue_frames(const sgm_frame *fr, int n, const std::vector<FramePlan> &pla
   {  // the stripes' ticket counters and error flags start at zero
     std::vector<SyncZeroJob> zj;
     for (int i = 0; i < n; ++i)
-      if (tp_waves(i)) zj.push_back(SyncZeroJob{reinterpret_cast<uint32_t *>(mem + plans[i].off_sync), kSyncWords, 0});
+      if (plans[i].off_sync != kNoSync)  // every frame's words of the batch header
+        zj.push_back(SyncZeroJob{reinterpret_cast<uint32_t *>(mem + plans[i].off_sync), kSyncWords, 0});
     if (!zj.empty()) {
       launch_zero_sync(zj, s);
       CHECK(check_launch());
@@ -1329,7 +1332,11 @@ static int submit_impl(sgm_ctx *c, const sgm_frame *frames, const sgm_remap *rem
   std::lock_guard<std::mutex> lk(c->mu);
   std::vector<int> hl(n), sw(n);
   std::vector<FramePlan> plans(n);
-  size_t total = 0;
+  // a header of kSyncWords words per frame (the two-pass frames' ticket
+  // counters and error flags), read back when the batch is done
+  bool any_tp = false;
+  for (int i = 0; i < n && !any_tp; ++i) any_tp = resolve_twopass(c, frames[i].p) != 0;
+  size_t total = any_tp ? align256((size_t)n * kSyncWords * 4) : 0;
   for (int i = 0; i < n; ++i) {
     // lanes per horizontal scanline (low byte), horizontal costs from codes
     // (bit 8), two-pass stripes (bit 9; bit 10: 16 waves per stripe, else
@@ -1341,6 +1348,7 @@ static int submit_impl(sgm_ctx *c, const sgm_frame *frames, const sgm_remap *rem
     hl[i] = h | (codes ? 1 << 8 : 0) | (tp ? 1 << 9 : 0) | (tp == 16 ? 1 << 10 : 0) |
             resolve_disp_threads(c, frames[i].p) << 16;
     plans[i] = plan_frame(frames[i].p, total, sw[i] != 0, codes, tp);
+    plans[i].off_sync = any_tp ? (size_t)i * kSyncWords * 4 : kNoSync;
     total += plans[i].bytes;
   }
   DeviceGuard g(c->device);
@@ -1389,6 +1397,7 @@ static int submit_impl(sgm_ctx *c, const sgm_frame *frames, const sgm_remap *rem
   }
   Batch b;
   b.mem = blk;
+  b.sync_frames = any_tp ? n : 0;
   b.stream = c->next_stream;
   c->next_stream = (c->next_stream + 1) % c->nstreams;
   hipStream_t s = c->streams[b.stream];
@@ -1496,6 +1505,13 @@ static int poll_locked(sgm_ctx *c, uint64_t ticket, int *done) {
     return SGM_OK;
   }
   if (e != hipSuccess) return fail(SGM_EHIP, "batch %llu: %s", (unsigned long long)ticket, hipGetErrorString(e));
+  int bad = -1;  // a two-pass frame whose stripes gave up waiting for a neighbour
+  if (it->second.sync_frames) {
+    std::vector<uint32_t> w((size_t)it->second.sync_frames * kSyncWords);
+    if (hipMemcpy(w.data(), it->second.mem.ptr, w.size() * 4, hipMemcpyDeviceToHost) != hipSuccess) bad = -2;
+    for (int i = 0; i < it->second.sync_frames && bad == -1; ++i)
+      if (w[(size_t)i * kSyncWords + 1]) bad = i;
+  }
   for (auto &e : it->second.prof) {
     float ms = 0.f;
     if (hipEventElapsedTime(&ms, e.begin, e.end) == hipSuccess) {
@@ -1507,6 +1523,10 @@ static int poll_locked(sgm_ctx *c, uint64_t ticket, int *done) {
   c->idle.push_back(it->second.mem);
   c->inflight.erase(it);
   *done = 1;
+  if (bad == -2) return fail(SGM_EHIP, "batch %llu: reading its sync words failed", (unsigned long long)ticket);
+  if (bad >= 0)
+    return fail(SGM_EHIP, "batch %llu, frame %d: a stripe pass gave up waiting for its neighbour stripe",
+                (unsigned long long)ticket, bad);
   return SGM_OK;
 }
 

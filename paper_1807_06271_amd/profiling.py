@@ -56,15 +56,17 @@ def _code_only(text: bytes) -> bytes:
     return " ".join(t.split()).encode()
 
 
-def source_hash(files=("aggregate.hip", "device_util.h")) -> str:
-    """Hash of the aggregation kernel's code: its file, the device helpers
-    and the aggregation section of the kernel header (changes elsewhere in
-    the header do not touch the kernel), comments and spacing ignored."""
+def source_hash(files=("aggregate.hip", "stripes.hip", "device_util.h")) -> str:
+    """Hash of the aggregation kernels' code (the per-direction kernel and
+    the two-pass stripe kernels): their files, the device helpers and their
+    sections of the kernel header (changes elsewhere in the header do not
+    touch them), comments and spacing ignored."""
     h = hashlib.sha256()
     for f in files:
         with open(os.path.join(PKG, "csrc", f), "rb") as fh:
             h.update(_code_only(fh.read()))
     h.update(_code_only(_header_section("sgm_kernels.h", "aggregation")))
+    h.update(_code_only(_header_section("sgm_kernels.h", "two-pass stripes")))
     return h.hexdigest()[:16]
 
 
@@ -153,7 +155,7 @@ def traffic(fetch_csv: str, write_csv: str, out_path: str, fetch_cmd: str, write
                            "fetch_kib": cfetch, "write_kib": cwrite,
                            "fetch_factor": fetch_factor, "write_factor": write_factor},
            "source_hash": source_hash(),
-           "source_hash_covers": "aggregate.hip, device_util.h and the aggregation section of sgm_kernels.h, comments and spacing ignored",
+           "source_hash_covers": "aggregate.hip, stripes.hip, device_util.h and the aggregation and two-pass sections of sgm_kernels.h, comments and spacing ignored",
            "fetch_command": fetch_cmd, "write_command": write_cmd,
            "kernels": kernels}
     json.dump(out, open(out_path, "w"), indent=1)

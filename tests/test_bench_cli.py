@@ -31,3 +31,20 @@ def test_aggregation_bytes_follow_the_schedule():
     assert bench.agg_kernel_name(codes).endswith("unsigned char, 8, false, 2>")
     assert bench.agg_kernel_name({"h_lanes": 32, "h_costs": "volume"}) == \
         "agg_kernel<16, 8, 32, 0, unsigned char, 8, false, 0>"
+
+
+def test_roofline_kernel_follows_the_two_pass_schedule():
+    # the bottom-up stripe pass reads cost (1 B), S_D (2 B) and four uint8
+    # path-cost slots (4 B) per cell while evaluating two paths
+    sys.path.insert(0, ROOT)
+    import bench
+    from paper_1807_06271_amd.sgm import Params
+    p = Params(width=1920, height=1080, max_disp=256)
+    cells = 1920 * 1080 * 256
+    name, stage, alg, evals, _ = bench.dominant_kernel(p, 8, {"h_lanes": 64, "h_costs": "codes",
+                                                              "two_pass": "narrow"})
+    assert (name, stage, alg, evals) == ("stripe_kernel<16, true, 8, false>", "disparity", 8 * 7 * cells,
+                                         8 * 2 * cells)
+    name, stage, alg, evals, _ = bench.dominant_kernel(p, 8, {"h_lanes": 64, "h_costs": "volume",
+                                                              "two_pass": "off"})
+    assert stage == "aggregate" and alg == 2 * evals == 2 * 8 * p.disp_evals()
