@@ -160,8 +160,7 @@ struct MedianJob {
 void launch_median(std::vector<MedianJob> jobs, hipStream_t s);
 
 // --------------------------------------------------------------- U/V maps
-// U must be zero before the launch (it is accumulated with atomics) and
-// 4-byte aligned.
+// Every count of U and V is written once (no zero fill needed).
 struct UVJob {
   const uint16_t *disp;
   uint16_t *U, *V;  // [D][W], [H][D]
