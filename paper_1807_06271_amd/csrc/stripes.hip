@@ -137,7 +137,7 @@ __global__ __launch_bounds__(WAVES * 64) void stripe_kernel(JobTable<StripeJob> 
 
   // LDS: the diagonal path costs of the stripe's pixels for two rows
   // ([2][SW][Dp] uint16, as words), then (up pass with the LR check) two
-  // zone key rows
+  // zone key rows, then the neighbour's edge pixel
   uint32_t *dg = lds;
   const int dg_words = SW * Dp / 2;
   const int zn = SW + D - 1;  // zone positions of a segment of SW pixels
@@ -159,7 +159,8 @@ __global__ __launch_bounds__(WAVES * 64) void stripe_kernel(JobTable<StripeJob> 
   const bool takes_edge = UP ? (px == SW - 1 && s + 1 < ns) : (px == 0 && s > 0);
   const bool gives_edge = UP ? (px == 0 && s > 0) : (px == SW - 1 && s + 1 < ns);
   const bool edge_wave = (UP ? wave == WAVES - 1 : wave == 0) && (UP ? s + 1 < ns : s > 0);
-  const uint64_t *bnd_in = J.bnd + ((int64_t)(UP ? s + 1 : s - 1) * H) * (Dp / 2);
+  const int s_in = min(max(UP ? s + 1 : s - 1, 0), ns - 1);  // the neighbour (if any)
+  const uint64_t *bnd_in = J.bnd + ((int64_t)s_in * H) * (Dp / 2);
   uint64_t *bnd_out = J.bnd + ((int64_t)s * H) * (Dp / 2) + dbase / 2;
   const int ew = 2 * lane;                  // this lane's first word of a record
   const bool ew_live = ew < Dp / 2;         // Dp / 2 words per record (even)
@@ -340,8 +341,6 @@ __global__ __launch_bounds__(WAVES * 64) void stripe_kernel(JobTable<StripeJob> 
     if (r0 + u < H) row(r0 + u, ring[u], erec[(u + ER - 1) % ER]);
 }
 
-void launch_zero_sync(std::vector<SyncZeroJob> jobs, hipStream_t s);
-
 namespace {
 __global__ __launch_bounds__(256) void zero_kernel(JobTable<SyncZeroJob> t) {
   const int ji = find_job(t.j, t.n, (int)blockIdx.x);
@@ -372,10 +371,13 @@ static void launch_kw(const JobTable<StripeJob> &t, int blocks, bool pad, size_t
   else hipLaunchKernelGGL((stripe_kernel<K, UP, WAVES, false>), dim3(blocks), dim3(WAVES * 64), lds, s, t);
 }
 
-template <int K, bool UP>
-static void launch_k(const JobTable<StripeJob> &t, int blocks, int waves, bool pad, size_t lds, hipStream_t s) {
-  if (waves == 16) launch_kw<K, UP, 16>(t, blocks, pad, lds, s);
-  else launch_kw<K, UP, 8>(t, blocks, pad, lds, s);
+template <int K>
+static void launch_k(const JobTable<StripeJob> &t, int blocks, bool up, int waves, bool pad, size_t lds,
+                     hipStream_t s) {
+  if (up && waves == 16) launch_kw<K, true, 16>(t, blocks, pad, lds, s);
+  else if (up) launch_kw<K, true, 8>(t, blocks, pad, lds, s);
+  else if (waves == 16) launch_kw<K, false, 16>(t, blocks, pad, lds, s);
+  else launch_kw<K, false, 8>(t, blocks, pad, lds, s);
 }
 
 void launch_stripes(std::vector<StripeJob> jobs, int K, bool up, int waves, hipStream_t s) {
@@ -393,10 +395,10 @@ void launch_stripes(std::vector<StripeJob> jobs, int K, bool up, int waves, hipS
       jobs, [](const StripeJob &j) { return (long)j.nstripes; },
       [&](const JobTable<StripeJob> &t, int blocks) {
         switch (K) {
-          case 4: up ? launch_k<4, true>(t, blocks, waves, pad, lds, s) : launch_k<4, false>(t, blocks, waves, pad, lds, s); break;
-          case 8: up ? launch_k<8, true>(t, blocks, waves, pad, lds, s) : launch_k<8, false>(t, blocks, waves, pad, lds, s); break;
-          case 12: up ? launch_k<12, true>(t, blocks, waves, pad, lds, s) : launch_k<12, false>(t, blocks, waves, pad, lds, s); break;
-          default: up ? launch_k<16, true>(t, blocks, waves, pad, lds, s) : launch_k<16, false>(t, blocks, waves, pad, lds, s); break;
+          case 4: launch_k<4>(t, blocks, up, waves, pad, lds, s); break;
+          case 8: launch_k<8>(t, blocks, up, waves, pad, lds, s); break;
+          case 12: launch_k<12>(t, blocks, up, waves, pad, lds, s); break;
+          default: launch_k<16>(t, blocks, up, waves, pad, lds, s); break;
         }
       });
 }
