@@ -390,9 +390,12 @@ int sgm_get_schedule(sgm_ctx *ctx, const sgm_params *shape, sgm_schedule *s);
 /* Autotuner: time the n >= 1 frames `samples` (inputs and outputs as for
  * sgm_submit; all of one shape -- width, height, max_disp, path_mask and
  * path-cost width -- else SGM_EINVAL), submitted as one batch, under
- * candidate schedules, `reps` timed repetitions back to back each after
- * `reps` warm-up repetitions (which also allocate the scratch the timed
- * ones hold), on one stream, and keep the fastest for their shape (as
+ * candidate schedules as the context runs batches -- `reps` submits back
+ * to back on its streams (sgm_set_streams, sgm_set_split), in flight
+ * together, timed by wall clock until all are done (the better of two such
+ * runs), after as many warm-up submits (which also allocate the scratch the
+ * timed ones hold) -- and keep
+ * the one with the least time per submit for their shape (as
  * sgm_set_schedule);
  * return it in *best (may be NULL).  A batch of the size the caller will
  * submit finds the schedule for that batch size.  The search is by

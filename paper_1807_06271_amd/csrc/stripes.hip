@@ -240,31 +240,22 @@ __global__ __launch_bounds__(WAVES * 64) void stripe_kernel(JobTable<StripeJob> 
       sd = load_nt<NP>(J.sd + cell);
     }
 
+    // diagonal path: the predecessor x -/+ 1 of the previous row, read
+    // without a branch (the taking pixel from eslot, the others from the
+    // previous LDS row; at a path start the values are replaced), so that
+    // the vertical and diagonal recurrences below share one basic block and
+    // their dependent chains interleave
+    const int pp = UP ? px + 1 : px - 1;  // predecessor pixel in the stripe
+    const bool start = r == 0 || (UP ? (x + 1 >= W) : (x == 0));
+    const uint32_t *src = takes_edge ? eslot + dbase / 2
+                                     : dg + (buf ^ 1) * dg_words + (min(max(pp, 0), SW - 1) * Dp + dbase) / 2;
+    const U32N<NP> pv = *reinterpret_cast<const U32N<NP> *>(src);
+    u16x2 Lp[NP];
+#pragma unroll
+    for (int q = 0; q < NP; ++q) Lp[q] = as_pair(start ? padmask[q] : pv.v[q]);
     // vertical path
     u16x2 Lcv[NP];
     recur<K, PAD>(Lv, c, P1, P2, padmask, Lcv);
-    // diagonal path: the predecessor x -/+ 1 of the previous row
-    u16x2 Lp[NP];
-    if (r == 0) {
-#pragma unroll
-      for (int q = 0; q < NP; ++q) Lp[q] = as_pair(padmask[q]);
-    } else {
-      const int pp = UP ? px + 1 : px - 1;  // predecessor pixel in the stripe
-      const bool outside = UP ? (x + 1 >= W) : (x == 0);
-      if (outside) {  // no predecessor: the path starts here
-#pragma unroll
-        for (int q = 0; q < NP; ++q) Lp[q] = as_pair(padmask[q]);
-      } else if (takes_edge) {  // the neighbour stripe's edge pixel (written by this wave)
-        const U32N<NP> v = *reinterpret_cast<const U32N<NP> *>(eslot + dbase / 2);
-#pragma unroll
-        for (int q = 0; q < NP; ++q) Lp[q] = as_pair(v.v[q]);
-      } else {
-        const uint32_t *src = dg + (buf ^ 1) * dg_words + (pp * Dp + dbase) / 2;
-        const U32N<NP> v = *reinterpret_cast<const U32N<NP> *>(src);
-#pragma unroll
-        for (int q = 0; q < NP; ++q) Lp[q] = as_pair(v.v[q]);
-      }
-    }
     u16x2 Lcd[NP];
     recur<K, PAD>(Lp, c, P1, P2, padmask, Lcd);
     {  // this row's diagonal path costs for the next row's predecessors

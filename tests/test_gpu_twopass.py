@@ -55,20 +55,37 @@ def check(f, want, tag):
     assert_equal(to_np(f.vmap), want[2], "vmap " + tag)
 
 
+# a batch runs its two-pass frames as such only with at least this many
+# stripes in all (else on the per-direction kernels)
+MIN_STRIPES = 128
+
+
+def copies_for(W, mode):
+    stripes = -(-W // (64 if mode == "wide" else 32))
+    return -(-MIN_STRIPES // stripes)
+
+
 @pytest.mark.parametrize("shape", SHAPES)
 @pytest.mark.parametrize("mode", ["wide", "narrow"])
 def test_two_pass_matches_oracle(env, shape, mode):
+    # the frame submitted as many times as it takes to reach the stripe
+    # threshold (one launch then holds several job tables, each with its own
+    # ticket counter); every copy must equal the oracle
     torch, sgm, ctx = env
     W, H, D, (cw, ch), p1, p2, lr, med = shape
-    announce("two-pass", mode, shape)
+    n = copies_for(W, mode)
+    announce("two-pass", mode, shape, n, "copies")
     left, right, _ = synthetic.make_pair("kitti", W + 7 * D + H, W, H, D)
     p = params(sgm, W, H, D, cw, ch, p1, p2, lr, med)
     tp = sgm.TWOPASS_WIDE if mode == "wide" else sgm.TWOPASS_NARROW
     sgm.sgm_set_schedule(ctx, p, 0, two_pass=tp)
     assert sgm.schedule_of(ctx, p)[4] == tp
-    f = sgm.Frame.alloc(p, to_dev(torch, left), to_dev(torch, right))
-    sgm.sgm_wait(ctx, sgm.sgm_submit(ctx, [f]))
-    check(f, oracle_maps(p, left, right), "%s %s" % (mode, shape))
+    L, R = to_dev(torch, left), to_dev(torch, right)
+    frames = [sgm.Frame.alloc(p, L, R) for _ in range(n)]
+    sgm.sgm_wait(ctx, sgm.sgm_submit(ctx, frames))
+    want = oracle_maps(p, left, right)
+    for i, f in enumerate(frames):
+        check(f, want, "%s %s copy %d" % (mode, shape, i))
 
 
 def test_two_pass_does_not_apply_elsewhere(env):
@@ -97,6 +114,7 @@ def test_mixed_batch_repeated_split_and_graphs(env):
     # context's streams, and replayed in graph mode
     torch, sgm, ctx = env
     announce("two-pass mixed batch")
+    # five shapes, each frame 16 times (the two-pass ones: 160 stripes)
     specs = [(150, 40, 128, 0xFF, sgm.TWOPASS_WIDE), (150, 40, 64, 0xFF, sgm.TWOPASS_NARROW),
              (130, 30, 128, 0x0F, sgm.TWOPASS_WIDE), (90, 44, 256, 0xFF, sgm.TWOPASS_OFF),
              (70, 25, 64, 0xFF, sgm.TWOPASS_WIDE)]
@@ -105,9 +123,11 @@ def test_mixed_batch_repeated_split_and_graphs(env):
         left, right, _ = synthetic.make_pair("kitti", 300 + i, W, H, D)
         p = sgm.Params(width=W, height=H, max_disp=D, path_mask=mask, invalid=65535 if D > 255 else 255)
         sgm.sgm_set_schedule(ctx, p, 0, two_pass=tp)
-        frames.append(sgm.Frame.alloc(p, to_dev(torch, left), to_dev(torch, right)))
         o = O.sgm(left, right, D, 9, 7, mask, 10, 120, True, 1, 3, p.inv())
-        want.append((o["disp"], o["umap"], o["vmap"]))
+        L, R = to_dev(torch, left), to_dev(torch, right)
+        for _ in range(16):
+            frames.append(sgm.Frame.alloc(p, L, R))
+            want.append((o["disp"], o["umap"], o["vmap"]))
     try:
         for split in (1, 4):
             sgm.sgm_set_split(ctx, split)
