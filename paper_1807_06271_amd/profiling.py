@@ -1,7 +1,7 @@
 """Summaries of rocprofv3 CSV output for the profiles/ directory.
 
     python -m paper_1807_06271_amd.profiling stats  <kernel_stats.csv> <out.txt> "<command>" \
-        [<kernel_trace.csv> <kernel name part> <N dispatches> [<skip> [largest]]]
+        [<kernel_trace.csv> (<kernel name part> <N dispatches> <skip, -1: the last N> <largest|all>)...]
     python -m paper_1807_06271_amd.profiling traffic <fetch_counter_collection.csv> \
         <write_counter_collection.csv> <out.json> "<fetch command>" "<write command>" [median|largest|max]
     python -m paper_1807_06271_amd.profiling counters <counter_collection.csv> <kernel_trace.csv> \
@@ -76,12 +76,13 @@ def short_name(name: str) -> str:
 
 
 def stats(csv_path: str, out_path: str, command: str, trace_csv: str | None = None,
-          kernel: str | None = None, first: int = 0, skip: int = 0, largest: bool = False) -> None:
-    """Kernel statistics; with trace_csv/kernel/first, also the average of
-    dispatches skip .. skip+first-1 (in start order; skip < 0: the last
-    `first`) of `kernel` (a loop of the benchmark in which the kernel runs
-    alone); with `largest`, counted among the dispatches with the kernel's
-    largest grid only (e.g. its 8-frame launches, not single frames)."""
+          selections=()) -> None:
+    """Kernel statistics; with trace_csv, also for each selection (kernel,
+    first, skip, largest) the average of dispatches skip .. skip+first-1 (in
+    start order; skip < 0: the last `first`) of `kernel` (a loop of the
+    benchmark in which the kernel runs alone); with `largest`, counted among
+    the dispatches with the kernel's largest grid only (e.g. its 8-frame
+    launches, not single frames)."""
     rows = list(csv.DictReader(open(csv_path)))
     lines = ["# rocprofv3 kernel statistics", "# command: " + command, "#",
              "%-100s %6s %12s %12s %12s %7s" % ("kernel", "calls", "avg_us", "min_us", "max_us", "pct")]
@@ -89,18 +90,21 @@ def stats(csv_path: str, out_path: str, command: str, trace_csv: str | None = No
         lines.append("%-100s %6s %12.1f %12.1f %12.1f %7.2f" % (
             short_name(r["Name"]), r["Calls"], float(r["AverageNs"]) / 1e3, float(r["MinNs"]) / 1e3,
             float(r["MaxNs"]) / 1e3, float(r["Percentage"])))
-    if trace_csv and kernel and first:
-        tr = [r for r in csv.DictReader(open(trace_csv)) if kernel in r["Kernel_Name"]]
-        tr.sort(key=lambda r: int(r["Start_Timestamp"]))
-        grid = max(int(r["Grid_Size_X"]) for r in tr)
-        if largest:
-            tr = [r for r in tr if int(r["Grid_Size_X"]) == grid]
-        if skip < 0:  # the last `first` dispatches
-            skip = len(tr) - first
-        d = [(int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3 for r in tr][skip:skip + first]
-        lines += ["#", "# dispatches %d..%d (in start order)%s of %s: avg %.1f us, min %.1f, max %.1f"
-                  % (skip, skip + len(d) - 1, " (grid %d only)" % grid if largest else "", kernel,
-                     sum(d) / len(d), min(d), max(d))]
+    if trace_csv and selections:
+        trace = list(csv.DictReader(open(trace_csv)))
+        lines.append("#")
+        for kernel, first, skip, largest in selections:
+            tr = [r for r in trace if kernel in r["Kernel_Name"]]
+            tr.sort(key=lambda r: int(r["Start_Timestamp"]))
+            grid = max(int(r["Grid_Size_X"]) for r in tr)
+            if largest:
+                tr = [r for r in tr if int(r["Grid_Size_X"]) == grid]
+            if skip < 0:  # the last `first` dispatches
+                skip = len(tr) - first
+            d = [(int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3 for r in tr][skip:skip + first]
+            lines.append("# dispatches %d..%d (in start order)%s of %s: avg %.1f us, min %.1f, max %.1f"
+                         % (skip, skip + len(d) - 1, " (grid %d only)" % grid if largest else "", kernel,
+                            sum(d) / len(d), min(d), max(d)))
     open(out_path, "w").write("\n".join(lines) + "\n")
 
 
@@ -210,10 +214,10 @@ def counters(csv_path: str, trace_csv: str, out_path: str, command: str, largest
 
 if __name__ == "__main__":
     if sys.argv[1] == "stats":
-        extra = sys.argv[5:7] + [int(v) for v in sys.argv[7:9]] if len(sys.argv) > 7 else []  # skip may be -1
-        if len(sys.argv) > 9:
-            extra.append(sys.argv[9] == "largest")
-        stats(sys.argv[2], sys.argv[3], sys.argv[4], *extra)
+        # ... <trace.csv> then groups of: <kernel name part> <N dispatches> <skip (-1: the last N)> <largest|all>
+        sel = sys.argv[6:]
+        groups = [(sel[i], int(sel[i + 1]), int(sel[i + 2]), sel[i + 3] == "largest") for i in range(0, len(sel) - 3, 4)]
+        stats(sys.argv[2], sys.argv[3], sys.argv[4], sys.argv[5] if len(sys.argv) > 5 else None, groups)
     elif sys.argv[1] == "traffic":
         traffic(sys.argv[2], sys.argv[3], sys.argv[4], sys.argv[5], sys.argv[6], *sys.argv[7:8])
     elif sys.argv[1] == "counters":
