@@ -375,7 +375,10 @@ typedef struct {
    * (NARROW) stripes, one workgroup per stripe.  The four other paths run
    * as per-direction kernels.  Applies to Census frames with all 8 paths
    * and N_b + p2 <= 255 that do not use the single-pass sweep; other frames
-   * use the per-direction kernels. */
+   * use the per-direction kernels.  A stripe is one workgroup walking all
+   * rows, so the schedule needs many of them: a batch whose two-pass frames
+   * have fewer than 128 stripes in all (ceil(width / 64) or ceil(width / 32)
+   * per frame) runs them on the per-direction kernels. */
   int32_t two_pass;
 } sgm_schedule;
 enum { SGM_HCOSTS_DEFAULT = 0, SGM_HCOSTS_VOLUME = 1, SGM_HCOSTS_CODES = 2 };
@@ -403,7 +406,9 @@ int sgm_get_schedule(sgm_ctx *ctx, const sgm_params *shape, sgm_schedule *s);
  * and 64 lanes with horizontal costs from the Census codes where that
  * applies (per-direction kernels, disp_threads 0); then, with the best of
  * these, the two-pass schedule with wide and with narrow stripes where it
- * applies; then, if the per-direction kernels still win, disp_threads 256,
+ * applies and the sample has at least 128 stripes (a batch with fewer runs
+ * its two-pass frames on the per-direction kernels); then, if the
+ * per-direction kernels still win, disp_threads 256,
  * 512, 1024; then, for frames the single-pass sweep can take, the sweep.
  * Blocks until done.
  * `ms`, if non-NULL, receives per-candidate milliseconds for up to `n_ms`

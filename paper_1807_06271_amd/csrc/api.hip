@@ -1681,11 +1681,15 @@ int sgm_autotune(sgm_ctx *c, const sgm_frame *samples, int n, int reps, sgm_sche
     sc.two_pass = SGM_TWOPASS_OFF;
     CHECK(consider(3, sc));
   }
-  // 2. the two-pass schedule with wide and narrow stripes
+  // 2. the two-pass schedule with wide and narrow stripes, where the sample
+  //    batch has enough stripes to run it (a smaller one would time the
+  //    per-direction kernels it falls back to)
   if (twopass_ok(sample->p)) {
     const sgm_schedule base = win;
     const int modes[2] = {SGM_TWOPASS_WIDE, SGM_TWOPASS_NARROW};
+    const int waves[2] = {16, 8};
     for (int ci = 0; ci < 2; ++ci) {
+      if (n * stripes_of(sample->p, waves[ci]) < kMinStripes) continue;
       sgm_schedule sc = base;
       sc.two_pass = modes[ci];
       CHECK(consider(4 + ci, sc));

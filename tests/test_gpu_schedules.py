@@ -131,13 +131,12 @@ def test_autotune_keeps_a_valid_schedule(env):
     f = sgm.Frame.alloc(p, to_dev(torch, left), to_dev(torch, right))
     best, ms = sgm.sgm_autotune(ctx, f, reps=2)
     # first lanes (16, 32, 64 with costs from the volume, 64 with costs from
-    # Census windows), then the two-pass stripes (8 paths, uint8 path
-    # costs), then -- only if the per-direction kernels still win -- the
-    # disparity block size; no sweep (9x7 codes, D = 128)
+    # Census windows), then the disparity block size; no two-pass stripes
+    # (one 300-column frame has 5 or 10 stripes, below the 128 a batch needs)
+    # and no sweep (9x7 codes, D = 128)
     stage1 = ("h_lanes=16", "h_lanes=32", "h_lanes=64", "h_costs=codes")
-    want = set(stage1) | {"two_pass=wide", "two_pass=narrow"}
-    if best["two_pass"] == "off":
-        want |= {"disp_threads=256", "disp_threads=512", "disp_threads=1024"}
+    want = set(stage1) | {"disp_threads=256", "disp_threads=512", "disp_threads=1024"}
+    assert best["two_pass"] == "off"
     assert set(ms) == want
     assert all(v > 0 for v in ms.values())
     first = min(stage1, key=lambda k: ms[k])
@@ -180,6 +179,30 @@ def test_autotune_on_a_batch_sample(env):
     with pytest.raises(sgm.SgmError) as e:
         sgm.sgm_autotune(ctx, [frames[0], odd], reps=1)
     assert e.value.status == sgm.SGM_EINVAL
+
+
+def test_autotune_considers_two_pass_on_large_batches(env):
+    # 32 frames of 260 columns: 5 wide or 9 narrow stripes each, 160 and 288
+    # in all, so both stripe widths are timed; the kept schedule gives the
+    # oracle's maps for every frame
+    torch, sgm, ctx = env
+    announce("autotune with two-pass candidates")
+    W, H, D = 260, 40, 256
+    p = sgm.Params(width=W, height=H, max_disp=D, invalid=65535)
+    left, right, _ = synthetic.make_pair("kitti", 95, W, H, D)
+    L, R = to_dev(torch, left), to_dev(torch, right)
+    frames = [sgm.Frame.alloc(p, L, R) for _ in range(32)]
+    best, ms = sgm.sgm_autotune(ctx, frames, reps=1)
+    assert {"two_pass=wide", "two_pass=narrow"} <= set(ms)
+    assert best["two_pass"] in ("off", "wide", "narrow")
+    for f in frames:
+        f.disp.view(torch.int16).fill_(7)
+    torch.cuda.synchronize()
+    sgm.sgm_wait(ctx, sgm.sgm_submit(ctx, frames))
+    want = O.sgm(left, right, D, 9, 7, 0xFF, 10, 120, True, 1, 3, 65535)
+    for i, f in enumerate(frames):
+        assert_equal(to_np(f.disp), want["disp"], "disp frame %d after autotune" % i)
+        assert_equal(to_np(f.vmap), want["vmap"], "vmap frame %d after autotune" % i)
 
 
 def test_schedule_rejects_bad_values(env):
