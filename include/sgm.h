@@ -285,6 +285,15 @@ int sgm_submit_after(sgm_ctx *ctx, const sgm_frame *frames, int n, void *const *
  * raise GPU_MAX_HW_QUEUES. */
 int sgm_set_streams(sgm_ctx *ctx, int n);
 
+/* Failure path of the two-pass schedule (sgm_schedule.two_pass), for tests
+ * that force it from the host: a stripe waits for its neighbour stripe's
+ * edge record of each row, and gives up after `max_polls` polls (0 = the
+ * default, about 4 million: seconds), records an error and goes on, so the
+ * kernel always ends; sgm_poll / sgm_wait then return SGM_EHIP for the batch
+ * (its maps are unspecified).  withhold_edges = 1 makes the stripes publish
+ * no edge records, so every such wait gives up.  For callers, leave both at
+ * 0. */
+int sgm_set_stripe_wait(sgm_ctx *ctx, int max_polls, int withhold_edges);
 /* Number of the context's streams a batch's frames are spread over (1 to 8;
  * 4 after sgm_create) when it is submitted while no other batch of the
  * context is in flight: the batch is split into up to n groups of about

@@ -124,6 +124,17 @@ struct StageEvents {
   hipEvent_t begin, end;
 };
 
+// Polls (each a device-scope load after a short sleep, ~1-2 us) before a
+// stripe's wait for its neighbour's edge gives up: seconds, far beyond any
+// legitimate wait.
+constexpr int kStripePolls = 1 << 22;
+
+// Bounds of the stripe passes' waits for a neighbour's edge (sgm_set_stripe_wait).
+struct StripeWait {
+  int max_polls = kStripePolls;
+  int withhold = 0;
+};
+
 struct Batch {
   hipEvent_t done = nullptr;
   Block mem;
@@ -166,6 +177,7 @@ struct sgm_ctx {
   double stage_ms[SGM_NSTAGES] = {};
   uint64_t stage_count[SGM_NSTAGES] = {};
   void *static_scratch = nullptr;  // device address of `scratch` on this device
+  StripeWait stripe_wait;          // sgm_set_stripe_wait
 
   size_t held() const {
     size_t s = stage.bytes;
@@ -532,7 +544,8 @@ struct StageMark {
 int enqueue_frames(const sgm_frame *fr, int n, const std::vector<FramePlan> &plans,
                    const std::vector<int> &hlps, const std::vector<int> &sweep,
                    const std::vector<RemapJob> &rect, char *mem, hipStream_t s,
-                   std::vector<StageEvents> *prof, hipEvent_t census_done = nullptr) {
+                   std::vector<StageEvents> *prof, hipEvent_t census_done = nullptr,
+                   StripeWait wait = StripeWait{}) {
   StageMark mark{prof, s};
   // rectification of the raw views into the frames' input buffers (one
   // launch for every view of the batch)
@@ -730,6 +743,8 @@ int enqueue_frames(const sgm_frame *fr, int n, const std::vector<FramePlan> &pla
       j.p2 = p.p2;
       j.lr_check = p.lr_check;
       j.epoch = epoch;
+      j.max_polls = wait.max_polls;
+      j.withhold = wait.withhold;
       sj.push_back(j);
     }
     return sj;
@@ -960,7 +975,7 @@ int enqueue_split(sgm_ctx *c, Batch &b, const sgm_frame *fr, int n, const std::v
         r.push_back(rect[2 * i + 1]);
       }
     }
-    CHECK(enqueue_frames(f.data(), (int)f.size(), pl, h, w, r, mem, sg, prof, fork));
+    CHECK(enqueue_frames(f.data(), (int)f.size(), pl, h, w, r, mem, sg, prof, fork, c->stripe_wait));
     if (sg != s0) {
       hipEvent_t join = nullptr;
       HIP_TRY(hipEventCreateWithFlags(&join, hipEventDisableTiming));
@@ -979,7 +994,7 @@ int enqueue_graph(sgm_ctx *c, const sgm_frame *fr, int n, const std::vector<Fram
                   const std::vector<int> &hlps, const std::vector<int> &sweep,
                   const std::vector<RemapJob> &rect, char *mem, hipStream_t s) {
   HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed));
-  int rc = enqueue_frames(fr, n, plans, hlps, sweep, rect, mem, s, nullptr);
+  int rc = enqueue_frames(fr, n, plans, hlps, sweep, rect, mem, s, nullptr, nullptr, c->stripe_wait);
   hipGraph_t g = nullptr;
   hipError_t e = hipStreamEndCapture(s, &g);
   if (rc != SGM_OK) {
@@ -1437,7 +1452,7 @@ static int submit_impl(sgm_ctx *c, const sgm_frame *frames, const sgm_remap *rem
                        c->profiling ? &b.prof : nullptr);
   } else {
     rc = enqueue_frames(frames, n, plans, hl, sw, rect, reinterpret_cast<char *>(blk.ptr), s,
-                        c->profiling ? &b.prof : nullptr);
+                        c->profiling ? &b.prof : nullptr, nullptr, c->stripe_wait);
   }
   if (rc == SGM_OK && hipEventCreateWithFlags(&b.done, hipEventDisableTiming) != hipSuccess)
     rc = fail(SGM_EHIP, "hipEventCreate failed");
@@ -1729,6 +1744,17 @@ int sgm_set_graphs(sgm_ctx *c, int on) {
   if (!c) return fail(SGM_EINVAL, "ctx is null");
   std::lock_guard<std::mutex> lk(c->mu);
   c->graphs = on != 0;
+  return SGM_OK;
+}
+
+int sgm_set_stripe_wait(sgm_ctx *c, int max_polls, int withhold_edges) {
+  if (!c) return fail(SGM_EINVAL, "ctx is null");
+  if (max_polls < 0) return fail(SGM_EINVAL, "max_polls must be >= 0 (got %d)", max_polls);
+  if (withhold_edges != 0 && withhold_edges != 1)
+    return fail(SGM_EINVAL, "withhold_edges must be 0 or 1 (got %d)", withhold_edges);
+  std::lock_guard<std::mutex> lk(c->mu);
+  c->stripe_wait.max_polls = max_polls ? max_polls : kStripePolls;
+  c->stripe_wait.withhold = withhold_edges;
   return SGM_OK;
 }
 

@@ -189,6 +189,8 @@ struct StripeJob {
   int W, H, D, Dp, p1, p2, lr_check;
   int nstripes;         // set by launch_stripes
   uint32_t epoch;       // tag of this launch's edge words (never 0, new per launch)
+  int max_polls;        // polls before a wait for a neighbour's edge gives up
+  int withhold;         // 1: publish no edges (tests of the failure path only)
   int blk0;
 };
 constexpr int kSyncWords = 4;

@@ -50,7 +50,6 @@ __device__ __forceinline__ u16x2 pmin(u16x2 a, u16x2 b) { return __builtin_eleme
 __device__ __forceinline__ u16x2 padd_sat(u16x2 a, u16x2 b) { return __builtin_elementwise_add_sat(a, b); }
 
 constexpr uint32_t kInf = 0xFFFFFFFFu;
-constexpr int kSpinLimit = 1 << 22;  // boundary polls before a wait gives up
 
 // One pixel of equation (2) for the lane's K disparities (16 lanes per
 // pixel): Lp the predecessor's path costs (packed pairs), c the lane's K
@@ -203,7 +202,7 @@ __global__ __launch_bounds__(WAVES * 64) void stripe_kernel(JobTable<StripeJob> 
     if (edge_wave && r > 0) {
       bool ok = !ew_live || ((uint32_t)(prev_rec[0] >> 32) == epoch && (uint32_t)(prev_rec[1] >> 32) == epoch);
       for (int n = 0; __builtin_amdgcn_ballot_w64(!ok) != 0 && !failed; ++n) {
-        if (n == kSpinLimit) {
+        if (n == J.max_polls) {
           failed = true;
           __hip_atomic_store(J.sync + 1, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
           break;
@@ -264,7 +263,7 @@ __global__ __launch_bounds__(WAVES * 64) void stripe_kernel(JobTable<StripeJob> 
       for (int q = 0; q < NP; ++q) v.v[q] = as_u32(Lcd[q]);
       *reinterpret_cast<U32N<NP> *>(dg + buf * dg_words + (px * Dp + dbase) / 2) = v;
     }
-    if (gives_edge) {
+    if (gives_edge && !J.withhold) {
 #pragma unroll
       for (int q = 0; q < NP; ++q)
         __hip_atomic_store(bnd_out + (int64_t)y * (Dp / 2) + q, (uint64_t)as_u32(Lcd[q]) | (uint64_t)epoch << 32,

@@ -41,7 +41,7 @@ EXPORTS = ["sgm_validate", "sgm_create", "sgm_destroy", "sgm_last_error", "sgm_c
            "sgm_profile_read", "sgm_set_streams", "sgm_set_schedule", "sgm_get_schedule",
            "sgm_autotune", "sgm_set_graphs", "sgm_graph_stats", "sgm_rectify",
            "sgm_submit_rectify", "uv_filter", "sgm_submit_after",
-           "sgm_disparity_noalloc", "sgm_set_split"]
+           "sgm_disparity_noalloc", "sgm_set_split", "sgm_set_stripe_wait"]
 STAGES = ["census", "aggregate", "disparity", "median", "uv", "rectify"]
 
 
@@ -525,6 +525,12 @@ def sgm_graph_stats(ctx: Context):
 
 def sgm_set_streams(ctx: Context, n: int) -> None:
     _check(lib().sgm_set_streams(ctx.handle, int(n)), "sgm_set_streams")
+
+
+def sgm_set_stripe_wait(ctx: Context, max_polls: int = 0, withhold_edges: bool = False) -> None:
+    """Bound the two-pass stripes' waits for a neighbour's edge (0: the
+    default) and optionally withhold the edges (tests of the failure path)."""
+    _check(lib().sgm_set_stripe_wait(ctx.handle, int(max_polls), int(bool(withhold_edges))), "sgm_set_stripe_wait")
 
 
 def sgm_set_split(ctx: Context, n: int) -> None:

@@ -178,3 +178,30 @@ def test_many_frames_in_one_launch(env):
         sgm.sgm_wait(ctx, sgm.sgm_submit(ctx, [g]))
         assert np.array_equal(to_np(g.disp), to_np(f.disp)), i
         assert np.array_equal(to_np(g.umap), to_np(f.umap)), i
+
+
+def test_a_stripe_wait_that_gives_up_fails_the_batch(env):
+    # the failure path forced from the host: stripes publish no edge records
+    # and every wait gives up after 64 polls (the kernels still end); the
+    # batch reports SGM_EHIP, and the context then works as before
+    torch, sgm, ctx = env
+    announce("two-pass failure path")
+    W, H, D = 256, 24, 64  # 4 wide stripes per frame, 32 frames: 128
+    p = sgm.Params(width=W, height=H, max_disp=D)
+    left, right, _ = synthetic.make_pair("kitti", 77, W, H, D)
+    L, R = to_dev(torch, left), to_dev(torch, right)
+    frames = [sgm.Frame.alloc(p, L, R) for _ in range(32)]
+    sgm.sgm_set_schedule(ctx, p, 0, two_pass=sgm.TWOPASS_WIDE)
+    try:
+        sgm.sgm_set_stripe_wait(ctx, 64, True)
+        with pytest.raises(sgm.SgmError) as e:
+            sgm.sgm_wait(ctx, sgm.sgm_submit(ctx, frames))
+        assert e.value.status == sgm.SGM_EHIP and "gave up waiting" in str(e.value)
+    finally:
+        sgm.sgm_set_stripe_wait(ctx, 0, False)
+    with pytest.raises(sgm.SgmError):
+        sgm.sgm_set_stripe_wait(ctx, -1, False)
+    sgm.sgm_wait(ctx, sgm.sgm_submit(ctx, frames))
+    want = oracle_maps(params(sgm, W, H, D, 9, 7, 10, 120, 1, 3), left, right)
+    for i, f in enumerate(frames):
+        check(f, want, "frame %d after the failed batch" % i)
