@@ -140,6 +140,7 @@ struct Batch {
   Block mem;
   int stream = 0;
   int sync_frames = 0;  // frames with stripe sync words at the start of mem (two-pass frames' slots)
+  uint32_t *sync_host = nullptr;  // pinned copy of those words, written by the batch's last copy
   std::vector<StageEvents> prof;  // empty unless profiling
   std::vector<hipEvent_t> joins;  // fork / join events of a batch split over streams
 };
@@ -178,6 +179,8 @@ struct sgm_ctx {
   uint64_t stage_count[SGM_NSTAGES] = {};
   void *static_scratch = nullptr;  // device address of `scratch` on this device
   StripeWait stripe_wait;          // sgm_set_stripe_wait
+  // pinned host blocks of kSyncHostBytes for batches' sync words (reused)
+  std::vector<uint32_t *> sync_pool;
 
   size_t held() const {
     size_t s = stage.bytes;
@@ -299,6 +302,7 @@ int check_dev_ptr(const void *ptr, int dev, const char *name) {
 // ------------------------------------------------------ whole-frame plan
 
 constexpr size_t kNoSync = ~(size_t)0;  // FramePlan::off_sync of a batch without a sync header
+constexpr size_t kSyncHostBytes = 4096;  // pinned block of a batch's sync words (256 frames; larger batches get their own)
 
 struct FramePlan {
   size_t off_cost, off_lr, off_dlr, off_dl, off_part, off_codes, bytes;
@@ -1078,7 +1082,9 @@ int sgm_destroy(sgm_ctx *c) {
     for (auto &kv : c->inflight) {
       destroy_events(kv.second);
       (void)hipFree(kv.second.mem.ptr);
+      if (kv.second.sync_host) (void)hipHostFree(kv.second.sync_host);
     }
+    for (uint32_t *h : c->sync_pool) (void)hipHostFree(h);
     for (auto &b : c->idle) (void)hipFree(b.ptr);
     for (auto &kv : c->graph_cache) (void)hipGraphExecDestroy(kv.second);
     if (c->stage.ptr) (void)hipFree(c->stage.ptr);
@@ -1454,6 +1460,21 @@ static int submit_impl(sgm_ctx *c, const sgm_frame *frames, const sgm_remap *rem
     rc = enqueue_frames(frames, n, plans, hl, sw, rect, reinterpret_cast<char *>(blk.ptr), s,
                         c->profiling ? &b.prof : nullptr, nullptr, c->stripe_wait);
   }
+  if (rc == SGM_OK && b.sync_frames) {
+    // the sync words (error flags) to pinned host memory, as the batch's
+    // last step: once its done event has completed they are readable
+    const size_t bytes = (size_t)n * kSyncWords * 4;
+    if (bytes <= kSyncHostBytes && !c->sync_pool.empty()) {
+      b.sync_host = c->sync_pool.back();
+      c->sync_pool.pop_back();
+    } else if (hipHostMalloc((void **)&b.sync_host, std::max(bytes, kSyncHostBytes), hipHostMallocDefault) !=
+               hipSuccess) {
+      b.sync_host = nullptr;
+      rc = fail(SGM_EHIP, "hipHostMalloc of %zu bytes failed", bytes);
+    }
+    if (rc == SGM_OK && hipMemcpyAsync(b.sync_host, blk.ptr, bytes, hipMemcpyDeviceToHost, s) != hipSuccess)
+      rc = fail(SGM_EHIP, "copy of the sync words failed");
+  }
   if (rc == SGM_OK && hipEventCreateWithFlags(&b.done, hipEventDisableTiming) != hipSuccess)
     rc = fail(SGM_EHIP, "hipEventCreate failed");
   if (rc == SGM_OK && hipEventRecord(b.done, s) != hipSuccess) rc = fail(SGM_EHIP, "hipEventRecord failed");
@@ -1463,6 +1484,7 @@ static int submit_impl(sgm_ctx *c, const sgm_frame *frames, const sgm_remap *rem
     for (int g = 0; g < std::max(groups, 1); ++g) (void)hipStreamSynchronize(c->streams[(b.stream + g) % c->nstreams]);
     destroy_events(b);
     c->idle.push_back(blk);
+    if (b.sync_host) c->sync_pool.push_back(b.sync_host);
     return rc;
   }
   *ticket = c->next_ticket++;
@@ -1537,11 +1559,13 @@ static int poll_locked(sgm_ctx *c, uint64_t ticket, int *done) {
   }
   if (e != hipSuccess) return fail(SGM_EHIP, "batch %llu: %s", (unsigned long long)ticket, hipGetErrorString(e));
   int bad = -1;  // a two-pass frame whose stripes gave up waiting for a neighbour
-  if (it->second.sync_frames) {
-    std::vector<uint32_t> w((size_t)it->second.sync_frames * kSyncWords);
-    if (hipMemcpy(w.data(), it->second.mem.ptr, w.size() * 4, hipMemcpyDeviceToHost) != hipSuccess) bad = -2;
+  if (it->second.sync_host) {
+    const uint32_t *w = it->second.sync_host;
     for (int i = 0; i < it->second.sync_frames && bad == -1; ++i)
       if (w[(size_t)i * kSyncWords + 1]) bad = i;
+    if ((size_t)it->second.sync_frames * kSyncWords * 4 <= kSyncHostBytes) c->sync_pool.push_back(it->second.sync_host);
+    else (void)hipHostFree(it->second.sync_host);
+    it->second.sync_host = nullptr;
   }
   for (auto &e : it->second.prof) {
     float ms = 0.f;
@@ -1554,7 +1578,6 @@ static int poll_locked(sgm_ctx *c, uint64_t ticket, int *done) {
   c->idle.push_back(it->second.mem);
   c->inflight.erase(it);
   *done = 1;
-  if (bad == -2) return fail(SGM_EHIP, "batch %llu: reading its sync words failed", (unsigned long long)ticket);
   if (bad >= 0)
     return fail(SGM_EHIP, "batch %llu, frame %d: a stripe pass gave up waiting for its neighbour stripe",
                 (unsigned long long)ticket, bad);
