@@ -25,17 +25,23 @@
 // from a double-buffered LDS row of the stripe's path costs, and at the
 // stripe's edge from the neighbouring stripe: the edge pixel's path costs of
 // every row are published as 64-bit words {two 16-bit path costs, epoch}
-// with device-scope relaxed atomic stores; the consumer loads them with
-// device-scope atomic loads (one row ahead) and retries until every word
-// carries the launch's epoch.  The epoch in the word makes a stale record
-// of an earlier launch unmistakable, and a 64-bit store is single-copy
-// atomic, so neither fences nor flags are needed.
+// with device-scope relaxed atomic stores; the consumer's edge wave (the
+// wave holding the stripe's edge pixel) keeps the records of the next rows in
+// flight as device-scope atomic loads (four rows ahead in the down pass, one
+// in the up pass, two words per lane), retries a row until every word
+// carries the launch's epoch, and hands it to the edge pixel through LDS.
+// The epoch in the word makes a stale record of an earlier launch
+// unmistakable, and a 64-bit store is single-copy atomic, so neither fences
+// nor flags are needed.  The predecessor is read without a branch (a per-lane
+// LDS address and a select) so that the vertical and diagonal recurrences
+// share one basic block and their dependent chains interleave.
 //
 // Workgroups take their stripe from a ticket counter (one atomic add each):
 // a stripe waits only for the stripe before it in ticket order, which took
 // its ticket earlier and is therefore running or done, so the waits always
 // end whatever the number of workgroups resident at once.  A wait is also
-// bounded (it then records an error and goes on).
+// bounded (after max_polls polls it records an error in the frame's sync
+// words, which the host reads when the batch is done, and goes on).
 #include "device_util.h"
 
 namespace sgmk {
