@@ -2,7 +2,8 @@
 workloads (GPU required), in the launch configurations the benchmark uses:
 
 * eight 1920x1080 pairs, D = 256, Census 9x7, 8 paths, LR check, 3x3
-  median, U/V maps, all in one sgm_submit;
+  median, U/V maps, all in one sgm_submit, on the per-direction kernels and
+  on the two-pass stripes;
 * the batch of 32 pairs of mixed sizes (320x240, 640x480, 1242x375,
   1280x720) and disparity ranges (64, 128) in one sgm_submit;
 * the four-camera request loop (640x480 and 1242x375 cameras, D = 128),
@@ -53,19 +54,30 @@ def check_frame(f, want, tag):
 
 @pytest.mark.timeout(900)
 def test_eight_1920x1080_d256_pairs_in_one_submit_match_oracle(env):
+    # on both aggregation schedules: the per-direction kernels and the
+    # two-pass stripes (8 frames: 240 stripes, so the batch runs them)
     torch, sgm, ctx = env
-    frames, inputs = [], []
+    frames, two_pass, inputs = [], [], []
+    p = full_path_params(sgm, 1920, 1080, 256)
     for i in range(8):
         left, right, _ = synthetic.make_pair("large", 4000 + i)
-        p = full_path_params(sgm, 1920, 1080, 256)
-        frames.append(sgm.Frame.alloc(p, to_dev(torch, left), to_dev(torch, right)))
-        inputs.append((p, left, right))
-    announce("8 x 1920x1080 D=256 in one submit")
+        L, R = to_dev(torch, left), to_dev(torch, right)
+        frames.append(sgm.Frame.alloc(p, L, R))
+        two_pass.append(sgm.Frame.alloc(p, L, R))
+        inputs.append((left, right))
+    announce("8 x 1920x1080 D=256 in one submit, per-direction kernels")
+    sgm.sgm_set_schedule(ctx, p, 0, two_pass=sgm.TWOPASS_OFF)
     sgm.sgm_wait(ctx, sgm.sgm_submit(ctx, frames))
+    announce("8 x 1920x1080 D=256 in one submit, two-pass stripes")
+    sgm.sgm_set_schedule(ctx, p, 0, two_pass=sgm.TWOPASS_WIDE)
+    sgm.sgm_wait(ctx, sgm.sgm_submit(ctx, two_pass))
     torch.cuda.synchronize()
-    for i, ((p, left, right), f) in enumerate(zip(inputs, frames)):
+    sgm.sgm_set_schedule(ctx, p, 0)
+    for i, ((left, right), f, g) in enumerate(zip(inputs, frames, two_pass)):
         announce("oracle frame", i)
-        check_frame(f, oracle_maps(p, left, right), "1920x1080 frame %d" % i)
+        want = oracle_maps(p, left, right)
+        check_frame(f, want, "1920x1080 frame %d" % i)
+        check_frame(g, want, "1920x1080 frame %d, two-pass" % i)
         # the maps are far from trivial: most pixels valid, many disparities
         d = to_np(f.disp)
         assert (d < 256).mean() > 0.5 and len(np.unique(d)) > 50
