@@ -93,6 +93,95 @@ __device__ __forceinline__ void recur(const u16x2 (&Lp)[K / 2], const uint32_t (
   }
 }
 
+// Raw buffer stores (a descriptor over one row of a volume; the hardware drops
+// a store whose offset lies beyond the descriptor's size), so that pixels
+// outside the image need no branch around their stores: a branch that skips
+// memory operations on some path makes the compiler's wait counts assume the
+// fewest operations in flight, i.e. wait for older loads and stores too soon.
+constexpr int kBufWord3 = 0x00020000;  // 32-bit data format (gfx9 descriptor word 3)
+constexpr int kBufNT = 2;              // non-temporal: written once, read by a later kernel
+constexpr uint32_t kDropped = 0x80000000u;  // an offset beyond any row
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t row_rsrc(void *base, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(base, (short)0, (int)bytes, kBufWord3);
+}
+
+// The chunked pixel layout of 16-bit path-cost sums ([Dp / 2] words per
+// pixel), used by the LDS rows of diagonal path costs and by S_D: lane j's NP
+// words in chunks of up to four, chunk c of the pixel's 16 lanes side by
+// side, so that one 128-bit access of a chunk by a pixel's lanes covers
+// consecutive words: no two lanes of an LDS pass on one bank, and whole
+// cache lines per store in memory (the disparity order would give each store
+// instruction 16-byte pieces at a 32-byte stride, which costs the down pass
+// a quarter of its time).
+template <int NP>
+__host__ __device__ constexpr int chunk_words(int c) {
+  return NP - 4 * c < 4 ? NP - 4 * c : 4;
+}
+template <int NP>
+__device__ __forceinline__ int chunk_at(int j, int c) {
+  return 64 * c + j * chunk_words<NP>(c);
+}
+// position of word w (disparity order) of a pixel in that layout
+template <int NP>
+__device__ __forceinline__ int chunk_pos(int w) {
+  const int t = w % NP;
+  return chunk_at<NP>(w / NP, t / 4) + t % 4;
+}
+
+typedef uint32_t u32x4v __attribute__((ext_vector_type(4)));  // 16-byte aligned
+typedef uint32_t u32x2v __attribute__((ext_vector_type(2)));
+
+template <int NP, int c>
+__device__ __forceinline__ void lds_chunk_read(U32N<NP> &v, const uint32_t *p) {
+  if constexpr (NP - 4 * c >= 4) {
+    const u32x4v a = *reinterpret_cast<const u32x4v *>(p);
+    v.v[4 * c] = a.x, v.v[4 * c + 1] = a.y, v.v[4 * c + 2] = a.z, v.v[4 * c + 3] = a.w;
+  } else {
+    const u32x2v a = *reinterpret_cast<const u32x2v *>(p);
+    v.v[4 * c] = a.x, v.v[4 * c + 1] = a.y;
+  }
+}
+template <int NP, int c>
+__device__ __forceinline__ void lds_chunk_write(const U32N<NP> &v, uint32_t *p) {
+  if constexpr (NP - 4 * c >= 4)
+    *reinterpret_cast<u32x4v *>(p) = u32x4v{v.v[4 * c], v.v[4 * c + 1], v.v[4 * c + 2], v.v[4 * c + 3]};
+  else
+    *reinterpret_cast<u32x2v *>(p) = u32x2v{v.v[4 * c], v.v[4 * c + 1]};
+}
+
+// one pixel's sums in the chunked layout to a row of S_D (off: the pixel's
+// byte offset in the row, or kDropped)
+template <int NP>
+__device__ __forceinline__ void store_pixel(const U32N<NP> &v, __amdgpu_buffer_rsrc_t r, uint32_t off, int j) {
+  if constexpr (NP >= 4)
+    __builtin_amdgcn_raw_buffer_store_b128(u32x4v{v.v[0], v.v[1], v.v[2], v.v[3]}, r, off + 4 * chunk_at<NP>(j, 0),
+                                           0, kBufNT);
+  else
+    __builtin_amdgcn_raw_buffer_store_b64(u32x2v{v.v[0], v.v[1]}, r, off + 4 * chunk_at<NP>(j, 0), 0, kBufNT);
+  if constexpr (NP == 8)
+    __builtin_amdgcn_raw_buffer_store_b128(u32x4v{v.v[4], v.v[5], v.v[6], v.v[7]}, r, off + 4 * chunk_at<NP>(j, 1),
+                                           0, kBufNT);
+  else if constexpr (NP == 6)
+    __builtin_amdgcn_raw_buffer_store_b64(u32x2v{v.v[4], v.v[5]}, r, off + 4 * chunk_at<NP>(j, 1), 0, kBufNT);
+}
+
+// and back (pix: the pixel's first word)
+template <int NP>
+__device__ __forceinline__ U32N<NP> load_pixel(const uint32_t *pix, int j) {
+  U32N<NP> v;
+  constexpr int c0 = NP >= 4 ? 4 : 2;
+  const U32N<c0> a = load_nt<c0>(pix + chunk_at<NP>(j, 0));
+#pragma unroll
+  for (int i = 0; i < c0; ++i) v.v[i] = a.v[i];
+  if constexpr (NP > 4) {
+    const U32N<NP - 4> b = load_nt<NP - 4>(pix + chunk_at<NP>(j, 1));
+#pragma unroll
+    for (int i = 0; i < NP - 4; ++i) v.v[4 + i] = b.v[i];
+  }
+  return v;
+}
+
 // LDS slot of the right-view key of zone position i (two padding slots per K
 // positions: the lanes of a pixel update positions K apart, the pixels of a
 // wave consecutive positions, and a half wave then hits 32 banks).
@@ -108,7 +197,7 @@ template <int K, bool UP, int WAVES, bool PAD>
 __global__ __launch_bounds__(WAVES * 64) void stripe_kernel(JobTable<StripeJob> t) {
   constexpr int NP = K / 2, NW = K / 4, SW = 4 * WAVES;
   constexpr int PFR = UP ? 1 : 4, ER = PFR;  // rows of costs and of edge records in flight
-  extern __shared__ uint32_t lds[];
+  extern __shared__ __align__(16) uint32_t lds[];  // 128-bit row accesses
   __shared__ int s_ticket;
   // ticket counters: word 0 (down pass) and word 2 (up pass) of the table's
   // first job
@@ -141,15 +230,15 @@ __global__ __launch_bounds__(WAVES * 64) void stripe_kernel(JobTable<StripeJob> 
   const uint32_t epoch = J.epoch;
 
   // LDS: the diagonal path costs of the stripe's pixels for two rows
-  // ([2][SW][Dp] uint16, as words), then (up pass with the LR check) two
-  // zone key rows, then the neighbour's edge pixel
+  // ([2][SW][Dp / 2] words, each pixel in the chunked layout), then the
+  // neighbour's edge pixel of the previous row (same layout), then (up pass
+  // with the LR check) two zone key rows
   uint32_t *dg = lds;
   const int dg_words = SW * Dp / 2;
   const int zn = SW + D - 1;  // zone positions of a segment of SW pixels
   const int zslots = zslot<K>(zn - 1) + 1;
-  uint32_t *zone = lds + 2 * dg_words;
-  // the neighbour's edge pixel of the previous row ([Dp] uint16 as words)
-  uint32_t *eslot = zone + 2 * zslots;
+  uint32_t *eslot = lds + 2 * dg_words;
+  uint32_t *zone = eslot + Dp / 2;
   const int zr = x0 - D + 1;
   if (UP && J.lr_check) {
     for (int i = (int)threadIdx.x; i < 2 * zslots; i += WAVES * 64) zone[i] = kInf;
@@ -220,16 +309,14 @@ __global__ __launch_bounds__(WAVES * 64) void stripe_kernel(JobTable<StripeJob> 
         }
       }
       if (ew_live) {
-        eslot[ew] = (uint32_t)prev_rec[0];
-        eslot[ew + 1] = (uint32_t)prev_rec[1];
+        eslot[chunk_pos<NP>(ew)] = (uint32_t)prev_rec[0];
+        eslot[chunk_pos<NP>(ew + 1)] = (uint32_t)prev_rec[1];
         if (r - 1 + ER < H) load_rec(r - 1 + ER, prev_rec);
       }
     }
-    U32N<NW> cw = slot;
-    slot = *reinterpret_cast<const U32N<NW> *>(cbase + (int64_t)(y_first + ystep * min(r + PFR, H - 1)) * row_cells);
     uint32_t c[NW];
 #pragma unroll
-    for (int i = 0; i < NW; ++i) c[i] = cw.v[i];
+    for (int i = 0; i < NW; ++i) c[i] = slot.v[i];
     // up pass: the path-cost slots and S_D of this pixel, loaded early
     U32N<4 * NW> sl;
     U32N<NP> sd;
@@ -242,7 +329,7 @@ __global__ __launch_bounds__(WAVES * 64) void stripe_kernel(JobTable<StripeJob> 
 #pragma unroll
         for (int i = 0; i < NW; ++i) sl.v[p * NW + i] = v.v[i];
       }
-      sd = load_nt<NP>(J.sd + cell);
+      sd = load_pixel<NP>(reinterpret_cast<const uint32_t *>(J.sd + cell - dbase), j);
     }
 
     // diagonal path: the predecessor x -/+ 1 of the previous row, read
@@ -252,9 +339,12 @@ __global__ __launch_bounds__(WAVES * 64) void stripe_kernel(JobTable<StripeJob> 
     // their dependent chains interleave
     const int pp = UP ? px + 1 : px - 1;  // predecessor pixel in the stripe
     const bool start = r == 0 || (UP ? (x + 1 >= W) : (x == 0));
-    const uint32_t *src = takes_edge ? eslot + dbase / 2
-                                     : dg + (buf ^ 1) * dg_words + (min(max(pp, 0), SW - 1) * Dp + dbase) / 2;
-    const U32N<NP> pv = *reinterpret_cast<const U32N<NP> *>(src);
+    U32N<NP> pv;
+    {
+      const uint32_t *pix = takes_edge ? eslot : dg + (buf ^ 1) * dg_words + min(max(pp, 0), SW - 1) * (Dp / 2);
+      lds_chunk_read<NP, 0>(pv, pix + chunk_at<NP>(j, 0));  // NP <= 8: at most two chunks
+      if constexpr (NP > 4) lds_chunk_read<NP, 1>(pv, pix + chunk_at<NP>(j, 1));
+    }
     u16x2 Lp[NP];
 #pragma unroll
     for (int q = 0; q < NP; ++q) Lp[q] = as_pair(start ? padmask[q] : pv.v[q]);
@@ -267,7 +357,9 @@ __global__ __launch_bounds__(WAVES * 64) void stripe_kernel(JobTable<StripeJob> 
       U32N<NP> v;
 #pragma unroll
       for (int q = 0; q < NP; ++q) v.v[q] = as_u32(Lcd[q]);
-      *reinterpret_cast<U32N<NP> *>(dg + buf * dg_words + (px * Dp + dbase) / 2) = v;
+      uint32_t *pix = dg + buf * dg_words + px * (Dp / 2);
+      lds_chunk_write<NP, 0>(v, pix + chunk_at<NP>(j, 0));
+      if constexpr (NP > 4) lds_chunk_write<NP, 1>(v, pix + chunk_at<NP>(j, 1));
     }
     if (gives_edge && !J.withhold) {
 #pragma unroll
@@ -277,14 +369,17 @@ __global__ __launch_bounds__(WAVES * 64) void stripe_kernel(JobTable<StripeJob> 
     }
 #pragma unroll
     for (int q = 0; q < NP; ++q) Lv[q] = Lcv[q];
+    // the ring slot's refill once its costs are consumed, into the same
+    // registers (a load into fresh ones would need a copy at the loop's back
+    // edge, which waits for every memory operation in flight)
+    slot = *reinterpret_cast<const U32N<NW> *>(cbase + (int64_t)(y_first + ystep * min(r + PFR, H - 1)) * row_cells);
 
     if constexpr (!UP) {
-      if (live) {
-        U32N<NP> o;
+      U32N<NP> o;
 #pragma unroll
-        for (int q = 0; q < NP; ++q) o.v[q] = as_u32(Lcv[q]) + as_u32(Lcd[q]);
-        store_nt<NP>(J.sd + cell, o);
-      }
+      for (int q = 0; q < NP; ++q) o.v[q] = as_u32(Lcv[q]) + as_u32(Lcd[q]);
+      store_pixel<NP>(o, row_rsrc(J.sd + (int64_t)y * row_cells, (uint32_t)(row_cells * 2)),
+                      live ? (uint32_t)(x * Dp * 2) : kDropped, j);
     } else {
       // S over the eight paths as packed 16-bit pairs (no carry reaches a
       // valid half: every valid sum is below 65536, and padding halves lie
