@@ -194,8 +194,8 @@ struct StripeJob {
   int blk0;
 };
 constexpr int kSyncWords = 4;
-// LDS bytes of a stripe workgroup.
-size_t stripe_lds(int K, int D, int waves);
+// LDS bytes of a stripe workgroup (up: the bottom-up pass).
+size_t stripe_lds(int K, int D, int waves, bool up);
 // One launch per job table; K = agg_k(D) of every job; waves: 8 or 16.
 void launch_stripes(std::vector<StripeJob> jobs, int K, bool up, int waves, hipStream_t s);
 struct SyncZeroJob {

@@ -102,8 +102,8 @@ constexpr int kBufWord3 = 0x00020000;  // 32-bit data format (gfx9 descriptor wo
 constexpr int kBufNT = 2;              // non-temporal: written once, read by a later kernel
 constexpr uint32_t kDropped = 0x80000000u;  // an offset beyond any row
 
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t row_rsrc(void *base, uint32_t bytes) {
-  return __builtin_amdgcn_make_buffer_rsrc(base, (short)0, (int)bytes, kBufWord3);
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t row_rsrc(const void *base, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, (int)bytes, kBufWord3);
 }
 
 // The chunked pixel layout of 16-bit path-cost sums ([Dp / 2] words per
@@ -121,12 +121,6 @@ __host__ __device__ constexpr int chunk_words(int c) {
 template <int NP>
 __device__ __forceinline__ int chunk_at(int j, int c) {
   return 64 * c + j * chunk_words<NP>(c);
-}
-// position of word w (disparity order) of a pixel in that layout
-template <int NP>
-__device__ __forceinline__ int chunk_pos(int w) {
-  const int t = w % NP;
-  return chunk_at<NP>(w / NP, t / 4) + t % 4;
 }
 
 typedef uint32_t u32x4v __attribute__((ext_vector_type(4)));  // 16-byte aligned
@@ -150,6 +144,27 @@ __device__ __forceinline__ void lds_chunk_write(const U32N<NP> &v, uint32_t *p) 
     *reinterpret_cast<u32x2v *>(p) = u32x2v{v.v[4 * c], v.v[4 * c + 1]};
 }
 
+// N words at byte offset off of a row (loads by row descriptor: one 32-bit
+// offset per lane instead of a 64-bit address per load)
+template <int N, int AUX>
+__device__ __forceinline__ U32N<N> load_row(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+  U32N<N> v;
+  if constexpr (N == 4) {
+    const u32x4v a = __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, AUX);
+    v.v[0] = a.x, v.v[1] = a.y, v.v[2] = a.z, v.v[3] = a.w;
+  } else if constexpr (N == 2) {
+    const u32x2v a = __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, AUX);
+    v.v[0] = a.x, v.v[1] = a.y;
+  } else if constexpr (N == 1) {
+    v.v[0] = __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, AUX);
+  } else {
+    static_assert(N == 3, "row loads of 1 to 4 words");
+    const u32x2v a = __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, AUX);
+    v.v[0] = a.x, v.v[1] = a.y, v.v[2] = __builtin_amdgcn_raw_buffer_load_b32(r, off + 8, 0, AUX);
+  }
+  return v;
+}
+
 // one pixel's sums in the chunked layout to a row of S_D (off: the pixel's
 // byte offset in the row, or kDropped)
 template <int NP>
@@ -166,16 +181,16 @@ __device__ __forceinline__ void store_pixel(const U32N<NP> &v, __amdgpu_buffer_r
     __builtin_amdgcn_raw_buffer_store_b64(u32x2v{v.v[4], v.v[5]}, r, off + 4 * chunk_at<NP>(j, 1), 0, kBufNT);
 }
 
-// and back (pix: the pixel's first word)
+// and back (off: the pixel's byte offset in the row)
 template <int NP>
-__device__ __forceinline__ U32N<NP> load_pixel(const uint32_t *pix, int j) {
+__device__ __forceinline__ U32N<NP> load_pixel(__amdgpu_buffer_rsrc_t r, uint32_t off, int j) {
   U32N<NP> v;
   constexpr int c0 = NP >= 4 ? 4 : 2;
-  const U32N<c0> a = load_nt<c0>(pix + chunk_at<NP>(j, 0));
+  const U32N<c0> a = load_row<c0, kBufNT>(r, off + 4 * chunk_at<NP>(j, 0));
 #pragma unroll
   for (int i = 0; i < c0; ++i) v.v[i] = a.v[i];
   if constexpr (NP > 4) {
-    const U32N<NP - 4> b = load_nt<NP - 4>(pix + chunk_at<NP>(j, 1));
+    const U32N<NP - 4> b = load_row<NP - 4, kBufNT>(r, off + 4 * chunk_at<NP>(j, 1));
 #pragma unroll
     for (int i = 0; i < NP - 4; ++i) v.v[4 + i] = b.v[i];
   }
@@ -231,14 +246,17 @@ __global__ __launch_bounds__(WAVES * 64) void stripe_kernel(JobTable<StripeJob> 
 
   // LDS: the diagonal path costs of the stripe's pixels for two rows
   // ([2][SW][Dp / 2] words, each pixel in the chunked layout), then the
-  // neighbour's edge pixel of the previous row (same layout), then (up pass
-  // with the LR check) two zone key rows
+  // neighbour's edge pixel of the previous row (same layout), then (up pass)
+  // the pixels' partial sums ([SW][Dp / 2] words, same layout) and, with the
+  // LR check, two zone key rows
   uint32_t *dg = lds;
   const int dg_words = SW * Dp / 2;
   const int zn = SW + D - 1;  // zone positions of a segment of SW pixels
   const int zslots = zslot<K>(zn - 1) + 1;
   uint32_t *eslot = lds + 2 * dg_words;
-  uint32_t *zone = eslot + Dp / 2;
+  // (up pass) each pixel's partial sum S_D + four slots of the current row
+  uint32_t *pacc = eslot + Dp / 2;
+  uint32_t *zone = pacc + (UP ? SW * Dp / 2 : 0);
   const int zr = x0 - D + 1;
   if (UP && J.lr_check) {
     for (int i = (int)threadIdx.x; i < 2 * zslots; i += WAVES * 64) zone[i] = kInf;
@@ -255,7 +273,6 @@ __global__ __launch_bounds__(WAVES * 64) void stripe_kernel(JobTable<StripeJob> 
   const bool edge_wave = (UP ? wave == WAVES - 1 : wave == 0) && (UP ? s + 1 < ns : s > 0);
   const int s_in = min(max(UP ? s + 1 : s - 1, 0), ns - 1);  // the neighbour (if any)
   const uint64_t *bnd_in = J.bnd + ((int64_t)s_in * H) * (Dp / 2);
-  uint64_t *bnd_out = J.bnd + ((int64_t)s * H) * (Dp / 2) + dbase / 2;
   const int ew = 2 * lane;                  // this lane's first word of a record
   const bool ew_live = ew < Dp / 2;         // Dp / 2 words per record (even)
   bool failed = false;
@@ -263,7 +280,11 @@ __global__ __launch_bounds__(WAVES * 64) void stripe_kernel(JobTable<StripeJob> 
   const int ystep = UP ? -1 : 1;
   const int y_first = UP ? H - 1 : 0;
   const int64_t row_cells = (int64_t)W * Dp;
-  const uint8_t *cbase = J.cost + (int64_t)xc * Dp + dbase;
+  const uint32_t lane_off = (uint32_t)(xc * Dp + dbase);  // the lane's bytes in a uint8 row
+  auto load_costs = [&](int pr) {
+    return load_row<NW, 0>(row_rsrc(J.cost + (int64_t)(y_first + ystep * pr) * row_cells, (uint32_t)row_cells),
+                           lane_off);
+  };
 
   u16x2 Lv[NP];  // vertical path: this pixel's previous row
 #pragma unroll
@@ -285,7 +306,22 @@ __global__ __launch_bounds__(WAVES * 64) void stripe_kernel(JobTable<StripeJob> 
   U32N<NW> ring[PFR];
 #pragma unroll
   for (int u = 0; u < PFR; ++u)
-    ring[u] = *reinterpret_cast<const U32N<NW> *>(cbase + (int64_t)(y_first + ystep * min(u, H - 1)) * row_cells);
+    ring[u] = load_costs(min(u, H - 1));
+  // up pass: S_D and the four path-cost slots of the next pass row
+  U32N<4 * NW> sl;
+  U32N<NP> sd;
+  auto load_sums = [&](int pr) {
+    const int64_t row0 = (int64_t)(y_first + ystep * pr) * row_cells;
+    const int64_t slot = (int64_t)H * row_cells;
+#pragma unroll
+    for (int p = 0; p < 4; ++p) {
+      const U32N<NW> v = load_row<NW, kBufNT>(row_rsrc(J.lr4 + p * slot + row0, (uint32_t)row_cells), lane_off);
+#pragma unroll
+      for (int i = 0; i < NW; ++i) sl.v[p * NW + i] = v.v[i];
+    }
+    sd = load_pixel<NP>(row_rsrc(J.sd + row0, (uint32_t)(row_cells * 2)), (uint32_t)(xc * Dp * 2), j);
+  };
+  if constexpr (UP) load_sums(0);
   __syncthreads();  // zone rows cleared
 
   auto row = [&](int r, U32N<NW> &slot, uint64_t (&prev_rec)[2]) {
@@ -309,8 +345,10 @@ __global__ __launch_bounds__(WAVES * 64) void stripe_kernel(JobTable<StripeJob> 
         }
       }
       if (ew_live) {
-        eslot[chunk_pos<NP>(ew)] = (uint32_t)prev_rec[0];
-        eslot[chunk_pos<NP>(ew + 1)] = (uint32_t)prev_rec[1];
+        int e = ew;
+        asm volatile("" : "+v"(e));  // recomputed per row, not held in a register along the row
+        eslot[e] = (uint32_t)prev_rec[0];  // records are in the chunked layout
+        eslot[e + 1] = (uint32_t)prev_rec[1];
         if (r - 1 + ER < H) load_rec(r - 1 + ER, prev_rec);
       }
     }
@@ -318,18 +356,25 @@ __global__ __launch_bounds__(WAVES * 64) void stripe_kernel(JobTable<StripeJob> 
 #pragma unroll
     for (int i = 0; i < NW; ++i) c[i] = slot.v[i];
     // up pass: the path-cost slots and S_D of this pixel, loaded early
-    U32N<4 * NW> sl;
-    U32N<NP> sd;
-    const int64_t cell = ((int64_t)y * W + xc) * Dp + dbase;
+    // up pass: this row's S_D and path-cost slots (loaded a row earlier) summed
+    // into the pixel's row of pacc, and the next row's loads issued into the
+    // same registers, so that they have a whole row to arrive
     if constexpr (UP) {
-      const int64_t slot = (int64_t)H * row_cells;
+      U32N<NP> part;
 #pragma unroll
-      for (int p = 0; p < 4; ++p) {
-        const U32N<NW> v = load_nt<NW>(J.lr4 + p * slot + cell);
+      for (int q = 0; q < NP; ++q) part.v[q] = sd.v[q];
 #pragma unroll
-        for (int i = 0; i < NW; ++i) sl.v[p * NW + i] = v.v[i];
-      }
-      sd = load_pixel<NP>(reinterpret_cast<const uint32_t *>(J.sd + cell - dbase), j);
+      for (int p = 0; p < 4; ++p)
+#pragma unroll
+        for (int i = 0; i < NW; ++i) {
+          const uint32_t w = sl.v[p * NW + i];
+          part.v[2 * i] += __builtin_amdgcn_perm(0u, w, 0x0c010c00u);
+          part.v[2 * i + 1] += __builtin_amdgcn_perm(0u, w, 0x0c030c02u);
+        }
+      uint32_t *pix = pacc + px * (Dp / 2);
+      lds_chunk_write<NP, 0>(part, pix + chunk_at<NP>(j, 0));
+      if constexpr (NP > 4) lds_chunk_write<NP, 1>(part, pix + chunk_at<NP>(j, 1));
+      load_sums(min(r + 1, H - 1));
     }
 
     // diagonal path: the predecessor x -/+ 1 of the previous row, read
@@ -362,17 +407,21 @@ __global__ __launch_bounds__(WAVES * 64) void stripe_kernel(JobTable<StripeJob> 
       if constexpr (NP > 4) lds_chunk_write<NP, 1>(v, pix + chunk_at<NP>(j, 1));
     }
     if (gives_edge && !J.withhold) {
+      // (addresses as a row base and a 32-bit lane offset: a 64-bit
+      // address per lane would take registers all along the row)
+      uint64_t *brow = J.bnd + ((int64_t)s * H + y) * (Dp / 2);
 #pragma unroll
       for (int q = 0; q < NP; ++q)
-        __hip_atomic_store(bnd_out + (int64_t)y * (Dp / 2) + q, (uint64_t)as_u32(Lcd[q]) | (uint64_t)epoch << 32,
-                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(brow + (uint32_t)(chunk_at<NP>(j, q / 4) + q % 4),
+                           (uint64_t)as_u32(Lcd[q]) | (uint64_t)epoch << 32, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
     }
 #pragma unroll
     for (int q = 0; q < NP; ++q) Lv[q] = Lcv[q];
     // the ring slot's refill once its costs are consumed, into the same
     // registers (a load into fresh ones would need a copy at the loop's back
     // edge, which waits for every memory operation in flight)
-    slot = *reinterpret_cast<const U32N<NW> *>(cbase + (int64_t)(y_first + ystep * min(r + PFR, H - 1)) * row_cells);
+    slot = load_costs(min(r + PFR, H - 1));
 
     if constexpr (!UP) {
       U32N<NP> o;
@@ -384,17 +433,15 @@ __global__ __launch_bounds__(WAVES * 64) void stripe_kernel(JobTable<StripeJob> 
       // S over the eight paths as packed 16-bit pairs (no carry reaches a
       // valid half: every valid sum is below 65536, and padding halves lie
       // above the valid ones)
+      U32N<NP> part;
+      {
+        const uint32_t *pix = pacc + px * (Dp / 2);
+        lds_chunk_read<NP, 0>(part, pix + chunk_at<NP>(j, 0));
+        if constexpr (NP > 4) lds_chunk_read<NP, 1>(part, pix + chunk_at<NP>(j, 1));
+      }
       uint32_t acc[NP];
 #pragma unroll
-      for (int q = 0; q < NP; ++q) acc[q] = sd.v[q] + as_u32(Lcv[q]) + as_u32(Lcd[q]);
-#pragma unroll
-      for (int p = 0; p < 4; ++p)
-#pragma unroll
-        for (int i = 0; i < NW; ++i) {
-          const uint32_t w = sl.v[p * NW + i];
-          acc[2 * i] += __builtin_amdgcn_perm(0u, w, 0x0c010c00u);
-          acc[2 * i + 1] += __builtin_amdgcn_perm(0u, w, 0x0c030c02u);
-        }
+      for (int q = 0; q < NP; ++q) acc[q] = part.v[q] + as_u32(Lcv[q]) + as_u32(Lcd[q]);
       uint32_t best = kInf;
       uint32_t *zrow = zone + buf * zslots;
 #pragma unroll
@@ -408,15 +455,18 @@ __global__ __launch_bounds__(WAVES * 64) void stripe_kernel(JobTable<StripeJob> 
         }
       }
       best = row16_allmin_u32(best);
-      if (live && j == 0) J.dl[(int64_t)y * W + x] = (uint16_t)(best & 0xFF);
+      __builtin_amdgcn_raw_buffer_store_b16((unsigned short)(best & 0xFF), row_rsrc(J.dl + (int64_t)y * W, W * 2),
+                                            live && j == 0 ? (uint32_t)(x * 2) : kDropped, 0, 0);
     }
     __syncthreads();
     if (UP && J.lr_check) {
       // the row's zone keys out, and the zone row cleared for two rows on
       uint32_t *zrow = zone + buf * zslots;
-      uint32_t *part = J.part + ((int64_t)y * ns + s) * zn;
-      for (int i = (int)threadIdx.x; i < zn; i += WAVES * 64) {
-        part[i] = zrow[zslot<K>(i)];
+      const __amdgpu_buffer_rsrc_t prow = row_rsrc(J.part + ((int64_t)y * ns + s) * zn, (uint32_t)zn * 4);
+      int i0 = (int)threadIdx.x;
+      asm volatile("" : "+v"(i0));  // recomputed per row, not held in a register along the row
+      for (int i = i0; i < zn; i += WAVES * 64) {
+        __builtin_amdgcn_raw_buffer_store_b32(zrow[zslot<K>(i)], prow, (uint32_t)i * 4, 0, 0);
         zrow[zslot<K>(i)] = kInf;
       }
     }
@@ -449,11 +499,12 @@ void launch_zero_sync(std::vector<SyncZeroJob> jobs, hipStream_t s) {
       });
 }
 
-size_t stripe_lds(int K, int D, int waves) {
+size_t stripe_lds(int K, int D, int waves, bool up) {
   const int SW = 4 * waves, Dp = 16 * K;
   const int zn = SW + D - 1;
   const int zslots = (K & (K - 1)) == 0 ? zn - 1 + 2 * ((zn - 1) / K) + 1 : zn - 1 + ((zn - 1) >> 3) + 1;
-  return (size_t)2 * SW * Dp * 2 + (size_t)2 * zslots * 4 + (size_t)Dp * 2;
+  // diagonal rows, edge pixel, (up) partial sums, zone rows
+  return (size_t)2 * SW * Dp * 2 + (size_t)Dp * 2 + (up ? (size_t)SW * Dp * 2 : 0) + (size_t)2 * zslots * 4;
 }
 
 template <int K, bool UP, int WAVES>
@@ -481,7 +532,7 @@ void launch_stripes(std::vector<StripeJob> jobs, int K, bool up, int waves, hipS
     maxd = std::max(maxd, j.D);
     j.nstripes = (j.W + 4 * waves - 1) / (4 * waves);
   }
-  const size_t lds = stripe_lds(K, maxd, waves);
+  const size_t lds = stripe_lds(K, maxd, waves, up);
   for_each_table(
       jobs, [](const StripeJob &j) { return (long)j.nstripes; },
       [&](const JobTable<StripeJob> &t, int blocks) {
