@@ -12,11 +12,14 @@
 // rows:
 //
 //   down pass (T->B, TL->BR), rows top to bottom: writes S_D = L_TB + L_TLBR
-//     as uint16 [H][W][Dp];
+//     as uint16 [H][W][Dp], each pixel in the chunked layout below;
 //   up pass (B->T, BR->TL), rows bottom to top: S = S_D + L_BT + L_BRTL + the
 //     four slots, then the WTA map D_L and each (row, stripe)'s right-view
 //     keys, in the layout of the disparity kernel's row segments (segment
 //     length SW), so that the LR check and the median read them unchanged.
+//     A row's S_D and slots are loaded a row ahead: at the start of a row
+//     they are summed into a partial sum parked in LDS, and the next row's
+//     loads go into the same registers.
 //
 // Lane layout: 16 lanes per pixel (a DPP row), lane j owning the K
 // disparities jK .. jK+K-1, four pixels per wave, consecutive pixels in
@@ -25,16 +28,24 @@
 // from a double-buffered LDS row of the stripe's path costs, and at the
 // stripe's edge from the neighbouring stripe: the edge pixel's path costs of
 // every row are published as 64-bit words {two 16-bit path costs, epoch}
-// with device-scope relaxed atomic stores; the consumer's edge wave (the
-// wave holding the stripe's edge pixel) keeps the records of the next rows in
-// flight as device-scope atomic loads (four rows ahead in the down pass, one
-// in the up pass, two words per lane), retries a row until every word
-// carries the launch's epoch, and hands it to the edge pixel through LDS.
-// The epoch in the word makes a stale record of an earlier launch
-// unmistakable, and a 64-bit store is single-copy atomic, so neither fences
-// nor flags are needed.  The predecessor is read without a branch (a per-lane
-// LDS address and a select) so that the vertical and diagonal recurrences
-// share one basic block and their dependent chains interleave.
+// (in the chunked order) with device-scope relaxed atomic stores; the
+// consumer's edge wave (the wave holding the stripe's edge pixel) keeps the
+// records of the next rows in flight as device-scope atomic loads (four rows
+// ahead in the down pass, one in the up pass, two words per lane), retries a
+// row until every word carries the launch's epoch, and hands it to the edge
+// pixel through LDS.  The epoch in the word makes a stale record of an
+// earlier launch unmistakable, and a 64-bit store is single-copy atomic, so
+// neither fences nor flags are needed.  The predecessor is read without a
+// branch (a per-lane LDS address and a select) so that the vertical and
+// diagonal recurrences share one basic block and their dependent chains
+// interleave.
+//
+// Memory operations go through per-row buffer descriptors (a scalar base and
+// a 32-bit lane offset) and stores of pixels outside the image are dropped by
+// the descriptor's range check rather than skipped by a branch: both keep the
+// compiler's in-order wait counts as loose as the ring allows and the
+// registers within the 128 a 1024-thread workgroup has (a spill's reload
+// would wait for every load in flight).
 //
 // Workgroups take their stripe from a ticket counter (one atomic add each):
 // a stripe waits only for the stripe before it in ticket order, which took
