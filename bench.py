@@ -500,16 +500,22 @@ def dominant_kernel(p, frames, sched):
     """(kernel name, library stage, algorithmic bytes per launch, unit
     evaluations per launch, description) of the dominant kernel of the
     schedule: the 8-direction aggregation launch, or -- on the two-pass
-    schedule -- the bottom-up stripe pass, which reads each cell's cost, its
-    uint16 S_D and the four uint8 per-direction path costs (7 B per cell)
-    for its two paths and the selection."""
+    schedule -- the bottom-up stripe pass, which reads each cell's uint16 S_D
+    and the four uint8 per-direction path costs, and its cost (7 B per cell)
+    or, where the frame has Census code records (horizontal costs from
+    codes), one 16-byte code record per pixel instead of the costs, for its
+    two paths and the selection."""
     if sched.get("two_pass", "off") == "off":
         return (agg_kernel_name(sched), "aggregate", agg_alg_bytes(p, frames, sched), frames * p.disp_evals(),
                 "8 directions of %d frames in one launch" % frames)
     waves = 16 if sched["two_pass"] == "wide" else 8
+    codes = sched["h_costs"] == "codes"
     cells = p.width * p.height * p.max_disp
-    return ("stripe_kernel<16, true, %d, false>" % waves, "disparity", frames * 7 * cells, frames * 2 * cells,
-            "bottom-up stripe pass of %d frames: B->T, BR->TL, the 8-path sum and the selection" % frames)
+    per_frame = 6 * cells + (CODE_RECORD_BYTES * p.width * p.height if codes else cells)
+    return ("stripe_kernel<16, true, %d, false, %s>" % (waves, "true" if codes else "false"), "disparity",
+            frames * per_frame, frames * 2 * cells,
+            "bottom-up stripe pass of %d frames: B->T, BR->TL, the 8-path sum and the selection%s"
+            % (frames, ", costs from Census code records" if codes else ""))
 
 
 def agg_alg_bytes(p, frames, sched):

@@ -725,13 +725,20 @@ int enqueue_frames(const sgm_frame *fr, int n, const std::vector<FramePlan> &pla
     }
   }
   // the stripe passes, one launch per (disparities per lane, stripe width)
-  auto stripe_jobs = [&](int K, int waves, uint32_t epoch) {
+  // frames with Census code records (bit 8: horizontal costs from codes)
+  // form their stripe passes' costs from the codes, the others read the
+  // cost volume: separate launches
+  auto stripe_jobs = [&](int K, int waves, bool codes, uint32_t epoch) {
     std::vector<StripeJob> sj;
     for (int i = 0; i < n; ++i) {
       const sgm_params &p = fr[i].p;
-      if (tp_waves(i) != waves || k_of(p) != K) continue;
+      const bool has_codes = ((hlps[i] >> 8) & 1) && (K == 8 || K == 16);
+      if (tp_waves(i) != waves || k_of(p) != K || has_codes != codes) continue;
       StripeJob j{};
       j.cost = reinterpret_cast<const uint8_t *>(mem + plans[i].off_cost);
+      if (has_codes)  // the records start after Dp padding records
+        j.codes = reinterpret_cast<const uint64_t *>(mem + plans[i].off_codes) + 2 * (size_t)dp_of(p);
+      j.nbits = nbits_of(p);
       j.sd = reinterpret_cast<uint16_t *>(mem + plans[i].off_sd);
       j.lr4 = reinterpret_cast<const uint8_t *>(mem + plans[i].off_lr);
       j.bnd = reinterpret_cast<uint64_t *>(mem + plans[i].off_bnd);
@@ -755,13 +762,14 @@ int enqueue_frames(const sgm_frame *fr, int n, const std::vector<FramePlan> &pla
   };
   const uint32_t epoch_down = next_epoch(), epoch_up = next_epoch();
   for (int K : {4, 8, 12, 16})
-    for (int waves : {8, 16}) {
-      std::vector<StripeJob> sj = stripe_jobs(K, waves, epoch_down);
-      if (sj.empty()) continue;
-      launch_stripes(sj, K, false, waves, s);
-      CHECK(check_launch());
-      ++groups;
-    }
+    for (int waves : {8, 16})
+      for (bool codes : {false, true}) {
+        std::vector<StripeJob> sj = stripe_jobs(K, waves, codes, epoch_down);
+        if (sj.empty()) continue;
+        launch_stripes(sj, K, false, waves, codes, s);
+        CHECK(check_launch());
+        ++groups;
+      }
   CHECK(mark.end(groups));
   CHECK(mark.begin(SGM_STAGE_DISPARITY));
   groups = 0;
@@ -795,13 +803,14 @@ int enqueue_frames(const sgm_frame *fr, int n, const std::vector<FramePlan> &pla
     }
   }
   for (int K : {4, 8, 12, 16})
-    for (int waves : {8, 16}) {
-      std::vector<StripeJob> sj = stripe_jobs(K, waves, epoch_up);
-      if (sj.empty()) continue;
-      launch_stripes(sj, K, true, waves, s);
-      CHECK(check_launch());
-      ++groups;
-    }
+    for (int waves : {8, 16})
+      for (bool codes : {false, true}) {
+        std::vector<StripeJob> sj = stripe_jobs(K, waves, codes, epoch_up);
+        if (sj.empty()) continue;
+        launch_stripes(sj, K, true, waves, codes, s);
+        CHECK(check_launch());
+        ++groups;
+      }
   // row segments of a frame's right-view keys: the stripes of two-pass
   // frames, else those of the disparity kernel
   auto segments = [&](int i, int *nseg, int *seglen) {

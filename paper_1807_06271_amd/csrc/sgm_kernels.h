@@ -179,7 +179,10 @@ void launch_uv(std::vector<UVJob> jobs, hipStream_t s);
 // one stripe).  Eligible frames: Census costs (uint8 volume), uint8 path
 // costs, all 8 paths.
 struct StripeJob {
-  const uint8_t *cost;  // [H][W][Dp]
+  const uint8_t *cost;  // [H][W][Dp] (launches without codes)
+  const uint64_t *codes;  // launches with codes: Census code records {left, right} per pixel [H][W]
+                          // (Dp zero records before pixel 0)
+  int nbits;              // N_b: the cost where x - d < 0
   uint16_t *sd;         // S_D = L_TB + L_TLBR, uint16 [H][W][Dp] (down: written, up: read)
   const uint8_t *lr4;   // up: the uint8 path costs of L->R, R->L, TR->BL, BL->TR [4][H][W][Dp]
   uint64_t *bnd;        // [nstripes][H][Dp / 2]: each stripe's published edge pixel per row
@@ -195,9 +198,11 @@ struct StripeJob {
 };
 constexpr int kSyncWords = 4;
 // LDS bytes of a stripe workgroup (up: the bottom-up pass).
-size_t stripe_lds(int K, int D, int waves, bool up);
-// One launch per job table; K = agg_k(D) of every job; waves: 8 or 16.
-void launch_stripes(std::vector<StripeJob> jobs, int K, bool up, int waves, hipStream_t s);
+size_t stripe_lds(int K, int D, int waves, bool up, bool codes);
+// One launch per job table; K = agg_k(D) of every job; waves: 8 or 16;
+// codes: costs formed from every job's Census code records (K = 8 or 16)
+// instead of read from the cost volume.
+void launch_stripes(std::vector<StripeJob> jobs, int K, bool up, int waves, bool codes, hipStream_t s);
 struct SyncZeroJob {
   uint32_t *p;
   int words;

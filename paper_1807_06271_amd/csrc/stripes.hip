@@ -21,6 +21,12 @@
 //     they are summed into a partial sum parked in LDS, and the next row's
 //     loads go into the same registers.
 //
+// Matching costs (equation (1)): read from the uint8 cost volume, or (CODES:
+// frames whose horizontal directions run on Census windows, so that their
+// code records {left, right} exist) formed from the Census codes, which the
+// workgroup stages in LDS a row ahead: the right-view codes of positions
+// x0 - Dp + 1 .. x0 + SW - 1 and the left codes of its pixels.
+//
 // Lane layout: 16 lanes per pixel (a DPP row), lane j owning the K
 // disparities jK .. jK+K-1, four pixels per wave, consecutive pixels in
 // consecutive rows of a wave.  A pixel's vertical predecessor is its own
@@ -69,10 +75,10 @@ __device__ __forceinline__ u16x2 padd_sat(u16x2 a, u16x2 b) { return __builtin_e
 constexpr uint32_t kInf = 0xFFFFFFFFu;
 
 // One pixel of equation (2) for the lane's K disparities (16 lanes per
-// pixel): Lp the predecessor's path costs (packed pairs), c the lane's K
-// uint8 costs (four per word).  Pairs with d >= D are forced to 0xFFFF.
+// pixel): Lp the predecessor's path costs and C the lane's K matching costs
+// (packed pairs).  Pairs with d >= D are forced to 0xFFFF.
 template <int K, bool PAD>
-__device__ __forceinline__ void recur(const u16x2 (&Lp)[K / 2], const uint32_t (&c)[K / 4], u16x2 P1, u16x2 P2,
+__device__ __forceinline__ void recur(const u16x2 (&Lp)[K / 2], const u16x2 (&C)[K / 2], u16x2 P1, u16x2 P2,
                                       const uint32_t (&padmask)[K / 2], u16x2 (&Lc)[K / 2]) {
   constexpr int NP = K / 2;
   const uint32_t prev = (uint32_t)__builtin_amdgcn_update_dpp((int)kInf, (int)as_u32(Lp[NP - 1]), kDppRowShr1,
@@ -96,9 +102,7 @@ __device__ __forceinline__ void recur(const u16x2 (&Lp)[K / 2], const uint32_t (
   const u16x2 MP2 = padd_sat(M, P2);
 #pragma unroll
   for (int q = 0; q < NP; ++q) {
-    const uint32_t sel = (q & 1) ? 0x0c030c02u : 0x0c010c00u;  // bytes 2q, 2q+1 of the lane's costs
-    const u16x2 C = as_pair(__builtin_amdgcn_perm(0u, c[q >> 1], sel));
-    u16x2 v = pmin(A[q], MP2) - M + C;
+    u16x2 v = pmin(A[q], MP2) - M + C[q];
     if (PAD) v = as_pair(as_u32(v) | padmask[q]);
     Lc[q] = v;
   }
@@ -208,6 +212,10 @@ __device__ __forceinline__ U32N<NP> load_pixel(__amdgpu_buffer_rsrc_t r, uint32_
   return v;
 }
 
+// LDS slot of staged right-view Census code t (one padding slot per 16: a
+// pixel's lanes read codes 16 apart, which then fall on different banks)
+__host__ __device__ constexpr int cslot(int t) { return t + (t >> 4); }
+
 // LDS slot of the right-view key of zone position i (two padding slots per K
 // positions: the lanes of a pixel update positions K apart, the pixels of a
 // wave consecutive positions, and a half wave then hits 32 banks).
@@ -219,7 +227,7 @@ __host__ __device__ constexpr int zslot(int i) {
 
 }  // namespace
 
-template <int K, bool UP, int WAVES, bool PAD>
+template <int K, bool UP, int WAVES, bool PAD, bool CODES>
 __global__ __launch_bounds__(WAVES * 64) void stripe_kernel(JobTable<StripeJob> t) {
   constexpr int NP = K / 2, NW = K / 4, SW = 4 * WAVES;
   constexpr int PFR = UP ? 1 : 4, ER = PFR;  // rows of costs and of edge records in flight
@@ -267,7 +275,14 @@ __global__ __launch_bounds__(WAVES * 64) void stripe_kernel(JobTable<StripeJob> 
   uint32_t *eslot = lds + 2 * dg_words;
   // (up pass) each pixel's partial sum S_D + four slots of the current row
   uint32_t *pacc = eslot + Dp / 2;
-  uint32_t *zone = pacc + (UP ? SW * Dp / 2 : 0);
+  // (CODES) the Census codes of two rows: right-view codes of positions
+  // x0 - Dp + 1 + t, t < span ([2][cr_slots], slot cslot(t)), and the left
+  // codes of the stripe's pixels ([2][SW])
+  const int span = SW + Dp - 1;
+  const int cr_slots = cslot(span - 1) + 1;
+  uint64_t *cR = reinterpret_cast<uint64_t *>(pacc + (UP ? SW * Dp / 2 : 0));
+  uint64_t *cL = cR + 2 * cr_slots;
+  uint32_t *zone = reinterpret_cast<uint32_t *>(CODES ? cL + 2 * SW : cR);
   const int zr = x0 - D + 1;
   if (UP && J.lr_check) {
     for (int i = (int)threadIdx.x; i < 2 * zslots; i += WAVES * 64) zone[i] = kInf;
@@ -315,9 +330,33 @@ __global__ __launch_bounds__(WAVES * 64) void stripe_kernel(JobTable<StripeJob> 
   // the costs of the next PFR rows in a register ring (loads are
   // unconditional: past the last row they re-read it)
   U32N<NW> ring[PFR];
+  if constexpr (!CODES) {
 #pragma unroll
-  for (int u = 0; u < PFR; ++u)
-    ring[u] = load_costs(min(u, H - 1));
+    for (int u = 0; u < PFR; ++u) ring[u] = load_costs(min(u, H - 1));
+  }
+  // CODES: thread t stages position t's record {left, right} of a row; the
+  // records of the row after next are loaded while a row runs (positions
+  // right of the image read nothing: the descriptor ends at column W - 1)
+  U32N<4> crec;
+  const int ct = (int)threadIdx.x;
+  auto load_codes = [&](int pr) {
+    const int64_t p0 = (int64_t)(y_first + ystep * pr) * W + (x0 - Dp + 1);  // record of t = 0
+    const uint32_t n = (uint32_t)min(span, W - x0 + Dp - 1);
+    crec = load_row<4, 0>(row_rsrc(J.codes + 2 * p0, n * 16), ct < span ? (uint32_t)ct * 16 : kDropped);
+  };
+  auto stage_codes = [&](int b) {
+    if (ct < span) {
+      cR[b * cr_slots + cslot(ct)] = (uint64_t)crec.v[2] | (uint64_t)crec.v[3] << 32;
+      if (ct >= Dp - 1) cL[b * SW + ct - (Dp - 1)] = (uint64_t)crec.v[0] | (uint64_t)crec.v[1] << 32;
+    }
+  };
+  if constexpr (CODES) {
+    load_codes(0);
+    stage_codes(0);
+    load_codes(min(1, H - 1));
+  }
+  const bool left_edge = x0 < Dp - 1;  // some of the stripe's costs reach left of the image
+  const uint32_t nbits = (uint32_t)J.nbits;
   // up pass: S_D and the four path-cost slots of the next pass row
   U32N<4 * NW> sl;
   U32N<NP> sd;
@@ -363,10 +402,41 @@ __global__ __launch_bounds__(WAVES * 64) void stripe_kernel(JobTable<StripeJob> 
         if (r - 1 + ER < H) load_rec(r - 1 + ER, prev_rec);
       }
     }
-    uint32_t c[NW];
+    // the lane's K matching costs as pairs: from the cost ring, or formed from
+    // the staged Census codes (equation (1): C = popcount(cl ^ cr(x - d)),
+    // N_b where x - d < 0), and the next row's codes staged
+    u16x2 C[NP];
+    if constexpr (!CODES) {
 #pragma unroll
-    for (int i = 0; i < NW; ++i) c[i] = slot.v[i];
-    // up pass: the path-cost slots and S_D of this pixel, loaded early
+      for (int q = 0; q < NP; ++q)  // bytes 2q, 2q+1 of the lane's costs
+        C[q] = as_pair(__builtin_amdgcn_perm(0u, slot.v[q >> 1], (q & 1) ? 0x0c030c02u : 0x0c010c00u));
+    } else {
+      // the lane's codes are positions t0 - k, k < K (K <= 16): consecutive
+      // slots except for at most one padding slot, after k = t0 mod 16; the
+      // two bases are formed per row (held along the row, each code's
+      // address would take a register)
+      int t0 = px + Dp - 1 - dbase;  // position of x - dbase
+      asm volatile("" : "+v"(t0));
+      const uint64_t *crA = cR + buf * cr_slots + cslot(t0);
+      const uint64_t *crB = crA - 1;
+      const int rk = t0 & 15;
+      const uint64_t cl = cL[buf * SW + px];
+#pragma unroll
+      for (int q = 0; q < NP; ++q) {
+        uint32_t c0 = (uint32_t)__popcll(cl ^ (2 * q > rk ? crB : crA)[-2 * q]);
+        uint32_t c1 = (uint32_t)__popcll(cl ^ (2 * q + 1 > rk ? crB : crA)[-2 * q - 1]);
+        if (left_edge) {
+          c0 = x - dbase - 2 * q >= 0 ? c0 : nbits;
+          c1 = x - dbase - 2 * q - 1 >= 0 ? c1 : nbits;
+        }
+        C[q] = as_pair(c0 | c1 << 16);
+        // four codes at a time: all of them in flight at once would take 32
+        // registers
+        if (q % 2 == 1) __builtin_amdgcn_sched_barrier(0);
+      }
+      stage_codes(buf ^ 1);
+      load_codes(min(r + 2, H - 1));
+    }
     // up pass: this row's S_D and path-cost slots (loaded a row earlier) summed
     // into the pixel's row of pacc, and the next row's loads issued into the
     // same registers, so that they have a whole row to arrive
@@ -406,9 +476,9 @@ __global__ __launch_bounds__(WAVES * 64) void stripe_kernel(JobTable<StripeJob> 
     for (int q = 0; q < NP; ++q) Lp[q] = as_pair(start ? padmask[q] : pv.v[q]);
     // vertical path
     u16x2 Lcv[NP];
-    recur<K, PAD>(Lv, c, P1, P2, padmask, Lcv);
+    recur<K, PAD>(Lv, C, P1, P2, padmask, Lcv);
     u16x2 Lcd[NP];
-    recur<K, PAD>(Lp, c, P1, P2, padmask, Lcd);
+    recur<K, PAD>(Lp, C, P1, P2, padmask, Lcd);
     {  // this row's diagonal path costs for the next row's predecessors
       U32N<NP> v;
 #pragma unroll
@@ -432,7 +502,7 @@ __global__ __launch_bounds__(WAVES * 64) void stripe_kernel(JobTable<StripeJob> 
     // the ring slot's refill once its costs are consumed, into the same
     // registers (a load into fresh ones would need a copy at the loop's back
     // edge, which waits for every memory operation in flight)
-    slot = load_costs(min(r + PFR, H - 1));
+    if constexpr (!CODES) slot = load_costs(min(r + PFR, H - 1));
 
     if constexpr (!UP) {
       U32N<NP> o;
@@ -455,6 +525,15 @@ __global__ __launch_bounds__(WAVES * 64) void stripe_kernel(JobTable<StripeJob> 
       for (int q = 0; q < NP; ++q) acc[q] = part.v[q] + as_u32(Lcv[q]) + as_u32(Lcd[q]);
       uint32_t best = kInf;
       uint32_t *zrow = zone + buf * zslots;
+      // the lane's zone positions i0 - k: with K a power of two they cross at
+      // most one block of K (two padding slots) after k = i0 mod K, so two
+      // bases formed per row address them all (held along the row, each
+      // position's address would take a register)
+      int i0 = x - dbase - zr;
+      asm volatile("" : "+v"(i0));
+      uint32_t *zA = zrow + zslot<K>(i0);
+      uint32_t *zB = zA - 2;
+      const int mk = i0 & (K - 1);
 #pragma unroll
       for (int k = 0; k < K; ++k) {
         if (k < dvalid) {
@@ -462,7 +541,10 @@ __global__ __launch_bounds__(WAVES * 64) void stripe_kernel(JobTable<StripeJob> 
           const uint32_t Sd = (k & 1) ? acc[k >> 1] >> 16 : acc[k >> 1] & 0xFFFFu;
           const uint32_t key = Sd << 8 | (uint32_t)d;
           best = min(best, key);
-          if (J.lr_check && live && x >= d) atomicMin(&zrow[zslot<K>(x - d - zr)], key);
+          if (J.lr_check && live && x >= d) {
+            if constexpr ((K & (K - 1)) == 0) atomicMin((k > mk ? zB : zA) - k, key);
+            else atomicMin(&zrow[zslot<K>(x - d - zr)], key);
+          }
         }
       }
       best = row16_allmin_u32(best);
@@ -510,32 +592,38 @@ void launch_zero_sync(std::vector<SyncZeroJob> jobs, hipStream_t s) {
       });
 }
 
-size_t stripe_lds(int K, int D, int waves, bool up) {
+size_t stripe_lds(int K, int D, int waves, bool up, bool codes) {
   const int SW = 4 * waves, Dp = 16 * K;
   const int zn = SW + D - 1;
   const int zslots = (K & (K - 1)) == 0 ? zn - 1 + 2 * ((zn - 1) / K) + 1 : zn - 1 + ((zn - 1) >> 3) + 1;
-  // diagonal rows, edge pixel, (up) partial sums, zone rows
-  return (size_t)2 * SW * Dp * 2 + (size_t)Dp * 2 + (up ? (size_t)SW * Dp * 2 : 0) + (size_t)2 * zslots * 4;
+  // diagonal rows, edge pixel, (up) partial sums, (codes) two rows of Census
+  // codes, zone rows
+  return (size_t)2 * SW * Dp * 2 + (size_t)Dp * 2 + (up ? (size_t)SW * Dp * 2 : 0) +
+         (codes ? (size_t)2 * (cslot(SW + Dp - 2) + 1 + SW) * 8 : 0) + (size_t)2 * zslots * 4;
 }
 
-template <int K, bool UP, int WAVES>
+template <int K, bool UP, int WAVES, bool CODES>
 static void launch_kw(const JobTable<StripeJob> &t, int blocks, bool pad, size_t lds, hipStream_t s) {
-  if (pad) hipLaunchKernelGGL((stripe_kernel<K, UP, WAVES, true>), dim3(blocks), dim3(WAVES * 64), lds, s, t);
-  else hipLaunchKernelGGL((stripe_kernel<K, UP, WAVES, false>), dim3(blocks), dim3(WAVES * 64), lds, s, t);
+  if (pad)
+    hipLaunchKernelGGL((stripe_kernel<K, UP, WAVES, true, CODES>), dim3(blocks), dim3(WAVES * 64), lds, s, t);
+  else
+    hipLaunchKernelGGL((stripe_kernel<K, UP, WAVES, false, CODES>), dim3(blocks), dim3(WAVES * 64), lds, s, t);
 }
 
-template <int K>
+template <int K, bool CODES>
 static void launch_k(const JobTable<StripeJob> &t, int blocks, bool up, int waves, bool pad, size_t lds,
                      hipStream_t s) {
-  if (up && waves == 16) launch_kw<K, true, 16>(t, blocks, pad, lds, s);
-  else if (up) launch_kw<K, true, 8>(t, blocks, pad, lds, s);
-  else if (waves == 16) launch_kw<K, false, 16>(t, blocks, pad, lds, s);
-  else launch_kw<K, false, 8>(t, blocks, pad, lds, s);
+  if (up && waves == 16) launch_kw<K, true, 16, CODES>(t, blocks, pad, lds, s);
+  else if (up) launch_kw<K, true, 8, CODES>(t, blocks, pad, lds, s);
+  else if (waves == 16) launch_kw<K, false, 16, CODES>(t, blocks, pad, lds, s);
+  else launch_kw<K, false, 8, CODES>(t, blocks, pad, lds, s);
 }
 
-void launch_stripes(std::vector<StripeJob> jobs, int K, bool up, int waves, hipStream_t s) {
+void launch_stripes(std::vector<StripeJob> jobs, int K, bool up, int waves, bool codes, hipStream_t s) {
   // one launch per table of jobs; the ticket counter of a table lives in its
-  // first job's sync words (the zero kernel cleared it)
+  // first job's sync words (the zero kernel cleared it).  Costs from Census
+  // code records exist for K = 8 and 16 (the layouts with code records).
+  codes = codes && (K == 8 || K == 16);
   bool pad = false;
   int maxd = 1;
   for (auto &j : jobs) {
@@ -543,15 +631,21 @@ void launch_stripes(std::vector<StripeJob> jobs, int K, bool up, int waves, hipS
     maxd = std::max(maxd, j.D);
     j.nstripes = (j.W + 4 * waves - 1) / (4 * waves);
   }
-  const size_t lds = stripe_lds(K, maxd, waves, up);
+  const size_t lds = stripe_lds(K, maxd, waves, up, codes);
   for_each_table(
       jobs, [](const StripeJob &j) { return (long)j.nstripes; },
       [&](const JobTable<StripeJob> &t, int blocks) {
         switch (K) {
-          case 4: launch_k<4>(t, blocks, up, waves, pad, lds, s); break;
-          case 8: launch_k<8>(t, blocks, up, waves, pad, lds, s); break;
-          case 12: launch_k<12>(t, blocks, up, waves, pad, lds, s); break;
-          default: launch_k<16>(t, blocks, up, waves, pad, lds, s); break;
+          case 4: launch_k<4, false>(t, blocks, up, waves, pad, lds, s); break;
+          case 8:
+            if (codes) launch_k<8, true>(t, blocks, up, waves, pad, lds, s);
+            else launch_k<8, false>(t, blocks, up, waves, pad, lds, s);
+            break;
+          case 12: launch_k<12, false>(t, blocks, up, waves, pad, lds, s); break;
+          default:
+            if (codes) launch_k<16, true>(t, blocks, up, waves, pad, lds, s);
+            else launch_k<16, false>(t, blocks, up, waves, pad, lds, s);
+            break;
         }
       });
 }

@@ -65,20 +65,35 @@ def copies_for(W, mode):
     return -(-MIN_STRIPES // stripes)
 
 
+def lanes_k(D):
+    # disparities per lane of a 16-lane pixel
+    return 4 if D <= 64 else 8 if D <= 128 else 12 if D <= 192 else 16
+
+
 @pytest.mark.parametrize("shape", SHAPES)
 @pytest.mark.parametrize("mode", ["wide", "narrow"])
-def test_two_pass_matches_oracle(env, shape, mode):
+@pytest.mark.parametrize("costs", ["volume", "codes"])
+def test_two_pass_matches_oracle(env, shape, mode, costs):
     # the frame submitted as many times as it takes to reach the stripe
     # threshold (one launch then holds several job tables, each with its own
-    # ticket counter); every copy must equal the oracle
+    # ticket counter); every copy must equal the oracle.  costs: the stripe
+    # passes read the cost volume, or (64-lane horizontals on Census code
+    # records, 8 or 16 disparities per lane) form the costs from the records
     torch, sgm, ctx = env
     W, H, D, (cw, ch), p1, p2, lr, med = shape
+    if costs == "codes" and lanes_k(D) not in (8, 16):
+        pytest.skip("Census code records exist for 8 or 16 disparities per lane")
     n = copies_for(W, mode)
-    announce("two-pass", mode, shape, n, "copies")
+    announce("two-pass", mode, costs, shape, n, "copies")
     left, right, _ = synthetic.make_pair("kitti", W + 7 * D + H, W, H, D)
     p = params(sgm, W, H, D, cw, ch, p1, p2, lr, med)
     tp = sgm.TWOPASS_WIDE if mode == "wide" else sgm.TWOPASS_NARROW
-    sgm.sgm_set_schedule(ctx, p, 0, two_pass=tp)
+    if costs == "codes":
+        sgm.sgm_set_schedule(ctx, p, 64, h_costs=sgm.HCOSTS_CODES, two_pass=tp)
+        assert sgm.schedule_of(ctx, p)[3] == sgm.HCOSTS_CODES
+    else:
+        sgm.sgm_set_schedule(ctx, p, 0, h_costs=sgm.HCOSTS_VOLUME, two_pass=tp)
+        assert sgm.schedule_of(ctx, p)[3] == sgm.HCOSTS_VOLUME
     assert sgm.schedule_of(ctx, p)[4] == tp
     L, R = to_dev(torch, left), to_dev(torch, right)
     frames = [sgm.Frame.alloc(p, L, R) for _ in range(n)]
@@ -114,15 +129,22 @@ def test_mixed_batch_repeated_split_and_graphs(env):
     # context's streams, and replayed in graph mode
     torch, sgm, ctx = env
     announce("two-pass mixed batch")
-    # five shapes, each frame 16 times (the two-pass ones: 160 stripes)
-    specs = [(150, 40, 128, 0xFF, sgm.TWOPASS_WIDE), (150, 40, 64, 0xFF, sgm.TWOPASS_NARROW),
-             (130, 30, 128, 0x0F, sgm.TWOPASS_WIDE), (90, 44, 256, 0xFF, sgm.TWOPASS_OFF),
-             (70, 25, 64, 0xFF, sgm.TWOPASS_WIDE)]
+    # six shapes, each frame 16 times (the two-pass ones: 160 stripes or
+    # more); the last two-pass shape forms its stripe passes' costs from
+    # Census code records, the others read the cost volume: separate
+    # launches within each pass
+    specs = [(150, 40, 128, 0xFF, sgm.TWOPASS_WIDE, False), (150, 40, 64, 0xFF, sgm.TWOPASS_NARROW, False),
+             (130, 30, 128, 0x0F, sgm.TWOPASS_WIDE, False), (90, 44, 256, 0xFF, sgm.TWOPASS_OFF, False),
+             (70, 25, 64, 0xFF, sgm.TWOPASS_WIDE, False), (160, 36, 256, 0xFF, sgm.TWOPASS_WIDE, True)]
     frames, want = [], []
-    for i, (W, H, D, mask, tp) in enumerate(specs):
+    for i, (W, H, D, mask, tp, codes) in enumerate(specs):
         left, right, _ = synthetic.make_pair("kitti", 300 + i, W, H, D)
         p = sgm.Params(width=W, height=H, max_disp=D, path_mask=mask, invalid=65535 if D > 255 else 255)
-        sgm.sgm_set_schedule(ctx, p, 0, two_pass=tp)
+        if codes:
+            sgm.sgm_set_schedule(ctx, p, 64, h_costs=sgm.HCOSTS_CODES, two_pass=tp)
+            assert sgm.schedule_of(ctx, p)[3] == sgm.HCOSTS_CODES
+        else:
+            sgm.sgm_set_schedule(ctx, p, 0, h_costs=sgm.HCOSTS_VOLUME, two_pass=tp)
         o = O.sgm(left, right, D, 9, 7, mask, 10, 120, True, 1, 3, p.inv())
         L, R = to_dev(torch, left), to_dev(torch, right)
         for _ in range(16):
