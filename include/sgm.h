@@ -382,9 +382,11 @@ typedef struct {
    * and BR->TL that also sums S over all 8 paths and selects the
    * disparities; both passes walk the rows of 64-column (WIDE) or 32-column
    * (NARROW) stripes, one workgroup per stripe.  The four other paths run
-   * as per-direction kernels.  Applies to Census frames with all 8 paths
-   * and N_b + p2 <= 255 that do not use the single-pass sweep; other frames
-   * use the per-direction kernels.  A stripe is one workgroup walking all
+   * as per-direction kernels; where the frame's horizontal costs come from
+   * the Census codes (h_costs), the two passes form their costs from the
+   * same code records instead of reading the cost volume.  Applies to
+   * Census frames with all 8 paths and N_b + p2 <= 255 that do not use the
+   * single-pass sweep; other frames use the per-direction kernels.  A stripe is one workgroup walking all
    * rows, so the schedule needs many of them: a batch whose two-pass frames
    * have fewer than 128 stripes in all (ceil(width / 64) or ceil(width / 32)
    * per frame) runs them on the per-direction kernels. */
