@@ -11,8 +11,10 @@
 // argmin_d S(x_r + d, d) collects the same keys by LDS atomicMin into slot
 // x - d.  A segment [x0, x0 + n) reaches the right-view pixels of its zone
 // [x0 - D + 1, x0 + n); it writes its D_L and its zone's keys, and the LR
-// check (lr_value) takes for each x_r the minimum over the (at most two)
-// segments whose zones hold it, then checks left against right: in
+// check (lr_value) takes for each x_r the minimum over the segments whose
+// zones hold it (at most two of this kernel's segments; up to
+// (D - 1) / n + 1 of the two-pass schedule's stripes, which use the same
+// layout), then checks left against right: in
 // lr_seg_kernel, or inside median_kernel when a median follows.  Splitting
 // rows keeps every CU busy on a single frame.
 //
@@ -224,9 +226,19 @@ __device__ __forceinline__ int lr_value(const uint16_t *dl_map, const uint32_t *
   if (xr < 0) return invalid;
   const int zs = seglen + D - 1;
   const int sa = xr / seglen, sb = min((xr + D - 1) / seglen, nseg - 1);
+  const uint32_t *row = part + (int64_t)y * nseg * zs + xr + D - 1;  // segment sg's key at row[sg * (zs - seglen)]
   uint32_t key = 0xFFFFFFFFu;
-  for (int sg = sa; sg <= sb; ++sg)
-    key = min(key, part[((int64_t)y * nseg + sg) * zs + xr - (sg * seglen - D + 1)]);
+  // the segments' loads issued together (indices clamped to the last
+  // segment: a repeated load leaves the minimum unchanged): two where no
+  // position lies in more than two zones, else eight and, if segments are
+  // short, the rest one by one
+  if ((D - 1) / seglen + 2 <= 2) {
+    key = min(row[(int64_t)sa * (zs - seglen)], row[(int64_t)min(sa + 1, sb) * (zs - seglen)]);
+  } else {
+#pragma unroll
+    for (int i = 0; i < 8; ++i) key = min(key, row[(int64_t)min(sa + i, sb) * (zs - seglen)]);
+    for (int sg = sa + 8; sg <= sb; ++sg) key = min(key, row[(int64_t)sg * (zs - seglen)]);
+  }
   const int dr = (int)(key & 0xFF);
   return abs(dl - dr) <= max_diff ? dl : invalid;
 }
