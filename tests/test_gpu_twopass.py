@@ -25,6 +25,8 @@ SHAPES = [
     (1, 5, 64, (5, 5), 10, 120, 1, 3),         # one column
     (300, 1, 128, (9, 7), 10, 120, 1, 3),      # one row
     (257, 40, 250, (9, 7), 10, 120, 1, 3),
+    (1, 6, 120, (9, 7), 10, 120, 1, 3),        # one column, 8 disparities per lane (code records too)
+    (65, 3, 256, (9, 7), 10, 120, 1, 3),       # a second wide stripe with one live column
 ]
 
 
