@@ -501,17 +501,17 @@ def dominant_kernel(p, frames, sched):
     evaluations per launch, description) of the dominant kernel of the
     schedule: the 8-direction aggregation launch, or -- on the two-pass
     schedule -- the bottom-up stripe pass, which reads each cell's uint16 S_D
-    and the four uint8 per-direction path costs, and its cost (7 B per cell)
-    or, where the frame has Census code records (horizontal costs from
-    codes), one 16-byte code record per pixel instead of the costs, for its
-    two paths and the selection."""
+    (which holds four paths' sum) and the two uint8 path costs of TR->BL and
+    BL->TR, and its cost (5 B per cell) or, where the frame has Census code
+    records (horizontal costs from codes), one 16-byte code record per pixel
+    instead of the costs, for its two paths and the selection."""
     if sched.get("two_pass", "off") == "off":
         return (agg_kernel_name(sched), "aggregate", agg_alg_bytes(p, frames, sched), frames * p.disp_evals(),
                 "8 directions of %d frames in one launch" % frames)
     waves = 16 if sched["two_pass"] == "wide" else 8
     codes = sched["h_costs"] == "codes"
     cells = p.width * p.height * p.max_disp
-    per_frame = 6 * cells + (CODE_RECORD_BYTES * p.width * p.height if codes else cells)
+    per_frame = 4 * cells + (CODE_RECORD_BYTES * p.width * p.height if codes else cells)
     return ("stripe_kernel<16, true, %d, false, %s>" % (waves, "true" if codes else "false"), "disparity",
             frames * per_frame, frames * 2 * cells,
             "bottom-up stripe pass of %d frames: B->T, BR->TL, the 8-path sum and the selection%s"

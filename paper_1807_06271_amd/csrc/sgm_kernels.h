@@ -183,8 +183,9 @@ struct StripeJob {
   const uint64_t *codes;  // launches with codes: Census code records {left, right} per pixel [H][W]
                           // (Dp zero records before pixel 0)
   int nbits;              // N_b: the cost where x - d < 0
-  uint16_t *sd;         // S_D = L_TB + L_TLBR, uint16 [H][W][Dp] (down: written, up: read)
-  const uint8_t *lr4;   // up: the uint8 path costs of L->R, R->L, TR->BL, BL->TR [4][H][W][Dp]
+  uint16_t *sd;         // S_D = L_TB + L_TLBR + L_LR + L_RL, uint16 [H][W][Dp] (down: written, up: read)
+  const uint8_t *lr4;   // the uint8 path costs of L->R, R->L (read by the down pass), TR->BL, BL->TR
+                        // (read by the up pass) [4][H][W][Dp]
   uint64_t *bnd;        // [nstripes][H][Dp / 2]: each stripe's published edge pixel per row
   uint32_t *sync;       // [0] down ticket counter, [1] error flag, [2] up ticket counter
   uint16_t *dl;         // up: D_L [H][W]

@@ -12,14 +12,17 @@
 // rows:
 //
 //   down pass (T->B, TL->BR), rows top to bottom: writes S_D = L_TB + L_TLBR
-//     as uint16 [H][W][Dp], each pixel in the chunked layout below;
+//     + the L->R and R->L slots as uint16 [H][W][Dp], each pixel in the
+//     chunked layout below;
 //   up pass (B->T, BR->TL), rows bottom to top: S = S_D + L_BT + L_BRTL + the
-//     four slots, then the WTA map D_L and each (row, stripe)'s right-view
-//     keys, in the layout of the disparity kernel's row segments (segment
-//     length SW), so that the LR check and the median read them unchanged.
-//     A row's S_D and slots are loaded a row ahead: at the start of a row
-//     they are summed into a partial sum parked in LDS, and the next row's
-//     loads go into the same registers.
+//     TR->BL and BL->TR slots, then the WTA map D_L and each (row, stripe)'s
+//     right-view keys, in the layout of the disparity kernel's row segments
+//     (segment length SW), so that the LR check and the median read them
+//     unchanged.
+// Each pass adds two of the slots (the down pass has the memory headroom,
+// the up pass moved the most bytes).  A row's slots (and, up, S_D) are
+// loaded a row ahead: at the start of a row they are summed into a partial
+// sum parked in LDS, and the next row's loads go into the same registers.
 //
 // Matching costs (equation (1)): read from the uint8 cost volume, or (CODES:
 // frames whose horizontal directions run on Census windows, so that their
@@ -265,22 +268,22 @@ __global__ __launch_bounds__(WAVES * 64) void stripe_kernel(JobTable<StripeJob> 
 
   // LDS: the diagonal path costs of the stripe's pixels for two rows
   // ([2][SW][Dp / 2] words, each pixel in the chunked layout), then the
-  // neighbour's edge pixel of the previous row (same layout), then (up pass)
-  // the pixels' partial sums ([SW][Dp / 2] words, same layout) and, with the
-  // LR check, two zone key rows
+  // neighbour's edge pixel of the previous row (same layout), then the
+  // pixels' partial sums ([SW][Dp / 2] words, same layout), (CODES) two rows
+  // of Census codes and (up pass with the LR check) two zone key rows
   uint32_t *dg = lds;
   const int dg_words = SW * Dp / 2;
   const int zn = SW + D - 1;  // zone positions of a segment of SW pixels
   const int zslots = zslot<K>(zn - 1) + 1;
   uint32_t *eslot = lds + 2 * dg_words;
-  // (up pass) each pixel's partial sum S_D + four slots of the current row
+  // each pixel's partial sum of the current row: two slots (up: + S_D)
   uint32_t *pacc = eslot + Dp / 2;
   // (CODES) the Census codes of two rows: right-view codes of positions
   // x0 - Dp + 1 + t, t < span ([2][cr_slots], slot cslot(t)), and the left
   // codes of the stripe's pixels ([2][SW])
   const int span = SW + Dp - 1;
   const int cr_slots = cslot(span - 1) + 1;
-  uint64_t *cR = reinterpret_cast<uint64_t *>(pacc + (UP ? SW * Dp / 2 : 0));
+  uint64_t *cR = reinterpret_cast<uint64_t *>(pacc + SW * Dp / 2);
   uint64_t *cL = cR + 2 * cr_slots;
   uint32_t *zone = reinterpret_cast<uint32_t *>(CODES ? cL + 2 * SW : cR);
   const int zr = x0 - D + 1;
@@ -357,21 +360,25 @@ __global__ __launch_bounds__(WAVES * 64) void stripe_kernel(JobTable<StripeJob> 
   }
   const bool left_edge = x0 < Dp - 1;  // some of the stripe's costs reach left of the image
   const uint32_t nbits = (uint32_t)J.nbits;
-  // up pass: S_D and the four path-cost slots of the next pass row
-  U32N<4 * NW> sl;
+  // the two path-cost slots this pass adds (down: L->R and R->L, into S_D;
+  // up: TR->BL and BL->TR) and, up, S_D, of the next pass row
+  constexpr int S0 = UP ? 2 : 0;
+  U32N<2 * NW> sl;
   U32N<NP> sd;
   auto load_sums = [&](int pr) {
     const int64_t row0 = (int64_t)(y_first + ystep * pr) * row_cells;
     const int64_t slot = (int64_t)H * row_cells;
 #pragma unroll
-    for (int p = 0; p < 4; ++p) {
-      const U32N<NW> v = load_row<NW, kBufNT>(row_rsrc(J.lr4 + p * slot + row0, (uint32_t)row_cells), lane_off);
+    for (int p = 0; p < 2; ++p) {
+      const U32N<NW> v =
+          load_row<NW, kBufNT>(row_rsrc(J.lr4 + (S0 + p) * slot + row0, (uint32_t)row_cells), lane_off);
 #pragma unroll
       for (int i = 0; i < NW; ++i) sl.v[p * NW + i] = v.v[i];
     }
-    sd = load_pixel<NP>(row_rsrc(J.sd + row0, (uint32_t)(row_cells * 2)), (uint32_t)(xc * Dp * 2), j);
+    if constexpr (UP)
+      sd = load_pixel<NP>(row_rsrc(J.sd + row0, (uint32_t)(row_cells * 2)), (uint32_t)(xc * Dp * 2), j);
   };
-  if constexpr (UP) load_sums(0);
+  load_sums(0);
   __syncthreads();  // zone rows cleared
 
   auto row = [&](int r, U32N<NW> &slot, uint64_t (&prev_rec)[2]) {
@@ -437,15 +444,15 @@ __global__ __launch_bounds__(WAVES * 64) void stripe_kernel(JobTable<StripeJob> 
       stage_codes(buf ^ 1);
       load_codes(min(r + 2, H - 1));
     }
-    // up pass: this row's S_D and path-cost slots (loaded a row earlier) summed
-    // into the pixel's row of pacc, and the next row's loads issued into the
-    // same registers, so that they have a whole row to arrive
-    if constexpr (UP) {
+    // this row's two path-cost slots and (up) S_D, loaded a row earlier,
+    // summed into the pixel's row of pacc, and the next row's loads issued
+    // into the same registers, so that they have a whole row to arrive
+    {
       U32N<NP> part;
 #pragma unroll
-      for (int q = 0; q < NP; ++q) part.v[q] = sd.v[q];
+      for (int q = 0; q < NP; ++q) part.v[q] = UP ? sd.v[q] : 0u;
 #pragma unroll
-      for (int p = 0; p < 4; ++p)
+      for (int p = 0; p < 2; ++p)
 #pragma unroll
         for (int i = 0; i < NW; ++i) {
           const uint32_t w = sl.v[p * NW + i];
@@ -505,9 +512,16 @@ __global__ __launch_bounds__(WAVES * 64) void stripe_kernel(JobTable<StripeJob> 
     if constexpr (!CODES) slot = load_costs(min(r + PFR, H - 1));
 
     if constexpr (!UP) {
+      // S_D = L_TB + L_TLBR + L_LR + L_RL as packed 16-bit pairs (no carry
+      // reaches a valid half, as in the up pass's sum below)
       U32N<NP> o;
+      {
+        const uint32_t *pix = pacc + px * (Dp / 2);
+        lds_chunk_read<NP, 0>(o, pix + chunk_at<NP>(j, 0));
+        if constexpr (NP > 4) lds_chunk_read<NP, 1>(o, pix + chunk_at<NP>(j, 1));
+      }
 #pragma unroll
-      for (int q = 0; q < NP; ++q) o.v[q] = as_u32(Lcv[q]) + as_u32(Lcd[q]);
+      for (int q = 0; q < NP; ++q) o.v[q] += as_u32(Lcv[q]) + as_u32(Lcd[q]);
       store_pixel<NP>(o, row_rsrc(J.sd + (int64_t)y * row_cells, (uint32_t)(row_cells * 2)),
                       live ? (uint32_t)(x * Dp * 2) : kDropped, j);
     } else {
@@ -596,9 +610,9 @@ size_t stripe_lds(int K, int D, int waves, bool up, bool codes) {
   const int SW = 4 * waves, Dp = 16 * K;
   const int zn = SW + D - 1;
   const int zslots = (K & (K - 1)) == 0 ? zn - 1 + 2 * ((zn - 1) / K) + 1 : zn - 1 + ((zn - 1) >> 3) + 1;
-  // diagonal rows, edge pixel, (up) partial sums, (codes) two rows of Census
+  // diagonal rows, edge pixel, partial sums, (codes) two rows of Census
   // codes, zone rows
-  return (size_t)2 * SW * Dp * 2 + (size_t)Dp * 2 + (up ? (size_t)SW * Dp * 2 : 0) +
+  return (size_t)2 * SW * Dp * 2 + (size_t)Dp * 2 + (size_t)SW * Dp * 2 +
          (codes ? (size_t)2 * (cslot(SW + Dp - 2) + 1 + SW) * 8 : 0) + (size_t)2 * zslots * 4;
 }
 
