@@ -412,10 +412,11 @@ def served_p99(extras):
             for mode in ("continuous_batching", "per_frame")}
 
 
-def measured_traffic(kernel_prefix, record="traffic_agg_1242x375_d128.json"):
-    """HBM bytes per launch of an aggregation kernel from a committed
-    FETCH_SIZE / WRITE_SIZE counter record (scaled by a copy of known size), or
-    None when the kernel sources changed since the counters were taken."""
+def measured_traffic(kernel_prefix, record="traffic_agg_1242x375_d128.json", grid=None):
+    """HBM bytes per launch of an aggregation kernel (of its launches with
+    `grid` threads, if given) from a committed FETCH_SIZE / WRITE_SIZE counter
+    record (scaled by a copy of known size), or None when the kernel sources
+    changed since the counters were taken."""
     path = os.path.join(ROOT, "profiles", record)
     if not os.path.exists(path):
         return None
@@ -425,6 +426,10 @@ def measured_traffic(kernel_prefix, record="traffic_agg_1242x375_d128.json"):
         return None
     for name, k in rec["kernels"].items():
         if kernel_prefix in name:
+            if grid is not None:
+                k = k.get("grids", {}).get(str(grid))
+                if k is None:
+                    return None
             return int(k["fetch_bytes"] + k["write_bytes"])
     return None
 
@@ -496,26 +501,40 @@ def agg_kernel_name(sched):
         256 // sched["h_lanes"], sched["h_lanes"], 2 if sched["h_costs"] == "codes" else 0)
 
 
+def agg_launch_grid(p, frames, sched, dirs):
+    """Threads of the aggregation launch of `frames` frames of params p over
+    directions `dirs` (0 L->R, 1 R->L, 2 T->B, 3 B->T, 4 TL->BR, 5 BR->TL,
+    6 TR->BL, 7 BL->TR), as the library forms it: one wave per 64 // lanes
+    scanlines of a direction (h_lanes lanes on the horizontal ones, 16 on the
+    others), four waves per 256-thread block."""
+    waves = 0
+    for d in dirs:
+        lines = p.height if d < 2 else p.width if d < 4 else p.width + p.height - 1
+        spw = 64 // (sched["h_lanes"] if d < 2 else 16)
+        waves += -(-lines // spw)
+    return -(-frames * waves // 4) * 256
+
+
 def dominant_kernel(p, frames, sched):
     """(kernel name, library stage, algorithmic bytes per launch, unit
-    evaluations per launch, description) of the dominant kernel of the
-    schedule: the 8-direction aggregation launch, or -- on the two-pass
-    schedule -- the bottom-up stripe pass, which reads each cell's uint16 S_D
-    (which holds four paths' sum) and the two uint8 path costs of TR->BL and
-    BL->TR, and its cost (5 B per cell) or, where the frame has Census code
-    records (horizontal costs from codes), one 16-byte code record per pixel
-    instead of the costs, for its two paths and the selection."""
+    evaluations per launch, description, launch grid) of the dominant kernel
+    of the schedule: the 8-direction aggregation launch, or -- on the
+    two-pass schedule -- the per-direction launch of its other four paths
+    (L->R, R->L, TR->BL, BL->TR), its longest kernel: the two diagonals read
+    their costs and write their path costs (2 B per cell), the horizontal
+    ones write theirs and read one 16-byte code record per pixel (sliding
+    Census windows) or the costs.  (The stripe passes: the bottom-up one
+    reads S_D and two slots, 4 B per cell, and the code records.)"""
     if sched.get("two_pass", "off") == "off":
         return (agg_kernel_name(sched), "aggregate", agg_alg_bytes(p, frames, sched), frames * p.disp_evals(),
-                "8 directions of %d frames in one launch" % frames)
-    waves = 16 if sched["two_pass"] == "wide" else 8
-    codes = sched["h_costs"] == "codes"
+                "8 directions of %d frames in one launch" % frames, agg_launch_grid(p, frames, sched, range(8)))
     cells = p.width * p.height * p.max_disp
-    per_frame = 4 * cells + (CODE_RECORD_BYTES * p.width * p.height if codes else cells)
-    return ("stripe_kernel<16, true, %d, false, %s>" % (waves, "true" if codes else "false"), "disparity",
-            frames * per_frame, frames * 2 * cells,
-            "bottom-up stripe pass of %d frames: B->T, BR->TL, the 8-path sum and the selection%s"
-            % (frames, ", costs from Census code records" if codes else ""))
+    codes = sched["h_costs"] == "codes"
+    horizontal = (cells + CODE_RECORD_BYTES * p.width * p.height) if codes else AGG_BYTES_PER_EVAL * cells
+    per_frame = 2 * AGG_BYTES_PER_EVAL * cells + 2 * horizontal
+    return (agg_kernel_name(sched), "aggregate", frames * per_frame, frames * 4 * cells,
+            "four directions (L->R, R->L, TR->BL, BL->TR) of %d frames in one launch (two-pass schedule; the "
+            "other four run in the stripe passes)" % frames, agg_launch_grid(p, frames, sched, (0, 1, 6, 7)))
 
 
 def agg_alg_bytes(p, frames, sched):
@@ -530,10 +549,11 @@ def agg_alg_bytes(p, frames, sched):
     return frames * per_frame
 
 
-def measured_valu(kernel_prefix, record):
-    """VALU issue utilisation of a kernel from a committed counter summary
-    (profiles/counters_*.txt), or None when the record is missing or was
-    taken on other aggregation sources."""
+def measured_valu(kernel_prefix, record, grid=None):
+    """VALU issue utilisation of a kernel (its launches with `grid` threads,
+    if given) from a committed counter summary (profiles/counters_*.txt), or
+    None when the record is missing or was taken on other aggregation
+    sources."""
     path = os.path.join(ROOT, "profiles", record)
     if not os.path.exists(path):
         return None
@@ -542,7 +562,7 @@ def measured_valu(kernel_prefix, record):
     if "source hash %s" % source_hash() not in text:
         return None
     for line in text.splitlines():
-        if kernel_prefix in line and "VALU util" in line:
+        if kernel_prefix in line and "VALU util" in line and (grid is None or "[grid %d]" % grid in line):
             return float(line.split("VALU util")[1].split()[0])
     return None
 
@@ -658,22 +678,23 @@ def main():
     def per_step(pr):
         # summed event time of each stage per batch (a stage may hold several
         # launches: on the two-pass schedule the aggregation stage is the
-        # sync-word clear, the four-direction launch and the down pass)
+        # four-direction launch, and the disparity stage holds both stripe
+        # passes)
         return {k: round(v[0] / args.steps, 5) for k, v in pr.items()}
 
     value = evals * args.steps / dt / 1e6
     # roofline: the aggregation launch time from the events of the one-stream
     # timed loop, where it runs alone on the GPU (with batches overlapping on
     # several streams an event pair also spans the other batches' kernels)
-    kname, kstage, alg, kevals, kdesc = dominant_kernel(p, 8, sched)
+    kname, kstage, alg, kevals, kdesc, kgrid = dominant_kernel(p, 8, sched)
     agg_ms, agg_n = prof1[kstage]
     # the dominant kernel is its stage's only launch of a batch
     assert agg_n == args.steps, (kstage, agg_n)
     agg_avg = agg_ms / max(agg_n, 1)
     agg_overlapped = prof[kstage][0] / max(prof[kstage][1], 1)
     achieved = alg / (agg_avg * 1e-3) / 1e9
-    traffic = measured_traffic(kname, "traffic_agg_1920x1080_d256_batch8.json")
-    valu = measured_valu(kname, "counters_1920x1080_d256_batch8.txt")
+    traffic = measured_traffic(kname, "traffic_agg_1920x1080_d256_batch8.json", kgrid)
+    valu = measured_valu(kname, "counters_1920x1080_d256_batch8.txt", kgrid)
 
     extras = {}
     sgm.sgm_profile(ctx, False)
@@ -736,7 +757,7 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic,
-                     "kernel": kname + " (" + kdesc + ")",
+                     "kernel": kname + " (" + kdesc + ")", "launch_grid": kgrid,
                      "alg_bytes_per_eval": round(alg / kevals, 4),
                      "alg_bytes_per_launch": alg, "evals_per_launch": kevals,
                      "avg_launch_ms": round(agg_avg, 5), "launches": agg_n,

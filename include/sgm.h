@@ -434,7 +434,11 @@ int sgm_autotune(sgm_ctx *ctx, const sgm_frame *samples, int n, int reps, sgm_sc
  * batch is bracketed by HIP events on the batch's stream; when the batch is
  * found done (sgm_poll / sgm_wait) the elapsed times are added per stage.
  * A stage is one kernel launch per group of frames with the same kernel
- * variant (a batch of uniform frames: one launch per stage). */
+ * variant (a batch of uniform frames: one launch per stage), except that on
+ * the two-pass schedule (sgm_schedule.two_pass) the aggregation stage is the
+ * per-direction launch of the four paths run that way, and the disparity
+ * stage holds both stripe passes (top-down, then bottom-up with the
+ * selection). */
 enum {
   SGM_STAGE_CENSUS = 0,
   SGM_STAGE_AGGREGATE = 1,

@@ -634,10 +634,8 @@ int enqueue_frames(const sgm_frame *fr, int n, const std::vector<FramePlan> &pla
   if (census_done) HIP_TRY(hipEventRecord(census_done, s));
   // two-pass frames: waves per stripe (0: per-direction kernels only)
   auto tp_waves = [&](int i) { return (hlps[i] >> 9) & 1 ? ((hlps[i] >> 10) & 1 ? 16 : 8) : 0; };
-  // aggregation, one launch per (disparities per lane, path-cost width)
-  CHECK(mark.begin(SGM_STAGE_AGGREGATE));
-  int groups = 0;
-  {  // the stripes' ticket counters and error flags start at zero
+  {  // the stripes' ticket counters and error flags start at zero (outside
+     // the stages: a few words)
     std::vector<SyncZeroJob> zj;
     for (int i = 0; i < n; ++i)
       if (plans[i].off_sync != kNoSync)  // every frame's words of the batch header
@@ -645,9 +643,12 @@ int enqueue_frames(const sgm_frame *fr, int n, const std::vector<FramePlan> &pla
     if (!zj.empty()) {
       launch_zero_sync(zj, s);
       CHECK(check_launch());
-      ++groups;
     }
   }
+  // aggregation, one launch per (disparities per lane, path-cost width); the
+  // two-pass frames' stripe passes belong to the disparity stage
+  CHECK(mark.begin(SGM_STAGE_AGGREGATE));
+  int groups = 0;
   for (int sad = 0; sad <= 1; ++sad)
   for (int K : {4, 8, 12, 16})
     for (int lb = 1; lb <= 2; ++lb)
@@ -761,6 +762,11 @@ int enqueue_frames(const sgm_frame *fr, int n, const std::vector<FramePlan> &pla
     return sj;
   };
   const uint32_t epoch_down = next_epoch(), epoch_up = next_epoch();
+  CHECK(mark.end(groups));
+  CHECK(mark.begin(SGM_STAGE_DISPARITY));
+  groups = 0;
+  // two-pass frames: the top-down stripe pass (then, below, the bottom-up
+  // pass with the selection)
   for (int K : {4, 8, 12, 16})
     for (int waves : {8, 16})
       for (bool codes : {false, true}) {
@@ -770,9 +776,6 @@ int enqueue_frames(const sgm_frame *fr, int n, const std::vector<FramePlan> &pla
         CHECK(check_launch());
         ++groups;
       }
-  CHECK(mark.end(groups));
-  CHECK(mark.begin(SGM_STAGE_DISPARITY));
-  groups = 0;
   // split image rows across blocks only when the batch's rows are too few to
   // fill the chip on their own
   int disp_rows = 0;

@@ -1,11 +1,11 @@
 """Summaries of rocprofv3 CSV output for the profiles/ directory.
 
     python -m paper_1807_06271_amd.profiling stats  <kernel_stats.csv> <out.txt> "<command>" \
-        [<kernel_trace.csv> (<kernel name part> <N dispatches> <skip, -1: the last N> <largest|all>)...]
+        [<kernel_trace.csv> (<kernel name part> <N dispatches> <skip, -1: the last N> <largest|all|grid=G>)...]
     python -m paper_1807_06271_amd.profiling traffic <fetch_counter_collection.csv> \
         <write_counter_collection.csv> <out.json> "<fetch command>" "<write command>" [median|largest|max]
     python -m paper_1807_06271_amd.profiling counters <counter_collection.csv> <kernel_trace.csv> \
-        <out.txt> "<command>" [largest]
+        <out.txt> "<command>" [largest [<kernel name part>@<grid>]...]
 
 `stats` keeps the per-kernel call count and average / min / max durations.
 `counters` keeps the median per dispatch of each SQ counter of each kernel and
@@ -14,7 +14,8 @@ what the chip can issue in the kernel's median duration (from the kernel
 trace of the same run): one wave64 VALU instruction per clock per CU (four
 SIMDs, each 16 lanes wide), 256 CUs at 2.4 GHz.
 `traffic` turns FETCH_SIZE and WRITE_SIZE (KiB per dispatch) into bytes per
-launch of each kernel, scaled by what the same counter reads for the plain
+launch of each kernel (and of each of its grid sizes, for a kernel whose
+launches of different shapes do different work), scaled by what the same counter reads for the plain
 copy kernel of known size that the profiled run also executes (bench.py
 --calibrate-copy copies CALIBRATION_BYTES between two device buffers); the
 JSON also records a hash of the kernel sources, so a reader can tell whether
@@ -78,11 +79,12 @@ def short_name(name: str) -> str:
 def stats(csv_path: str, out_path: str, command: str, trace_csv: str | None = None,
           selections=()) -> None:
     """Kernel statistics; with trace_csv, also for each selection (kernel,
-    first, skip, largest) the average of dispatches skip .. skip+first-1 (in
+    first, skip, grid) the average of dispatches skip .. skip+first-1 (in
     start order; skip < 0: the last `first`) of `kernel` (a loop of the
-    benchmark in which the kernel runs alone); with `largest`, counted among
-    the dispatches with the kernel's largest grid only (e.g. its 8-frame
-    launches, not single frames)."""
+    benchmark in which the kernel runs alone); grid True: counted among the
+    dispatches with the kernel's largest grid only (e.g. its 8-frame
+    launches, not single frames), an int: among those with that grid, False:
+    all."""
     rows = list(csv.DictReader(open(csv_path)))
     lines = ["# rocprofv3 kernel statistics", "# command: " + command, "#",
              "%-100s %6s %12s %12s %12s %7s" % ("kernel", "calls", "avg_us", "min_us", "max_us", "pct")]
@@ -96,16 +98,25 @@ def stats(csv_path: str, out_path: str, command: str, trace_csv: str | None = No
         for kernel, first, skip, largest in selections:
             tr = [r for r in trace if kernel in r["Kernel_Name"]]
             tr.sort(key=lambda r: int(r["Start_Timestamp"]))
-            grid = max(int(r["Grid_Size_X"]) for r in tr)
-            if largest:
+            grid = max(int(r["Grid_Size_X"]) for r in tr) if largest is True else largest
+            if largest is not False:
                 tr = [r for r in tr if int(r["Grid_Size_X"]) == grid]
             if skip < 0:  # the last `first` dispatches
                 skip = len(tr) - first
             d = [(int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3 for r in tr][skip:skip + first]
             lines.append("# dispatches %d..%d (in start order)%s of %s: avg %.1f us, min %.1f, max %.1f"
-                         % (skip, skip + len(d) - 1, " (grid %d only)" % grid if largest else "", kernel,
+                         % (skip, skip + len(d) - 1, " (grid %d only)" % grid if largest is not False else "", kernel,
                             sum(d) / len(d), min(d), max(d)))
     open(out_path, "w").write("\n".join(lines) + "\n")
+
+
+def _per_grid(csv_path: str, counter: str):
+    """{kernel name: {grid: [per-dispatch counter values]}}."""
+    acc = defaultdict(lambda: defaultdict(list))
+    for r in csv.DictReader(open(csv_path)):
+        if r.get("Counter_Name") == counter:
+            acc[r["Kernel_Name"]][int(r["Grid_Size"])].append(float(r["Counter_Value"]))
+    return acc
 
 
 def _per_kernel(csv_path: str, counter: str, largest: bool = False):
@@ -142,6 +153,7 @@ def traffic(fetch_csv: str, write_csv: str, out_path: str, fetch_cmd: str, write
     cwrite = max(w.get(cname, [0.0]))
     fetch_factor = CALIBRATION_BYTES / (cfetch * 1024.0)
     write_factor = CALIBRATION_BYTES / (cwrite * 1024.0) if cwrite else None
+    fg, wg = _per_grid(fetch_csv, "FETCH_SIZE"), _per_grid(write_csv, "WRITE_SIZE")
     kernels = {}
     for k in f:
         if k == cname:
@@ -149,11 +161,20 @@ def traffic(fetch_csv: str, write_csv: str, out_path: str, fetch_cmd: str, write
         fs, ws = sorted(f[k]), sorted(w.get(k, [0.0]))
         fv = fs[-1] if pick == "max" else fs[len(fs) // 2]
         wv = ws[-1] if pick == "max" else ws[len(ws) // 2]
+        grids = {}
+        for g, vals in sorted(fg.get(k, {}).items()):
+            fgv = sorted(vals)[len(vals) // 2]
+            wgs = sorted(wg.get(k, {}).get(g, [0.0]))
+            wgv = wgs[len(wgs) // 2]
+            grids[str(g)] = {"dispatches": len(vals), "fetch_kib": fgv, "write_kib": wgv,
+                             "fetch_bytes": fgv * 1024.0 * fetch_factor,
+                             "write_bytes": wgv * 1024.0 * (write_factor or 1.0)}
         kernels[short_name(k)] = {
             "dispatches": len(f[k]),
             "fetch_kib": fv, "write_kib": wv, "pick": pick,
             "fetch_bytes": fv * 1024.0 * fetch_factor,
             "write_bytes": wv * 1024.0 * (write_factor or 1.0),
+            "grids": grids,
         }
     out = {"calibration": {"kernel": short_name(cname), "bytes": CALIBRATION_BYTES,
                            "fetch_kib": cfetch, "write_kib": cwrite,
@@ -169,10 +190,13 @@ def traffic(fetch_csv: str, write_csv: str, out_path: str, fetch_cmd: str, write
 CUS, CLOCK_HZ = 256, 2.4e9
 
 
-def counters(csv_path: str, trace_csv: str, out_path: str, command: str, largest: bool = False) -> None:
+def counters(csv_path: str, trace_csv: str, out_path: str, command: str, largest: bool = False,
+             extra=()) -> None:
     """Median per dispatch of each counter of each kernel; with `largest`,
     only the dispatches with the kernel's largest grid (e.g. the 8-frame
-    launches of a kernel that also ran single frames)."""
+    launches of a kernel that also ran single frames), each entry labelled
+    with that grid; `extra`: (kernel name part, grid) pairs summarised as
+    entries of their own (a kernel's launches of another shape)."""
     def grid_ok(name, grid, biggest):
         return not largest or grid == biggest[name]
 
@@ -200,14 +224,28 @@ def counters(csv_path: str, trace_csv: str, out_path: str, command: str, largest
              % (CUS, CLOCK_HZ / 1e9),
              "# dispatches: " + ("only each kernel's largest grid" if largest else "all"),
              "# aggregation source hash %s" % source_hash(), "#"]
-    for k in sorted(acc, key=lambda k: -max(acc[k].get("SQ_INSTS_VALU", [0]))):
-        med = {c: sorted(v)[len(v) // 2] for c, v in acc[k].items()}
+    entries = {(k + (" [grid %d]" % big[k] if largest else "")): (acc[k], dur.get(k)) for k in acc}
+    for part, g in extra:
+        for k in {short_name(r["Kernel_Name"]) for r in rows}:
+            if part not in k:
+                continue
+            ca = defaultdict(list)
+            for r in rows:
+                if short_name(r["Kernel_Name"]) == k and int(r["Grid_Size"]) == g:
+                    ca[r["Counter_Name"]].append(float(r["Counter_Value"]))
+            du = [(int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3 for r in tr
+                  if short_name(r["Kernel_Name"]) == k and int(r["Grid_Size_X"]) == g]
+            if ca:
+                entries["%s [grid %d]" % (k, g)] = (ca, du)
+    for name in sorted(entries, key=lambda n: -max(entries[n][0].get("SQ_INSTS_VALU", [0]))):
+        ca, du = entries[name]
+        med = {c: sorted(v)[len(v) // 2] for c, v in ca.items()}
         util = ""
-        if dur.get(k) and "SQ_INSTS_VALU" in med:
-            us = sorted(dur[k])[len(dur[k]) // 2]
+        if du and "SQ_INSTS_VALU" in med:
+            us = sorted(du)[len(du) // 2]
             util = "  VALU util %.2f (median %.1f us, %d dispatches)" % (
-                med["SQ_INSTS_VALU"] / (CUS * CLOCK_HZ * us * 1e-6), us, len(dur[k]))
-        lines.append(k + util)
+                med["SQ_INSTS_VALU"] / (CUS * CLOCK_HZ * us * 1e-6), us, len(du))
+        lines.append(name + util)
         lines.append("    " + ", ".join("%s %d" % (c, v) for c, v in sorted(med.items())))
     open(out_path, "w").write("\n".join(lines) + "\n")
 
@@ -216,11 +254,14 @@ if __name__ == "__main__":
     if sys.argv[1] == "stats":
         # ... <trace.csv> then groups of: <kernel name part> <N dispatches> <skip (-1: the last N)> <largest|all>
         sel = sys.argv[6:]
-        groups = [(sel[i], int(sel[i + 1]), int(sel[i + 2]), sel[i + 3] == "largest") for i in range(0, len(sel) - 3, 4)]
+        def mode(m):
+            return True if m == "largest" else int(m[5:]) if m.startswith("grid=") else False
+        groups = [(sel[i], int(sel[i + 1]), int(sel[i + 2]), mode(sel[i + 3])) for i in range(0, len(sel) - 3, 4)]
         stats(sys.argv[2], sys.argv[3], sys.argv[4], sys.argv[5] if len(sys.argv) > 5 else None, groups)
     elif sys.argv[1] == "traffic":
         traffic(sys.argv[2], sys.argv[3], sys.argv[4], sys.argv[5], sys.argv[6], *sys.argv[7:8])
     elif sys.argv[1] == "counters":
-        counters(sys.argv[2], sys.argv[3], sys.argv[4], sys.argv[5], len(sys.argv) > 6 and sys.argv[6] == "largest")
+        counters(sys.argv[2], sys.argv[3], sys.argv[4], sys.argv[5], len(sys.argv) > 6 and sys.argv[6] == "largest",
+                 [(a.rsplit("@", 1)[0], int(a.rsplit("@", 1)[1])) for a in sys.argv[7:]])
     else:
         raise SystemExit(__doc__)

@@ -34,22 +34,23 @@ def test_aggregation_bytes_follow_the_schedule():
 
 
 def test_roofline_kernel_follows_the_two_pass_schedule():
-    # the bottom-up stripe pass reads S_D (2 B) and two uint8 path-cost
-    # slots (2 B) per cell, and the cost (1 B per cell) or, with Census code
-    # records, one 16-byte record per pixel, while evaluating two paths
+    # on the two-pass schedule the longest kernel is the per-direction launch
+    # of L->R, R->L, TR->BL and BL->TR: the diagonals read their costs and
+    # write their path costs (2 B per cell), the horizontal ones write theirs
+    # and read one 16-byte code record per pixel (or the costs); its grid is
+    # the library's: one wave per scanline of 64 lanes horizontally, per four
+    # 16-lane diagonal scanlines, four waves per 256-thread block
     sys.path.insert(0, ROOT)
     import bench
     from paper_1807_06271_amd.sgm import Params
     p = Params(width=1920, height=1080, max_disp=256)
     cells = 1920 * 1080 * 256
-    name, stage, alg, evals, _ = bench.dominant_kernel(p, 8, {"h_lanes": 64, "h_costs": "codes",
-                                                              "two_pass": "narrow"})
-    assert (name, stage, alg, evals) == ("stripe_kernel<16, true, 8, false, true>", "disparity",
-                                         8 * (4 * cells + 16 * 1920 * 1080), 8 * 2 * cells)
-    name, stage, alg, evals, _ = bench.dominant_kernel(p, 8, {"h_lanes": 64, "h_costs": "volume",
-                                                              "two_pass": "wide"})
-    assert (name, stage, alg, evals) == ("stripe_kernel<16, true, 16, false, false>", "disparity", 8 * 5 * cells,
-                                         8 * 2 * cells)
-    name, stage, alg, evals, _ = bench.dominant_kernel(p, 8, {"h_lanes": 64, "h_costs": "volume",
-                                                              "two_pass": "off"})
+    name, stage, alg, evals, _, grid = bench.dominant_kernel(p, 8, {"h_lanes": 64, "h_costs": "codes",
+                                                                    "two_pass": "wide"})
+    assert name == "agg_kernel<16, 4, 64, 0, unsigned char, 8, false, 2>" and stage == "aggregate"
+    assert alg == 8 * (2 * 2 * cells + 2 * (cells + 16 * 1920 * 1080)) and evals == 8 * 4 * cells
+    assert grid == 1873920  # 8 x (2 x 1080 + 2 x 750) waves in blocks of 4
+    name, stage, alg, evals, _, grid = bench.dominant_kernel(p, 8, {"h_lanes": 64, "h_costs": "volume",
+                                                                    "two_pass": "off"})
     assert stage == "aggregate" and alg == 2 * evals == 2 * 8 * p.disp_evals()
+    assert grid == 3133440  # 8 x (2 x 1080 + 2 x 480 + 4 x 750) waves in blocks of 4
