@@ -155,6 +155,19 @@ __device__ __forceinline__ uint32_t group_allmin_u32(uint32_t v) {
   return v;
 }
 
+// f(std::integral_constant<int, S>{}) for S = B .. E - 1: a loop whose index
+// is a compile-time constant in every iteration.
+template <int B, int E>
+struct Unrolled {
+  template <class F>
+  __device__ __forceinline__ static void run(F &&f) {
+    if constexpr (B < E) {
+      f(std::integral_constant<int, B>{});
+      Unrolled<B + 1, E>::run(f);
+    }
+  }
+};
+
 // One wave's share of one direction: 64/LPS scanlines side by side, LPS lanes
 // per scanline, K disparities per lane (K * LPS = Dp).
 // HS = +1 / -1: the wave runs a horizontal direction (L->R / R->L), whose
@@ -251,8 +264,12 @@ __device__ __forceinline__ void agg_wave(const AggJob &J, int slot, int wave_in_
 
   // GUARD = false: every scanline of the wave has pixels i and i + PF, so
   // the load needs no clamp and the store no per-lane test
-  auto pixel = [&](auto guard, int i, CostWords<K, SRC> &rs) {
+  // rot: the window ring's rotation before this pixel (kSlide); edgy: the
+  // pixel may reach right-view columns left of the image (kSlide)
+  auto pixel = [&](auto guard, auto rot, auto edgy, int i, CostWords<K, SRC> &rs) {
     constexpr bool GUARD = decltype(guard)::value;
+    constexpr int R = decltype(rot)::value;
+    constexpr bool EDGE = decltype(edgy)::value;
     // keep each pixel's instructions together: hoisting the unpacking of
     // later pixels' costs would wait on loads issued one pixel ago
     __builtin_amdgcn_sched_barrier(0);
@@ -260,41 +277,30 @@ __device__ __forceinline__ void agg_wave(const AggJob &J, int slot, int wave_in_
     if constexpr (SRC == kSlide) {
       // slide the window one code along the row: every code moves one
       // disparity up (L->R) or down (R->L), across lanes by DPP, and the
-      // code entering at the window's end comes in as the DPP's old value
-      if constexpr (HS > 0) {
-        const uint32_t in_lo = (uint32_t)__builtin_amdgcn_update_dpp((int)rs.w[2], (int)sc[2 * K - 2],
-                                                                     kDppWaveShr1, 0xF, 0xF, false);
-        const uint32_t in_hi = (uint32_t)__builtin_amdgcn_update_dpp((int)rs.w[3], (int)sc[2 * K - 1],
-                                                                     kDppWaveShr1, 0xF, 0xF, false);
-#pragma unroll
-        for (int k = K - 1; k > 0; --k) {
-          sc[2 * k] = sc[2 * k - 2];
-          sc[2 * k + 1] = sc[2 * k - 1];
-        }
-        sc[0] = in_lo;
-        sc[1] = in_hi;
-      } else {
-        const uint32_t in_lo = (uint32_t)__builtin_amdgcn_update_dpp((int)rs.w[2], (int)sc[0], kDppWaveShl1,
-                                                                     0xF, 0xF, false);
-        const uint32_t in_hi = (uint32_t)__builtin_amdgcn_update_dpp((int)rs.w[3], (int)sc[1], kDppWaveShl1,
-                                                                     0xF, 0xF, false);
-#pragma unroll
-        for (int k = 0; k < K - 1; ++k) {
-          sc[2 * k] = sc[2 * k + 2];
-          sc[2 * k + 1] = sc[2 * k + 3];
-        }
-        sc[2 * K - 2] = in_lo;
-        sc[2 * K - 1] = in_hi;
-      }
+      // code entering at the window's end comes in as the DPP's old value.
+      // The window is a ring of K code pairs: the code of position k (right
+      // view x - dbase - k) sits in slot (k - R) mod K (L->R) or (k + R) mod
+      // K (R->L), R the pixels slid since the block of PF pixels began (a
+      // multiple of K: each block begins at R = 0), so a slide overwrites
+      // the leaving code's slot instead of moving the others.
+      constexpr int OUT = HS > 0 ? (K - 1 - R % K) % K : R % K;  // the leaving code's slot
+      sc[2 * OUT] = (uint32_t)__builtin_amdgcn_update_dpp((int)rs.w[2], (int)sc[2 * OUT],
+                                                          HS > 0 ? kDppWaveShr1 : kDppWaveShl1, 0xF, 0xF, false);
+      sc[2 * OUT + 1] = (uint32_t)__builtin_amdgcn_update_dpp((int)rs.w[3], (int)sc[2 * OUT + 1],
+                                                              HS > 0 ? kDppWaveShr1 : kDppWaveShl1, 0xF, 0xF, false);
       // Hamming costs; right-view pixels left of the image cost N_b (only
-      // while x < Dp - 1, the same x for the whole wave)
-      const int x = sx + (GUARD ? min(i, last) : i) * HS;
-      const bool edge = x < Dp - 1;
+      // while x < Dp - 1, the same x for the whole wave: blocks without such
+      // pixels skip the test)
       uint32_t c[K];
 #pragma unroll
       for (int k = 0; k < K; ++k) {
-        c[k] = (uint32_t)__builtin_popcount(sc[2 * k] ^ rs.w[0]) + (uint32_t)__builtin_popcount(sc[2 * k + 1] ^ rs.w[1]);
-        if (edge) c[k] = x - dbase - k >= 0 ? c[k] : nbits;
+        const int sl = HS > 0 ? (k + K - (R + 1) % K) % K : (k + R + 1) % K;  // after the slide
+        c[k] = (uint32_t)__builtin_popcount(sc[2 * sl] ^ rs.w[0]) +
+               (uint32_t)__builtin_popcount(sc[2 * sl + 1] ^ rs.w[1]);
+        if constexpr (EDGE) {
+          const int x = sx + (GUARD ? min(i, last) : i) * HS;
+          if (x < Dp - 1) c[k] = x - dbase - k >= 0 ? c[k] : nbits;
+        }
       }
 #pragma unroll
       for (int q = 0; q < NP; ++q) Cs[q] = as_pair(c[2 * q] | c[2 * q + 1] << 16);
@@ -422,18 +428,34 @@ __device__ __forceinline__ void agg_wave(const AggJob &J, int slot, int wave_in_
 
   using Guarded = std::integral_constant<bool, true>;
   using Unguarded = std::integral_constant<bool, false>;
+  using Edge = std::integral_constant<bool, true>;
+  using NoEdge = std::integral_constant<bool, false>;
+  static_assert(SRC != kSlide || PF % K == 0, "a block of PF pixels must turn the window ring back to its start");
+  // PF pixels from b0 (tail: only those below maxlen), ring slot and window
+  // rotation compile-time constants
+  auto block = [&](auto guard, auto edgy, int b0, bool tail) {
+    Unrolled<0, PF>::run([&](auto si) {
+      constexpr int s = decltype(si)::value;
+      if (!tail || b0 + s < maxlen) pixel(guard, std::integral_constant<int, s % K>{}, edgy, b0 + s, ring[s]);
+    });
+  };
   int i0 = 0;
-  for (; i0 + 2 * PF <= minlen; i0 += PF) {  // whole blocks, all scanlines long enough
-#pragma unroll
-    for (int s = 0; s < PF; ++s) pixel(Unguarded{}, i0 + s, ring[s]);
+  // whole blocks, all scanlines long enough.  On sliding windows (one
+  // scanline per wave) the blocks whose columns all lie at x >= Dp - 1 need
+  // no left-edge test: L->R they follow the first ones, R->L they precede
+  // the last ones (two loops rather than a branch per block, which would
+  // hold both variants' registers)
+  if constexpr (SRC == kSlide && HS > 0) {
+    for (; i0 + 2 * PF <= minlen && sx + i0 < Dp - 1; i0 += PF) block(Unguarded{}, Edge{}, i0, false);
+    for (; i0 + 2 * PF <= minlen; i0 += PF) block(Unguarded{}, NoEdge{}, i0, false);
+  } else if constexpr (SRC == kSlide) {
+    for (; i0 + 2 * PF <= minlen && sx - (i0 + PF - 1) >= Dp - 1; i0 += PF) block(Unguarded{}, NoEdge{}, i0, false);
+    for (; i0 + 2 * PF <= minlen; i0 += PF) block(Unguarded{}, Edge{}, i0, false);
+  } else {
+    for (; i0 + 2 * PF <= minlen; i0 += PF) block(Unguarded{}, NoEdge{}, i0, false);
   }
-  for (; i0 + PF <= maxlen; i0 += PF) {  // whole blocks of PF pixels
-#pragma unroll
-    for (int s = 0; s < PF; ++s) pixel(Guarded{}, i0 + s, ring[s]);
-  }
-#pragma unroll
-  for (int s = 0; s < PF; ++s)  // remaining < PF pixels
-    if (i0 + s < maxlen) pixel(Guarded{}, i0 + s, ring[s]);
+  for (; i0 + PF <= maxlen; i0 += PF) block(Guarded{}, Edge{}, i0, false);  // whole blocks of PF pixels
+  block(Guarded{}, Edge{}, i0, true);  // remaining < PF pixels
 }
 
 // Scanlines per wave of direction `dir` under a schedule whose horizontal
