@@ -70,12 +70,17 @@ __global__ __launch_bounds__(256) void cost_kernel(JobTable<CostJob> t) {
 
 constexpr int kSeg = 256;
 // Right-view codes a segment reaches: kSeg + D - 1, plus up to 3 more because
-// the first one is aligned down to a multiple of 4; LDS slots for them,
-// swizzled: swz(kRightMax - 1) + 1
+// the first one is aligned down to a multiple of 4.  They are stored behind
+// kFront unused slots, so that the cost loop may read the codes of pixels
+// left of the image (index down to -255, for x = 0 and d0 = 252) from inside
+// the array and mask their costs afterwards; LDS slots, swizzled:
+// rslot(kRightMax - 1) + 1
 constexpr int kRightMax = kSeg + 255 + 3;
-constexpr int kCodeRSlots = (kRightMax - 1) + (kRightMax - 1) / 4 + 1;
+constexpr int kFront = 256;  // a multiple of 4: keeps an index's residue mod 4
 
-__device__ __forceinline__ int swz(int i) { return i + (i >> 2); }
+__host__ __device__ constexpr int swz(int i) { return i + (i >> 2); }
+__host__ __device__ constexpr int rslot(int i) { return swz(i + kFront); }
+constexpr int kCodeRSlots = swz(kRightMax - 1 + kFront) + 1;
 
 __global__ __launch_bounds__(256) void census_cost_kernel(JobTable<FusedCostJob> t) {
   extern __shared__ uint64_t lds64[];
@@ -97,10 +102,11 @@ __global__ __launch_bounds__(256) void census_cost_kernel(JobTable<FusedCostJob>
   const int nr = x0 + nx - xr0;         // right-view codes needed
   const int rx = J.cw / 2, ry = J.ch / 2;
   const int sl = nx + 2 * rx, sr = nr + 2 * rx;  // staged row lengths
-  // right-view codes are stored at swz(i) = i + i/4: the cost loop's lanes
-  // read codes 4 apart, and the padding spreads them over all LDS banks
+  // right-view code i is stored at rslot(i) = swz(i + kFront), swz(i) = i +
+  // i/4: the cost loop's lanes read codes 4 apart, and the padding spreads
+  // them over all LDS banks
   uint64_t *codeL = lds64;            // [nx]   codes of x0 ..
-  uint64_t *codeR = lds64 + kSeg;     // [swz(nr)] codes of xr0 ..
+  uint64_t *codeR = lds64 + kSeg;     // [rslot(nr)] codes of xr0 ..
   uint8_t *rowsL = reinterpret_cast<uint8_t *>(lds64 + kSeg + kCodeRSlots);  // [ch][sl]
   uint8_t *rowsR = rowsL + J.ch * (kSeg + 2 * rx);                       // [ch][sr]
   {
@@ -124,13 +130,13 @@ __global__ __launch_bounds__(256) void census_cost_kernel(JobTable<FusedCostJob>
   }
   __syncthreads();
   for (int i = threadIdx.x; i < nr; i += blockDim.x) {
-    codeR[swz(i)] = census_at(rowsR, sr, i, J.cw, J.ch);
+    codeR[rslot(i)] = census_at(rowsR, sr, i, J.cw, J.ch);
     if (i < nx) codeL[i] = census_at(rowsL, sl, i, J.cw, J.ch);
   }
   __syncthreads();
   if (J.codes) {  // the segment's code records {left, right}, for sliding horizontal windows
     for (int i = threadIdx.x; i < nx; i += blockDim.x) {
-      const uint64_t rec[2] = {codeL[i], codeR[swz(x0 + i - xr0)]};
+      const uint64_t rec[2] = {codeL[i], codeR[rslot(x0 + i - xr0)]};
       *reinterpret_cast<U32N<4> *>(J.codes + 2 * ((int64_t)y * W + x0 + i)) = *reinterpret_cast<const U32N<4> *>(rec);
     }
   }
@@ -143,38 +149,70 @@ __global__ __launch_bounds__(256) void census_cost_kernel(JobTable<FusedCostJob>
   if (g >= groups) return;
   const int d0 = q * 4;
   uint32_t *out = reinterpret_cast<uint32_t *>(J.out8 + ((int64_t)y * W + x0) * Dp) + q;
-  // groups with x >= d0 + 3 and all four disparities below D need no checks
-  const bool full = d0 + 3 < D;
+  // padded disparities d0 + b >= D cost N_b: byte b of every word is kept
+  // (keep) or replaced (fill)
+  const uint32_t nb = (uint32_t)J.nbits;
+  uint32_t keep = 0, fill = 0;
+#pragma unroll
+  for (int b = 0; b < 4; ++b) {
+    if (d0 + b < D) keep |= 0xFFu << (8 * b);
+    else fill |= nb << (8 * b);
+  }
   for (int xi = 4 * g; xi < nx; xi += 4 * groups) {
     const int x = x0 + xi;
-    if (full && x >= d0 + 3 && xi + 3 < nx) {
-      // codes x - d0 - 3 .. x - d0 + 3 at indices a .. a + 6, a = i0 - 3 = 1
-      // (mod 4): swz(a + k) = swz(a) + k + (1 + k) / 4, one base address
+    if (xi + 3 < nx) {
+      // codes x - d0 - 3 .. x - d0 + 3 at indices a .. a + 6, a = 1 (mod 4):
+      // rslot(a + k) = rslot(a) + k + (1 + k) / 4, one base address.  Code k
+      // serves the cells p - b = k - 3; it lies left of the image when
+      // x - d0 + k - 3 < 0, possible only while x < d0 + 3 (left of Dp - 1):
+      // the whole wave then takes the masked variant, one branch per wave
       const int a = x - d0 - xr0 - 3;
-      const uint64_t *cb = codeR + swz(a);
+      const uint64_t *cb = codeR + rslot(a);
       uint64_t r[7];
 #pragma unroll
       for (int k = 0; k < 7; ++k) r[k] = cb[k + ((1 + k) >> 2)];
+      const int t = x - d0;
+      if (__builtin_amdgcn_ballot_w64(t < 3) == 0) {
 #pragma unroll
-      for (int p = 0; p < 4; ++p) {
-        const uint64_t cl = codeL[xi + p];
-        uint32_t word = 0;
+        for (int p = 0; p < 4; ++p) {
+          const uint64_t cl = codeL[xi + p];
+          uint32_t word = 0;
 #pragma unroll
-        for (int b = 0; b < 4; ++b) word |= (uint32_t)__popcll(cl ^ r[p - b + 3]) << (8 * b);
-        out[(int64_t)(xi + p) * qpp] = word;
+          for (int b = 0; b < 4; ++b) word |= (uint32_t)__popcll(cl ^ r[p - b + 3]) << (8 * b);
+          out[(xi + p) * qpp] = (word & keep) | fill;
+        }
+      } else {
+        // left[k]: all ones when code k lies left of the image; the cost is
+        // then N_b, merged bitwise (a conditional expression here becomes a
+        // branch per cell)
+        uint32_t left[7];
+#pragma unroll
+        for (int k = 0; k < 7; ++k) left[k] = (uint32_t)((t + k - 3) >> 31);
+#pragma unroll
+        for (int p = 0; p < 4; ++p) {
+          const uint64_t cl = codeL[xi + p];
+          uint32_t word = 0;
+#pragma unroll
+          for (int b = 0; b < 4; ++b) {
+            const int k = p - b + 3;
+            const uint32_t c = (uint32_t)__popcll(cl ^ r[k]);
+            word |= ((left[k] & nb) | (~left[k] & c)) << (8 * b);
+          }
+          out[(xi + p) * qpp] = (word & keep) | fill;
+        }
       }
     } else {
-      for (int p = 0; p < 4 && xi + p < nx; ++p) {
+      for (int p = 0; p < 4 && xi + p < nx; ++p) {  // the segment's last < 4 pixels
         const int xp = x + p;
         const uint64_t cl = codeL[xi + p];
         uint32_t word = 0;
 #pragma unroll
         for (int b = 0; b < 4; ++b) {
           const int d = d0 + b;
-          const int v = (d < D && xp >= d) ? __popcll(cl ^ codeR[swz(max(xp - d - xr0, 0))]) : J.nbits;
+          const int v = (d < D && xp >= d) ? __popcll(cl ^ codeR[rslot(max(xp - d - xr0, 0))]) : J.nbits;
           word |= (uint32_t)v << (8 * b);
         }
-        out[(int64_t)(xi + p) * qpp] = word;
+        out[(xi + p) * qpp] = word;
       }
     }
   }
