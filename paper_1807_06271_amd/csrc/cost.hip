@@ -148,7 +148,9 @@ __global__ __launch_bounds__(256) void census_cost_kernel(JobTable<FusedCostJob>
   const int q = threadIdx.x % qpp, g = threadIdx.x / qpp;
   if (g >= groups) return;
   const int d0 = q * 4;
-  uint32_t *out = reinterpret_cast<uint32_t *>(J.out8 + ((int64_t)y * W + x0) * Dp) + q;
+  // the segment's cost rows through one buffer descriptor: a lane stores at
+  // byte (xi + p) * Dp + 4q, the pixel term p * Dp a scalar offset
+  const __amdgpu_buffer_rsrc_t orow = row_rsrc(J.out8 + ((int64_t)y * W + x0) * Dp, (uint32_t)(nx * Dp));
   // padded disparities d0 + b >= D cost N_b: byte b of every word is kept
   // (keep) or replaced (fill)
   const uint32_t nb = (uint32_t)J.nbits;
@@ -160,6 +162,7 @@ __global__ __launch_bounds__(256) void census_cost_kernel(JobTable<FusedCostJob>
   }
   for (int xi = 4 * g; xi < nx; xi += 4 * groups) {
     const int x = x0 + xi;
+    const uint32_t vo = (uint32_t)(xi * Dp + 4 * q);
     if (xi + 3 < nx) {
       // codes x - d0 - 3 .. x - d0 + 3 at indices a .. a + 6, a = 1 (mod 4):
       // rslot(a + k) = rslot(a) + k + (1 + k) / 4, one base address.  Code k
@@ -172,22 +175,17 @@ __global__ __launch_bounds__(256) void census_cost_kernel(JobTable<FusedCostJob>
 #pragma unroll
       for (int k = 0; k < 7; ++k) r[k] = cb[k + ((1 + k) >> 2)];
       const int t = x - d0;
-      if (__builtin_amdgcn_ballot_w64(t < 3) == 0) {
-#pragma unroll
-        for (int p = 0; p < 4; ++p) {
-          const uint64_t cl = codeL[xi + p];
-          uint32_t word = 0;
-#pragma unroll
-          for (int b = 0; b < 4; ++b) word |= (uint32_t)__popcll(cl ^ r[p - b + 3]) << (8 * b);
-          out[(xi + p) * qpp] = (word & keep) | fill;
-        }
-      } else {
-        // left[k]: all ones when code k lies left of the image; the cost is
-        // then N_b, merged bitwise (a conditional expression here becomes a
-        // branch per cell)
+      // EDGE: merge N_b into the costs of codes left of the image; PAD: apply
+      // keep / fill (frames with D < Dp)
+      auto tile = [&](auto edge, auto pad) {
+        constexpr bool EDGE = decltype(edge)::value, PAD = decltype(pad)::value;
+        // left[k]: all ones when code k lies left of the image (merged
+        // bitwise: a conditional expression here becomes a branch per cell)
         uint32_t left[7];
+        if constexpr (EDGE) {
 #pragma unroll
-        for (int k = 0; k < 7; ++k) left[k] = (uint32_t)((t + k - 3) >> 31);
+          for (int k = 0; k < 7; ++k) left[k] = (uint32_t)((t + k - 3) >> 31);
+        }
 #pragma unroll
         for (int p = 0; p < 4; ++p) {
           const uint64_t cl = codeL[xi + p];
@@ -195,12 +193,19 @@ __global__ __launch_bounds__(256) void census_cost_kernel(JobTable<FusedCostJob>
 #pragma unroll
           for (int b = 0; b < 4; ++b) {
             const int k = p - b + 3;
-            const uint32_t c = (uint32_t)__popcll(cl ^ r[k]);
-            word |= ((left[k] & nb) | (~left[k] & c)) << (8 * b);
+            uint32_t c = (uint32_t)__popcll(cl ^ r[k]);
+            if constexpr (EDGE) c = (left[k] & nb) | (~left[k] & c);
+            word |= c << (8 * b);
           }
-          out[(xi + p) * qpp] = (word & keep) | fill;
+          if constexpr (PAD) word = (word & keep) | fill;
+          __builtin_amdgcn_raw_buffer_store_b32(word, orow, vo, p * Dp, 0);
         }
-      }
+      };
+      using T = std::integral_constant<bool, true>;
+      using F = std::integral_constant<bool, false>;
+      if (__builtin_amdgcn_ballot_w64(t < 3) != 0) tile(T{}, T{});
+      else if (D != Dp) tile(F{}, T{});
+      else tile(F{}, F{});
     } else {
       for (int p = 0; p < 4 && xi + p < nx; ++p) {  // the segment's last < 4 pixels
         const int xp = x + p;
@@ -212,7 +217,7 @@ __global__ __launch_bounds__(256) void census_cost_kernel(JobTable<FusedCostJob>
           const int v = (d < D && xp >= d) ? __popcll(cl ^ codeR[rslot(max(xp - d - xr0, 0))]) : J.nbits;
           word |= (uint32_t)v << (8 * b);
         }
-        out[(xi + p) * qpp] = word;
+        __builtin_amdgcn_raw_buffer_store_b32(word, orow, vo, p * Dp, 0);
       }
     }
   }

@@ -30,6 +30,16 @@ enum : int {
   kDppRowBcast31 = 0x143,
 };
 
+// A raw buffer descriptor over `bytes` bytes from `base`: loads and stores
+// through it take one 32-bit offset (no 64-bit address per lane), and the
+// hardware drops a store, or returns 0 for a load, whose offset lies beyond
+// the size.
+constexpr int kBufWord3 = 0x00020000;  // 32-bit data format (gfx9 descriptor word 3)
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t row_rsrc(const void *base, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, (int)bytes, kBufWord3);
+}
+
 // Value of lane i-1 (lane 0 gets `edge`).
 __device__ __forceinline__ uint32_t from_lower_lane(uint32_t v, uint32_t edge) {
   return (uint32_t)__builtin_amdgcn_update_dpp((int)edge, (int)v, kDppWaveShr1, 0xF, 0xF, false);

@@ -111,18 +111,14 @@ __device__ __forceinline__ void recur(const u16x2 (&Lp)[K / 2], const u16x2 (&C)
   }
 }
 
-// Raw buffer stores (a descriptor over one row of a volume; the hardware drops
-// a store whose offset lies beyond the descriptor's size), so that pixels
-// outside the image need no branch around their stores: a branch that skips
-// memory operations on some path makes the compiler's wait counts assume the
-// fewest operations in flight, i.e. wait for older loads and stores too soon.
-constexpr int kBufWord3 = 0x00020000;  // 32-bit data format (gfx9 descriptor word 3)
+// Raw buffer stores (row_rsrc: a descriptor over one row of a volume; the
+// hardware drops a store whose offset lies beyond the descriptor's size), so
+// that pixels outside the image need no branch around their stores: a branch
+// that skips memory operations on some path makes the compiler's wait counts
+// assume the fewest operations in flight, i.e. wait for older loads and
+// stores too soon.
 constexpr int kBufNT = 2;              // non-temporal: written once, read by a later kernel
 constexpr uint32_t kDropped = 0x80000000u;  // an offset beyond any row
-
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t row_rsrc(const void *base, uint32_t bytes) {
-  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, (int)bytes, kBufWord3);
-}
 
 // The chunked pixel layout of 16-bit path-cost sums ([Dp / 2] words per
 // pixel), used by the LDS rows of diagonal path costs and by S_D: lane j's NP
