@@ -81,6 +81,8 @@ constexpr int kFront = 256;  // a multiple of 4: keeps an index's residue mod 4
 __host__ __device__ constexpr int swz(int i) { return i + (i >> 2); }
 __host__ __device__ constexpr int rslot(int i) { return swz(i + kFront); }
 constexpr int kCodeRSlots = swz(kRightMax - 1 + kFront) + 1;
+// the lowest index the cost loop reads is x - d0 - 3 - xr0 >= -(256 - 4) - 3
+static_assert(kFront % 4 == 0 && kFront - (256 - 4) - 3 >= 0, "front slots too few");
 
 __global__ __launch_bounds__(256) void census_cost_kernel(JobTable<FusedCostJob> t) {
   extern __shared__ uint64_t lds64[];
